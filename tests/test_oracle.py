@@ -1,0 +1,267 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+library and textbook transforms, values the paper states, closed forms of the
+operator on special inputs, exact symmetries, brute-force direct sums and
+linear-algebra identities of the adjoint."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import jtfs_oracle as O
+import synth
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def plan(cfg):
+    p = synth.PARAMS[cfg]
+    return O.Plan(p["N"], p["J"], p["Q"][0], p["Q"][1], p["J_fr"], p["Q_fr"], p["T"], p["F"])
+
+
+@pytest.fixture(scope="module")
+def P1():
+    return plan(1)
+
+
+@pytest.fixture(scope="module")
+def x1():
+    return synth.batch(1)[0].astype(np.float64)
+
+
+# --------------------------------------------------------------------------- DFT
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 64, 256, 1024])
+def test_fft_matches_defining_sum(n):
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))
+    for inv in (False, True):
+        ref = O.dft_direct(a, inverse=inv)
+        got = O.fft(a, inverse=inv)
+        assert np.max(np.abs(got - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("n", [2 ** 11, 2 ** 16])
+def test_fft_matches_numpy_fft(n):
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    assert np.max(np.abs(O.fft(a) - np.fft.fft(a))) <= 1e-13 * np.max(np.abs(np.fft.fft(a)))
+    assert np.max(np.abs(O.ifft(a) - np.fft.ifft(a))) <= 1e-13 * np.max(np.abs(np.fft.ifft(a)))
+
+
+# -------------------------------------------------------------------- filterbank
+
+def test_quality_factor_matches_paper():
+    g = GOLDEN["quality_factor_Q1"]
+    assert abs(O.quality_factor(1) - g["value"]) <= g["abs_tol"]
+
+
+@pytest.mark.parametrize("Q", [1, 2, 8, 16, 24])
+def test_wavelets_analytic_zero_mean_and_lp_bound(Q):
+    M = 4096
+    xi, sg = O.filterbank_centres(8, Q)
+    hat, _ = O.morlet_family_hat(xi, sg, M)
+    neg = O.signed_bins(M) < 0
+    assert np.all(hat[:, neg] == 0.0)                 # analytic (sec. 2)
+    assert np.all(hat[:, 0] == 0.0)                   # zero mean, exactly
+    lp = np.sum(hat ** 2, axis=0)
+    assert lp.max() <= 1.0 + 1e-12
+    assert abs(lp[: M // 2 + 1].max() - 1.0) <= 1e-12
+    f = np.arange(M // 2 + 1) / M
+    band = (f >= xi.min()) & (f <= xi.max())
+    floor = {1: 0.67, 2: 0.78}.get(Q, 0.86)
+    assert lp[: M // 2 + 1][band].min() >= floor     # close to 1 in band
+
+
+def test_filterbank_geometry():
+    for Q in (1, 2, 8, 16):
+        xi, sg = O.filterbank_centres(10, Q)
+        Qf = O.quality_factor(Q)
+        ncq = int(np.sum(np.isclose(xi / sg, Qf)))
+        # constant-Q part: ratio 2^(1/Q) between neighbours
+        r = xi[1:ncq] / xi[: ncq - 1]
+        assert np.allclose(r, 2.0 ** (-1.0 / Q), rtol=1e-13)
+        # neighbouring constant-Q filters cross at -3 dB (amplitude 1/sqrt 2)
+        a, b = xi[0], xi[1]
+        fx = (a * sg[1] + b * sg[0]) / (sg[0] + sg[1])
+        g = math.exp(-(fx - a) ** 2 / (2 * sg[0] ** 2))
+        assert abs(g - 1 / math.sqrt(2)) < 1e-12
+        # linear part: minimum bandwidth, spacing 2 sqrt(ln 2) sigma_min
+        smin = O.SIGMA0 / 2 ** 10
+        assert np.allclose(sg[ncq:], smin)
+        if len(xi) > ncq + 1:
+            assert np.allclose(-np.diff(xi[ncq - 1:]), 2 * math.sqrt(math.log(2)) * smin)
+
+
+def test_peak_response_at_centre(P1):
+    """A tone at psi_lambda's centre frequency excites psi_lambda the most."""
+    N = P1.N
+    hits = 0
+    for lam in range(P1.n1):
+        m = int(round(P1.xi1[lam] * N))
+        S1, _ = O.jtfs(synth.tone(N, m), P1)
+        hits += int(np.argmax(S1[:, 0]) == lam)
+    assert hits == P1.n1
+
+
+# ------------------------------------------------------------ closed forms of S
+
+def test_pure_tone_closed_form(P1):
+    N, m, A = P1.N, 301, 0.7
+    S1, S2 = O.jtfs(synth.tone(N, m, A, 0.3), P1)
+    expect = 0.5 * A * np.abs(P1.psi1_hat[:, m])
+    assert np.max(np.abs(S1 - expect[:, None])) <= 1e-12 * expect.max()
+    assert np.max(np.abs(S2)) <= 1e-12 * expect.max()
+
+
+def test_dc_gives_zero(P1):
+    S1, S2 = O.jtfs(np.full(P1.N, 3.25), P1)
+    assert np.max(np.abs(S1)) <= 1e-14 and np.max(np.abs(S2)) <= 1e-14
+
+
+def test_homogeneity(P1, x1):
+    S1, S2 = O.jtfs(x1, P1)
+    c = -2.5
+    T1, T2 = O.jtfs(c * x1, P1)
+    assert np.max(np.abs(T1 - abs(c) * S1)) <= 1e-13 * np.max(np.abs(T1))
+    assert np.max(np.abs(T2 - abs(c) * S2)) <= 1e-13 * np.max(np.abs(T2))
+
+
+def test_shift_by_T_is_exact_frame_shift(P1, x1):
+    S1, S2 = O.jtfs(x1, P1)
+    T1, T2 = O.jtfs(np.roll(x1, P1.T), P1)
+    assert np.max(np.abs(T1 - np.roll(S1, 1, axis=-1))) <= 1e-13 * np.max(S1)
+    assert np.max(np.abs(T2 - np.roll(S2, 1, axis=-1))) <= 1e-13 * np.max(S2)
+
+
+def test_shift_invariance_below_T(P1, x1):
+    """Invariance to time shifts within the support T (sec. 2): the change grows
+    with the shift and stays well below the coefficients' norm."""
+    S1, S2 = O.jtfs(x1, P1)
+    prev = 0.0
+    for s in (1, 4, 16, 32):
+        T1, T2 = O.jtfs(np.roll(x1, s), P1)
+        d = np.linalg.norm(T2 - S2) / np.linalg.norm(S2)
+        d1 = np.linalg.norm(T1 - S1) / np.linalg.norm(S1)
+        assert d > prev
+        assert d < 0.25 * s / P1.T + 1e-3 and d1 < 0.25 * s / P1.T + 1e-3
+        prev = d
+
+
+def test_frame_count_matches_paper():
+    g = GOLDEN["frames_N65536_T2048"]
+    P = plan(2)
+    assert P.N == g["N"] and P.T == g["T"] and P.s1_shape()[1] == g["value"]
+    assert P.s2_shape()[-1] == g["value"]
+
+
+@pytest.mark.parametrize("kind", ["linear", "exp"])
+def test_spin_direction(P1, kind):
+    """Upward chirp -> energy on theta = -1 (spin index 0); downward -> theta = +1."""
+    assert GOLDEN["spin_of_upward_chirp"]["value"] == -1
+    N = P1.N
+    rng = np.random.default_rng(5)
+    up = synth.chirp_signal(rng, N, 0.02, 0.4, kind=kind, snr_db=None, am=False)
+    down = synth.chirp_signal(rng, N, 0.4, 0.02, kind=kind, snr_db=None, am=False)
+    eu = np.sum(O.jtfs(up, P1)[1] ** 2, axis=(0, 1, 3, 4))
+    ed = np.sum(O.jtfs(down, P1)[1] ** 2, axis=(0, 1, 3, 4))
+    assert eu[0] > 10 * eu[1]
+    assert ed[1] > 10 * ed[0]
+
+
+# ----------------------------------------------- brute force on tiny inputs
+
+SMALL = [
+    dict(N=128, J=3, Q=(2, 1), J_fr=2, Q_fr=1, T=16, F=2),
+    dict(N=256, J=4, Q=(4, 1), J_fr=2, Q_fr=1, T=16, F=2),
+    dict(N=256, J=5, Q=(8, 2), J_fr=3, Q_fr=2, T=32, F=4),
+    dict(N=64, J=3, Q=(1, 1), J_fr=1, Q_fr=1, T=8, F=2),
+]
+
+
+@pytest.mark.parametrize("p", SMALL)
+def test_cascade_matches_direct_sums(p):
+    P = O.Plan(p["N"], p["J"], p["Q"][0], p["Q"][1], p["J_fr"], p["Q_fr"], p["T"], p["F"])
+    x = np.random.default_rng(p["N"] + p["J"]).standard_normal(p["N"])
+    a1, a2 = O.jtfs(x, P)
+    b1, b2 = O.jtfs_direct(x, P)
+    assert np.max(np.abs(a1 - b1)) <= 1e-12 * np.max(np.abs(b1))
+    assert np.max(np.abs(a2 - b2)) <= 1e-12 * np.max(np.abs(b2))
+
+
+# ---------------------------------------------------------------- adjoints
+
+def _rdot(a, b):
+    return float(np.real(np.sum(np.conj(a) * b)))
+
+
+def test_stage_adjoints_dot_product(P1):
+    rng = np.random.default_rng(11)
+    P = P1
+    # first order: real x -> complex Y1d
+    x = rng.standard_normal(P.N)
+    g = rng.standard_normal((P.n1, P.NX)) + 1j * rng.standard_normal((P.n1, P.NX))
+    lhs = _rdot(O.first_order_linear(x, P), g)
+    rhs = _rdot(x, O.first_order_linear_adj(g, P))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    # second order: real X -> complex Y2
+    X = rng.standard_normal((P.n1, P.NX))
+    for a in range(P.n_alpha):
+        g = rng.standard_normal((P.n1, P.T_alpha(a))) + 1j * rng.standard_normal((P.n1, P.T_alpha(a)))
+        lhs = _rdot(O.second_order_linear(X, P, a), g)
+        rhs = _rdot(X, O.second_order_linear_adj(g, P, a))
+        assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    # time lowpass at each rate
+    for k in sorted({P.kX} | {P.kX + k2 for k2 in P.k2}):
+        M = P.N >> k
+        U = rng.standard_normal((5, M))
+        g = rng.standard_normal((5, P.out_t))
+        lhs = _rdot(O.time_lowpass(U, P, k), g)
+        rhs = _rdot(U, O.time_lowpass_adj(g, P, k, M))
+        assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    # frequential wavelet matrices and lowpass: spin mirror and conjugation
+    for b in range(P.n_beta):
+        W0 = P.freq_wavelet_matrix(b, 0)
+        W1 = P.freq_wavelet_matrix(b, 1)
+        h0, h1 = P.psi_fr(b, 0), P.psi_fr(b, 1)
+        assert np.allclose(h1, np.conj(h0), atol=1e-15)          # real spectrum -> mirror = conj
+        assert W0.shape == (P.L_beta(b), P.n1) and W1.shape == W0.shape
+        Pm = P.freq_lowpass_matrix(b)
+        assert np.allclose(Pm.sum(axis=1), 1.0, atol=1e-12)       # DC gain 1
+
+
+def test_vjp_matches_finite_differences(P1, x1):
+    """FP64 central differences of <gS, S(x)> along random directions (N=2048)."""
+    gS1, gS2 = synth.cotangents(P1.s1_shape(), P1.s2_shape())
+    g = O.jtfs_vjp(x1, gS1, gS2, P1)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        v = rng.standard_normal(P1.N)
+        h = 1e-6      # truncation error is O(h^2): 6e-5 at 1e-4, 6e-9 here
+        fd = (O.loss(x1 + h * v, gS1, gS2, P1) - O.loss(x1 - h * v, gS1, gS2, P1)) / (2 * h)
+        assert abs(fd - g @ v) <= 1e-7 * abs(fd)
+
+
+def test_vjp_alpha_subset_consistent(P1, x1):
+    gS1, gS2 = synth.cotangents(P1.s1_shape(), P1.s2_shape())
+    full = O.jtfs_vjp(x1, gS1, gS2, P1)
+    parts = O.jtfs_vjp(x1, gS1, np.zeros_like(gS2), P1)
+    for a in range(P1.n_alpha):
+        g = np.zeros_like(gS2)
+        g[a] = gS2[a]
+        parts = parts + O.jtfs_vjp(x1, np.zeros_like(gS1), g, P1)
+    assert np.max(np.abs(parts - full)) <= 1e-12 * np.max(np.abs(full))
+
+
+def test_plan_sizes_follow_readings():
+    """Derived sizes obey the definitions: L = next pow2 of n1, every decimation
+    divides T (resp. F), and the output grid is N/T x L/F."""
+    for cfg in (1, 2, 3, 4, 5):
+        P = plan(cfg)
+        assert P.L >= P.n1 > P.L // 2
+        assert P.kX <= int(math.log2(P.T))
+        assert all(P.kX + k <= int(math.log2(P.T)) for k in P.k2)
+        assert all(k <= int(math.log2(P.F)) for k in P.k_fr)
+        assert list(P.k2) == sorted(P.k2) and list(P.k_fr) == sorted(P.k_fr)
+        assert P.s2_shape() == (P.n_alpha, P.n_beta, 2, P.L // P.F, P.N // P.T)
