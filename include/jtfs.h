@@ -1,0 +1,144 @@
+/*
+ * jtfs.h -- C ABI of libjtfs: joint time-frequency scattering (JTFS) and its
+ * gradient on AMD Instinct MI355X (gfx950).
+ *
+ * Operator (arxiv 2204.08269, sec. 2): for a real signal x of N samples,
+ *   first order   X(t,lambda) = |x * psi_lambda|(t)                 (scalogram)
+ *                 S1 = X *_t phi_T                                   (sec. 4.2: no phi_F)
+ *   second order  S2 = | X *_{t,lambda} Psi_{alpha,beta,theta} | *_{t,lambda} Phi_{T,F}   (eq. 3)
+ *                 Psi_{alpha,beta,theta}(t,lambda) = psi_alpha(t) psi_{beta,theta}(lambda) (eq. 2)
+ *                 psi_alpha(t) = 2^alpha psi(2^alpha t), psi_{beta,theta}(lambda) = 2^beta psi(theta 2^beta lambda) (eq. 1)
+ * and the vector-Jacobian product of (S1, S2) with respect to x, formed by the
+ * Hermitian adjoints of the stages in reverse order (sec. 5).
+ *
+ * Discretisation (the paper gives continuous equations only):
+ *   - circular convolutions on power-of-two grids, Morlet wavelets defined by
+ *     their spectra (analytic: zero on negative frequencies, zero at DC), Gaussian
+ *     lowpasses of width 0.1/T and 0.1/F, neighbouring wavelets crossing at -3 dB
+ *     (quality factor about 2.5 at Q = 1, sec. 3.3);
+ *   - every band is computed at a critical rate set by its bandwidth (sec. 1);
+ *   - the log-frequency axis (n1 first-order bands) is zero-padded to the next
+ *     power of two L; its index 0 is the highest frequency;
+ *   - spin index 0 is theta = -1 (positive slope: an upward chirp lands there),
+ *     spin index 1 is theta = +1 (sec. 2, Fig. 1).
+ *
+ * Layouts (row-major, contiguous float32):
+ *   x   [B][N]
+ *   S1  [B][n1][N/T]
+ *   S2  [B][n_alpha][n_beta][2][L/F][N/T]       (the paper's out_3D mode, sec. 4.2)
+ *   gx  [B][N]
+ *
+ * Memory and streams: x, S1, S2, gS1, gS2, gx and the workspace are device
+ * pointers owned by the caller.  The plan owns its filter tables (device memory
+ * allocated at creation, freed by jtfs_plan_destroy).  All work is enqueued on the
+ * given stream with no host synchronisation; a plan may be used from several
+ * threads and streams at once as long as each call has its own workspace.
+ *
+ * Errors: functions return JTFS_OK (0) or a negative status; jtfs_last_error()
+ * returns a thread-local description of the last failure.  Argument validation
+ * happens before any HIP call.
+ */
+#ifndef JTFS_H
+#define JTFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JTFS_OK          0
+#define JTFS_EINVAL     -1   /* invalid parameter, shape or null pointer          */
+#define JTFS_ENOMEM     -2   /* device allocation of plan tables failed            */
+#define JTFS_EHIP       -3   /* a HIP runtime call or kernel launch failed         */
+#define JTFS_EWORKSPACE -4   /* workspace smaller than jtfs_workspace_size()       */
+#define JTFS_ENOTSUP    -6   /* valid parameters outside what this build supports  */
+
+/* Flags of jtfs_backward. */
+#define JTFS_BWD_REUSE_FORWARD 1u  /* ws holds the intermediates of the immediately
+                                      preceding jtfs_forward on the same x, B and plan:
+                                      skip recomputing the first and second order */
+
+typedef struct jtfs_plan jtfs_plan;
+
+/* Transform parameters (sec. 2, sec. 4.2): N samples; J octaves of the temporal
+ * filterbanks; Q1 / Q2 wavelets per octave at first / second order; J_fr octaves
+ * and Q_fr wavelets per octave of the frequential filterbank; lowpass supports T
+ * (time, samples) and F (log-frequency, bins).  N, T, F are powers of two with
+ * 16 <= N <= 2^24, T <= N, F <= L. */
+typedef struct {
+    int64_t N;
+    int32_t J, Q1, Q2, J_fr, Q_fr;
+    int64_t T, F;
+} jtfs_params;
+
+/* Derived sizes. */
+typedef struct {
+    int32_t n1;        /* first-order wavelets (lambda rows of the scalogram)      */
+    int32_t n_alpha;   /* second-order temporal wavelets                             */
+    int32_t n_beta;    /* frequential wavelets (each with two spins)                 */
+    int32_t L;         /* zero-padded log-frequency length, next power of two >= n1 */
+    int32_t kX;        /* scalogram decimation: X has N / 2^kX samples per row       */
+    int32_t M_h;       /* frequential output rows per spin: sum_beta L / 2^kfr(beta) */
+    int64_t NX;        /* N / 2^kX                                                   */
+    int64_t out_t;     /* N / T frames                                               */
+    int64_t out_l;     /* L / F log-frequency rows of S2                             */
+    int64_t sum_T;     /* sum over alpha of the second-order lengths NX / 2^k2(alpha) */
+    int64_t s1_per_signal;   /* n1 * out_t                                          */
+    int64_t s2_per_signal;   /* n_alpha * n_beta * 2 * out_l * out_t                */
+} jtfs_info;
+
+/* Host-only queries (no GPU needed). */
+
+/* Validate p and fill the derived sizes. */
+int jtfs_query(const jtfs_params* p, jtfs_info* out);
+
+/* Filter tables of one family, host FP64: family 0 = first-order temporal
+ * (cycles/sample), 1 = second-order temporal (cycles per scalogram sample),
+ * 2 = frequential (cycles per lambda bin).  xi and sigma are the centre and
+ * Gaussian width of each wavelet; log2_decim is its critical decimation
+ * exponent (family 0: kX for every row).  Arrays hold `cap` entries; the count
+ * is returned through *count (a count above cap gives JTFS_EINVAL). */
+int jtfs_query_filters(const jtfs_params* p, int family, int32_t cap,
+                       double* xi, double* sigma, int32_t* log2_decim, int32_t* count);
+
+/* Plan creation builds every filter table on the device in FP64 (spectra,
+ * Littlewood-Paley normalisation, lambda-domain wavelet matrices, lowpass
+ * matrices) and stores them as FP32.  Q = {Q1, Q2}. */
+int jtfs_plan_create(jtfs_plan** out, int64_t N, int J, const int Q[2], int J_fr, int Q_fr,
+                     int64_t T, int64_t F);
+int jtfs_plan_create_ex(jtfs_plan** out, const jtfs_params* p);
+int jtfs_plan_info(const jtfs_plan* plan, jtfs_info* out);
+void jtfs_plan_destroy(jtfs_plan* plan);
+
+/* Device bytes of workspace needed by jtfs_forward and jtfs_backward for a
+ * batch of B signals (the same workspace serves both; the backward reuses the
+ * forward's intermediates when called with JTFS_BWD_REUSE_FORWARD). */
+int jtfs_workspace_size(const jtfs_plan* plan, int64_t B, size_t* bytes);
+
+/* S1 and S2 of B signals (layouts above).  ws: device workspace of ws_bytes. */
+int jtfs_forward(const jtfs_plan* plan, const float* x, int64_t B, float* s1, float* s2,
+                 void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* gx = d<gS1,S1(x)> + <gS2,S2(x)> / dx for B signals.  gx is overwritten.
+ * Either of gs1 / gs2 may be NULL (a zero cotangent). */
+int jtfs_backward(const jtfs_plan* plan, const float* x, const float* gs1, const float* gs2,
+                  float* gx, int64_t B, void* ws, size_t ws_bytes, uint32_t flags,
+                  hipStream_t stream);
+
+/* Copy a device filter table of the plan to host memory, for inspection in
+ * tests.  which: 0 = first-order spectra as a dense [n1][N/2+1] FP32 array,
+ * 1 = second-order spectra dense [n_alpha][NX/2+1], 2 = frequential wavelet
+ * matrix, spin theta = -1, as interleaved complex FP32 [M_h][n1].
+ * bytes must equal the table's size.  Synchronous. */
+int jtfs_plan_table(const jtfs_plan* plan, int which, void* host_dst, size_t bytes);
+
+/* Thread-local text of the last error ("" if none). */
+const char* jtfs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JTFS_H */

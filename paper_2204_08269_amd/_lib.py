@@ -1,0 +1,107 @@
+"""ctypes binding of libjtfs.so (the C ABI declared in include/jtfs.h).
+
+Argument marshalling only: every step of the transform runs in the library's
+HIP kernels.  Importing this module does not touch the GPU; loading the library
+fails loudly if it has not been built."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjtfs.so")
+
+JTFS_OK = 0
+JTFS_EINVAL = -1
+JTFS_ENOMEM = -2
+JTFS_EHIP = -3
+JTFS_EWORKSPACE = -4
+JTFS_ENOTSUP = -6
+JTFS_BWD_REUSE_FORWARD = 1
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("J", ctypes.c_int32), ("Q1", ctypes.c_int32), ("Q2", ctypes.c_int32),
+                ("J_fr", ctypes.c_int32), ("Q_fr", ctypes.c_int32), ("T", ctypes.c_int64), ("F", ctypes.c_int64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int32), ("n_alpha", ctypes.c_int32), ("n_beta", ctypes.c_int32),
+                ("L", ctypes.c_int32), ("kX", ctypes.c_int32), ("M_h", ctypes.c_int32),
+                ("NX", ctypes.c_int64), ("out_t", ctypes.c_int64), ("out_l", ctypes.c_int64),
+                ("sum_T", ctypes.c_int64), ("s1_per_signal", ctypes.c_int64), ("s2_per_signal", ctypes.c_int64)]
+
+
+EXPORTS = ["jtfs_query", "jtfs_query_filters", "jtfs_plan_create", "jtfs_plan_create_ex", "jtfs_plan_info",
+           "jtfs_plan_destroy", "jtfs_workspace_size", "jtfs_forward", "jtfs_backward", "jtfs_plan_table",
+           "jtfs_last_error"]
+
+_lib = None
+
+
+class JTFSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libjtfs error {code}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load libjtfs.so and declare its signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2204_08269_amd.build` "
+                           "(there is no fallback implementation)")
+    L = ctypes.CDLL(path)
+    vp, i64, i32, u32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
+    P = ctypes.POINTER
+    L.jtfs_query.argtypes = [P(Params), P(Info)]
+    L.jtfs_query_filters.argtypes = [P(Params), ctypes.c_int, i32, P(ctypes.c_double), P(ctypes.c_double),
+                                     P(i32), P(i32)]
+    L.jtfs_plan_create.argtypes = [P(vp), i64, ctypes.c_int, P(ctypes.c_int), ctypes.c_int, ctypes.c_int, i64, i64]
+    L.jtfs_plan_create_ex.argtypes = [P(vp), P(Params)]
+    L.jtfs_plan_info.argtypes = [vp, P(Info)]
+    L.jtfs_plan_destroy.argtypes = [vp]
+    L.jtfs_plan_destroy.restype = None
+    L.jtfs_workspace_size.argtypes = [vp, i64, P(sz)]
+    L.jtfs_forward.argtypes = [vp, vp, i64, vp, vp, vp, sz, vp]
+    L.jtfs_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, sz, u32, vp]
+    L.jtfs_plan_table.argtypes = [vp, ctypes.c_int, vp, sz]
+    L.jtfs_last_error.argtypes = []
+    L.jtfs_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("jtfs_plan_destroy", "jtfs_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(code: int):
+    if code != JTFS_OK:
+        raise JTFSError(code, load().jtfs_last_error().decode())
+    return code
+
+
+def params(N, J, Q, J_fr, Q_fr, T, F) -> Params:
+    return Params(int(N), int(J), int(Q[0]), int(Q[1]), int(J_fr), int(Q_fr), int(T), int(F))
+
+
+def query(p: Params) -> Info:
+    info = Info()
+    check(load().jtfs_query(ctypes.byref(p), ctypes.byref(info)))
+    return info
+
+
+def query_filters(p: Params, family: int):
+    """(xi, sigma, log2_decim) of one family from the host FP64 solve."""
+    import numpy as np
+    L = load()
+    cnt = ctypes.c_int32(0)
+    cap = 4096
+    xi = (ctypes.c_double * cap)()
+    sg = (ctypes.c_double * cap)()
+    k = (ctypes.c_int32 * cap)()
+    check(L.jtfs_query_filters(ctypes.byref(p), family, cap, xi, sg, k, ctypes.byref(cnt)))
+    n = cnt.value
+    return np.array(xi[:n]), np.array(sg[:n]), np.array(k[:n])

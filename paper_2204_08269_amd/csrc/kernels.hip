@@ -1,0 +1,885 @@
+// JTFS forward and backward on gfx950: FFT passes in LDS, the fused scalogram
+// and second-order kernels, the frequential contraction on FP32 MFMA with the
+// modulus and time lowpass fused into its epilogue, and every stage's adjoint.
+//
+// Scaling conventions: all FFTs are unnormalised; every 1/M of an inverse DFT is
+// applied explicitly where the stage's definition puts it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "fft_lds.hpp"
+#include "plan.hpp"
+
+namespace jtfs {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
+    // D[i][j] += sum_k A[i][k] B[k][j], 32x32x2: lane (i + 32k) holds A[i][k] and
+    // B[k][i]; D element (i, j) sits in lane j + 32*((i/4)%2), register (i%4) + 4*(i/8).
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx16 zero16() {
+    floatx16 z;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z[r] = 0.f;
+    return z;
+}
+// row (within a 32x32 tile) held by register r of a lane in half h
+__device__ __forceinline__ int crow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+
+// ---------------------------------------------------------------------------
+// Generic batched FFT over LDS: transform c of batch b has element e at
+// in[b*ib + c*ics + e*ies]; the output X_c[k] (times w_n^{c k} when twl > 0, the
+// four-step twist, and times scale) goes to out[b*ob + c*ocs + k*oes].
+// Column mode (ics == 1): C = 2^logC adjacent transforms per workgroup, loaded
+// with adjacent columns on adjacent threads.  Row mode: transforms contiguous.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(512) k_fft_cols(const float2* in, float2* out, int loglen,
+                                                  int ncols, int logC, int64_t ib, int64_t ics, int64_t ies, int64_t ob,
+                                                  int64_t ocs, int64_t oes, int twl, const float2* __restrict__ tw,
+                                                  int tw_log, int inv, float scale) {
+    extern __shared__ float2 s[];
+    const int len = 1 << loglen, st = len + 1;
+    const int C = 1 << logC;
+    const int c0 = blockIdx.x * C;
+    const int nc = min(C, ncols - c0);
+    const int tot = nc * len;
+    const int64_t b = blockIdx.y;
+    in += b * ib;
+    out += b * ob;
+    if (ics == 1) {
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int c = e & (C - 1), k = e >> logC;
+            s[c * st + k] = in[(int64_t)(c0 + c) + (int64_t)k * ies];
+        }
+    } else {
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int c = e >> loglen, k = e & (len - 1);
+            s[c * st + k] = in[(int64_t)(c0 + c) * ics + (int64_t)k * ies];
+        }
+    }
+    __syncthreads();
+    lds_fft<32>(s, loglen, nc, st, tw, tw_log, inv != 0);
+    const int tws = tw_log - twl;
+    if (ocs == 1) {
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int c = e & (C - 1), k = e >> logC;
+            float2 v = s[c * st + k];
+            if (twl) v = cmul(v, twiddle(tw, ((c0 + c) * k) << tws, inv != 0));
+            out[(int64_t)(c0 + c) + (int64_t)k * oes] = cscale(v, scale);
+        }
+    } else {
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int c = e >> loglen, k = e & (len - 1);
+            float2 v = s[c * st + k];
+            if (twl) v = cmul(v, twiddle(tw, ((c0 + c) * k) << tws, inv != 0));
+            out[(int64_t)(c0 + c) * ocs + (int64_t)k * oes] = cscale(v, scale);
+        }
+    }
+}
+
+// Real-input spectrum from the half-length complex FFT of z[k] = x[2k] + i x[2k+1]:
+// X[m] = E[m] + w_n^m O[m], E/O the spectra of the even/odd samples; in place on
+// rows of pitch H+1 (H = n/2), bins 0..H.
+__global__ void k_rfft_post(float2* __restrict__ xh, int64_t pitch, int logn, const float2* __restrict__ tw,
+                            int tw_log) {
+    const int H = 1 << (logn - 1);
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m > H / 2) return;
+    float2* row = xh + (int64_t)blockIdx.y * pitch;
+    const int tws = tw_log - logn;
+    if (m == 0) {
+        const float2 z = row[0];
+        row[0] = make_float2(z.x + z.y, 0.f);
+        row[H] = make_float2(z.x - z.y, 0.f);
+        return;
+    }
+    const float2 a = row[m], b = row[H - m];
+    auto spec = [&](float2 p, float2 q, int k) {
+        const float2 E = make_float2(0.5f * (p.x + q.x), 0.5f * (p.y - q.y));
+        const float2 D = make_float2(p.x - q.x, p.y + q.y);          // p - conj(q)
+        const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);      // D / (2i)
+        return cadd(E, cmul(O, tw[k << tws]));
+    };
+    const float2 Xm = spec(a, b, m);
+    const float2 Xn = spec(b, a, H - m);
+    row[m] = Xm;
+    row[H - m] = Xn;
+}
+
+// Inverse of k_rfft_post: Z'[k] = (X[k] + conj X[H-k]) + i w_n^{-k} (X[k] - conj X[H-k]),
+// whose unnormalised inverse FFT is n times the interleaved real signal.
+__global__ void k_irfft_pack(const float2* __restrict__ xh, int64_t pitch, float2* __restrict__ z, int64_t zpitch,
+                             int logn, const float2* __restrict__ tw, int tw_log) {
+    const int H = 1 << (logn - 1);
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > H / 2) return;
+    const float2* row = xh + (int64_t)blockIdx.y * pitch;
+    float2* zr = z + (int64_t)blockIdx.y * zpitch;
+    const int tws = tw_log - logn;
+    auto pk = [&](float2 p, float2 q, int kk) {
+        const float2 S = make_float2(p.x + q.x, p.y - q.y);          // p + conj q
+        const float2 D = make_float2(p.x - q.x, p.y + q.y);          // p - conj q
+        const float2 wD = cmulc(D, tw[kk << tws]);                   // w^{-k} D
+        return make_float2(S.x - wD.y, S.y + wD.x);                  // S + i wD
+    };
+    const float2 a = row[k], b = row[H - k];
+    zr[k] = pk(a, b, k);
+    if (k > 0 && H - k != k) zr[H - k] = pk(b, a, H - k);
+}
+
+// ---------------------------------------------------------------------------
+// First order (fused): fold x_hat * psi_hat_lambda over the band into NX bins,
+// inverse FFT (the filtered signal at the scalogram rate), modulus, real FFT of
+// the scalogram row; writes X_hat[b][lambda][0..NX/2].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void fold_band(float2* s, const float2* __restrict__ src, const float* __restrict__ ps, int lo,
+                                          int hi, int logM) {
+    const int M = 1 << logM;
+    for (int p = threadIdx.x; p < M; p += blockDim.x) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int m = lo + ((p - lo) & (M - 1)); m <= hi; m += M) {
+            const float2 v = src[m];
+            const float g = ps[m - lo];
+            acc.x += v.x * g;
+            acc.y += v.y * g;
+        }
+        s[p] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(512) k_scalogram(const float2* __restrict__ xh, int64_t xh_pitch,
+                                                   const float* __restrict__ psi1, const int* __restrict__ band1,
+                                                   const int64_t* __restrict__ off1, float2* __restrict__ Xh,
+                                                   int64_t Xh_pitch, int logNX, float invN,
+                                                   const float2* __restrict__ tw, int tw_log) {
+    extern __shared__ float2 s[];
+    const int lam = blockIdx.x, n1 = gridDim.x;
+    const int64_t b = blockIdx.y;
+    const int NX = 1 << logNX, H = NX >> 1;
+    fold_band(s, xh + b * xh_pitch, psi1 + off1[lam], band1[2 * lam], band1[2 * lam + 1], logNX);
+    __syncthreads();
+    lds_fft<32>(s, logNX, 1, NX, tw, tw_log, true);
+    // modulus of the scalogram-rate samples, packed as z[k] = X[2k] + i X[2k+1]
+    {
+        float2 v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int k = threadIdx.x + q * blockDim.x;
+            if (k < H) {
+                const float2 a = s[2 * k], c = s[2 * k + 1];
+                v[q] = make_float2(sqrtf(a.x * a.x + a.y * a.y) * invN, sqrtf(c.x * c.x + c.y * c.y) * invN);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int k = threadIdx.x + q * blockDim.x;
+            if (k < H) s[k] = v[q];
+        }
+        __syncthreads();
+    }
+    if (logNX > 1) lds_fft<32>(s, logNX - 1, 1, H, tw, tw_log, false);
+    float2* out = Xh + (b * n1 + lam) * Xh_pitch;
+    const int tws = tw_log - logNX;
+    for (int m = threadIdx.x; m <= H / 2; m += blockDim.x) {
+        if (m == 0) {
+            const float2 z = s[0];
+            out[0] = make_float2(z.x + z.y, 0.f);
+            out[H] = make_float2(z.x - z.y, 0.f);
+            continue;
+        }
+        const float2 a = s[m], c = s[H - m];
+        auto spec = [&](float2 p, float2 q, int k) {
+            const float2 E = make_float2(0.5f * (p.x + q.x), 0.5f * (p.y - q.y));
+            const float2 D = make_float2(p.x - q.x, p.y + q.y);
+            const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);
+            return cadd(E, cmul(O, tw[k << tws]));
+        };
+        out[m] = spec(a, c, m);
+        if (H - m != m) out[H - m] = spec(c, a, H - m);
+    }
+}
+
+// S1[tau] = (X (*) phi_T)[tau T/2^kX]: fold X_hat * phi_hat over the N/T-bin grid
+// (bins -Mneg..Mphi of the NX grid), inverse FFT, real part / NX.
+__global__ void __launch_bounds__(256) k_s1(const float2* __restrict__ Xh, int64_t Xh_pitch,
+                                            const float* __restrict__ phiX, int Mphi, int logNX, int logNT, float invNX,
+                                            float* __restrict__ S1, const float2* __restrict__ tw, int tw_log) {
+    extern __shared__ float2 s[];
+    const int lam = blockIdx.x, n1 = gridDim.x;
+    const int64_t b = blockIdx.y;
+    const int NX = 1 << logNX, NT = 1 << logNT;
+    const float2* row = Xh + (b * n1 + lam) * Xh_pitch;
+    const int Mneg = (Mphi == NX / 2) ? Mphi - 1 : Mphi;
+    for (int p = threadIdx.x; p < NT; p += blockDim.x) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int mt = -Mneg + ((p + Mneg) & (NT - 1)); mt <= Mphi; mt += NT) {
+            const float2 v = mt >= 0 ? row[mt] : conjf2(row[-mt]);
+            const float g = phiX[mt >= 0 ? mt : -mt];
+            acc.x += v.x * g;
+            acc.y += v.y * g;
+        }
+        s[p] = acc;
+    }
+    __syncthreads();
+    lds_fft<64>(s, logNT, 1, NT, tw, tw_log, true);
+    float* o = S1 + (b * n1 + lam) * NT;
+    for (int t = threadIdx.x; t < NT; t += blockDim.x) o[t] = s[t].x * invNX;
+}
+
+// Second order: Y2[b][alpha][lambda][t] = (X_lambda (*) psi_alpha)[t 2^k2] for t < Ta,
+// zero for Ta <= t < Tp and for lambda >= n1 (the K padding of the contraction).
+__global__ void __launch_bounds__(512) k_second_order(const float2* __restrict__ Xh, int64_t Xh_pitch, int n1,
+                                                      const float* __restrict__ ps, int lo, int hi, int logTa, int Tp,
+                                                      int rows, int Kp, float2* __restrict__ Y, int64_t y_bstride,
+                                                      float invNX, const float2* __restrict__ tw, int tw_log) {
+    extern __shared__ float2 s[];
+    const int64_t b = blockIdx.y;
+    const int r0 = blockIdx.x * rows;
+    const int Ta = 1 << logTa;
+    const int nr = min(rows, Kp - r0);
+    for (int e = threadIdx.x; e < nr * Ta; e += blockDim.x) {
+        const int c = e >> logTa, p = e & (Ta - 1);
+        const int lam = r0 + c;
+        float2 acc = make_float2(0.f, 0.f);
+        if (lam < n1) {
+            const float2* row = Xh + (b * n1 + lam) * Xh_pitch;
+            for (int m = lo + ((p - lo) & (Ta - 1)); m <= hi; m += Ta) {
+                const float2 v = row[m];
+                const float g = ps[m - lo];
+                acc.x += v.x * g;
+                acc.y += v.y * g;
+            }
+        }
+        s[e] = acc;
+    }
+    __syncthreads();
+    lds_fft<32>(s, logTa, nr, Ta, tw, tw_log, true);
+    float2* out = Y + b * y_bstride + (int64_t)r0 * Tp;
+    for (int e = threadIdx.x; e < nr * Tp; e += blockDim.x) {
+        const int c = e / Tp, t = e - c * Tp;
+        out[e] = t < Ta ? cscale(s[c * Ta + t], invNX) : make_float2(0.f, 0.f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Frequential contraction (eq. 3 along lambda, both spins) on FP32 MFMA, fused
+// with the modulus and the time lowpass:
+//   Z_up^T[t][l]   = sum_k Y[k][t] W[l][k]        (theta = -1)
+//   Z_down^T[t][l] = sum_k Y[k][t] conj W[l][k]   (theta = +1, the mirrored wavelet)
+// from the four real products of (Yr, Yi) x (Wr, Wi); then
+//   V^T[tau][l] += sum_t Phi[t][tau] |Z^T[t][l]|   (second MFMA, the C registers of
+// the first serve directly as its B operand).  One workgroup: 64 l x one t-chunk,
+// four waves on 32x32 sub-tiles; partial V per (t-chunk, t-half) slot.
+// ---------------------------------------------------------------------------
+template <int NTB>
+__global__ void __launch_bounds__(256) k_freq_fwd(const float2* __restrict__ Y, int64_t y_bstride, int Tp, int chunk,
+                                                  const float2* __restrict__ Wt, int Mp, int Kp,
+                                                  const float* __restrict__ Phi, float* __restrict__ Vp,
+                                                  int64_t vp_bstride, int slot0, int nlt) {
+    constexpr int NTp = 32 * NTB;
+    __shared__ float2 Ys[kKStep][kTileT];
+    __shared__ float2 Ws[kKStep][kTileL];
+    const int lt = blockIdx.x, ch = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    const int l0 = lt * kTileL;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, i32 = lane & 31;
+    const int lw = (wave >> 1) * 32, twv = (wave & 1) * 32;
+    const float2* Yb = Y + b * y_bstride;
+    floatx16 vu[NTB], vd[NTB];
+#pragma unroll
+    for (int n = 0; n < NTB; ++n) { vu[n] = zero16(); vd[n] = zero16(); }
+
+    for (int t0 = ch * chunk; t0 < (ch + 1) * chunk; t0 += kTileT) {
+        floatx16 rr = zero16(), ir = zero16(), ri = zero16(), ii = zero16();
+        for (int k0 = 0; k0 < Kp; k0 += kKStep) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int f = tid + q * 256, row = f >> 5, c = (f & 31) * 2;
+                *(float4*)&Ys[row][c] = *(const float4*)(Yb + (int64_t)(k0 + row) * Tp + t0 + c);
+                *(float4*)&Ws[row][c] = *(const float4*)(Wt + (int64_t)(k0 + row) * Mp + l0 + c);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < kKStep / 2; ++ks) {
+                const float2 a = Ys[2 * ks + h][twv + i32];
+                const float2 w = Ws[2 * ks + h][lw + i32];
+                rr = mfma32(a.x, w.x, rr);
+                ir = mfma32(a.y, w.x, ir);
+                ri = mfma32(a.x, w.y, ri);
+                ii = mfma32(a.y, w.y, ii);
+            }
+            __syncthreads();
+        }
+        floatx16 uu, ud;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float ur = rr[r] - ii[r], ui = ir[r] + ri[r];
+            const float dr = rr[r] + ii[r], di = ir[r] - ri[r];
+            uu[r] = sqrtf(ur * ur + ui * ui);
+            ud[r] = sqrtf(dr * dr + di * di);
+        }
+        const float* ph = Phi + (int64_t)(t0 + twv) * NTp;
+#pragma unroll
+        for (int n = 0; n < NTB; ++n) {
+#pragma unroll
+            for (int sidx = 0; sidx < 16; ++sidx) {
+                const float p = ph[crow(sidx, h) * NTp + n * 32 + i32];
+                vu[n] = mfma32(p, uu[sidx], vu[n]);
+                vd[n] = mfma32(p, ud[sidx], vd[n]);
+            }
+        }
+    }
+    // partial V: [slot][lt][spin][tau][64 l]
+    const int slot = slot0 + ch * 2 + (wave & 1);
+    float* out = Vp + b * vp_bstride + ((int64_t)slot * nlt + lt) * 2 * NTp * kTileL;
+#pragma unroll
+    for (int n = 0; n < NTB; ++n) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int tau = n * 32 + crow(r, h);
+            out[(int64_t)tau * kTileL + lw + i32] = vu[n][r];
+            out[(int64_t)(NTp + tau) * kTileL + lw + i32] = vd[n][r];
+        }
+    }
+}
+
+// S2[b][alpha][beta][theta][m][tau] = sum_l PF_beta[m][l] V[theta][rowoff+l][tau],
+// V = sum over the partial slots.  grid (n_beta, 2, B).
+__global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, int64_t vp_bstride, int slot0,
+                                                int nslots, int nlt, int NTp, int NT, const float* __restrict__ PFall,
+                                                const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
+                                                const int* __restrict__ rowoffv, int NL, int alpha, int n_alpha,
+                                                float* __restrict__ S2) {
+    extern __shared__ float Vs[];   // [Lb][33]
+    const int beta = blockIdx.x, th = blockIdx.y, n_beta = gridDim.x;
+    const int64_t b = blockIdx.z;
+    const int Lb = Lbv[beta], ro = rowoffv[beta];
+    const float* PF = PFall + pfoff[beta];
+    const float* Vb = Vp + b * vp_bstride;
+    float* o = S2 + ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NL) * (int64_t)NT;
+    for (int tb = 0; tb < NT; tb += 32) {
+        for (int e = threadIdx.x; e < Lb * 32; e += blockDim.x) {
+            const int tau = e / Lb, l = e - tau * Lb;
+            const int row = ro + l, lt = row / kTileL, lr = row % kTileL;
+            float acc = 0.f;
+            if (tb + tau < NT) {
+                for (int sl = 0; sl < nslots; ++sl)
+                    acc += Vb[(((int64_t)(slot0 + sl) * nlt + lt) * 2 + th) * NTp * kTileL +
+                              (int64_t)(tb + tau) * kTileL + lr];
+            }
+            Vs[l * 33 + tau] = acc;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < NL * 32; e += blockDim.x) {
+            const int m = e / 32, tau = e % 32;
+            if (tb + tau >= NT) continue;
+            float acc = 0.f;
+            for (int l = 0; l < Lb; ++l) acc += PF[m * Lb + l] * Vs[l * 33 + tau];
+            o[(int64_t)m * NT + tb + tau] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward.
+// ---------------------------------------------------------------------------
+
+// gV[b][alpha][theta][rowoff+l][tau] = sum_m PF_beta[m][l] gS2[b][alpha][beta][theta][m][tau]
+// (adjoint of the frequency lowpass); block n_beta zeroes the padding rows.
+__global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, const float* __restrict__ PFall,
+                                                const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
+                                                const int* __restrict__ rowoffv, int n_beta, int NL, int NT, int NTp,
+                                                int Mh, int Mp, int alpha, int n_alpha, float* __restrict__ gV) {
+    const int beta = blockIdx.x, th = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    float* g = gV + (((b * n_alpha + alpha) * 2 + th) * (int64_t)Mp) * NTp;
+    if (beta == n_beta) {
+        for (int e = threadIdx.x; e < (Mp - Mh) * NTp; e += blockDim.x) g[(int64_t)Mh * NTp + e] = 0.f;
+        return;
+    }
+    const int Lb = Lbv[beta], ro = rowoffv[beta];
+    const float* PF = PFall + pfoff[beta];
+    const float* src =
+        gS2 ? gS2 + ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NL) * (int64_t)NT : nullptr;
+    for (int e = threadIdx.x; e < Lb * NTp; e += blockDim.x) {
+        const int l = e / NTp, tau = e - l * NTp;
+        float acc = 0.f;
+        if (src && tau < NT)
+            for (int m = 0; m < NL; ++m) acc += PF[m * Lb + l] * src[(int64_t)m * NT + tau];
+        g[(int64_t)(ro + l) * NTp + tau] = acc;
+    }
+}
+
+// Recompute Z = W Y (both spins) on a 64 l x 64 t tile, gU = gV Phi^T (adjoint of
+// the time lowpass), gZ = gU Z / max(|Z|, eps) (modulus adjoint), and store
+// P = gZ_up + gZ_down and Q' = i (gZ_down - gZ_up), so that the adjoint of the
+// contraction is gY = Wr^T P + Wi^T Q'.  Non-transposed orientation: C rows = l.
+template <int NTB>
+__global__ void __launch_bounds__(256) k_bwd_pq(const float2* __restrict__ Y, int64_t y_bstride, int Tp,
+                                                const float2* __restrict__ Wt, int Mp, int Kp,
+                                                const float* __restrict__ Phi, const float* __restrict__ gV,
+                                                int64_t gv_bstride, float2* __restrict__ PQ) {
+    constexpr int NTp = 32 * NTB;
+    constexpr int LDG = NTp + 1;
+    __shared__ float2 Ys[kKStep][kTileT];
+    __shared__ float2 Ws[kKStep][kTileL];
+    __shared__ float gVs[2][kTileL][LDG];
+    __shared__ float Phs[kTileT][LDG];
+    const int lt = blockIdx.x, tt = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    const int l0 = lt * kTileL, t0 = tt * kTileT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, i32 = lane & 31;
+    const int lw = (wave >> 1) * 32, twv = (wave & 1) * 32;
+    const float2* Yb = Y + b * y_bstride;
+    const float* gvb = gV + b * gv_bstride;
+    for (int e = tid; e < kTileL * NTp; e += 256) {
+        const int l = e / NTp, tau = e - l * NTp;
+        gVs[0][l][tau] = gvb[(int64_t)(l0 + l) * NTp + tau];
+        gVs[1][l][tau] = gvb[(int64_t)(Mp + l0 + l) * NTp + tau];
+        Phs[l][tau] = Phi[(int64_t)(t0 + l) * NTp + tau];
+    }
+    floatx16 rr = zero16(), ri = zero16(), ir = zero16(), ii = zero16();
+    for (int k0 = 0; k0 < Kp; k0 += kKStep) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int f = tid + q * 256, row = f >> 5, c = (f & 31) * 2;
+            *(float4*)&Ys[row][c] = *(const float4*)(Yb + (int64_t)(k0 + row) * Tp + t0 + c);
+            *(float4*)&Ws[row][c] = *(const float4*)(Wt + (int64_t)(k0 + row) * Mp + l0 + c);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kKStep / 2; ++ks) {
+            const float2 w = Ws[2 * ks + h][lw + i32];   // A: rows l
+            const float2 y = Ys[2 * ks + h][twv + i32];  // B: columns t
+            rr = mfma32(w.x, y.x, rr);
+            ri = mfma32(w.x, y.y, ri);
+            ir = mfma32(w.y, y.x, ir);
+            ii = mfma32(w.y, y.y, ii);
+        }
+        __syncthreads();
+    }
+    floatx16 gu = zero16(), gd = zero16();
+#pragma unroll
+    for (int n = 0; n < NTB; ++n) {
+#pragma unroll
+        for (int sidx = 0; sidx < 16; ++sidx) {
+            const int tau = n * 32 + 2 * sidx + h;
+            const float p = Phs[twv + i32][tau];
+            gu = mfma32(gVs[0][lw + i32][tau], p, gu);
+            gd = mfma32(gVs[1][lw + i32][tau], p, gd);
+        }
+    }
+    float2* Pp = PQ + b * (2 * (int64_t)Mp * Tp);
+    float2* Qp = Pp + (int64_t)Mp * Tp;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const float ur = rr[r] - ii[r], ui = ri[r] + ir[r];
+        const float dr = rr[r] + ii[r], di = ri[r] - ir[r];
+        const float su = gu[r] / fmaxf(sqrtf(ur * ur + ui * ui), kEpsMod);
+        const float sd = gd[r] / fmaxf(sqrtf(dr * dr + di * di), kEpsMod);
+        const float gur = su * ur, gui = su * ui, gdr = sd * dr, gdi = sd * di;
+        const int l = l0 + lw + crow(r, h), t = t0 + twv + i32;
+        Pp[(int64_t)l * Tp + t] = make_float2(gur + gdr, gui + gdi);
+        Qp[(int64_t)l * Tp + t] = make_float2(-(gdi - gui), gdr - gur);
+    }
+}
+
+// gY[i][t] = sum_l Wr[l][i] P[l][t] + Wi[l][i] Q'[l][t]  (adjoint of the contraction)
+__global__ void __launch_bounds__(256) k_bwd_gy(const float2* __restrict__ PQ, int Tp, const float2* __restrict__ Wl,
+                                                int Mp, int Kp, float2* __restrict__ gY, int64_t gy_bstride) {
+    __shared__ float As[kKStep][kTileL];
+    __shared__ float2 Bs[kKStep][kTileT];
+    const int it = blockIdx.x, tt = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    const int i0 = it * 64, t0 = tt * kTileT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, i32 = lane & 31;
+    const int iw = (wave >> 1) * 32, twv = (wave & 1) * 32;
+    const float2* PQb = PQ + b * (2 * (int64_t)Mp * Tp);
+    floatx16 are = zero16(), aim = zero16();
+    for (int plane = 0; plane < 2; ++plane) {
+        const float2* Bsrc = PQb + (int64_t)plane * Mp * Tp;
+        for (int k0 = 0; k0 < Mp; k0 += kKStep) {
+            for (int e = tid; e < kKStep * 64; e += 256) {
+                const int row = e >> 6, c = e & 63;
+                float v = 0.f;
+                if (i0 + c < Kp) {
+                    const float2 w = Wl[(int64_t)(k0 + row) * Kp + i0 + c];
+                    v = plane ? w.y : w.x;
+                }
+                As[row][c] = v;
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int f = tid + q * 256, row = f >> 5, c = (f & 31) * 2;
+                *(float4*)&Bs[row][c] = *(const float4*)(Bsrc + (int64_t)(k0 + row) * Tp + t0 + c);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < kKStep / 2; ++ks) {
+                const float a = As[2 * ks + h][iw + i32];
+                const float2 v = Bs[2 * ks + h][twv + i32];
+                are = mfma32(a, v.x, are);
+                aim = mfma32(a, v.y, aim);
+            }
+            __syncthreads();
+        }
+    }
+    float2* o = gY + b * gy_bstride;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = i0 + iw + crow(r, h), t = t0 + twv + i32;
+        if (i < Kp) o[(int64_t)i * Tp + t] = make_float2(are[r], aim[r]);
+    }
+}
+
+// Adjoint of the second order and of S1 for one scalogram row: accumulates the
+// Hermitian half-spectrum of gX,
+//   H[m] = 1/2 sum_alpha psi_hat_alpha[m] G_alpha[m mod Ta] (real part at m = 0, NX/2)
+//        + phi_hat[m] G1[m mod NT],
+// G_alpha = FFT of gY2 rows (done beforehand), G1 = FFT of gS1 row, then the
+// real inverse FFT gives gX[b][lambda][0..NX) (scaled 1/NX).
+__global__ void __launch_bounds__(512) k_scal_bwd_a(const float2* __restrict__ G, int64_t y_bstride,
+                                                    const int64_t* __restrict__ yoff, const int* __restrict__ Tpv,
+                                                    const int* __restrict__ Tav, const float* __restrict__ psi2,
+                                                    const int* __restrict__ band2, const int64_t* __restrict__ off2,
+                                                    int n_alpha, const float* __restrict__ gS1,
+                                                    const float* __restrict__ phiX, int Mphi, int logNT, int logNX,
+                                                    float* __restrict__ gX, const float2* __restrict__ tw, int tw_log) {
+    extern __shared__ float2 s[];
+    const int lam = blockIdx.x, n1 = gridDim.x;
+    const int64_t b = blockIdx.y;
+    const int NX = 1 << logNX, H = NX >> 1, NT = 1 << logNT;
+    float2* g1 = s + H + 1;
+    for (int t = threadIdx.x; t < NT; t += blockDim.x)
+        g1[t] = make_float2(gS1 ? gS1[(b * n1 + lam) * NT + t] : 0.f, 0.f);
+    __syncthreads();
+    lds_fft<32>(g1, logNT, 1, NT, tw, tw_log, false);
+    for (int m = threadIdx.x; m <= H; m += blockDim.x) {
+        float2 c = make_float2(0.f, 0.f);
+        for (int a = 0; a < n_alpha; ++a) {
+            const int lo = band2[2 * a], hi = band2[2 * a + 1];
+            if (m < lo || m > hi) continue;
+            const float g = psi2[off2[a] + m - lo];
+            const float2 v = G[b * y_bstride + yoff[a] + (int64_t)lam * Tpv[a] + (m & (Tav[a] - 1))];
+            c.x += g * v.x;
+            c.y += g * v.y;
+        }
+        float2 hm = (m == 0 || m == H) ? make_float2(c.x, 0.f) : cscale(c, 0.5f);
+        if (m <= Mphi) {
+            const float2 v = g1[m & (NT - 1)];
+            hm.x += phiX[m] * v.x;
+            hm.y += phiX[m] * v.y;
+        }
+        s[m] = hm;
+    }
+    __syncthreads();
+    const int tws = tw_log - logNX;
+    for (int k = threadIdx.x; k <= H / 2; k += blockDim.x) {
+        const float2 p = s[k], q = s[H - k];
+        auto pk = [&](float2 pp, float2 qq, int kk) {
+            const float2 S = make_float2(pp.x + qq.x, pp.y - qq.y);
+            const float2 D = make_float2(pp.x - qq.x, pp.y + qq.y);
+            const float2 wD = cmulc(D, tw[kk << tws]);
+            return make_float2(S.x - wD.y, S.y + wD.x);
+        };
+        const float2 zk = pk(p, q, k);
+        float2 zn = make_float2(0.f, 0.f);
+        const bool two = k > 0 && H - k != k;
+        if (two) zn = pk(q, p, H - k);
+        s[k] = zk;
+        if (two) s[H - k] = zn;
+    }
+    __syncthreads();
+    if (logNX > 1) lds_fft<32>(s, logNX - 1, 1, H, tw, tw_log, true);
+    float2* o = (float2*)(gX + (b * n1 + lam) * (int64_t)NX);
+    const float sc = 1.f / (float)NX;
+    for (int k = threadIdx.x; k < H; k += blockDim.x) o[k] = cscale(s[k], sc);
+}
+
+// Adjoint of the modulus and of the first-order filter for one row: recompute the
+// scalogram-rate filtered signal y, gY1 = gX y / max(|y|, eps), and its FFT
+// (the spectrum that the decimation adjoint replicates): g1[b][lambda][0..NX).
+__global__ void __launch_bounds__(512) k_scal_bwd_b(const float2* __restrict__ xh, int64_t xh_pitch,
+                                                    const float* __restrict__ psi1, const int* __restrict__ band1,
+                                                    const int64_t* __restrict__ off1, const float* __restrict__ gX,
+                                                    float2* __restrict__ g1, int logNX, float invN,
+                                                    const float2* __restrict__ tw, int tw_log) {
+    extern __shared__ float2 s[];
+    const int lam = blockIdx.x, n1 = gridDim.x;
+    const int64_t b = blockIdx.y;
+    const int NX = 1 << logNX;
+    fold_band(s, xh + b * xh_pitch, psi1 + off1[lam], band1[2 * lam], band1[2 * lam + 1], logNX);
+    __syncthreads();
+    lds_fft<32>(s, logNX, 1, NX, tw, tw_log, true);
+    const float* gx = gX + (b * n1 + lam) * (int64_t)NX;
+    for (int n = threadIdx.x; n < NX; n += blockDim.x) {
+        const float2 y = cscale(s[n], invN);
+        const float sc = gx[n] / fmaxf(sqrtf(y.x * y.x + y.y * y.y), kEpsMod);
+        s[n] = cscale(y, sc);
+    }
+    __syncthreads();
+    lds_fft<32>(s, logNX, 1, NX, tw, tw_log, false);
+    float2* o = g1 + (b * n1 + lam) * (int64_t)NX;
+    for (int n = threadIdx.x; n < NX; n += blockDim.x) o[n] = s[n];
+}
+
+// Band-owned accumulation of the first-order adjoint over lambda for bins
+// 0..N/2: K[m] = sum_lambda psi_hat_lambda[m] g1_lambda[m mod NX]; writes the
+// Hermitian half-spectrum of gx (K/2, real part at m = 0 and N/2).
+__global__ void __launch_bounds__(256) k_band_accum(const float2* __restrict__ g1, int n1, int logNX,
+                                                    const float* __restrict__ psi1, const int* __restrict__ band1,
+                                                    const int64_t* __restrict__ off1,
+                                                    const int* __restrict__ lam_range, int Hn,
+                                                    float2* __restrict__ gxh, int64_t pitch) {
+    const int r = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    const int m = r * 256 + threadIdx.x;
+    if (m > Hn) return;
+    const int la = lam_range[2 * r], lb = lam_range[2 * r + 1];
+    const int mask = (1 << logNX) - 1;
+    float2 k = make_float2(0.f, 0.f);
+    for (int lam = la; lam <= lb; ++lam) {
+        const int lo = band1[2 * lam], hi = band1[2 * lam + 1];
+        if (m < lo || m > hi) continue;
+        const float g = psi1[off1[lam] + m - lo];
+        const float2 v = g1[(b * n1 + lam) * (int64_t)(mask + 1) + (m & mask)];
+        k.x += g * v.x;
+        k.y += g * v.y;
+    }
+    gxh[b * pitch + m] = (m == 0 || m == Hn) ? make_float2(k.x, 0.f) : cscale(k, 0.5f);
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+static bool g_attr_done = false;
+
+int setup_kernel_attributes() {
+    if (g_attr_done) return JTFS_OK;
+    const int lds = 160 * 1024;
+    const void* ks[] = {(const void*)k_fft_cols, (const void*)k_scalogram, (const void*)k_s1, (const void*)k_s2_out,
+                        (const void*)k_second_order, (const void*)k_scal_bwd_a, (const void*)k_scal_bwd_b};
+    for (const void* k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) {
+            set_error(std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+            return JTFS_EHIP;
+        }
+    }
+    g_attr_done = true;
+    return JTFS_OK;
+}
+
+// FFT of B rows of length n = 2^logn: in (row pitch ip) -> out (row pitch op),
+// through scratch (pitch n) when n exceeds one LDS transform (four-step).
+static void fft_rows(const float2* in, int64_t ip, float2* out, int64_t op, float2* scratch, int logn, int64_t B,
+                     bool inv, float scale, const jtfs_plan* P, hipStream_t st) {
+    if (logn <= kLdsFftMax) {
+        const int logC = logn >= 12 ? 0 : 12 - logn;       // rows per workgroup
+        const size_t lds = (size_t)(1 << logC) * ((1 << logn) + 1) * sizeof(float2);
+        hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((B + (1 << logC) - 1) >> logC)), dim3(512), lds, st, in, out,
+                           logn, (int)B, logC, (int64_t)0, ip, (int64_t)1, (int64_t)0, op, (int64_t)1, 0, P->tw,
+                           P->tw_log, (int)inv, scale);
+        return;
+    }
+    // n = P Q: input index a + P*bq (a < P columns, bq < Q), output k_b + Q*k_a
+    const int lq = (logn + 1) / 2, lp = logn - lq;
+    const int64_t Pn = (int64_t)1 << lp, Qn = (int64_t)1 << lq;
+    int logC = std::max(0, 12 - lq);
+    logC = std::min(logC, lp);
+    size_t lds = (size_t)(1 << logC) * (Qn + 1) * sizeof(float2);
+    hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)(Pn >> logC), (unsigned)B), dim3(512), lds, st, in, scratch, lq,
+                       (int)Pn, logC, ip, (int64_t)1, Pn, (int64_t)1 << logn, Qn, (int64_t)1, logn, P->tw, P->tw_log,
+                       (int)inv, 1.0f);
+    logC = std::min(std::max(0, 12 - lp), lq);
+    lds = (size_t)(1 << logC) * (Pn + 1) * sizeof(float2);
+    hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)(Qn >> logC), (unsigned)B), dim3(512), lds, st, scratch, out, lp,
+                       (int)Qn, logC, (int64_t)1 << logn, (int64_t)1, Qn, op, (int64_t)1, Qn, 0, P->tw, P->tw_log,
+                       (int)inv, scale);
+}
+
+}  // namespace jtfs
+
+using namespace jtfs;
+
+#define LAUNCHCHK(what)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = hipGetLastError();                                               \
+        if (e_ != hipSuccess) {                                                          \
+            set_error(std::string(what) + ": " + hipGetErrorString(e_));                 \
+            return JTFS_EHIP;                                                            \
+        }                                                                                \
+    } while (0)
+
+static int check_common(const jtfs_plan* P, int64_t B, void* ws, size_t ws_bytes) {
+    if (!P) { set_error("null plan"); return JTFS_EINVAL; }
+    if (B < 1) { set_error("B must be >= 1"); return JTFS_EINVAL; }
+    if (!ws) { set_error("null workspace"); return JTFS_EINVAL; }
+    const Workspace w = layout(P->s, B);
+    if (ws_bytes < w.total) { set_error("workspace too small"); return JTFS_EWORKSPACE; }
+    return JTFS_OK;
+}
+
+extern "C" int jtfs_workspace_size(const jtfs_plan* P, int64_t B, size_t* bytes) {
+    if (!P || !bytes) { set_error("null pointer"); return JTFS_EINVAL; }
+    if (B < 1) { set_error("B must be >= 1"); return JTFS_EINVAL; }
+    *bytes = layout(P->s, B).total;
+    return JTFS_OK;
+}
+
+namespace {
+
+// x -> x_hat -> X_hat -> S1, Y2
+int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char* base, const Workspace& w,
+                  hipStream_t st) {
+    const Shapes& s = P->s;
+    float2* xh = (float2*)(base + w.xh);
+    float2* tmp = (float2*)(base + w.tmp);
+    float2* Xh = (float2*)(base + w.Xh);
+    float2* Y2 = (float2*)(base + w.Y2);
+    const int logH = s.logN - 1;
+    fft_rows((const float2*)x, s.N / 2, xh, w.xh_pitch, tmp, logH, B, false, 1.0f, P, st);
+    LAUNCHCHK("input FFT");
+    hipLaunchKernelGGL(k_rfft_post, dim3((unsigned)(((s.N / 4) + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, xh,
+                       w.xh_pitch, s.logN, P->tw, P->tw_log);
+    LAUNCHCHK("input real-FFT post-processing");
+    hipLaunchKernelGGL(k_scalogram, dim3(s.n1, (unsigned)B), dim3(512), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
+                       P->psi1, P->band1, P->off1, Xh, w.Xh_pitch, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log);
+    LAUNCHCHK("scalogram");
+    if (s1) {
+        const int logNT = s.logN - s.logT;
+        hipLaunchKernelGGL(k_s1, dim3(s.n1, (unsigned)B), dim3(256), sizeof(float2) * s.NT, st, Xh, w.Xh_pitch,
+                           P->phiX, s.Mphi, s.logNX, logNT, 1.0f / (float)s.NX, s1, P->tw, P->tw_log);
+        LAUNCHCHK("first-order lowpass");
+    }
+    for (int a = 0; a < s.n_alpha; ++a) {
+        const int logTa = s.logNX - s.k2[a];
+        const int rows = std::max(1, 4096 >> logTa);
+        const size_t lds = sizeof(float2) * rows * s.Ta[a];
+        const Family& f2 = s.f2;
+        // packed second-order spectrum of alpha: the plan's device table at its offset
+        hipLaunchKernelGGL(k_second_order, dim3((unsigned)((s.Kp + rows - 1) / rows), (unsigned)B), dim3(512), lds, st,
+                           Xh, w.Xh_pitch, s.n1, P->psi2 + f2.off[a], f2.lo[a], f2.hi[a], logTa, s.Tp[a], rows, s.Kp,
+                           Y2 + s.yoff[a], (int64_t)s.Kp * s.sumTp, 1.0f / (float)s.NX, P->tw, P->tw_log);
+        LAUNCHCHK("second order");
+    }
+    return JTFS_OK;
+}
+
+}  // namespace
+
+extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float* s1, float* s2, void* ws,
+                            size_t ws_bytes, hipStream_t st) {
+    int rc = check_common(P, B, ws, ws_bytes);
+    if (rc != JTFS_OK) return rc;
+    if (!x || !s1 || !s2) { set_error("null pointer"); return JTFS_EINVAL; }
+    const Shapes& s = P->s;
+    const Workspace w = layout(s, B);
+    char* base = (char*)ws;
+    rc = forward_front(P, x, B, s1, base, w, st);
+    if (rc != JTFS_OK) return rc;
+    float2* Y2 = (float2*)(base + w.Y2);
+    float* Vp = (float*)(base + w.Vp);
+    const int nlt = s.Mp / kTileL;
+    for (int a = 0; a < s.n_alpha; ++a) {
+        dim3 grid(nlt, s.nch[a], (unsigned)B);
+        const int slot0 = (int)s.vchoff[a] * 2;
+        const float2* Ya = Y2 + s.yoff[a];
+        const float* Ph = P->Phi + s.phioff[a];
+        const int64_t yb = (int64_t)s.Kp * s.sumTp;
+        switch (s.NTp / 32) {
+            case 1: hipLaunchKernelGGL(k_freq_fwd<1>, grid, dim3(256), 0, st, Ya, yb, s.Tp[a], s.chunk[a], P->Wt, s.Mp, s.Kp, Ph, Vp, w.vp_bstride, slot0, nlt); break;
+            case 2: hipLaunchKernelGGL(k_freq_fwd<2>, grid, dim3(256), 0, st, Ya, yb, s.Tp[a], s.chunk[a], P->Wt, s.Mp, s.Kp, Ph, Vp, w.vp_bstride, slot0, nlt); break;
+            case 4: hipLaunchKernelGGL(k_freq_fwd<4>, grid, dim3(256), 0, st, Ya, yb, s.Tp[a], s.chunk[a], P->Wt, s.Mp, s.Kp, Ph, Vp, w.vp_bstride, slot0, nlt); break;
+            default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
+        }
+        LAUNCHCHK("frequential contraction");
+        hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), sizeof(float) * 33 * s.L, st, Vp, w.vp_bstride, slot0,
+                           2 * s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2);
+        LAUNCHCHK("frequency lowpass");
+    }
+    return JTFS_OK;
+}
+
+extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs1, const float* gs2, float* gx,
+                             int64_t B, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t st) {
+    int rc = check_common(P, B, ws, ws_bytes);
+    if (rc != JTFS_OK) return rc;
+    if (!x || !gx) { set_error("null pointer"); return JTFS_EINVAL; }
+    const Shapes& s = P->s;
+    const Workspace w = layout(s, B);
+    char* base = (char*)ws;
+    if (!(flags & JTFS_BWD_REUSE_FORWARD)) {
+        rc = forward_front(P, x, B, nullptr, base, w, st);
+        if (rc != JTFS_OK) return rc;
+    }
+    float2* xh = (float2*)(base + w.xh);
+    float2* tmp = (float2*)(base + w.tmp);
+    float2* Y2 = (float2*)(base + w.Y2);
+    float* gV = (float*)(base + w.gV);
+    float2* PQ = (float2*)(base + w.PQ);
+    float2* gY2 = (float2*)(base + w.gY2);
+    float* gX = (float*)(base + w.gX);
+    float2* g1 = (float2*)(base + w.g1);
+    float2* gxh = (float2*)(base + w.gxh);
+    const int64_t yb = (int64_t)s.Kp * s.sumTp;
+    const int nlt = s.Mp / kTileL;
+    for (int a = 0; a < s.n_alpha; ++a) {
+        hipLaunchKernelGGL(k_s2_bwd, dim3(s.n_beta + 1, 2, (unsigned)B), dim3(256), 0, st, gs2, P->PF, P->d_pfoff, P->d_Lb,
+                           P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, a, s.n_alpha, gV);
+        LAUNCHCHK("frequency lowpass adjoint");
+    }
+    for (int a = 0; a < s.n_alpha; ++a) {
+        dim3 grid(nlt, s.Tp[a] / kTileT, (unsigned)B);
+        const float2* Ya = Y2 + s.yoff[a];
+        const float* Ph = P->Phi + s.phioff[a];
+        const float* gVa = gV + (int64_t)a * 2 * s.Mp * s.NTp;
+        const int64_t gvb = (int64_t)s.n_alpha * 2 * s.Mp * s.NTp;
+        switch (s.NTp / 32) {
+            case 1: hipLaunchKernelGGL(k_bwd_pq<1>, grid, dim3(256), 0, st, Ya, yb, s.Tp[a], P->Wt, s.Mp, s.Kp, Ph, gVa, gvb, PQ); break;
+            case 2: hipLaunchKernelGGL(k_bwd_pq<2>, grid, dim3(256), 0, st, Ya, yb, s.Tp[a], P->Wt, s.Mp, s.Kp, Ph, gVa, gvb, PQ); break;
+            case 4: hipLaunchKernelGGL(k_bwd_pq<4>, grid, dim3(256), 0, st, Ya, yb, s.Tp[a], P->Wt, s.Mp, s.Kp, Ph, gVa, gvb, PQ); break;
+            default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
+        }
+        LAUNCHCHK("contraction adjoint (recompute, modulus)");
+        hipLaunchKernelGGL(k_bwd_gy, dim3((s.Kp + 63) / 64, s.Tp[a] / kTileT, (unsigned)B), dim3(256), 0, st, PQ,
+                           s.Tp[a], P->Wl, s.Mp, s.Kp, gY2 + s.yoff[a], yb);
+        LAUNCHCHK("contraction adjoint (W^H)");
+        // forward FFT of every gY2 row of alpha (length Ta, rows lambda < n1), in place
+        const int logTa = s.logNX - s.k2[a];
+        const int logC = logTa >= 12 ? 0 : 12 - logTa;
+        const size_t lds = (size_t)(1 << logC) * (s.Ta[a] + 1) * sizeof(float2);
+        hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(512), lds,
+                           st, gY2 + s.yoff[a], gY2 + s.yoff[a], logTa, s.n1, logC, yb, (int64_t)s.Tp[a], (int64_t)1,
+                           yb, (int64_t)s.Tp[a], (int64_t)1, 0, P->tw, P->tw_log, 0, 1.0f);
+        LAUNCHCHK("second-order adjoint FFT");
+    }
+    const int logNT = s.logN - s.logT;
+    const size_t lds_a = sizeof(float2) * (s.NX / 2 + 1 + s.NT);
+    hipLaunchKernelGGL(k_scal_bwd_a, dim3(s.n1, (unsigned)B), dim3(512), lds_a, st, gY2, yb, P->d_yoff, P->d_Tp, P->d_Ta, P->psi2,
+                       P->band2, P->off2, s.n_alpha, gs1, P->phiX, s.Mphi, logNT, s.logNX, gX, P->tw, P->tw_log);
+    LAUNCHCHK("scalogram adjoint");
+    hipLaunchKernelGGL(k_scal_bwd_b, dim3(s.n1, (unsigned)B), dim3(512), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
+                       P->psi1, P->band1, P->off1, gX, g1, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log);
+    LAUNCHCHK("modulus and first-order adjoint");
+    const int Hn = (int)(s.N / 2);
+    hipLaunchKernelGGL(k_band_accum, dim3((unsigned)((Hn + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, g1, s.n1,
+                       s.logNX, P->psi1, P->band1, P->off1, P->lam_range, Hn, gxh, w.xh_pitch);
+    LAUNCHCHK("band accumulation");
+    hipLaunchKernelGGL(k_irfft_pack, dim3((unsigned)((Hn / 2 + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, gxh,
+                       w.xh_pitch, tmp, (int64_t)Hn, s.logN, P->tw, P->tw_log);
+    LAUNCHCHK("inverse real-FFT packing");
+    fft_rows(tmp, Hn, (float2*)gx, Hn, gxh, s.logN - 1, B, true, 1.0f / (float)s.N, P, st);
+    LAUNCHCHK("output inverse FFT");
+    return JTFS_OK;
+}
+

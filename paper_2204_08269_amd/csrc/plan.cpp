@@ -1,0 +1,231 @@
+// Host FP64 solve of the JTFS plan (validation, filterbank centres and widths,
+// critical-rate schedule, padded shapes, workspace layout).  No GPU calls.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace jtfs {
+
+static thread_local std::string g_err;
+void set_error(const std::string& s) { g_err = s; }
+const char* last_error() { return g_err.c_str(); }
+
+static bool pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
+static int ilog2(int64_t v) { int k = 0; while ((int64_t(1) << k) < v) ++k; return k; }
+static int64_t rup(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// xi / sigma of a Gaussian-spectrum wavelet whose neighbours 2^(1/Q) apart cross
+// at -3 dB; one wavelet per octave gives about 2.5 (sec. 3.3).
+static double quality_factor(int Q) {
+    const double rho = std::pow(2.0, -1.0 / Q);
+    return (1.0 + rho) / (1.0 - rho) * std::sqrt(std::log(2.0));
+}
+
+// Largest k in [0, cap] leaving a decimated Nyquist 2^-(k+1) of at least kCEnv*sigma
+// (sec. 1: the critical sample rate depends on the band).
+static int critical_log2(double sigma, int cap) {
+    const double v = 1.0 / (2.0 * kCEnv * sigma);
+    int k = v >= 1.0 ? (int)std::floor(std::log2(v)) : 0;
+    return std::min(std::max(k, 0), cap);
+}
+
+// Centres and widths of a Morlet family: constant-Q wavelets xi_max 2^(-n/Q) down
+// to the minimum width kSigma0/2^Jp, then minimum-width wavelets spaced by their
+// -3 dB width (eq. 1 dilations, discretised).
+static bool family_centres(int Jp, int Q, std::vector<double>* xi, std::vector<double>* sg) {
+    const double Qf = quality_factor(Q);
+    const double xi_max = std::max(1.0 / (1.0 + std::pow(2.0, 1.0 / Q)), 0.35);
+    const double smin = kSigma0 / std::pow(2.0, Jp);
+    xi->clear(); sg->clear();
+    for (int n = 0;; ++n) {
+        const double c = xi_max * std::pow(2.0, -(double)n / Q);
+        if (c / Qf < smin) break;
+        xi->push_back(c);
+        sg->push_back(c / Qf);
+        if (n > 100000) return false;
+    }
+    if (xi->empty()) return false;
+    const double delta = 2.0 * std::sqrt(std::log(2.0)) * smin;
+    const double xc = xi->back();
+    for (int k = 1; xc - k * delta >= delta; ++k) {
+        xi->push_back(xc - k * delta);
+        sg->push_back(smin);
+    }
+    return true;
+}
+
+// Bins of an M-point grid (f = m/M, 0 <= m <= M/2) where the un-normalised
+// Morlet spectrum can exceed kSupportTol / 2.
+static void family_supports(Family* f) {
+    const int n = f->n();
+    f->lo.resize(n); f->hi.resize(n); f->off.resize(n);
+    const double R = std::sqrt(2.0 * std::log(2.0 / kSupportTol));
+    int64_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        double a = (f->xi[i] - R * f->sigma[i]) * f->M, b = (f->xi[i] + R * f->sigma[i]) * f->M;
+        int lo = (int)std::max(0.0, std::floor(a));
+        int hi = (int)std::min((double)(f->M / 2), std::ceil(b));
+        if (lo > hi) lo = hi;
+        f->lo[i] = lo; f->hi[i] = hi; f->off[i] = off;
+        off += hi - lo + 1;
+    }
+    f->total = off;
+}
+
+int solve_shapes(const jtfs_params& p, Shapes* s) {
+    *s = Shapes{};
+    s->p = p;
+    if (!pow2(p.N) || !pow2(p.T) || !pow2(p.F)) { set_error("N, T and F must be powers of two"); return JTFS_EINVAL; }
+    if (p.N < 16 || p.N > (int64_t(1) << 24)) { set_error("N must lie in [2^4, 2^24]"); return JTFS_EINVAL; }
+    if (p.T > p.N) { set_error("T must not exceed N"); return JTFS_EINVAL; }
+    if (p.Q1 < 1 || p.Q2 < 1 || p.Q_fr < 1 || p.Q1 > 64 || p.Q2 > 64 || p.Q_fr > 64) {
+        set_error("Q1, Q2 and Q_fr must lie in [1, 64]"); return JTFS_EINVAL; }
+    s->N = p.N; s->T = p.T; s->F = p.F;
+    s->logN = ilog2(p.N); s->logT = ilog2(p.T); s->logF = ilog2(p.F);
+    if (p.J < 1 || p.J > s->logN) { set_error("J must lie in [1, log2 N]"); return JTFS_EINVAL; }
+
+    // first order, cycles/sample on the N grid
+    Family& f1 = s->f1;
+    f1.M = (int)p.N;
+    if (!family_centres(p.J, p.Q1, &f1.xi, &f1.sigma)) { set_error("first-order filterbank is empty"); return JTFS_EINVAL; }
+    s->n1 = f1.n();
+    s->kX = std::min(s->logT, critical_log2(f1.sigma[0], s->logN));
+    s->NX = p.N >> s->kX;
+    s->logNX = s->logN - s->kX;
+    if (p.J - s->kX < 1) { set_error("J - kX must be >= 1"); return JTFS_EINVAL; }
+
+    // second order, cycles per scalogram sample on the NX grid
+    Family& f2 = s->f2;
+    f2.M = (int)s->NX;
+    if (!family_centres(p.J - s->kX, p.Q2, &f2.xi, &f2.sigma)) { set_error("second-order filterbank is empty"); return JTFS_EINVAL; }
+    s->n_alpha = f2.n();
+
+    // frequential, cycles per lambda bin on the zero-padded L grid
+    s->logL = ilog2(s->n1);
+    s->L = 1 << s->logL;
+    if (p.J_fr < 1 || p.J_fr > s->logL) { set_error("J_fr must lie in [1, log2 L]"); return JTFS_EINVAL; }
+    if (p.F > s->L) { set_error("F must not exceed L"); return JTFS_EINVAL; }
+    Family& ff = s->ffr;
+    ff.M = s->L;
+    if (!family_centres(p.J_fr, p.Q_fr, &ff.xi, &ff.sigma)) { set_error("frequential filterbank is empty"); return JTFS_EINVAL; }
+    s->n_beta = ff.n();
+
+    family_supports(&f1);
+    family_supports(&f2);
+    family_supports(&ff);
+
+    // schedules and padded shapes
+    s->NT = (int)(p.N / p.T);
+    s->NTp = (int)rup(s->NT, 32);
+    s->NL = (int)(s->L / p.F);
+    s->Kp = (int)rup(s->n1, kKStep);
+    s->k2.resize(s->n_alpha); s->Ta.resize(s->n_alpha); s->Tp.resize(s->n_alpha);
+    s->nch.resize(s->n_alpha); s->chunk.resize(s->n_alpha);
+    s->yoff.resize(s->n_alpha); s->phioff.resize(s->n_alpha); s->vchoff.resize(s->n_alpha);
+    int64_t yo = 0, po = 0, co = 0;
+    for (int a = 0; a < s->n_alpha; ++a) {
+        s->k2[a] = critical_log2(f2.sigma[a], s->logT - s->kX);
+        s->Ta[a] = (int)(s->NX >> s->k2[a]);
+        s->Tp[a] = std::max(s->Ta[a], kTileT);
+        s->chunk[a] = std::min(s->Tp[a], kChunkT);
+        s->nch[a] = s->Tp[a] / s->chunk[a];
+        s->yoff[a] = yo; s->phioff[a] = po; s->vchoff[a] = co;
+        yo += (int64_t)s->Kp * s->Tp[a];
+        po += (int64_t)s->Tp[a] * s->NTp;
+        co += s->nch[a];
+        s->sumT += s->Ta[a];
+    }
+    s->sumTp = yo / s->Kp;
+    s->sumch = co;
+    s->kfr.resize(s->n_beta); s->Lb.resize(s->n_beta); s->rowoff.resize(s->n_beta); s->pfoff.resize(s->n_beta);
+    int ro = 0; int64_t pf = 0;
+    for (int b = 0; b < s->n_beta; ++b) {
+        s->kfr[b] = critical_log2(ff.sigma[b], s->logF);
+        s->Lb[b] = s->L >> s->kfr[b];
+        s->rowoff[b] = ro; ro += s->Lb[b];
+        s->pfoff[b] = pf; pf += (int64_t)s->NL * s->Lb[b];
+    }
+    s->Mh = ro;
+    s->Mp = (int)rup(ro, kTileL);
+    // phi_T support on the NX grid (frequency m/N cycles/sample)
+    {
+        const double sg = kSigma0 / (double)p.T;
+        const double mm = (double)p.N * sg * std::sqrt(2.0 * std::log(1.0 / kSupportTol));
+        s->Mphi = (int)std::min<double>((double)(s->NX / 2), std::floor(mm) + 1.0);
+    }
+    return JTFS_OK;
+}
+
+int check_supported(const Shapes& s) {
+    if (s.logNX > kLdsFftMax) {
+        set_error("scalogram length N/2^kX above 2^14 is not supported by this build");
+        return JTFS_ENOTSUP;
+    }
+    return JTFS_OK;
+}
+
+Workspace layout(const Shapes& s, int64_t B) {
+    Workspace w;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) / 256 * 256; return r; };
+    w.xh_pitch = s.N / 2 + 1;
+    w.Xh_pitch = s.NX / 2 + 1;
+    w.xh = take(sizeof(float2) * B * w.xh_pitch);
+    w.tmp = take(sizeof(float2) * B * (s.N / 2));
+    w.Xh = take(sizeof(float2) * B * s.n1 * w.Xh_pitch);
+    w.Y2 = take(sizeof(float2) * B * s.Kp * s.sumTp);
+    // partial V: per signal, per (alpha, t-chunk, t-half) slot, per l-tile, spin, tau, l
+    w.vp_bstride = s.sumch * 2 * (s.Mp / kTileL) * 2 * (int64_t)s.NTp * kTileL;
+    w.Vp = take(sizeof(float) * B * w.vp_bstride);
+    w.gV = take(sizeof(float) * B * s.n_alpha * 2 * s.Mp * s.NTp);
+    int64_t maxTp = 0;
+    for (int a = 0; a < s.n_alpha; ++a) maxTp = std::max<int64_t>(maxTp, s.Tp[a]);
+    w.PQ = take(sizeof(float2) * B * 2 * s.Mp * maxTp);
+    w.gY2 = take(sizeof(float2) * B * s.Kp * s.sumTp);
+    w.gX = take(sizeof(float) * B * s.n1 * s.NX);
+    w.g1 = take(sizeof(float2) * B * s.n1 * s.NX);
+    w.gxh = take(sizeof(float2) * B * w.xh_pitch);
+    w.total = o;
+    return w;
+}
+
+}  // namespace jtfs
+
+extern "C" {
+
+const char* jtfs_last_error(void) { return jtfs::last_error(); }
+
+int jtfs_query(const jtfs_params* p, jtfs_info* out) {
+    if (!p || !out) { jtfs::set_error("null pointer"); return JTFS_EINVAL; }
+    jtfs::Shapes s;
+    int st = jtfs::solve_shapes(*p, &s);
+    if (st != JTFS_OK) return st;
+    std::memset(out, 0, sizeof(*out));
+    out->n1 = s.n1; out->n_alpha = s.n_alpha; out->n_beta = s.n_beta; out->L = s.L; out->kX = s.kX;
+    out->M_h = s.Mh; out->NX = s.NX; out->out_t = s.NT; out->out_l = s.NL; out->sum_T = s.sumT;
+    out->s1_per_signal = (int64_t)s.n1 * s.NT;
+    out->s2_per_signal = (int64_t)s.n_alpha * s.n_beta * 2 * s.NL * s.NT;
+    return st;
+}
+
+int jtfs_query_filters(const jtfs_params* p, int family, int32_t cap, double* xi, double* sigma,
+                       int32_t* log2_decim, int32_t* count) {
+    if (!p || !count) { jtfs::set_error("null pointer"); return JTFS_EINVAL; }
+    jtfs::Shapes s;
+    int st = jtfs::solve_shapes(*p, &s);
+    if (st != JTFS_OK) return st;
+    const jtfs::Family* f = family == 0 ? &s.f1 : family == 1 ? &s.f2 : family == 2 ? &s.ffr : nullptr;
+    if (!f) { jtfs::set_error("family must be 0, 1 or 2"); return JTFS_EINVAL; }
+    *count = f->n();
+    if (f->n() > cap) { jtfs::set_error("cap too small"); return JTFS_EINVAL; }
+    for (int i = 0; i < f->n(); ++i) {
+        if (xi) xi[i] = f->xi[i];
+        if (sigma) sigma[i] = f->sigma[i];
+        if (log2_decim) log2_decim[i] = family == 0 ? s.kX : family == 1 ? s.k2[i] : s.kfr[i];
+    }
+    return JTFS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Host-side plan of the JTFS transform: parameter validation, the FP64 solve of
+// every filterbank's centre frequencies and widths, the critical-rate schedule,
+// padded shapes, device table handles and the workspace layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/jtfs.h"
+
+namespace jtfs {
+
+constexpr double kSigma0 = 0.1;    // lowpass width: phi_T has sigma = kSigma0 / T
+constexpr double kCEnv = 5.0;      // critical rate: decimated Nyquist >= kCEnv * sigma
+constexpr double kSupportTol = 1e-13;  // spectra below this (after normalisation) are not stored
+constexpr float kEpsMod = 1e-30f;  // modulus-gradient guard: z / max(|z|, eps)
+
+constexpr int kTileL = 64;         // frequential GEMM: rows (l) per tile
+constexpr int kTileT = 64;         // frequential GEMM: columns (t) per tile
+constexpr int kKStep = 16;         // frequential GEMM: K (lambda_1) per LDS stage
+constexpr int kChunkT = 4096;      // frequential GEMM: t-range reduced by one workgroup
+constexpr int kLdsFftMax = 14;     // log2 of the largest complex FFT held in LDS
+
+void set_error(const std::string& s);
+
+// One Morlet family (sec. 2): centres, widths and band supports on its grid.
+struct Family {
+    int M = 0;                       // grid length (spectrum bins 0..M-1)
+    std::vector<double> xi, sigma;   // centre / Gaussian width in cycles per grid sample
+    std::vector<int> lo, hi;         // stored support [lo, hi], 0 <= lo <= hi <= M/2
+    std::vector<int64_t> off;        // offset of each filter in the packed value table
+    int64_t total = 0;               // packed table length
+    int n() const { return (int)xi.size(); }
+};
+
+struct Shapes {
+    jtfs_params p{};
+    int logN = 0, logT = 0, logF = 0;
+    int n1 = 0, kX = 0, logNX = 0, n_alpha = 0, n_beta = 0, L = 0, logL = 0;
+    int64_t N = 0, NX = 0, T = 0, F = 0;
+    int NT = 0, NTp = 0, NL = 0;     // N/T, padded to 32, L/F
+    int Kp = 0;                      // n1 padded to kKStep
+    int Mh = 0, Mp = 0;              // frequential rows per spin, padded to kTileL
+    std::vector<int> k2, Ta, Tp, nch, chunk;   // per alpha: decimation, length, padded length, t-chunks
+    std::vector<int64_t> yoff, phioff, vchoff; // per alpha offsets
+    int64_t sumTp = 0, sumch = 0, sumT = 0;
+    std::vector<int> kfr, Lb, rowoff;          // per beta
+    std::vector<int64_t> pfoff;
+    int Mphi = 0;                    // phi_T support on the NX grid (bins 0..Mphi)
+    Family f1, f2, ffr;
+};
+
+// Validate and solve; returns JTFS_OK or JTFS_EINVAL with the error set.
+int solve_shapes(const jtfs_params& p, Shapes* s);
+// JTFS_OK if the device path of this build handles the shapes, else JTFS_ENOTSUP.
+int check_supported(const Shapes& s);
+const char* last_error();
+
+// Workspace layout for B signals (byte offsets from the workspace base).
+struct Workspace {
+    size_t xh = 0, tmp = 0, Xh = 0, Y2 = 0, Vp = 0;            // forward
+    size_t gV = 0, PQ = 0, gY2 = 0, gX = 0, g1 = 0, gxh = 0;   // backward
+    int64_t vp_bstride = 0;        // floats of partial V per signal
+    size_t total = 0;
+    int64_t xh_pitch = 0, Xh_pitch = 0;
+};
+Workspace layout(const Shapes& s, int64_t B);
+
+}  // namespace jtfs
+
+struct jtfs_plan {
+    jtfs::Shapes s;
+    int device = 0;
+    int tw_log = 0;
+    float2* tw = nullptr;          // e^{-2 pi i k / 2^tw_log}
+    float* psi1 = nullptr;         // packed first-order spectra (real)
+    int* band1 = nullptr;          // [n1][2] lo, hi
+    int64_t* off1 = nullptr;
+    float* psi2 = nullptr;         // packed second-order spectra
+    int* band2 = nullptr;
+    int64_t* off2 = nullptr;
+    float2* Wt = nullptr;          // frequential wavelet matrix, theta=-1, [Kp][Mp] (k-major)
+    float2* Wl = nullptr;          // same, [Mp][Kp] (row-major)
+    float* Phi = nullptr;          // per alpha [Tp][NTp]: phi_alpha[(tau d - t) mod T_alpha]
+    float* PF = nullptr;           // per beta [NL][Lb]: phi_F[(m F/2^kfr - l) mod Lb]
+    float* phiX = nullptr;         // phi_T spectrum on the NX grid, bins 0..Mphi
+    int* lam_range = nullptr;      // per 256-bin range of 0..N/2: first and last lambda touching it
+    int64_t* d_yoff = nullptr;     // per alpha: offset of its Y2 block
+    int* d_Tp = nullptr;           // per alpha: padded length
+    int* d_Ta = nullptr;           // per alpha: length NX / 2^k2
+    int64_t* d_pfoff = nullptr;    // per beta: offset of its frequency-lowpass matrix
+    int* d_Lb = nullptr;           // per beta: L / 2^kfr
+    int* d_rowoff = nullptr;       // per beta: first row of the contraction
+    double c1 = 0, c2 = 0, cfr = 0;  // Littlewood-Paley normalisations
+    void* owned = nullptr;         // list of device allocations released by destroy
+};

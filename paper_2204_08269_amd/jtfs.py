@@ -1,0 +1,126 @@
+"""PyTorch-facing JTFS module: torch supplies device memory and the stream; the
+transform and its gradient run in libjtfs's HIP kernels (see include/jtfs.h)."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class JTFS:
+    """Joint time-frequency scattering of real signals x [B, N] (float32, on the GPU).
+
+    S1 [B, n1, N/T] and S2 [B, n_alpha, n_beta, 2, L/F, N/T] (spin index 0 is
+    theta = -1).  Calling the object is differentiable through
+    torch.autograd; forward() and vjp() call the library directly."""
+
+    def __init__(self, N, J, Q, J_fr, Q_fr, T, F):
+        if not torch.cuda.is_available():
+            raise RuntimeError("JTFS needs a ROCm GPU (no CPU fallback)")
+        self.lib = _lib.load()
+        self.params = _lib.params(N, J, Q, J_fr, Q_fr, T, F)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        plan = ctypes.c_void_p()
+        _lib.check(self.lib.jtfs_plan_create_ex(ctypes.byref(plan), ctypes.byref(self.params)))
+        self.plan = plan
+        info = _lib.Info()
+        _lib.check(self.lib.jtfs_plan_info(self.plan, ctypes.byref(info)))
+        self.info = info
+        self.N = int(N)
+        self.s1_shape = (info.n1, info.out_t)
+        self.s2_shape = (info.n_alpha, info.n_beta, 2, info.out_l, info.out_t)
+        self._ws = {}
+
+    def __del__(self):
+        try:
+            if getattr(self, "plan", None) is not None and self.plan.value:
+                self.lib.jtfs_plan_destroy(self.plan)
+                self.plan = None
+        except Exception:
+            pass
+
+    def workspace_bytes(self, B: int) -> int:
+        n = ctypes.c_size_t(0)
+        _lib.check(self.lib.jtfs_workspace_size(self.plan, int(B), ctypes.byref(n)))
+        return n.value
+
+    def new_workspace(self, B: int) -> torch.Tensor:
+        return torch.empty(self.workspace_bytes(B), dtype=torch.uint8, device=self.device)
+
+    def _workspace(self, B):
+        ws = self._ws.get(B)
+        if ws is None:
+            ws = self._ws[B] = self.new_workspace(B)
+        return ws
+
+    def _check_x(self, x):
+        if x.dim() != 2 or x.shape[1] != self.N or x.dtype != torch.float32 or not x.is_cuda:
+            raise ValueError(f"x must be a float32 CUDA tensor of shape [B, {self.N}]")
+        return x.contiguous()
+
+    def forward(self, x, ws=None):
+        x = self._check_x(x)
+        B = x.shape[0]
+        ws = self._workspace(B) if ws is None else ws
+        s1 = torch.empty((B,) + self.s1_shape, dtype=torch.float32, device=x.device)
+        s2 = torch.empty((B,) + self.s2_shape, dtype=torch.float32, device=x.device)
+        _lib.check(self.lib.jtfs_forward(self.plan, _ptr(x), B, _ptr(s1), _ptr(s2), _ptr(ws), ws.numel(), _stream()))
+        return s1, s2
+
+    def vjp(self, x, gs1, gs2, ws=None, reuse_forward=False):
+        x = self._check_x(x)
+        B = x.shape[0]
+        ws = self._workspace(B) if ws is None else ws
+        gs1 = gs1.contiguous().float() if gs1 is not None else None
+        gs2 = gs2.contiguous().float() if gs2 is not None else None
+        gx = torch.empty_like(x)
+        flags = _lib.JTFS_BWD_REUSE_FORWARD if reuse_forward else 0
+        _lib.check(self.lib.jtfs_backward(self.plan, _ptr(x), _ptr(gs1), _ptr(gs2), _ptr(gx), B, _ptr(ws),
+                                          ws.numel(), flags, _stream()))
+        return gx
+
+    def table(self, which: int):
+        """Device filter table copied to the host (0: psi1 dense, 1: psi2 dense, 2: W spin -1)."""
+        import numpy as np
+        i = self.info
+        if which == 0:
+            a = np.zeros((i.n1, self.N // 2 + 1), np.float32)
+        elif which == 1:
+            a = np.zeros((i.n_alpha, i.NX // 2 + 1), np.float32)
+        else:
+            a = np.zeros((i.M_h, i.n1), np.complex64)
+        _lib.check(self.lib.jtfs_plan_table(self.plan, which, a.ctypes.data_as(ctypes.c_void_p), a.nbytes))
+        return a
+
+    def __call__(self, x):
+        return _JTFSFunction.apply(x, self)
+
+
+class _JTFSFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, op: JTFS):
+        x = op._check_x(x)
+        ws = op.new_workspace(x.shape[0])          # holds the intermediates for backward
+        s1, s2 = op.forward(x, ws)
+        ctx.op = op
+        ctx.ws = ws
+        ctx.save_for_backward(x)
+        return s1, s2
+
+    @staticmethod
+    def backward(ctx, gs1, gs2):
+        (x,) = ctx.saved_tensors
+        ws = ctx.ws
+        ctx.ws = None
+        gx = ctx.op.vjp(x, gs1, gs2, ws=ws, reuse_forward=True)
+        return gx, None

@@ -1,0 +1,187 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, on seeded
+inputs, per coefficient path (relative L2 <= 1e-5 for the transform)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import jtfs_oracle as O
+from tests._util import oracle_plan, path_errors, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5          # per-path relative L2 of S1 and S2 against FP64
+TOL_VJP = 1e-4      # relative L2 of the gradient against the FP64 oracle's VJP
+TOL_FD = 1e-3       # gradient against FP64 central finite differences
+
+
+def gpu_op(p):
+    from paper_2204_08269_amd.jtfs import JTFS
+    return JTFS(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"])
+
+
+def run_forward(op, x):
+    xt = torch.from_numpy(x).cuda()
+    s1, s2 = op.forward(xt)
+    torch.cuda.synchronize()
+    return s1.cpu().numpy(), s2.cpu().numpy()
+
+
+def check_paths(g1, g2, r1, r2, tol=TOL, alphas=None):
+    e1, _ = path_errors(g1, r1, 1)
+    if alphas is not None:
+        g2 = g2[alphas]
+        r2 = r2[alphas]
+    e2, _ = path_errors(g2, r2, 3)
+    assert e1.max() <= tol, f"S1 worst path error {e1.max():.3e} at {np.unravel_index(e1.argmax(), e1.shape)}"
+    assert e2.max() <= tol, f"S2 worst path error {e2.max():.3e} at {np.unravel_index(e2.argmax(), e2.shape)}"
+    return e1.max(), e2.max()
+
+
+P1 = synth.PARAMS[1]
+RAGGED = [
+    dict(N=2048, J=6, Q=(8, 1), J_fr=3, Q_fr=1, T=2048, F=2),     # T = N: one frame; 224 rows (ragged tile)
+    dict(N=1024, J=5, Q=(4, 1), J_fr=2, Q_fr=1, T=32, F=1),       # F = 1: no log-frequency decimation
+    dict(N=4096, J=7, Q=(12, 2), J_fr=3, Q_fr=2, T=128, F=4),     # Q2 = 2, n1 = 70 (K tail)
+    dict(N=8192, J=9, Q=(6, 1), J_fr=3, Q_fr=1, T=512, F=4),      # kX = 1
+]
+
+
+def test_filter_tables_match_oracle():
+    for p in (P1, synth.PARAMS[2]):
+        op = gpu_op(p)
+        P = oracle_plan(p)
+        t0 = op.table(0)
+        ref0 = P.psi1_hat[:, : p["N"] // 2 + 1]
+        assert np.max(np.abs(t0 - ref0)) <= 2e-7 * np.max(ref0)
+        t1 = op.table(1)
+        ref1 = P.psi2_hat[:, : P.NX // 2 + 1]
+        assert np.max(np.abs(t1 - ref1)) <= 2e-7 * np.max(ref1)
+        t2 = op.table(2)
+        ref2 = np.concatenate([P.freq_wavelet_matrix(b, 0) for b in range(P.n_beta)])
+        assert np.max(np.abs(t2 - ref2)) <= 2e-7 * np.max(np.abs(ref2))
+
+
+def test_forward_parity_cfg1_batch():
+    x = synth.batch(1, B=3)
+    op = gpu_op(P1)
+    g1, g2 = run_forward(op, x)
+    P = oracle_plan(P1)
+    for b in range(3):
+        r1, r2 = O.jtfs(x[b].astype(np.float64), P)
+        check_paths(g1[b], g2[b], r1, r2)
+
+
+@pytest.mark.parametrize("p", RAGGED)
+def test_forward_parity_ragged_shapes(p):
+    rng = np.random.default_rng(p["N"] + p["T"])
+    x = (rng.standard_normal((2, p["N"])) * 0.5).astype(np.float32)
+    op = gpu_op(p)
+    g1, g2 = run_forward(op, x)
+    P = oracle_plan(p)
+    for b in range(2):
+        r1, r2 = O.jtfs(x[b].astype(np.float64), P)
+        check_paths(g1[b], g2[b], r1, r2)
+
+
+def test_forward_parity_cfg2_full_batch_sampled():
+    """64 x 2^16 chirps in the benchmark's launch configuration; the oracle
+    checks two signals on every S1 path and on three temporal rates of S2."""
+    p = synth.PARAMS[2]
+    x = synth.batch(2)
+    op = gpu_op(p)
+    g1, g2 = run_forward(op, x)
+    P = oracle_plan(p)
+    alphas = [0, 6, P.n_alpha - 1]
+    for b in (0, 63):
+        r1, r2 = O.jtfs(x[b].astype(np.float64), P, alphas=alphas)
+        check_paths(g1[b], g2[b], r1, r2, alphas=alphas)
+
+
+def test_pure_tone_closed_form_on_gpu():
+    """S1 of A cos(2 pi m n/N) is (A/2) |psi_hat_lambda(m/N)| and S2 vanishes."""
+    N, m, A = P1["N"], 301, 0.7
+    x = synth.tone(N, m, A, 0.3).astype(np.float32)[None]
+    op = gpu_op(P1)
+    g1, g2 = run_forward(op, x)
+    P = oracle_plan(P1)
+    expect = 0.5 * A * np.abs(P.psi1_hat[:, m])
+    assert np.max(np.abs(g1[0] - expect[:, None])) <= 1e-5 * expect.max()
+    assert np.max(np.abs(g2)) <= 1e-5 * expect.max()
+
+
+def test_zero_input_gives_zero_and_finite_gradient():
+    op = gpu_op(P1)
+    x = torch.zeros((2, P1["N"]), device="cuda")
+    s1, s2 = op.forward(x)
+    g = op.vjp(x, torch.ones_like(s1), torch.ones_like(s2))
+    torch.cuda.synchronize()
+    assert float(s1.abs().max()) == 0.0 and float(s2.abs().max()) == 0.0
+    assert torch.isfinite(g).all() and float(g.abs().max()) == 0.0
+
+
+def test_batch_invariance_and_determinism():
+    x = synth.batch(1, B=4)
+    op = gpu_op(P1)
+    a1, a2 = run_forward(op, x)
+    b1, b2 = run_forward(op, x)
+    assert np.array_equal(a1, b1) and np.array_equal(a2, b2)          # run to run
+    for b in range(4):
+        c1, c2 = run_forward(op, x[b:b + 1])
+        assert np.array_equal(c1[0], a1[b]) and np.array_equal(c2[0], a2[b])   # batch = stacked singles
+
+
+def test_vjp_parity_cfg1():
+    x = synth.batch(1, B=2)
+    P = oracle_plan(P1)
+    gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape())
+    op = gpu_op(P1)
+    xt = torch.from_numpy(x).cuda()
+    g = op.vjp(xt, torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda()).cpu().numpy()
+    for b in range(2):
+        ref = O.jtfs_vjp(x[b].astype(np.float64), gs1[b].astype(np.float64), gs2[b].astype(np.float64), P)
+        err = rel_l2(g[b], ref)
+        assert err <= TOL_VJP, f"signal {b}: relative L2 {err:.3e}"
+
+
+@pytest.mark.parametrize("p", RAGGED[:2])
+def test_vjp_parity_ragged(p):
+    rng = np.random.default_rng(p["N"] + 7)
+    x = (rng.standard_normal((1, p["N"])) * 0.5).astype(np.float32)
+    P = oracle_plan(p)
+    gs1, gs2 = synth.cotangents((1,) + P.s1_shape(), (1,) + P.s2_shape(), seed=3)
+    op = gpu_op(p)
+    g = op.vjp(torch.from_numpy(x).cuda(), torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda()).cpu().numpy()
+    ref = O.jtfs_vjp(x[0].astype(np.float64), gs1[0].astype(np.float64), gs2[0].astype(np.float64), P)
+    assert rel_l2(g[0], ref) <= TOL_VJP
+
+
+def test_gradient_matches_finite_differences():
+    """GPU gradient of <gS, S(x)> against FP64 central differences of the
+    transform along random directions (N = 2048 instance)."""
+    x = synth.batch(1, B=1)
+    P = oracle_plan(P1)
+    gs1, gs2 = synth.cotangents((1,) + P.s1_shape(), (1,) + P.s2_shape())
+    op = gpu_op(P1)
+    g = op.vjp(torch.from_numpy(x).cuda(), torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda())
+    g = g.cpu().numpy()[0].astype(np.float64)
+    x0 = x[0].astype(np.float64)
+    rng = np.random.default_rng(9)
+    for _ in range(3):
+        v = rng.standard_normal(P1["N"])
+        h = 1e-6
+        fd = (O.loss(x0 + h * v, gs1[0], gs2[0], P) - O.loss(x0 - h * v, gs1[0], gs2[0], P)) / (2 * h)
+        assert abs(g @ v - fd) <= TOL_FD * abs(fd)
+
+
+def test_autograd_function_matches_vjp():
+    x = torch.from_numpy(synth.batch(1, B=2)).cuda().requires_grad_(True)
+    op = gpu_op(P1)
+    P = oracle_plan(P1)
+    gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape())
+    gs1, gs2 = torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda()
+    s1, s2 = op(x)
+    ((s1 * gs1).sum() + (s2 * gs2).sum()).backward()
+    g_ref = op.vjp(x.detach(), gs1, gs2)
+    torch.cuda.synchronize()
+    assert torch.equal(x.grad, g_ref)
