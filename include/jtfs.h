@@ -135,6 +135,26 @@ int jtfs_backward(const jtfs_plan* plan, const float* x, const float* gs1, const
  * bytes must equal the table's size.  Synchronous. */
 int jtfs_plan_table(const jtfs_plan* plan, int which, void* host_dst, size_t bytes);
 
+/* Per-stage kernel timing (tracing).  While enabled, every launch of each stage
+ * below is bracketed by a pair of HIP events recorded on the launch's stream.
+ * jtfs_timing_read waits for the recorded events of one stage, returns their
+ * summed duration in milliseconds and the number of launches, and clears that
+ * stage.  Process-wide; thread-safe.  Disabled by default (no events recorded). */
+#define JTFS_STAGE_INPUT_FFT     0   /* real FFT of x                                   */
+#define JTFS_STAGE_SCALOGRAM     1   /* first order: fold, iFFT, modulus, real FFT, S1  */
+#define JTFS_STAGE_SECOND_ORDER  2   /* second-order temporal wavelets                  */
+#define JTFS_STAGE_FREQ_FWD      3   /* frequential contraction + modulus + time lowpass*/
+#define JTFS_STAGE_FREQ_LOWPASS  4   /* frequency lowpass -> S2                         */
+#define JTFS_STAGE_LOWPASS_ADJ   5   /* adjoint of the frequency lowpass                */
+#define JTFS_STAGE_FREQ_ADJ_PQ   6   /* contraction recompute, lowpass and modulus adj. */
+#define JTFS_STAGE_FREQ_ADJ_WH   7   /* adjoint of the contraction (W^H)                */
+#define JTFS_STAGE_SECOND_ADJ    8   /* second-order and S1 adjoints                    */
+#define JTFS_STAGE_FIRST_ADJ     9   /* modulus and first-order adjoints, accumulation  */
+#define JTFS_STAGE_OUTPUT_FFT   10   /* inverse real FFT to gx                          */
+#define JTFS_NUM_STAGES         11
+int jtfs_timing_enable(int on);
+int jtfs_timing_read(int stage, double* ms, int64_t* launches);
+
 /* Thread-local text of the last error ("" if none). */
 const char* jtfs_last_error(void);
 

@@ -18,6 +18,8 @@ JTFS_EHIP = -3
 JTFS_EWORKSPACE = -4
 JTFS_ENOTSUP = -6
 JTFS_BWD_REUSE_FORWARD = 1
+STAGES = ["input_fft", "scalogram", "second_order", "freq_fwd", "freq_lowpass", "lowpass_adj", "freq_adj_pq",
+          "freq_adj_wh", "second_adj", "first_adj", "output_fft"]
 
 
 class Params(ctypes.Structure):
@@ -34,7 +36,7 @@ class Info(ctypes.Structure):
 
 EXPORTS = ["jtfs_query", "jtfs_query_filters", "jtfs_plan_create", "jtfs_plan_create_ex", "jtfs_plan_info",
            "jtfs_plan_destroy", "jtfs_workspace_size", "jtfs_forward", "jtfs_backward", "jtfs_plan_table",
-           "jtfs_last_error"]
+           "jtfs_timing_enable", "jtfs_timing_read", "jtfs_last_error"]
 
 _lib = None
 
@@ -68,6 +70,8 @@ def load(path: str = LIB_PATH):
     L.jtfs_forward.argtypes = [vp, vp, i64, vp, vp, vp, sz, vp]
     L.jtfs_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, sz, u32, vp]
     L.jtfs_plan_table.argtypes = [vp, ctypes.c_int, vp, sz]
+    L.jtfs_timing_enable.argtypes = [ctypes.c_int]
+    L.jtfs_timing_read.argtypes = [ctypes.c_int, P(ctypes.c_double), P(i64)]
     L.jtfs_last_error.argtypes = []
     L.jtfs_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -105,3 +109,18 @@ def query_filters(p: Params, family: int):
     check(L.jtfs_query_filters(ctypes.byref(p), family, cap, xi, sg, k, ctypes.byref(cnt)))
     n = cnt.value
     return np.array(xi[:n]), np.array(sg[:n]), np.array(k[:n])
+
+
+def timing_enable(on: bool):
+    check(load().jtfs_timing_enable(1 if on else 0))
+
+
+def timing_read():
+    """{stage name: (total ms, launches)} for every stage; clears the records."""
+    out = {}
+    for i, name in enumerate(STAGES):
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        check(load().jtfs_timing_read(i, ctypes.byref(ms), ctypes.byref(n)))
+        out[name] = (ms.value, n.value)
+    return out

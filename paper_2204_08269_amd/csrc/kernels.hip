@@ -11,6 +11,7 @@
 
 #include "fft_lds.hpp"
 #include "plan.hpp"
+#include "timing.hpp"
 
 namespace jtfs {
 
@@ -747,18 +748,18 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
     float2* Xh = (float2*)(base + w.Xh);
     float2* Y2 = (float2*)(base + w.Y2);
     const int logH = s.logN - 1;
-    fft_rows((const float2*)x, s.N / 2, xh, w.xh_pitch, tmp, logH, B, false, 1.0f, P, st);
+    JTFS_TIMED(JTFS_STAGE_INPUT_FFT, st, fft_rows((const float2*)x, s.N / 2, xh, w.xh_pitch, tmp, logH, B, false, 1.0f, P, st));
     LAUNCHCHK("input FFT");
-    hipLaunchKernelGGL(k_rfft_post, dim3((unsigned)(((s.N / 4) + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, xh,
-                       w.xh_pitch, s.logN, P->tw, P->tw_log);
+    JTFS_TIMED(JTFS_STAGE_INPUT_FFT, st, hipLaunchKernelGGL(k_rfft_post, dim3((unsigned)(((s.N / 4) + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, xh,
+                       w.xh_pitch, s.logN, P->tw, P->tw_log));
     LAUNCHCHK("input real-FFT post-processing");
-    hipLaunchKernelGGL(k_scalogram, dim3(s.n1, (unsigned)B), dim3(512), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
-                       P->psi1, P->band1, P->off1, Xh, w.Xh_pitch, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log);
+    JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, hipLaunchKernelGGL(k_scalogram, dim3(s.n1, (unsigned)B), dim3(512), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
+                       P->psi1, P->band1, P->off1, Xh, w.Xh_pitch, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log));
     LAUNCHCHK("scalogram");
     if (s1) {
         const int logNT = s.logN - s.logT;
-        hipLaunchKernelGGL(k_s1, dim3(s.n1, (unsigned)B), dim3(256), sizeof(float2) * s.NT, st, Xh, w.Xh_pitch,
-                           P->phiX, s.Mphi, s.logNX, logNT, 1.0f / (float)s.NX, s1, P->tw, P->tw_log);
+        JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, hipLaunchKernelGGL(k_s1, dim3(s.n1, (unsigned)B), dim3(256), sizeof(float2) * s.NT, st, Xh, w.Xh_pitch,
+                           P->phiX, s.Mphi, s.logNX, logNT, 1.0f / (float)s.NX, s1, P->tw, P->tw_log));
         LAUNCHCHK("first-order lowpass");
     }
     for (int a = 0; a < s.n_alpha; ++a) {
@@ -767,9 +768,9 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
         const size_t lds = sizeof(float2) * rows * s.Ta[a];
         const Family& f2 = s.f2;
         // packed second-order spectrum of alpha: the plan's device table at its offset
-        hipLaunchKernelGGL(k_second_order, dim3((unsigned)((s.Kp + rows - 1) / rows), (unsigned)B), dim3(512), lds, st,
+        JTFS_TIMED(JTFS_STAGE_SECOND_ORDER, st, hipLaunchKernelGGL(k_second_order, dim3((unsigned)((s.Kp + rows - 1) / rows), (unsigned)B), dim3(512), lds, st,
                            Xh, w.Xh_pitch, s.n1, P->psi2 + f2.off[a], f2.lo[a], f2.hi[a], logTa, s.Tp[a], rows, s.Kp,
-                           Y2 + s.yoff[a], (int64_t)s.Kp * s.sumTp, 1.0f / (float)s.NX, P->tw, P->tw_log);
+                           Y2 + s.yoff[a], (int64_t)s.Kp * s.sumTp, 1.0f / (float)s.NX, P->tw, P->tw_log));
         LAUNCHCHK("second order");
     }
     return JTFS_OK;
@@ -796,6 +797,8 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
         const float2* Ya = Y2 + s.yoff[a];
         const float* Ph = P->Phi + s.phioff[a];
         const int64_t yb = (int64_t)s.Kp * s.sumTp;
+        {
+        TimedLaunch tl_fwd(JTFS_STAGE_FREQ_FWD, st);
         switch (s.NTp / 32) {
             case 1: hipLaunchKernelGGL(k_freq_fwd<1>, grid, dim3(256), 0, st, Ya, yb, s.Tp[a], s.chunk[a], P->Wt, s.Mp, s.Kp, Ph, Vp, w.vp_bstride, slot0, nlt); break;
             case 2: hipLaunchKernelGGL(k_freq_fwd<2>, grid, dim3(256), 0, st, Ya, yb, s.Tp[a], s.chunk[a], P->Wt, s.Mp, s.Kp, Ph, Vp, w.vp_bstride, slot0, nlt); break;
@@ -803,8 +806,9 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
             default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
         }
         LAUNCHCHK("frequential contraction");
-        hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), sizeof(float) * 33 * s.L, st, Vp, w.vp_bstride, slot0,
-                           2 * s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2);
+        }
+        JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), sizeof(float) * 33 * s.L, st, Vp, w.vp_bstride, slot0,
+                           2 * s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2));
         LAUNCHCHK("frequency lowpass");
     }
     return JTFS_OK;
@@ -834,8 +838,8 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     const int64_t yb = (int64_t)s.Kp * s.sumTp;
     const int nlt = s.Mp / kTileL;
     for (int a = 0; a < s.n_alpha; ++a) {
-        hipLaunchKernelGGL(k_s2_bwd, dim3(s.n_beta + 1, 2, (unsigned)B), dim3(256), 0, st, gs2, P->PF, P->d_pfoff, P->d_Lb,
-                           P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, a, s.n_alpha, gV);
+        JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_s2_bwd, dim3(s.n_beta + 1, 2, (unsigned)B), dim3(256), 0, st, gs2, P->PF, P->d_pfoff, P->d_Lb,
+                           P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, a, s.n_alpha, gV));
         LAUNCHCHK("frequency lowpass adjoint");
     }
     for (int a = 0; a < s.n_alpha; ++a) {
@@ -844,6 +848,8 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
         const float* Ph = P->Phi + s.phioff[a];
         const float* gVa = gV + (int64_t)a * 2 * s.Mp * s.NTp;
         const int64_t gvb = (int64_t)s.n_alpha * 2 * s.Mp * s.NTp;
+        {
+        TimedLaunch tl_pq(JTFS_STAGE_FREQ_ADJ_PQ, st);
         switch (s.NTp / 32) {
             case 1: hipLaunchKernelGGL(k_bwd_pq<1>, grid, dim3(256), 0, st, Ya, yb, s.Tp[a], P->Wt, s.Mp, s.Kp, Ph, gVa, gvb, PQ); break;
             case 2: hipLaunchKernelGGL(k_bwd_pq<2>, grid, dim3(256), 0, st, Ya, yb, s.Tp[a], P->Wt, s.Mp, s.Kp, Ph, gVa, gvb, PQ); break;
@@ -851,34 +857,35 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
             default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
         }
         LAUNCHCHK("contraction adjoint (recompute, modulus)");
-        hipLaunchKernelGGL(k_bwd_gy, dim3((s.Kp + 63) / 64, s.Tp[a] / kTileT, (unsigned)B), dim3(256), 0, st, PQ,
-                           s.Tp[a], P->Wl, s.Mp, s.Kp, gY2 + s.yoff[a], yb);
+        }
+        JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_WH, st, hipLaunchKernelGGL(k_bwd_gy, dim3((s.Kp + 63) / 64, s.Tp[a] / kTileT, (unsigned)B), dim3(256), 0, st, PQ,
+                           s.Tp[a], P->Wl, s.Mp, s.Kp, gY2 + s.yoff[a], yb));
         LAUNCHCHK("contraction adjoint (W^H)");
         // forward FFT of every gY2 row of alpha (length Ta, rows lambda < n1), in place
         const int logTa = s.logNX - s.k2[a];
         const int logC = logTa >= 12 ? 0 : 12 - logTa;
         const size_t lds = (size_t)(1 << logC) * (s.Ta[a] + 1) * sizeof(float2);
-        hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(512), lds,
+        JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(512), lds,
                            st, gY2 + s.yoff[a], gY2 + s.yoff[a], logTa, s.n1, logC, yb, (int64_t)s.Tp[a], (int64_t)1,
-                           yb, (int64_t)s.Tp[a], (int64_t)1, 0, P->tw, P->tw_log, 0, 1.0f);
+                           yb, (int64_t)s.Tp[a], (int64_t)1, 0, P->tw, P->tw_log, 0, 1.0f));
         LAUNCHCHK("second-order adjoint FFT");
     }
     const int logNT = s.logN - s.logT;
     const size_t lds_a = sizeof(float2) * (s.NX / 2 + 1 + s.NT);
-    hipLaunchKernelGGL(k_scal_bwd_a, dim3(s.n1, (unsigned)B), dim3(512), lds_a, st, gY2, yb, P->d_yoff, P->d_Tp, P->d_Ta, P->psi2,
-                       P->band2, P->off2, s.n_alpha, gs1, P->phiX, s.Mphi, logNT, s.logNX, gX, P->tw, P->tw_log);
+    JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_a, dim3(s.n1, (unsigned)B), dim3(512), lds_a, st, gY2, yb, P->d_yoff, P->d_Tp, P->d_Ta, P->psi2,
+                       P->band2, P->off2, s.n_alpha, gs1, P->phiX, s.Mphi, logNT, s.logNX, gX, P->tw, P->tw_log));
     LAUNCHCHK("scalogram adjoint");
-    hipLaunchKernelGGL(k_scal_bwd_b, dim3(s.n1, (unsigned)B), dim3(512), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
-                       P->psi1, P->band1, P->off1, gX, g1, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log);
+    JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_b, dim3(s.n1, (unsigned)B), dim3(512), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
+                       P->psi1, P->band1, P->off1, gX, g1, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log));
     LAUNCHCHK("modulus and first-order adjoint");
     const int Hn = (int)(s.N / 2);
-    hipLaunchKernelGGL(k_band_accum, dim3((unsigned)((Hn + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, g1, s.n1,
-                       s.logNX, P->psi1, P->band1, P->off1, P->lam_range, Hn, gxh, w.xh_pitch);
+    JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, hipLaunchKernelGGL(k_band_accum, dim3((unsigned)((Hn + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, g1, s.n1,
+                       s.logNX, P->psi1, P->band1, P->off1, P->lam_range, Hn, gxh, w.xh_pitch));
     LAUNCHCHK("band accumulation");
-    hipLaunchKernelGGL(k_irfft_pack, dim3((unsigned)((Hn / 2 + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, gxh,
-                       w.xh_pitch, tmp, (int64_t)Hn, s.logN, P->tw, P->tw_log);
+    JTFS_TIMED(JTFS_STAGE_OUTPUT_FFT, st, hipLaunchKernelGGL(k_irfft_pack, dim3((unsigned)((Hn / 2 + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, gxh,
+                       w.xh_pitch, tmp, (int64_t)Hn, s.logN, P->tw, P->tw_log));
     LAUNCHCHK("inverse real-FFT packing");
-    fft_rows(tmp, Hn, (float2*)gx, Hn, gxh, s.logN - 1, B, true, 1.0f / (float)s.N, P, st);
+    JTFS_TIMED(JTFS_STAGE_OUTPUT_FFT, st, fft_rows(tmp, Hn, (float2*)gx, Hn, gxh, s.logN - 1, B, true, 1.0f / (float)s.N, P, st));
     LAUNCHCHK("output inverse FFT");
     return JTFS_OK;
 }

@@ -92,3 +92,13 @@ def test_null_pointers_rejected(L):
     assert lib.jtfs_backward(None, None, None, None, None, 1, None, 0, 0, None) == L.JTFS_EINVAL
     assert lib.jtfs_workspace_size(None, 1, None) == L.JTFS_EINVAL
     lib.jtfs_plan_destroy(None)
+
+
+def test_timing_api_host_side(L):
+    lib = L.load()
+    ms = ctypes.c_double(1.0)
+    n = ctypes.c_int64(5)
+    assert lib.jtfs_timing_read(99, ctypes.byref(ms), ctypes.byref(n)) == L.JTFS_EINVAL
+    assert lib.jtfs_timing_read(0, ctypes.byref(ms), ctypes.byref(n)) == L.JTFS_OK
+    assert ms.value == 0.0 and n.value == 0
+    assert lib.jtfs_timing_enable(0) == L.JTFS_OK
