@@ -1,5 +1,5 @@
-// Batched power-of-two complex FFT held in LDS (Stockham autosort, radix 4 with
-// one radix-2 pass for odd log2 sizes).  Every pass reads all of a thread's
+// Batched power-of-two complex FFT held in LDS (Stockham autosort: radix-8 passes,
+// then one radix-4 or radix-2 pass).  Every pass reads all of a thread's
 // butterfly inputs, waits at a barrier, and writes the outputs back in place, so
 // a single LDS buffer suffices.  Twiddles come from an FP64-generated table
 // tw[k] = exp(-2 pi i k / 2^tw_log) (no recurrences), conjugated for the inverse.
@@ -26,6 +26,17 @@ __device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int k, 
     float2 w = tw[k];
     if (inv) w.y = -w.y;
     return w;
+}
+
+// In-register 4-point DFT (sign -1 forward, +1 inverse).
+__device__ __forceinline__ void dft4(float2* a, bool inv) {
+    const float2 t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]), t2 = cadd(a[1], a[3]);
+    const float2 d = csub(a[1], a[3]);
+    const float2 t3 = inv ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);   // d * (s i)
+    a[0] = cadd(t0, t2);
+    a[2] = csub(t0, t2);
+    a[1] = cadd(t1, t3);
+    a[3] = csub(t1, t3);
 }
 
 // One Stockham pass of radix R = 2^LR over `count` transforms of length 2^logn
@@ -59,16 +70,31 @@ __device__ __forceinline__ void fft_pass(float2* s, int logn, int count, int str
                 const float2 a0 = v[q][0], a1 = v[q][1];
                 v[q][0] = cadd(a0, a1);
                 v[q][1] = csub(a0, a1);
+            } else if constexpr (R == 4) {
+                dft4(v[q], inv);
             } else {
-                const float2 a0 = v[q][0], a1 = v[q][1], a2 = v[q][2], a3 = v[q][3];
-                const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3);
-                const float2 d = csub(a1, a3);
-                // (a1 - a3) times (s i), s = -1 forward, +1 inverse
-                const float2 t3 = inv ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
-                v[q][0] = cadd(t0, t2);
-                v[q][2] = csub(t0, t2);
-                v[q][1] = cadd(t1, t3);
-                v[q][3] = csub(t1, t3);
+                // 8-point DFT as two 4-point DFTs: X[2q] = DFT4(a_r + a_{r+4}),
+                // X[2q+1] = DFT4((a_r - a_{r+4}) w8^r)
+                float2 b[4], c[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    b[r] = cadd(v[q][r], v[q][r + 4]);
+                    c[r] = csub(v[q][r], v[q][r + 4]);
+                }
+                const float h = 0.70710678118654752f;
+                // c1 *= w8, c2 *= w8^2 = -/+ i, c3 *= w8^3
+                c[1] = inv ? make_float2(h * (c[1].x - c[1].y), h * (c[1].x + c[1].y))
+                           : make_float2(h * (c[1].x + c[1].y), h * (c[1].y - c[1].x));
+                c[2] = inv ? make_float2(-c[2].y, c[2].x) : make_float2(c[2].y, -c[2].x);
+                c[3] = inv ? make_float2(-h * (c[3].x + c[3].y), h * (c[3].x - c[3].y))
+                           : make_float2(h * (c[3].y - c[3].x), -h * (c[3].x + c[3].y));
+                dft4(b, inv);
+                dft4(c, inv);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    v[q][2 * r] = b[r];
+                    v[q][2 * r + 1] = c[r];
+                }
             }
         }
     }
@@ -92,17 +118,16 @@ __device__ __forceinline__ void fft_pass(float2* s, int logn, int count, int str
 // taking part; count * 2^logn <= MAXE * blockDim.x.  Starts and ends with the
 // data in LDS; the caller must __syncthreads() before calling.
 template <int MAXE>
-__device__ void lds_fft(float2* s, int logn, int count, int stride, const float2* __restrict__ tw,
+__device__ __forceinline__ void lds_fft(float2* s, int logn, int count, int stride, const float2* __restrict__ tw,
                         int tw_log, bool inv) {
     int lNs = 0;
-    if (logn & 1) {
-        fft_pass<1, MAXE>(s, logn, count, stride, lNs, tw, tw_log, inv);
-        lNs += 1;
+    // radix-8 passes while three or more stages remain, then one radix-4 or radix-2
+    while (logn - lNs >= 3) {
+        fft_pass<3, MAXE>(s, logn, count, stride, lNs, tw, tw_log, inv);
+        lNs += 3;
     }
-    while (lNs < logn) {
-        fft_pass<2, MAXE>(s, logn, count, stride, lNs, tw, tw_log, inv);
-        lNs += 2;
-    }
+    if (logn - lNs == 2) fft_pass<2, MAXE>(s, logn, count, stride, lNs, tw, tw_log, inv);
+    if (logn - lNs == 1) fft_pass<1, MAXE>(s, logn, count, stride, lNs, tw, tw_log, inv);
 }
 
 }  // namespace jtfs

@@ -38,7 +38,7 @@ __device__ __forceinline__ int crow(int r, int h) { return 8 * (r >> 2) + 4 * h 
 // Column mode (ics == 1): C = 2^logC adjacent transforms per workgroup, loaded
 // with adjacent columns on adjacent threads.  Row mode: transforms contiguous.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(512) k_fft_cols(const float2* in, float2* out, int loglen,
+__global__ void __launch_bounds__(1024) k_fft_cols(const float2* in, float2* out, int loglen,
                                                   int ncols, int logC, int64_t ib, int64_t ics, int64_t ies, int64_t ob,
                                                   int64_t ocs, int64_t oes, int twl, const float2* __restrict__ tw,
                                                   int tw_log, int inv, float scale) {
@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(512) k_fft_cols(const float2* in, float2* out,
         }
     }
     __syncthreads();
-    lds_fft<32>(s, loglen, nc, st, tw, tw_log, inv != 0);
+    lds_fft<16>(s, loglen, nc, st, tw, tw_log, inv != 0);
     const int tws = tw_log - twl;
     if (ocs == 1) {
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
@@ -152,7 +152,7 @@ __device__ __forceinline__ void fold_band(float2* s, const float2* __restrict__ 
     }
 }
 
-__global__ void __launch_bounds__(512) k_scalogram(const float2* __restrict__ xh, int64_t xh_pitch,
+__global__ void __launch_bounds__(1024) k_scalogram(const float2* __restrict__ xh, int64_t xh_pitch,
                                                    const float* __restrict__ psi1, const int* __restrict__ band1,
                                                    const int64_t* __restrict__ off1, float2* __restrict__ Xh,
                                                    int64_t Xh_pitch, int logNX, float invN,
@@ -163,12 +163,12 @@ __global__ void __launch_bounds__(512) k_scalogram(const float2* __restrict__ xh
     const int NX = 1 << logNX, H = NX >> 1;
     fold_band(s, xh + b * xh_pitch, psi1 + off1[lam], band1[2 * lam], band1[2 * lam + 1], logNX);
     __syncthreads();
-    lds_fft<32>(s, logNX, 1, NX, tw, tw_log, true);
+    lds_fft<16>(s, logNX, 1, NX, tw, tw_log, true);
     // modulus of the scalogram-rate samples, packed as z[k] = X[2k] + i X[2k+1]
     {
-        float2 v[16];
+        float2 v[8];   // H <= 8192 = 8 * blockDim
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < 8; ++q) {
             const int k = threadIdx.x + q * blockDim.x;
             if (k < H) {
                 const float2 a = s[2 * k], c = s[2 * k + 1];
@@ -177,13 +177,13 @@ __global__ void __launch_bounds__(512) k_scalogram(const float2* __restrict__ xh
         }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < 8; ++q) {
             const int k = threadIdx.x + q * blockDim.x;
             if (k < H) s[k] = v[q];
         }
         __syncthreads();
     }
-    if (logNX > 1) lds_fft<32>(s, logNX - 1, 1, H, tw, tw_log, false);
+    if (logNX > 1) lds_fft<16>(s, logNX - 1, 1, H, tw, tw_log, false);
     float2* out = Xh + (b * n1 + lam) * Xh_pitch;
     const int tws = tw_log - logNX;
     for (int m = threadIdx.x; m <= H / 2; m += blockDim.x) {
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(256) k_s1(const float2* __restrict__ Xh, int64
 
 // Second order: Y2[b][alpha][lambda][t] = (X_lambda (*) psi_alpha)[t 2^k2] for t < Ta,
 // zero for Ta <= t < Tp and for lambda >= n1 (the K padding of the contraction).
-__global__ void __launch_bounds__(512) k_second_order(const float2* __restrict__ Xh, int64_t Xh_pitch, int n1,
+__global__ void __launch_bounds__(1024) k_second_order(const float2* __restrict__ Xh, int64_t Xh_pitch, int n1,
                                                       const float* __restrict__ ps, int lo, int hi, int logTa, int Tp,
                                                       int rows, int Kp, float2* __restrict__ Y, int64_t y_bstride,
                                                       float invNX, const float2* __restrict__ tw, int tw_log) {
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(512) k_second_order(const float2* __restrict__
         s[e] = acc;
     }
     __syncthreads();
-    lds_fft<32>(s, logTa, nr, Ta, tw, tw_log, true);
+    lds_fft<16>(s, logTa, nr, Ta, tw, tw_log, true);
     float2* out = Y + b * y_bstride + (int64_t)r0 * Tp;
     for (int e = threadIdx.x; e < nr * Tp; e += blockDim.x) {
         const int c = e / Tp, t = e - c * Tp;
@@ -548,7 +548,7 @@ __global__ void __launch_bounds__(256) k_bwd_gy(const float2* __restrict__ PQ, i
 //        + phi_hat[m] G1[m mod NT],
 // G_alpha = FFT of gY2 rows (done beforehand), G1 = FFT of gS1 row, then the
 // real inverse FFT gives gX[b][lambda][0..NX) (scaled 1/NX).
-__global__ void __launch_bounds__(512) k_scal_bwd_a(const float2* __restrict__ G, int64_t y_bstride,
+__global__ void __launch_bounds__(1024) k_scal_bwd_a(const float2* __restrict__ G, int64_t y_bstride,
                                                     const int64_t* __restrict__ yoff, const int* __restrict__ Tpv,
                                                     const int* __restrict__ Tav, const float* __restrict__ psi2,
                                                     const int* __restrict__ band2, const int64_t* __restrict__ off2,
@@ -563,7 +563,7 @@ __global__ void __launch_bounds__(512) k_scal_bwd_a(const float2* __restrict__ G
     for (int t = threadIdx.x; t < NT; t += blockDim.x)
         g1[t] = make_float2(gS1 ? gS1[(b * n1 + lam) * NT + t] : 0.f, 0.f);
     __syncthreads();
-    lds_fft<32>(g1, logNT, 1, NT, tw, tw_log, false);
+    lds_fft<16>(g1, logNT, 1, NT, tw, tw_log, false);
     for (int m = threadIdx.x; m <= H; m += blockDim.x) {
         float2 c = make_float2(0.f, 0.f);
         for (int a = 0; a < n_alpha; ++a) {
@@ -600,7 +600,7 @@ __global__ void __launch_bounds__(512) k_scal_bwd_a(const float2* __restrict__ G
         if (two) s[H - k] = zn;
     }
     __syncthreads();
-    if (logNX > 1) lds_fft<32>(s, logNX - 1, 1, H, tw, tw_log, true);
+    if (logNX > 1) lds_fft<16>(s, logNX - 1, 1, H, tw, tw_log, true);
     float2* o = (float2*)(gX + (b * n1 + lam) * (int64_t)NX);
     const float sc = 1.f / (float)NX;
     for (int k = threadIdx.x; k < H; k += blockDim.x) o[k] = cscale(s[k], sc);
@@ -609,7 +609,7 @@ __global__ void __launch_bounds__(512) k_scal_bwd_a(const float2* __restrict__ G
 // Adjoint of the modulus and of the first-order filter for one row: recompute the
 // scalogram-rate filtered signal y, gY1 = gX y / max(|y|, eps), and its FFT
 // (the spectrum that the decimation adjoint replicates): g1[b][lambda][0..NX).
-__global__ void __launch_bounds__(512) k_scal_bwd_b(const float2* __restrict__ xh, int64_t xh_pitch,
+__global__ void __launch_bounds__(1024) k_scal_bwd_b(const float2* __restrict__ xh, int64_t xh_pitch,
                                                     const float* __restrict__ psi1, const int* __restrict__ band1,
                                                     const int64_t* __restrict__ off1, const float* __restrict__ gX,
                                                     float2* __restrict__ g1, int logNX, float invN,
@@ -620,7 +620,7 @@ __global__ void __launch_bounds__(512) k_scal_bwd_b(const float2* __restrict__ x
     const int NX = 1 << logNX;
     fold_band(s, xh + b * xh_pitch, psi1 + off1[lam], band1[2 * lam], band1[2 * lam + 1], logNX);
     __syncthreads();
-    lds_fft<32>(s, logNX, 1, NX, tw, tw_log, true);
+    lds_fft<16>(s, logNX, 1, NX, tw, tw_log, true);
     const float* gx = gX + (b * n1 + lam) * (int64_t)NX;
     for (int n = threadIdx.x; n < NX; n += blockDim.x) {
         const float2 y = cscale(s[n], invN);
@@ -628,7 +628,7 @@ __global__ void __launch_bounds__(512) k_scal_bwd_b(const float2* __restrict__ x
         s[n] = cscale(y, sc);
     }
     __syncthreads();
-    lds_fft<32>(s, logNX, 1, NX, tw, tw_log, false);
+    lds_fft<16>(s, logNX, 1, NX, tw, tw_log, false);
     float2* o = g1 + (b * n1 + lam) * (int64_t)NX;
     for (int n = threadIdx.x; n < NX; n += blockDim.x) o[n] = s[n];
 }
@@ -687,7 +687,7 @@ static void fft_rows(const float2* in, int64_t ip, float2* out, int64_t op, floa
     if (logn <= kLdsFftMax) {
         const int logC = logn >= 12 ? 0 : 12 - logn;       // rows per workgroup
         const size_t lds = (size_t)(1 << logC) * ((1 << logn) + 1) * sizeof(float2);
-        hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((B + (1 << logC) - 1) >> logC)), dim3(512), lds, st, in, out,
+        hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((B + (1 << logC) - 1) >> logC)), dim3(1024), lds, st, in, out,
                            logn, (int)B, logC, (int64_t)0, ip, (int64_t)1, (int64_t)0, op, (int64_t)1, 0, P->tw,
                            P->tw_log, (int)inv, scale);
         return;
@@ -698,12 +698,12 @@ static void fft_rows(const float2* in, int64_t ip, float2* out, int64_t op, floa
     int logC = std::max(0, 12 - lq);
     logC = std::min(logC, lp);
     size_t lds = (size_t)(1 << logC) * (Qn + 1) * sizeof(float2);
-    hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)(Pn >> logC), (unsigned)B), dim3(512), lds, st, in, scratch, lq,
+    hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)(Pn >> logC), (unsigned)B), dim3(1024), lds, st, in, scratch, lq,
                        (int)Pn, logC, ip, (int64_t)1, Pn, (int64_t)1 << logn, Qn, (int64_t)1, logn, P->tw, P->tw_log,
                        (int)inv, 1.0f);
     logC = std::min(std::max(0, 12 - lp), lq);
     lds = (size_t)(1 << logC) * (Pn + 1) * sizeof(float2);
-    hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)(Qn >> logC), (unsigned)B), dim3(512), lds, st, scratch, out, lp,
+    hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)(Qn >> logC), (unsigned)B), dim3(1024), lds, st, scratch, out, lp,
                        (int)Qn, logC, (int64_t)1 << logn, (int64_t)1, Qn, op, (int64_t)1, Qn, 0, P->tw, P->tw_log,
                        (int)inv, scale);
 }
@@ -753,7 +753,7 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
     JTFS_TIMED(JTFS_STAGE_INPUT_FFT, st, hipLaunchKernelGGL(k_rfft_post, dim3((unsigned)(((s.N / 4) + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, xh,
                        w.xh_pitch, s.logN, P->tw, P->tw_log));
     LAUNCHCHK("input real-FFT post-processing");
-    JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, hipLaunchKernelGGL(k_scalogram, dim3(s.n1, (unsigned)B), dim3(512), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
+    JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, hipLaunchKernelGGL(k_scalogram, dim3(s.n1, (unsigned)B), dim3(1024), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
                        P->psi1, P->band1, P->off1, Xh, w.Xh_pitch, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log));
     LAUNCHCHK("scalogram");
     if (s1) {
@@ -768,7 +768,7 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
         const size_t lds = sizeof(float2) * rows * s.Ta[a];
         const Family& f2 = s.f2;
         // packed second-order spectrum of alpha: the plan's device table at its offset
-        JTFS_TIMED(JTFS_STAGE_SECOND_ORDER, st, hipLaunchKernelGGL(k_second_order, dim3((unsigned)((s.Kp + rows - 1) / rows), (unsigned)B), dim3(512), lds, st,
+        JTFS_TIMED(JTFS_STAGE_SECOND_ORDER, st, hipLaunchKernelGGL(k_second_order, dim3((unsigned)((s.Kp + rows - 1) / rows), (unsigned)B), dim3(1024), lds, st,
                            Xh, w.Xh_pitch, s.n1, P->psi2 + f2.off[a], f2.lo[a], f2.hi[a], logTa, s.Tp[a], rows, s.Kp,
                            Y2 + s.yoff[a], (int64_t)s.Kp * s.sumTp, 1.0f / (float)s.NX, P->tw, P->tw_log));
         LAUNCHCHK("second order");
@@ -865,17 +865,17 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
         const int logTa = s.logNX - s.k2[a];
         const int logC = logTa >= 12 ? 0 : 12 - logTa;
         const size_t lds = (size_t)(1 << logC) * (s.Ta[a] + 1) * sizeof(float2);
-        JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(512), lds,
+        JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
                            st, gY2 + s.yoff[a], gY2 + s.yoff[a], logTa, s.n1, logC, yb, (int64_t)s.Tp[a], (int64_t)1,
                            yb, (int64_t)s.Tp[a], (int64_t)1, 0, P->tw, P->tw_log, 0, 1.0f));
         LAUNCHCHK("second-order adjoint FFT");
     }
     const int logNT = s.logN - s.logT;
     const size_t lds_a = sizeof(float2) * (s.NX / 2 + 1 + s.NT);
-    JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_a, dim3(s.n1, (unsigned)B), dim3(512), lds_a, st, gY2, yb, P->d_yoff, P->d_Tp, P->d_Ta, P->psi2,
+    JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_a, dim3(s.n1, (unsigned)B), dim3(1024), lds_a, st, gY2, yb, P->d_yoff, P->d_Tp, P->d_Ta, P->psi2,
                        P->band2, P->off2, s.n_alpha, gs1, P->phiX, s.Mphi, logNT, s.logNX, gX, P->tw, P->tw_log));
     LAUNCHCHK("scalogram adjoint");
-    JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_b, dim3(s.n1, (unsigned)B), dim3(512), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
+    JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_b, dim3(s.n1, (unsigned)B), dim3(1024), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
                        P->psi1, P->band1, P->off1, gX, g1, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log));
     LAUNCHCHK("modulus and first-order adjoint");
     const int Hn = (int)(s.N / 2);
