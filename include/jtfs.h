@@ -128,12 +128,50 @@ int jtfs_backward(const jtfs_plan* plan, const float* x, const float* gs1, const
                   float* gx, int64_t B, void* ws, size_t ws_bytes, uint32_t flags,
                   hipStream_t stream);
 
+/* Arithmetic of the frequential contraction (both accumulate in FP32 on MFMA):
+ *   JTFS_CONTRACTION_FP32      FP32 operands on the FP32 matrix cores;
+ *   JTFS_CONTRACTION_SPLIT_F16 each FP32 operand v (times a power of two) is split
+ *                              as v = hi + lo with hi, lo FP16, and the product
+ *                              formed as hi*hi + hi*lo + lo*hi on the FP16 matrix
+ *                              cores (22-bit operand precision; products exact).
+ * The default is SPLIT_F16 where the shapes allow it (n1 <= 240), else FP32.
+ * Returns JTFS_ENOTSUP if the requested mode is not available for the plan. */
+#define JTFS_CONTRACTION_FP32      0
+#define JTFS_CONTRACTION_SPLIT_F16 1
+int jtfs_plan_set_contraction(jtfs_plan* plan, int mode);
+int jtfs_plan_get_contraction(const jtfs_plan* plan, int* mode);
+
 /* Copy a device filter table of the plan to host memory, for inspection in
  * tests.  which: 0 = first-order spectra as a dense [n1][N/2+1] FP32 array,
  * 1 = second-order spectra dense [n_alpha][NX/2+1], 2 = frequential wavelet
  * matrix, spin theta = -1, as interleaved complex FP32 [M_h][n1].
  * bytes must equal the table's size.  Synchronous. */
 int jtfs_plan_table(const jtfs_plan* plan, int which, void* host_dst, size_t bytes);
+
+/* Ragged batches (many signals of uneven lengths).  Each signal of length L_i
+ * (16 <= L_i <= 2^24) is zero-padded to the next power of two N_i; the signals of
+ * one padded length form a bucket with its own plan (the parameters p with N = N_i)
+ * and workspace, owned by the bucket object.
+ *
+ * Packed layouts (float32, device):
+ *   x_packed  the signals back to back, signal i at x_offset[i], L_i samples;
+ *   s_packed  per signal i at s_offset[i]: S1 [n1][N_i/T] then S2
+ *             [n_alpha][n_beta][2][L/F][N_i/T] (layouts of jtfs_forward);
+ *   g_packed  a cotangent in the layout of s_packed;
+ *   gx_packed the gradient with respect to the L_i input samples, layout of x_packed.
+ * jtfs_bucket_offsets fills x_offset[count+1] and s_offset[count+1] (the last
+ * entries are the totals).
+ *
+ * jtfs_bucket_run computes S (and gx when g_packed and gx_packed are non-NULL).
+ * The first call for a given (pointer set, stream) records all buckets' work as
+ * one HIP graph (pack, forward, backward, unpack); later calls with the same
+ * pointers replay it with a single graph launch.  Not thread-safe per object. */
+typedef struct jtfs_bucket jtfs_bucket;
+int jtfs_bucket_create(jtfs_bucket** out, const int64_t* lengths, int count, const jtfs_params* p);
+int jtfs_bucket_offsets(const jtfs_bucket* bk, int64_t* x_offset, int64_t* s_offset);
+int jtfs_bucket_run(jtfs_bucket* bk, const float* x_packed, float* s_packed, const float* g_packed,
+                    float* gx_packed, hipStream_t stream);
+void jtfs_bucket_destroy(jtfs_bucket* bk);
 
 /* Per-stage kernel timing (tracing).  While enabled, every launch of each stage
  * below is bracketed by a pair of HIP events recorded on the launch's stream.

@@ -18,6 +18,8 @@ JTFS_EHIP = -3
 JTFS_EWORKSPACE = -4
 JTFS_ENOTSUP = -6
 JTFS_BWD_REUSE_FORWARD = 1
+JTFS_CONTRACTION_FP32 = 0
+JTFS_CONTRACTION_SPLIT_F16 = 1
 STAGES = ["input_fft", "scalogram", "second_order", "freq_fwd", "freq_lowpass", "lowpass_adj", "freq_adj_pq",
           "freq_adj_wh", "second_adj", "first_adj", "output_fft"]
 
@@ -36,7 +38,8 @@ class Info(ctypes.Structure):
 
 EXPORTS = ["jtfs_query", "jtfs_query_filters", "jtfs_plan_create", "jtfs_plan_create_ex", "jtfs_plan_info",
            "jtfs_plan_destroy", "jtfs_workspace_size", "jtfs_forward", "jtfs_backward", "jtfs_plan_table",
-           "jtfs_timing_enable", "jtfs_timing_read", "jtfs_last_error"]
+           "jtfs_plan_set_contraction", "jtfs_plan_get_contraction", "jtfs_bucket_create", "jtfs_bucket_offsets",
+           "jtfs_bucket_run", "jtfs_bucket_destroy", "jtfs_timing_enable", "jtfs_timing_read", "jtfs_last_error"]
 
 _lib = None
 
@@ -70,12 +73,19 @@ def load(path: str = LIB_PATH):
     L.jtfs_forward.argtypes = [vp, vp, i64, vp, vp, vp, sz, vp]
     L.jtfs_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, sz, u32, vp]
     L.jtfs_plan_table.argtypes = [vp, ctypes.c_int, vp, sz]
+    L.jtfs_plan_set_contraction.argtypes = [vp, ctypes.c_int]
+    L.jtfs_plan_get_contraction.argtypes = [vp, P(ctypes.c_int)]
+    L.jtfs_bucket_create.argtypes = [P(vp), P(i64), ctypes.c_int, P(Params)]
+    L.jtfs_bucket_offsets.argtypes = [vp, P(i64), P(i64)]
+    L.jtfs_bucket_run.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.jtfs_bucket_destroy.argtypes = [vp]
+    L.jtfs_bucket_destroy.restype = None
     L.jtfs_timing_enable.argtypes = [ctypes.c_int]
     L.jtfs_timing_read.argtypes = [ctypes.c_int, P(ctypes.c_double), P(i64)]
     L.jtfs_last_error.argtypes = []
     L.jtfs_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("jtfs_plan_destroy", "jtfs_last_error"):
+        if name not in ("jtfs_plan_destroy", "jtfs_bucket_destroy", "jtfs_last_error"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "plan.hpp"
+#include "split.hpp"
 
 namespace jtfs {
 
@@ -316,6 +317,7 @@ extern "C" int jtfs_plan_create_ex(jtfs_plan** out, const jtfs_params* p) {
         if (A.failed) { set_error("device allocation failed"); return fail(JTFS_ENOMEM); }
     }
     if (hipDeviceSynchronize() != hipSuccess) { set_error("plan construction failed on the device"); return fail(JTFS_EHIP); }
+    if ((st = build_split_tables(P, A.ptrs)) != JTFS_OK) return fail(st);
     // the plan keeps every allocation; stash the list for destroy
     auto* keep = new (std::nothrow) std::vector<void*>(A.ptrs);
     if (!keep) return fail(JTFS_ENOMEM);

@@ -12,6 +12,8 @@
 #include "fft_lds.hpp"
 #include "plan.hpp"
 #include "timing.hpp"
+#include "split.hpp"
+#include "regk.hpp"
 
 namespace jtfs {
 
@@ -237,12 +239,15 @@ __global__ void __launch_bounds__(256) k_s1(const float2* __restrict__ Xh, int64
 __global__ void __launch_bounds__(1024) k_second_order(const float2* __restrict__ Xh, int64_t Xh_pitch, int n1,
                                                       const float* __restrict__ ps, int lo, int hi, int logTa, int Tp,
                                                       int rows, int Kp, float2* __restrict__ Y, int64_t y_bstride,
-                                                      float invNX, const float2* __restrict__ tw, int tw_log) {
+                                                      float invNX, const float2* __restrict__ tw, int tw_log,
+                                                      float* __restrict__ rowmax, int alpha, int n_alpha) {
     extern __shared__ float2 s[];
+    __shared__ unsigned int rmx[64];
     const int64_t b = blockIdx.y;
     const int r0 = blockIdx.x * rows;
     const int Ta = 1 << logTa;
     const int nr = min(rows, Kp - r0);
+    if (threadIdx.x < 64) rmx[threadIdx.x] = 0u;
     for (int e = threadIdx.x; e < nr * Ta; e += blockDim.x) {
         const int c = e >> logTa, p = e & (Ta - 1);
         const int lam = r0 + c;
@@ -261,10 +266,19 @@ __global__ void __launch_bounds__(1024) k_second_order(const float2* __restrict_
     __syncthreads();
     lds_fft<16>(s, logTa, nr, Ta, tw, tw_log, true);
     float2* out = Y + b * y_bstride + (int64_t)r0 * Tp;
-    for (int e = threadIdx.x; e < nr * Tp; e += blockDim.x) {
-        const int c = e / Tp, t = e - c * Tp;
-        out[e] = t < Ta ? cscale(s[c * Ta + t], invNX) : make_float2(0.f, 0.f);
+    for (int c = 0; c < nr; ++c) {
+        float m = 0.f;
+        for (int t = threadIdx.x; t < Tp; t += blockDim.x) {
+            const float2 v = t < Ta ? cscale(s[c * Ta + t], invNX) : make_float2(0.f, 0.f);
+            out[(int64_t)c * Tp + t] = v;
+            m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        if ((threadIdx.x & 63) == 0) atomicMax(&rmx[c], __float_as_uint(m));
     }
+    __syncthreads();
+    if ((int)threadIdx.x < nr) rowmax[(b * n_alpha + alpha) * Kp + r0 + threadIdx.x] = __uint_as_float(rmx[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -394,10 +408,14 @@ __global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, in
 
 // gV[b][alpha][theta][rowoff+l][tau] = sum_m PF_beta[m][l] gS2[b][alpha][beta][theta][m][tau]
 // (adjoint of the frequency lowpass); block n_beta zeroes the padding rows.
+// Also writes, per (signal, alpha, spin, beta), the largest row sum over tau of
+// |gV| (a bound used to scale the split backward contraction).
 __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, const float* __restrict__ PFall,
                                                 const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
                                                 const int* __restrict__ rowoffv, int n_beta, int NL, int NT, int NTp,
-                                                int Mh, int Mp, int alpha, int n_alpha, float* __restrict__ gV) {
+                                                int Mh, int Mp, int alpha, int n_alpha, float* __restrict__ gV,
+                                                float* __restrict__ gvmax) {
+    __shared__ float rowsum[512];
     const int beta = blockIdx.x, th = blockIdx.y;
     const int64_t b = blockIdx.z;
     float* g = gV + (((b * n_alpha + alpha) * 2 + th) * (int64_t)Mp) * NTp;
@@ -406,6 +424,8 @@ __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, c
         return;
     }
     const int Lb = Lbv[beta], ro = rowoffv[beta];
+    for (int l = threadIdx.x; l < Lb; l += blockDim.x) rowsum[l] = 0.f;
+    __syncthreads();
     const float* PF = PFall + pfoff[beta];
     const float* src =
         gS2 ? gS2 + ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NL) * (int64_t)NT : nullptr;
@@ -415,6 +435,13 @@ __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, c
         if (src && tau < NT)
             for (int m = 0; m < NL; ++m) acc += PF[m * Lb + l] * src[(int64_t)m * NT + tau];
         g[(int64_t)(ro + l) * NTp + tau] = acc;
+        atomicAdd(&rowsum[l], fabsf(acc));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = 0.f;
+        for (int l = 0; l < Lb; ++l) m = fmaxf(m, rowsum[l]);
+        gvmax[((b * n_alpha + alpha) * 2 + th) * n_beta + beta] = m;
     }
 }
 
@@ -666,7 +693,7 @@ static bool g_attr_done = false;
 
 int setup_kernel_attributes() {
     if (g_attr_done) return JTFS_OK;
-    const int lds = 160 * 1024;
+    const int lds = kMaxDynLds;
     const void* ks[] = {(const void*)k_fft_cols, (const void*)k_scalogram, (const void*)k_s1, (const void*)k_s2_out,
                         (const void*)k_second_order, (const void*)k_scal_bwd_a, (const void*)k_scal_bwd_b};
     for (const void* k : ks) {
@@ -676,6 +703,10 @@ int setup_kernel_attributes() {
             return JTFS_EHIP;
         }
     }
+    int rs = split_attributes();
+    if (rs != JTFS_OK) return rs;
+    rs = reg_attributes();
+    if (rs != JTFS_OK) return rs;
     g_attr_done = true;
     return JTFS_OK;
 }
@@ -721,11 +752,17 @@ using namespace jtfs;
         }                                                                                \
     } while (0)
 
+// Workspace of a plan in its current contraction mode.
+static Workspace plan_layout(const jtfs_plan* P, int64_t B) {
+    const bool split = P->contraction == JTFS_CONTRACTION_SPLIT_F16;
+    return layout(P->s, B, split, !(split && P->split_bwd_ok));
+}
+
 static int check_common(const jtfs_plan* P, int64_t B, void* ws, size_t ws_bytes) {
     if (!P) { set_error("null plan"); return JTFS_EINVAL; }
     if (B < 1) { set_error("B must be >= 1"); return JTFS_EINVAL; }
     if (!ws) { set_error("null workspace"); return JTFS_EINVAL; }
-    const Workspace w = layout(P->s, B);
+    const Workspace w = plan_layout(P, B);
     if (ws_bytes < w.total) { set_error("workspace too small"); return JTFS_EWORKSPACE; }
     return JTFS_OK;
 }
@@ -733,7 +770,7 @@ static int check_common(const jtfs_plan* P, int64_t B, void* ws, size_t ws_bytes
 extern "C" int jtfs_workspace_size(const jtfs_plan* P, int64_t B, size_t* bytes) {
     if (!P || !bytes) { set_error("null pointer"); return JTFS_EINVAL; }
     if (B < 1) { set_error("B must be >= 1"); return JTFS_EINVAL; }
-    *bytes = layout(P->s, B).total;
+    *bytes = plan_layout(P, B).total;
     return JTFS_OK;
 }
 
@@ -753,8 +790,12 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
     JTFS_TIMED(JTFS_STAGE_INPUT_FFT, st, hipLaunchKernelGGL(k_rfft_post, dim3((unsigned)(((s.N / 4) + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, xh,
                        w.xh_pitch, s.logN, P->tw, P->tw_log));
     LAUNCHCHK("input real-FFT post-processing");
-    JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, hipLaunchKernelGGL(k_scalogram, dim3(s.n1, (unsigned)B), dim3(1024), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
+    if (s.logNX >= kRegMinLog) {
+        JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, launch_scalogram_r(P, xh, w.xh_pitch, Xh, w.Xh_pitch, B, st));
+    } else {
+        JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, hipLaunchKernelGGL(k_scalogram, dim3(s.n1, (unsigned)B), dim3(1024), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
                        P->psi1, P->band1, P->off1, Xh, w.Xh_pitch, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log));
+    }
     LAUNCHCHK("scalogram");
     if (s1) {
         const int logNT = s.logN - s.logT;
@@ -764,13 +805,20 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
     }
     for (int a = 0; a < s.n_alpha; ++a) {
         const int logTa = s.logNX - s.k2[a];
-        const int rows = std::max(1, 4096 >> logTa);
+        if (logTa >= kRegMinLog) {
+            JTFS_TIMED(JTFS_STAGE_SECOND_ORDER, st,
+                       launch_second_order_r(P, a, Xh, w.Xh_pitch, Y2, (float*)(base + w.rowmax), B, st));
+            LAUNCHCHK("second order");
+            continue;
+        }
+        const int rows = std::min(64, std::max(1, 4096 >> logTa));   // <= 64: row-maximum slots
         const size_t lds = sizeof(float2) * rows * s.Ta[a];
         const Family& f2 = s.f2;
         // packed second-order spectrum of alpha: the plan's device table at its offset
         JTFS_TIMED(JTFS_STAGE_SECOND_ORDER, st, hipLaunchKernelGGL(k_second_order, dim3((unsigned)((s.Kp + rows - 1) / rows), (unsigned)B), dim3(1024), lds, st,
                            Xh, w.Xh_pitch, s.n1, P->psi2 + f2.off[a], f2.lo[a], f2.hi[a], logTa, s.Tp[a], rows, s.Kp,
-                           Y2 + s.yoff[a], (int64_t)s.Kp * s.sumTp, 1.0f / (float)s.NX, P->tw, P->tw_log));
+                           Y2 + s.yoff[a], (int64_t)s.Kp * s.sumTp, 1.0f / (float)s.NX, P->tw, P->tw_log,
+                           (float*)(base + w.rowmax), a, s.n_alpha));
         LAUNCHCHK("second order");
     }
     return JTFS_OK;
@@ -784,14 +832,27 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
     if (rc != JTFS_OK) return rc;
     if (!x || !s1 || !s2) { set_error("null pointer"); return JTFS_EINVAL; }
     const Shapes& s = P->s;
-    const Workspace w = layout(s, B);
+    const Workspace w = plan_layout(P, B);
     char* base = (char*)ws;
     rc = forward_front(P, x, B, s1, base, w, st);
     if (rc != JTFS_OK) return rc;
     float2* Y2 = (float2*)(base + w.Y2);
     float* Vp = (float*)(base + w.Vp);
     const int nlt = s.Mp / kTileL;
-    for (int a = 0; a < s.n_alpha; ++a) {
+    const bool split = P->contraction == JTFS_CONTRACTION_SPLIT_F16;
+    for (int a = 0; a < s.n_alpha && split; ++a) {
+        unsigned short* Yh = (unsigned short*)(base + w.Yh);
+        float* ysc = (float*)(base + w.yscale);
+        JTFS_TIMED(JTFS_STAGE_FREQ_FWD, st,
+                   rc = launch_ysplit(P, a, Y2, (const float*)(base + w.rowmax), Yh, ysc, B, st));
+        if (rc != JTFS_OK) { set_error("operand split kernel failed"); return rc; }
+        JTFS_TIMED(JTFS_STAGE_FREQ_FWD, st, rc = launch_freq_fwd_split(P, a, Yh, ysc, Vp, w.vp_bstride, B, st));
+        if (rc != JTFS_OK) { if (rc == JTFS_EHIP) set_error("split contraction launch failed"); return rc; }
+        JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), sizeof(float) * 33 * s.L, st, Vp, w.vp_bstride, (int)s.vchoff[a],
+                           s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2));
+        LAUNCHCHK("frequency lowpass");
+    }
+    for (int a = 0; a < s.n_alpha && !split; ++a) {
         dim3 grid(nlt, s.nch[a], (unsigned)B);
         const int slot0 = (int)s.vchoff[a] * 2;
         const float2* Ya = Y2 + s.yoff[a];
@@ -820,7 +881,7 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     if (rc != JTFS_OK) return rc;
     if (!x || !gx) { set_error("null pointer"); return JTFS_EINVAL; }
     const Shapes& s = P->s;
-    const Workspace w = layout(s, B);
+    const Workspace w = plan_layout(P, B);
     char* base = (char*)ws;
     if (!(flags & JTFS_BWD_REUSE_FORWARD)) {
         rc = forward_front(P, x, B, nullptr, base, w, st);
@@ -839,10 +900,38 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     const int nlt = s.Mp / kTileL;
     for (int a = 0; a < s.n_alpha; ++a) {
         JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_s2_bwd, dim3(s.n_beta + 1, 2, (unsigned)B), dim3(256), 0, st, gs2, P->PF, P->d_pfoff, P->d_Lb,
-                           P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, a, s.n_alpha, gV));
+                           P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, a, s.n_alpha, gV,
+                           (float*)(base + w.gvmax)));
         LAUNCHCHK("frequency lowpass adjoint");
     }
-    for (int a = 0; a < s.n_alpha; ++a) {
+    const bool split = P->contraction == JTFS_CONTRACTION_SPLIT_F16 && P->split_bwd_ok;
+    unsigned short* Yh = (unsigned short*)(base + w.Yh);
+    float* ysc = (float*)(base + w.yscale);
+    if (split && !(flags & JTFS_BWD_REUSE_FORWARD)) {
+        for (int a = 0; a < s.n_alpha; ++a) {
+            JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,
+                       rc = launch_ysplit(P, a, Y2, (const float*)(base + w.rowmax), Yh, ysc, B, st));
+            if (rc != JTFS_OK) { set_error("operand split kernel failed"); return rc; }
+        }
+    }
+    for (int a = 0; a < s.n_alpha && split; ++a) {
+        JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,
+                   rc = launch_freq_bwd_split(P, a, Yh, ysc, gV, (const float*)(base + w.gvmax), gY2, B, st));
+        if (rc != JTFS_OK) { if (rc == JTFS_EHIP) set_error("split backward contraction launch failed"); return rc; }
+        const int logTa = s.logNX - s.k2[a];
+        const int logC = logTa >= 12 ? 0 : 12 - logTa;
+        const size_t lds = (size_t)(1 << logC) * (s.Ta[a] + 1) * sizeof(float2);
+        if (logTa >= kRegMinLog) {
+            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st,
+                       launch_rowfft_r(P, gY2 + s.yoff[a], yb, (int64_t)s.Tp[a], s.n1, logTa, B, st));
+        } else {
+            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
+                           st, gY2 + s.yoff[a], gY2 + s.yoff[a], logTa, s.n1, logC, yb, (int64_t)s.Tp[a], (int64_t)1,
+                           yb, (int64_t)s.Tp[a], (int64_t)1, 0, P->tw, P->tw_log, 0, 1.0f));
+        }
+        LAUNCHCHK("second-order adjoint FFT");
+    }
+    for (int a = 0; a < s.n_alpha && !split; ++a) {
         dim3 grid(nlt, s.Tp[a] / kTileT, (unsigned)B);
         const float2* Ya = Y2 + s.yoff[a];
         const float* Ph = P->Phi + s.phioff[a];
@@ -865,9 +954,14 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
         const int logTa = s.logNX - s.k2[a];
         const int logC = logTa >= 12 ? 0 : 12 - logTa;
         const size_t lds = (size_t)(1 << logC) * (s.Ta[a] + 1) * sizeof(float2);
-        JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
+        if (logTa >= kRegMinLog) {
+            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st,
+                       launch_rowfft_r(P, gY2 + s.yoff[a], yb, (int64_t)s.Tp[a], s.n1, logTa, B, st));
+        } else {
+            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
                            st, gY2 + s.yoff[a], gY2 + s.yoff[a], logTa, s.n1, logC, yb, (int64_t)s.Tp[a], (int64_t)1,
                            yb, (int64_t)s.Tp[a], (int64_t)1, 0, P->tw, P->tw_log, 0, 1.0f));
+        }
         LAUNCHCHK("second-order adjoint FFT");
     }
     const int logNT = s.logN - s.logT;
@@ -875,8 +969,12 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_a, dim3(s.n1, (unsigned)B), dim3(1024), lds_a, st, gY2, yb, P->d_yoff, P->d_Tp, P->d_Ta, P->psi2,
                        P->band2, P->off2, s.n_alpha, gs1, P->phiX, s.Mphi, logNT, s.logNX, gX, P->tw, P->tw_log));
     LAUNCHCHK("scalogram adjoint");
-    JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_b, dim3(s.n1, (unsigned)B), dim3(1024), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
+    if (s.logNX >= kRegMinLog) {
+        JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, launch_scal_bwd_b_r(P, xh, w.xh_pitch, gX, g1, B, st));
+    } else {
+        JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_b, dim3(s.n1, (unsigned)B), dim3(1024), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
                        P->psi1, P->band1, P->off1, gX, g1, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log));
+    }
     LAUNCHCHK("modulus and first-order adjoint");
     const int Hn = (int)(s.N / 2);
     JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, hipLaunchKernelGGL(k_band_accum, dim3((unsigned)((Hn + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, g1, s.n1,

@@ -1,0 +1,356 @@
+// First- and second-order kernels for long rows (2^14 and 2^15 points) built on
+// the register-resident FFT: 32 values per thread, LDS used only as a float
+// exchange buffer of one row (64 KB at 2^14 -> two workgroups per CU; 128 KB at
+// 2^15, which an in-LDS complex transform could not hold).
+#include <hip/hip_runtime.h>
+
+#include "plan.hpp"
+#include "reg_fft.hpp"
+#include "regk.hpp"
+
+namespace jtfs {
+
+constexpr int kRegE = 32;
+
+// fold of src * ps over the band [lo, hi] onto M = 2^logM bins, at bin p
+__device__ __forceinline__ float2 fold_at(const float2* __restrict__ src, const float* __restrict__ ps, int lo, int hi,
+                                          int logM, int p) {
+    const int M = 1 << logM;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int m = lo + ((p - lo) & (M - 1)); m <= hi; m += M) {
+        const float2 v = src[m];
+        const float g = ps[m - lo];
+        acc.x += v.x * g;
+        acc.y += v.y * g;
+    }
+    return acc;
+}
+
+// Rows of 2^15 points run as two 2^14-point register transforms:
+//  inverse (decimation in frequency):  y[2k] = IDFT_m(u[p] + u[p+m])[k],
+//                                      y[2k+1] = IDFT_m((u[p] - u[p+m]) e^{+2 pi i p/n})[k];
+//  forward (decimation in time):       G[k] = E[k] + e^{-2 pi i k/n} O[k], G[k+m] = E[k] - e^{-2 pi i k/n} O[k],
+//                                      E, O the m-point DFTs of the even and odd samples (m = n/2).
+
+// Inputs of one sub-transform of the inverse split (decimation in frequency),
+// staged through LDS (real parts in A, imaginary parts in B, m = n/2 floats
+// each) and loaded in the register transform's input layout.  half 0:
+// u[p] + u[p+m]; half 1: (u[p] - u[p+m]) e^{+2 pi i p/n}.  Without the split
+// (TWO false) each thread folds u at its own input positions; no LDS is used.
+template <bool TWO>
+__device__ __forceinline__ void load_dif(float2 (&v)[kRegE], float* A, float* B, const float2* __restrict__ src,
+                                         const float* __restrict__ ps, int lo, int hi, int logn, int half,
+                                         const float2* __restrict__ tw, int tw_log, bool zero) {
+    if constexpr (!TWO) {
+        // no staging: each thread folds its own inputs
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e)
+            v[e] = zero ? make_float2(0.f, 0.f) : fold_at(src, ps, lo, hi, logn, reg_input_pos(e, logn));
+        return;
+    }
+    const int logS = logn - 1;
+    const int m = 1 << logS;
+    __syncthreads();                                   // A, B free (2^logn floats)
+    for (int p = threadIdx.x; p < m; p += blockDim.x) {
+        float2 u = make_float2(0.f, 0.f);
+        if (!zero) {
+            const float2 a = fold_at(src, ps, lo, hi, logn, p);
+            if (TWO) {
+                const float2 c = fold_at(src, ps, lo, hi, logn, p + m);
+                u = half == 0 ? cadd(a, c) : cmul(csub(a, c), twiddle(tw, p << (tw_log - logn), true));
+            } else {
+                u = a;
+            }
+        }
+        A[p] = u.x;
+        B[p] = u.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kRegE; ++e) {
+        const int q = reg_input_pos(e, logS);
+        v[e] = make_float2(A[q], B[q]);
+    }
+}
+
+// scalogram row -> X_hat (same computation as the in-LDS scalogram kernel)
+template <bool TWO>
+__global__ void __launch_bounds__(512) k_scalogram_r(const float2* __restrict__ xh, int64_t xh_pitch,
+                                                     const float* __restrict__ psi1, const int* __restrict__ band1,
+                                                     const int64_t* __restrict__ off1, float2* __restrict__ Xh,
+                                                     int64_t Xh_pitch, int logNX, float invN,
+                                                     const float2* __restrict__ tw, int tw_log) {
+    extern __shared__ float xbuf[];          // NX floats (TWO: A = first NX/2, B = second NX/2)
+    const int lam = blockIdx.x, n1 = gridDim.x;
+    const int64_t b = blockIdx.y;
+    const int NX = 1 << logNX, H = NX >> 1, logH = logNX - 1;
+    const int logS = TWO ? logNX - 1 : logNX;
+    float* A = xbuf;
+    float* Bf = xbuf + (1 << logS);
+    const float2* src = xh + b * xh_pitch;
+    const float* ps = psi1 + off1[lam];
+    const int lo = band1[2 * lam], hi = band1[2 * lam + 1];
+    float2 v[kRegE];
+    float even[TWO ? kRegE : 1];
+    if constexpr (TWO) {
+        load_dif<true>(v, A, Bf, src, ps, lo, hi, logNX, 0, tw, tw_log, false);
+        reg_fft<kRegE>(v, A, logS, tw, tw_log, true);
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) even[e] = sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN;   // X[2 pos]
+        load_dif<true>(v, A, Bf, src, ps, lo, hi, logNX, 1, tw, tw_log, false);
+        reg_fft<kRegE>(v, A, logS, tw, tw_log, true);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            const int pos = reg_output_pos(e, logS);
+            xbuf[pos] = even[e];                                              // X[2 pos]
+            xbuf[H + pos] = sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN; // X[2 pos + 1]
+        }
+    } else {
+        // the whole row fits one register transform; the exchange buffer is NX floats
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) v[e] = fold_at(src, ps, lo, hi, logNX, reg_input_pos(e, logNX));
+        reg_fft<kRegE>(v, xbuf, logNX, tw, tw_log, true);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            const int pos = reg_output_pos(e, logNX);
+            xbuf[(pos & 1) * H + (pos >> 1)] = sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN;
+        }
+    }
+    __syncthreads();
+    // real FFT of X through the complex FFT of z[k] = X[2k] + i X[2k+1] (H points)
+    constexpr int EZ = TWO ? kRegE : kRegE / 2;
+    float2 z[EZ];
+#pragma unroll
+    for (int e = 0; e < EZ; ++e) {
+        const int k = reg_input_pos(e, logH);
+        z[e] = make_float2(xbuf[k], xbuf[H + k]);
+    }
+    reg_fft<EZ>(z, xbuf, logH, tw, tw_log, false);
+    __syncthreads();
+    float2* Z = (float2*)xbuf;               // H complex values = NX floats
+#pragma unroll
+    for (int e = 0; e < EZ; ++e) Z[reg_output_pos(e, logH)] = z[e];
+    __syncthreads();
+    float2* out = Xh + (b * n1 + lam) * Xh_pitch;
+    const int tws = tw_log - logNX;
+    for (int m = threadIdx.x; m <= H / 2; m += blockDim.x) {
+        if (m == 0) {
+            const float2 q = Z[0];
+            out[0] = make_float2(q.x + q.y, 0.f);
+            out[H] = make_float2(q.x - q.y, 0.f);
+            continue;
+        }
+        const float2 a = Z[m], c = Z[H - m];
+        auto spec = [&](float2 p, float2 q, int k) {
+            const float2 E = make_float2(0.5f * (p.x + q.x), 0.5f * (p.y - q.y));
+            const float2 D = make_float2(p.x - q.x, p.y + q.y);
+            const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);
+            return cadd(E, cmul(O, tw[k << tws]));
+        };
+        out[m] = spec(a, c, m);
+        if (H - m != m) out[H - m] = spec(c, a, H - m);
+    }
+}
+
+// one second-order row (T_alpha = 2^logTa >= 2^14): fold, inverse FFT, store, row max
+template <bool TWO>
+__global__ void __launch_bounds__(512) k_second_order_r(const float2* __restrict__ Xh, int64_t Xh_pitch, int n1,
+                                                        const float* __restrict__ ps, int lo, int hi, int logTa,
+                                                        int Tp, int Kp, float2* __restrict__ Y, int64_t y_bstride,
+                                                        float invNX, const float2* __restrict__ tw, int tw_log,
+                                                        float* __restrict__ rowmax, int alpha, int n_alpha) {
+    extern __shared__ float xbuf[];
+    __shared__ unsigned int rmx;
+    const int lam = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    const int logS = TWO ? logTa - 1 : logTa;
+    float* A = xbuf;
+    float* Bf = xbuf + (1 << logS);
+    if (threadIdx.x == 0) rmx = 0u;
+    float2* out = Y + b * y_bstride + (int64_t)lam * Tp;
+    const float2* row = Xh + (b * n1 + (lam < n1 ? lam : 0)) * Xh_pitch;
+    float m = 0.f;
+    float2 v[kRegE];
+#pragma unroll
+    for (int half = 0; half < (TWO ? 2 : 1); ++half) {
+        load_dif<TWO>(v, A, Bf, row, ps, lo, hi, logTa, half, tw, tw_log, lam >= n1);
+        reg_fft<kRegE>(v, A, logS, tw, tw_log, true);
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            const float2 y = cscale(v[e], invNX);
+            const int pos = reg_output_pos(e, logS);
+            out[TWO ? 2 * pos + half : pos] = y;
+            m = fmaxf(m, fmaxf(fabsf(y.x), fabsf(y.y)));
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) atomicMax(&rmx, __float_as_uint(m));
+    __syncthreads();
+    if (threadIdx.x == 0) rowmax[(b * n_alpha + alpha) * Kp + lam] = __uint_as_float(rmx);
+}
+
+// in-place forward FFT of rows of 2^logn points (row r of batch b at base + b*bs + r*rs)
+template <bool TWO>
+__global__ void __launch_bounds__(512) k_rowfft_r(float2* __restrict__ base, int64_t bs, int64_t rs, int logn,
+                                                  const float2* __restrict__ tw, int tw_log) {
+    extern __shared__ float xbuf[];
+    float2* row = base + (int64_t)blockIdx.y * bs + (int64_t)blockIdx.x * rs;
+    const int logS = TWO ? logn - 1 : logn;
+    float2 v[kRegE];
+    if constexpr (!TWO) {
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) v[e] = row[reg_input_pos(e, logn)];
+        reg_fft<kRegE>(v, xbuf, logn, tw, tw_log, false);
+        __syncthreads();      // every thread has read its inputs before any output is stored
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) row[reg_output_pos(e, logn)] = v[e];
+    } else {
+        const int m = 1 << logS;
+        // E = DFT of the even samples, parked in the first half of the row once every
+        // thread holds its odd samples; then O = DFT of the odd samples; combine
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) v[e] = row[2 * reg_input_pos(e, logS)];
+        reg_fft<kRegE>(v, xbuf, logS, tw, tw_log, false);
+        float2 o[kRegE];
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) o[e] = row[2 * reg_input_pos(e, logS) + 1];
+        __syncthreads();
+        __threadfence_block();
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) row[reg_output_pos(e, logS)] = v[e];
+        reg_fft<kRegE>(o, xbuf, logS, tw, tw_log, false);
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            const int k = reg_output_pos(e, logS);
+            const float2 ev = row[k];                  // written by this thread above
+            const float2 wo = cmul(o[e], twiddle(tw, k << (tw_log - logn), false));
+            row[k] = cadd(ev, wo);
+            row[k + m] = csub(ev, wo);
+        }
+    }
+}
+
+// adjoint of the modulus and first-order filter for one row: recompute y, weight
+// gX by its phase, forward FFT -> g1[b][lambda][0..NX)
+template <bool TWO>
+__global__ void __launch_bounds__(512) k_scal_bwd_b_r(const float2* __restrict__ xh, int64_t xh_pitch,
+                                                      const float* __restrict__ psi1, const int* __restrict__ band1,
+                                                      const int64_t* __restrict__ off1, const float* __restrict__ gX,
+                                                      float2* __restrict__ g1, int logNX, float invN,
+                                                      const float2* __restrict__ tw, int tw_log) {
+    extern __shared__ float xbuf[];
+    const int lam = blockIdx.x, n1 = gridDim.x;
+    const int64_t b = blockIdx.y;
+    const int NX = 1 << logNX;
+    const int logS = TWO ? logNX - 1 : logNX;
+    float* A = xbuf;
+    float* Bf = xbuf + (1 << logS);
+    const float2* src = xh + b * xh_pitch;
+    const float* ps = psi1 + off1[lam];
+    const int lo = band1[2 * lam], hi = band1[2 * lam + 1];
+    const float* gx = gX + (b * n1 + lam) * (int64_t)NX;
+    float2* o = g1 + (b * n1 + lam) * (int64_t)NX;
+    const int lr = reg_pass_lr(logS, reg_num_passes(logS) - 1);
+    const int lNs = logS - lr;
+    float2 v[kRegE];
+#pragma unroll
+    for (int half = 0; half < (TWO ? 2 : 1); ++half) {
+        if (TWO) {
+            load_dif<true>(v, A, Bf, src, ps, lo, hi, logNX, half, tw, tw_log, false);
+        } else {
+#pragma unroll
+            for (int e = 0; e < kRegE; ++e) v[e] = fold_at(src, ps, lo, hi, logNX, reg_input_pos(e, logNX));
+        }
+        reg_fft<kRegE>(v, A, logS, tw, tw_log, true);
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            const float2 y = cscale(v[e], invN);
+            const int pos = reg_output_pos(e, logS);
+            const float sc = gx[TWO ? 2 * pos + half : pos] / fmaxf(sqrtf(y.x * y.x + y.y * y.y), kEpsMod);
+            v[e] = cscale(y, sc);
+        }
+        // from the last pass's output layout to the first pass's input layout
+        if (lr == 3) reg_exchange<3, 3, kRegE>(v, A, logS, lNs);
+        else if (lr == 2) reg_exchange<2, 3, kRegE>(v, A, logS, lNs);
+        else reg_exchange<1, 3, kRegE>(v, A, logS, lNs);
+        reg_fft<kRegE>(v, A, logS, tw, tw_log, false);
+        if (TWO && half == 0) {
+            // spectrum of the even samples, parked in the output row
+#pragma unroll
+            for (int e = 0; e < kRegE; ++e) o[reg_output_pos(e, logS)] = v[e];
+        }
+    }
+    if constexpr (!TWO) {
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) o[reg_output_pos(e, logNX)] = v[e];
+    } else {
+        const int m = 1 << logS;
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            const int k = reg_output_pos(e, logS);
+            const float2 ev = o[k];                    // written by this thread above
+            const float2 wo = cmul(v[e], twiddle(tw, k << (tw_log - logNX), false));
+            o[k] = cadd(ev, wo);
+            o[k + m] = csub(ev, wo);
+        }
+    }
+}
+
+int reg_attributes() {
+    const void* ks[] = {(const void*)k_scalogram_r<false>,    (const void*)k_scalogram_r<true>,
+                        (const void*)k_second_order_r<false>, (const void*)k_second_order_r<true>,
+                        (const void*)k_rowfft_r<false>,       (const void*)k_rowfft_r<true>,
+                        (const void*)k_scal_bwd_b_r<false>,   (const void*)k_scal_bwd_b_r<true>};
+    for (const void* k : ks)
+        if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds) != hipSuccess) {
+            set_error("hipFuncSetAttribute failed for the long-row kernels");
+            return JTFS_EHIP;
+        }
+    return JTFS_OK;
+}
+
+// rows of 2^14 points: one 512-thread register transform; 2^15: two of them
+static inline bool two_of(int logn) { return logn == kRegMinLog + 1; }
+static inline unsigned reg_threads() { return (unsigned)((1 << kRegMinLog) / kRegE); }
+
+void launch_scalogram_r(const jtfs_plan* P, const float2* xh, int64_t xh_pitch, float2* Xh, int64_t Xh_pitch,
+                        int64_t B, hipStream_t st) {
+    const Shapes& s = P->s;
+    auto k = two_of(s.logNX) ? k_scalogram_r<true> : k_scalogram_r<false>;
+    hipLaunchKernelGGL(k, dim3(s.n1, (unsigned)B), dim3(reg_threads()), sizeof(float) * s.NX, st, xh, xh_pitch,
+                       P->psi1, P->band1, P->off1, Xh, Xh_pitch, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log);
+    // LDS: NX floats (exchange of one 2^14 transform, or the two staged halves at 2^15)
+}
+
+void launch_second_order_r(const jtfs_plan* P, int a, const float2* Xh, int64_t Xh_pitch, float2* Y2, float* rowmax,
+                           int64_t B, hipStream_t st) {
+    const Shapes& s = P->s;
+    const int logTa = s.logNX - s.k2[a];
+    const Family& f2 = s.f2;
+    auto k = two_of(logTa) ? k_second_order_r<true> : k_second_order_r<false>;
+    hipLaunchKernelGGL(k, dim3(s.Kp, (unsigned)B), dim3(reg_threads()), sizeof(float) << (logTa == kRegMinLog ? kRegMinLog : kRegMinLog + 1), st, Xh, Xh_pitch,
+                       s.n1, P->psi2 + f2.off[a], f2.lo[a], f2.hi[a], logTa, s.Tp[a], s.Kp, Y2 + s.yoff[a],
+                       (int64_t)s.Kp * s.sumTp, 1.0f / (float)s.NX, P->tw, P->tw_log, rowmax, a, s.n_alpha);
+}
+
+void launch_rowfft_r(const jtfs_plan* P, float2* base, int64_t bs, int64_t rs, int rows, int logn, int64_t B,
+                     hipStream_t st) {
+    auto k = two_of(logn) ? k_rowfft_r<true> : k_rowfft_r<false>;
+    hipLaunchKernelGGL(k, dim3((unsigned)rows, (unsigned)B), dim3(reg_threads()), sizeof(float) << kRegMinLog, st,
+                       base, bs, rs, logn, P->tw, P->tw_log);
+}
+
+void launch_scal_bwd_b_r(const jtfs_plan* P, const float2* xh, int64_t xh_pitch, const float* gX, float2* g1,
+                         int64_t B, hipStream_t st) {
+    const Shapes& s = P->s;
+    auto k = two_of(s.logNX) ? k_scal_bwd_b_r<true> : k_scal_bwd_b_r<false>;
+    hipLaunchKernelGGL(k, dim3(s.n1, (unsigned)B), dim3(reg_threads()), sizeof(float) * s.NX, st, xh,
+                       xh_pitch, P->psi1, P->band1, P->off1, gX, g1, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log);
+}
+
+}  // namespace jtfs

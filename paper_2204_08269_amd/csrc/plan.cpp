@@ -128,7 +128,7 @@ int solve_shapes(const jtfs_params& p, Shapes* s) {
     for (int a = 0; a < s->n_alpha; ++a) {
         s->k2[a] = critical_log2(f2.sigma[a], s->logT - s->kX);
         s->Ta[a] = (int)(s->NX >> s->k2[a]);
-        s->Tp[a] = std::max(s->Ta[a], kTileT);
+        s->Tp[a] = std::max(s->Ta[a], kTileTh);
         s->chunk[a] = std::min(s->Tp[a], kChunkT);
         s->nch[a] = s->Tp[a] / s->chunk[a];
         s->yoff[a] = yo; s->phioff[a] = po; s->vchoff[a] = co;
@@ -159,14 +159,14 @@ int solve_shapes(const jtfs_params& p, Shapes* s) {
 }
 
 int check_supported(const Shapes& s) {
-    if (s.logNX > kLdsFftMax) {
+    if (s.logNX > kMaxLogNX) {
         set_error("scalogram length N/2^kX above 2^14 is not supported by this build");
         return JTFS_ENOTSUP;
     }
     return JTFS_OK;
 }
 
-Workspace layout(const Shapes& s, int64_t B) {
+Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq) {
     Workspace w;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) / 256 * 256; return r; };
@@ -176,13 +176,17 @@ Workspace layout(const Shapes& s, int64_t B) {
     w.tmp = take(sizeof(float2) * B * (s.N / 2));
     w.Xh = take(sizeof(float2) * B * s.n1 * w.Xh_pitch);
     w.Y2 = take(sizeof(float2) * B * s.Kp * s.sumTp);
+    w.Yh = take(with_split ? sizeof(float2) * B * s.Kp * s.sumTp : 0);   // 4 halves per complex value
+    w.rowmax = take(sizeof(float) * B * s.n_alpha * s.Kp);
+    w.yscale = take(sizeof(float) * B * s.n_alpha);
+    w.gvmax = take(sizeof(float) * B * s.n_alpha * 2 * s.n_beta);
     // partial V: per signal, per (alpha, t-chunk, t-half) slot, per l-tile, spin, tau, l
     w.vp_bstride = s.sumch * 2 * (s.Mp / kTileL) * 2 * (int64_t)s.NTp * kTileL;
     w.Vp = take(sizeof(float) * B * w.vp_bstride);
     w.gV = take(sizeof(float) * B * s.n_alpha * 2 * s.Mp * s.NTp);
     int64_t maxTp = 0;
     for (int a = 0; a < s.n_alpha; ++a) maxTp = std::max<int64_t>(maxTp, s.Tp[a]);
-    w.PQ = take(sizeof(float2) * B * 2 * s.Mp * maxTp);
+    w.PQ = take(with_pq ? sizeof(float2) * B * 2 * s.Mp * maxTp : 0);
     w.gY2 = take(sizeof(float2) * B * s.Kp * s.sumTp);
     w.gX = take(sizeof(float) * B * s.n1 * s.NX);
     w.g1 = take(sizeof(float2) * B * s.n1 * s.NX);

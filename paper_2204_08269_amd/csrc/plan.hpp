@@ -20,9 +20,12 @@ constexpr float kEpsMod = 1e-30f;  // modulus-gradient guard: z / max(|z|, eps)
 
 constexpr int kTileL = 64;         // frequential GEMM: rows (l) per tile
 constexpr int kTileT = 64;         // frequential GEMM: columns (t) per tile
+constexpr int kTileTh = 128;       // split-FP16 contraction: columns (t) per tile (t padding unit)
 constexpr int kKStep = 16;         // frequential GEMM: K (lambda_1) per LDS stage
 constexpr int kChunkT = 4096;      // frequential GEMM: t-range reduced by one workgroup
 constexpr int kLdsFftMax = 14;     // log2 of the largest complex FFT held in LDS
+constexpr int kMaxLogNX = 14;      // longest scalogram row
+constexpr int kMaxDynLds = 159 * 1024;  // dynamic LDS limit set on kernels (1 KB left for static LDS)
 
 void set_error(const std::string& s);
 
@@ -62,12 +65,14 @@ const char* last_error();
 // Workspace layout for B signals (byte offsets from the workspace base).
 struct Workspace {
     size_t xh = 0, tmp = 0, Xh = 0, Y2 = 0, Vp = 0;            // forward
+    size_t Yh = 0, rowmax = 0, yscale = 0, gvmax = 0;          // split-FP16 operands
     size_t gV = 0, PQ = 0, gY2 = 0, gX = 0, g1 = 0, gxh = 0;   // backward
     int64_t vp_bstride = 0;        // floats of partial V per signal
     size_t total = 0;
     int64_t xh_pitch = 0, Xh_pitch = 0;
 };
-Workspace layout(const Shapes& s, int64_t B);
+// with_split: the split-FP16 operand copy of Y2; with_pq: the FP32 backward's P/Q'.
+Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq);
 
 }  // namespace jtfs
 
@@ -95,5 +100,16 @@ struct jtfs_plan {
     int* d_Lb = nullptr;           // per beta: L / 2^kfr
     int* d_rowoff = nullptr;       // per beta: first row of the contraction
     double c1 = 0, c2 = 0, cfr = 0;  // Littlewood-Paley normalisations
+    // split-FP16 contraction operands (hi + lo halves of power-of-two scaled FP32 values)
+    int contraction = 0;           // JTFS_CONTRACTION_FP32 or JTFS_CONTRACTION_SPLIT_F16
+    bool split_ok = false;         // shapes allow the split kernels (W tile fits in LDS)
+    bool split_bwd_ok = false;     // ... and the split backward (register budget)
+    unsigned short* Wsp = nullptr; // [Mp][Kp/8][4][8]: re_hi, re_lo, im_hi, im_lo of W * sw
+    float sw = 1.f;
+    unsigned short* Phsp = nullptr;  // per alpha [Tp/32][2][2][NTp][2][8]: Phi * sphi[alpha]
+    int KpT = 0;                   // Kp rounded up to 32 (rows of WTsp)
+    unsigned short* WTsp = nullptr;  // [KpT][Mp/32][2][2][4][8]: W^T * sw in C-register row order
+    unsigned short* PhTsp = nullptr; // per alpha [Tp][NTp/8][2][8]: Phi * sphi[alpha], tau contiguous
+    std::vector<float> sphi;
     void* owned = nullptr;         // list of device allocations released by destroy
 };

@@ -1,0 +1,19 @@
+// Launchers of the split-FP16 frequential contraction (split.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "plan.hpp"
+
+namespace jtfs {
+bool split_supported(const Shapes& s);
+int build_split_tables(jtfs_plan* P, std::vector<void*>& owned);
+int split_attributes();
+int launch_ysplit(const jtfs_plan* P, int a, const float2* Y2, const float* rowmax, unsigned short* Yh, float* yscale,
+                  int64_t B, hipStream_t st);
+int launch_freq_bwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, const float* yscale, const float* gV,
+                          const float* gvmax, float2* gY2, int64_t B, hipStream_t st);
+int launch_freq_fwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, const float* yscale, float* Vp,
+                          int64_t vp_bstride, int64_t B, hipStream_t st);
+}  // namespace jtfs

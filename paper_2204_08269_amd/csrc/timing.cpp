@@ -25,6 +25,8 @@ bool timing_on() { std::lock_guard<std::mutex> l(g_mu); return g_on; }
 TimedLaunch::TimedLaunch(int stage, hipStream_t st) : stage_(stage), st_(st) {
     std::lock_guard<std::mutex> l(g_mu);
     if (!g_on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;  // no events in graphs
     a_ = take(); b_ = take();
     if (a_ && b_) (void)hipEventRecord(a_, st_);
 }

@@ -21,10 +21,11 @@ class JTFS:
     """Joint time-frequency scattering of real signals x [B, N] (float32, on the GPU).
 
     S1 [B, n1, N/T] and S2 [B, n_alpha, n_beta, 2, L/F, N/T] (spin index 0 is
-    theta = -1).  Calling the object is differentiable through
+    theta = -1).  contraction: "split16" (FP16 matrix cores with split operands,
+    the default where available) or "fp32" (FP32 matrix cores).  Calling the object is differentiable through
     torch.autograd; forward() and vjp() call the library directly."""
 
-    def __init__(self, N, J, Q, J_fr, Q_fr, T, F):
+    def __init__(self, N, J, Q, J_fr, Q_fr, T, F, contraction=None):
         if not torch.cuda.is_available():
             raise RuntimeError("JTFS needs a ROCm GPU (no CPU fallback)")
         self.lib = _lib.load()
@@ -36,6 +37,12 @@ class JTFS:
         info = _lib.Info()
         _lib.check(self.lib.jtfs_plan_info(self.plan, ctypes.byref(info)))
         self.info = info
+        if contraction is not None:
+            mode = {"fp32": _lib.JTFS_CONTRACTION_FP32, "split16": _lib.JTFS_CONTRACTION_SPLIT_F16}[contraction]
+            _lib.check(self.lib.jtfs_plan_set_contraction(self.plan, mode))
+        m = ctypes.c_int(0)
+        _lib.check(self.lib.jtfs_plan_get_contraction(self.plan, ctypes.byref(m)))
+        self.contraction = "split16" if m.value == _lib.JTFS_CONTRACTION_SPLIT_F16 else "fp32"
         self.N = int(N)
         self.s1_shape = (info.n1, info.out_t)
         self.s2_shape = (info.n_alpha, info.n_beta, 2, info.out_l, info.out_t)
@@ -124,3 +131,53 @@ class _JTFSFunction(torch.autograd.Function):
         ctx.ws = None
         gx = ctx.op.vjp(x, gs1, gs2, ws=ws, reuse_forward=True)
         return gx, None
+
+
+class JTFSBucket:
+    """Ragged batch: signals of lengths `lengths` (zero-padded to powers of two,
+    one plan per padded length), run as one recorded HIP graph.
+
+    run(x_packed, g_packed=None) takes the signals back to back (float32, CUDA)
+    and returns the packed coefficients (and the packed gradient with respect to
+    the input samples when a packed cotangent is given).  Must be called on a
+    non-default stream (graph capture)."""
+
+    def __init__(self, lengths, J, Q, J_fr, Q_fr, T, F):
+        if not torch.cuda.is_available():
+            raise RuntimeError("JTFSBucket needs a ROCm GPU (no CPU fallback)")
+        self.lib = _lib.load()
+        self.lengths = [int(v) for v in lengths]
+        n = len(self.lengths)
+        arr = (ctypes.c_int64 * n)(*self.lengths)
+        self.params = _lib.params(16, J, Q, J_fr, Q_fr, T, F)
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.jtfs_bucket_create(ctypes.byref(h), arr, n, ctypes.byref(self.params)))
+        self.h = h
+        xo = (ctypes.c_int64 * (n + 1))()
+        so = (ctypes.c_int64 * (n + 1))()
+        _lib.check(self.lib.jtfs_bucket_offsets(self.h, xo, so))
+        self.x_offset = list(xo)
+        self.s_offset = list(so)
+        self.pads = []
+        for L in self.lengths:
+            N = 16
+            while N < L:
+                N *= 2
+            self.pads.append(N)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None and self.h.value:
+                self.lib.jtfs_bucket_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def run(self, x_packed, g_packed=None, out=None, gx_out=None):
+        dev = x_packed.device
+        s = out if out is not None else torch.empty(self.s_offset[-1], dtype=torch.float32, device=dev)
+        gx = None
+        if g_packed is not None:
+            gx = gx_out if gx_out is not None else torch.zeros(self.x_offset[-1], dtype=torch.float32, device=dev)
+        _lib.check(self.lib.jtfs_bucket_run(self.h, _ptr(x_packed), _ptr(s), _ptr(g_packed), _ptr(gx), _stream()))
+        return s, gx

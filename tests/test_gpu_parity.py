@@ -15,9 +15,12 @@ TOL_VJP = 1e-4      # relative L2 of the gradient against the FP64 oracle's VJP
 TOL_FD = 1e-3       # gradient against FP64 central finite differences
 
 
-def gpu_op(p):
+def gpu_op(p, contraction=None):
     from paper_2204_08269_amd.jtfs import JTFS
-    return JTFS(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"])
+    return JTFS(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"], contraction=contraction)
+
+
+MODES = ["fp32", "split16"]
 
 
 def run_forward(op, x):
@@ -62,9 +65,11 @@ def test_filter_tables_match_oracle():
         assert np.max(np.abs(t2 - ref2)) <= 2e-7 * np.max(np.abs(ref2))
 
 
-def test_forward_parity_cfg1_batch():
+@pytest.mark.parametrize("mode", MODES)
+def test_forward_parity_cfg1_batch(mode):
     x = synth.batch(1, B=3)
-    op = gpu_op(P1)
+    op = gpu_op(P1, mode)
+    assert op.contraction == mode
     g1, g2 = run_forward(op, x)
     P = oracle_plan(P1)
     for b in range(3):
@@ -72,11 +77,12 @@ def test_forward_parity_cfg1_batch():
         check_paths(g1[b], g2[b], r1, r2)
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("p", RAGGED)
-def test_forward_parity_ragged_shapes(p):
+def test_forward_parity_ragged_shapes(p, mode):
     rng = np.random.default_rng(p["N"] + p["T"])
     x = (rng.standard_normal((2, p["N"])) * 0.5).astype(np.float32)
-    op = gpu_op(p)
+    op = gpu_op(p, mode)
     g1, g2 = run_forward(op, x)
     P = oracle_plan(p)
     for b in range(2):
@@ -84,12 +90,13 @@ def test_forward_parity_ragged_shapes(p):
         check_paths(g1[b], g2[b], r1, r2)
 
 
-def test_forward_parity_cfg2_full_batch_sampled():
+@pytest.mark.parametrize("mode", MODES)
+def test_forward_parity_cfg2_full_batch_sampled(mode):
     """64 x 2^16 chirps in the benchmark's launch configuration; the oracle
     checks two signals on every S1 path and on three temporal rates of S2."""
     p = synth.PARAMS[2]
     x = synth.batch(2)
-    op = gpu_op(p)
+    op = gpu_op(p, mode)
     g1, g2 = run_forward(op, x)
     P = oracle_plan(p)
     alphas = [0, 6, P.n_alpha - 1]
@@ -98,11 +105,12 @@ def test_forward_parity_cfg2_full_batch_sampled():
         check_paths(g1[b], g2[b], r1, r2, alphas=alphas)
 
 
-def test_pure_tone_closed_form_on_gpu():
+@pytest.mark.parametrize("mode", MODES)
+def test_pure_tone_closed_form_on_gpu(mode):
     """S1 of A cos(2 pi m n/N) is (A/2) |psi_hat_lambda(m/N)| and S2 vanishes."""
     N, m, A = P1["N"], 301, 0.7
     x = synth.tone(N, m, A, 0.3).astype(np.float32)[None]
-    op = gpu_op(P1)
+    op = gpu_op(P1, mode)
     g1, g2 = run_forward(op, x)
     P = oracle_plan(P1)
     expect = 0.5 * A * np.abs(P.psi1_hat[:, m])
@@ -120,9 +128,10 @@ def test_zero_input_gives_zero_and_finite_gradient():
     assert torch.isfinite(g).all() and float(g.abs().max()) == 0.0
 
 
-def test_batch_invariance_and_determinism():
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_invariance_and_determinism(mode):
     x = synth.batch(1, B=4)
-    op = gpu_op(P1)
+    op = gpu_op(P1, mode)
     a1, a2 = run_forward(op, x)
     b1, b2 = run_forward(op, x)
     assert np.array_equal(a1, b1) and np.array_equal(a2, b2)          # run to run
@@ -185,3 +194,49 @@ def test_autograd_function_matches_vjp():
     g_ref = op.vjp(x.detach(), gs1, gs2)
     torch.cuda.synchronize()
     assert torch.equal(x.grad, g_ref)
+
+
+def test_ragged_bucket_graph_matches_oracle_and_replays():
+    """Uneven lengths, bucketed to powers of two and run as one HIP graph: every
+    signal's coefficients equal the oracle's on the zero-padded signal, the
+    gradient equals the oracle's VJP on the true samples, and replays of the
+    graph (with eager work between them) are bitwise identical."""
+    from paper_2204_08269_amd.jtfs import JTFSBucket
+    prm = dict(J=6, Q=(8, 1), J_fr=3, Q_fr=1, T=64, F=4)
+    lengths = [3000, 2048, 5000, 1500, 8000, 2500]
+    rng = np.random.default_rng(77)
+    sigs = [(rng.standard_normal(L) * 0.5).astype(np.float32) for L in lengths]
+    bk = JTFSBucket(lengths, **prm)
+    x = torch.from_numpy(np.concatenate(sigs)).cuda()
+    g = torch.from_numpy(rng.standard_normal(bk.s_offset[-1]).astype(np.float32)).cuda()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        s_a, gx_a = bk.run(x, g)
+    st.synchronize()
+    s_a, gx_a = s_a.cpu().numpy(), gx_a.cpu().numpy()
+    # the graph is keyed by pointers: the same output buffers give true replays
+    out = torch.empty(bk.s_offset[-1], device="cuda")
+    gxo = torch.zeros(bk.x_offset[-1], device="cuda")
+    results = []
+    for rep in range(3):
+        torch.randn(1 << 20, device="cuda").sum()                # eager work between replays
+        torch.cuda.synchronize()
+        with torch.cuda.stream(st):
+            bk.run(x, g, out=out, gx_out=gxo)
+        st.synchronize()
+        results.append((out.cpu().numpy().copy(), gxo.cpu().numpy().copy()))
+    for r in results:
+        assert np.array_equal(r[0], s_a) and np.array_equal(r[1], gx_a)
+    for i, L in enumerate(lengths):
+        N = bk.pads[i]
+        p = dict(N=N, **prm)
+        P = oracle_plan(p)
+        xp = np.zeros(N)
+        xp[:L] = sigs[i]
+        s1n = int(np.prod(P.s1_shape()))
+        seg = s_a[bk.s_offset[i]: bk.s_offset[i + 1]]
+        r1, r2 = O.jtfs(xp, P)
+        check_paths(seg[:s1n].reshape(P.s1_shape()), seg[s1n:].reshape(P.s2_shape()), r1, r2)
+        gseg = g.cpu().numpy()[bk.s_offset[i]: bk.s_offset[i + 1]].astype(np.float64)
+        ref = O.jtfs_vjp(xp, gseg[:s1n].reshape(P.s1_shape()), gseg[s1n:].reshape(P.s2_shape()), P)[:L]
+        assert rel_l2(gx_a[bk.x_offset[i]: bk.x_offset[i + 1]], ref) <= TOL_VJP
