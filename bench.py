@@ -93,6 +93,33 @@ def algorithmic_flops(info, shapes, B, split):
     return {"freq_fwd": fwd, "freq_adj_pq": fwd, "freq_adj_wh": wh}
 
 
+def algorithmic_bytes(info, N, shapes, B):
+    """Mandatory HBM bytes per step of the FFT-based stages: each stage's input
+    plus output at their unpadded sizes, each read or written once (c64 = 8 B,
+    f32 = 4 B).  x_hat has N/2+1 bins, X_hat n1 rows of N_X/2+1 bins, Y2 and
+    its gradient n1 rows of T_alpha values per rate, gX n1 x N_X reals, the
+    first-order gradient spectra n1 x N_X."""
+    n1, NX, NT = info.n1, info.NX, info.out_t
+    xh = 8 * (N // 2 + 1)
+    Xh = 8 * n1 * (NX // 2 + 1)
+    Y2 = 8 * n1 * sum(shapes)
+    S1 = 4 * n1 * NT
+    gX = 4 * n1 * NX
+    g1 = 8 * n1 * NX
+    per = {
+        "input_fft": 4 * N + xh,
+        "scalogram": xh + Xh,
+        "s1": Xh + S1,
+        "second_order": Xh + Y2,
+        "second_adj_fft": 2 * Y2,
+        "second_adj": Y2 + S1 + gX,
+        "first_adj": xh + gX + g1,
+        "band_accum": g1 + xh,
+        "output_fft": xh + 4 * N,
+    }
+    return {k: v * B for k, v in per.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,20 +218,34 @@ def main():
         times.append(time.perf_counter() - t0)
     single_ms = float(np.median(times)) * 1e3
 
-    # roofline of the dominant kernel (HIP-event times over the timed region)
+    # rooflines from HIP-event times over the timed region: MFMA stages against
+    # their algorithmic flops, FFT stages against their mandatory HBM bytes
     shapes = [Po.T_alpha(a) for a in range(Po.n_alpha)]
     flops = algorithmic_flops(op.info, shapes, B, split)
-    dom = max(flops, key=lambda k: stages[k][0])
-    dom_ms, dom_n = stages[dom]
-    achieved = flops[dom] * args.steps / (dom_ms * 1e-3) / 1e12
+    nbytes = algorithmic_bytes(op.info, p["N"], shapes, B)
     peak = PEAK_F16_MFMA if split else PEAK_FP32_MFMA
-    roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 2), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                "launches_per_step": dom_n // args.steps,
-                "avg_launch_ms": round(dom_ms / max(dom_n, 1), 4),
-                "dtype": "f16 operands (hi/lo split, 3 products), f32 accumulate" if split else "f32"}
-    if split:
-        roofline["executed_frac"] = round(3 * achieved / peak, 4)   # the three split products issued
+    stage_roofline = {}
+    for k, (ms, n) in stages.items():
+        if n == 0 or ms <= 0:
+            continue
+        if k in flops:
+            a = flops[k] * args.steps / (ms * 1e-3) / 1e12
+            stage_roofline[k] = {"bound": "mfma", "achieved": round(a, 2), "peak": peak, "unit": "TFLOP/s",
+                                 "frac": round(a / peak, 4)}
+            if split and k != "freq_adj_wh":
+                stage_roofline[k]["executed_frac"] = round(3 * a / peak, 4)
+        elif k in nbytes:
+            a = nbytes[k] * args.steps / (ms * 1e-3) / 1e9
+            stage_roofline[k] = {"bound": "hbm", "achieved": round(a, 1), "peak": PEAK_HBM, "unit": "GB/s",
+                                 "frac": round(a / PEAK_HBM, 4)}
+    dom = max(stage_roofline, key=lambda k: stages[k][0])
+    dom_ms, dom_n = stages[dom]
+    roofline = dict(stage_roofline[dom])
+    roofline.update({"kernel": dom, "traffic": None, "launches_per_step": dom_n // args.steps,
+                     "avg_launch_ms": round(dom_ms / max(dom_n, 1), 4),
+                     "per_launch_algorithmic": (flops[dom] if dom in flops else nbytes[dom]) // max(dom_n // args.steps, 1)})
+    if dom in flops:
+        roofline["dtype"] = "f16 operands (hi/lo split, 3 products), f32 accumulate" if split else "f32"
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Msamples/s", "n_gpus": 1,
@@ -219,6 +260,7 @@ def main():
         "plain_fwd_single_ms": round(single_ms, 3),
         "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "roofline": roofline,
+        "stage_roofline": stage_roofline,
     }
     if cpu is not None:
         from tests._util import path_errors, rel_l2

@@ -178,18 +178,23 @@ void jtfs_bucket_destroy(jtfs_bucket* bk);
  * jtfs_timing_read waits for the recorded events of one stage, returns their
  * summed duration in milliseconds and the number of launches, and clears that
  * stage.  Process-wide; thread-safe.  Disabled by default (no events recorded). */
-#define JTFS_STAGE_INPUT_FFT     0   /* real FFT of x                                   */
-#define JTFS_STAGE_SCALOGRAM     1   /* first order: fold, iFFT, modulus, real FFT, S1  */
-#define JTFS_STAGE_SECOND_ORDER  2   /* second-order temporal wavelets                  */
-#define JTFS_STAGE_FREQ_FWD      3   /* frequential contraction + modulus + time lowpass*/
-#define JTFS_STAGE_FREQ_LOWPASS  4   /* frequency lowpass -> S2                         */
-#define JTFS_STAGE_LOWPASS_ADJ   5   /* adjoint of the frequency lowpass                */
-#define JTFS_STAGE_FREQ_ADJ_PQ   6   /* contraction recompute, lowpass and modulus adj. */
-#define JTFS_STAGE_FREQ_ADJ_WH   7   /* adjoint of the contraction (W^H)                */
-#define JTFS_STAGE_SECOND_ADJ    8   /* second-order and S1 adjoints                    */
-#define JTFS_STAGE_FIRST_ADJ     9   /* modulus and first-order adjoints, accumulation  */
-#define JTFS_STAGE_OUTPUT_FFT   10   /* inverse real FFT to gx                          */
-#define JTFS_NUM_STAGES         11
+#define JTFS_STAGE_INPUT_FFT      0  /* real FFT of x                                    */
+#define JTFS_STAGE_SCALOGRAM      1  /* first order: fold, iFFT, modulus, real FFT of X   */
+#define JTFS_STAGE_S1             2  /* time lowpass of the scalogram -> S1               */
+#define JTFS_STAGE_SECOND_ORDER   3  /* second-order temporal wavelets -> Y2              */
+#define JTFS_STAGE_OPERAND_SPLIT  4  /* Y2 -> scaled FP16 halves (split contraction only) */
+#define JTFS_STAGE_FREQ_FWD       5  /* frequential contraction + modulus + time lowpass  */
+#define JTFS_STAGE_FREQ_LOWPASS   6  /* frequency lowpass -> S2                           */
+#define JTFS_STAGE_LOWPASS_ADJ    7  /* adjoint of the frequency lowpass                  */
+#define JTFS_STAGE_FREQ_ADJ_PQ    8  /* contraction recompute, lowpass and modulus adj.
+                                        (split mode: also the W^H product)                */
+#define JTFS_STAGE_FREQ_ADJ_WH    9  /* adjoint of the contraction (W^H), FP32 mode       */
+#define JTFS_STAGE_SECOND_ADJ_FFT 10 /* forward FFT of the gY2 rows                       */
+#define JTFS_STAGE_SECOND_ADJ     11 /* second-order and S1 adjoints -> gX                */
+#define JTFS_STAGE_FIRST_ADJ      12 /* modulus adjoint and FFT of each first-order row   */
+#define JTFS_STAGE_BAND_ACCUM     13 /* band-limited accumulation over lambda1 -> gx_hat  */
+#define JTFS_STAGE_OUTPUT_FFT     14 /* inverse real FFT to gx                            */
+#define JTFS_NUM_STAGES           15
 int jtfs_timing_enable(int on);
 int jtfs_timing_read(int stage, double* ms, int64_t* launches);
 

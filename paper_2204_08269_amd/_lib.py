@@ -20,8 +20,9 @@ JTFS_ENOTSUP = -6
 JTFS_BWD_REUSE_FORWARD = 1
 JTFS_CONTRACTION_FP32 = 0
 JTFS_CONTRACTION_SPLIT_F16 = 1
-STAGES = ["input_fft", "scalogram", "second_order", "freq_fwd", "freq_lowpass", "lowpass_adj", "freq_adj_pq",
-          "freq_adj_wh", "second_adj", "first_adj", "output_fft"]
+STAGES = ["input_fft", "scalogram", "s1", "second_order", "operand_split", "freq_fwd", "freq_lowpass",
+          "lowpass_adj", "freq_adj_pq", "freq_adj_wh", "second_adj_fft", "second_adj", "first_adj", "band_accum",
+          "output_fft"]
 
 
 class Params(ctypes.Structure):

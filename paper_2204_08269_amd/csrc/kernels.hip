@@ -799,7 +799,7 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
     LAUNCHCHK("scalogram");
     if (s1) {
         const int logNT = s.logN - s.logT;
-        JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, hipLaunchKernelGGL(k_s1, dim3(s.n1, (unsigned)B), dim3(256), sizeof(float2) * s.NT, st, Xh, w.Xh_pitch,
+        JTFS_TIMED(JTFS_STAGE_S1, st, hipLaunchKernelGGL(k_s1, dim3(s.n1, (unsigned)B), dim3(256), sizeof(float2) * s.NT, st, Xh, w.Xh_pitch,
                            P->phiX, s.Mphi, s.logNX, logNT, 1.0f / (float)s.NX, s1, P->tw, P->tw_log));
         LAUNCHCHK("first-order lowpass");
     }
@@ -843,7 +843,7 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
     for (int a = 0; a < s.n_alpha && split; ++a) {
         unsigned short* Yh = (unsigned short*)(base + w.Yh);
         float* ysc = (float*)(base + w.yscale);
-        JTFS_TIMED(JTFS_STAGE_FREQ_FWD, st,
+        JTFS_TIMED(JTFS_STAGE_OPERAND_SPLIT, st,
                    rc = launch_ysplit(P, a, Y2, (const float*)(base + w.rowmax), Yh, ysc, B, st));
         if (rc != JTFS_OK) { set_error("operand split kernel failed"); return rc; }
         JTFS_TIMED(JTFS_STAGE_FREQ_FWD, st, rc = launch_freq_fwd_split(P, a, Yh, ysc, Vp, w.vp_bstride, B, st));
@@ -909,7 +909,7 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     float* ysc = (float*)(base + w.yscale);
     if (split && !(flags & JTFS_BWD_REUSE_FORWARD)) {
         for (int a = 0; a < s.n_alpha; ++a) {
-            JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,
+            JTFS_TIMED(JTFS_STAGE_OPERAND_SPLIT, st,
                        rc = launch_ysplit(P, a, Y2, (const float*)(base + w.rowmax), Yh, ysc, B, st));
             if (rc != JTFS_OK) { set_error("operand split kernel failed"); return rc; }
         }
@@ -922,10 +922,10 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
         const int logC = logTa >= 12 ? 0 : 12 - logTa;
         const size_t lds = (size_t)(1 << logC) * (s.Ta[a] + 1) * sizeof(float2);
         if (logTa >= kRegMinLog) {
-            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st,
+            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st,
                        launch_rowfft_r(P, gY2 + s.yoff[a], yb, (int64_t)s.Tp[a], s.n1, logTa, B, st));
         } else {
-            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
+            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st, hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
                            st, gY2 + s.yoff[a], gY2 + s.yoff[a], logTa, s.n1, logC, yb, (int64_t)s.Tp[a], (int64_t)1,
                            yb, (int64_t)s.Tp[a], (int64_t)1, 0, P->tw, P->tw_log, 0, 1.0f));
         }
@@ -955,10 +955,10 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
         const int logC = logTa >= 12 ? 0 : 12 - logTa;
         const size_t lds = (size_t)(1 << logC) * (s.Ta[a] + 1) * sizeof(float2);
         if (logTa >= kRegMinLog) {
-            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st,
+            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st,
                        launch_rowfft_r(P, gY2 + s.yoff[a], yb, (int64_t)s.Tp[a], s.n1, logTa, B, st));
         } else {
-            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
+            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st, hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
                            st, gY2 + s.yoff[a], gY2 + s.yoff[a], logTa, s.n1, logC, yb, (int64_t)s.Tp[a], (int64_t)1,
                            yb, (int64_t)s.Tp[a], (int64_t)1, 0, P->tw, P->tw_log, 0, 1.0f));
         }
@@ -977,7 +977,7 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     }
     LAUNCHCHK("modulus and first-order adjoint");
     const int Hn = (int)(s.N / 2);
-    JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, hipLaunchKernelGGL(k_band_accum, dim3((unsigned)((Hn + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, g1, s.n1,
+    JTFS_TIMED(JTFS_STAGE_BAND_ACCUM, st, hipLaunchKernelGGL(k_band_accum, dim3((unsigned)((Hn + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, g1, s.n1,
                        s.logNX, P->psi1, P->band1, P->off1, P->lam_range, Hn, gxh, w.xh_pitch));
     LAUNCHCHK("band accumulation");
     JTFS_TIMED(JTFS_STAGE_OUTPUT_FFT, st, hipLaunchKernelGGL(k_irfft_pack, dim3((unsigned)((Hn / 2 + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, gxh,

@@ -24,7 +24,7 @@ constexpr int kTileTh = 128;       // split-FP16 contraction: columns (t) per ti
 constexpr int kKStep = 16;         // frequential GEMM: K (lambda_1) per LDS stage
 constexpr int kChunkT = 4096;      // frequential GEMM: t-range reduced by one workgroup
 constexpr int kLdsFftMax = 14;     // log2 of the largest complex FFT held in LDS
-constexpr int kMaxLogNX = 14;      // longest scalogram row
+constexpr int kMaxLogNX = 15;      // longest scalogram row
 constexpr int kMaxDynLds = 159 * 1024;  // dynamic LDS limit set on kernels (1 KB left for static LDS)
 
 void set_error(const std::string& s);

@@ -240,3 +240,94 @@ def test_ragged_bucket_graph_matches_oracle_and_replays():
         gseg = g.cpu().numpy()[bk.s_offset[i]: bk.s_offset[i + 1]].astype(np.float64)
         ref = O.jtfs_vjp(xp, gseg[:s1n].reshape(P.s1_shape()), gseg[s1n:].reshape(P.s2_shape()), P)[:L]
         assert rel_l2(gx_a[bk.x_offset[i]: bk.x_offset[i + 1]], ref) <= TOL_VJP
+
+
+# Scalogram rows and second-order rows of 2^15 points: each runs as two 2^14-point
+# register transforms (decimation in frequency for the inverse, in time for the
+# forward).  kX = 0 here, so N_X = N and the two fastest temporal rates keep 2^15.
+LONG = dict(N=2 ** 15, J=5, Q=(1, 1), J_fr=2, Q_fr=1, T=2 ** 10, F=2)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_long_rows_forward_and_vjp(mode):
+    P = oracle_plan(LONG)
+    assert P.NX == 2 ** 15 and P.T_alpha(0) == 2 ** 15
+    rng = np.random.default_rng(215)
+    x = (rng.standard_normal((2, LONG["N"])) * 0.5).astype(np.float32)
+    op = gpu_op(LONG, mode)
+    g1, g2 = run_forward(op, x)
+    gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape(), seed=5)
+    g = op.vjp(torch.from_numpy(x).cuda(), torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda()).cpu().numpy()
+    for b in range(2):
+        xb = x[b].astype(np.float64)
+        r1, r2 = O.jtfs(xb, P)
+        check_paths(g1[b], g2[b], r1, r2)
+        ref = O.jtfs_vjp(xb, gs1[b].astype(np.float64), gs2[b].astype(np.float64), P)
+        err = rel_l2(g[b], ref)
+        assert err <= TOL_VJP, f"signal {b}: gradient relative L2 {err:.3e}"
+
+
+def test_cfg3_full_batch_sampled_forward_and_gradient():
+    """8 x 2^17 click trains (N_X = 2^15): every S1 path and two temporal rates of
+    S2 of the first and last target against the oracle, and the gradient at the
+    first white-noise start (where texture synthesis differentiates) for a
+    cotangent on S1 and on those two rates.  At the click trains themselves the
+    gradient is ill-conditioned in any FP32 arithmetic: between clicks the
+    high-frequency first-order outputs sit at the rounding floor, and the phase
+    factor y/|y| of the modulus adjoint there is rounding noise (a 1e-7 relative
+    perturbation of y moves the FP64 gradient by about 6 %)."""
+    p = synth.PARAMS[3]
+    y, x0 = synth.cfg3_batch()
+    P = oracle_plan(p)
+    assert P.NX == 2 ** 15
+    alphas = [P.n_alpha - 1, P.n_alpha - 4]
+    op = gpu_op(p)
+    g1, g2 = run_forward(op, y)
+    for b in (0, y.shape[0] - 1):
+        r1, r2 = O.jtfs(y[b].astype(np.float64), P, alphas=alphas)
+        check_paths(g1[b], g2[b], r1, r2, alphas=alphas)
+    gs1, gs2 = synth.cotangents((1,) + P.s1_shape(), (1,) + P.s2_shape(), seed=9)
+    keep = np.zeros(P.n_alpha, bool)
+    keep[alphas] = True
+    gs2[:, ~keep] = 0.0
+    g = op.vjp(torch.from_numpy(x0[:1]).cuda(), torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda())
+    ref = O.jtfs_vjp(x0[0].astype(np.float64), gs1[0].astype(np.float64), gs2[0].astype(np.float64), P)
+    err = rel_l2(g.cpu().numpy()[0], ref)
+    assert err <= TOL_VJP, f"gradient relative L2 {err:.3e}"
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_cfg5_full_batch_sampled_and_properties(mode):
+    """32 x 2^18 FM mixtures (N_X = 2^15, 285 first-order and 24 second-order
+    filters).  S1 rows that the oracle computes one at a time; exact equivariance
+    to a shift by T and batch invariance, which hold at any size; the pure-tone
+    closed form (S1 = (A/2)|psi_hat(m/N)|, S2 = 0)."""
+    p = synth.PARAMS[5]
+    T = p["T"]
+    x = synth.batch(5)
+    P = oracle_plan(p)
+    assert P.NX == 2 ** 15
+    op = gpu_op(p, mode)
+    g1, g2 = run_forward(op, x)
+    # S1 rows from the oracle's stage definitions, one row at a time
+    for b in (0, x.shape[0] - 1):
+        xb = x[b].astype(np.float64)[None, :]
+        for lam in (0, P.n1 // 2, P.n1 - 1):
+            Xr = np.abs(O.filt_decimate(xb, P.psi1_hat[lam], 1 << P.kX))
+            ref = O.time_lowpass(Xr, P, P.kX)[0]
+            err = rel_l2(g1[b, lam], ref)
+            assert err <= TOL, f"signal {b} row {lam}: {err:.3e}"
+    # shift by T moves every output frame by one
+    xs = np.roll(x[:2], T, axis=1)
+    h1, h2 = run_forward(op, xs)
+    check_paths(h1[0], h2[0], np.roll(g1[0], 1, axis=-1), np.roll(g2[0], 1, axis=-1))
+    check_paths(h1[1], h2[1], np.roll(g1[1], 1, axis=-1), np.roll(g2[1], 1, axis=-1))
+    # a signal alone gives the same bits as in the batch
+    c1, c2 = run_forward(op, x[5:6])
+    assert np.array_equal(c1[0], g1[5]) and np.array_equal(c2[0], g2[5])
+    # pure tone on an exact bin
+    m, A = 9001, 0.6
+    t1, t2 = run_forward(op, synth.tone(p["N"], m, A, 1.1).astype(np.float32)[None])
+    expect = 0.5 * A * np.abs(P.psi1_hat[:, m])
+    assert np.max(np.abs(t1[0] - expect[:, None])) <= 1e-5 * expect.max()
+    assert np.max(np.abs(t2)) <= 1e-5 * expect.max()
