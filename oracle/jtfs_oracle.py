@@ -11,6 +11,9 @@ It computes, in float64 and in the order the paper states them:
 * second order, eq. (3):     S2 = | X *_{t,lambda} Psi_{alpha,beta,theta} | *_{t,lambda} Phi_{T,F}
   with the separable joint wavelet of eq. (2), Psi = psi_alpha(t) psi_{beta,theta}(lambda),
   and the dilations of eq. (1)
+* the variant of eq. (4) (``average_fr=False``): no frequential averaging, each
+  (alpha, beta, theta) slice is |X *_{t,lambda} Psi| *_t phi_T on the lambda grid of
+  its frequential wavelet
 * the reverse-mode gradient by Hermitian adjoints of each stage in reverse order (sec. 5)
 
 The paper states the operator only as continuous equations.  The discretisation
@@ -274,8 +277,23 @@ class Plan:
     def s1_shape(self):
         return (self.n1, self.out_t)
 
-    def s2_shape(self):
-        return (self.n_alpha, self.n_beta, 2, self.out_l, self.out_t)
+    @property
+    def M_h(self):
+        """lambda rows of one spin summed over beta on the wavelets' own grids."""
+        return sum(self.L_beta(b) for b in range(self.n_beta))
+
+    def s2_shape(self, average_fr=True):
+        """eq. (3): [n_alpha, n_beta, 2, L/F, N/T].  eq. (4) (no frequential
+        averaging): the ragged slices packed as [n_alpha, sum_beta 2 L_beta, N/T],
+        beta outer and theta inner (see s2_rows)."""
+        if average_fr:
+            return (self.n_alpha, self.n_beta, 2, self.out_l, self.out_t)
+        return (self.n_alpha, 2 * self.M_h, self.out_t)
+
+    def s2_rows(self, b, spin):
+        """Rows of the (beta, theta) slice in the packed eq. (4) output."""
+        o = 2 * sum(self.L_beta(q) for q in range(b)) + spin * self.L_beta(b)
+        return slice(o, o + self.L_beta(b))
 
     # frequential wavelets and lowpass matrices ---------------------------
     def psi_fr(self, b, spin):
@@ -365,8 +383,10 @@ def modulus_adj(gu, z):
     return gu * z / np.maximum(np.abs(z), EPS_MOD)
 
 
-def jtfs(x, P: Plan, return_intermediates=False, alphas=None):
-    """S1 [n1, N/T] and S2 [n_alpha, n_beta, 2, L/F, N/T] of one real signal x.
+def jtfs(x, P: Plan, return_intermediates=False, alphas=None, average_fr=True):
+    """S1 [n1, N/T] and S2 [n_alpha, n_beta, 2, L/F, N/T] of one real signal x
+    (eq. (3)); with ``average_fr=False`` the eq. (4) variant, S2 packed as
+    P.s2_shape(False).
 
     ``alphas`` restricts the second order to those temporal-rate indices (the
     other S2 slices are returned as NaN); used to sample very large cases."""
@@ -376,7 +396,7 @@ def jtfs(x, P: Plan, return_intermediates=False, alphas=None):
     Y1d = first_order_linear(x, P)
     X = np.abs(Y1d)
     S1 = time_lowpass(X, P, P.kX)
-    S2 = np.zeros(P.s2_shape())
+    S2 = np.zeros(P.s2_shape(average_fr))
     inter = {"Y1d": Y1d, "X": X, "Y2": [], "Z": {}}
     todo = range(P.n_alpha) if alphas is None else sorted(set(alphas))
     if alphas is not None:
@@ -392,17 +412,20 @@ def jtfs(x, P: Plan, return_intermediates=False, alphas=None):
                 if return_intermediates:
                     inter["Z"][(a, b, s)] = Z
                 V = time_lowpass(np.abs(Z), P, P.kX + P.k2[a])
-                S2[a, b, s] = Pm @ V
+                if average_fr:
+                    S2[a, b, s] = Pm @ V
+                else:
+                    S2[a, P.s2_rows(b, s)] = V
     if return_intermediates:
         return S1, S2, inter
     return S1, S2
 
 
-def jtfs_vjp(x, gS1, gS2, P: Plan):
+def jtfs_vjp(x, gS1, gS2, P: Plan, average_fr=True):
     """Gradient of sum(gS1*S1) + sum(gS2*S2) with respect to x, by the
-    Hermitian adjoint of every stage applied in reverse order.  Temporal-rate
-    indices whose S2 cotangent is identically zero contribute nothing and are
-    skipped."""
+    Hermitian adjoint of every stage applied in reverse order (gS2 laid out as
+    P.s2_shape(average_fr)).  Temporal-rate indices whose S2 cotangent is
+    identically zero contribute nothing and are skipped."""
     x = np.asarray(x, dtype=np.float64)
     gS1 = np.asarray(gS1, dtype=np.float64)
     gS2 = np.asarray(gS2, dtype=np.float64)
@@ -420,7 +443,7 @@ def jtfs_vjp(x, gS1, gS2, P: Plan):
             for s in range(2):
                 W = P.freq_wavelet_matrix(b, s)
                 Z = W @ Y2
-                gV = Pm.T @ gS2[a, b, s]
+                gV = Pm.T @ gS2[a, b, s] if average_fr else gS2[a, P.s2_rows(b, s)]
                 gU = time_lowpass_adj(gV, P, P.kX + P.k2[a], Ta)
                 gZ = modulus_adj(gU, Z)
                 gY2 += W.conj().T @ gZ
@@ -429,8 +452,8 @@ def jtfs_vjp(x, gS1, gS2, P: Plan):
     return first_order_linear_adj(gY1d, P)
 
 
-def loss(x, gS1, gS2, P):
-    S1, S2 = jtfs(x, P)
+def loss(x, gS1, gS2, P, average_fr=True):
+    S1, S2 = jtfs(x, P, average_fr=average_fr)
     return float(np.sum(gS1 * S1) + np.sum(gS2 * S2))
 
 
@@ -447,7 +470,7 @@ def _circ_direct(a, h, d):
     return a @ C.T
 
 
-def jtfs_direct(x, P: Plan):
+def jtfs_direct(x, P: Plan, average_fr=True):
     """Same operator as jtfs() with every convolution evaluated as a direct sum
     and every filter brought to the time domain by the defining DFT sum."""
     x = np.asarray(x, dtype=np.float64)
@@ -456,7 +479,7 @@ def jtfs_direct(x, P: Plan):
                          for l in range(P.n1)]))
     phiX = dft_direct(gauss_lowpass_hat(P.NX, P.N, P.T), inverse=True)
     S1 = _circ_direct(X.astype(complex), phiX, P.T >> P.kX).real
-    S2 = np.zeros(P.s2_shape())
+    S2 = np.zeros(P.s2_shape(average_fr))
     psi2 = dft_direct(P.psi2_hat, inverse=True)
     for a in range(P.n_alpha):
         Ta = P.T_alpha(a)
@@ -472,5 +495,8 @@ def jtfs_direct(x, P: Plan):
                 h = h0 if s == 0 else h0[(-np.arange(P.L)) % P.L]
                 Z = _circ_direct(Yp.T, h, 1 << P.k_fr[b]).T          # along lambda
                 V = _circ_direct(np.abs(Z).astype(complex), phiU, P.T >> (P.kX + P.k2[a])).real
-                S2[a, b, s] = _circ_direct(V.T, phiF, P.F >> P.k_fr[b]).T
+                if average_fr:
+                    S2[a, b, s] = _circ_direct(V.T, phiF, P.F >> P.k_fr[b]).T
+                else:
+                    S2[a, P.s2_rows(b, s)] = V
     return S1, S2

@@ -190,6 +190,30 @@ def test_cascade_matches_direct_sums(p):
     assert np.max(np.abs(a2 - b2)) <= 1e-12 * np.max(np.abs(b2))
 
 
+@pytest.mark.parametrize("p", SMALL)
+def test_unaveraged_cascade_matches_direct_sums(p):
+    """Eq. (4) (no frequential averaging): FFT cascade against direct sums."""
+    P = O.Plan(p["N"], p["J"], p["Q"][0], p["Q"][1], p["J_fr"], p["Q_fr"], p["T"], p["F"])
+    x = np.random.default_rng(p["N"] + 5).standard_normal(p["N"])
+    a1, a2 = O.jtfs(x, P, average_fr=False)
+    b1, b2 = O.jtfs_direct(x, P, average_fr=False)
+    assert a2.shape == (P.n_alpha, 2 * P.M_h, P.out_t)
+    assert np.max(np.abs(a1 - b1)) <= 1e-12 * np.max(np.abs(b1))
+    assert np.max(np.abs(a2 - b2)) <= 1e-12 * np.max(np.abs(b2))
+
+
+def test_unaveraged_pure_tone_and_frame_shift(P1, x1):
+    """Eq. (4) keeps the closed forms of eq. (3): a pure tone has no second order
+    and a shift by T moves every frame by one."""
+    m, A = 301, 0.7
+    n = np.arange(P1.N)
+    _, s2 = O.jtfs(A * np.cos(2 * np.pi * m * n / P1.N + 0.3), P1, average_fr=False)
+    assert np.max(np.abs(s2)) <= 1e-12
+    _, a2 = O.jtfs(x1, P1, average_fr=False)
+    _, b2 = O.jtfs(np.roll(x1, P1.T), P1, average_fr=False)
+    assert np.max(np.abs(np.roll(a2, 1, axis=-1) - b2)) <= 1e-12 * np.max(np.abs(a2))
+
+
 # ---------------------------------------------------------------- adjoints
 
 def _rdot(a, b):
@@ -240,6 +264,18 @@ def test_vjp_matches_finite_differences(P1, x1):
         v = rng.standard_normal(P1.N)
         h = 1e-6      # truncation error is O(h^2): 6e-5 at 1e-4, 6e-9 here
         fd = (O.loss(x1 + h * v, gS1, gS2, P1) - O.loss(x1 - h * v, gS1, gS2, P1)) / (2 * h)
+        assert abs(fd - g @ v) <= 1e-7 * abs(fd)
+
+
+def test_unaveraged_vjp_matches_finite_differences(P1, x1):
+    """Eq. (4): FP64 central differences against the VJP."""
+    gS1, gS2 = synth.cotangents(P1.s1_shape(), P1.s2_shape(False), seed=21)
+    g = O.jtfs_vjp(x1, gS1, gS2, P1, average_fr=False)
+    rng = np.random.default_rng(4)
+    for _ in range(2):
+        v = rng.standard_normal(P1.N)
+        h = 1e-6
+        fd = (O.loss(x1 + h * v, gS1, gS2, P1, False) - O.loss(x1 - h * v, gS1, gS2, P1, False)) / (2 * h)
         assert abs(fd - g @ v) <= 1e-7 * abs(fd)
 
 
