@@ -15,6 +15,8 @@ It computes, in float64 and in the order the paper states them:
   (alpha, beta, theta) slice is |X *_{t,lambda} Psi| *_t phi_T on the lambda grid of
   its frequential wavelet
 * the reverse-mode gradient by Hermitian adjoints of each stage in reverse order (sec. 5)
+* the mu-log renormalisation of the convnet input (sec. 4): per-path means mu
+  over a set of signals and log(1 + S / (eps mu))
 
 The paper states the operator only as continuous equations.  The discretisation
 used here (each item is a reading of the paper, listed in the design notes):
@@ -500,3 +502,36 @@ def jtfs_direct(x, P: Plan, average_fr=True):
                 else:
                     S2[a, P.s2_rows(b, s)] = V
     return S1, S2
+
+
+# ---------------------------------------------------------------------------
+# mu-log (sec. 4): mean-based renormalisation and pointwise logarithm
+# ---------------------------------------------------------------------------
+
+MULOG_EPS = 0.1   # the constant epsilon of the paper, the same for every path
+
+
+def path_means(S1s, S2s):
+    """mu per path over a set of signals.  S1s [n, n1, N/T] is one path (the
+    first order); S2s [n, n_alpha, n_beta, 2, L/F, N/T] has one path per
+    (alpha, beta, theta).  mu is the mean over the signals and over (lambda, t):
+    the integral over the time-frequency plane divided by its area."""
+    S1s = np.asarray(S1s, np.float64)
+    S2s = np.asarray(S2s, np.float64)
+    mu1 = np.float64(S1s.mean())
+    mu2 = S2s.mean(axis=(0, 4, 5))
+    return mu1, mu2
+
+
+def mulog(S1, S2, mu1, mu2, eps=MULOG_EPS):
+    """log(1 + S / (eps mu(path))) for one or several signals."""
+    S1 = np.asarray(S1, np.float64)
+    S2 = np.asarray(S2, np.float64)
+    return np.log1p(S1 / (eps * mu1)), np.log1p(S2 / (eps * mu2[..., None, None]))
+
+
+def mulog_vjp(S1, S2, mu1, mu2, g1, g2, eps=MULOG_EPS):
+    """Adjoint of mulog in S with mu held fixed: g / (eps mu + S)."""
+    S1 = np.asarray(S1, np.float64)
+    S2 = np.asarray(S2, np.float64)
+    return np.asarray(g1) / (eps * mu1 + S1), np.asarray(g2) / (eps * mu2[..., None, None] + S2)

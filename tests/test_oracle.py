@@ -301,3 +301,38 @@ def test_plan_sizes_follow_readings():
         assert all(k <= int(math.log2(P.F)) for k in P.k_fr)
         assert list(P.k2) == sorted(P.k2) and list(P.k_fr) == sorted(P.k_fr)
         assert P.s2_shape() == (P.n_alpha, P.n_beta, 2, P.L // P.F, P.N // P.T)
+
+
+# ----------------------------------------------------------------- mu-log
+
+def test_mulog_means_and_closed_values():
+    """mu is the plain average of each path (a brute-force loop); S = eps mu (e - 1)
+    maps to exactly 1, S = 0 to 0; the map is increasing; the adjoint matches
+    central differences of the elementwise log."""
+    rng = np.random.default_rng(8)
+    S1 = rng.random((3, 5, 4))
+    S2 = rng.random((3, 2, 3, 2, 4, 4))
+    mu1, mu2 = O.path_means(S1, S2)
+    assert abs(mu1 - sum(S1.ravel()) / S1.size) <= 1e-15
+    for a in range(2):
+        for b in range(3):
+            for t in range(2):
+                vals = [S2[n, a, b, t, l, k] for n in range(3) for l in range(4) for k in range(4)]
+                assert abs(mu2[a, b, t] - sum(vals) / len(vals)) <= 1e-15
+    e = O.MULOG_EPS
+    T1 = np.full_like(S1, e * mu1 * (math.e - 1.0))
+    T2 = e * mu2[None, :, :, :, None, None] * (math.e - 1.0) * np.ones_like(S2)
+    o1, o2 = O.mulog(T1, T2, mu1, mu2)
+    assert np.allclose(o1, 1.0, atol=1e-15) and np.allclose(o2, 1.0, atol=1e-15)
+    z1, z2 = O.mulog(np.zeros_like(S1), np.zeros_like(S2), mu1, mu2)
+    assert not z1.any() and not z2.any()
+    a1, _ = O.mulog(S1, S2, mu1, mu2)
+    b1, _ = O.mulog(S1 + 1e-3, S2, mu1, mu2)
+    assert np.all(b1 > a1)
+    g1, g2 = rng.standard_normal(S1.shape), rng.standard_normal(S2.shape)
+    v1, v2 = O.mulog_vjp(S1, S2, mu1, mu2, g1, g2)
+    h = 1e-6
+    p1, p2 = O.mulog(S1 + h, S2 + h, mu1, mu2)
+    m1, m2 = O.mulog(S1 - h, S2 - h, mu1, mu2)
+    assert np.allclose(v1, g1 * (p1 - m1) / (2 * h), rtol=1e-7, atol=1e-9)
+    assert np.allclose(v2, g2 * (p2 - m2) / (2 * h), rtol=1e-7, atol=1e-9)
