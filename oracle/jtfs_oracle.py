@@ -17,6 +17,8 @@ It computes, in float64 and in the order the paper states them:
 * the reverse-mode gradient by Hermitian adjoints of each stage in reverse order (sec. 5)
 * the mu-log renormalisation of the convnet input (sec. 4): per-path means mu
   over a set of signals and log(1 + S / (eps mu))
+* texture resynthesis (sec. 5): gradient descent on the normalised error
+  ||Sx - Sy|| / ||Sx|| with the bold-driver learning rate
 
 The paper states the operator only as continuous equations.  The discretisation
 used here (each item is a reading of the paper, listed in the design notes):
@@ -535,3 +537,57 @@ def mulog_vjp(S1, S2, mu1, mu2, g1, g2, eps=MULOG_EPS):
     S1 = np.asarray(S1, np.float64)
     S2 = np.asarray(S2, np.float64)
     return np.asarray(g1) / (eps * mu1 + S1), np.asarray(g2) / (eps * mu2[..., None, None] + S2)
+
+
+# ---------------------------------------------------------------------------
+# Texture resynthesis (sec. 5)
+# ---------------------------------------------------------------------------
+
+BOLD_UP = 1.2      # learning-rate factor after an accepted (error-decreasing) step
+BOLD_DOWN = 0.5    # factor after a rejected step; the iterate is kept
+
+
+def texture_target(x, P, average_fr=True):
+    """Coefficients Sx of the target and their norm ||Sx|| (S1 and S2 together)."""
+    S1, S2 = jtfs(x, P, average_fr=average_fr)
+    return S1, S2, math.sqrt(float(np.sum(S1 ** 2) + np.sum(S2 ** 2)))
+
+
+def texture_error_grad(y, target, P, average_fr=True):
+    """E(y) = ||Sx - Sy|| / ||Sx|| and its gradient, the VJP of the cotangent
+    (Sy - Sx) / (||Sy - Sx|| ||Sx||) (zero where Sy = Sx)."""
+    Sx1, Sx2, nx = target
+    S1, S2 = jtfs(y, P, average_fr=average_fr)
+    r1, r2 = S1 - Sx1, S2 - Sx2
+    nr = math.sqrt(float(np.sum(r1 ** 2) + np.sum(r2 ** 2)))
+    if nr == 0.0:
+        return 0.0, np.zeros(P.N)
+    g = jtfs_vjp(y, r1 / (nr * nx), r2 / (nr * nx), P, average_fr=average_fr)
+    return nr / nx, g
+
+
+def texture_resynthesis(x, y0, P, iters, mu0, average_fr=True):
+    """Bold-driver gradient descent from y0 towards the coefficients of x.
+
+    The start is evaluated first; each of the ``iters`` iterations then
+    evaluates one candidate y - mu grad E(y): if its error is lower it is
+    accepted and mu grows by BOLD_UP, otherwise it is rejected and mu shrinks
+    by BOLD_DOWN.  mu0 > 0 is the initial rate; mu0 < 0 sets it relative to the
+    start, |mu0| ||y0|| / ||grad E(y0)||.  Returns the best iterate, the best
+    error after the start and after every iteration, and the final rate."""
+    target = texture_target(x, P, average_fr)
+    y = np.asarray(y0, np.float64)
+    E, g = texture_error_grad(y, target, P, average_fr)
+    gn = float(np.linalg.norm(g))
+    mu = mu0 if mu0 > 0 else (-mu0 * float(np.linalg.norm(y)) / gn if gn > 0 else 0.0)
+    hist = [E]
+    for _ in range(iters):
+        yc = y - mu * g
+        Ec, gc = texture_error_grad(yc, target, P, average_fr)
+        if Ec < E:
+            y, E, g = yc, Ec, gc
+            mu *= BOLD_UP
+        else:
+            mu *= BOLD_DOWN
+        hist.append(E)
+    return y, np.array(hist), mu

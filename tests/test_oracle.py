@@ -336,3 +336,40 @@ def test_mulog_means_and_closed_values():
     m1, m2 = O.mulog(S1 - h, S2 - h, mu1, mu2)
     assert np.allclose(v1, g1 * (p1 - m1) / (2 * h), rtol=1e-7, atol=1e-9)
     assert np.allclose(v2, g2 * (p2 - m2) / (2 * h), rtol=1e-7, atol=1e-9)
+
+
+# ------------------------------------------------------- texture resynthesis
+
+def test_texture_error_gradient_matches_finite_differences(P1, x1):
+    """The gradient of E(y) = ||Sx - Sy|| / ||Sx|| against FP64 central differences."""
+    rng = np.random.default_rng(31)
+    y = rng.standard_normal(P1.N) * np.std(x1)
+    target = O.texture_target(x1, P1)
+    E, g = O.texture_error_grad(y, target, P1)
+    for _ in range(2):
+        v = rng.standard_normal(P1.N)
+        h = 1e-6
+        fd = (O.texture_error_grad(y + h * v, target, P1)[0] - O.texture_error_grad(y - h * v, target, P1)[0]) / (2 * h)
+        assert abs(fd - g @ v) <= 1e-6 * abs(fd)
+
+
+def test_texture_loop_bold_driver_rules(P1, x1):
+    """Starting at the target the error is 0 and nothing moves; from noise the
+    best error never increases, a small first step lowers E by about
+    mu ||grad E||^2 (first order), and mu follows the accept/reject factors."""
+    y, hist, mu = O.texture_resynthesis(x1, x1, P1, 3, 1e-3)
+    assert hist.max() == 0.0 and np.array_equal(y, x1)
+    rng = np.random.default_rng(32)
+    y0 = rng.standard_normal(P1.N) * np.std(x1)
+    target = O.texture_target(x1, P1)
+    E0, g0 = O.texture_error_grad(y0, target, P1)
+    mu0 = 1e-4 * np.linalg.norm(y0) / np.linalg.norm(g0)
+    E1, _ = O.texture_error_grad(y0 - mu0 * g0, target, P1)
+    pred = mu0 * float(g0 @ g0)
+    assert abs((E0 - E1) - pred) <= 1e-2 * pred
+    y, hist, mu = O.texture_resynthesis(x1, y0, P1, 12, -0.05)
+    assert hist[0] == pytest.approx(E0, rel=1e-12)
+    assert np.all(np.diff(hist) <= 0.0) and hist[-1] < 0.9 * hist[0]
+    ups = int(np.sum(np.diff(hist) < 0))
+    mu_start = 0.05 * np.linalg.norm(y0) / np.linalg.norm(g0)
+    assert mu == pytest.approx(mu_start * O.BOLD_UP ** ups * O.BOLD_DOWN ** (12 - ups), rel=1e-12)
