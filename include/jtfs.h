@@ -67,12 +67,22 @@ typedef struct jtfs_plan jtfs_plan;
  * filterbanks; Q1 / Q2 wavelets per octave at first / second order; J_fr octaves
  * and Q_fr wavelets per octave of the frequential filterbank; lowpass supports T
  * (time, samples) and F (log-frequency, bins).  N, T, F are powers of two with
- * 16 <= N <= 2^24, T <= N, F <= L. */
+ * 16 <= N <= 2^24, T <= N, F <= L.  flags: 0 or JTFS_NO_FREQ_AVERAGE (any
+ * other bit gives JTFS_EINVAL). */
 typedef struct {
     int64_t N;
     int32_t J, Q1, Q2, J_fr, Q_fr;
+    uint32_t flags;
     int64_t T, F;
 } jtfs_params;
+
+/* The variant of eq. (4): no frequential lowpass phi_F, so S2 keeps the lambda
+ * grid of each frequential wavelet (L / 2^kfr(beta) rows, kfr capped by log2 F)
+ * and stays equivariant to frequency transposition.  S2 layout then packs the
+ * ragged (beta, theta) slices: [B][n_alpha][2 M_h][N/T] with beta outer, theta
+ * inner: the slice (beta, theta) occupies rows 2 r(beta) + theta L_beta ..
+ * + L_beta - 1, r(beta) = sum of L_beta' over beta' < beta.  S1 is unchanged. */
+#define JTFS_NO_FREQ_AVERAGE 1u
 
 /* Derived sizes. */
 typedef struct {
@@ -87,7 +97,8 @@ typedef struct {
     int64_t out_l;     /* L / F log-frequency rows of S2                             */
     int64_t sum_T;     /* sum over alpha of the second-order lengths NX / 2^k2(alpha) */
     int64_t s1_per_signal;   /* n1 * out_t                                          */
-    int64_t s2_per_signal;   /* n_alpha * n_beta * 2 * out_l * out_t                */
+    int64_t s2_per_signal;   /* n_alpha * n_beta * 2 * out_l * out_t, or with
+                                JTFS_NO_FREQ_AVERAGE n_alpha * 2 * M_h * out_t       */
 } jtfs_info;
 
 /* Host-only queries (no GPU needed). */
@@ -172,6 +183,51 @@ int jtfs_bucket_offsets(const jtfs_bucket* bk, int64_t* x_offset, int64_t* s_off
 int jtfs_bucket_run(jtfs_bucket* bk, const float* x_packed, float* s_packed, const float* g_packed,
                     float* gx_packed, hipStream_t stream);
 void jtfs_bucket_destroy(jtfs_bucket* bk);
+
+/* mu-log renormalisation (sec. 4, the input transform of the convnet): a path
+ * is S1 as a whole or one (alpha, beta, theta) slice of S2 (either layout).
+ * jtfs_path_means writes mu = the mean of each path over the B signals and over
+ * (lambda, t): mu1 [1] for S1 and mu2 [n_alpha * n_beta * 2] (theta fastest),
+ * device FP32, accumulated in FP64.  jtfs_mulog writes log(1 + S / (eps mu)) for
+ * every coefficient (o1, o2 may alias s1, s2); jtfs_mulog_backward writes
+ * gS = g / (eps mu + S), the adjoint with mu held fixed (mu estimated beforehand
+ * over a training set).  eps > 0 (the paper uses 0.1).  All pointers are device
+ * memory in the layouts of jtfs_forward; 1 <= B <= 65535.  Stream-ordered. */
+int jtfs_path_means(const jtfs_plan* plan, const float* s1, const float* s2, int64_t B, float* mu1, float* mu2,
+                    hipStream_t stream);
+int jtfs_mulog(const jtfs_plan* plan, const float* s1, const float* s2, int64_t B, const float* mu1,
+               const float* mu2, float eps, float* o1, float* o2, hipStream_t stream);
+int jtfs_mulog_backward(const jtfs_plan* plan, const float* s1, const float* s2, int64_t B, const float* mu1,
+                        const float* mu2, float eps, const float* g1, const float* g2, float* gs1, float* gs2,
+                        hipStream_t stream);
+
+/* Texture resynthesis (sec. 5): from a start y0, gradient descent on the
+ * normalised error E(y) = ||Sx - Sy|| / ||Sx|| (S1 and S2 of the plan's layout
+ * together) towards the coefficients of a target x, for B independent signals,
+ * with the bold-driver rate: each iteration evaluates the candidate
+ * y - mu grad E(y) (one forward and one backward); a lower error accepts it and
+ * multiplies mu by 1.2, otherwise it is rejected and mu is halved.
+ *   create: the texture keeps `plan` (which must outlive it) and allocates its
+ *     own device state (workspace, coefficients, iterates: about
+ *     B * (workspace + 4 N + 6 coefficients) floats).  mu0 > 0 is the initial
+ *     rate; mu0 < 0 sets it per signal to |mu0| ||y0|| / ||grad E(y0)||.
+ *   set_target: x [B][N] device; computes and keeps Sx and ||Sx||.
+ *   set_start: y0 [B][N] device; evaluates it (error and gradient).
+ *   iterate: `iters` iterations, replayed from one captured HIP graph (the
+ *     stream must not be the legacy null stream).  hist (device, optional):
+ *     hist[i][b] = best error of signal b after iteration i of this call, for
+ *     i < hist_cap.
+ *   read: best iterate y [B][N], its error err [B] and the current rate mu [B]
+ *     (device pointers, each optional).
+ * All calls are stream-ordered.  Errors: JTFS_EINVAL (null pointers, B outside
+ * [1, 65535], mu0 zero or not finite, calls out of order), JTFS_ENOMEM, JTFS_EHIP. */
+typedef struct jtfs_texture jtfs_texture;
+int jtfs_texture_create(jtfs_texture** out, const jtfs_plan* plan, int64_t B, float mu0);
+int jtfs_texture_set_target(jtfs_texture* tex, const float* x, hipStream_t stream);
+int jtfs_texture_set_start(jtfs_texture* tex, const float* y0, hipStream_t stream);
+int jtfs_texture_iterate(jtfs_texture* tex, int iters, float* hist, int hist_cap, hipStream_t stream);
+int jtfs_texture_read(const jtfs_texture* tex, float* y, float* err, float* mu, hipStream_t stream);
+void jtfs_texture_destroy(jtfs_texture* tex);
 
 /* Per-stage kernel timing (tracing).  While enabled, every launch of each stage
  * below is bracketed by a pair of HIP events recorded on the launch's stream.

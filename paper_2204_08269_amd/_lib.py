@@ -18,6 +18,7 @@ JTFS_EHIP = -3
 JTFS_EWORKSPACE = -4
 JTFS_ENOTSUP = -6
 JTFS_BWD_REUSE_FORWARD = 1
+JTFS_NO_FREQ_AVERAGE = 1
 JTFS_CONTRACTION_FP32 = 0
 JTFS_CONTRACTION_SPLIT_F16 = 1
 STAGES = ["input_fft", "scalogram", "s1", "second_order", "operand_split", "freq_fwd", "freq_lowpass",
@@ -27,7 +28,8 @@ STAGES = ["input_fft", "scalogram", "s1", "second_order", "operand_split", "freq
 
 class Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("J", ctypes.c_int32), ("Q1", ctypes.c_int32), ("Q2", ctypes.c_int32),
-                ("J_fr", ctypes.c_int32), ("Q_fr", ctypes.c_int32), ("T", ctypes.c_int64), ("F", ctypes.c_int64)]
+                ("J_fr", ctypes.c_int32), ("Q_fr", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("T", ctypes.c_int64), ("F", ctypes.c_int64)]
 
 
 class Info(ctypes.Structure):
@@ -40,7 +42,10 @@ class Info(ctypes.Structure):
 EXPORTS = ["jtfs_query", "jtfs_query_filters", "jtfs_plan_create", "jtfs_plan_create_ex", "jtfs_plan_info",
            "jtfs_plan_destroy", "jtfs_workspace_size", "jtfs_forward", "jtfs_backward", "jtfs_plan_table",
            "jtfs_plan_set_contraction", "jtfs_plan_get_contraction", "jtfs_bucket_create", "jtfs_bucket_offsets",
-           "jtfs_bucket_run", "jtfs_bucket_destroy", "jtfs_timing_enable", "jtfs_timing_read", "jtfs_last_error"]
+           "jtfs_bucket_run", "jtfs_bucket_destroy", "jtfs_path_means", "jtfs_mulog", "jtfs_mulog_backward",
+           "jtfs_texture_create", "jtfs_texture_set_target", "jtfs_texture_set_start", "jtfs_texture_iterate",
+           "jtfs_texture_read", "jtfs_texture_destroy",
+           "jtfs_timing_enable", "jtfs_timing_read", "jtfs_last_error"]
 
 _lib = None
 
@@ -81,12 +86,22 @@ def load(path: str = LIB_PATH):
     L.jtfs_bucket_run.argtypes = [vp, vp, vp, vp, vp, vp]
     L.jtfs_bucket_destroy.argtypes = [vp]
     L.jtfs_bucket_destroy.restype = None
+    L.jtfs_path_means.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.jtfs_mulog.argtypes = [vp, vp, vp, i64, vp, vp, ctypes.c_float, vp, vp, vp]
+    L.jtfs_mulog_backward.argtypes = [vp, vp, vp, i64, vp, vp, ctypes.c_float, vp, vp, vp, vp, vp]
+    L.jtfs_texture_create.argtypes = [P(vp), vp, i64, ctypes.c_float]
+    L.jtfs_texture_set_target.argtypes = [vp, vp, vp]
+    L.jtfs_texture_set_start.argtypes = [vp, vp, vp]
+    L.jtfs_texture_iterate.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp]
+    L.jtfs_texture_read.argtypes = [vp, vp, vp, vp, vp]
+    L.jtfs_texture_destroy.argtypes = [vp]
+    L.jtfs_texture_destroy.restype = None
     L.jtfs_timing_enable.argtypes = [ctypes.c_int]
     L.jtfs_timing_read.argtypes = [ctypes.c_int, P(ctypes.c_double), P(i64)]
     L.jtfs_last_error.argtypes = []
     L.jtfs_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("jtfs_plan_destroy", "jtfs_bucket_destroy", "jtfs_last_error"):
+        if name not in ("jtfs_plan_destroy", "jtfs_bucket_destroy", "jtfs_texture_destroy", "jtfs_last_error"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -98,8 +113,9 @@ def check(code: int):
     return code
 
 
-def params(N, J, Q, J_fr, Q_fr, T, F) -> Params:
-    return Params(int(N), int(J), int(Q[0]), int(Q[1]), int(J_fr), int(Q_fr), int(T), int(F))
+def params(N, J, Q, J_fr, Q_fr, T, F, average_fr=True) -> Params:
+    return Params(N=int(N), J=int(J), Q1=int(Q[0]), Q2=int(Q[1]), J_fr=int(J_fr), Q_fr=int(Q_fr),
+                  flags=0 if average_fr else JTFS_NO_FREQ_AVERAGE, T=int(T), F=int(F))
 
 
 def query(p: Params) -> Info:

@@ -21,18 +21,37 @@ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 
+// the same operations in FP64 (the input transform runs in double precision)
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+template <typename C> struct cplx;
+template <> struct cplx<float2> {
+    using real = float;
+    static __device__ __forceinline__ float2 make(float x, float y) { return make_float2(x, y); }
+};
+template <> struct cplx<double2> {
+    using real = double;
+    static __device__ __forceinline__ double2 make(double x, double y) { return make_double2(x, y); }
+};
+
 // twiddle e^{sign 2 pi i k / 2^tw_log}, sign = -1 (forward) or +1 (inverse)
-__device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int k, bool inv) {
-    float2 w = tw[k];
+template <typename C>
+__device__ __forceinline__ C twiddle(const C* __restrict__ tw, int k, bool inv) {
+    C w = tw[k];
     if (inv) w.y = -w.y;
     return w;
 }
 
 // In-register 4-point DFT (sign -1 forward, +1 inverse).
-__device__ __forceinline__ void dft4(float2* a, bool inv) {
-    const float2 t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]), t2 = cadd(a[1], a[3]);
-    const float2 d = csub(a[1], a[3]);
-    const float2 t3 = inv ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);   // d * (s i)
+template <typename C>
+__device__ __forceinline__ void dft4(C* a, bool inv) {
+    const C t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]), t2 = cadd(a[1], a[3]);
+    const C d = csub(a[1], a[3]);
+    const C t3 = inv ? cplx<C>::make(-d.y, d.x) : cplx<C>::make(d.y, -d.x);   // d * (s i)
     a[0] = cadd(t0, t2);
     a[2] = csub(t0, t2);
     a[1] = cadd(t1, t3);
@@ -42,32 +61,33 @@ __device__ __forceinline__ void dft4(float2* a, bool inv) {
 // One Stockham pass of radix R = 2^LR over `count` transforms of length 2^logn
 // located at s + t*stride.  Ns = 2^lNs is the length of the sub-transforms
 // already combined.  MAXE bounds the elements each thread holds.
-template <int LR, int MAXE>
-__device__ __forceinline__ void fft_pass(float2* s, int logn, int count, int stride, int lNs,
-                                         const float2* __restrict__ tw, int tw_log, bool inv) {
+template <int LR, int MAXE, typename C>
+__device__ __forceinline__ void fft_pass(C* s, int logn, int count, int stride, int lNs,
+                                         const C* __restrict__ tw, int tw_log, bool inv) {
+    using Rl = typename cplx<C>::real;
     constexpr int R = 1 << LR;
     constexpr int MAXB = MAXE / R;
     const int nb_log = logn - LR;            // butterflies per transform = 2^nb_log
     const int total = count << nb_log;
     const int Ns = 1 << lNs;
     const int tws = tw_log - lNs - LR;       // table step of the angle unit 1/(Ns R)
-    float2 v[MAXB][R];
+    C v[MAXB][R];
 #pragma unroll
     for (int q = 0; q < MAXB; ++q) {
         const int g = threadIdx.x + q * blockDim.x;
         if (g < total) {
             const int t = g >> nb_log;
             const int j = g & ((1 << nb_log) - 1);
-            const float2* src = s + t * stride;
+            const C* src = s + t * stride;
             const int k = j & (Ns - 1);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                float2 a = src[j + (r << nb_log)];
+                C a = src[j + (r << nb_log)];
                 if (r) a = cmul(a, twiddle(tw, (r * k) << tws, inv));
                 v[q][r] = a;
             }
             if constexpr (R == 2) {
-                const float2 a0 = v[q][0], a1 = v[q][1];
+                const C a0 = v[q][0], a1 = v[q][1];
                 v[q][0] = cadd(a0, a1);
                 v[q][1] = csub(a0, a1);
             } else if constexpr (R == 4) {
@@ -75,19 +95,19 @@ __device__ __forceinline__ void fft_pass(float2* s, int logn, int count, int str
             } else {
                 // 8-point DFT as two 4-point DFTs: X[2q] = DFT4(a_r + a_{r+4}),
                 // X[2q+1] = DFT4((a_r - a_{r+4}) w8^r)
-                float2 b[4], c[4];
+                C b[4], c[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     b[r] = cadd(v[q][r], v[q][r + 4]);
                     c[r] = csub(v[q][r], v[q][r + 4]);
                 }
-                const float h = 0.70710678118654752f;
+                const Rl h = (Rl)0.70710678118654752440;
                 // c1 *= w8, c2 *= w8^2 = -/+ i, c3 *= w8^3
-                c[1] = inv ? make_float2(h * (c[1].x - c[1].y), h * (c[1].x + c[1].y))
-                           : make_float2(h * (c[1].x + c[1].y), h * (c[1].y - c[1].x));
-                c[2] = inv ? make_float2(-c[2].y, c[2].x) : make_float2(c[2].y, -c[2].x);
-                c[3] = inv ? make_float2(-h * (c[3].x + c[3].y), h * (c[3].x - c[3].y))
-                           : make_float2(h * (c[3].y - c[3].x), -h * (c[3].x + c[3].y));
+                c[1] = inv ? cplx<C>::make(h * (c[1].x - c[1].y), h * (c[1].x + c[1].y))
+                           : cplx<C>::make(h * (c[1].x + c[1].y), h * (c[1].y - c[1].x));
+                c[2] = inv ? cplx<C>::make(-c[2].y, c[2].x) : cplx<C>::make(c[2].y, -c[2].x);
+                c[3] = inv ? cplx<C>::make(-h * (c[3].x + c[3].y), h * (c[3].x - c[3].y))
+                           : cplx<C>::make(h * (c[3].y - c[3].x), -h * (c[3].x + c[3].y));
                 dft4(b, inv);
                 dft4(c, inv);
 #pragma unroll
@@ -105,7 +125,7 @@ __device__ __forceinline__ void fft_pass(float2* s, int logn, int count, int str
         if (g < total) {
             const int t = g >> nb_log;
             const int j = g & ((1 << nb_log) - 1);
-            float2* dst = s + t * stride;
+            C* dst = s + t * stride;
             const int idx = ((j >> lNs) << (lNs + LR)) + (j & (Ns - 1));
 #pragma unroll
             for (int r = 0; r < R; ++r) dst[idx + r * Ns] = v[q][r];
@@ -117,8 +137,8 @@ __device__ __forceinline__ void fft_pass(float2* s, int logn, int count, int str
 // count transforms of length 2^logn at s + t*stride, all threads of the block
 // taking part; count * 2^logn <= MAXE * blockDim.x.  Starts and ends with the
 // data in LDS; the caller must __syncthreads() before calling.
-template <int MAXE>
-__device__ __forceinline__ void lds_fft(float2* s, int logn, int count, int stride, const float2* __restrict__ tw,
+template <int MAXE, typename C>
+__device__ __forceinline__ void lds_fft(C* s, int logn, int count, int stride, const C* __restrict__ tw,
                         int tw_log, bool inv) {
     int lNs = 0;
     // radix-8 passes while three or more stages remain, then one radix-4 or radix-2

@@ -157,6 +157,14 @@ __global__ void k_fb_twiddle(float2* __restrict__ tw, int tw_log) {
     tw[k] = make_float2((float)c, (float)-s);
 }
 
+__global__ void k_fb_twiddle64(double2* __restrict__ tw, int tw_log) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ((int64_t)1 << tw_log)) return;
+    double s, c;
+    sincospi(2.0 * (double)k / (double)((int64_t)1 << tw_log), &s, &c);
+    tw[k] = make_double2(c, -s);
+}
+
 }  // namespace jtfs
 
 using namespace jtfs;
@@ -243,9 +251,12 @@ extern "C" int jtfs_plan_create_ex(jtfs_plan** out, const jtfs_params* p) {
     // twiddles for every FFT length up to N
     P->tw_log = s.logN;
     P->tw = A.get<float2>((size_t)1 << P->tw_log);
+    P->tw64 = A.get<double2>((size_t)1 << P->tw_log);
     if (A.failed) { set_error("device allocation failed"); return fail(JTFS_ENOMEM); }
     hipLaunchKernelGGL(k_fb_twiddle, dim3((unsigned)((((int64_t)1 << P->tw_log) + 255) / 256)), dim3(256), 0, 0, P->tw,
                        P->tw_log);
+    hipLaunchKernelGGL(k_fb_twiddle64, dim3((unsigned)((((int64_t)1 << P->tw_log) + 255) / 256)), dim3(256), 0, 0,
+                       P->tw64, P->tw_log);
     if (hipGetLastError() != hipSuccess) { set_error("twiddle kernel failed"); return fail(JTFS_EHIP); }
 
     if ((st = build_family(A, s.f1, &P->psi1, &P->band1, &P->off1, &P->c1)) != JTFS_OK) return fail(st);
@@ -330,7 +341,7 @@ extern "C" int jtfs_plan_create(jtfs_plan** out, int64_t N, int J, const int Q[2
                                 int64_t F) {
     if (!Q) { set_error("null pointer"); return JTFS_EINVAL; }
     jtfs_params p{};
-    p.N = N; p.J = J; p.Q1 = Q[0]; p.Q2 = Q[1]; p.J_fr = J_fr; p.Q_fr = Q_fr; p.T = T; p.F = F;
+    p.N = N; p.J = J; p.Q1 = Q[0]; p.Q2 = Q[1]; p.J_fr = J_fr; p.Q_fr = Q_fr; p.T = T; p.F = F; p.flags = 0;
     return jtfs_plan_create_ex(out, &p);
 }
 

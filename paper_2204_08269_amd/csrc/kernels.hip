@@ -40,28 +40,36 @@ __device__ __forceinline__ int crow(int r, int h) { return 8 * (r >> 2) + 4 * h 
 // Column mode (ics == 1): C = 2^logC adjacent transforms per workgroup, loaded
 // with adjacent columns on adjacent threads.  Row mode: transforms contiguous.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_fft_cols(const float2* in, float2* out, int loglen,
-                                                  int ncols, int logC, int64_t ib, int64_t ics, int64_t ies, int64_t ob,
-                                                  int64_t ocs, int64_t oes, int twl, const float2* __restrict__ tw,
-                                                  int tw_log, int inv, float scale) {
-    extern __shared__ float2 s[];
+template <typename CI, typename C>
+__device__ __forceinline__ C to_cplx(CI v) {
+    using R = typename cplx<C>::real;
+    return cplx<C>::make((R)v.x, (R)v.y);
+}
+
+template <typename CI, typename C>
+__global__ void __launch_bounds__(1024) k_fft_cols_t(const CI* in, C* out, int loglen, int ncols, int logC,
+                                                    int64_t ib, int64_t ics, int64_t ies, int64_t ob, int64_t ocs,
+                                                    int64_t oes, int twl, const C* __restrict__ tw, int tw_log, int inv,
+                                                    typename cplx<C>::real scale) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    C* s = (C*)lds_raw;
     const int len = 1 << loglen, st = len + 1;
-    const int C = 1 << logC;
-    const int c0 = blockIdx.x * C;
-    const int nc = min(C, ncols - c0);
+    const int Cn = 1 << logC;
+    const int c0 = blockIdx.x * Cn;
+    const int nc = min(Cn, ncols - c0);
     const int tot = nc * len;
     const int64_t b = blockIdx.y;
     in += b * ib;
     out += b * ob;
     if (ics == 1) {
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-            const int c = e & (C - 1), k = e >> logC;
-            s[c * st + k] = in[(int64_t)(c0 + c) + (int64_t)k * ies];
+            const int c = e & (Cn - 1), k = e >> logC;
+            s[c * st + k] = to_cplx<CI, C>(in[(int64_t)(c0 + c) + (int64_t)k * ies]);
         }
     } else {
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
             const int c = e >> loglen, k = e & (len - 1);
-            s[c * st + k] = in[(int64_t)(c0 + c) * ics + (int64_t)k * ies];
+            s[c * st + k] = to_cplx<CI, C>(in[(int64_t)(c0 + c) * ics + (int64_t)k * ies]);
         }
     }
     __syncthreads();
@@ -69,51 +77,55 @@ __global__ void __launch_bounds__(1024) k_fft_cols(const float2* in, float2* out
     const int tws = tw_log - twl;
     if (ocs == 1) {
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-            const int c = e & (C - 1), k = e >> logC;
-            float2 v = s[c * st + k];
+            const int c = e & (Cn - 1), k = e >> logC;
+            C v = s[c * st + k];
             if (twl) v = cmul(v, twiddle(tw, ((c0 + c) * k) << tws, inv != 0));
-            out[(int64_t)(c0 + c) + (int64_t)k * oes] = cscale(v, scale);
+            out[(int64_t)(c0 + c) + (int64_t)k * oes] = cplx<C>::make(v.x * scale, v.y * scale);
         }
     } else {
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
             const int c = e >> loglen, k = e & (len - 1);
-            float2 v = s[c * st + k];
+            C v = s[c * st + k];
             if (twl) v = cmul(v, twiddle(tw, ((c0 + c) * k) << tws, inv != 0));
-            out[(int64_t)(c0 + c) * ocs + (int64_t)k * oes] = cscale(v, scale);
+            out[(int64_t)(c0 + c) * ocs + (int64_t)k * oes] = cplx<C>::make(v.x * scale, v.y * scale);
         }
     }
 }
 
-// Real-input spectrum from the half-length complex FFT of z[k] = x[2k] + i x[2k+1]:
-// X[m] = E[m] + w_n^m O[m], E/O the spectra of the even/odd samples; in place on
-// rows of pitch H+1 (H = n/2), bins 0..H.
-__global__ void k_rfft_post(float2* __restrict__ xh, int64_t pitch, int logn, const float2* __restrict__ tw,
-                            int tw_log) {
+// The FP32 transform used by the intermediate stages.
+#define k_fft_cols k_fft_cols_t<float2, float2>
+
+// Real-input spectrum in FP64 from the half-length complex FFT of
+// z[k] = x[2k] + i x[2k+1] (z rows of pitch zp): X[m] = E[m] + w_n^m O[m], E/O the
+// spectra of the even/odd samples; bins 0..H rounded once to FP32 into rows of
+// pitch H+1 (H = n/2).
+__global__ void k_rfft_post64(const double2* __restrict__ z, int64_t zp, float2* __restrict__ xh, int64_t pitch,
+                              int logn, const double2* __restrict__ tw, int tw_log) {
     const int H = 1 << (logn - 1);
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m > H / 2) return;
+    const double2* zr = z + (int64_t)blockIdx.y * zp;
     float2* row = xh + (int64_t)blockIdx.y * pitch;
     const int tws = tw_log - logn;
     if (m == 0) {
-        const float2 z = row[0];
-        row[0] = make_float2(z.x + z.y, 0.f);
-        row[H] = make_float2(z.x - z.y, 0.f);
+        const double2 q = zr[0];
+        row[0] = make_float2((float)(q.x + q.y), 0.f);
+        row[H] = make_float2((float)(q.x - q.y), 0.f);
         return;
     }
-    const float2 a = row[m], b = row[H - m];
-    auto spec = [&](float2 p, float2 q, int k) {
-        const float2 E = make_float2(0.5f * (p.x + q.x), 0.5f * (p.y - q.y));
-        const float2 D = make_float2(p.x - q.x, p.y + q.y);          // p - conj(q)
-        const float2 O = make_float2(0.5f * D.y, -0.5f * D.x);      // D / (2i)
-        return cadd(E, cmul(O, tw[k << tws]));
+    const double2 a = zr[m], b = zr[H - m];
+    auto spec = [&](double2 p, double2 q, int k) {
+        const double2 E = make_double2(0.5 * (p.x + q.x), 0.5 * (p.y - q.y));
+        const double2 D = make_double2(p.x - q.x, p.y + q.y);          // p - conj(q)
+        const double2 O = make_double2(0.5 * D.y, -0.5 * D.x);      // D / (2i)
+        const double2 X = cadd(E, cmul(O, tw[k << tws]));
+        return make_float2((float)X.x, (float)X.y);
     };
-    const float2 Xm = spec(a, b, m);
-    const float2 Xn = spec(b, a, H - m);
-    row[m] = Xm;
-    row[H - m] = Xn;
+    row[m] = spec(a, b, m);
+    row[H - m] = spec(b, a, H - m);
 }
 
-// Inverse of k_rfft_post: Z'[k] = (X[k] + conj X[H-k]) + i w_n^{-k} (X[k] - conj X[H-k]),
+// Inverse of the real-spectrum post-pass: Z'[k] = (X[k] + conj X[H-k]) + i w_n^{-k} (X[k] - conj X[H-k]),
 // whose unnormalised inverse FFT is n times the interleaved real signal.
 __global__ void k_irfft_pack(const float2* __restrict__ xh, int64_t pitch, float2* __restrict__ z, int64_t zpitch,
                              int logn, const float2* __restrict__ tw, int tw_log) {
@@ -402,19 +414,42 @@ __global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, in
     }
 }
 
+// Eq. (4) (no frequential lowpass): V summed over its partial slots and stored per
+// (beta, theta) at rows 2 rowoff(beta) + theta Lb + l of S2[b][alpha][2 Mh][NT].
+// lambda runs fastest so that the partial-slot reads are contiguous.
+__global__ void __launch_bounds__(256) k_v_out(const float* __restrict__ Vp, int64_t vp_bstride, int slot0,
+                                               int nslots, int nlt, int NTp, int NT, const int* __restrict__ Lbv,
+                                               const int* __restrict__ rowoffv, int Mh, int alpha, int n_alpha,
+                                               float* __restrict__ S2) {
+    const int beta = blockIdx.x, th = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    const int Lb = Lbv[beta], ro = rowoffv[beta];
+    const float* Vb = Vp + b * vp_bstride;
+    float* o = S2 + ((b * n_alpha + alpha) * 2 * (int64_t)Mh + 2 * ro + th * Lb) * NT;
+    for (int e = threadIdx.x; e < Lb * NT; e += blockDim.x) {
+        const int tau = e / Lb, l = e - tau * Lb;
+        const int row = ro + l, lt = row / kTileL, lr = row % kTileL;
+        float acc = 0.f;
+        for (int sl = 0; sl < nslots; ++sl)
+            acc += Vb[(((int64_t)(slot0 + sl) * nlt + lt) * 2 + th) * NTp * kTileL + (int64_t)tau * kTileL + lr];
+        o[(int64_t)l * NT + tau] = acc;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Backward.
 // ---------------------------------------------------------------------------
 
 // gV[b][alpha][theta][rowoff+l][tau] = sum_m PF_beta[m][l] gS2[b][alpha][beta][theta][m][tau]
-// (adjoint of the frequency lowpass); block n_beta zeroes the padding rows.
+// (adjoint of the frequency lowpass), or with avg = 0 (eq. (4)) the gS2 row
+// itself; block n_beta zeroes the padding rows.
 // Also writes, per (signal, alpha, spin, beta), the largest row sum over tau of
 // |gV| (a bound used to scale the split backward contraction).
 __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, const float* __restrict__ PFall,
                                                 const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
                                                 const int* __restrict__ rowoffv, int n_beta, int NL, int NT, int NTp,
-                                                int Mh, int Mp, int alpha, int n_alpha, float* __restrict__ gV,
-                                                float* __restrict__ gvmax) {
+                                                int Mh, int Mp, int alpha, int n_alpha, int avg,
+                                                float* __restrict__ gV, float* __restrict__ gvmax) {
     __shared__ float rowsum[512];
     const int beta = blockIdx.x, th = blockIdx.y;
     const int64_t b = blockIdx.z;
@@ -427,13 +462,18 @@ __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, c
     for (int l = threadIdx.x; l < Lb; l += blockDim.x) rowsum[l] = 0.f;
     __syncthreads();
     const float* PF = PFall + pfoff[beta];
-    const float* src =
-        gS2 ? gS2 + ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NL) * (int64_t)NT : nullptr;
+    const float* src = !gS2 ? nullptr
+                       : avg ? gS2 + ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NL) * (int64_t)NT
+                             : gS2 + ((b * n_alpha + alpha) * 2 * (int64_t)Mh + 2 * ro + th * Lb) * NT;
     for (int e = threadIdx.x; e < Lb * NTp; e += blockDim.x) {
         const int l = e / NTp, tau = e - l * NTp;
         float acc = 0.f;
-        if (src && tau < NT)
-            for (int m = 0; m < NL; ++m) acc += PF[m * Lb + l] * src[(int64_t)m * NT + tau];
+        if (src && tau < NT) {
+            if (avg)
+                for (int m = 0; m < NL; ++m) acc += PF[m * Lb + l] * src[(int64_t)m * NT + tau];
+            else
+                acc = src[(int64_t)l * NT + tau];
+        }
         g[(int64_t)(ro + l) * NTp + tau] = acc;
         atomicAdd(&rowsum[l], fabsf(acc));
     }
@@ -694,7 +734,8 @@ static bool g_attr_done = false;
 int setup_kernel_attributes() {
     if (g_attr_done) return JTFS_OK;
     const int lds = kMaxDynLds;
-    const void* ks[] = {(const void*)k_fft_cols, (const void*)k_scalogram, (const void*)k_s1, (const void*)k_s2_out,
+    const void* ks[] = {(const void*)k_fft_cols_t<float2, float2>, (const void*)k_fft_cols_t<float2, double2>,
+                        (const void*)k_fft_cols_t<double2, double2>, (const void*)k_scalogram, (const void*)k_s1, (const void*)k_s2_out,
                         (const void*)k_second_order, (const void*)k_scal_bwd_a, (const void*)k_scal_bwd_b};
     for (const void* k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -718,7 +759,7 @@ static void fft_rows(const float2* in, int64_t ip, float2* out, int64_t op, floa
     if (logn <= kLdsFftMax) {
         const int logC = logn >= 12 ? 0 : 12 - logn;       // rows per workgroup
         const size_t lds = (size_t)(1 << logC) * ((1 << logn) + 1) * sizeof(float2);
-        hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((B + (1 << logC) - 1) >> logC)), dim3(1024), lds, st, in, out,
+        hipLaunchKernelGGL((k_fft_cols), dim3((unsigned)((B + (1 << logC) - 1) >> logC)), dim3(1024), lds, st, in, out,
                            logn, (int)B, logC, (int64_t)0, ip, (int64_t)1, (int64_t)0, op, (int64_t)1, 0, P->tw,
                            P->tw_log, (int)inv, scale);
         return;
@@ -729,14 +770,49 @@ static void fft_rows(const float2* in, int64_t ip, float2* out, int64_t op, floa
     int logC = std::max(0, 12 - lq);
     logC = std::min(logC, lp);
     size_t lds = (size_t)(1 << logC) * (Qn + 1) * sizeof(float2);
-    hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)(Pn >> logC), (unsigned)B), dim3(1024), lds, st, in, scratch, lq,
+    hipLaunchKernelGGL((k_fft_cols), dim3((unsigned)(Pn >> logC), (unsigned)B), dim3(1024), lds, st, in, scratch, lq,
                        (int)Pn, logC, ip, (int64_t)1, Pn, (int64_t)1 << logn, Qn, (int64_t)1, logn, P->tw, P->tw_log,
                        (int)inv, 1.0f);
     logC = std::min(std::max(0, 12 - lp), lq);
     lds = (size_t)(1 << logC) * (Pn + 1) * sizeof(float2);
-    hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)(Qn >> logC), (unsigned)B), dim3(1024), lds, st, scratch, out, lp,
+    hipLaunchKernelGGL((k_fft_cols), dim3((unsigned)(Qn >> logC), (unsigned)B), dim3(1024), lds, st, scratch, out, lp,
                        (int)Qn, logC, (int64_t)1 << logn, (int64_t)1, Qn, op, (int64_t)1, Qn, 0, P->tw, P->tw_log,
                        (int)inv, scale);
+}
+
+// Real FFT of the B input rows (N samples) in FP64: the complex FFT of the N/2
+// interleaved pairs (one LDS transform up to 2^13 points, four-step above, the
+// double-precision rows being twice as large), then the real-spectrum
+// post-pass, which rounds each bin once to FP32.  Every later stage works on
+// bands of x_hat, so the only transform that mixes all bands keeps its error
+// below FP32 rounding of each bin (not of the whole spectrum).
+static void input_fft64(const float* x, int64_t B, float2* xh, int64_t xh_pitch, double2* scratch, double2* z,
+                        const jtfs_plan* P, hipStream_t st) {
+    const int logn = P->s.logN - 1;
+    const int64_t H = (int64_t)1 << logn;
+    const float2* in = (const float2*)x;
+    if (logn <= 13) {
+        const int logC = logn >= 12 ? 0 : 12 - logn;
+        const size_t lds = (size_t)(1 << logC) * (H + 1) * sizeof(double2);
+        hipLaunchKernelGGL((k_fft_cols_t<float2, double2>), dim3((unsigned)((B + (1 << logC) - 1) >> logC)), dim3(1024),
+                           lds, st, in, z, logn, (int)B, logC, (int64_t)0, H, (int64_t)1, (int64_t)0, H, (int64_t)1, 0,
+                           P->tw64, P->tw_log, 0, 1.0);
+    } else {
+        const int lq = (logn + 1) / 2, lp = logn - lq;
+        const int64_t Pn = (int64_t)1 << lp, Qn = (int64_t)1 << lq;
+        int logC = std::min(std::max(0, 12 - lq), lp);
+        size_t lds = (size_t)(1 << logC) * (Qn + 1) * sizeof(double2);
+        hipLaunchKernelGGL((k_fft_cols_t<float2, double2>), dim3((unsigned)(Pn >> logC), (unsigned)B), dim3(1024), lds,
+                           st, in, scratch, lq, (int)Pn, logC, H, (int64_t)1, Pn, H, Qn, (int64_t)1, logn, P->tw64,
+                           P->tw_log, 0, 1.0);
+        logC = std::min(std::max(0, 12 - lp), lq);
+        lds = (size_t)(1 << logC) * (Pn + 1) * sizeof(double2);
+        hipLaunchKernelGGL((k_fft_cols_t<double2, double2>), dim3((unsigned)(Qn >> logC), (unsigned)B), dim3(1024), lds,
+                           st, scratch, z, lp, (int)Qn, logC, H, (int64_t)1, Qn, H, (int64_t)1, Qn, 0, P->tw64,
+                           P->tw_log, 0, 1.0);
+    }
+    hipLaunchKernelGGL(k_rfft_post64, dim3((unsigned)((H / 2 + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, z, H,
+                       xh, xh_pitch, P->s.logN, P->tw64, P->tw_log);
 }
 
 }  // namespace jtfs
@@ -781,15 +857,11 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
                   hipStream_t st) {
     const Shapes& s = P->s;
     float2* xh = (float2*)(base + w.xh);
-    float2* tmp = (float2*)(base + w.tmp);
     float2* Xh = (float2*)(base + w.Xh);
     float2* Y2 = (float2*)(base + w.Y2);
-    const int logH = s.logN - 1;
-    JTFS_TIMED(JTFS_STAGE_INPUT_FFT, st, fft_rows((const float2*)x, s.N / 2, xh, w.xh_pitch, tmp, logH, B, false, 1.0f, P, st));
+    JTFS_TIMED(JTFS_STAGE_INPUT_FFT, st, input_fft64(x, B, xh, w.xh_pitch, (double2*)(base + w.tmp64),
+                                                     (double2*)(base + w.z64), P, st));
     LAUNCHCHK("input FFT");
-    JTFS_TIMED(JTFS_STAGE_INPUT_FFT, st, hipLaunchKernelGGL(k_rfft_post, dim3((unsigned)(((s.N / 4) + 1 + 255) / 256), (unsigned)B), dim3(256), 0, st, xh,
-                       w.xh_pitch, s.logN, P->tw, P->tw_log));
-    LAUNCHCHK("input real-FFT post-processing");
     if (s.logNX >= kRegMinLog) {
         JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, launch_scalogram_r(P, xh, w.xh_pitch, Xh, w.Xh_pitch, B, st));
     } else {
@@ -848,8 +920,13 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
         if (rc != JTFS_OK) { set_error("operand split kernel failed"); return rc; }
         JTFS_TIMED(JTFS_STAGE_FREQ_FWD, st, rc = launch_freq_fwd_split(P, a, Yh, ysc, Vp, w.vp_bstride, B, st));
         if (rc != JTFS_OK) { if (rc == JTFS_EHIP) set_error("split contraction launch failed"); return rc; }
-        JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), sizeof(float) * 33 * s.L, st, Vp, w.vp_bstride, (int)s.vchoff[a],
-                           s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2));
+        if (s.avg_fr) {
+            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), sizeof(float) * 33 * s.L, st, Vp, w.vp_bstride, (int)s.vchoff[a],
+                               s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2));
+        } else {
+            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_v_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), 0, st, Vp, w.vp_bstride, (int)s.vchoff[a],
+                               s.nch[a], nlt, s.NTp, s.NT, P->d_Lb, P->d_rowoff, s.Mh, a, s.n_alpha, s2));
+        }
         LAUNCHCHK("frequency lowpass");
     }
     for (int a = 0; a < s.n_alpha && !split; ++a) {
@@ -868,8 +945,13 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
         }
         LAUNCHCHK("frequential contraction");
         }
-        JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), sizeof(float) * 33 * s.L, st, Vp, w.vp_bstride, slot0,
-                           2 * s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2));
+        if (s.avg_fr) {
+            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), sizeof(float) * 33 * s.L, st, Vp, w.vp_bstride, slot0,
+                               2 * s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2));
+        } else {
+            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_v_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), 0, st, Vp, w.vp_bstride, slot0,
+                               2 * s.nch[a], nlt, s.NTp, s.NT, P->d_Lb, P->d_rowoff, s.Mh, a, s.n_alpha, s2));
+        }
         LAUNCHCHK("frequency lowpass");
     }
     return JTFS_OK;
@@ -900,7 +982,7 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     const int nlt = s.Mp / kTileL;
     for (int a = 0; a < s.n_alpha; ++a) {
         JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_s2_bwd, dim3(s.n_beta + 1, 2, (unsigned)B), dim3(256), 0, st, gs2, P->PF, P->d_pfoff, P->d_Lb,
-                           P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, a, s.n_alpha, gV,
+                           P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, a, s.n_alpha, (int)s.avg_fr, gV,
                            (float*)(base + w.gvmax)));
         LAUNCHCHK("frequency lowpass adjoint");
     }
@@ -925,7 +1007,7 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
             JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st,
                        launch_rowfft_r(P, gY2 + s.yoff[a], yb, (int64_t)s.Tp[a], s.n1, logTa, B, st));
         } else {
-            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st, hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
+            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st, hipLaunchKernelGGL((k_fft_cols), dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
                            st, gY2 + s.yoff[a], gY2 + s.yoff[a], logTa, s.n1, logC, yb, (int64_t)s.Tp[a], (int64_t)1,
                            yb, (int64_t)s.Tp[a], (int64_t)1, 0, P->tw, P->tw_log, 0, 1.0f));
         }
@@ -958,7 +1040,7 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
             JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st,
                        launch_rowfft_r(P, gY2 + s.yoff[a], yb, (int64_t)s.Tp[a], s.n1, logTa, B, st));
         } else {
-            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st, hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
+            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st, hipLaunchKernelGGL((k_fft_cols), dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
                            st, gY2 + s.yoff[a], gY2 + s.yoff[a], logTa, s.n1, logC, yb, (int64_t)s.Tp[a], (int64_t)1,
                            yb, (int64_t)s.Tp[a], (int64_t)1, 0, P->tw, P->tw_log, 0, 1.0f));
         }

@@ -44,6 +44,7 @@ struct Shapes {
     int logN = 0, logT = 0, logF = 0;
     int n1 = 0, kX = 0, logNX = 0, n_alpha = 0, n_beta = 0, L = 0, logL = 0;
     int64_t N = 0, NX = 0, T = 0, F = 0;
+    bool avg_fr = true;              // eq. (3); false: eq. (4), no frequency lowpass
     int NT = 0, NTp = 0, NL = 0;     // N/T, padded to 32, L/F
     int Kp = 0;                      // n1 padded to kKStep
     int Mh = 0, Mp = 0;              // frequential rows per spin, padded to kTileL
@@ -64,7 +65,7 @@ const char* last_error();
 
 // Workspace layout for B signals (byte offsets from the workspace base).
 struct Workspace {
-    size_t xh = 0, tmp = 0, Xh = 0, Y2 = 0, Vp = 0;            // forward
+    size_t xh = 0, tmp = 0, tmp64 = 0, z64 = 0, Xh = 0, Y2 = 0, Vp = 0;   // forward
     size_t Yh = 0, rowmax = 0, yscale = 0, gvmax = 0;          // split-FP16 operands
     size_t gV = 0, PQ = 0, gY2 = 0, gX = 0, g1 = 0, gxh = 0;   // backward
     int64_t vp_bstride = 0;        // floats of partial V per signal
@@ -81,6 +82,7 @@ struct jtfs_plan {
     int device = 0;
     int tw_log = 0;
     float2* tw = nullptr;          // e^{-2 pi i k / 2^tw_log}
+    double2* tw64 = nullptr;       // the same in FP64 (input transform)
     float* psi1 = nullptr;         // packed first-order spectra (real)
     int* band1 = nullptr;          // [n1][2] lo, hi
     int64_t* off1 = nullptr;

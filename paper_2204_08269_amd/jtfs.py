@@ -21,15 +21,20 @@ class JTFS:
     """Joint time-frequency scattering of real signals x [B, N] (float32, on the GPU).
 
     S1 [B, n1, N/T] and S2 [B, n_alpha, n_beta, 2, L/F, N/T] (spin index 0 is
-    theta = -1).  contraction: "split16" (FP16 matrix cores with split operands,
-    the default where available) or "fp32" (FP32 matrix cores).  Calling the object is differentiable through
-    torch.autograd; forward() and vjp() call the library directly."""
+    theta = -1), eq. (3).  With average_fr=False, the eq. (4) variant without
+    frequential averaging: S2 [B, n_alpha, 2 M_h, N/T], the (beta, theta) slices
+    of L/2^kfr(beta) rows packed beta-major (s2_rows gives a slice's rows).
+    contraction: "split16" (FP16 matrix cores with split operands, the default
+    where available) or "fp32" (FP32 matrix cores).  Calling the object is
+    differentiable through torch.autograd; forward() and vjp() call the library
+    directly."""
 
-    def __init__(self, N, J, Q, J_fr, Q_fr, T, F, contraction=None):
+    def __init__(self, N, J, Q, J_fr, Q_fr, T, F, contraction=None, average_fr=True):
         if not torch.cuda.is_available():
             raise RuntimeError("JTFS needs a ROCm GPU (no CPU fallback)")
         self.lib = _lib.load()
-        self.params = _lib.params(N, J, Q, J_fr, Q_fr, T, F)
+        self.average_fr = bool(average_fr)
+        self.params = _lib.params(N, J, Q, J_fr, Q_fr, T, F, average_fr)
         self.device = torch.device("cuda", torch.cuda.current_device())
         plan = ctypes.c_void_p()
         _lib.check(self.lib.jtfs_plan_create_ex(ctypes.byref(plan), ctypes.byref(self.params)))
@@ -45,8 +50,18 @@ class JTFS:
         self.contraction = "split16" if m.value == _lib.JTFS_CONTRACTION_SPLIT_F16 else "fp32"
         self.N = int(N)
         self.s1_shape = (info.n1, info.out_t)
-        self.s2_shape = (info.n_alpha, info.n_beta, 2, info.out_l, info.out_t)
+        if self.average_fr:
+            self.s2_shape = (info.n_alpha, info.n_beta, 2, info.out_l, info.out_t)
+        else:
+            self.s2_shape = (info.n_alpha, 2 * info.M_h, info.out_t)
         self._ws = {}
+
+    def s2_rows(self, beta, theta):
+        """Rows of the (beta, theta) slice in the eq. (4) layout (average_fr=False)."""
+        _, _, k = _lib.query_filters(self.params, 2)
+        Lb = [self.info.L >> int(v) for v in k]
+        o = 2 * sum(Lb[:beta]) + theta * Lb[beta]
+        return slice(o, o + Lb[beta])
 
     def __del__(self):
         try:
@@ -95,6 +110,40 @@ class JTFS:
         _lib.check(self.lib.jtfs_backward(self.plan, _ptr(x), _ptr(gs1), _ptr(gs2), _ptr(gx), B, _ptr(ws),
                                           ws.numel(), flags, _stream()))
         return gx
+
+    # mu-log renormalisation (sec. 4) -------------------------------------
+    def _check_s(self, s1, s2):
+        B = s1.shape[0]
+        if tuple(s1.shape) != (B,) + self.s1_shape or tuple(s2.shape) != (B,) + self.s2_shape:
+            raise ValueError("S1 / S2 shapes do not match the plan")
+        return s1.contiguous(), s2.contiguous(), B
+
+    def path_means(self, s1, s2):
+        """mu per path over the batch: (mu1 [1], mu2 [n_alpha * n_beta * 2])."""
+        s1, s2, B = self._check_s(s1, s2)
+        i = self.info
+        mu1 = torch.empty(1, dtype=torch.float32, device=s1.device)
+        mu2 = torch.empty(i.n_alpha * i.n_beta * 2, dtype=torch.float32, device=s1.device)
+        _lib.check(self.lib.jtfs_path_means(self.plan, _ptr(s1), _ptr(s2), B, _ptr(mu1), _ptr(mu2), _stream()))
+        return mu1, mu2
+
+    def mulog(self, s1, s2, mu1, mu2, eps=0.1):
+        """log(1 + S / (eps mu)) per path."""
+        s1, s2, B = self._check_s(s1, s2)
+        o1, o2 = torch.empty_like(s1), torch.empty_like(s2)
+        _lib.check(self.lib.jtfs_mulog(self.plan, _ptr(s1), _ptr(s2), B, _ptr(mu1.contiguous()),
+                                       _ptr(mu2.contiguous()), float(eps), _ptr(o1), _ptr(o2), _stream()))
+        return o1, o2
+
+    def mulog_vjp(self, s1, s2, mu1, mu2, g1, g2, eps=0.1):
+        """Adjoint of mulog with mu fixed: g / (eps mu + S)."""
+        s1, s2, B = self._check_s(s1, s2)
+        g1, g2 = g1.contiguous().float(), g2.contiguous().float()
+        d1, d2 = torch.empty_like(s1), torch.empty_like(s2)
+        _lib.check(self.lib.jtfs_mulog_backward(self.plan, _ptr(s1), _ptr(s2), B, _ptr(mu1.contiguous()),
+                                                _ptr(mu2.contiguous()), float(eps), _ptr(g1), _ptr(g2), _ptr(d1),
+                                                _ptr(d2), _stream()))
+        return d1, d2
 
     def table(self, which: int):
         """Device filter table copied to the host (0: psi1 dense, 1: psi2 dense, 2: W spin -1)."""
@@ -181,3 +230,60 @@ class JTFSBucket:
             gx = gx_out if gx_out is not None else torch.zeros(self.x_offset[-1], dtype=torch.float32, device=dev)
         _lib.check(self.lib.jtfs_bucket_run(self.h, _ptr(x_packed), _ptr(s), _ptr(g_packed), _ptr(gx), _stream()))
         return s, gx
+
+
+class Texture:
+    """Texture resynthesis (sec. 5) of B signals with the plan of ``op``: bold-driver
+    gradient descent on ||Sx - Sy|| / ||Sx||, every step on the GPU.  mu0 > 0 is
+    the initial rate, mu0 < 0 a rate relative to the start (|mu0| ||y0|| / ||grad||)."""
+
+    def __init__(self, op: JTFS, B: int, mu0: float = -0.05):
+        self.op = op
+        self.B = int(B)
+        t = ctypes.c_void_p()
+        _lib.check(op.lib.jtfs_texture_create(ctypes.byref(t), op.plan, self.B, float(mu0)))
+        self.tex = t
+        # iterations are replayed from a captured graph, which needs a stream of its own
+        self.stream = torch.cuda.Stream(device=op.device)
+
+    def _run(self, fn):
+        cur = torch.cuda.current_stream(self.op.device)
+        self.stream.wait_stream(cur)
+        with torch.cuda.stream(self.stream):
+            _lib.check(fn(ctypes.c_void_p(self.stream.cuda_stream)))
+        cur.wait_stream(self.stream)
+
+    def __del__(self):
+        t = getattr(self, "tex", None)
+        if t is not None and t.value:
+            self.op.lib.jtfs_texture_destroy(t)
+            self.tex = None
+
+    def set_target(self, x):
+        x = self.op._check_x(x)
+        if x.shape[0] != self.B:
+            raise ValueError(f"x must hold {self.B} signals")
+        self._x = x                       # kept alive until the stream has used it
+        self._run(lambda st: self.op.lib.jtfs_texture_set_target(self.tex, _ptr(x), st))
+
+    def set_start(self, y0):
+        y0 = self.op._check_x(y0)
+        if y0.shape[0] != self.B:
+            raise ValueError(f"y0 must hold {self.B} signals")
+        self._y0 = y0
+        self._run(lambda st: self.op.lib.jtfs_texture_set_start(self.tex, _ptr(y0), st))
+
+    def iterate(self, iters: int, record: bool = True):
+        """Runs ``iters`` iterations; returns the best error after each [iters, B] (if record)."""
+        hist = torch.empty((max(int(iters), 1), self.B), dtype=torch.float32, device=self.op.device) if record else None
+        cap = hist.shape[0] if record else 0
+        self._run(lambda st: self.op.lib.jtfs_texture_iterate(self.tex, int(iters), _ptr(hist), cap, st))
+        return hist[:iters] if record else None
+
+    def read(self):
+        """(best iterate [B, N], its error [B], current rate [B])."""
+        y = torch.empty((self.B, self.op.N), dtype=torch.float32, device=self.op.device)
+        e = torch.empty(self.B, dtype=torch.float32, device=self.op.device)
+        m = torch.empty(self.B, dtype=torch.float32, device=self.op.device)
+        self._run(lambda st: self.op.lib.jtfs_texture_read(self.tex, _ptr(y), _ptr(e), _ptr(m), st))
+        return y, e, m

@@ -53,6 +53,9 @@ def test_host_plan_matches_oracle(L, cfg):
     assert info.sum_T == sum(P.T_alpha(a) for a in range(P.n_alpha))
     assert info.s1_per_signal == int(np.prod(P.s1_shape()))
     assert info.s2_per_signal == int(np.prod(P.s2_shape()))
+    info4 = L.query(L.params(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"], average_fr=False))
+    assert info4.s2_per_signal == int(np.prod(P.s2_shape(False)))      # eq. (4) packing
+    assert info4.s1_per_signal == info.s1_per_signal and info4.M_h == info.M_h
     for fam, (xi, sg, ks) in enumerate([(P.xi1, P.sigma1, [P.kX] * P.n1), (P.xi2, P.sigma2, P.k2),
                                         (P.xi_fr, P.sigma_fr, P.k_fr)]):
         hx, hs, hk = L.query_filters(prm, fam)
@@ -82,6 +85,15 @@ def test_invalid_parameters_rejected_before_any_hip_call(L, p):
     plan = ctypes.c_void_p()
     assert L.load().jtfs_plan_create_ex(ctypes.byref(plan), ctypes.byref(prm)) == L.JTFS_EINVAL
     assert not plan.value
+
+
+def test_unknown_flag_bits_rejected(L):
+    p = synth.PARAMS[1]
+    prm = L.params(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"])
+    prm.flags = 2
+    info = L.Info()
+    assert L.load().jtfs_query(ctypes.byref(prm), ctypes.byref(info)) == L.JTFS_EINVAL
+    assert ctypes.sizeof(L.Params) == 48
 
 
 def test_null_pointers_rejected(L):

@@ -15,9 +15,10 @@ TOL_VJP = 1e-4      # relative L2 of the gradient against the FP64 oracle's VJP
 TOL_FD = 1e-3       # gradient against FP64 central finite differences
 
 
-def gpu_op(p, contraction=None):
+def gpu_op(p, contraction=None, average_fr=True):
     from paper_2204_08269_amd.jtfs import JTFS
-    return JTFS(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"], contraction=contraction)
+    return JTFS(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"], contraction=contraction,
+                average_fr=average_fr)
 
 
 MODES = ["fp32", "split16"]
@@ -312,7 +313,7 @@ def test_cfg5_full_batch_sampled_and_properties(mode):
     # S1 rows from the oracle's stage definitions, one row at a time
     for b in (0, x.shape[0] - 1):
         xb = x[b].astype(np.float64)[None, :]
-        for lam in (0, P.n1 // 2, P.n1 - 1):
+        for lam in list(range(0, P.n1, 16)) + [P.n1 - 1]:
             Xr = np.abs(O.filt_decimate(xb, P.psi1_hat[lam], 1 << P.kX))
             ref = O.time_lowpass(Xr, P, P.kX)[0]
             err = rel_l2(g1[b, lam], ref)
@@ -331,3 +332,105 @@ def test_cfg5_full_batch_sampled_and_properties(mode):
     expect = 0.5 * A * np.abs(P.psi1_hat[:, m])
     assert np.max(np.abs(t1[0] - expect[:, None])) <= 1e-5 * expect.max()
     assert np.max(np.abs(t2)) <= 1e-5 * expect.max()
+
+
+# Eq. (4): no frequential averaging.  The packed (beta, theta) slices are spread
+# to [n_alpha, n_beta, 2, L, N/T] (rows beyond L_beta zero) so that each
+# (alpha, beta, theta) path is compared on its own.
+def unpack_eq4(S2, P):
+    out = np.zeros(S2.shape[:-2] + (P.n_beta, 2, P.L, P.out_t), S2.dtype)
+    for b in range(P.n_beta):
+        for s in range(2):
+            out[..., b, s, :P.L_beta(b), :] = S2[..., P.s2_rows(b, s), :]
+    return out
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("p", [P1, RAGGED[2], RAGGED[3]])
+def test_unaveraged_forward_and_vjp(p, mode):
+    P = oracle_plan(p)
+    rng = np.random.default_rng(404 + p["N"])
+    x = (rng.standard_normal((2, p["N"])) * 0.5).astype(np.float32)
+    op = gpu_op(p, mode, average_fr=False)
+    assert op.s2_shape == P.s2_shape(False)
+    assert all(op.s2_rows(b, t) == P.s2_rows(b, t) for b in range(P.n_beta) for t in range(2))
+    g1, g2 = run_forward(op, x)
+    gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape(False), seed=13)
+    g = op.vjp(torch.from_numpy(x).cuda(), torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda()).cpu().numpy()
+    for b in range(2):
+        xb = x[b].astype(np.float64)
+        r1, r2 = O.jtfs(xb, P, average_fr=False)
+        check_paths(g1[b], unpack_eq4(g2[b], P), r1, unpack_eq4(r2, P))
+        ref = O.jtfs_vjp(xb, gs1[b].astype(np.float64), gs2[b].astype(np.float64), P, average_fr=False)
+        err = rel_l2(g[b], ref)
+        assert err <= TOL_VJP, f"signal {b}: gradient relative L2 {err:.3e}"
+
+
+@pytest.mark.parametrize("average_fr", [True, False])
+def test_mulog_matches_oracle(average_fr):
+    """mu-log (sec. 4) end to end from x: path means over a batch of 3, the
+    renormalised coefficients per path, and the adjoint with mu fixed."""
+    P = oracle_plan(P1)
+    x = synth.batch(1, B=3)
+    op = gpu_op(P1, average_fr=average_fr)
+    s1, s2 = op.forward(torch.from_numpy(x).cuda())
+    mu1, mu2 = op.path_means(s1, s2)
+    o1, o2 = op.mulog(s1, s2, mu1, mu2)
+    gs1, gs2 = synth.cotangents(tuple(s1.shape), tuple(s2.shape), seed=17)
+    d1, d2 = op.mulog_vjp(s1, s2, mu1, mu2, torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda())
+    refs = [O.jtfs(x[b].astype(np.float64), P, average_fr=average_fr) for b in range(3)]
+    R1 = np.stack([r[0] for r in refs])
+    R2 = np.stack([r[1] for r in refs])
+    if average_fr:
+        m1, m2 = O.path_means(R1, R2)
+        R2u, G2 = R2, gs2
+        g_o2, g_d2 = o2.cpu().numpy(), d2.cpu().numpy()
+    else:
+        m1 = np.float64(R1.mean())
+        m2 = np.array([[[R2[:, a, P.s2_rows(b, t)].mean() for t in range(2)] for b in range(P.n_beta)]
+                       for a in range(P.n_alpha)])
+        R2u, G2 = unpack_eq4(R2, P), unpack_eq4(gs2.astype(np.float64), P)
+        g_o2, g_d2 = unpack_eq4(o2.cpu().numpy(), P), unpack_eq4(d2.cpu().numpy(), P)
+    assert abs(float(mu1.cpu()) - m1) <= 1e-5 * m1
+    assert np.max(np.abs(mu2.cpu().numpy().reshape(m2.shape) - m2) / m2) <= 1e-5
+    e1, e2 = O.mulog(R1, R2u, m1, m2)
+    f1, f2 = O.mulog_vjp(R1, R2u, m1, m2, gs1, G2)
+    for b in range(3):
+        check_paths(o1.cpu().numpy()[b], g_o2[b], e1[b], e2[b])
+        check_paths(d1.cpu().numpy()[b], g_d2[b], f1[b], f2[b])
+
+
+def test_texture_loop_matches_oracle():
+    """Texture resynthesis (sec. 5), every step on the GPU, against the oracle's
+    loop from the same start: the start's error, the best error after each of 8
+    bold-driver iterations, the final iterate and rate, for 2 signals; and 3 + 5
+    iterations in two calls (two graph captures) equal 8 in one."""
+    from paper_2204_08269_amd.jtfs import Texture
+    P = oracle_plan(P1)
+    x = synth.batch(1, B=2)
+    rng = np.random.default_rng(55)
+    y0 = (rng.standard_normal((2, P1["N"])) * x.std(axis=1, keepdims=True)).astype(np.float32)
+    op = gpu_op(P1)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y0).cuda()
+    tex = Texture(op, 2, mu0=-0.05)
+    tex.set_target(xt)
+    tex.set_start(yt)
+    _, e0, _ = tex.read()
+    hist = tex.iterate(8).cpu().numpy()
+    y, e, mu = (v.cpu().numpy() for v in tex.read())
+    e0 = e0.cpu().numpy()
+    for b in range(2):
+        yo, ho, muo = O.texture_resynthesis(x[b].astype(np.float64), y0[b].astype(np.float64), P, 8, -0.05)
+        assert abs(e0[b] - ho[0]) <= 1e-5 * ho[0]
+        assert np.max(np.abs(hist[:, b] - ho[1:]) / ho[1:]) <= 1e-4, (hist[:, b], ho[1:])
+        assert ho[-1] < ho[0]
+        assert rel_l2(y[b], yo) <= 1e-4
+        assert abs(mu[b] - muo) <= 1e-4 * muo
+    tex2 = Texture(op, 2, mu0=-0.05)
+    tex2.set_target(xt)
+    tex2.set_start(yt)
+    h1 = tex2.iterate(3).cpu().numpy()
+    h2 = tex2.iterate(5).cpu().numpy()
+    y2, _, _ = tex2.read()
+    assert np.allclose(np.concatenate([h1, h2]), hist, rtol=1e-6, atol=0)
+    assert rel_l2(y2.cpu().numpy(), y) <= 1e-6
