@@ -106,15 +106,15 @@ def algorithmic_bytes(info, N, shapes, B):
     S1 = 4 * n1 * NT
     gX = 4 * n1 * NX
     g1 = 8 * n1 * NX
+    # (S1 and the band accumulation read only band-limited bins of their inputs;
+    # their mandatory bytes depend on the filter supports and they are not listed)
     per = {
         "input_fft": 4 * N + xh,
         "scalogram": xh + Xh,
-        "s1": Xh + S1,
         "second_order": Xh + Y2,
         "second_adj_fft": 2 * Y2,
         "second_adj": Y2 + S1 + gX,
         "first_adj": xh + gX + g1,
-        "band_accum": g1 + xh,
         "output_fft": xh + 4 * N,
     }
     return {k: v * B for k, v in per.items()}

@@ -155,7 +155,7 @@ struct jtfs_texture {
     std::vector<void*> owned;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    const void* key[2] = {nullptr, nullptr};
+    const void* key[3] = {nullptr, nullptr, nullptr};
 };
 
 static void tex_release(jtfs_texture* t) {
@@ -252,8 +252,9 @@ extern "C" int jtfs_texture_iterate(jtfs_texture* t, int iters, float* hist, int
     if (!t->have_start) { set_error("set the start first"); return JTFS_EINVAL; }
     if (iters < 0 || (hist && hist_cap < 1)) { set_error("invalid iteration count or history capacity"); return JTFS_EINVAL; }
     if (iters == 0) return JTFS_OK;
-    const void* key[2] = {hist, st};
-    if (!(t->exec && key[0] == t->key[0] && key[1] == t->key[1])) {
+    // the graph bakes in the history pointer, its capacity and the stream
+    const void* key[3] = {hist, st, (const void*)(intptr_t)(hist ? hist_cap : 0)};
+    if (!(t->exec && key[0] == t->key[0] && key[1] == t->key[1] && key[2] == t->key[2])) {
         if (t->exec) { (void)hipGraphExecDestroy(t->exec); t->exec = nullptr; }
         if (t->graph) { (void)hipGraphDestroy(t->graph); t->graph = nullptr; }
         if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -270,6 +271,7 @@ extern "C" int jtfs_texture_iterate(jtfs_texture* t, int iters, float* hist, int
             set_error("hipGraphInstantiate failed"); return JTFS_EHIP; }
         t->key[0] = key[0];
         t->key[1] = key[1];
+        t->key[2] = key[2];
     }
     if (hist) hipLaunchKernelGGL(k_tex_zero, dim3(1), dim3(64), 0, st, t->count);
     for (int i = 0; i < iters; ++i)
