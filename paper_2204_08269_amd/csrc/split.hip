@@ -98,9 +98,10 @@ __global__ void k_phsplit(const float* __restrict__ Phi, int Tp, int NTp, float 
     o[8] = lo;
 }
 
-// WTsp[i][c][s][h][p][j]: W[l][i] * sw split (p = re hi, re lo, im hi, im lo) for
+// WTsp[c][i][s][h][p][j]: W[l][i] * sw split (p = re hi, re lo, im hi, im lo) for
 // l = 32 c + crow(8 s + j, h): the rows of a 32-row chunk in the order in which the
-// contraction's C registers hold them.  Rows i >= Kp are zero.
+// contraction's C registers hold them; chunk-major, so that the KpT x 32 block of
+// one chunk is contiguous.  Rows i >= Kp are zero.
 __global__ void k_wtsplit(const float2* __restrict__ Wl, int Mp, int Kp, int KpT, float sw,
                           unsigned short* __restrict__ WTsp) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -109,14 +110,14 @@ __global__ void k_wtsplit(const float2* __restrict__ Wl, int Mp, int Kp, int KpT
     int64_t r = e >> 3;
     const int h = (int)(r & 1); r >>= 1;
     const int s = (int)(r & 1); r >>= 1;
-    const int c = (int)(r % (Mp / 32));
-    const int i = (int)(r / (Mp / 32));
+    const int i = (int)(r % KpT);
+    const int c = (int)(r / KpT);
     const int l = 32 * c + crow(8 * s + j, h);
     const float2 w = i < Kp ? Wl[(int64_t)l * Kp + i] : make_float2(0.f, 0.f);
     _Float16 a, b, cc, d;
     split_h(w.x * sw, a, b);
     split_h(w.y * sw, cc, d);
-    _Float16* o = (_Float16*)WTsp + ((((int64_t)i * (Mp / 32) + c) * 2 + s) * 2 + h) * 32 + j;
+    _Float16* o = (_Float16*)WTsp + ((((int64_t)c * KpT + i) * 2 + s) * 2 + h) * 32 + j;
     o[0] = a; o[8] = b; o[16] = cc; o[24] = d;
 }
 
@@ -349,7 +350,7 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
 // ------------------------------------------------------ backward contraction
 
 // Fused adjoint of the contraction, modulus and time lowpass for one signal and
-// 128 columns t (four waves of 32).  Each wave loops over the 32-row chunks l of
+// 128 columns t (four waves of 32).  The block loops over the 32-row chunks l of
 // both spins and, per chunk:
 //   Z[l][t] = sum_k W[l][k] Y[k][t]  (recomputed; both spins from four products)
 //   gU[l][t] = sum_tau gV[l][tau] Phi[t][tau]       (adjoint of the time lowpass)
@@ -359,6 +360,185 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
 // P and Q' feed the last product straight from the C registers.  gV is split
 // with a per-row scale (max over tau); P, Q' with one scale bounded by
 // 2 max_l sum_tau |gV| max|Phi|; both are powers of two removed exactly.
+//
+// The chunks of split W (32 rows x Kp) and of split W^T (KpT rows x 32) are
+// staged in LDS by direct global-to-LDS loads (no registers) and shared by the
+// four waves: W^T double-buffered (the next chunk lands during the current
+// one), W single-buffered (the next chunk lands during the W^T product, after
+// every wave has finished the recompute).  The waits of a chunk never depend
+// on those loads: they are issued after the chunk's last ordinary global loads.
+// LDS slots are 16 bytes; a fragment segment is 32 consecutive slots (one per
+// lane i32), which the MFMA fragment reads take conflict-free.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glob_void_t;
+
+// one wave copies 64 slots: slot e = g * 64 + lane of the chunk's LDS layout
+__device__ __forceinline__ void dma16(const uint4* src, uint4* lds_group) {
+    __builtin_amdgcn_global_load_lds((glob_void_t*)src, (lds_void_t*)lds_group, 16, 0, 0);
+}
+
+// W chunk c (rows 32c..32c+31): LDS slot e = seg * 32 + r, seg = (2 kq + h) * 4 + p
+__device__ __forceinline__ void stage_w(uint4* Ls, const uint4* Wsrc, int c, int nK, int nkb, int wave, int lane) {
+    const uint4* base = Wsrc + (int64_t)c * (nK * 256);
+    for (int g = wave; g < nK * 4; g += 4) {
+        const int e = g * 64 + lane, seg = e >> 5, r = e & 31;
+        dma16(base + r * (nkb * 4) + seg, Ls + g * 64);
+    }
+}
+
+// W^T chunk c (KpT = 32 NI rows): LDS slot e = seg * 32 + i32, seg = q * 16 + (sp * 2 + h) * 4 + p
+template <int NI>
+__device__ __forceinline__ void stage_t(uint4* Ls, const uint4* Tsrc, int c, int wave, int lane) {
+    const uint4* base = Tsrc + (int64_t)c * (NI * 512);
+#pragma unroll
+    for (int k = 0; k < 2 * NI; ++k) {
+        const int g = wave + 4 * k;
+        const int e = g * 64 + lane, seg = e >> 5, i32 = e & 31;
+        dma16(base + ((seg >> 4) * 32 + i32) * 16 + (seg & 15), Ls + g * 64);
+    }
+}
+
+// One 32-row chunk: recompute, lowpass and modulus adjoints, W^T product.
+template <int NTB, int NI>
+__device__ __forceinline__ void bwd_chunk(int c, int nC, int nK, int nkb, int Mp, int wave, int lane, int h, int i32,
+                                          const uint4* ycol, const uint4* phrow, const float* gvb, float inv_wy,
+                                          float inv_phi, float spq, uint4* Ls_W, const uint4* Tcur, uint4* Tnext,
+                                          const uint4* Wsrc, const uint4* Tsrc, floatx16 (&gyr)[NI],
+                                          floatx16 (&gyi)[NI]) {
+    constexpr int NTp = 32 * NTB;
+    // ---- recompute Z for rows 32c.., columns tw0.. (four independent chains)
+    const uint4* lw = Ls_W + h * 4 * 32 + i32;
+    floatx16 rr = z16(), ri = z16(), ir = z16(), ii = z16();
+    uint4 ya0 = ycol[0], ya1 = ycol[1], ya2 = ycol[2], ya3 = ycol[3];
+    for (int kq = 0; kq < nK; ++kq) {
+        const uint4* wk = lw + kq * 8 * 32;
+        const half8 w0 = as_h8(wk[0]), w1 = as_h8(wk[32]), w2 = as_h8(wk[64]), w3 = as_h8(wk[96]);
+        const half8 y0 = as_h8(ya0), y1 = as_h8(ya1), y2 = as_h8(ya2), y3 = as_h8(ya3);
+        if (kq + 1 < nK) {
+            const uint4* yp = ycol + 8 * (kq + 1);
+            ya0 = yp[0]; ya1 = yp[1]; ya2 = yp[2]; ya3 = yp[3];
+        }
+        rr = mfma16(w0, y0, rr); ri = mfma16(w0, y2, ri); ir = mfma16(w2, y0, ir); ii = mfma16(w2, y2, ii);
+        rr = mfma16(w0, y1, rr); ri = mfma16(w0, y3, ri); ir = mfma16(w2, y1, ir); ii = mfma16(w2, y3, ii);
+        rr = mfma16(w1, y0, rr); ri = mfma16(w1, y2, ri); ir = mfma16(w3, y0, ir); ii = mfma16(w3, y2, ii);
+    }
+    // ---- gV rows of both spins, then the next W^T chunk (lands during this chunk)
+    const int l0 = 32 * c;
+    float4 v[2][NTB * 2][2];
+#pragma unroll
+    for (int spin = 0; spin < 2; ++spin) {
+        const float* gr = gvb + ((int64_t)spin * Mp + l0 + i32) * NTp + 8 * h;
+#pragma unroll
+        for (int kb = 0; kb < NTB * 2; ++kb) {
+            v[spin][kb][0] = *(const float4*)(gr + 16 * kb);
+            v[spin][kb][1] = *(const float4*)(gr + 16 * kb + 4);
+        }
+    }
+    // unconditional (the last chunk reloads itself into the idle buffer): with no
+    // branch here the gV waits below count past these loads
+    const int cn = c + 1 < nC ? c + 1 : c;
+    stage_t<NI>(Tnext, Tsrc, cn, wave, lane);
+    // ---- gU = gV Phi^T for both spins (gV split per row, Phi pre-split)
+    floatx16 gu[2];
+#pragma unroll
+    for (int spin = 0; spin < 2; ++spin) {
+        float mx = 0.f;
+#pragma unroll
+        for (int kb = 0; kb < NTB * 2; ++kb) {
+            const float4 a0 = v[spin][kb][0], a1 = v[spin][kb][1];
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(a0.x), fabsf(a0.y)), fmaxf(fabsf(a0.z), fabsf(a0.w))));
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(a1.x), fabsf(a1.y)), fmaxf(fabsf(a1.z), fabsf(a1.w))));
+        }
+        mx = fmaxf(mx, __shfl_xor(mx, 32));
+        const float sg = pow2_scale(mx);
+        floatx16 acc = z16();
+#pragma unroll
+        for (int kb = 0; kb < NTB * 2; ++kb) {
+            half8 ah, al;
+            const float vv[8] = {v[spin][kb][0].x, v[spin][kb][0].y, v[spin][kb][0].z, v[spin][kb][0].w,
+                                 v[spin][kb][1].x, v[spin][kb][1].y, v[spin][kb][1].z, v[spin][kb][1].w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                _Float16 hi, lo;
+                split_h(vv[j] * sg, hi, lo);
+                ah[j] = hi;
+                al[j] = lo;
+            }
+            const uint4* pp = phrow + 4 * kb;       // k-group 2 kb + h: 32 bytes (hi, lo)
+            const half8 bh = as_h8(pp[0]), bl = as_h8(pp[1]);
+            acc = mfma16(ah, bh, acc);
+            acc = mfma16(ah, bl, acc);
+            acc = mfma16(al, bh, acc);
+        }
+        // row crow(r, h) of the C tile carries that row's gV scale
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float s_row = __shfl(sg, crow(r, h));
+            acc[r] *= inv_phi / s_row;
+        }
+        gu[spin] = acc;
+    }
+    // ---- modulus adjoint, P and Q' (FP32), split with the common scale
+    half8 ph[2][4], pl[2][4];       // [s'][Pr, Pi, Qr, Qi]
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const float ur = (rr[r] - ii[r]) * inv_wy, ui = (ri[r] + ir[r]) * inv_wy;
+        const float dr = (rr[r] + ii[r]) * inv_wy, di = (ri[r] - ir[r]) * inv_wy;
+        const float su = gu[0][r] / fmaxf(sqrtf(ur * ur + ui * ui), kEpsMod);
+        const float sd = gu[1][r] / fmaxf(sqrtf(dr * dr + di * di), kEpsMod);
+        const float gur = su * ur, gui = su * ui, gdr = sd * dr, gdi = sd * di;
+        const float vals[4] = {gur + gdr, gui + gdi, -(gdi - gui), gdr - gur};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            _Float16 hi, lo;
+            split_h(vals[q] * spq, hi, lo);
+            ph[r >> 3][q][r & 7] = hi;
+            pl[r >> 3][q][r & 7] = lo;
+        }
+    }
+    // ---- every wave is done with this W chunk: stage the next one.  Only this
+    // wave's LDS reads have to be complete (lgkmcnt 0; vmcnt and expcnt left at
+    // their maxima in the gfx9 encoding), not the W^T staging just issued: a
+    // fence would wait for that too, since it writes LDS through the vector
+    // memory counter.
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    stage_w(Ls_W, Wsrc, cn, nK, nkb, wave, lane);
+    // ---- gY += Wr^T P + Wi^T Q' (A operand from the staged W^T chunk); two
+    // i-blocks at a time, so that four independent accumulations alternate
+#pragma unroll
+    for (int q0 = 0; q0 < NI; q0 += 2) {
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+            half8 wr[2][2], wi[2][2];             // [block][hi, lo]
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                const int q = q0 + d < NI ? q0 + d : q0;
+                const uint4* lt = Tcur + (q * 16 + (sp * 2 + h) * 4) * 32 + i32;
+                wr[d][0] = as_h8(lt[0]); wr[d][1] = as_h8(lt[32]);
+                wi[d][0] = as_h8(lt[64]); wi[d][1] = as_h8(lt[96]);
+            }
+#pragma unroll
+            for (int term = 0; term < 6; ++term) {
+                // (W part, P/Q' part): Wr hi*P hi, Wr hi*P lo, Wr lo*P hi, then the Wi terms with Q'
+                const int wsel = term < 3 ? 0 : 1, whl = (term % 3) == 2 ? 1 : 0, phl = (term % 3) == 1 ? 1 : 0;
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    if (q0 + d >= NI) continue;
+                    const half8 a = wsel ? wi[d][whl] : wr[d][whl];
+                    const half8 br = phl ? pl[sp][wsel * 2] : ph[sp][wsel * 2];
+                    const half8 bi = phl ? pl[sp][wsel * 2 + 1] : ph[sp][wsel * 2 + 1];
+                    gyr[q0 + d] = mfma16(a, br, gyr[q0 + d]);
+                    gyi[q0 + d] = mfma16(a, bi, gyi[q0 + d]);
+                }
+            }
+        }
+    }
+    // ---- the next chunk's W and W^T have landed; every wave is done with this W^T chunk
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
 template <int NTB, int NI>
 __global__ void __launch_bounds__(256) k_freq_bwd_h(const unsigned short* __restrict__ Yh, int64_t yh_bstride,
                                                     int Tp, int nTt, int nU,
@@ -370,8 +550,11 @@ __global__ void __launch_bounds__(256) k_freq_bwd_h(const unsigned short* __rest
                                                     const float* __restrict__ yscale, int alpha, int n_alpha,
                                                     float sw, float2* __restrict__ gY, int64_t gy_bstride) {
     constexpr int NTp = 32 * NTB;
+    __shared__ uint4 Ls_W[NI * 512];                // nK <= 2 NI k-steps x 8 segments x 32 slots
+    __shared__ uint4 Ls_T0[NI * 512];               // 32 NI rows x 16 segments ... x 32 slots / 32
+    __shared__ uint4 Ls_T1[NI * 512];
     const int u = blockIdx.x;
-    if (u >= nU) return;
+    if (u >= nU) return;                            // whole block
     const int64_t b = u / nTt;
     const int t0 = (u % nTt) * kTileTh;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -395,106 +578,18 @@ __global__ void __launch_bounds__(256) k_freq_bwd_h(const unsigned short* __rest
     const uint4* ycol = (const uint4*)(Yb + ((int64_t)(tw0 + i32) * nkb + h) * 32);   // B operand: column t
     const float* gvb = gV + b * gv_bstride;
     const uint4* phrow = (const uint4*)(PhTsp + ((int64_t)(tw0 + i32) * (NTp / 8) + h) * 16);
+    const uint4* Wsrc = (const uint4*)Wsp;
+    const uint4* Tsrc = (const uint4*)WTsp;
 
+    stage_w(Ls_W, Wsrc, 0, nK, nkb, wave, lane);
+    stage_t<NI>(Ls_T0, Tsrc, 0, wave, lane);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     for (int c = 0; c < nC; ++c) {
-        const int l0 = 32 * c;
-        // ---- recompute Z for rows l0.., columns tw0..
-        const uint4* wrow = (const uint4*)(Wsp + ((int64_t)(l0 + i32) * nkb + h) * 32);  // A operand: row l
-        floatx16 rr = z16(), ri = z16(), ir = z16(), ii = z16();
-        uint4 wa0 = wrow[0], wa1 = wrow[1], wa2 = wrow[2], wa3 = wrow[3];
-        uint4 ya0 = ycol[0], ya1 = ycol[1], ya2 = ycol[2], ya3 = ycol[3];
-        for (int kq = 0; kq < nK; ++kq) {
-            const half8 w0 = as_h8(wa0), w1 = as_h8(wa1), w2 = as_h8(wa2), w3 = as_h8(wa3);
-            const half8 y0 = as_h8(ya0), y1 = as_h8(ya1), y2 = as_h8(ya2), y3 = as_h8(ya3);
-            if (kq + 1 < nK) {
-                const uint4* wp = wrow + 8 * (kq + 1);
-                const uint4* yp = ycol + 8 * (kq + 1);
-                wa0 = wp[0]; wa1 = wp[1]; wa2 = wp[2]; wa3 = wp[3];
-                ya0 = yp[0]; ya1 = yp[1]; ya2 = yp[2]; ya3 = yp[3];
-            }
-            rr = mfma16(w0, y0, rr); rr = mfma16(w0, y1, rr); rr = mfma16(w1, y0, rr);
-            ri = mfma16(w0, y2, ri); ri = mfma16(w0, y3, ri); ri = mfma16(w1, y2, ri);
-            ir = mfma16(w2, y0, ir); ir = mfma16(w2, y1, ir); ir = mfma16(w3, y0, ir);
-            ii = mfma16(w2, y2, ii); ii = mfma16(w2, y3, ii); ii = mfma16(w3, y2, ii);
-        }
-        // ---- gU = gV Phi^T for both spins (gV split per row, Phi pre-split)
-        floatx16 gu[2];
-#pragma unroll
-        for (int spin = 0; spin < 2; ++spin) {
-            const float* gr = gvb + ((int64_t)spin * Mp + l0 + i32) * NTp + 8 * h;
-            float4 v[NTB * 2][2];
-            float mx = 0.f;
-#pragma unroll
-            for (int kb = 0; kb < NTB * 2; ++kb) {
-                v[kb][0] = *(const float4*)(gr + 16 * kb);
-                v[kb][1] = *(const float4*)(gr + 16 * kb + 4);
-                mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[kb][0].x), fabsf(v[kb][0].y)), fmaxf(fabsf(v[kb][0].z), fabsf(v[kb][0].w))));
-                mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[kb][1].x), fabsf(v[kb][1].y)), fmaxf(fabsf(v[kb][1].z), fabsf(v[kb][1].w))));
-            }
-            mx = fmaxf(mx, __shfl_xor(mx, 32));
-            const float sg = pow2_scale(mx);
-            floatx16 acc = z16();
-#pragma unroll
-            for (int kb = 0; kb < NTB * 2; ++kb) {
-                half8 ah, al;
-                const float vv[8] = {v[kb][0].x, v[kb][0].y, v[kb][0].z, v[kb][0].w,
-                                     v[kb][1].x, v[kb][1].y, v[kb][1].z, v[kb][1].w};
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    _Float16 hi, lo;
-                    split_h(vv[j] * sg, hi, lo);
-                    ah[j] = hi;
-                    al[j] = lo;
-                }
-                const uint4* pp = phrow + 4 * kb;       // k-group 2 kb + h: 32 bytes (hi, lo)
-                const half8 bh = as_h8(pp[0]), bl = as_h8(pp[1]);
-                acc = mfma16(ah, bh, acc);
-                acc = mfma16(ah, bl, acc);
-                acc = mfma16(al, bh, acc);
-            }
-            // row crow(r, h) of the C tile carries that row's gV scale
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const float s_row = __shfl(sg, crow(r, h));
-                acc[r] *= inv_phi / s_row;
-            }
-            gu[spin] = acc;
-        }
-        // ---- modulus adjoint, P and Q' (FP32), split with the common scale
-        half8 ph[2][4], pl[2][4];       // [s'][Pr, Pi, Qr, Qi]
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float ur = (rr[r] - ii[r]) * inv_wy, ui = (ri[r] + ir[r]) * inv_wy;
-            const float dr = (rr[r] + ii[r]) * inv_wy, di = (ri[r] - ir[r]) * inv_wy;
-            const float su = gu[0][r] / fmaxf(sqrtf(ur * ur + ui * ui), kEpsMod);
-            const float sd = gu[1][r] / fmaxf(sqrtf(dr * dr + di * di), kEpsMod);
-            const float gur = su * ur, gui = su * ui, gdr = sd * dr, gdi = sd * di;
-            const float vals[4] = {gur + gdr, gui + gdi, -(gdi - gui), gdr - gur};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                _Float16 hi, lo;
-                split_h(vals[q] * spq, hi, lo);
-                ph[r >> 3][q][r & 7] = hi;
-                pl[r >> 3][q][r & 7] = lo;
-            }
-        }
-        // ---- gY += Wr^T P + Wi^T Q'
-#pragma unroll
-        for (int q = 0; q < NI; ++q) {
-#pragma unroll
-            for (int sp = 0; sp < 2; ++sp) {
-                const uint4* wt = (const uint4*)(WTsp + ((((int64_t)(q * 32 + i32) * nC + c) * 2 + sp) * 2 + h) * 32);
-                const half8 wrh = as_h8(wt[0]), wrl = as_h8(wt[1]), wih = as_h8(wt[2]), wil = as_h8(wt[3]);
-                gyr[q] = mfma16(wrh, ph[sp][0], gyr[q]); gyr[q] = mfma16(wrh, pl[sp][0], gyr[q]);
-                gyr[q] = mfma16(wrl, ph[sp][0], gyr[q]);
-                gyr[q] = mfma16(wih, ph[sp][2], gyr[q]); gyr[q] = mfma16(wih, pl[sp][2], gyr[q]);
-                gyr[q] = mfma16(wil, ph[sp][2], gyr[q]);
-                gyi[q] = mfma16(wrh, ph[sp][1], gyi[q]); gyi[q] = mfma16(wrh, pl[sp][1], gyi[q]);
-                gyi[q] = mfma16(wrl, ph[sp][1], gyi[q]);
-                gyi[q] = mfma16(wih, ph[sp][3], gyi[q]); gyi[q] = mfma16(wih, pl[sp][3], gyi[q]);
-                gyi[q] = mfma16(wil, ph[sp][3], gyi[q]);
-            }
-        }
+        uint4* Tc = (c & 1) ? Ls_T1 : Ls_T0;
+        uint4* Tn = (c & 1) ? Ls_T0 : Ls_T1;
+        bwd_chunk<NTB, NI>(c, nC, nK, nkb, Mp, wave, lane, h, i32, ycol, phrow, gvb, inv_wy, inv_phi, spq, Ls_W,
+                           Tc, Tn, Wsrc, Tsrc, gyr, gyi);
     }
     // ---- store gY rows i < Kp, columns tw0.. (FP32 complex)
     const float inv = 1.f / (sw * spq);
@@ -578,13 +673,15 @@ int build_split_tables(jtfs_plan* P, std::vector<void*>& owned) {
         set_error("split-operand construction failed"); return JTFS_EHIP; }
     {
         const int NI = P->KpT / 32;
-        P->split_bwd_ok = (s.NTp == 32 && NI <= 7) || (s.NTp == 64 && NI <= 5);
+        // static LDS of the backward: W chunk + two W^T chunks, 24 NI KB (<= 160 KB)
+        P->split_bwd_ok = (s.NTp == 32 && NI <= 6) || (s.NTp == 64 && NI <= 5);
     }
     P->contraction = JTFS_CONTRACTION_SPLIT_F16;
     return JTFS_OK;
 }
 
 int split_attributes() {
+    // the backward kernels use static LDS only; the forward takes it dynamically
     const void* ks[] = {(const void*)k_freq_fwd_h<1>, (const void*)k_freq_fwd_h<2>};
     for (const void* k : ks)
         if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds) != hipSuccess) {
@@ -629,15 +726,16 @@ static void launch_bwd_ni(int NI, dim3 grid, hipStream_t st, const unsigned shor
     const Shapes& s = P->s;
 #define JTFS_BWD_CASE(ni)                                                                                      \
     case ni:                                                                                                   \
-        hipLaunchKernelGGL((k_freq_bwd_h<NTB, ni>), grid, dim3(256), 0, st, Ya, yhb, Tp, nTt, nU, P->Wsp,     \
+        hipLaunchKernelGGL((k_freq_bwd_h<NTB, ni>), grid, dim3(256), 0, st, Ya,                               \
+                           yhb, Tp, nTt, nU, P->Wsp,                                                            \
                            P->WTsp, s.Kp, s.Mp, PhT, sphi, gVa, gvb, gvmax, s.n_beta, yscale, a, s.n_alpha,    \
                            P->sw, gYa, gyb);                                                                   \
         break;
-    // register budget (one wave per SIMD, no scratch): NI <= 7 at N/T <= 32, NI <= 5 at N/T = 64
+    // LDS 24 NI KB and one wave per SIMD without scratch: NI <= 6 at N/T <= 32, NI <= 5 at N/T = 64
     if constexpr (NTB == 1) {
         switch (NI) {
             JTFS_BWD_CASE(1) JTFS_BWD_CASE(2) JTFS_BWD_CASE(3) JTFS_BWD_CASE(4)
-            JTFS_BWD_CASE(5) JTFS_BWD_CASE(6) JTFS_BWD_CASE(7)
+            JTFS_BWD_CASE(5) JTFS_BWD_CASE(6)
             default: break;
         }
     } else {
