@@ -120,6 +120,60 @@ def algorithmic_bytes(info, N, shapes, B):
     return {k: v * B for k, v in per.items()}
 
 
+# HBM bytes per launch of a stage's kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes (scaled by the same counters on a copy of known size), kept beside the
+# profiles with the hash of the kernel's source; stale once that source changes.
+TRAFFIC_FILES = {"freq_adj_pq": ("profiles/k_freq_bwd_h_64x65536_hbm_traffic.json",
+                                 "paper_2204_08269_amd/csrc/split.hip")}
+
+
+def measured_traffic(stage):
+    import hashlib
+    if stage not in TRAFFIC_FILES:
+        return None
+    rec_path, src = (os.path.join(HERE, v) for v in TRAFFIC_FILES[stage])
+    if not os.path.exists(rec_path):
+        return None
+    rec = json.load(open(rec_path))
+    if rec.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return {"bytes_per_launch": rec["bytes_per_launch"], "fetch_bytes_per_launch": rec["fetch_bytes_per_launch"],
+            "write_bytes_per_launch": rec["write_bytes_per_launch"], "source": os.path.basename(rec_path)}
+
+
+def ragged_batch(torch, dev, runs=3):
+    """Forward + backward of the 256-signal ragged workload through the bucket API."""
+    from paper_2204_08269_amd.jtfs import JTFSBucket
+    p = synth.PARAMS[4]
+    sigs = synth.cfg4_ragged(synth.BATCH[4])
+    lengths = [len(v) for v in sigs]
+    bk = JTFSBucket(lengths, p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"])
+    x = torch.from_numpy(np.concatenate(sigs)).to(dev)
+    g = torch.from_numpy(np.random.default_rng(4).standard_normal(bk.s_offset[-1]).astype(np.float32)).to(dev)
+    out = torch.empty(bk.s_offset[-1], dtype=torch.float32, device=dev)
+    gx = torch.empty(bk.x_offset[-1], dtype=torch.float32, device=dev)
+    st = torch.cuda.Stream(device=dev)
+    st.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(st):
+        bk.run(x, g, out, gx)                    # capture + first replay
+        st.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(runs):
+            bk.run(x, g, out, gx)
+        st.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / runs
+    real, padded = sum(lengths), sum(bk.pads)
+    counts = {}
+    for n in bk.pads:
+        counts[str(n)] = counts.get(str(n), 0) + 1
+    print(f"[bench] ragged batch: {ms:.2f} ms per fwd+bwd run", file=sys.stderr, flush=True)
+    return {"workload": "256 harmonic tones + pink noise, lengths log-uniform in [2^13, 2^16], J=11, Q=(16,1), "
+                        "J_fr=4, Q_fr=1, T=2^10, F=2^3; buckets of power-of-two pads, one HIP graph per run",
+            "ms_per_run": round(ms, 3), "fwd_bwd_msamples_s_real": round(real / (ms * 1e-3) / 1e6, 3),
+            "fwd_bwd_msamples_s_padded": round(padded / (ms * 1e-3) / 1e6, 3),
+            "real_samples": real, "padded_samples": padded, "signals_per_pad": counts}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +185,8 @@ def main():
                     help="frequential contraction arithmetic (default: the plan's, split16 where available)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device copy first (calibrates HBM byte counters)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the fwd+bwd step only (no forward-only or ragged-batch legs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -192,31 +248,38 @@ def main():
     samples = B * p["N"]
     value = samples / (ms_per_step * 1e-3) / 1e6
 
-    # forward only, batched
-    for _ in range(2):
-        op.forward(x, ws)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    nf = max(3, args.steps)
-    for _ in range(nf):
-        op.forward(x, ws)
-    torch.cuda.synchronize()
-    fwd_ms = (time.perf_counter() - t0) * 1e3 / nf
-
-    # plain single-signal forward (B = 1, eager)
-    x1 = x[:1].contiguous()
-    ws1 = op.new_workspace(1)
-    for _ in range(3):
-        op.forward(x1, ws1)
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(20):
+    fwd_ms = single_ms = None
+    ragged = None
+    if not args.no_extras:
+        # forward only, batched
+        for _ in range(2):
+            op.forward(x, ws)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        op.forward(x1, ws1)
+        nf = max(3, args.steps)
+        for _ in range(nf):
+            op.forward(x, ws)
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    single_ms = float(np.median(times)) * 1e3
+        fwd_ms = (time.perf_counter() - t0) * 1e3 / nf
+
+        # plain single-signal forward (B = 1, eager)
+        x1 = x[:1].contiguous()
+        ws1 = op.new_workspace(1)
+        for _ in range(3):
+            op.forward(x1, ws1)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(20):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            op.forward(x1, ws1)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        single_ms = float(np.median(times)) * 1e3
+
+        # ragged batch (bucketed to power-of-two pads, one graph per run): 256 harmonic
+        # tones of log-uniform lengths in [2^13, 2^16], fwd+bwd
+        ragged = ragged_batch(torch, dev)
 
     # rooflines from HIP-event times over the timed region: MFMA stages against
     # their algorithmic flops, FFT stages against their mandatory HBM bytes
@@ -241,7 +304,9 @@ def main():
     dom = max(stage_roofline, key=lambda k: stages[k][0])
     dom_ms, dom_n = stages[dom]
     roofline = dict(stage_roofline[dom])
-    roofline.update({"kernel": dom, "traffic": None, "launches_per_step": dom_n // args.steps,
+    traffic = measured_traffic(dom)
+    roofline.update({"kernel": dom, "traffic": traffic["bytes_per_launch"] if traffic else None,
+                     "traffic_detail": traffic, "launches_per_step": dom_n // args.steps,
                      "avg_launch_ms": round(dom_ms / max(dom_n, 1), 4),
                      "per_launch_algorithmic": (flops[dom] if dom in flops else nbytes[dom]) // max(dom_n // args.steps, 1)})
     if dom in flops:
@@ -255,12 +320,13 @@ def main():
         "config": {"workload": "JTFS fwd+bwd, 64 signals x 2^16 samples, J=12, Q=(16,1), J_fr=4, Q_fr=1, "
                                "T=2^11, F=2^3", "global_batch": B, "signal_length": p["N"],
                    "contraction": op.contraction},
-        "batched_fwd_msamples_s": round(samples / (fwd_ms * 1e-3) / 1e6, 3),
-        "plain_fwd_single_msamples_s": round(p["N"] / (single_ms * 1e-3) / 1e6, 3),
-        "plain_fwd_single_ms": round(single_ms, 3),
+        "batched_fwd_msamples_s": round(samples / (fwd_ms * 1e-3) / 1e6, 3) if fwd_ms else None,
+        "plain_fwd_single_msamples_s": round(p["N"] / (single_ms * 1e-3) / 1e6, 3) if single_ms else None,
+        "plain_fwd_single_ms": round(single_ms, 3) if single_ms else None,
         "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "roofline": roofline,
         "stage_roofline": stage_roofline,
+        "ragged_batch": ragged,
     }
     if cpu is not None:
         from tests._util import path_errors, rel_l2

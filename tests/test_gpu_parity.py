@@ -434,3 +434,46 @@ def test_texture_loop_matches_oracle():
     y2, _, _ = tex2.read()
     assert np.allclose(np.concatenate([h1, h2]), hist, rtol=1e-6, atol=0)
     assert rel_l2(y2.cpu().numpy(), y) <= 1e-6
+
+
+def test_cfg4_ragged_full_batch_sampled():
+    """The 256-signal ragged workload through the bucket graph: the shortest
+    signal of every pad length against the oracle on the zero-padded signal (two temporal rates of S2, every S1 path), and the
+    gradient of the shortest on its true samples."""
+    from paper_2204_08269_amd.jtfs import JTFSBucket
+    p = synth.PARAMS[4]
+    sigs = synth.cfg4_ragged(synth.BATCH[4])
+    lengths = [len(v) for v in sigs]
+    bk = JTFSBucket(lengths, p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"])
+    x = torch.from_numpy(np.concatenate(sigs)).cuda()
+    g = torch.from_numpy(np.random.default_rng(12).standard_normal(bk.s_offset[-1]).astype(np.float32)).cuda()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        s, gx = bk.run(x, g)
+    st.synchronize()
+    s, gx = s.cpu().numpy(), gx.cpu().numpy()
+    picks = {}
+    for j, n in enumerate(bk.pads):
+        if n not in picks or lengths[j] < lengths[picks[n]]:
+            picks[n] = j
+    assert sorted(picks) == [2 ** 14, 2 ** 15, 2 ** 16]          # the shortest length is above 2^13
+    for n, j in sorted(picks.items()):
+        prm = dict(p, N=n)
+        P = oracle_plan(prm)
+        xp = np.zeros(n)
+        xp[:lengths[j]] = sigs[j]
+        alphas = [P.n_alpha - 1, P.n_alpha // 2]
+        r1, r2 = O.jtfs(xp, P, alphas=alphas)
+        n1 = int(np.prod(P.s1_shape()))
+        got = s[bk.s_offset[j]:bk.s_offset[j + 1]]
+        check_paths(got[:n1].reshape(P.s1_shape()), got[n1:].reshape(P.s2_shape()), r1, r2, alphas=alphas)
+    j = picks[2 ** 14]
+    P = oracle_plan(dict(p, N=2 ** 14))
+    n1 = int(np.prod(P.s1_shape()))
+    gs = g.cpu().numpy()[bk.s_offset[j]:bk.s_offset[j + 1]].astype(np.float64)
+    xp = np.zeros(2 ** 14)
+    xp[:lengths[j]] = sigs[j]
+    ref = O.jtfs_vjp(xp, gs[:n1].reshape(P.s1_shape()), gs[n1:].reshape(P.s2_shape()), P)[:lengths[j]]
+    err = rel_l2(gx[bk.x_offset[j]:bk.x_offset[j + 1]], ref)
+    assert err <= TOL_VJP, f"gradient relative L2 {err:.3e}"
