@@ -17,6 +17,9 @@ constexpr double kSigma0 = 0.1;    // lowpass width: phi_T has sigma = kSigma0 /
 constexpr double kCEnv = 5.0;      // critical rate: decimated Nyquist >= kCEnv * sigma
 constexpr double kSupportTol = 1e-13;  // spectra below this (after normalisation) are not stored
 constexpr float kEpsMod = 1e-30f;  // modulus-gradient guard: z / max(|z|, eps)
+// The same guard on |z|^2 where the gradient takes rsqrt(|z|^2): the floor must
+// stay a normal FP32 number, so it acts at |z| = 1e-18 (z = 0 still gives 0).
+constexpr float kEpsMod2 = 1e-36f;
 
 constexpr int kTileL = 64;         // frequential GEMM: rows (l) per tile
 constexpr int kTileT = 64;         // frequential GEMM: columns (t) per tile

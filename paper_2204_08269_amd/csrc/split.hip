@@ -377,28 +377,26 @@ __device__ __forceinline__ void dma16(const uint4* src, uint4* lds_group) {
     __builtin_amdgcn_global_load_lds((glob_void_t*)src, (lds_void_t*)lds_group, 16, 0, 0);
 }
 
-// W chunk c (rows 32c..32c+31): LDS slot e = seg * 32 + r, seg = (2 kq + h) * 4 + p
+// W chunk c (rows 32c..32c+31): LDS slot e = seg * 32 + r, seg = (2 kq + h) * 4 + p.
+// Group g = wave + 4 j covers slots 64 g + lane: seg = 2 g + h, r = lane & 31, so a
+// lane's source is its row's base plus 8 j slots.
 __device__ __forceinline__ void stage_w(uint4* Ls, const uint4* Wsrc, int c, int nK, int nkb, int wave, int lane) {
-    const uint4* base = Wsrc + (int64_t)c * (nK * 256);
-    for (int g = wave; g < nK * 4; g += 4) {
-        const int e = g * 64 + lane, seg = e >> 5, r = e & 31;
-        dma16(base + r * (nkb * 4) + seg, Ls + g * 64);
-    }
+    const uint4* src = Wsrc + (int64_t)c * (nK * 256) + (lane & 31) * (nkb * 4) + 2 * wave + (lane >> 5);
+    uint4* dst = Ls + wave * 64;
+    for (int j = 0; j < nK; ++j) dma16(src + 8 * j, dst + 256 * j);
 }
 
-// W^T chunk c (KpT = 32 NI rows): LDS slot e = seg * 32 + i32, seg = q * 16 + (sp * 2 + h) * 4 + p
+// W^T chunk c (KpT = 32 NI rows): LDS slot e = seg * 32 + i32, seg = q * 16 + (sp * 2 + h) * 4 + p.
+// Group g = wave + 4 k: seg = 8 k + 2 wave + h, i.e. q = k >> 1 and the segment
+// inside q is 8 (k & 1) + 2 wave + h.
 template <int NI>
 __device__ __forceinline__ void stage_t(uint4* Ls, const uint4* Tsrc, int c, int wave, int lane) {
-    const uint4* base = Tsrc + (int64_t)c * (NI * 512);
+    const uint4* src = Tsrc + (int64_t)c * (NI * 512) + (lane & 31) * 16 + 2 * wave + (lane >> 5);
+    uint4* dst = Ls + wave * 64;
 #pragma unroll
-    for (int k = 0; k < 2 * NI; ++k) {
-        const int g = wave + 4 * k;
-        const int e = g * 64 + lane, seg = e >> 5, i32 = e & 31;
-        dma16(base + ((seg >> 4) * 32 + i32) * 16 + (seg & 15), Ls + g * 64);
-    }
+    for (int k = 0; k < 2 * NI; ++k) dma16(src + (k >> 1) * 512 + 8 * (k & 1), dst + 256 * k);
 }
 
-// One 32-row chunk: recompute, lowpass and modulus adjoints, W^T product.
 template <int NTB, int NI>
 __device__ __forceinline__ void bwd_chunk(int c, int nC, int nK, int nkb, int Mp, int wave, int lane, int h, int i32,
                                           const uint4* ycol, const uint4* phrow, const float* gvb, float inv_wy,
@@ -409,14 +407,18 @@ __device__ __forceinline__ void bwd_chunk(int c, int nC, int nK, int nkb, int Mp
     // ---- recompute Z for rows 32c.., columns tw0.. (four independent chains)
     const uint4* lw = Ls_W + h * 4 * 32 + i32;
     floatx16 rr = z16(), ri = z16(), ir = z16(), ii = z16();
+    // Y fragments two k-steps ahead
     uint4 ya0 = ycol[0], ya1 = ycol[1], ya2 = ycol[2], ya3 = ycol[3];
+    uint4 yb0 = ya0, yb1 = ya1, yb2 = ya2, yb3 = ya3;
+    if (nK > 1) { yb0 = ycol[8]; yb1 = ycol[9]; yb2 = ycol[10]; yb3 = ycol[11]; }
     for (int kq = 0; kq < nK; ++kq) {
         const uint4* wk = lw + kq * 8 * 32;
         const half8 w0 = as_h8(wk[0]), w1 = as_h8(wk[32]), w2 = as_h8(wk[64]), w3 = as_h8(wk[96]);
         const half8 y0 = as_h8(ya0), y1 = as_h8(ya1), y2 = as_h8(ya2), y3 = as_h8(ya3);
-        if (kq + 1 < nK) {
-            const uint4* yp = ycol + 8 * (kq + 1);
-            ya0 = yp[0]; ya1 = yp[1]; ya2 = yp[2]; ya3 = yp[3];
+        ya0 = yb0; ya1 = yb1; ya2 = yb2; ya3 = yb3;
+        if (kq + 2 < nK) {
+            const uint4* yp = ycol + 8 * (kq + 2);
+            yb0 = yp[0]; yb1 = yp[1]; yb2 = yp[2]; yb3 = yp[3];
         }
         rr = mfma16(w0, y0, rr); ri = mfma16(w0, y2, ri); ir = mfma16(w2, y0, ir); ii = mfma16(w2, y2, ii);
         rr = mfma16(w0, y1, rr); ri = mfma16(w0, y3, ri); ir = mfma16(w2, y1, ir); ii = mfma16(w2, y3, ii);
@@ -470,12 +472,11 @@ __device__ __forceinline__ void bwd_chunk(int c, int nC, int nK, int nkb, int Mp
             acc = mfma16(ah, bl, acc);
             acc = mfma16(al, bh, acc);
         }
-        // row crow(r, h) of the C tile carries that row's gV scale
+        // row crow(r, h) of the C tile carries that row's gV scale (a power of
+        // two: its reciprocal is exact)
+        const float isg = inv_phi / sg;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float s_row = __shfl(sg, crow(r, h));
-            acc[r] *= inv_phi / s_row;
-        }
+        for (int r = 0; r < 16; ++r) acc[r] *= __shfl(isg, crow(r, h));
         gu[spin] = acc;
     }
     // ---- modulus adjoint, P and Q' (FP32), split with the common scale
@@ -484,8 +485,10 @@ __device__ __forceinline__ void bwd_chunk(int c, int nC, int nK, int nkb, int Mp
     for (int r = 0; r < 16; ++r) {
         const float ur = (rr[r] - ii[r]) * inv_wy, ui = (ri[r] + ir[r]) * inv_wy;
         const float dr = (rr[r] + ii[r]) * inv_wy, di = (ri[r] - ir[r]) * inv_wy;
-        const float su = gu[0][r] / fmaxf(sqrtf(ur * ur + ui * ui), kEpsMod);
-        const float sd = gu[1][r] / fmaxf(sqrtf(dr * dr + di * di), kEpsMod);
+        // gU / |z| as gU * rsqrt(|z|^2), |z|^2 floored at a normal FP32 number
+        // (kEpsMod2); z = 0 gives 0 as with the plain guard
+        const float su = gu[0][r] * rsqrtf(fmaxf(ur * ur + ui * ui, kEpsMod2));
+        const float sd = gu[1][r] * rsqrtf(fmaxf(dr * dr + di * di, kEpsMod2));
         const float gur = su * ur, gui = su * ui, gdr = sd * dr, gdi = sd * di;
         const float vals[4] = {gur + gdr, gui + gdi, -(gdi - gui), gdr - gur};
 #pragma unroll
