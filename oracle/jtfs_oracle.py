@@ -15,6 +15,9 @@ It computes, in float64 and in the order the paper states them:
   (alpha, beta, theta) slice is |X *_{t,lambda} Psi| *_t phi_T on the lambda grid of
   its frequential wavelet
 * the reverse-mode gradient by Hermitian adjoints of each stage in reverse order (sec. 5)
+* time scattering (sec. 4, the Scattering1D comparison): the temporal wavelets
+  alone applied to the scalogram, S2 = |X_lambda * psi_alpha| *_t phi_T for every
+  (alpha, lambda) pair, no averaging along lambda
 * the mu-log renormalisation of the convnet input (sec. 4): per-path means mu
   over a set of signals and log(1 + S / (eps mu))
 * texture resynthesis (sec. 5): gradient descent on the normalised error
@@ -591,3 +594,48 @@ def texture_resynthesis(x, y0, P, iters, mu0, average_fr=True):
             mu *= BOLD_DOWN
         hist.append(E)
     return y, np.array(hist), mu
+
+
+# ---------------------------------------------------------------------------
+# Time scattering (sec. 4): the temporal filterbank alone on the scalogram
+# ---------------------------------------------------------------------------
+
+def scattering1d(x, P: Plan):
+    """S1 [n1, N/T] (as jtfs) and S2 [n_alpha, n1, N/T] with
+    S2[alpha, lambda] = (|X_lambda (*) psi_alpha| (*) phi_T) on the N/T frames."""
+    x = np.asarray(x, dtype=np.float64)
+    X = np.abs(first_order_linear(x, P))
+    S1 = time_lowpass(X, P, P.kX)
+    S2 = np.stack([time_lowpass(np.abs(second_order_linear(X, P, a)), P, P.kX + P.k2[a])
+                   for a in range(P.n_alpha)])
+    return S1, S2
+
+
+def scattering1d_vjp(x, gS1, gS2, P: Plan):
+    """Gradient of sum(gS1*S1) + sum(gS2*S2) of scattering1d by the stage adjoints."""
+    x = np.asarray(x, dtype=np.float64)
+    Y1d = first_order_linear(x, P)
+    X = np.abs(Y1d)
+    gX = time_lowpass_adj(np.asarray(gS1, np.float64), P, P.kX, P.NX)
+    for a in range(P.n_alpha):
+        Y2 = second_order_linear(X, P, a)
+        gU = time_lowpass_adj(np.asarray(gS2[a], np.float64), P, P.kX + P.k2[a], P.T_alpha(a))
+        gX += second_order_linear_adj(modulus_adj(gU, Y2), P, a)
+    return first_order_linear_adj(modulus_adj(gX, Y1d), P)
+
+
+def scattering1d_direct(x, P: Plan):
+    """scattering1d with every convolution as a direct sum (small N)."""
+    x = np.asarray(x, dtype=np.float64)
+    psi1 = dft_direct(P.psi1_hat, inverse=True)
+    X = np.abs(np.stack([_circ_direct(x[None, :].astype(complex), psi1[l], 1 << P.kX)[0]
+                         for l in range(P.n1)]))
+    phiX = dft_direct(gauss_lowpass_hat(P.NX, P.N, P.T), inverse=True)
+    S1 = _circ_direct(X.astype(complex), phiX, P.T >> P.kX).real
+    psi2 = dft_direct(P.psi2_hat, inverse=True)
+    S2 = []
+    for a in range(P.n_alpha):
+        U = np.abs(_circ_direct(X.astype(complex), psi2[a], 1 << P.k2[a]))
+        phiU = dft_direct(gauss_lowpass_hat(P.T_alpha(a), P.N, P.T), inverse=True)
+        S2.append(_circ_direct(U.astype(complex), phiU, P.T >> (P.kX + P.k2[a])).real)
+    return S1, np.stack(S2)

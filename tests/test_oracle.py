@@ -373,3 +373,46 @@ def test_texture_loop_bold_driver_rules(P1, x1):
     ups = int(np.sum(np.diff(hist) < 0))
     mu_start = 0.05 * np.linalg.norm(y0) / np.linalg.norm(g0)
     assert mu == pytest.approx(mu_start * O.BOLD_UP ** ups * O.BOLD_DOWN ** (12 - ups), rel=1e-12)
+
+
+# ------------------------------------------------------------ time scattering
+
+@pytest.mark.parametrize("p", SMALL)
+def test_scattering1d_matches_direct_sums(p):
+    P = O.Plan(p["N"], p["J"], p["Q"][0], p["Q"][1], p["J_fr"], p["Q_fr"], p["T"], p["F"])
+    x = np.random.default_rng(p["N"] + 9).standard_normal(p["N"])
+    a1, a2 = O.scattering1d(x, P)
+    b1, b2 = O.scattering1d_direct(x, P)
+    assert a2.shape == (P.n_alpha, P.n1, P.out_t)
+    assert np.max(np.abs(a1 - b1)) <= 1e-12 * np.max(np.abs(b1))
+    assert np.max(np.abs(a2 - b2)) <= 1e-12 * np.max(np.abs(b2))
+
+
+def test_scattering1d_closed_forms_and_relation_to_jtfs(P1, x1):
+    """A pure tone has no second order; a shift by T moves every frame by one; S1
+    is that of jtfs, and each S2 row is the time lowpass of the modulus of the
+    second-order row that jtfs passes to its frequential stage."""
+    m, A = 301, 0.7
+    n = np.arange(P1.N)
+    _, s2 = O.scattering1d(A * np.cos(2 * np.pi * m * n / P1.N + 0.3), P1)
+    assert np.max(np.abs(s2)) <= 1e-12
+    a1, a2 = O.scattering1d(x1, P1)
+    b1, b2 = O.scattering1d(np.roll(x1, P1.T), P1)
+    assert np.max(np.abs(np.roll(a2, 1, axis=-1) - b2)) <= 1e-12 * np.max(np.abs(a2))
+    j1, _, inter = O.jtfs(x1, P1, return_intermediates=True)
+    assert np.array_equal(j1, a1)
+    for a in range(P1.n_alpha):
+        ref = O.time_lowpass(np.abs(inter["Y2"][a]), P1, P1.kX + P1.k2[a])
+        assert np.allclose(a2[a], ref, rtol=0, atol=1e-14 * np.max(np.abs(ref)))
+
+
+def test_scattering1d_vjp_matches_finite_differences(P1, x1):
+    gS1, gS2 = synth.cotangents(P1.s1_shape(), (P1.n_alpha, P1.n1, P1.out_t), seed=23)
+    g = O.scattering1d_vjp(x1, gS1, gS2, P1)
+    f = lambda y: float(np.sum(gS1 * O.scattering1d(y, P1)[0]) + np.sum(gS2 * O.scattering1d(y, P1)[1]))
+    rng = np.random.default_rng(5)
+    for _ in range(2):
+        v = rng.standard_normal(P1.N)
+        h = 1e-6
+        fd = (f(x1 + h * v) - f(x1 - h * v)) / (2 * h)
+        assert abs(fd - g @ v) <= 1e-7 * abs(fd)
