@@ -67,8 +67,8 @@ typedef struct jtfs_plan jtfs_plan;
  * filterbanks; Q1 / Q2 wavelets per octave at first / second order; J_fr octaves
  * and Q_fr wavelets per octave of the frequential filterbank; lowpass supports T
  * (time, samples) and F (log-frequency, bins).  N, T, F are powers of two with
- * 16 <= N <= 2^24, T <= N, F <= L.  flags: 0 or JTFS_NO_FREQ_AVERAGE (any
- * other bit gives JTFS_EINVAL). */
+ * 16 <= N <= 2^24, T <= N, F <= L.  flags: 0, JTFS_NO_FREQ_AVERAGE or
+ * JTFS_TIME_SCATTERING (other bits, or both, give JTFS_EINVAL). */
 typedef struct {
     int64_t N;
     int32_t J, Q1, Q2, J_fr, Q_fr;
@@ -84,6 +84,13 @@ typedef struct {
  * + L_beta - 1, r(beta) = sum of L_beta' over beta' < beta.  S1 is unchanged. */
 #define JTFS_NO_FREQ_AVERAGE 1u
 
+/* Time scattering (sec. 4, the Scattering1D comparison): the temporal wavelets
+ * alone applied to the scalogram, no frequential stage:
+ *   S2[b][alpha][lambda1][tau] = (|X_lambda1 * psi_alpha| * phi_T)(tau T)
+ * for every (alpha, lambda1) pair, layout [B][n_alpha][n1][N/T]; S1 unchanged.
+ * Not combinable with JTFS_NO_FREQ_AVERAGE. */
+#define JTFS_TIME_SCATTERING 2u
+
 /* Derived sizes. */
 typedef struct {
     int32_t n1;        /* first-order wavelets (lambda rows of the scalogram)      */
@@ -97,8 +104,9 @@ typedef struct {
     int64_t out_l;     /* L / F log-frequency rows of S2                             */
     int64_t sum_T;     /* sum over alpha of the second-order lengths NX / 2^k2(alpha) */
     int64_t s1_per_signal;   /* n1 * out_t                                          */
-    int64_t s2_per_signal;   /* n_alpha * n_beta * 2 * out_l * out_t, or with
-                                JTFS_NO_FREQ_AVERAGE n_alpha * 2 * M_h * out_t       */
+    int64_t s2_per_signal;   /* n_alpha * n_beta * 2 * out_l * out_t; with
+                                JTFS_NO_FREQ_AVERAGE n_alpha * 2 * M_h * out_t; with
+                                JTFS_TIME_SCATTERING n_alpha * n1 * out_t            */
 } jtfs_info;
 
 /* Host-only queries (no GPU needed). */

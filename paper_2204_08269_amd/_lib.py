@@ -19,6 +19,7 @@ JTFS_EWORKSPACE = -4
 JTFS_ENOTSUP = -6
 JTFS_BWD_REUSE_FORWARD = 1
 JTFS_NO_FREQ_AVERAGE = 1
+JTFS_TIME_SCATTERING = 2
 JTFS_CONTRACTION_FP32 = 0
 JTFS_CONTRACTION_SPLIT_F16 = 1
 STAGES = ["input_fft", "scalogram", "s1", "second_order", "operand_split", "freq_fwd", "freq_lowpass",
@@ -113,9 +114,10 @@ def check(code: int):
     return code
 
 
-def params(N, J, Q, J_fr, Q_fr, T, F, average_fr=True) -> Params:
+def params(N, J, Q, J_fr, Q_fr, T, F, average_fr=True, time_scattering=False) -> Params:
+    flags = (0 if average_fr else JTFS_NO_FREQ_AVERAGE) | (JTFS_TIME_SCATTERING if time_scattering else 0)
     return Params(N=int(N), J=int(J), Q1=int(Q[0]), Q2=int(Q[1]), J_fr=int(J_fr), Q_fr=int(Q_fr),
-                  flags=0 if average_fr else JTFS_NO_FREQ_AVERAGE, T=int(T), F=int(F))
+                  flags=flags, T=int(T), F=int(F))
 
 
 def query(p: Params) -> Info:

@@ -436,9 +436,69 @@ __global__ void __launch_bounds__(256) k_v_out(const float* __restrict__ Vp, int
     }
 }
 
+// Time scattering (sec. 4): S2[b][alpha][lambda][tau] = sum_t |Y2[b][alpha][lambda][t]| Phi_alpha[t][tau]
+// (modulus of the second-order row, then the time lowpass on the N/T frames).
+// Threads are (tau, t-group) pairs; |Y2| of 256 samples at a time goes through LDS.
+__global__ void __launch_bounds__(256) k_ts_out(const float2* __restrict__ Y, int64_t y_bstride, int Tp, int Ta,
+                                                const float* __restrict__ Phi, int NTp, int NT, int alpha,
+                                                int n_alpha, float* __restrict__ S2) {
+    __shared__ float mag[256];
+    __shared__ float part[256];
+    const int lam = blockIdx.x, n1 = gridDim.x;
+    const int64_t b = blockIdx.y;
+    const float2* row = Y + b * y_bstride + (int64_t)lam * Tp;
+    const int tau = threadIdx.x % NTp, g = threadIdx.x / NTp, G = blockDim.x / NTp;
+    float acc = 0.f;
+    for (int t0 = 0; t0 < Ta; t0 += 256) {
+        __syncthreads();
+        const int t = t0 + threadIdx.x;
+        if (t < Ta) {
+            const float2 y = row[t];
+            mag[threadIdx.x] = sqrtf(y.x * y.x + y.y * y.y);
+        }
+        __syncthreads();
+        const int n = min(256, Ta - t0);
+        for (int j = g; j < n; j += G) acc += mag[j] * Phi[(int64_t)(t0 + j) * NTp + tau];
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (g == 0 && tau < NT) {
+        float s = 0.f;
+        for (int q = 0; q < G; ++q) s += part[q * NTp + tau];
+        S2[((b * n_alpha + alpha) * n1 + lam) * (int64_t)NT + tau] = s;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Backward.
 // ---------------------------------------------------------------------------
+
+// Time scattering adjoint: gY2[t] = (sum_tau gS2[tau] Phi_alpha[t][tau]) y_t / max(|y_t|, eps)
+// for t < Ta, zero for Ta <= t < Tp (rows lambda < n1).
+__global__ void __launch_bounds__(256) k_ts_bwd(const float2* __restrict__ Y, int64_t y_bstride, int Tp, int Ta,
+                                                const float* __restrict__ Phi, int NTp, int NT, int alpha,
+                                                int n_alpha, const float* __restrict__ gS2, float2* __restrict__ gY) {
+    __shared__ float gs[128];
+    const int lam = blockIdx.x, n1 = gridDim.x;
+    const int64_t b = blockIdx.y;
+    const float* src = gS2 ? gS2 + ((b * n_alpha + alpha) * n1 + lam) * (int64_t)NT : nullptr;
+    for (int i = threadIdx.x; i < NTp; i += blockDim.x) gs[i] = (src && i < NT) ? src[i] : 0.f;
+    __syncthreads();
+    const float2* row = Y + b * y_bstride + (int64_t)lam * Tp;
+    float2* out = gY + b * y_bstride + (int64_t)lam * Tp;
+    for (int t = threadIdx.x; t < Tp; t += blockDim.x) {
+        float2 r = make_float2(0.f, 0.f);
+        if (t < Ta) {
+            const float* ph = Phi + (int64_t)t * NTp;
+            float gu = 0.f;
+            for (int tau = 0; tau < NT; ++tau) gu += gs[tau] * ph[tau];
+            const float2 y = row[t];
+            const float sc = gu / fmaxf(sqrtf(y.x * y.x + y.y * y.y), kEpsMod);
+            r = make_float2(y.x * sc, y.y * sc);
+        }
+        out[t] = r;
+    }
+}
 
 // gV[b][alpha][theta][rowoff+l][tau] = sum_m PF_beta[m][l] gS2[b][alpha][beta][theta][m][tau]
 // (adjoint of the frequency lowpass), or with avg = 0 (eq. (4)) the gS2 row
@@ -911,7 +971,13 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
     float2* Y2 = (float2*)(base + w.Y2);
     float* Vp = (float*)(base + w.Vp);
     const int nlt = s.Mp / kTileL;
-    const bool split = P->contraction == JTFS_CONTRACTION_SPLIT_F16;
+    for (int a = 0; a < s.n_alpha && s.tscat; ++a) {
+        JTFS_TIMED(JTFS_STAGE_FREQ_FWD, st, hipLaunchKernelGGL(k_ts_out, dim3(s.n1, (unsigned)B), dim3(256), 0, st, Y2 + s.yoff[a],
+                           (int64_t)s.Kp * s.sumTp, s.Tp[a], s.Ta[a], P->Phi + s.phioff[a], s.NTp, s.NT, a,
+                           s.n_alpha, s2));
+        LAUNCHCHK("time-scattering lowpass");
+    }
+    const bool split = P->contraction == JTFS_CONTRACTION_SPLIT_F16 && !s.tscat;
     for (int a = 0; a < s.n_alpha && split; ++a) {
         unsigned short* Yh = (unsigned short*)(base + w.Yh);
         float* ysc = (float*)(base + w.yscale);
@@ -929,7 +995,7 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
         }
         LAUNCHCHK("frequency lowpass");
     }
-    for (int a = 0; a < s.n_alpha && !split; ++a) {
+    for (int a = 0; a < s.n_alpha && !split && !s.tscat; ++a) {
         dim3 grid(nlt, s.nch[a], (unsigned)B);
         const int slot0 = (int)s.vchoff[a] * 2;
         const float2* Ya = Y2 + s.yoff[a];
@@ -957,6 +1023,24 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
     return JTFS_OK;
 }
 
+// forward FFT of every gY2 row of alpha (length T_alpha, rows lambda < n1), in place
+static int gy2_row_fft(const jtfs_plan* P, int a, float2* gY2, int64_t yb, int64_t B, hipStream_t st) {
+    const Shapes& s = P->s;
+    const int logTa = s.logNX - s.k2[a];
+    const int logC = logTa >= 12 ? 0 : 12 - logTa;
+    const size_t lds = (size_t)(1 << logC) * (s.Ta[a] + 1) * sizeof(float2);
+    if (logTa >= kRegMinLog) {
+        JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st,
+                   launch_rowfft_r(P, gY2 + s.yoff[a], yb, (int64_t)s.Tp[a], s.n1, logTa, B, st));
+    } else {
+        JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st, hipLaunchKernelGGL((k_fft_cols), dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
+                       st, gY2 + s.yoff[a], gY2 + s.yoff[a], logTa, s.n1, logC, yb, (int64_t)s.Tp[a], (int64_t)1,
+                       yb, (int64_t)s.Tp[a], (int64_t)1, 0, P->tw, P->tw_log, 0, 1.0f));
+    }
+    LAUNCHCHK("second-order adjoint FFT");
+    return JTFS_OK;
+}
+
 extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs1, const float* gs2, float* gx,
                              int64_t B, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t st) {
     int rc = check_common(P, B, ws, ws_bytes);
@@ -980,13 +1064,22 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     float2* gxh = (float2*)(base + w.gxh);
     const int64_t yb = (int64_t)s.Kp * s.sumTp;
     const int nlt = s.Mp / kTileL;
-    for (int a = 0; a < s.n_alpha; ++a) {
+    // time scattering: the lowpass and modulus adjoints give gY2 directly
+    for (int a = 0; a < s.n_alpha && s.tscat; ++a) {
+        JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_ts_bwd, dim3(s.n1, (unsigned)B), dim3(256), 0, st, Y2 + s.yoff[a],
+                           yb, s.Tp[a], s.Ta[a], P->Phi + s.phioff[a], s.NTp, s.NT, a, s.n_alpha, gs2,
+                           gY2 + s.yoff[a]));
+        LAUNCHCHK("time-scattering adjoint");
+        rc = gy2_row_fft(P, a, gY2, yb, B, st);
+        if (rc != JTFS_OK) return rc;
+    }
+    for (int a = 0; a < s.n_alpha && !s.tscat; ++a) {
         JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_s2_bwd, dim3(s.n_beta + 1, 2, (unsigned)B), dim3(256), 0, st, gs2, P->PF, P->d_pfoff, P->d_Lb,
                            P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, a, s.n_alpha, (int)s.avg_fr, gV,
                            (float*)(base + w.gvmax)));
         LAUNCHCHK("frequency lowpass adjoint");
     }
-    const bool split = P->contraction == JTFS_CONTRACTION_SPLIT_F16 && P->split_bwd_ok;
+    const bool split = P->contraction == JTFS_CONTRACTION_SPLIT_F16 && P->split_bwd_ok && !s.tscat;
     unsigned short* Yh = (unsigned short*)(base + w.Yh);
     float* ysc = (float*)(base + w.yscale);
     if (split && !(flags & JTFS_BWD_REUSE_FORWARD)) {
@@ -1000,20 +1093,10 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
         JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,
                    rc = launch_freq_bwd_split(P, a, Yh, ysc, gV, (const float*)(base + w.gvmax), gY2, B, st));
         if (rc != JTFS_OK) { if (rc == JTFS_EHIP) set_error("split backward contraction launch failed"); return rc; }
-        const int logTa = s.logNX - s.k2[a];
-        const int logC = logTa >= 12 ? 0 : 12 - logTa;
-        const size_t lds = (size_t)(1 << logC) * (s.Ta[a] + 1) * sizeof(float2);
-        if (logTa >= kRegMinLog) {
-            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st,
-                       launch_rowfft_r(P, gY2 + s.yoff[a], yb, (int64_t)s.Tp[a], s.n1, logTa, B, st));
-        } else {
-            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st, hipLaunchKernelGGL((k_fft_cols), dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
-                           st, gY2 + s.yoff[a], gY2 + s.yoff[a], logTa, s.n1, logC, yb, (int64_t)s.Tp[a], (int64_t)1,
-                           yb, (int64_t)s.Tp[a], (int64_t)1, 0, P->tw, P->tw_log, 0, 1.0f));
-        }
-        LAUNCHCHK("second-order adjoint FFT");
+        rc = gy2_row_fft(P, a, gY2, yb, B, st);
+        if (rc != JTFS_OK) return rc;
     }
-    for (int a = 0; a < s.n_alpha && !split; ++a) {
+    for (int a = 0; a < s.n_alpha && !split && !s.tscat; ++a) {
         dim3 grid(nlt, s.Tp[a] / kTileT, (unsigned)B);
         const float2* Ya = Y2 + s.yoff[a];
         const float* Ph = P->Phi + s.phioff[a];
@@ -1032,19 +1115,8 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
         JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_WH, st, hipLaunchKernelGGL(k_bwd_gy, dim3((s.Kp + 63) / 64, s.Tp[a] / kTileT, (unsigned)B), dim3(256), 0, st, PQ,
                            s.Tp[a], P->Wl, s.Mp, s.Kp, gY2 + s.yoff[a], yb));
         LAUNCHCHK("contraction adjoint (W^H)");
-        // forward FFT of every gY2 row of alpha (length Ta, rows lambda < n1), in place
-        const int logTa = s.logNX - s.k2[a];
-        const int logC = logTa >= 12 ? 0 : 12 - logTa;
-        const size_t lds = (size_t)(1 << logC) * (s.Ta[a] + 1) * sizeof(float2);
-        if (logTa >= kRegMinLog) {
-            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st,
-                       launch_rowfft_r(P, gY2 + s.yoff[a], yb, (int64_t)s.Tp[a], s.n1, logTa, B, st));
-        } else {
-            JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st, hipLaunchKernelGGL((k_fft_cols), dim3((unsigned)((s.n1 + (1 << logC) - 1) >> logC), (unsigned)B), dim3(1024), lds,
-                           st, gY2 + s.yoff[a], gY2 + s.yoff[a], logTa, s.n1, logC, yb, (int64_t)s.Tp[a], (int64_t)1,
-                           yb, (int64_t)s.Tp[a], (int64_t)1, 0, P->tw, P->tw_log, 0, 1.0f));
-        }
-        LAUNCHCHK("second-order adjoint FFT");
+        rc = gy2_row_fft(P, a, gY2, yb, B, st);
+        if (rc != JTFS_OK) return rc;
     }
     const int logNT = s.logN - s.logT;
     const size_t lds_a = sizeof(float2) * (s.NX / 2 + 1 + s.NT);

@@ -80,8 +80,11 @@ int solve_shapes(const jtfs_params& p, Shapes* s) {
     if (!pow2(p.N) || !pow2(p.T) || !pow2(p.F)) { set_error("N, T and F must be powers of two"); return JTFS_EINVAL; }
     if (p.N < 16 || p.N > (int64_t(1) << 24)) { set_error("N must lie in [2^4, 2^24]"); return JTFS_EINVAL; }
     if (p.T > p.N) { set_error("T must not exceed N"); return JTFS_EINVAL; }
-    if (p.flags & ~JTFS_NO_FREQ_AVERAGE) { set_error("unknown flag bits"); return JTFS_EINVAL; }
+    if (p.flags & ~(JTFS_NO_FREQ_AVERAGE | JTFS_TIME_SCATTERING)) { set_error("unknown flag bits"); return JTFS_EINVAL; }
+    if ((p.flags & JTFS_NO_FREQ_AVERAGE) && (p.flags & JTFS_TIME_SCATTERING)) {
+        set_error("JTFS_NO_FREQ_AVERAGE and JTFS_TIME_SCATTERING exclude each other"); return JTFS_EINVAL; }
     s->avg_fr = !(p.flags & JTFS_NO_FREQ_AVERAGE);
+    s->tscat = (p.flags & JTFS_TIME_SCATTERING) != 0;
     if (p.Q1 < 1 || p.Q2 < 1 || p.Q_fr < 1 || p.Q1 > 64 || p.Q2 > 64 || p.Q_fr > 64) {
         set_error("Q1, Q2 and Q_fr must lie in [1, 64]"); return JTFS_EINVAL; }
     s->N = p.N; s->T = p.T; s->F = p.F;
@@ -214,8 +217,9 @@ int jtfs_query(const jtfs_params* p, jtfs_info* out) {
     out->n1 = s.n1; out->n_alpha = s.n_alpha; out->n_beta = s.n_beta; out->L = s.L; out->kX = s.kX;
     out->M_h = s.Mh; out->NX = s.NX; out->out_t = s.NT; out->out_l = s.NL; out->sum_T = s.sumT;
     out->s1_per_signal = (int64_t)s.n1 * s.NT;
-    out->s2_per_signal = s.avg_fr ? (int64_t)s.n_alpha * s.n_beta * 2 * s.NL * s.NT
-                                  : (int64_t)s.n_alpha * 2 * s.Mh * s.NT;
+    out->s2_per_signal = s.tscat    ? (int64_t)s.n_alpha * s.n1 * s.NT
+                         : s.avg_fr ? (int64_t)s.n_alpha * s.n_beta * 2 * s.NL * s.NT
+                                    : (int64_t)s.n_alpha * 2 * s.Mh * s.NT;
     return st;
 }
 

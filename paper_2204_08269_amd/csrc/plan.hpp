@@ -48,6 +48,7 @@ struct Shapes {
     int n1 = 0, kX = 0, logNX = 0, n_alpha = 0, n_beta = 0, L = 0, logL = 0;
     int64_t N = 0, NX = 0, T = 0, F = 0;
     bool avg_fr = true;              // eq. (3); false: eq. (4), no frequency lowpass
+    bool tscat = false;              // time scattering: no frequential stage
     int NT = 0, NTp = 0, NL = 0;     // N/T, padded to 32, L/F
     int Kp = 0;                      // n1 padded to kKStep
     int Mh = 0, Mp = 0;              // frequential rows per spin, padded to kTileL

@@ -24,17 +24,20 @@ class JTFS:
     theta = -1), eq. (3).  With average_fr=False, the eq. (4) variant without
     frequential averaging: S2 [B, n_alpha, 2 M_h, N/T], the (beta, theta) slices
     of L/2^kfr(beta) rows packed beta-major (s2_rows gives a slice's rows).
+    With time_scattering=True, the time-scattering variant of sec. 4 instead (no
+    frequential stage): S2 [B, n_alpha, n1, N/T].
     contraction: "split16" (FP16 matrix cores with split operands, the default
     where available) or "fp32" (FP32 matrix cores).  Calling the object is
     differentiable through torch.autograd; forward() and vjp() call the library
     directly."""
 
-    def __init__(self, N, J, Q, J_fr, Q_fr, T, F, contraction=None, average_fr=True):
+    def __init__(self, N, J, Q, J_fr, Q_fr, T, F, contraction=None, average_fr=True, time_scattering=False):
         if not torch.cuda.is_available():
             raise RuntimeError("JTFS needs a ROCm GPU (no CPU fallback)")
         self.lib = _lib.load()
         self.average_fr = bool(average_fr)
-        self.params = _lib.params(N, J, Q, J_fr, Q_fr, T, F, average_fr)
+        self.time_scattering = bool(time_scattering)
+        self.params = _lib.params(N, J, Q, J_fr, Q_fr, T, F, average_fr, time_scattering)
         self.device = torch.device("cuda", torch.cuda.current_device())
         plan = ctypes.c_void_p()
         _lib.check(self.lib.jtfs_plan_create_ex(ctypes.byref(plan), ctypes.byref(self.params)))
@@ -50,7 +53,9 @@ class JTFS:
         self.contraction = "split16" if m.value == _lib.JTFS_CONTRACTION_SPLIT_F16 else "fp32"
         self.N = int(N)
         self.s1_shape = (info.n1, info.out_t)
-        if self.average_fr:
+        if self.time_scattering:
+            self.s2_shape = (info.n_alpha, info.n1, info.out_t)
+        elif self.average_fr:
             self.s2_shape = (info.n_alpha, info.n_beta, 2, info.out_l, info.out_t)
         else:
             self.s2_shape = (info.n_alpha, 2 * info.M_h, info.out_t)

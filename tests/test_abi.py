@@ -56,6 +56,8 @@ def test_host_plan_matches_oracle(L, cfg):
     info4 = L.query(L.params(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"], average_fr=False))
     assert info4.s2_per_signal == int(np.prod(P.s2_shape(False)))      # eq. (4) packing
     assert info4.s1_per_signal == info.s1_per_signal and info4.M_h == info.M_h
+    infot = L.query(L.params(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"], time_scattering=True))
+    assert infot.s2_per_signal == P.n_alpha * P.n1 * P.out_t            # time scattering
     for fam, (xi, sg, ks) in enumerate([(P.xi1, P.sigma1, [P.kX] * P.n1), (P.xi2, P.sigma2, P.k2),
                                         (P.xi_fr, P.sigma_fr, P.k_fr)]):
         hx, hs, hk = L.query_filters(prm, fam)
@@ -90,9 +92,10 @@ def test_invalid_parameters_rejected_before_any_hip_call(L, p):
 def test_unknown_flag_bits_rejected(L):
     p = synth.PARAMS[1]
     prm = L.params(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"])
-    prm.flags = 2
     info = L.Info()
-    assert L.load().jtfs_query(ctypes.byref(prm), ctypes.byref(info)) == L.JTFS_EINVAL
+    for bad in (4, 3):                      # an unknown bit; both variants at once
+        prm.flags = bad
+        assert L.load().jtfs_query(ctypes.byref(prm), ctypes.byref(info)) == L.JTFS_EINVAL
     assert ctypes.sizeof(L.Params) == 48
 
 

@@ -15,10 +15,10 @@ TOL_VJP = 1e-4      # relative L2 of the gradient against the FP64 oracle's VJP
 TOL_FD = 1e-3       # gradient against FP64 central finite differences
 
 
-def gpu_op(p, contraction=None, average_fr=True):
+def gpu_op(p, contraction=None, average_fr=True, time_scattering=False):
     from paper_2204_08269_amd.jtfs import JTFS
     return JTFS(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"], contraction=contraction,
-                average_fr=average_fr)
+                average_fr=average_fr, time_scattering=time_scattering)
 
 
 MODES = ["fp32", "split16"]
@@ -477,3 +477,26 @@ def test_cfg4_ragged_full_batch_sampled():
     ref = O.jtfs_vjp(xp, gs[:n1].reshape(P.s1_shape()), gs[n1:].reshape(P.s2_shape()), P)[:lengths[j]]
     err = rel_l2(gx[bk.x_offset[j]:bk.x_offset[j + 1]], ref)
     assert err <= TOL_VJP, f"gradient relative L2 {err:.3e}"
+
+
+@pytest.mark.parametrize("p", [P1, RAGGED[3], LONG])
+def test_time_scattering_forward_and_vjp(p):
+    """Time scattering (sec. 4): S1 and |X * psi_alpha| * phi_T per (alpha, lambda)
+    path against the oracle, and the gradient."""
+    P = oracle_plan(p)
+    rng = np.random.default_rng(808 + p["N"])
+    x = (rng.standard_normal((2, p["N"])) * 0.5).astype(np.float32)
+    op = gpu_op(p, time_scattering=True)
+    assert op.s2_shape == (P.n_alpha, P.n1, P.out_t)
+    g1, g2 = run_forward(op, x)
+    gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2, P.n_alpha, P.n1, P.out_t), seed=29)
+    g = op.vjp(torch.from_numpy(x).cuda(), torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda()).cpu().numpy()
+    for b in range(2):
+        xb = x[b].astype(np.float64)
+        r1, r2 = O.scattering1d(xb, P)
+        e1, _ = path_errors(g1[b], r1, 1)
+        e2, _ = path_errors(g2[b], r2, 2)
+        assert e1.max() <= TOL and e2.max() <= TOL, (e1.max(), e2.max())
+        ref = O.scattering1d_vjp(xb, gs1[b].astype(np.float64), gs2[b].astype(np.float64), P)
+        err = rel_l2(g[b], ref)
+        assert err <= TOL_VJP, f"signal {b}: gradient relative L2 {err:.3e}"
