@@ -185,6 +185,8 @@ def main():
                     help="frequential contraction arithmetic (default: the plan's, split16 where available)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device copy first (calibrates HBM byte counters)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the plan's default launch choices (no autotuning before the timed steps)")
     ap.add_argument("--no-extras", action="store_true",
                     help="time the fwd+bwd step only (no forward-only or ragged-batch legs)")
     args = ap.parse_args()
@@ -219,10 +221,16 @@ def main():
         torch.cuda.synchronize()
         del a, b
     op = JTFS(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"], contraction=args.contraction)
-    split = op.contraction == "split16"
     x = torch.from_numpy(x_np).to(dev)
     gs1 = torch.from_numpy(gs1_np).to(dev)
     gs2 = torch.from_numpy(gs2_np).to(dev)
+    tuning = None
+    if not args.no_autotune and args.contraction is None:
+        tuning = op.autotune(B, x, reps=2)      # launch choices for this GPU and batch (before the workspace)
+        torch.cuda.synchronize()
+        print(f"[bench] autotune: {tuning['contraction']}, register rows {tuning['register_rows']}, "
+              f"{tuning['step_ms']:.2f} ms/step", file=sys.stderr, flush=True)
+    split = op.contraction == "split16"
     ws = op.new_workspace(B)
 
     def step():
@@ -323,6 +331,7 @@ def main():
         "batched_fwd_msamples_s": round(samples / (fwd_ms * 1e-3) / 1e6, 3) if fwd_ms else None,
         "plain_fwd_single_msamples_s": round(p["N"] / (single_ms * 1e-3) / 1e6, 3) if single_ms else None,
         "plain_fwd_single_ms": round(single_ms, 3) if single_ms else None,
+        "tuning": tuning,
         "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "roofline": roofline,
         "stage_roofline": stage_roofline,

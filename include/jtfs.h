@@ -237,6 +237,33 @@ int jtfs_texture_iterate(jtfs_texture* tex, int iters, float* hist, int hist_cap
 int jtfs_texture_read(const jtfs_texture* tex, float* y, float* err, float* mu, hipStream_t stream);
 void jtfs_texture_destroy(jtfs_texture* tex);
 
+/* Launch choices and their autotuning.  reg_rows is a bit mask over the four
+ * stages that have both a register-resident and an in-LDS transform for rows of
+ * 2^14 points (longer rows always use the register-resident one, shorter rows the
+ * in-LDS one).  jtfs_plan_autotune runs, for B signals x (device, [B][N]; NULL:
+ * zeros), one untimed and `reps` timed fwd+bwd steps per candidate: each
+ * available contraction mode, with all four stages register-resident and with
+ * all four in LDS.  It keeps the contraction whose own stages took least time
+ * and, per stage, the faster transform, then times the result (step_ms).  It
+ * allocates its buffers itself (the largest workspace over the modes plus
+ * coefficients and gradient for B signals), synchronises the stream, uses the
+ * per-stage timers (JTFS_EINVAL if timing is enabled) and leaves their records
+ * cleared.  candidates_ms: fwd+bwd per step of (split, register), (split, LDS),
+ * (FP32, register), (FP32, LDS); 0 for candidates not run. */
+#define JTFS_REG_SCALOGRAM    1
+#define JTFS_REG_SECOND_ORDER 2
+#define JTFS_REG_ROW_FFT      4
+#define JTFS_REG_FIRST_ADJ    8
+typedef struct {
+    int32_t contraction;
+    int32_t reg_rows;
+    double step_ms;
+    double candidates_ms[4];
+} jtfs_tuning;
+int jtfs_plan_autotune(jtfs_plan* plan, const float* x, int64_t B, int reps, hipStream_t stream, jtfs_tuning* out);
+int jtfs_plan_set_tuning(jtfs_plan* plan, int contraction, int reg_rows);
+int jtfs_plan_get_tuning(const jtfs_plan* plan, int* contraction, int* reg_rows);
+
 /* Per-stage kernel timing (tracing).  While enabled, every launch of each stage
  * below is bracketed by a pair of HIP events recorded on the launch's stream.
  * jtfs_timing_read waits for the recorded events of one stage, returns their

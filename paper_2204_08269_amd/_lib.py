@@ -27,6 +27,11 @@ STAGES = ["input_fft", "scalogram", "s1", "second_order", "operand_split", "freq
           "output_fft"]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("contraction", ctypes.c_int32), ("reg_rows", ctypes.c_int32), ("step_ms", ctypes.c_double),
+                ("candidates_ms", ctypes.c_double * 4)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("J", ctypes.c_int32), ("Q1", ctypes.c_int32), ("Q2", ctypes.c_int32),
                 ("J_fr", ctypes.c_int32), ("Q_fr", ctypes.c_int32), ("flags", ctypes.c_uint32),
@@ -45,7 +50,8 @@ EXPORTS = ["jtfs_query", "jtfs_query_filters", "jtfs_plan_create", "jtfs_plan_cr
            "jtfs_plan_set_contraction", "jtfs_plan_get_contraction", "jtfs_bucket_create", "jtfs_bucket_offsets",
            "jtfs_bucket_run", "jtfs_bucket_destroy", "jtfs_path_means", "jtfs_mulog", "jtfs_mulog_backward",
            "jtfs_texture_create", "jtfs_texture_set_target", "jtfs_texture_set_start", "jtfs_texture_iterate",
-           "jtfs_texture_read", "jtfs_texture_destroy",
+           "jtfs_texture_read", "jtfs_texture_destroy", "jtfs_plan_autotune", "jtfs_plan_set_tuning",
+           "jtfs_plan_get_tuning",
            "jtfs_timing_enable", "jtfs_timing_read", "jtfs_last_error"]
 
 _lib = None
@@ -90,6 +96,9 @@ def load(path: str = LIB_PATH):
     L.jtfs_path_means.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     L.jtfs_mulog.argtypes = [vp, vp, vp, i64, vp, vp, ctypes.c_float, vp, vp, vp]
     L.jtfs_mulog_backward.argtypes = [vp, vp, vp, i64, vp, vp, ctypes.c_float, vp, vp, vp, vp, vp]
+    L.jtfs_plan_autotune.argtypes = [vp, vp, i64, ctypes.c_int, vp, P(Tuning)]
+    L.jtfs_plan_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.jtfs_plan_get_tuning.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int)]
     L.jtfs_texture_create.argtypes = [P(vp), vp, i64, ctypes.c_float]
     L.jtfs_texture_set_target.argtypes = [vp, vp, vp]
     L.jtfs_texture_set_start.argtypes = [vp, vp, vp]

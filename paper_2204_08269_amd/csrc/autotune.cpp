@@ -1,0 +1,194 @@
+// Autotuning of a plan's launch choices on the caller's GPU and batch size.
+//
+// Candidates: the contraction arithmetic (split FP16 or FP32 matrix cores) and,
+// for rows of 2^14 points, the register-resident or the in-LDS transform in each
+// of the four stages that have both (scalogram, second order, gY2 row FFTs,
+// first-order adjoint).  Every candidate runs whole fwd+bwd steps; the per-stage
+// HIP-event timers attribute the time, so the four row choices are settled from
+// two runs per contraction mode (all register-resident, all in LDS) rather than
+// from sixteen.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace jtfs {
+bool timing_on();
+}
+using namespace jtfs;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    bool alloc(size_t n) { return hipMalloc(&p, std::max<size_t>(n, 256)) == hipSuccess; }
+};
+
+void set_rows(jtfs_plan* P, int mask) {
+    P->tune.reg_scalogram = (mask & JTFS_REG_SCALOGRAM) != 0;
+    P->tune.reg_second = (mask & JTFS_REG_SECOND_ORDER) != 0;
+    P->tune.reg_rowfft = (mask & JTFS_REG_ROW_FFT) != 0;
+    P->tune.reg_first_adj = (mask & JTFS_REG_FIRST_ADJ) != 0;
+}
+
+int get_rows(const jtfs_plan* P) {
+    return (P->tune.reg_scalogram ? JTFS_REG_SCALOGRAM : 0) | (P->tune.reg_second ? JTFS_REG_SECOND_ORDER : 0) |
+           (P->tune.reg_rowfft ? JTFS_REG_ROW_FFT : 0) | (P->tune.reg_first_adj ? JTFS_REG_FIRST_ADJ : 0);
+}
+
+// reps timed fwd+bwd steps after one untimed one: total ms per step and ms per stage per step
+int run_steps(jtfs_plan* P, const float* x, int64_t B, float* s1, float* s2, float* gx, void* ws, size_t wsb,
+              int reps, hipStream_t st, double* step_ms, double* stage_ms) {
+    auto step = [&]() -> int {
+        int rc = jtfs_forward(P, x, B, s1, s2, ws, wsb, st);
+        if (rc != JTFS_OK) return rc;
+        return jtfs_backward(P, x, s1, s2, gx, B, ws, wsb, JTFS_BWD_REUSE_FORWARD, st);
+    };
+    int rc = step();
+    if (rc != JTFS_OK) return rc;
+    if (hipStreamSynchronize(st) != hipSuccess) { set_error("autotune: stream synchronisation failed"); return JTFS_EHIP; }
+    double ms = 0.0;
+    int64_t n = 0;
+    for (int k = 0; k < JTFS_NUM_STAGES; ++k) jtfs_timing_read(k, &ms, &n);       // clear
+    jtfs_timing_enable(1);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        jtfs_timing_enable(0);
+        set_error("autotune: event creation failed");
+        return JTFS_EHIP;
+    }
+    (void)hipEventRecord(a, st);
+    for (int r = 0; r < reps && rc == JTFS_OK; ++r) rc = step();
+    (void)hipEventRecord(b, st);
+    const hipError_t es = hipEventSynchronize(b);
+    jtfs_timing_enable(0);
+    float total = 0.f;
+    if (rc == JTFS_OK && es == hipSuccess) (void)hipEventElapsedTime(&total, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc != JTFS_OK) return rc;
+    if (es != hipSuccess) { set_error("autotune: event synchronisation failed"); return JTFS_EHIP; }
+    *step_ms = total / reps;
+    for (int k = 0; k < JTFS_NUM_STAGES; ++k) {
+        jtfs_timing_read(k, &ms, &n);
+        stage_ms[k] = ms / reps;
+    }
+    return JTFS_OK;
+}
+
+}  // namespace
+
+extern "C" int jtfs_plan_set_tuning(jtfs_plan* P, int contraction, int reg_rows) {
+    if (!P) { set_error("null plan"); return JTFS_EINVAL; }
+    if (reg_rows & ~(JTFS_REG_SCALOGRAM | JTFS_REG_SECOND_ORDER | JTFS_REG_ROW_FFT | JTFS_REG_FIRST_ADJ)) {
+        set_error("unknown row-kernel bits"); return JTFS_EINVAL; }
+    const int rc = jtfs_plan_set_contraction(P, contraction);
+    if (rc != JTFS_OK) return rc;
+    set_rows(P, reg_rows);
+    return JTFS_OK;
+}
+
+extern "C" int jtfs_plan_get_tuning(const jtfs_plan* P, int* contraction, int* reg_rows) {
+    if (!P || !contraction || !reg_rows) { set_error("null pointer"); return JTFS_EINVAL; }
+    *contraction = P->contraction;
+    *reg_rows = get_rows(P);
+    return JTFS_OK;
+}
+
+extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int reps, hipStream_t st,
+                                  jtfs_tuning* out) {
+    if (!P || !out) { set_error("null pointer"); return JTFS_EINVAL; }
+    if (B < 1 || B > 65535 || reps < 1 || reps > 100) { set_error("B in [1, 65535] and reps in [1, 100]"); return JTFS_EINVAL; }
+    if (timing_on()) { set_error("autotune uses the stage timers: disable jtfs timing first"); return JTFS_EINVAL; }
+    std::memset(out, 0, sizeof(*out));
+    const Shapes& s = P->s;
+    const int saved_mode = P->contraction, saved_rows = get_rows(P);
+    // candidates
+    std::vector<int> modes;
+    if (P->split_ok) modes.push_back(JTFS_CONTRACTION_SPLIT_F16);
+    modes.push_back(JTFS_CONTRACTION_FP32);
+    bool has14 = s.logNX == kRegMinLogRows;
+    for (int a = 0; a < s.n_alpha; ++a) has14 = has14 || (s.logNX - s.k2[a] == kRegMinLogRows);
+    const int all_rows = JTFS_REG_SCALOGRAM | JTFS_REG_SECOND_ORDER | JTFS_REG_ROW_FFT | JTFS_REG_FIRST_ADJ;
+    std::vector<int> row_opts = has14 ? std::vector<int>{all_rows, 0} : std::vector<int>{all_rows};
+    // buffers: the largest workspace over the modes; the coefficients double as cotangents
+    size_t wsb = 0;
+    for (int m : modes) {
+        P->contraction = m;
+        size_t b = 0;
+        jtfs_workspace_size(P, B, &b);
+        wsb = std::max(wsb, b);
+    }
+    jtfs_info info;
+    jtfs_plan_info(P, &info);
+    DevBuf ws, s1, s2, gx, xz;
+    if (!ws.alloc(wsb) || !s1.alloc(sizeof(float) * B * info.s1_per_signal) ||
+        !s2.alloc(sizeof(float) * B * info.s2_per_signal) || !gx.alloc(sizeof(float) * B * s.N)) {
+        P->contraction = saved_mode;
+        set_error("autotune: device allocation failed");
+        return JTFS_ENOMEM;
+    }
+    if (!x) {
+        if (!xz.alloc(sizeof(float) * B * s.N) || hipMemsetAsync(xz.p, 0, sizeof(float) * B * s.N, st) != hipSuccess) {
+            P->contraction = saved_mode;
+            set_error("autotune: device allocation failed");
+            return JTFS_ENOMEM;
+        }
+        x = (const float*)xz.p;
+    }
+    // measure
+    double stage[2][2][JTFS_NUM_STAGES] = {};
+    double total[2][2] = {};
+    for (size_t mi = 0; mi < modes.size(); ++mi) {
+        for (size_t ri = 0; ri < row_opts.size(); ++ri) {
+            P->contraction = modes[mi];
+            set_rows(P, row_opts[ri]);
+            const int rc = run_steps(P, x, B, (float*)s1.p, (float*)s2.p, (float*)gx.p, ws.p, wsb, reps, st,
+                                     &total[mi][ri], stage[mi][ri]);
+            if (rc != JTFS_OK) {
+                P->contraction = saved_mode;
+                set_rows(P, saved_rows);
+                return rc;
+            }
+            const int slot = (modes[mi] == JTFS_CONTRACTION_FP32 ? 2 : 0) + (row_opts[ri] ? 0 : 1);
+            out->candidates_ms[slot] = total[mi][ri];
+        }
+    }
+    // contraction: the stages it owns, with register-resident rows
+    const int cstages[] = {JTFS_STAGE_OPERAND_SPLIT, JTFS_STAGE_FREQ_FWD, JTFS_STAGE_FREQ_LOWPASS,
+                           JTFS_STAGE_LOWPASS_ADJ, JTFS_STAGE_FREQ_ADJ_PQ, JTFS_STAGE_FREQ_ADJ_WH};
+    size_t best_m = 0;
+    double best_c = 1e300;
+    for (size_t mi = 0; mi < modes.size(); ++mi) {
+        double c = 0.0;
+        for (int k : cstages) c += stage[mi][0][k];
+        if (c < best_c) { best_c = c; best_m = mi; }
+    }
+    // rows of 2^14 points: per stage, the faster of the two runs of the chosen mode
+    int rows = all_rows;
+    if (row_opts.size() == 2) {
+        const int kstage[4] = {JTFS_STAGE_SCALOGRAM, JTFS_STAGE_SECOND_ORDER, JTFS_STAGE_SECOND_ADJ_FFT,
+                               JTFS_STAGE_FIRST_ADJ};
+        const int kbit[4] = {JTFS_REG_SCALOGRAM, JTFS_REG_SECOND_ORDER, JTFS_REG_ROW_FFT, JTFS_REG_FIRST_ADJ};
+        rows = 0;
+        for (int q = 0; q < 4; ++q)
+            if (stage[best_m][0][kstage[q]] <= stage[best_m][1][kstage[q]]) rows |= kbit[q];
+    }
+    P->contraction = modes[best_m];
+    set_rows(P, rows);
+    double stage_final[JTFS_NUM_STAGES];
+    const int rc = run_steps(P, x, B, (float*)s1.p, (float*)s2.p, (float*)gx.p, ws.p, wsb, reps, st, &out->step_ms,
+                             stage_final);
+    if (rc != JTFS_OK) {
+        P->contraction = saved_mode;
+        set_rows(P, saved_rows);
+        return rc;
+    }
+    out->contraction = P->contraction;
+    out->reg_rows = rows;
+    return JTFS_OK;
+}

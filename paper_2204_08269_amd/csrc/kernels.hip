@@ -922,7 +922,7 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
     JTFS_TIMED(JTFS_STAGE_INPUT_FFT, st, input_fft64(x, B, xh, w.xh_pitch, (double2*)(base + w.tmp64),
                                                      (double2*)(base + w.z64), P, st));
     LAUNCHCHK("input FFT");
-    if (s.logNX >= kRegMinLog) {
+    if (use_reg_rows(s.logNX, P->tune.reg_scalogram)) {
         JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, launch_scalogram_r(P, xh, w.xh_pitch, Xh, w.Xh_pitch, B, st));
     } else {
         JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, hipLaunchKernelGGL(k_scalogram, dim3(s.n1, (unsigned)B), dim3(1024), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
@@ -937,7 +937,7 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
     }
     for (int a = 0; a < s.n_alpha; ++a) {
         const int logTa = s.logNX - s.k2[a];
-        if (logTa >= kRegMinLog) {
+        if (use_reg_rows(logTa, P->tune.reg_second)) {
             JTFS_TIMED(JTFS_STAGE_SECOND_ORDER, st,
                        launch_second_order_r(P, a, Xh, w.Xh_pitch, Y2, (float*)(base + w.rowmax), B, st));
             LAUNCHCHK("second order");
@@ -1029,7 +1029,7 @@ static int gy2_row_fft(const jtfs_plan* P, int a, float2* gY2, int64_t yb, int64
     const int logTa = s.logNX - s.k2[a];
     const int logC = logTa >= 12 ? 0 : 12 - logTa;
     const size_t lds = (size_t)(1 << logC) * (s.Ta[a] + 1) * sizeof(float2);
-    if (logTa >= kRegMinLog) {
+    if (use_reg_rows(logTa, P->tune.reg_rowfft)) {
         JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st,
                    launch_rowfft_r(P, gY2 + s.yoff[a], yb, (int64_t)s.Tp[a], s.n1, logTa, B, st));
     } else {
@@ -1123,7 +1123,7 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_a, dim3(s.n1, (unsigned)B), dim3(1024), lds_a, st, gY2, yb, P->d_yoff, P->d_Tp, P->d_Ta, P->psi2,
                        P->band2, P->off2, s.n_alpha, gs1, P->phiX, s.Mphi, logNT, s.logNX, gX, P->tw, P->tw_log));
     LAUNCHCHK("scalogram adjoint");
-    if (s.logNX >= kRegMinLog) {
+    if (use_reg_rows(s.logNX, P->tune.reg_first_adj)) {
         JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, launch_scal_bwd_b_r(P, xh, w.xh_pitch, gX, g1, B, st));
     } else {
         JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_b, dim3(s.n1, (unsigned)B), dim3(1024), sizeof(float2) * s.NX, st, xh, w.xh_pitch,

@@ -28,6 +28,7 @@ constexpr int kKStep = 16;         // frequential GEMM: K (lambda_1) per LDS sta
 constexpr int kChunkT = 4096;      // frequential GEMM: t-range reduced by one workgroup
 constexpr int kLdsFftMax = 14;     // log2 of the largest complex FFT held in LDS
 constexpr int kMaxLogNX = 15;      // longest scalogram row
+constexpr int kRegMinLogRows = 14; // shortest row length (log2) with a register-resident kernel
 constexpr int kMaxDynLds = 159 * 1024;  // dynamic LDS limit set on kernels (1 KB left for static LDS)
 
 void set_error(const std::string& s);
@@ -81,8 +82,22 @@ Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq);
 
 }  // namespace jtfs
 
+namespace jtfs {
+// Launch choices an autotuner may change (defaults: register-resident 2^14-point rows).
+struct Tuning {
+    bool reg_scalogram = true;   // scalogram rows of 2^14 points
+    bool reg_second = true;      // second-order rows of 2^14 points
+    bool reg_rowfft = true;      // FFT of the gY2 rows of 2^14 points
+    bool reg_first_adj = true;   // first-order adjoint rows of 2^14 points
+};
+// rows of 2^logn points take the register-resident kernels above 2^14 always, at
+// 2^14 when the tuning says so, and the in-LDS kernels below
+inline bool use_reg_rows(int logn, bool knob) { return logn > kRegMinLogRows || (logn == kRegMinLogRows && knob); }
+}  // namespace jtfs
+
 struct jtfs_plan {
     jtfs::Shapes s;
+    jtfs::Tuning tune;
     int device = 0;
     int tw_log = 0;
     float2* tw = nullptr;          // e^{-2 pi i k / 2^tw_log}

@@ -5,7 +5,7 @@
 #include "plan.hpp"
 
 namespace jtfs {
-constexpr int kRegMinLog = 14;   // rows of 2^14 points and longer use the register-resident FFT
+constexpr int kRegMinLog = kRegMinLogRows;   // shortest row length (log2) of the register-resident FFT
 int reg_attributes();
 void launch_scalogram_r(const jtfs_plan* P, const float2* xh, int64_t xh_pitch, float2* Xh, int64_t Xh_pitch,
                         int64_t B, hipStream_t st);

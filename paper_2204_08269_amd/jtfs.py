@@ -116,6 +116,30 @@ class JTFS:
                                           ws.numel(), flags, _stream()))
         return gx
 
+    # launch choices --------------------------------------------------------
+    REG_BITS = {"scalogram": 1, "second_order": 2, "row_fft": 4, "first_adj": 8}
+
+    def autotune(self, B, x=None, reps=3):
+        """Times the candidate launch choices for B signals (x: [B, N] on the
+        GPU, or None for zeros), keeps the fastest and returns what was chosen."""
+        t = _lib.Tuning()
+        xp = _ptr(self._check_x(x)) if x is not None else None
+        _lib.check(self.lib.jtfs_plan_autotune(self.plan, xp, int(B), int(reps), _stream(), ctypes.byref(t)))
+        self.contraction = "split16" if t.contraction == _lib.JTFS_CONTRACTION_SPLIT_F16 else "fp32"
+        self._ws = {}                          # the workspace size may have changed with the mode
+        return {"contraction": self.contraction,
+                "register_rows": [k for k, v in self.REG_BITS.items() if t.reg_rows & v],
+                "step_ms": t.step_ms,
+                "candidates_ms": {"split16_register": t.candidates_ms[0], "split16_lds": t.candidates_ms[1],
+                                  "fp32_register": t.candidates_ms[2], "fp32_lds": t.candidates_ms[3]}}
+
+    def set_tuning(self, contraction, register_rows):
+        mode = {"fp32": _lib.JTFS_CONTRACTION_FP32, "split16": _lib.JTFS_CONTRACTION_SPLIT_F16}[contraction]
+        mask = sum(self.REG_BITS[k] for k in register_rows)
+        _lib.check(self.lib.jtfs_plan_set_tuning(self.plan, mode, mask))
+        self.contraction = contraction
+        self._ws = {}
+
     # mu-log renormalisation (sec. 4) -------------------------------------
     def _check_s(self, s1, s2):
         B = s1.shape[0]

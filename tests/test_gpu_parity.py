@@ -500,3 +500,35 @@ def test_time_scattering_forward_and_vjp(p):
         ref = O.scattering1d_vjp(xb, gs1[b].astype(np.float64), gs2[b].astype(np.float64), P)
         err = rel_l2(g[b], ref)
         assert err <= TOL_VJP, f"signal {b}: gradient relative L2 {err:.3e}"
+
+
+# rows of 2^14 points (kX = 0): the autotuner's register-resident / in-LDS choice matters
+MID = dict(N=2 ** 14, J=5, Q=(1, 1), J_fr=2, Q_fr=1, T=2 ** 9, F=2)
+
+
+def test_autotune_then_every_row_choice_matches_oracle():
+    """The autotuner returns a valid choice; and every combination of
+    register-resident and in-LDS transforms for 2^14-point rows, in both
+    contraction modes, gives the oracle's coefficients and gradient."""
+    P = oracle_plan(MID)
+    assert P.NX == 2 ** 14
+    rng = np.random.default_rng(1414)
+    x = (rng.standard_normal((2, MID["N"])) * 0.5).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    op = gpu_op(MID)
+    choice = op.autotune(2, xt, reps=2)
+    assert choice["contraction"] in ("split16", "fp32") and choice["step_ms"] > 0
+    gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape(), seed=31)
+    refs = [(O.jtfs(x[b].astype(np.float64), P),
+             O.jtfs_vjp(x[b].astype(np.float64), gs1[b].astype(np.float64), gs2[b].astype(np.float64), P))
+            for b in range(2)]
+    for mode in MODES:
+        for rows in ([], ["scalogram", "second_order", "row_fft", "first_adj"], ["scalogram", "row_fft"],
+                     ["second_order", "first_adj"]):
+            op.set_tuning(mode, rows)
+            g1, g2 = run_forward(op, x)
+            g = op.vjp(xt, torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda()).cpu().numpy()
+            for b in range(2):
+                (r1, r2), rg = refs[b]
+                check_paths(g1[b], g2[b], r1, r2)
+                assert rel_l2(g[b], rg) <= TOL_VJP, (mode, rows)
