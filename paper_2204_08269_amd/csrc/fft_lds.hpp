@@ -46,6 +46,24 @@ __device__ __forceinline__ C twiddle(const C* __restrict__ tw, int k, bool inv) 
     return w;
 }
 
+// Twiddles w^r, r = 1..R-1, of one radix-R butterfly, w = twiddle(tw, k, inv): w,
+// w^2 and w^4 come from the table, the others are products of those (at most
+// two roundings deep), so a radix-8 butterfly loads three twiddles, not seven.
+template <int R, typename C>
+__device__ __forceinline__ void butterfly_twiddles(C (&w)[R], const C* __restrict__ tw, int k, bool inv) {
+    if constexpr (R >= 2) w[1] = twiddle(tw, k, inv);
+    if constexpr (R >= 4) {
+        w[2] = twiddle(tw, 2 * k, inv);
+        w[3] = cmul(w[1], w[2]);
+    }
+    if constexpr (R >= 8) {
+        w[4] = twiddle(tw, 4 * k, inv);
+        w[5] = cmul(w[1], w[4]);
+        w[6] = cmul(w[2], w[4]);
+        w[7] = cmul(w[3], w[4]);
+    }
+}
+
 // In-register 4-point DFT (sign -1 forward, +1 inverse).
 template <typename C>
 __device__ __forceinline__ void dft4(C* a, bool inv) {
@@ -80,10 +98,12 @@ __device__ __forceinline__ void fft_pass(C* s, int logn, int count, int stride, 
             const int j = g & ((1 << nb_log) - 1);
             const C* src = s + t * stride;
             const int k = j & (Ns - 1);
+            C w[R];
+            butterfly_twiddles<R>(w, tw, k << tws, inv);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 C a = src[j + (r << nb_log)];
-                if (r) a = cmul(a, twiddle(tw, (r * k) << tws, inv));
+                if (r) a = cmul(a, w[r]);
                 v[q][r] = a;
             }
             if constexpr (R == 2) {

@@ -48,8 +48,10 @@ __device__ __forceinline__ void reg_butterflies(float2 (&v)[E], int lNs, const f
         const int j = (int)threadIdx.x + q * (int)blockDim.x;
         const int k = j & ((1 << lNs) - 1);
         float2* a = v + q * R;
+        float2 w[R];
+        butterfly_twiddles<R>(w, tw, k << tws, inv);
 #pragma unroll
-        for (int r = 1; r < R; ++r) a[r] = cmul(a[r], twiddle(tw, (r * k) << tws, inv));
+        for (int r = 1; r < R; ++r) a[r] = cmul(a[r], w[r]);
         if constexpr (R == 2) {
             const float2 a0 = a[0], a1 = a[1];
             a[0] = cadd(a0, a1);
