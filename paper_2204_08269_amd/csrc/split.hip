@@ -44,13 +44,14 @@ __device__ __forceinline__ void split_h(float v, _Float16& hi, _Float16& lo) {
     lo = (_Float16)(v - (float)hi);
 }
 
-// 2^(13 - e) with m < 2^e (frexp exponent): m * scale < 2^14; 1 for m == 0.
-__device__ __forceinline__ float pow2_scale(float m) {
-    if (!(m > 0.f)) return 1.f;
+// s = 13 - e with m < 2^e (frexp exponent), so that m 2^s < 2^14; 0 for m == 0.
+__device__ __forceinline__ int pow2_exp(float m) {
+    if (!(m > 0.f)) return 0;
     int e;
     (void)frexpf(m, &e);
-    return ldexpf(1.f, max(-120, min(120, 13 - e)));
+    return max(-120, min(120, 13 - e));
 }
+__device__ __forceinline__ float pow2_scale(float m) { return ldexpf(1.f, pow2_exp(m)); }
 
 // ---------------------------------------------------------------- plan tables
 
@@ -186,6 +187,37 @@ __global__ void __launch_bounds__(256) k_ysplit(const float2* __restrict__ Y, in
     }
 }
 
+// A pointer the compiler cannot trace back to its (read-only, non-aliasing)
+// kernel argument.  Loads through it are not taken as invariant, so the
+// register allocator does not re-issue them next to their uses (possibly
+// behind outstanding global-to-LDS loads, whose waits would then cover those
+// too), and the Y loads, whose addresses are the same for every chunk, are not
+// hoisted out of the chunk loop.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> launder_v(const T* p) {
+    gptr<T> g = (gptr<T>)p;
+    asm volatile("" : "+v"(g));
+    return g;
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> launder_s(const T* p) {
+    gptr<T> g = (gptr<T>)p;
+    asm volatile("" : "+s"(g));
+    return g;
+}
+
+// Y fragments of k-step kq (k-groups 2 kq + h) of this lane's column
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void load_y(uint4 (&y)[4], gptr<uint4> ycol, int kq) {
+    gptr<u32x4> p = (gptr<u32x4>)(ycol + 8 * kq);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) y[j] = __builtin_bit_cast(uint4, p[j]);
+}
+
 // ------------------------------------------------------- forward contraction
 
 // One workgroup: 64 rows l (W resident in LDS) x one t-chunk, in tiles of 128 t.
@@ -196,14 +228,15 @@ __global__ void __launch_bounds__(256) k_ysplit(const float2* __restrict__ Y, in
 // The modulus enters the second product split with a per-column power-of-two
 // scale, removed from that tile's contribution before accumulation.
 // Workgroups are mapped so that the row tiles sharing a t-chunk run on one XCD.
-template <int NTB>
+template <int NTB, int NK>
 __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __restrict__ Yh, int64_t yh_bstride, int Tp,
                                                     int chunk, int nch, int nU, int nlt,
-                                                    const unsigned short* __restrict__ Wsp, int Kp,
+                                                    const unsigned short* __restrict__ Wsp,
                                                     const unsigned short* __restrict__ Phsp, float unscale_wphi,
                                                     const float* __restrict__ yscale, int alpha, int n_alpha,
                                                     float* __restrict__ Vp, int64_t vp_bstride, int slot0) {
     constexpr int NTp = 32 * NTB;
+    constexpr int Kp = 16 * NK;            // K = NK k-steps of 16 (compile time: the K loop is unrolled)
     extern __shared__ __align__(16) unsigned char lds[];
     const int WS = Kp * 8 + 16;            // bytes per resident W row
     unsigned char* lw_ = lds;
@@ -233,42 +266,77 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
 #pragma unroll
     for (int n = 0; n < NTB; ++n) { vu[n] = z16(); vd[n] = z16(); }
 
-    const int nK = Kp / 16;
     __syncthreads();                     // resident W complete
     const unsigned char* wbase = lw_ + (wl * 32 + i32) * WS + h * 64;
-    for (int t0 = ch * chunk; t0 < (ch + 1) * chunk; t0 += kTileTh) {
-        // each lane streams its own Y fragments (row t, k-group 2 kq + h) from global
-        // memory two K-blocks ahead of use; W fragments come from the resident LDS rows.
-        // One k-group is 4 planes x 8 halves = 4 uint4, one K-block (16 k) 8 uint4.
-        const uint4* yrow = (const uint4*)(Yb + ((int64_t)(t0 + wt * 32 + i32) * nkb + h) * 32);
-        uint4 a0 = yrow[0], a1 = yrow[1], a2 = yrow[2], a3 = yrow[3];
-        uint4 b0 = a0, b1 = a1, b2 = a2, b3 = a3;
-        if (nK > 1) { b0 = yrow[8]; b1 = yrow[9]; b2 = yrow[10]; b3 = yrow[11]; }
+    // Each lane streams its own Y fragments (column t, k-group 2 kq + h; one
+    // k-step is 4 uint4) from global memory through a ring of NR k-steps,
+    // refilled as it drains; the next tile's first NR k-steps are requested
+    // before the current tile's epilogue.  W fragments come from the resident
+    // LDS rows.  The Phi fragments of a tile are requested before its Y loads,
+    // so that waiting for them never waits for Y.
+    const int tbeg = ch * chunk, tend = (ch + 1) * chunk;
+    auto ycol_at = [&](int t0) {
+        return launder_v((const uint4*)(Yb + ((int64_t)(t0 + wt * 32 + i32) * nkb + h) * 32));
+    };
+    constexpr int NR0 = NTB == 1 ? 4 : 2;                     // ring depth within the register budget
+    constexpr int NR = NK < NR0 ? NK : NR0;
+    uint4 yr[NR][4];
+    gptr<uint4> yc = ycol_at(tbeg);
+#pragma unroll
+    for (int s = 0; s < NR; ++s) load_y(yr[s], yc, s);
+    for (int t0 = tbeg; t0 < tend; t0 += kTileTh) {
+        const int t32 = (t0 >> 5) + wt;
+        auto load_phi = [&](int n, int s, uint4 (&f)[2]) {
+            gptr<u32x4> ph = (gptr<u32x4>)launder_v(
+                (const uint4*)(Phsp + (((((int64_t)t32 * 2 + s) * 2 + h) * NTp + n * 32 + i32) * 2) * 8));
+            f[0] = __builtin_bit_cast(uint4, ph[0]);
+            f[1] = __builtin_bit_cast(uint4, ph[1]);
+        };
+        // with one 32-frame block the Phi fragments are held from here and the
+        // next tile's Y is requested before the epilogue; wider frame counts
+        // have no registers for that and request both where they are used
+        constexpr bool early = NTB == 1;
+        uint4 phf[2][2];                             // [s][hi, lo] of block n = 0
+        if constexpr (early) {
+            load_phi(0, 0, phf[0]);
+            load_phi(0, 1, phf[1]);
+        }
+        // K loop, unrolled: k-step kq lives in ring slot kq % NR; W fragments are
+        // read one k-step ahead, and a scheduling barrier closes every k-step so
+        // that the LDS reads are not all hoisted to the top
         floatx16 rr = z16(), ir = z16(), ri = z16(), ii = z16();
-        auto block = [&](int kq, uint4 q0, uint4 q1, uint4 q2, uint4 q3) {
-            const unsigned char* wr = wbase + kq * 128;
-            const half8 w0 = as_h8(*(const uint4*)(wr + 0)), w1 = as_h8(*(const uint4*)(wr + 16));
-            const half8 w2 = as_h8(*(const uint4*)(wr + 32)), w3 = as_h8(*(const uint4*)(wr + 48));
-            const half8 y0 = as_h8(q0), y1 = as_h8(q1), y2 = as_h8(q2), y3 = as_h8(q3);
+        uint4 wc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) wc[j] = *(const uint4*)(wbase + 16 * j);
+#pragma unroll
+        for (int kq = 0; kq < NK; ++kq) {
+            uint4 wn[4];
+            if (kq + 1 < NK) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) wn[j] = *(const uint4*)(wbase + (kq + 1) * 128 + 16 * j);
+            }
+            const half8 w0 = as_h8(wc[0]), w1 = as_h8(wc[1]), w2 = as_h8(wc[2]), w3 = as_h8(wc[3]);
+            uint4(&q)[4] = yr[kq % NR];
+            const half8 y0 = as_h8(q[0]), y1 = as_h8(q[1]), y2 = as_h8(q[2]), y3 = as_h8(q[3]);
             rr = mfma16(y0, w0, rr); rr = mfma16(y0, w1, rr); rr = mfma16(y1, w0, rr);
             ir = mfma16(y2, w0, ir); ir = mfma16(y2, w1, ir); ir = mfma16(y3, w0, ir);
             ri = mfma16(y0, w2, ri); ri = mfma16(y0, w3, ri); ri = mfma16(y1, w2, ri);
             ii = mfma16(y2, w2, ii); ii = mfma16(y2, w3, ii); ii = mfma16(y3, w2, ii);
-        };
-        for (int kq = 0; kq < nK; kq += 2) {
-            block(kq, a0, a1, a2, a3);
-            if (kq + 2 < nK) {
-                const uint4* p = yrow + 8 * (kq + 2);
-                a0 = p[0]; a1 = p[1]; a2 = p[2]; a3 = p[3];
+            if (kq + NR < NK) load_y(q, yc, kq + NR);
+            if (kq + 1 < NK) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) wc[j] = wn[j];
             }
-            if (kq + 1 < nK) {
-                block(kq + 1, b0, b1, b2, b3);
-                if (kq + 3 < nK) {
-                    const uint4* p = yrow + 8 * (kq + 3);
-                    b0 = p[0]; b1 = p[1]; b2 = p[2]; b3 = p[3];
-                }
-            }
+            __builtin_amdgcn_sched_barrier(0);
         }
+        auto next_tile = [&]() {
+            if (t0 + kTileTh < tend) {
+                yc = ycol_at(t0 + kTileTh);
+#pragma unroll
+                for (int s = 0; s < NR; ++s) load_y(yr[s], yc, s);
+            }
+        };
+        if constexpr (early) next_tile();
         // modulus of both spins, per-column scale, split, second product with Phi
 #pragma unroll
         for (int spin = 0; spin < 2; ++spin) {
@@ -294,14 +362,19 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
                     uh[s][j] = hi;
                     ul[s][j] = lo;
                 }
-            const int t32 = (t0 >> 5) + wt;
 #pragma unroll
             for (int n = 0; n < NTB; ++n) {
                 floatx16 tmp = z16();
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    const uint4* ph = (const uint4*)(Phsp + (((((int64_t)t32 * 2 + s) * 2 + h) * NTp + n * 32 + i32) * 2) * 8);
-                    const half8 phi = as_h8(ph[0]), plo = as_h8(ph[1]);
+                    uint4 f[2];
+                    if constexpr (early) {
+                        f[0] = phf[s][0];
+                        f[1] = phf[s][1];
+                    } else {
+                        load_phi(n, s, f);
+                    }
+                    const half8 phi = as_h8(f[0]), plo = as_h8(f[1]);
                     tmp = mfma16(phi, uh[s], tmp);
                     tmp = mfma16(phi, ul[s], tmp);
                     tmp = mfma16(plo, uh[s], tmp);
@@ -315,6 +388,7 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
                 }
             }
         }
+        if constexpr (!early) next_tile();
     }
     // sum the four t-quarter waves of each row half through LDS, unscale, store
     const float unscale = unscale_wphi / yscale[b * n_alpha + alpha];
@@ -372,18 +446,24 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glob_void_t;
 
-// one wave copies 64 slots: slot e = g * 64 + lane of the chunk's LDS layout
-__device__ __forceinline__ void dma16(const uint4* src, uint4* lds_group) {
-    __builtin_amdgcn_global_load_lds((glob_void_t*)src, (lds_void_t*)lds_group, 16, 0, 0);
+// one wave copies 64 slots: slot e = g * 64 + lane of the chunk's LDS layout.
+// The source is a block-uniform base plus this lane's byte offset (32 bits), the
+// form the global-to-LDS load takes with the base in scalar registers, so that
+// a staging sequence keeps one offset register instead of one 64-bit address
+// per load.
+__device__ __forceinline__ void dma16(const uint4* ubase, uint32_t lane_bytes, uint4* lds_group) {
+    __builtin_amdgcn_global_load_lds((glob_void_t*)((const char*)ubase + lane_bytes), (lds_void_t*)lds_group, 16,
+                                     0, 0);
 }
 
 // W chunk c (rows 32c..32c+31): LDS slot e = seg * 32 + r, seg = (2 kq + h) * 4 + p.
 // Group g = wave + 4 j covers slots 64 g + lane: seg = 2 g + h, r = lane & 31, so a
 // lane's source is its row's base plus 8 j slots.
 __device__ __forceinline__ void stage_w(uint4* Ls, const uint4* Wsrc, int c, int nK, int nkb, int wave, int lane) {
-    const uint4* src = Wsrc + (int64_t)c * (nK * 256) + (lane & 31) * (nkb * 4) + 2 * wave + (lane >> 5);
+    const uint4* base = Wsrc + (int64_t)c * (nK * 256);
+    const uint32_t off = (uint32_t)((lane & 31) * (nkb * 4) + 2 * wave + (lane >> 5)) * 16u;
     uint4* dst = Ls + wave * 64;
-    for (int j = 0; j < nK; ++j) dma16(src + 8 * j, dst + 256 * j);
+    for (int j = 0; j < nK; ++j) dma16(base + 8 * j, off, dst + 256 * j);
 }
 
 // W^T chunk c (KpT = 32 NI rows): LDS slot e = seg * 32 + i32, seg = q * 16 + (sp * 2 + h) * 4 + p.
@@ -391,56 +471,95 @@ __device__ __forceinline__ void stage_w(uint4* Ls, const uint4* Wsrc, int c, int
 // inside q is 8 (k & 1) + 2 wave + h.
 template <int NI>
 __device__ __forceinline__ void stage_t(uint4* Ls, const uint4* Tsrc, int c, int wave, int lane) {
-    const uint4* src = Tsrc + (int64_t)c * (NI * 512) + (lane & 31) * 16 + 2 * wave + (lane >> 5);
+    const uint4* base = Tsrc + (int64_t)c * (NI * 512);
+    const uint32_t off = (uint32_t)((lane & 31) * 16 + 2 * wave + (lane >> 5)) * 16u;
     uint4* dst = Ls + wave * 64;
 #pragma unroll
-    for (int k = 0; k < 2 * NI; ++k) dma16(src + (k >> 1) * 512 + 8 * (k & 1), dst + 256 * k);
+    for (int k = 0; k < 2 * NI; ++k) dma16(base + (k >> 1) * 512 + 8 * (k & 1), off, dst + 256 * k);
 }
 
-template <int NTB, int NI>
-__device__ __forceinline__ void bwd_chunk(int c, int nC, int nK, int nkb, int Mp, int wave, int lane, int h, int i32,
-                                          const uint4* ycol, const uint4* phrow, const float* gvb, float inv_wy,
-                                          float inv_phi, float spq, uint4* Ls_W, const uint4* Tcur, uint4* Tnext,
-                                          const uint4* Wsrc, const uint4* Tsrc, floatx16 (&gyr)[NI],
-                                          floatx16 (&gyi)[NI]) {
+// gV rows l0 + i32 of both spins, this lane's tau half (8 h.. of each 16)
+template <int NTB>
+__device__ __forceinline__ void load_gv(float4 (&v)[2][NTB * 2][2], gptr<float4> gvb, int Mp, int l0, int i32,
+                                        int h) {
     constexpr int NTp = 32 * NTB;
-    // ---- recompute Z for rows 32c.., columns tw0.. (four independent chains)
-    const uint4* lw = Ls_W + h * 4 * 32 + i32;
-    floatx16 rr = z16(), ri = z16(), ir = z16(), ii = z16();
-    // Y fragments two k-steps ahead
-    uint4 ya0 = ycol[0], ya1 = ycol[1], ya2 = ycol[2], ya3 = ycol[3];
-    uint4 yb0 = ya0, yb1 = ya1, yb2 = ya2, yb3 = ya3;
-    if (nK > 1) { yb0 = ycol[8]; yb1 = ycol[9]; yb2 = ycol[10]; yb3 = ycol[11]; }
-    for (int kq = 0; kq < nK; ++kq) {
-        const uint4* wk = lw + kq * 8 * 32;
-        const half8 w0 = as_h8(wk[0]), w1 = as_h8(wk[32]), w2 = as_h8(wk[64]), w3 = as_h8(wk[96]);
-        const half8 y0 = as_h8(ya0), y1 = as_h8(ya1), y2 = as_h8(ya2), y3 = as_h8(ya3);
-        ya0 = yb0; ya1 = yb1; ya2 = yb2; ya3 = yb3;
-        if (kq + 2 < nK) {
-            const uint4* yp = ycol + 8 * (kq + 2);
-            yb0 = yp[0]; yb1 = yp[1]; yb2 = yp[2]; yb3 = yp[3];
+#pragma unroll
+    for (int spin = 0; spin < 2; ++spin) {
+        gptr<f32x4> gr = (gptr<f32x4>)(gvb + (((int64_t)spin * Mp + l0 + i32) * NTp + 8 * h) / 4);
+#pragma unroll
+        for (int kb = 0; kb < NTB * 2; ++kb) {
+            v[spin][kb][0] = __builtin_bit_cast(float4, gr[4 * kb]);
+            v[spin][kb][1] = __builtin_bit_cast(float4, gr[4 * kb + 1]);
         }
+    }
+}
+
+// One 32-row chunk c.  On entry the first min(NK, 4) k-steps of Y sit in the
+// ring yr and the chunk's gV rows in v (both loaded during the previous chunk),
+// and the chunk's W and W^T are in LDS.  On exit the same holds for chunk c + 1.
+// Order of memory operations: the ring is refilled inside the recompute loop
+// (ordinary loads, waited for there); the DMA staging of the next W and W^T is
+// issued after that loop, and the next chunk's Y ring and gV after it, all of
+// them waited for only at the chunk's end.  No wait for an ordinary load is
+// therefore ever placed behind an outstanding global-to-LDS load.
+template <int NTB, int NI, int NK>
+__device__ __forceinline__ void bwd_chunk(int c, int nC, int Mp, int wave, int lane, int h, int i32,
+                                          const uint4* ycol, const uint4 (&phv)[NTB * 2][2], const float* gvb,
+                                          float eps2s,
+                                          float ips, float spq, uint4* Ls_W, const uint4* Tcur, uint4* Tnext,
+                                          const uint4* Wsrc, const uint4* Tsrc, floatx16 (&gyr)[NI],
+                                          floatx16 (&gyi)[NI], uint4 (&yr)[4][4]) {
+    constexpr int NR = NK < 4 ? NK : 4;                       // Y ring depth (k-steps in flight)
+    // this chunk's gV rows (older than every Y load of the loop below, so the
+    // loop's waits cover them)
+    float4 v[2][NTB * 2][2];
+    load_gv<NTB>(v, launder_s((const float4*)gvb), Mp, 32 * c, i32, h);
+    // ---- recompute Z for rows 32c.., columns tw0.. (four independent chains)
+    // (W fragments read one k-step ahead; a scheduling barrier closes every
+    // k-step so that the reads are not all hoisted to the top)
+    const uint4* lw = Ls_W + h * 4 * 32 + i32;
+    gptr<uint4> yc = launder_v(ycol);
+    floatx16 rr = z16(), ri = z16(), ir = z16(), ii = z16();
+    uint4 wc[4] = {lw[0], lw[32], lw[64], lw[96]};
+#pragma unroll
+    for (int kq = 0; kq < NK; ++kq) {
+        uint4 wn[4];
+        if (kq + 1 < NK) {
+            const uint4* wk = lw + (kq + 1) * 8 * 32;
+            wn[0] = wk[0]; wn[1] = wk[32]; wn[2] = wk[64]; wn[3] = wk[96];
+        }
+        const half8 w0 = as_h8(wc[0]), w1 = as_h8(wc[1]), w2 = as_h8(wc[2]), w3 = as_h8(wc[3]);
+        uint4(&ys)[4] = yr[kq % NR];
+        const half8 y0 = as_h8(ys[0]), y1 = as_h8(ys[1]), y2 = as_h8(ys[2]), y3 = as_h8(ys[3]);
         rr = mfma16(w0, y0, rr); ri = mfma16(w0, y2, ri); ir = mfma16(w2, y0, ir); ii = mfma16(w2, y2, ii);
         rr = mfma16(w0, y1, rr); ri = mfma16(w0, y3, ri); ir = mfma16(w2, y1, ir); ii = mfma16(w2, y3, ii);
         rr = mfma16(w1, y0, rr); ri = mfma16(w1, y2, ri); ir = mfma16(w3, y0, ir); ii = mfma16(w3, y2, ii);
-    }
-    // ---- gV rows of both spins, then the next W^T chunk (lands during this chunk)
-    const int l0 = 32 * c;
-    float4 v[2][NTB * 2][2];
-#pragma unroll
-    for (int spin = 0; spin < 2; ++spin) {
-        const float* gr = gvb + ((int64_t)spin * Mp + l0 + i32) * NTp + 8 * h;
-#pragma unroll
-        for (int kb = 0; kb < NTB * 2; ++kb) {
-            v[spin][kb][0] = *(const float4*)(gr + 16 * kb);
-            v[spin][kb][1] = *(const float4*)(gr + 16 * kb + 4);
+        if (kq + NR < NK) load_y(ys, yc, kq + NR);
+        if (kq + 1 < NK) {
+            wc[0] = wn[0]; wc[1] = wn[1]; wc[2] = wn[2]; wc[3] = wn[3];
         }
+        __builtin_amdgcn_sched_barrier(0);
     }
-    // unconditional (the last chunk reloads itself into the idle buffer): with no
-    // branch here the gV waits below count past these loads
+    // gV is used from here on only: its wait lands here (long after the loads,
+    // and ahead of the staging below), and nothing computed from it is moved
+    // into the loop above
+#pragma unroll
+    for (int spin = 0; spin < 2; ++spin)
+#pragma unroll
+        for (int kb = 0; kb < NTB * 2; ++kb)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                asm volatile("" : "+v"(v[spin][kb][j].x), "+v"(v[spin][kb][j].y), "+v"(v[spin][kb][j].z),
+                             "+v"(v[spin][kb][j].w));
+    // ---- every wave is done with this W chunk (only this wave's LDS reads must
+    // be complete: lgkmcnt 0, vmcnt and expcnt at their maxima in the gfx9
+    // encoding); stage the next W and W^T chunks (the last chunk reloads itself)
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
     const int cn = c + 1 < nC ? c + 1 : c;
+    stage_w(Ls_W, Wsrc, cn, NK, 2 * NK, wave, lane);
     stage_t<NI>(Tnext, Tsrc, cn, wave, lane);
-    // ---- gU = gV Phi^T for both spins (gV split per row, Phi pre-split)
+    // ---- gU = gV Phi^T for both spins (gV split per row, Phi pre-split), times spq
     floatx16 gu[2];
 #pragma unroll
     for (int spin = 0; spin < 2; ++spin) {
@@ -452,7 +571,8 @@ __device__ __forceinline__ void bwd_chunk(int c, int nC, int nK, int nkb, int Mp
             mx = fmaxf(mx, fmaxf(fmaxf(fabsf(a1.x), fabsf(a1.y)), fmaxf(fabsf(a1.z), fabsf(a1.w))));
         }
         mx = fmaxf(mx, __shfl_xor(mx, 32));
-        const float sg = pow2_scale(mx);
+        const int se = pow2_exp(mx);
+        const float sg = ldexpf(1.f, se);
         floatx16 acc = z16();
 #pragma unroll
         for (int kb = 0; kb < NTB * 2; ++kb) {
@@ -466,47 +586,47 @@ __device__ __forceinline__ void bwd_chunk(int c, int nC, int nK, int nkb, int Mp
                 ah[j] = hi;
                 al[j] = lo;
             }
-            const uint4* pp = phrow + 4 * kb;       // k-group 2 kb + h: 32 bytes (hi, lo)
-            const half8 bh = as_h8(pp[0]), bl = as_h8(pp[1]);
+            const half8 bh = as_h8(phv[kb][0]), bl = as_h8(phv[kb][1]);
             acc = mfma16(ah, bh, acc);
             acc = mfma16(ah, bl, acc);
             acc = mfma16(al, bh, acc);
         }
-        // row crow(r, h) of the C tile carries that row's gV scale (a power of
-        // two: its reciprocal is exact)
-        const float isg = inv_phi / sg;
+        // row crow(r, h) of the C tile carries that row's gV scale; every factor
+        // is a power of two, so the rescaling is exact
+        const float isg = ldexpf(ips, -se);
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[r] *= __shfl(isg, crow(r, h));
         gu[spin] = acc;
     }
-    // ---- modulus adjoint, P and Q' (FP32), split with the common scale
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- modulus adjoint, P and Q' (FP32, already carrying the scale spq).
+    // gU z / |z| does not depend on the scale of z, so the scaled Z is used as
+    // it is; |z|^2 is floored at kEpsMod2 on the unscaled value (eps2s)
     half8 ph[2][4], pl[2][4];       // [s'][Pr, Pi, Qr, Qi]
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const float ur = (rr[r] - ii[r]) * inv_wy, ui = (ri[r] + ir[r]) * inv_wy;
-        const float dr = (rr[r] + ii[r]) * inv_wy, di = (ri[r] - ir[r]) * inv_wy;
-        // gU / |z| as gU * rsqrt(|z|^2), |z|^2 floored at a normal FP32 number
-        // (kEpsMod2); z = 0 gives 0 as with the plain guard
-        const float su = gu[0][r] * rsqrtf(fmaxf(ur * ur + ui * ui, kEpsMod2));
-        const float sd = gu[1][r] * rsqrtf(fmaxf(dr * dr + di * di, kEpsMod2));
-        const float gur = su * ur, gui = su * ui, gdr = sd * dr, gdi = sd * di;
-        const float vals[4] = {gur + gdr, gui + gdi, -(gdi - gui), gdr - gur};
+        if (r == 8) __builtin_amdgcn_sched_barrier(0);
+        const float ur = rr[r] - ii[r], ui = ri[r] + ir[r];
+        const float dr = rr[r] + ii[r], di = ri[r] - ir[r];
+        // (eps2s is a normal number: the hardware reciprocal square root needs no
+        // denormal handling)
+        const float su = gu[0][r] * __builtin_amdgcn_rsqf(fmaxf(ur * ur + ui * ui, eps2s));
+        const float sd = gu[1][r] * __builtin_amdgcn_rsqf(fmaxf(dr * dr + di * di, eps2s));
+        const float vals[4] = {su * ur + sd * dr, su * ui + sd * di, su * ui - sd * di, sd * dr - su * ur};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             _Float16 hi, lo;
-            split_h(vals[q] * spq, hi, lo);
+            split_h(vals[q], hi, lo);
             ph[r >> 3][q][r & 7] = hi;
             pl[r >> 3][q][r & 7] = lo;
         }
     }
-    // ---- every wave is done with this W chunk: stage the next one.  Only this
-    // wave's LDS reads have to be complete (lgkmcnt 0; vmcnt and expcnt left at
-    // their maxima in the gfx9 encoding), not the W^T staging just issued: a
-    // fence would wait for that too, since it writes LDS through the vector
-    // memory counter.
-    __builtin_amdgcn_s_waitcnt(0xC07F);
-    __builtin_amdgcn_s_barrier();
-    stage_w(Ls_W, Wsrc, cn, nK, nkb, wave, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- the next chunk's Y ring (lands during the product below)
+    gptr<uint4> yn = launder_v(ycol);
+#pragma unroll
+    for (int s = 0; s < NR; ++s) load_y(yr[s], yn, s);
+    __builtin_amdgcn_sched_barrier(0);
     // ---- gY += Wr^T P + Wi^T Q' (A operand from the staged W^T chunk); two
     // i-blocks at a time, so that four independent accumulations alternate
 #pragma unroll
@@ -535,25 +655,27 @@ __device__ __forceinline__ void bwd_chunk(int c, int nC, int nK, int nkb, int Mp
                     gyi[q0 + d] = mfma16(a, bi, gyi[q0 + d]);
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
-    // ---- the next chunk's W and W^T have landed; every wave is done with this W^T chunk
+    // ---- the next chunk's operands have landed; every wave is done with this W^T chunk
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 }
 
-template <int NTB, int NI>
+template <int NTB, int NI, int NK>
 __global__ void __launch_bounds__(256) k_freq_bwd_h(const unsigned short* __restrict__ Yh, int64_t yh_bstride,
                                                     int Tp, int nTt, int nU,
                                                     const unsigned short* __restrict__ Wsp,
-                                                    const unsigned short* __restrict__ WTsp, int Kp, int Mp,
+                                                    const unsigned short* __restrict__ WTsp, int Mp,
                                                     const unsigned short* __restrict__ PhTsp, float sphi,
                                                     const float* __restrict__ gV, int64_t gv_bstride,
                                                     const float* __restrict__ gvmax, int n_beta,
                                                     const float* __restrict__ yscale, int alpha, int n_alpha,
                                                     float sw, float2* __restrict__ gY, int64_t gy_bstride) {
     constexpr int NTp = 32 * NTB;
-    __shared__ uint4 Ls_W[NI * 512];                // nK <= 2 NI k-steps x 8 segments x 32 slots
+    constexpr int Kp = 16 * NK, nkb = 2 * NK;
+    __shared__ uint4 Ls_W[NI * 512];                // NK <= 2 NI k-steps x 8 segments x 32 slots
     __shared__ uint4 Ls_T0[NI * 512];               // 32 NI rows x 16 segments ... x 32 slots / 32
     __shared__ uint4 Ls_T1[NI * 512];
     const int u = blockIdx.x;
@@ -563,15 +685,16 @@ __global__ void __launch_bounds__(256) k_freq_bwd_h(const unsigned short* __rest
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, i32 = lane & 31;
     const int tw0 = t0 + wave * 32;                 // this wave's columns
-    const int nkb = Kp / 8, nK = Kp / 16, nC = Mp / 32;
+    const int nC = Mp / 32;
 
-    // scales
+    // scales (all powers of two but the modulus floor)
     float G = 0.f;
     for (int q = 0; q < 2 * n_beta; ++q) G = fmaxf(G, gvmax[(b * n_alpha + alpha) * 2 * n_beta + q]);
     const float spq = pow2_scale(2.f * G * 16384.f / sphi);
     const float sy = yscale[b * n_alpha + alpha];
-    const float inv_wy = 1.f / (sw * sy);
-    const float inv_phi = 1.f / sphi;
+    const double wy = (double)sw * (double)sy;
+    const float eps2s = (float)fmax(fmin((double)kEpsMod2 * wy * wy, 1e30), 1.1754943508222875e-38);
+    const float ips = spq / sphi;
 
     floatx16 gyr[NI], gyi[NI];
 #pragma unroll
@@ -584,15 +707,28 @@ __global__ void __launch_bounds__(256) k_freq_bwd_h(const unsigned short* __rest
     const uint4* Wsrc = (const uint4*)Wsp;
     const uint4* Tsrc = (const uint4*)WTsp;
 
-    stage_w(Ls_W, Wsrc, 0, nK, nkb, wave, lane);
+    // Phi^T fragments of the four columns (the same for every chunk): k-group
+    // 2 kb + h, 32 bytes (hi, lo)
+    uint4 phv[NTB * 2][2];
+#pragma unroll
+    for (int kb = 0; kb < NTB * 2; ++kb) {
+        phv[kb][0] = phrow[4 * kb];
+        phv[kb][1] = phrow[4 * kb + 1];
+    }
+    uint4 yr[4][4];
+#pragma unroll
+    for (int s = 0; s < (NK < 4 ? NK : 4); ++s) load_y(yr[s], (gptr<uint4>)ycol, s);
+    stage_w(Ls_W, Wsrc, 0, NK, nkb, wave, lane);
     stage_t<NI>(Ls_T0, Tsrc, 0, wave, lane);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (int c = 0; c < nC; ++c) {
-        uint4* Tc = (c & 1) ? Ls_T1 : Ls_T0;
-        uint4* Tn = (c & 1) ? Ls_T0 : Ls_T1;
-        bwd_chunk<NTB, NI>(c, nC, nK, nkb, Mp, wave, lane, h, i32, ycol, phrow, gvb, inv_wy, inv_phi, spq, Ls_W,
-                           Tc, Tn, Wsrc, Tsrc, gyr, gyi);
+    // nC is even (Mp is a multiple of 64): the W^T buffers alternate at compile
+    // time, so that the reads of one are not made to wait for the staging of the other
+    for (int c = 0; c < nC; c += 2) {
+        bwd_chunk<NTB, NI, NK>(c, nC, Mp, wave, lane, h, i32, ycol, phv, gvb, eps2s, ips, spq, Ls_W, Ls_T0, Ls_T1,
+                               Wsrc, Tsrc, gyr, gyi, yr);
+        bwd_chunk<NTB, NI, NK>(c + 1, nC, Mp, wave, lane, h, i32, ycol, phv, gvb, eps2s, ips, spq, Ls_W, Ls_T1,
+                               Ls_T0, Wsrc, Tsrc, gyr, gyi, yr);
     }
     // ---- store gY rows i < Kp, columns tw0.. (FP32 complex)
     const float inv = 1.f / (sw * spq);
@@ -683,13 +819,37 @@ int build_split_tables(jtfs_plan* P, std::vector<void*>& owned) {
     return JTFS_OK;
 }
 
+// largest K (in k-steps of 16) whose resident W tile fits the dynamic LDS limit
+constexpr int kMaxFwdNK = (kMaxDynLds / 64 - 16) / 8 / 16;
+
+template <int NTB, int NK = 1>
+static int fwd_attributes() {
+    if constexpr (NK > kMaxFwdNK) {
+        return JTFS_OK;
+    } else {
+        if (hipFuncSetAttribute((const void*)k_freq_fwd_h<NTB, NK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kMaxDynLds) != hipSuccess) {
+            set_error("hipFuncSetAttribute failed for the split contraction");
+            return JTFS_EHIP;
+        }
+        return fwd_attributes<NTB, NK + 1>();
+    }
+}
+
 int split_attributes() {
     // the backward kernels use static LDS only; the forward takes it dynamically
-    const void* ks[] = {(const void*)k_freq_fwd_h<1>, (const void*)k_freq_fwd_h<2>};
-    for (const void* k : ks)
-        if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds) != hipSuccess) {
-            set_error("hipFuncSetAttribute failed for the split contraction"); return JTFS_EHIP; }
-    return JTFS_OK;
+    int rc = fwd_attributes<1>();
+    if (rc == JTFS_OK) rc = fwd_attributes<2>();
+    if (rc == JTFS_OK) rc = fwd_attributes<4>();
+    return rc;
+}
+
+template <int NTB, int NK = 1, typename... Args>
+static void launch_fwd_nk(int nk, dim3 grid, size_t lds, hipStream_t st, Args... args) {
+    if constexpr (NK <= kMaxFwdNK) {
+        if (nk == NK) hipLaunchKernelGGL((k_freq_fwd_h<NTB, NK>), grid, dim3(512), lds, st, args...);
+        else launch_fwd_nk<NTB, NK + 1>(nk, grid, lds, st, args...);
+    }
 }
 
 int launch_ysplit(const jtfs_plan* P, int a, const float2* Y2, const float* rowmax, unsigned short* Yh, float* yscale,
@@ -713,26 +873,34 @@ int launch_freq_fwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, c
     const unsigned short* Ya = Yh + s.yoff[a] * 4;
     const unsigned short* Ph = P->Phsp + s.phioff[a] * 2;
     const int slot0 = (int)s.vchoff[a];
+    const int nk = s.Kp / 16;
+    if (nk < 1 || nk > kMaxFwdNK) { set_error("K beyond the split contraction's LDS tile"); return JTFS_ENOTSUP; }
     switch (s.NTp / 32) {
-        case 1: hipLaunchKernelGGL(k_freq_fwd_h<1>, dim3(grid), dim3(512), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, P->Wsp, s.Kp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0); break;
-        case 2: hipLaunchKernelGGL(k_freq_fwd_h<2>, dim3(grid), dim3(512), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, P->Wsp, s.Kp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0); break;
-        case 4: hipLaunchKernelGGL(k_freq_fwd_h<4>, dim3(grid), dim3(512), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, P->Wsp, s.Kp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0); break;
+        case 1: launch_fwd_nk<1>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0); break;
+        case 2: launch_fwd_nk<2>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0); break;
+        case 4: launch_fwd_nk<4>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0); break;
         default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
     }
     return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
 }
 
 template <int NTB>
-static void launch_bwd_ni(int NI, dim3 grid, hipStream_t st, const unsigned short* Ya, int64_t yhb, int Tp, int nTt,
-                          int nU, const jtfs_plan* P, const unsigned short* PhT, float sphi, const float* gVa,
-                          int64_t gvb, const float* gvmax, const float* yscale, int a, float2* gYa, int64_t gyb) {
+static void launch_bwd_ni(int NI, int NK, dim3 grid, hipStream_t st, const unsigned short* Ya, int64_t yhb, int Tp,
+                          int nTt, int nU, const jtfs_plan* P, const unsigned short* PhT, float sphi,
+                          const float* gVa, int64_t gvb, const float* gvmax, const float* yscale, int a, float2* gYa,
+                          int64_t gyb) {
     const Shapes& s = P->s;
+    // NK = Kp / 16 k-steps is 2 NI - 1 or 2 NI (Kp is a multiple of 16, KpT = 32 NI)
 #define JTFS_BWD_CASE(ni)                                                                                      \
     case ni:                                                                                                   \
-        hipLaunchKernelGGL((k_freq_bwd_h<NTB, ni>), grid, dim3(256), 0, st, Ya,                               \
-                           yhb, Tp, nTt, nU, P->Wsp,                                                            \
-                           P->WTsp, s.Kp, s.Mp, PhT, sphi, gVa, gvb, gvmax, s.n_beta, yscale, a, s.n_alpha,    \
-                           P->sw, gYa, gyb);                                                                   \
+        if (NK == 2 * ni)                                                                                      \
+            hipLaunchKernelGGL((k_freq_bwd_h<NTB, ni, 2 * ni>), grid, dim3(256), 0, st, Ya, yhb, Tp, nTt, nU, \
+                               P->Wsp, P->WTsp, s.Mp, PhT, sphi, gVa, gvb, gvmax, s.n_beta, yscale, a,         \
+                               s.n_alpha, P->sw, gYa, gyb);                                                    \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_freq_bwd_h<NTB, ni, 2 * ni - 1>), grid, dim3(256), 0, st, Ya, yhb, Tp, nTt, \
+                               nU, P->Wsp, P->WTsp, s.Mp, PhT, sphi, gVa, gvb, gvmax, s.n_beta, yscale, a,     \
+                               s.n_alpha, P->sw, gYa, gyb);                                                    \
         break;
     // LDS 24 NI KB and one wave per SIMD without scratch: NI <= 6 at N/T <= 32, NI <= 5 at N/T = 64
     if constexpr (NTB == 1) {
@@ -765,8 +933,8 @@ int launch_freq_bwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, c
     const int64_t gvb = (int64_t)s.n_alpha * 2 * s.Mp * s.NTp;
     float2* gYa = gY2 + s.yoff[a];
     switch (s.NTp / 32) {
-        case 1: launch_bwd_ni<1>(NI, dim3(nU), st, Ya, yhb, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], gVa, gvb, gvmax, yscale, a, gYa, yb); break;
-        case 2: launch_bwd_ni<2>(NI, dim3(nU), st, Ya, yhb, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], gVa, gvb, gvmax, yscale, a, gYa, yb); break;
+        case 1: launch_bwd_ni<1>(NI, s.Kp / 16, dim3(nU), st, Ya, yhb, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], gVa, gvb, gvmax, yscale, a, gYa, yb); break;
+        case 2: launch_bwd_ni<2>(NI, s.Kp / 16, dim3(nU), st, Ya, yhb, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], gVa, gvb, gvmax, yscale, a, gYa, yb); break;
         default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
     }
     return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
