@@ -46,6 +46,14 @@ __device__ __forceinline__ C twiddle(const C* __restrict__ tw, int k, bool inv) 
     return w;
 }
 
+// Workgroup barrier that orders LDS only: it waits for this wave's LDS accesses
+// (not for its global loads and stores, which may stay in flight across it).
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Twiddles w^r, r = 1..R-1, of one radix-R butterfly, w = twiddle(tw, k, inv): w,
 // w^2 and w^4 come from the table, the others are products of those (at most
 // two roundings deep), so a radix-8 butterfly loads three twiddles, not seven.

@@ -259,6 +259,13 @@ __global__ void __launch_bounds__(1024) k_second_order(const float2* __restrict_
     const int r0 = blockIdx.x * rows;
     const int Ta = 1 << logTa;
     const int nr = min(rows, Kp - r0);
+    if (r0 >= n1) {
+        // padding rows lambda >= n1 only: zero rows (the contraction reads them), maxima 0
+        float2* out = Y + b * y_bstride + (int64_t)r0 * Tp;
+        for (int64_t e = threadIdx.x; e < (int64_t)nr * Tp; e += blockDim.x) out[e] = make_float2(0.f, 0.f);
+        if ((int)threadIdx.x < nr) rowmax[(b * n_alpha + alpha) * Kp + r0 + threadIdx.x] = 0.f;
+        return;
+    }
     if (threadIdx.x < 64) rmx[threadIdx.x] = 0u;
     for (int e = threadIdx.x; e < nr * Ta; e += blockDim.x) {
         const int c = e >> logTa, p = e & (Ta - 1);

@@ -4,6 +4,8 @@
 // 2^15, which an in-LDS complex transform could not hold).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "plan.hpp"
 #include "reg_fft.hpp"
 #include "regk.hpp"
@@ -169,8 +171,14 @@ __global__ void __launch_bounds__(512) k_second_order_r(const float2* __restrict
     const int logS = TWO ? logTa - 1 : logTa;
     float* A = xbuf;
     float* Bf = xbuf + (1 << logS);
-    if (threadIdx.x == 0) rmx = 0u;
     float2* out = Y + b * y_bstride + (int64_t)lam * Tp;
+    if (lam >= n1) {
+        // padding row: zeros (the contraction reads them), maximum 0
+        for (int t = threadIdx.x; t < Tp; t += blockDim.x) out[t] = make_float2(0.f, 0.f);
+        if (threadIdx.x == 0) rowmax[(b * n_alpha + alpha) * Kp + lam] = 0.f;
+        return;
+    }
+    if (threadIdx.x == 0) rmx = 0u;
     const float2* row = Xh + (b * n1 + (lam < n1 ? lam : 0)) * Xh_pitch;
     float m = 0.f;
     float2 v[kRegE];
@@ -317,14 +325,19 @@ int reg_attributes() {
 // rows of 2^14 points: one 512-thread register transform; 2^15: two of them
 static inline bool two_of(int logn) { return logn == kRegMinLog + 1; }
 static inline unsigned reg_threads() { return (unsigned)((1 << kRegMinLog) / kRegE); }
+// LDS of a long-row kernel: `floats` of its own use, and at least the padded
+// exchange buffer of one 2^14-point transform
+static inline size_t reg_lds(size_t floats) {
+    return sizeof(float) * std::max(floats, (size_t)reg_xbuf_floats(kRegMinLog));
+}
 
 void launch_scalogram_r(const jtfs_plan* P, const float2* xh, int64_t xh_pitch, float2* Xh, int64_t Xh_pitch,
                         int64_t B, hipStream_t st) {
     const Shapes& s = P->s;
     auto k = two_of(s.logNX) ? k_scalogram_r<true> : k_scalogram_r<false>;
-    hipLaunchKernelGGL(k, dim3(s.n1, (unsigned)B), dim3(reg_threads()), sizeof(float) * s.NX, st, xh, xh_pitch,
+    hipLaunchKernelGGL(k, dim3(s.n1, (unsigned)B), dim3(reg_threads()), reg_lds(s.NX), st, xh, xh_pitch,
                        P->psi1, P->band1, P->off1, Xh, Xh_pitch, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log);
-    // LDS: NX floats (exchange of one 2^14 transform, or the two staged halves at 2^15)
+    // LDS: NX floats (the two staged halves at 2^15), at least one padded exchange buffer
 }
 
 void launch_second_order_r(const jtfs_plan* P, int a, const float2* Xh, int64_t Xh_pitch, float2* Y2, float* rowmax,
@@ -333,7 +346,7 @@ void launch_second_order_r(const jtfs_plan* P, int a, const float2* Xh, int64_t 
     const int logTa = s.logNX - s.k2[a];
     const Family& f2 = s.f2;
     auto k = two_of(logTa) ? k_second_order_r<true> : k_second_order_r<false>;
-    hipLaunchKernelGGL(k, dim3(s.Kp, (unsigned)B), dim3(reg_threads()), sizeof(float) << (logTa == kRegMinLog ? kRegMinLog : kRegMinLog + 1), st, Xh, Xh_pitch,
+    hipLaunchKernelGGL(k, dim3(s.Kp, (unsigned)B), dim3(reg_threads()), reg_lds((size_t)1 << logTa), st, Xh, Xh_pitch,
                        s.n1, P->psi2 + f2.off[a], f2.lo[a], f2.hi[a], logTa, s.Tp[a], s.Kp, Y2 + s.yoff[a],
                        (int64_t)s.Kp * s.sumTp, 1.0f / (float)s.NX, P->tw, P->tw_log, rowmax, a, s.n_alpha);
 }
@@ -341,7 +354,7 @@ void launch_second_order_r(const jtfs_plan* P, int a, const float2* Xh, int64_t 
 void launch_rowfft_r(const jtfs_plan* P, float2* base, int64_t bs, int64_t rs, int rows, int logn, int64_t B,
                      hipStream_t st) {
     auto k = two_of(logn) ? k_rowfft_r<true> : k_rowfft_r<false>;
-    hipLaunchKernelGGL(k, dim3((unsigned)rows, (unsigned)B), dim3(reg_threads()), sizeof(float) << kRegMinLog, st,
+    hipLaunchKernelGGL(k, dim3((unsigned)rows, (unsigned)B), dim3(reg_threads()), reg_lds(0), st,
                        base, bs, rs, logn, P->tw, P->tw_log);
 }
 
@@ -349,7 +362,7 @@ void launch_scal_bwd_b_r(const jtfs_plan* P, const float2* xh, int64_t xh_pitch,
                          int64_t B, hipStream_t st) {
     const Shapes& s = P->s;
     auto k = two_of(s.logNX) ? k_scal_bwd_b_r<true> : k_scal_bwd_b_r<false>;
-    hipLaunchKernelGGL(k, dim3(s.n1, (unsigned)B), dim3(reg_threads()), sizeof(float) * s.NX, st, xh,
+    hipLaunchKernelGGL(k, dim3(s.n1, (unsigned)B), dim3(reg_threads()), reg_lds(s.NX), st, xh,
                        xh_pitch, P->psi1, P->band1, P->off1, gX, g1, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log);
 }
 

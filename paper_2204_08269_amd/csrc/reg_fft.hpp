@@ -3,8 +3,8 @@
 // Each of the T = blockDim.x threads holds E = n / T complex values.  Passes are
 // Stockham radix-8 (then one radix-4 or radix-2 pass); between passes the values
 // move to the thread that needs them through LDS, the real parts first and the
-// imaginary parts second, so the exchange buffer holds only n floats (half of an
-// in-LDS complex transform).  Unnormalised in both directions; twiddles from the
+// imaginary parts second, so the exchange buffer holds only n floats plus one pad
+// float per eight (a little over half of an in-LDS complex transform).  Unnormalised in both directions; twiddles from the
 // FP64-generated table tw[k] = exp(-2 pi i k / 2^tw_log).
 #pragma once
 
@@ -82,25 +82,36 @@ __device__ __forceinline__ void reg_butterflies(float2 (&v)[E], int lNs, const f
     }
 }
 
+// Exchange-buffer slot of position i: one unused float after every eight.  The
+// stores of the first passes go to positions R apart across the lanes (R = 8);
+// with the pad those become 9 floats apart, an odd stride, so that consecutive
+// lanes fall into distinct LDS banks.  Contiguous reads gain at most a 2-way
+// conflict where a run crosses a pad.
+__device__ __forceinline__ int xpad(int i) { return i + (i >> 3); }
+
+// floats of exchange buffer that reg_fft needs for 2^logn points
+constexpr int reg_xbuf_floats(int logn) { return (1 << logn) + (1 << (logn - 3)); }
+
 // Move the outputs of a radix-2^LR pass (sub-length 2^lNs) to the inputs of the
-// next pass (radix 2^LR2) through `x` (n floats): real parts, then imaginary.
+// next pass (radix 2^LR2) through `x` (reg_xbuf_floats(logn) floats): real
+// parts, then imaginary.
 template <int LR, int LR2, int E>
 __device__ __forceinline__ void reg_exchange(float2 (&v)[E], float* x, int logn, int lNs) {
-    __syncthreads();
+    lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) x[reg_out_pos<LR>(e, lNs)] = v[e].x;
-    __syncthreads();
+    for (int e = 0; e < E; ++e) x[xpad(reg_out_pos<LR>(e, lNs))] = v[e].x;
+    lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e].x = x[reg_in_pos<LR2>(e, logn)];
-    __syncthreads();
+    for (int e = 0; e < E; ++e) v[e].x = x[xpad(reg_in_pos<LR2>(e, logn))];
+    lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) x[reg_out_pos<LR>(e, lNs)] = v[e].y;
-    __syncthreads();
+    for (int e = 0; e < E; ++e) x[xpad(reg_out_pos<LR>(e, lNs))] = v[e].y;
+    lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e].y = x[reg_in_pos<LR2>(e, logn)];
+    for (int e = 0; e < E; ++e) v[e].y = x[xpad(reg_in_pos<LR2>(e, logn))];
 }
 
-// Full transform.  On entry element e of the thread holds the input at
+// Full transform (x: reg_xbuf_floats(logn) floats of LDS).  On entry element e of the thread holds the input at
 // reg_in_pos<first radix>(e) (use reg_input_pos below); on exit it holds the
 // output at reg_output_pos(e, logn).  Needs 2^logn = E * blockDim.x and logn >= 6.
 template <int E>
