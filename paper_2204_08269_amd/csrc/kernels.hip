@@ -385,37 +385,66 @@ __global__ void __launch_bounds__(256) k_freq_fwd(const float2* __restrict__ Y, 
 
 // S2[b][alpha][beta][theta][m][tau] = sum_l PF_beta[m][l] V[theta][rowoff+l][tau],
 // V = sum over the partial slots.  grid (n_beta, 2, B).
+// Frequency lowpass (eq. (3)): sum the partial V of the block's t-chunks, then
+// S2[m][tau] = sum_l PF[m][l] V[l][tau] per (beta, spin).  With stage_pf the
+// matrix PF (NL x Lb) is held in LDS transposed, and each thread forms four
+// outputs m..m+3 of one tau from one read of V[l][tau] and one 16-byte read of PF.
 __global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, int64_t vp_bstride, int slot0,
                                                 int nslots, int nlt, int NTp, int NT, const float* __restrict__ PFall,
                                                 const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
                                                 const int* __restrict__ rowoffv, int NL, int alpha, int n_alpha,
-                                                float* __restrict__ S2) {
-    extern __shared__ float Vs[];   // [Lb][33]
+                                                int stage_pf, float* __restrict__ S2) {
+    extern __shared__ float Vs[];   // [Lb][33], then (stage_pf) Pt [Lb][NL] at a 16-byte boundary
     const int beta = blockIdx.x, th = blockIdx.y, n_beta = gridDim.x;
     const int64_t b = blockIdx.z;
     const int Lb = Lbv[beta], ro = rowoffv[beta];
     const float* PF = PFall + pfoff[beta];
     const float* Vb = Vp + b * vp_bstride;
     float* o = S2 + ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NL) * (int64_t)NT;
+    float* Pt = Vs + ((Lb * 33 + 3) & ~3);
+    const bool vec = stage_pf && (NL & 3) == 0;
+    if (stage_pf)
+        for (int e = threadIdx.x; e < NL * Lb; e += blockDim.x) {
+            const int l = e / NL, m = e - l * NL;
+            Pt[e] = PF[m * Lb + l];
+        }
+    const int tau = threadIdx.x & 31, grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
     for (int tb = 0; tb < NT; tb += 32) {
         for (int e = threadIdx.x; e < Lb * 32; e += blockDim.x) {
-            const int tau = e / Lb, l = e - tau * Lb;
+            const int tt = e / Lb, l = e - tt * Lb;
             const int row = ro + l, lt = row / kTileL, lr = row % kTileL;
             float acc = 0.f;
-            if (tb + tau < NT) {
+            if (tb + tt < NT) {
                 for (int sl = 0; sl < nslots; ++sl)
                     acc += Vb[(((int64_t)(slot0 + sl) * nlt + lt) * 2 + th) * NTp * kTileL +
-                              (int64_t)(tb + tau) * kTileL + lr];
+                              (int64_t)(tb + tt) * kTileL + lr];
             }
-            Vs[l * 33 + tau] = acc;
+            Vs[l * 33 + tt] = acc;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < NL * 32; e += blockDim.x) {
-            const int m = e / 32, tau = e % 32;
-            if (tb + tau >= NT) continue;
-            float acc = 0.f;
-            for (int l = 0; l < Lb; ++l) acc += PF[m * Lb + l] * Vs[l * 33 + tau];
-            o[(int64_t)m * NT + tb + tau] = acc;
+        if (tb + tau < NT) {
+            for (int m0 = 4 * grp; m0 < NL; m0 += 4 * ngrp) {
+                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+                if (vec) {
+                    for (int l = 0; l < Lb; ++l) {
+                        const float v = Vs[l * 33 + tau];
+                        const float4 p = *(const float4*)(Pt + l * NL + m0);
+                        a0 += p.x * v; a1 += p.y * v; a2 += p.z * v; a3 += p.w * v;
+                    }
+                } else {
+                    for (int l = 0; l < Lb; ++l) {
+                        const float v = Vs[l * 33 + tau];
+                        a0 += PF[m0 * Lb + l] * v;
+                        if (m0 + 1 < NL) a1 += PF[(m0 + 1) * Lb + l] * v;
+                        if (m0 + 2 < NL) a2 += PF[(m0 + 2) * Lb + l] * v;
+                        if (m0 + 3 < NL) a3 += PF[(m0 + 3) * Lb + l] * v;
+                    }
+                }
+                o[(int64_t)m0 * NT + tb + tau] = a0;
+                if (m0 + 1 < NL) o[(int64_t)(m0 + 1) * NT + tb + tau] = a1;
+                if (m0 + 2 < NL) o[(int64_t)(m0 + 2) * NT + tb + tau] = a2;
+                if (m0 + 3 < NL) o[(int64_t)(m0 + 3) * NT + tb + tau] = a3;
+            }
         }
         __syncthreads();
     }
@@ -512,12 +541,17 @@ __global__ void __launch_bounds__(256) k_ts_bwd(const float2* __restrict__ Y, in
 // itself; block n_beta zeroes the padding rows.
 // Also writes, per (signal, alpha, spin, beta), the largest row sum over tau of
 // |gV| (a bound used to scale the split backward contraction).
+// Adjoint of the frequency lowpass: gV[l][tau] = sum_m PF[m][l] gS2[m][tau] (or
+// gS2 itself without frequential averaging), with the per-row sums of |gV| whose
+// maximum sets the split scale of the backward contraction.  The gS2 tile and,
+// with stage_pf, PF are held in LDS; row sums are reduced across the lanes of a
+// row before one LDS atomic per row segment.
 __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, const float* __restrict__ PFall,
                                                 const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
                                                 const int* __restrict__ rowoffv, int n_beta, int NL, int NT, int NTp,
-                                                int Mh, int Mp, int alpha, int n_alpha, int avg,
+                                                int Mh, int Mp, int alpha, int n_alpha, int avg, int stage_pf,
                                                 float* __restrict__ gV, float* __restrict__ gvmax) {
-    __shared__ float rowsum[512];
+    extern __shared__ float sm[];      // rowsum [Lb] | gS2 tile [NL][NT] | (stage_pf) PF [NL][Lb]
     const int beta = blockIdx.x, th = blockIdx.y;
     const int64_t b = blockIdx.z;
     float* g = gV + (((b * n_alpha + alpha) * 2 + th) * (int64_t)Mp) * NTp;
@@ -526,23 +560,38 @@ __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, c
         return;
     }
     const int Lb = Lbv[beta], ro = rowoffv[beta];
-    for (int l = threadIdx.x; l < Lb; l += blockDim.x) rowsum[l] = 0.f;
-    __syncthreads();
+    float* rowsum = sm;
+    float* st = sm + Lb;
+    float* pf = st + NL * NT;
     const float* PF = PFall + pfoff[beta];
     const float* src = !gS2 ? nullptr
                        : avg ? gS2 + ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NL) * (int64_t)NT
                              : gS2 + ((b * n_alpha + alpha) * 2 * (int64_t)Mh + 2 * ro + th * Lb) * NT;
-    for (int e = threadIdx.x; e < Lb * NTp; e += blockDim.x) {
+    for (int l = threadIdx.x; l < Lb; l += blockDim.x) rowsum[l] = 0.f;
+    if (src && avg) {
+        for (int e = threadIdx.x; e < NL * NT; e += blockDim.x) st[e] = src[e];
+        if (stage_pf)
+            for (int e = threadIdx.x; e < NL * Lb; e += blockDim.x) pf[e] = PF[e];
+    }
+    __syncthreads();
+    const int width = NTp < 64 ? NTp : 64;           // lanes of one row segment within a wave
+    for (int e0 = 0; e0 < Lb * NTp; e0 += blockDim.x) {
+        const int e = e0 + (int)threadIdx.x;
+        const bool valid = e < Lb * NTp;
         const int l = e / NTp, tau = e - l * NTp;
         float acc = 0.f;
-        if (src && tau < NT) {
-            if (avg)
-                for (int m = 0; m < NL; ++m) acc += PF[m * Lb + l] * src[(int64_t)m * NT + tau];
-            else
+        if (valid && src && tau < NT) {
+            if (avg) {
+                const float* pc = stage_pf ? pf + l : PF + l;
+                for (int m = 0; m < NL; ++m) acc += pc[m * Lb] * st[m * NT + tau];
+            } else {
                 acc = src[(int64_t)l * NT + tau];
+            }
         }
-        g[(int64_t)(ro + l) * NTp + tau] = acc;
-        atomicAdd(&rowsum[l], fabsf(acc));
+        if (valid) g[(int64_t)(ro + l) * NTp + tau] = acc;
+        float a = fabsf(acc);
+        for (int w = width >> 1; w > 0; w >>= 1) a += __shfl_xor(a, w);
+        if (valid && (tau & (width - 1)) == 0) atomicAdd(&rowsum[l], a);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -796,6 +845,20 @@ __global__ void __launch_bounds__(256) k_band_accum(const float2* __restrict__ g
 // ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
+// LDS of the frequency lowpass and its adjoint: V tile (or row sums and the gS2
+// tile), and the PF matrix when all of it fits kS2LdsCap (then held in LDS)
+constexpr size_t kS2LdsCap = 96 * 1024;
+static size_t s2_out_floats(const Shapes& s, bool stage) {
+    return (size_t)((s.L * 33 + 3) & ~3) + (stage ? (size_t)s.L * s.NL : 0);
+}
+static int s2_out_stage(const Shapes& s) { return sizeof(float) * s2_out_floats(s, true) <= kS2LdsCap ? 1 : 0; }
+static size_t s2_out_lds(const Shapes& s) { return sizeof(float) * s2_out_floats(s, s2_out_stage(s)); }
+static size_t s2_bwd_floats(const Shapes& s, bool stage) {
+    return (size_t)s.L + (size_t)s.NL * s.NT + (stage ? (size_t)s.NL * s.L : 0);
+}
+static int s2_bwd_stage(const Shapes& s) { return sizeof(float) * s2_bwd_floats(s, true) <= kS2LdsCap ? 1 : 0; }
+static size_t s2_bwd_lds(const Shapes& s) { return sizeof(float) * s2_bwd_floats(s, s2_bwd_stage(s)); }
+
 static bool g_attr_done = false;
 
 int setup_kernel_attributes() {
@@ -803,7 +866,8 @@ int setup_kernel_attributes() {
     const int lds = kMaxDynLds;
     const void* ks[] = {(const void*)k_fft_cols_t<float2, float2>, (const void*)k_fft_cols_t<float2, double2>,
                         (const void*)k_fft_cols_t<double2, double2>, (const void*)k_scalogram, (const void*)k_s1, (const void*)k_s2_out,
-                        (const void*)k_second_order, (const void*)k_scal_bwd_a, (const void*)k_scal_bwd_b};
+                        (const void*)k_s2_bwd, (const void*)k_second_order, (const void*)k_scal_bwd_a,
+                        (const void*)k_scal_bwd_b};
     for (const void* k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) {
@@ -994,8 +1058,8 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
         JTFS_TIMED(JTFS_STAGE_FREQ_FWD, st, rc = launch_freq_fwd_split(P, a, Yh, ysc, Vp, w.vp_bstride, B, st));
         if (rc != JTFS_OK) { if (rc == JTFS_EHIP) set_error("split contraction launch failed"); return rc; }
         if (s.avg_fr) {
-            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), sizeof(float) * 33 * s.L, st, Vp, w.vp_bstride, (int)s.vchoff[a],
-                               s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2));
+            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), s2_out_lds(s), st, Vp, w.vp_bstride, (int)s.vchoff[a],
+                               s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2_out_stage(s), s2));
         } else {
             JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_v_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), 0, st, Vp, w.vp_bstride, (int)s.vchoff[a],
                                s.nch[a], nlt, s.NTp, s.NT, P->d_Lb, P->d_rowoff, s.Mh, a, s.n_alpha, s2));
@@ -1019,8 +1083,8 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
         LAUNCHCHK("frequential contraction");
         }
         if (s.avg_fr) {
-            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), sizeof(float) * 33 * s.L, st, Vp, w.vp_bstride, slot0,
-                               2 * s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2));
+            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), s2_out_lds(s), st, Vp, w.vp_bstride, slot0,
+                               2 * s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2_out_stage(s), s2));
         } else {
             JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_v_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), 0, st, Vp, w.vp_bstride, slot0,
                                2 * s.nch[a], nlt, s.NTp, s.NT, P->d_Lb, P->d_rowoff, s.Mh, a, s.n_alpha, s2));
@@ -1081,9 +1145,9 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
         if (rc != JTFS_OK) return rc;
     }
     for (int a = 0; a < s.n_alpha && !s.tscat; ++a) {
-        JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_s2_bwd, dim3(s.n_beta + 1, 2, (unsigned)B), dim3(256), 0, st, gs2, P->PF, P->d_pfoff, P->d_Lb,
-                           P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, a, s.n_alpha, (int)s.avg_fr, gV,
-                           (float*)(base + w.gvmax)));
+        JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_s2_bwd, dim3(s.n_beta + 1, 2, (unsigned)B), dim3(256), s2_bwd_lds(s), st, gs2, P->PF, P->d_pfoff, P->d_Lb,
+                           P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, a, s.n_alpha, (int)s.avg_fr,
+                           s2_bwd_stage(s), gV, (float*)(base + w.gvmax)));
         LAUNCHCHK("frequency lowpass adjoint");
     }
     const bool split = P->contraction == JTFS_CONTRACTION_SPLIT_F16 && P->split_bwd_ok && !s.tscat;
