@@ -186,7 +186,8 @@ __global__ void __launch_bounds__(1024) k_scalogram(const float2* __restrict__ x
             const int k = threadIdx.x + q * blockDim.x;
             if (k < H) {
                 const float2 a = s[2 * k], c = s[2 * k + 1];
-                v[q] = make_float2(sqrtf(a.x * a.x + a.y * a.y) * invN, sqrtf(c.x * c.x + c.y * c.y) * invN);
+                v[q] = make_float2(__builtin_amdgcn_sqrtf(a.x * a.x + a.y * a.y) * invN,
+                                   __builtin_amdgcn_sqrtf(c.x * c.x + c.y * c.y) * invN);
             }
         }
         __syncthreads();
@@ -807,7 +808,7 @@ __global__ void __launch_bounds__(1024) k_scal_bwd_b(const float2* __restrict__ 
     const float* gx = gX + (b * n1 + lam) * (int64_t)NX;
     for (int n = threadIdx.x; n < NX; n += blockDim.x) {
         const float2 y = cscale(s[n], invN);
-        const float sc = gx[n] / fmaxf(sqrtf(y.x * y.x + y.y * y.y), kEpsMod);
+        const float sc = gx[n] * __builtin_amdgcn_rcpf(fmaxf(__builtin_amdgcn_sqrtf(y.x * y.x + y.y * y.y), kEpsMod));
         s[n] = cscale(y, sc);
     }
     __syncthreads();

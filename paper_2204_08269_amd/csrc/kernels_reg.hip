@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(512) k_scalogram_r(const float2* __restrict__ 
         load_dif<true>(v, A, Bf, src, ps, lo, hi, logNX, 0, tw, tw_log, false);
         reg_fft<kRegE>(v, A, logS, tw, tw_log, true);
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e) even[e] = sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN;   // X[2 pos]
+        for (int e = 0; e < kRegE; ++e) even[e] = __builtin_amdgcn_sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN;   // X[2 pos]
         load_dif<true>(v, A, Bf, src, ps, lo, hi, logNX, 1, tw, tw_log, false);
         reg_fft<kRegE>(v, A, logS, tw, tw_log, true);
         __syncthreads();
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(512) k_scalogram_r(const float2* __restrict__ 
         for (int e = 0; e < kRegE; ++e) {
             const int pos = reg_output_pos(e, logS);
             xbuf[pos] = even[e];                                              // X[2 pos]
-            xbuf[H + pos] = sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN; // X[2 pos + 1]
+            xbuf[H + pos] = __builtin_amdgcn_sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN; // X[2 pos + 1]
         }
     } else {
         // the whole row fits one register transform; the exchange buffer is NX floats
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(512) k_scalogram_r(const float2* __restrict__ 
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
             const int pos = reg_output_pos(e, logNX);
-            xbuf[(pos & 1) * H + (pos >> 1)] = sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN;
+            xbuf[(pos & 1) * H + (pos >> 1)] = __builtin_amdgcn_sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN;
         }
     }
     __syncthreads();
@@ -279,7 +279,8 @@ __global__ void __launch_bounds__(512) k_scal_bwd_b_r(const float2* __restrict__
         for (int e = 0; e < kRegE; ++e) {
             const float2 y = cscale(v[e], invN);
             const int pos = reg_output_pos(e, logS);
-            const float sc = gx[TWO ? 2 * pos + half : pos] / fmaxf(sqrtf(y.x * y.x + y.y * y.y), kEpsMod);
+            const float sc = gx[TWO ? 2 * pos + half : pos] *
+                             __builtin_amdgcn_rcpf(fmaxf(__builtin_amdgcn_sqrtf(y.x * y.x + y.y * y.y), kEpsMod));
             v[e] = cscale(y, sc);
         }
         // from the last pass's output layout to the first pass's input layout

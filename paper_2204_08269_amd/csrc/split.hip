@@ -346,12 +346,12 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
             for (int r = 0; r < 16; ++r) {
                 const float zr = spin ? rr[r] + ii[r] : rr[r] - ii[r];
                 const float zi = spin ? ir[r] - ri[r] : ir[r] + ri[r];
-                uval[r] = sqrtf(zr * zr + zi * zi);
+                uval[r] = __builtin_amdgcn_sqrtf(zr * zr + zi * zi);   // hardware square root (1 ulp)
                 m = fmaxf(m, uval[r]);
             }
             m = fmaxf(m, __shfl_xor(m, 32));
-            const float su = pow2_scale(m);
-            const float inv_su = 1.f / su;
+            const int se = pow2_exp(m);
+            const float su = ldexpf(1.f, se), inv_su = ldexpf(1.f, -se);
             half8 uh[2], ul[2];
 #pragma unroll
             for (int s = 0; s < 2; ++s)
