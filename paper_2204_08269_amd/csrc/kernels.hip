@@ -154,6 +154,30 @@ __global__ void k_irfft_pack(const float2* __restrict__ xh, int64_t pitch, float
 __device__ __forceinline__ void fold_band(float2* s, const float2* __restrict__ src, const float* __restrict__ ps, int lo,
                                           int hi, int logM) {
     const int M = 1 << logM;
+    if (hi - lo < M && M <= 16 * (int)blockDim.x) {
+        // every bin receives at most one band sample: all of a thread's loads are
+        // issued before any product is formed
+        // (two rounds of eight keep the kernels within 64 VGPRs)
+#pragma unroll
+        for (int q0 = 0; q0 < 16; q0 += 8) {
+            float2 v[8];
+            float g[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int p = threadIdx.x + (q0 + q) * blockDim.x;
+                const int m = lo + ((p - lo) & (M - 1));
+                const bool ok = p < M && m <= hi;
+                v[q] = ok ? src[m] : make_float2(0.f, 0.f);
+                g[q] = ok ? ps[m - lo] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int p = threadIdx.x + (q0 + q) * blockDim.x;
+                if (p < M) s[p] = make_float2(v[q].x * g[q], v[q].y * g[q]);
+            }
+        }
+        return;
+    }
     for (int p = threadIdx.x; p < M; p += blockDim.x) {
         float2 acc = make_float2(0.f, 0.f);
         for (int m = lo + ((p - lo) & (M - 1)); m <= hi; m += M) {
@@ -166,7 +190,7 @@ __device__ __forceinline__ void fold_band(float2* s, const float2* __restrict__ 
     }
 }
 
-__global__ void __launch_bounds__(1024) k_scalogram(const float2* __restrict__ xh, int64_t xh_pitch,
+__global__ void __launch_bounds__(1024, 8) k_scalogram(const float2* __restrict__ xh, int64_t xh_pitch,
                                                    const float* __restrict__ psi1, const int* __restrict__ band1,
                                                    const int64_t* __restrict__ off1, float2* __restrict__ Xh,
                                                    int64_t Xh_pitch, int logNX, float invN,
@@ -268,20 +292,45 @@ __global__ void __launch_bounds__(1024) k_second_order(const float2* __restrict_
         return;
     }
     if (threadIdx.x < 64) rmx[threadIdx.x] = 0u;
-    for (int e = threadIdx.x; e < nr * Ta; e += blockDim.x) {
-        const int c = e >> logTa, p = e & (Ta - 1);
-        const int lam = r0 + c;
-        float2 acc = make_float2(0.f, 0.f);
-        if (lam < n1) {
-            const float2* row = Xh + (b * n1 + lam) * Xh_pitch;
-            for (int m = lo + ((p - lo) & (Ta - 1)); m <= hi; m += Ta) {
-                const float2 v = row[m];
-                const float g = ps[m - lo];
-                acc.x += v.x * g;
-                acc.y += v.y * g;
+    if (hi - lo < Ta && nr * Ta <= 16 * (int)blockDim.x) {
+        // every bin receives at most one band sample: all of a thread's loads are
+        // issued before any product is formed
+#pragma unroll
+        for (int q0 = 0; q0 < 16; q0 += 8) {
+            float2 v[8];
+            float g[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = threadIdx.x + (q0 + q) * blockDim.x;
+                const int c = e >> logTa, p = e & (Ta - 1);
+                const int lam = r0 + c;
+                const int m = lo + ((p - lo) & (Ta - 1));
+                const bool ok = e < nr * Ta && lam < n1 && m <= hi;
+                v[q] = ok ? Xh[(b * n1 + lam) * Xh_pitch + m] : make_float2(0.f, 0.f);
+                g[q] = ok ? ps[m - lo] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = threadIdx.x + (q0 + q) * blockDim.x;
+                if (e < nr * Ta) s[e] = make_float2(v[q].x * g[q], v[q].y * g[q]);
             }
         }
-        s[e] = acc;
+    } else {
+        for (int e = threadIdx.x; e < nr * Ta; e += blockDim.x) {
+            const int c = e >> logTa, p = e & (Ta - 1);
+            const int lam = r0 + c;
+            float2 acc = make_float2(0.f, 0.f);
+            if (lam < n1) {
+                const float2* row = Xh + (b * n1 + lam) * Xh_pitch;
+                for (int m = lo + ((p - lo) & (Ta - 1)); m <= hi; m += Ta) {
+                    const float2 v = row[m];
+                    const float g = ps[m - lo];
+                    acc.x += v.x * g;
+                    acc.y += v.y * g;
+                }
+            }
+            s[e] = acc;
+        }
     }
     __syncthreads();
     lds_fft<16>(s, logTa, nr, Ta, tw, tw_log, true);
@@ -732,7 +781,7 @@ __global__ void __launch_bounds__(256) k_bwd_gy(const float2* __restrict__ PQ, i
 //        + phi_hat[m] G1[m mod NT],
 // G_alpha = FFT of gY2 rows (done beforehand), G1 = FFT of gS1 row, then the
 // real inverse FFT gives gX[b][lambda][0..NX) (scaled 1/NX).
-__global__ void __launch_bounds__(1024) k_scal_bwd_a(const float2* __restrict__ G, int64_t y_bstride,
+__global__ void __launch_bounds__(1024, 8) k_scal_bwd_a(const float2* __restrict__ G, int64_t y_bstride,
                                                     const int64_t* __restrict__ yoff, const int* __restrict__ Tpv,
                                                     const int* __restrict__ Tav, const float* __restrict__ psi2,
                                                     const int* __restrict__ band2, const int64_t* __restrict__ off2,
@@ -748,23 +797,40 @@ __global__ void __launch_bounds__(1024) k_scal_bwd_a(const float2* __restrict__ 
         g1[t] = make_float2(gS1 ? gS1[(b * n1 + lam) * NT + t] : 0.f, 0.f);
     __syncthreads();
     lds_fft<16>(g1, logNT, 1, NT, tw, tw_log, false);
-    for (int m = threadIdx.x; m <= H; m += blockDim.x) {
-        float2 c = make_float2(0.f, 0.f);
+    // bins m = m0 + tid + q blockDim, q < 5: the temporal rates in the outer loop,
+    // so that a rate's loads for all of a thread's bins issue together
+    for (int m0 = 0; m0 <= H; m0 += 5 * (int)blockDim.x) {
+        float2 c[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) c[q] = make_float2(0.f, 0.f);
         for (int a = 0; a < n_alpha; ++a) {
             const int lo = band2[2 * a], hi = band2[2 * a + 1];
-            if (m < lo || m > hi) continue;
-            const float g = psi2[off2[a] + m - lo];
-            const float2 v = G[b * y_bstride + yoff[a] + (int64_t)lam * Tpv[a] + (m & (Tav[a] - 1))];
-            c.x += g * v.x;
-            c.y += g * v.y;
+            const float* pa = psi2 + off2[a] - lo;
+            const float2* ga = G + b * y_bstride + yoff[a] + (int64_t)lam * Tpv[a];
+            const int tmask = Tav[a] - 1;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const int m = m0 + threadIdx.x + q * blockDim.x;
+                if (m >= lo && m <= hi) {
+                    const float g = pa[m];
+                    const float2 v = ga[m & tmask];
+                    c[q].x += g * v.x;
+                    c[q].y += g * v.y;
+                }
+            }
         }
-        float2 hm = (m == 0 || m == H) ? make_float2(c.x, 0.f) : cscale(c, 0.5f);
-        if (m <= Mphi) {
-            const float2 v = g1[m & (NT - 1)];
-            hm.x += phiX[m] * v.x;
-            hm.y += phiX[m] * v.y;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const int m = m0 + threadIdx.x + q * blockDim.x;
+            if (m > H) continue;
+            float2 hm = (m == 0 || m == H) ? make_float2(c[q].x, 0.f) : cscale(c[q], 0.5f);
+            if (m <= Mphi) {
+                const float2 v = g1[m & (NT - 1)];
+                hm.x += phiX[m] * v.x;
+                hm.y += phiX[m] * v.y;
+            }
+            s[m] = hm;
         }
-        s[m] = hm;
     }
     __syncthreads();
     const int tws = tw_log - logNX;
@@ -793,7 +859,7 @@ __global__ void __launch_bounds__(1024) k_scal_bwd_a(const float2* __restrict__ 
 // Adjoint of the modulus and of the first-order filter for one row: recompute the
 // scalogram-rate filtered signal y, gY1 = gX y / max(|y|, eps), and its FFT
 // (the spectrum that the decimation adjoint replicates): g1[b][lambda][0..NX).
-__global__ void __launch_bounds__(1024) k_scal_bwd_b(const float2* __restrict__ xh, int64_t xh_pitch,
+__global__ void __launch_bounds__(1024, 8) k_scal_bwd_b(const float2* __restrict__ xh, int64_t xh_pitch,
                                                     const float* __restrict__ psi1, const int* __restrict__ band1,
                                                     const int64_t* __restrict__ off1, const float* __restrict__ gX,
                                                     float2* __restrict__ g1, int logNX, float invN,

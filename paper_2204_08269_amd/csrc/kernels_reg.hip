@@ -28,6 +28,34 @@ __device__ __forceinline__ float2 fold_at(const float2* __restrict__ src, const 
     return acc;
 }
 
+// The thread's inputs of a register transform of 2^logM points (input layout
+// of reg_fft), folded from src * ps over [lo, hi].  When the band fits the row
+// every bin receives at most one band sample, and the loads go out four
+// elements at a time with no loop between them.
+__device__ __forceinline__ void fold_inputs(float2 (&v)[kRegE], const float2* __restrict__ src,
+                                            const float* __restrict__ ps, int lo, int hi, int logM) {
+    const int M = 1 << logM;
+    if (hi - lo < M) {
+#pragma unroll
+        for (int e0 = 0; e0 < kRegE; e0 += 4) {
+            float g[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int p = reg_input_pos(e0 + q, logM);
+                const int m = lo + ((p - lo) & (M - 1));
+                const bool ok = m <= hi;
+                v[e0 + q] = ok ? src[m] : make_float2(0.f, 0.f);
+                g[q] = ok ? ps[m - lo] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[e0 + q] = cscale(v[e0 + q], g[q]);
+        }
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < kRegE; ++e) v[e] = fold_at(src, ps, lo, hi, logM, reg_input_pos(e, logM));
+}
+
 // Rows of 2^15 points run as two 2^14-point register transforms:
 //  inverse (decimation in frequency):  y[2k] = IDFT_m(u[p] + u[p+m])[k],
 //                                      y[2k+1] = IDFT_m((u[p] - u[p+m]) e^{+2 pi i p/n})[k];
@@ -45,9 +73,12 @@ __device__ __forceinline__ void load_dif(float2 (&v)[kRegE], float* A, float* B,
                                          const float2* __restrict__ tw, int tw_log, bool zero) {
     if constexpr (!TWO) {
         // no staging: each thread folds its own inputs
+        if (zero) {
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e)
-            v[e] = zero ? make_float2(0.f, 0.f) : fold_at(src, ps, lo, hi, logn, reg_input_pos(e, logn));
+            for (int e = 0; e < kRegE; ++e) v[e] = make_float2(0.f, 0.f);
+        } else {
+            fold_inputs(v, src, ps, lo, hi, logn);
+        }
         return;
     }
     const int logS = logn - 1;
@@ -111,8 +142,7 @@ __global__ void __launch_bounds__(512) k_scalogram_r(const float2* __restrict__ 
     } else {
         // the whole row fits one register transform; the exchange buffer is NX floats
         __syncthreads();
-#pragma unroll
-        for (int e = 0; e < kRegE; ++e) v[e] = fold_at(src, ps, lo, hi, logNX, reg_input_pos(e, logNX));
+        fold_inputs(v, src, ps, lo, hi, logNX);
         reg_fft<kRegE>(v, xbuf, logNX, tw, tw_log, true);
         __syncthreads();
 #pragma unroll
@@ -271,8 +301,7 @@ __global__ void __launch_bounds__(512) k_scal_bwd_b_r(const float2* __restrict__
         if (TWO) {
             load_dif<true>(v, A, Bf, src, ps, lo, hi, logNX, half, tw, tw_log, false);
         } else {
-#pragma unroll
-            for (int e = 0; e < kRegE; ++e) v[e] = fold_at(src, ps, lo, hi, logNX, reg_input_pos(e, logNX));
+            fold_inputs(v, src, ps, lo, hi, logNX);
         }
         reg_fft<kRegE>(v, A, logS, tw, tw_log, true);
 #pragma unroll
