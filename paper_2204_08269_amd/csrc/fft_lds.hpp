@@ -46,6 +46,15 @@ __device__ __forceinline__ C twiddle(const C* __restrict__ tw, int k, bool inv) 
     return w;
 }
 
+// LDS slot of element j of one transform: one unused element after every eight,
+// so that the strided stores of the first passes (8 and 64 elements apart across
+// the lanes) fall into distinct banks; contiguous runs gain at most a 2-way
+// conflict where they cross a pad.  Every kernel that fills or reads an LDS
+// transform buffer indexes it through lpad.
+__device__ __forceinline__ int lpad(int j) { return j + (j >> 3); }
+// slots one transform of n points occupies
+constexpr int lpad_len(int n) { return n + (n >> 3); }
+
 // Workgroup barrier that orders LDS only: it waits for this wave's LDS accesses
 // (not for its global loads and stores, which may stay in flight across it).
 __device__ __forceinline__ void lds_sync() {
@@ -110,7 +119,7 @@ __device__ __forceinline__ void fft_pass(C* s, int logn, int count, int stride, 
             butterfly_twiddles<R>(w, tw, k << tws, inv);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                C a = src[j + (r << nb_log)];
+                C a = src[lpad(j + (r << nb_log))];
                 if (r) a = cmul(a, w[r]);
                 v[q][r] = a;
             }
@@ -156,15 +165,16 @@ __device__ __forceinline__ void fft_pass(C* s, int logn, int count, int stride, 
             C* dst = s + t * stride;
             const int idx = ((j >> lNs) << (lNs + LR)) + (j & (Ns - 1));
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[idx + r * Ns] = v[q][r];
+            for (int r = 0; r < R; ++r) dst[lpad(idx + r * Ns)] = v[q][r];
         }
     }
     __syncthreads();
 }
 
-// count transforms of length 2^logn at s + t*stride, all threads of the block
-// taking part; count * 2^logn <= MAXE * blockDim.x.  Starts and ends with the
-// data in LDS; the caller must __syncthreads() before calling.
+// count transforms of length 2^logn at s + t*stride (element j of a transform at
+// slot lpad(j); stride >= lpad_len(2^logn)), all threads of the block taking
+// part; count * 2^logn <= MAXE * blockDim.x.  Starts and ends with the data in
+// LDS; the caller must __syncthreads() before calling.
 template <int MAXE, typename C>
 __device__ __forceinline__ void lds_fft(C* s, int logn, int count, int stride, const C* __restrict__ tw,
                         int tw_log, bool inv) {

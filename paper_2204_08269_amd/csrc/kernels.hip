@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(1024) k_fft_cols_t(const CI* in, C* out, int l
                                                     typename cplx<C>::real scale) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     C* s = (C*)lds_raw;
-    const int len = 1 << loglen, st = len + 1;
+    const int len = 1 << loglen, st = lpad_len(len) + 1;     // odd stride: columns in distinct banks
     const int Cn = 1 << logC;
     const int c0 = blockIdx.x * Cn;
     const int nc = min(Cn, ncols - c0);
@@ -64,12 +64,12 @@ __global__ void __launch_bounds__(1024) k_fft_cols_t(const CI* in, C* out, int l
     if (ics == 1) {
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
             const int c = e & (Cn - 1), k = e >> logC;
-            s[c * st + k] = to_cplx<CI, C>(in[(int64_t)(c0 + c) + (int64_t)k * ies]);
+            s[c * st + lpad(k)] = to_cplx<CI, C>(in[(int64_t)(c0 + c) + (int64_t)k * ies]);
         }
     } else {
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
             const int c = e >> loglen, k = e & (len - 1);
-            s[c * st + k] = to_cplx<CI, C>(in[(int64_t)(c0 + c) * ics + (int64_t)k * ies]);
+            s[c * st + lpad(k)] = to_cplx<CI, C>(in[(int64_t)(c0 + c) * ics + (int64_t)k * ies]);
         }
     }
     __syncthreads();
@@ -78,14 +78,14 @@ __global__ void __launch_bounds__(1024) k_fft_cols_t(const CI* in, C* out, int l
     if (ocs == 1) {
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
             const int c = e & (Cn - 1), k = e >> logC;
-            C v = s[c * st + k];
+            C v = s[lpad(k) + c * st];
             if (twl) v = cmul(v, twiddle(tw, ((c0 + c) * k) << tws, inv != 0));
             out[(int64_t)(c0 + c) + (int64_t)k * oes] = cplx<C>::make(v.x * scale, v.y * scale);
         }
     } else {
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
             const int c = e >> loglen, k = e & (len - 1);
-            C v = s[c * st + k];
+            C v = s[lpad(k) + c * st];
             if (twl) v = cmul(v, twiddle(tw, ((c0 + c) * k) << tws, inv != 0));
             out[(int64_t)(c0 + c) * ocs + (int64_t)k * oes] = cplx<C>::make(v.x * scale, v.y * scale);
         }
@@ -173,7 +173,7 @@ __device__ __forceinline__ void fold_band(float2* s, const float2* __restrict__ 
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int p = threadIdx.x + (q0 + q) * blockDim.x;
-                if (p < M) s[p] = make_float2(v[q].x * g[q], v[q].y * g[q]);
+                if (p < M) s[lpad(p)] = make_float2(v[q].x * g[q], v[q].y * g[q]);
             }
         }
         return;
@@ -186,7 +186,7 @@ __device__ __forceinline__ void fold_band(float2* s, const float2* __restrict__ 
             acc.x += v.x * g;
             acc.y += v.y * g;
         }
-        s[p] = acc;
+        s[lpad(p)] = acc;
     }
 }
 
@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(1024, 8) k_scalogram(const float2* __restrict_
         for (int q = 0; q < 8; ++q) {
             const int k = threadIdx.x + q * blockDim.x;
             if (k < H) {
-                const float2 a = s[2 * k], c = s[2 * k + 1];
+                const float2 a = s[lpad(2 * k)], c = s[lpad(2 * k + 1)];
                 v[q] = make_float2(__builtin_amdgcn_sqrtf(a.x * a.x + a.y * a.y) * invN,
                                    __builtin_amdgcn_sqrtf(c.x * c.x + c.y * c.y) * invN);
             }
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(1024, 8) k_scalogram(const float2* __restrict_
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int k = threadIdx.x + q * blockDim.x;
-            if (k < H) s[k] = v[q];
+            if (k < H) s[lpad(k)] = v[q];
         }
         __syncthreads();
     }
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(1024, 8) k_scalogram(const float2* __restrict_
             out[H] = make_float2(z.x - z.y, 0.f);
             continue;
         }
-        const float2 a = s[m], c = s[H - m];
+        const float2 a = s[lpad(m)], c = s[lpad(H - m)];
         auto spec = [&](float2 p, float2 q, int k) {
             const float2 E = make_float2(0.5f * (p.x + q.x), 0.5f * (p.y - q.y));
             const float2 D = make_float2(p.x - q.x, p.y + q.y);
@@ -263,12 +263,12 @@ __global__ void __launch_bounds__(256) k_s1(const float2* __restrict__ Xh, int64
             acc.x += v.x * g;
             acc.y += v.y * g;
         }
-        s[p] = acc;
+        s[lpad(p)] = acc;
     }
     __syncthreads();
     lds_fft<64>(s, logNT, 1, NT, tw, tw_log, true);
     float* o = S1 + (b * n1 + lam) * NT;
-    for (int t = threadIdx.x; t < NT; t += blockDim.x) o[t] = s[t].x * invNX;
+    for (int t = threadIdx.x; t < NT; t += blockDim.x) o[t] = s[lpad(t)].x * invNX;
 }
 
 // Second order: Y2[b][alpha][lambda][t] = (X_lambda (*) psi_alpha)[t 2^k2] for t < Ta,
@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(1024) k_second_order(const float2* __restrict_
     __shared__ unsigned int rmx[64];
     const int64_t b = blockIdx.y;
     const int r0 = blockIdx.x * rows;
-    const int Ta = 1 << logTa;
+    const int Ta = 1 << logTa, rs = lpad_len(Ta);    // row stride in LDS
     const int nr = min(rows, Kp - r0);
     if (r0 >= n1) {
         // padding rows lambda >= n1 only: zero rows (the contraction reads them), maxima 0
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(1024) k_second_order(const float2* __restrict_
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int e = threadIdx.x + (q0 + q) * blockDim.x;
-                if (e < nr * Ta) s[e] = make_float2(v[q].x * g[q], v[q].y * g[q]);
+                if (e < nr * Ta) s[(e >> logTa) * rs + lpad(e & (Ta - 1))] = make_float2(v[q].x * g[q], v[q].y * g[q]);
             }
         }
     } else {
@@ -329,16 +329,16 @@ __global__ void __launch_bounds__(1024) k_second_order(const float2* __restrict_
                     acc.y += v.y * g;
                 }
             }
-            s[e] = acc;
+            s[c * rs + lpad(p)] = acc;
         }
     }
     __syncthreads();
-    lds_fft<16>(s, logTa, nr, Ta, tw, tw_log, true);
+    lds_fft<16>(s, logTa, nr, rs, tw, tw_log, true);
     float2* out = Y + b * y_bstride + (int64_t)r0 * Tp;
     for (int c = 0; c < nr; ++c) {
         float m = 0.f;
         for (int t = threadIdx.x; t < Tp; t += blockDim.x) {
-            const float2 v = t < Ta ? cscale(s[c * Ta + t], invNX) : make_float2(0.f, 0.f);
+            const float2 v = t < Ta ? cscale(s[c * rs + lpad(t)], invNX) : make_float2(0.f, 0.f);
             out[(int64_t)c * Tp + t] = v;
             m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
         }
@@ -792,9 +792,9 @@ __global__ void __launch_bounds__(1024, 8) k_scal_bwd_a(const float2* __restrict
     const int lam = blockIdx.x, n1 = gridDim.x;
     const int64_t b = blockIdx.y;
     const int NX = 1 << logNX, H = NX >> 1, NT = 1 << logNT;
-    float2* g1 = s + H + 1;
+    float2* g1 = s + lpad(H) + 1;
     for (int t = threadIdx.x; t < NT; t += blockDim.x)
-        g1[t] = make_float2(gS1 ? gS1[(b * n1 + lam) * NT + t] : 0.f, 0.f);
+        g1[lpad(t)] = make_float2(gS1 ? gS1[(b * n1 + lam) * NT + t] : 0.f, 0.f);
     __syncthreads();
     lds_fft<16>(g1, logNT, 1, NT, tw, tw_log, false);
     // bins m = m0 + tid + q blockDim, q < 5: the temporal rates in the outer loop,
@@ -825,17 +825,17 @@ __global__ void __launch_bounds__(1024, 8) k_scal_bwd_a(const float2* __restrict
             if (m > H) continue;
             float2 hm = (m == 0 || m == H) ? make_float2(c[q].x, 0.f) : cscale(c[q], 0.5f);
             if (m <= Mphi) {
-                const float2 v = g1[m & (NT - 1)];
+                const float2 v = g1[lpad(m & (NT - 1))];
                 hm.x += phiX[m] * v.x;
                 hm.y += phiX[m] * v.y;
             }
-            s[m] = hm;
+            s[lpad(m)] = hm;
         }
     }
     __syncthreads();
     const int tws = tw_log - logNX;
     for (int k = threadIdx.x; k <= H / 2; k += blockDim.x) {
-        const float2 p = s[k], q = s[H - k];
+        const float2 p = s[lpad(k)], q = s[lpad(H - k)];
         auto pk = [&](float2 pp, float2 qq, int kk) {
             const float2 S = make_float2(pp.x + qq.x, pp.y - qq.y);
             const float2 D = make_float2(pp.x - qq.x, pp.y + qq.y);
@@ -846,14 +846,14 @@ __global__ void __launch_bounds__(1024, 8) k_scal_bwd_a(const float2* __restrict
         float2 zn = make_float2(0.f, 0.f);
         const bool two = k > 0 && H - k != k;
         if (two) zn = pk(q, p, H - k);
-        s[k] = zk;
-        if (two) s[H - k] = zn;
+        s[lpad(k)] = zk;
+        if (two) s[lpad(H - k)] = zn;
     }
     __syncthreads();
     if (logNX > 1) lds_fft<16>(s, logNX - 1, 1, H, tw, tw_log, true);
     float2* o = (float2*)(gX + (b * n1 + lam) * (int64_t)NX);
     const float sc = 1.f / (float)NX;
-    for (int k = threadIdx.x; k < H; k += blockDim.x) o[k] = cscale(s[k], sc);
+    for (int k = threadIdx.x; k < H; k += blockDim.x) o[k] = cscale(s[lpad(k)], sc);
 }
 
 // Adjoint of the modulus and of the first-order filter for one row: recompute the
@@ -873,14 +873,14 @@ __global__ void __launch_bounds__(1024, 8) k_scal_bwd_b(const float2* __restrict
     lds_fft<16>(s, logNX, 1, NX, tw, tw_log, true);
     const float* gx = gX + (b * n1 + lam) * (int64_t)NX;
     for (int n = threadIdx.x; n < NX; n += blockDim.x) {
-        const float2 y = cscale(s[n], invN);
+        const float2 y = cscale(s[lpad(n)], invN);
         const float sc = gx[n] * __builtin_amdgcn_rcpf(fmaxf(__builtin_amdgcn_sqrtf(y.x * y.x + y.y * y.y), kEpsMod));
-        s[n] = cscale(y, sc);
+        s[lpad(n)] = cscale(y, sc);
     }
     __syncthreads();
     lds_fft<16>(s, logNX, 1, NX, tw, tw_log, false);
     float2* o = g1 + (b * n1 + lam) * (int64_t)NX;
-    for (int n = threadIdx.x; n < NX; n += blockDim.x) o[n] = s[n];
+    for (int n = threadIdx.x; n < NX; n += blockDim.x) o[n] = s[lpad(n)];
 }
 
 // Band-owned accumulation of the first-order adjoint over lambda for bins
@@ -956,7 +956,7 @@ static void fft_rows(const float2* in, int64_t ip, float2* out, int64_t op, floa
                      bool inv, float scale, const jtfs_plan* P, hipStream_t st) {
     if (logn <= kLdsFftMax) {
         const int logC = logn >= 12 ? 0 : 12 - logn;       // rows per workgroup
-        const size_t lds = (size_t)(1 << logC) * ((1 << logn) + 1) * sizeof(float2);
+        const size_t lds = (size_t)(1 << logC) * (lpad_len(1 << logn) + 1) * sizeof(float2);
         hipLaunchKernelGGL((k_fft_cols), dim3((unsigned)((B + (1 << logC) - 1) >> logC)), dim3(1024), lds, st, in, out,
                            logn, (int)B, logC, (int64_t)0, ip, (int64_t)1, (int64_t)0, op, (int64_t)1, 0, P->tw,
                            P->tw_log, (int)inv, scale);
@@ -967,12 +967,12 @@ static void fft_rows(const float2* in, int64_t ip, float2* out, int64_t op, floa
     const int64_t Pn = (int64_t)1 << lp, Qn = (int64_t)1 << lq;
     int logC = std::max(0, 12 - lq);
     logC = std::min(logC, lp);
-    size_t lds = (size_t)(1 << logC) * (Qn + 1) * sizeof(float2);
+    size_t lds = (size_t)(1 << logC) * (lpad_len(Qn) + 1) * sizeof(float2);
     hipLaunchKernelGGL((k_fft_cols), dim3((unsigned)(Pn >> logC), (unsigned)B), dim3(1024), lds, st, in, scratch, lq,
                        (int)Pn, logC, ip, (int64_t)1, Pn, (int64_t)1 << logn, Qn, (int64_t)1, logn, P->tw, P->tw_log,
                        (int)inv, 1.0f);
     logC = std::min(std::max(0, 12 - lp), lq);
-    lds = (size_t)(1 << logC) * (Pn + 1) * sizeof(float2);
+    lds = (size_t)(1 << logC) * (lpad_len(Pn) + 1) * sizeof(float2);
     hipLaunchKernelGGL((k_fft_cols), dim3((unsigned)(Qn >> logC), (unsigned)B), dim3(1024), lds, st, scratch, out, lp,
                        (int)Qn, logC, (int64_t)1 << logn, (int64_t)1, Qn, op, (int64_t)1, Qn, 0, P->tw, P->tw_log,
                        (int)inv, scale);
@@ -991,7 +991,7 @@ static void input_fft64(const float* x, int64_t B, float2* xh, int64_t xh_pitch,
     const float2* in = (const float2*)x;
     if (logn <= 13) {
         const int logC = logn >= 12 ? 0 : 12 - logn;
-        const size_t lds = (size_t)(1 << logC) * (H + 1) * sizeof(double2);
+        const size_t lds = (size_t)(1 << logC) * (lpad_len(H) + 1) * sizeof(double2);
         hipLaunchKernelGGL((k_fft_cols_t<float2, double2>), dim3((unsigned)((B + (1 << logC) - 1) >> logC)), dim3(1024),
                            lds, st, in, z, logn, (int)B, logC, (int64_t)0, H, (int64_t)1, (int64_t)0, H, (int64_t)1, 0,
                            P->tw64, P->tw_log, 0, 1.0);
@@ -999,12 +999,12 @@ static void input_fft64(const float* x, int64_t B, float2* xh, int64_t xh_pitch,
         const int lq = (logn + 1) / 2, lp = logn - lq;
         const int64_t Pn = (int64_t)1 << lp, Qn = (int64_t)1 << lq;
         int logC = std::min(std::max(0, 12 - lq), lp);
-        size_t lds = (size_t)(1 << logC) * (Qn + 1) * sizeof(double2);
+        size_t lds = (size_t)(1 << logC) * (lpad_len(Qn) + 1) * sizeof(double2);
         hipLaunchKernelGGL((k_fft_cols_t<float2, double2>), dim3((unsigned)(Pn >> logC), (unsigned)B), dim3(1024), lds,
                            st, in, scratch, lq, (int)Pn, logC, H, (int64_t)1, Pn, H, Qn, (int64_t)1, logn, P->tw64,
                            P->tw_log, 0, 1.0);
         logC = std::min(std::max(0, 12 - lp), lq);
-        lds = (size_t)(1 << logC) * (Pn + 1) * sizeof(double2);
+        lds = (size_t)(1 << logC) * (lpad_len(Pn) + 1) * sizeof(double2);
         hipLaunchKernelGGL((k_fft_cols_t<double2, double2>), dim3((unsigned)(Qn >> logC), (unsigned)B), dim3(1024), lds,
                            st, scratch, z, lp, (int)Qn, logC, H, (int64_t)1, Qn, H, (int64_t)1, Qn, 0, P->tw64,
                            P->tw_log, 0, 1.0);
@@ -1063,13 +1063,13 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
     if (use_reg_rows(s.logNX, P->tune.reg_scalogram)) {
         JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, launch_scalogram_r(P, xh, w.xh_pitch, Xh, w.Xh_pitch, B, st));
     } else {
-        JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, hipLaunchKernelGGL(k_scalogram, dim3(s.n1, (unsigned)B), dim3(1024), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
+        JTFS_TIMED(JTFS_STAGE_SCALOGRAM, st, hipLaunchKernelGGL(k_scalogram, dim3(s.n1, (unsigned)B), dim3(1024), sizeof(float2) * lpad_len(s.NX), st, xh, w.xh_pitch,
                        P->psi1, P->band1, P->off1, Xh, w.Xh_pitch, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log));
     }
     LAUNCHCHK("scalogram");
     if (s1) {
         const int logNT = s.logN - s.logT;
-        JTFS_TIMED(JTFS_STAGE_S1, st, hipLaunchKernelGGL(k_s1, dim3(s.n1, (unsigned)B), dim3(256), sizeof(float2) * s.NT, st, Xh, w.Xh_pitch,
+        JTFS_TIMED(JTFS_STAGE_S1, st, hipLaunchKernelGGL(k_s1, dim3(s.n1, (unsigned)B), dim3(256), sizeof(float2) * lpad_len(s.NT), st, Xh, w.Xh_pitch,
                            P->phiX, s.Mphi, s.logNX, logNT, 1.0f / (float)s.NX, s1, P->tw, P->tw_log));
         LAUNCHCHK("first-order lowpass");
     }
@@ -1082,7 +1082,7 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
             continue;
         }
         const int rows = std::min(64, std::max(1, 4096 >> logTa));   // <= 64: row-maximum slots
-        const size_t lds = sizeof(float2) * rows * s.Ta[a];
+        const size_t lds = sizeof(float2) * rows * lpad_len(s.Ta[a]);
         const Family& f2 = s.f2;
         // packed second-order spectrum of alpha: the plan's device table at its offset
         JTFS_TIMED(JTFS_STAGE_SECOND_ORDER, st, hipLaunchKernelGGL(k_second_order, dim3((unsigned)((s.Kp + rows - 1) / rows), (unsigned)B), dim3(1024), lds, st,
@@ -1166,7 +1166,7 @@ static int gy2_row_fft(const jtfs_plan* P, int a, float2* gY2, int64_t yb, int64
     const Shapes& s = P->s;
     const int logTa = s.logNX - s.k2[a];
     const int logC = logTa >= 12 ? 0 : 12 - logTa;
-    const size_t lds = (size_t)(1 << logC) * (s.Ta[a] + 1) * sizeof(float2);
+    const size_t lds = (size_t)(1 << logC) * (lpad_len(s.Ta[a]) + 1) * sizeof(float2);
     if (use_reg_rows(logTa, P->tune.reg_rowfft)) {
         JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st,
                    launch_rowfft_r(P, gY2 + s.yoff[a], yb, (int64_t)s.Tp[a], s.n1, logTa, B, st));
@@ -1257,14 +1257,14 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
         if (rc != JTFS_OK) return rc;
     }
     const int logNT = s.logN - s.logT;
-    const size_t lds_a = sizeof(float2) * (s.NX / 2 + 1 + s.NT);
+    const size_t lds_a = sizeof(float2) * (lpad_len(s.NX / 2) + 1 + lpad_len(s.NT));   // g1 at lpad(H) + 1
     JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_a, dim3(s.n1, (unsigned)B), dim3(1024), lds_a, st, gY2, yb, P->d_yoff, P->d_Tp, P->d_Ta, P->psi2,
                        P->band2, P->off2, s.n_alpha, gs1, P->phiX, s.Mphi, logNT, s.logNX, gX, P->tw, P->tw_log));
     LAUNCHCHK("scalogram adjoint");
     if (use_reg_rows(s.logNX, P->tune.reg_first_adj)) {
         JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, launch_scal_bwd_b_r(P, xh, w.xh_pitch, gX, g1, B, st));
     } else {
-        JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_b, dim3(s.n1, (unsigned)B), dim3(1024), sizeof(float2) * s.NX, st, xh, w.xh_pitch,
+        JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_b, dim3(s.n1, (unsigned)B), dim3(1024), sizeof(float2) * lpad_len(s.NX), st, xh, w.xh_pitch,
                        P->psi1, P->band1, P->off1, gX, g1, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log));
     }
     LAUNCHCHK("modulus and first-order adjoint");
