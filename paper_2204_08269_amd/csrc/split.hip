@@ -169,20 +169,22 @@ __global__ void __launch_bounds__(256) k_ysplit(const float2* __restrict__ Y, in
             tile[r][c] = Yb[(int64_t)(k0 + r) * Tp + t0 + c];
         }
         __syncthreads();
+        // one work item per (t, k-group, plane): consecutive lanes store consecutive
+        // 16-byte planes, so that a column's k-groups go out as one contiguous run
         const int nkb = nk / 8;
-        for (int e = threadIdx.x; e < 64 * nkb; e += 256) {
-            const int t = e / nkb, kb = e % nkb;
-            half8 p0, p1, p2, p3;
+        for (int e = threadIdx.x; e < 64 * nkb * 4; e += 256) {
+            const int pl = e & 3, g = e >> 2;
+            const int t = g / nkb, kb = g % nkb;
+            half8 out;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const float2 v = tile[kb * 8 + j][t];
-                _Float16 a, bb, c, d;
-                split_h(v.x * sy, a, bb);
-                split_h(v.y * sy, c, d);
-                p0[j] = a; p1[j] = bb; p2[j] = c; p3[j] = d;
+                _Float16 hi, lo;
+                split_h((pl < 2 ? v.x : v.y) * sy, hi, lo);
+                out[j] = (pl & 1) ? lo : hi;
             }
             half8* o = (half8*)(Ho + ((int64_t)(t0 + t) * (Kp / 8) + k0 / 8 + kb) * 32);
-            o[0] = p0; o[1] = p1; o[2] = p2; o[3] = p3;
+            o[pl] = out;
         }
     }
 }
