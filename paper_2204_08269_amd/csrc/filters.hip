@@ -322,6 +322,8 @@ extern "C" int jtfs_plan_create_ex(jtfs_plan** out, const jtfs_params* p) {
         P->d_yoff = upload(A, s.yoff);
         P->d_Tp = upload(A, s.Tp);
         P->d_Ta = upload(A, s.Ta);
+        P->d_vchoff = upload(A, s.vchoff);
+        P->d_nch = upload(A, s.nch);
         P->d_pfoff = upload(A, s.pfoff);
         P->d_Lb = upload(A, s.Lb);
         P->d_rowoff = upload(A, s.rowoff);

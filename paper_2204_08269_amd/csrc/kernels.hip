@@ -439,13 +439,16 @@ __global__ void __launch_bounds__(256) k_freq_fwd(const float2* __restrict__ Y, 
 // S2[m][tau] = sum_l PF[m][l] V[l][tau] per (beta, spin).  With stage_pf the
 // matrix PF (NL x Lb) is held in LDS transposed, and each thread forms four
 // outputs m..m+3 of one tau from one read of V[l][tau] and one 16-byte read of PF.
-__global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, int64_t vp_bstride, int slot0,
-                                                int nslots, int nlt, int NTp, int NT, const float* __restrict__ PFall,
+__global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, int64_t vp_bstride,
+                                                const int64_t* __restrict__ vchoff, const int* __restrict__ nch,
+                                                int slot_mult, int nlt, int NTp, int NT, const float* __restrict__ PFall,
                                                 const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
-                                                const int* __restrict__ rowoffv, int NL, int alpha, int n_alpha,
+                                                const int* __restrict__ rowoffv, int NL, int n_alpha,
                                                 int stage_pf, float* __restrict__ S2) {
     extern __shared__ float Vs[];   // [Lb][33], then (stage_pf) Pt [Lb][NL] at a 16-byte boundary
-    const int beta = blockIdx.x, th = blockIdx.y, n_beta = gridDim.x;
+    // grid (n_beta, 2 n_alpha, B): every temporal rate in one launch
+    const int beta = blockIdx.x, th = blockIdx.y & 1, alpha = blockIdx.y >> 1, n_beta = gridDim.x;
+    const int slot0 = (int)vchoff[alpha] * slot_mult, nslots = nch[alpha] * slot_mult;
     const int64_t b = blockIdx.z;
     const int Lb = Lbv[beta], ro = rowoffv[beta];
     const float* PF = PFall + pfoff[beta];
@@ -503,11 +506,14 @@ __global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, in
 // Eq. (4) (no frequential lowpass): V summed over its partial slots and stored per
 // (beta, theta) at rows 2 rowoff(beta) + theta Lb + l of S2[b][alpha][2 Mh][NT].
 // lambda runs fastest so that the partial-slot reads are contiguous.
-__global__ void __launch_bounds__(256) k_v_out(const float* __restrict__ Vp, int64_t vp_bstride, int slot0,
-                                               int nslots, int nlt, int NTp, int NT, const int* __restrict__ Lbv,
-                                               const int* __restrict__ rowoffv, int Mh, int alpha, int n_alpha,
+__global__ void __launch_bounds__(256) k_v_out(const float* __restrict__ Vp, int64_t vp_bstride,
+                                               const int64_t* __restrict__ vchoff, const int* __restrict__ nch,
+                                               int slot_mult, int nlt, int NTp, int NT, const int* __restrict__ Lbv,
+                                               const int* __restrict__ rowoffv, int Mh, int n_alpha,
                                                float* __restrict__ S2) {
-    const int beta = blockIdx.x, th = blockIdx.y;
+    // grid (n_beta, 2 n_alpha, B): every temporal rate in one launch
+    const int beta = blockIdx.x, th = blockIdx.y & 1, alpha = blockIdx.y >> 1;
+    const int slot0 = (int)vchoff[alpha] * slot_mult, nslots = nch[alpha] * slot_mult;
     const int64_t b = blockIdx.z;
     const int Lb = Lbv[beta], ro = rowoffv[beta];
     const float* Vb = Vp + b * vp_bstride;
@@ -599,10 +605,11 @@ __global__ void __launch_bounds__(256) k_ts_bwd(const float2* __restrict__ Y, in
 __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, const float* __restrict__ PFall,
                                                 const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
                                                 const int* __restrict__ rowoffv, int n_beta, int NL, int NT, int NTp,
-                                                int Mh, int Mp, int alpha, int n_alpha, int avg, int stage_pf,
+                                                int Mh, int Mp, int n_alpha, int avg, int stage_pf,
                                                 float* __restrict__ gV, float* __restrict__ gvmax) {
     extern __shared__ float sm[];      // rowsum [Lb] | gS2 tile [NL][NT] | (stage_pf) PF [NL][Lb]
-    const int beta = blockIdx.x, th = blockIdx.y;
+    // grid (n_beta + 1, 2 n_alpha, B): every temporal rate in one launch
+    const int beta = blockIdx.x, th = blockIdx.y & 1, alpha = blockIdx.y >> 1;
     const int64_t b = blockIdx.z;
     float* g = gV + (((b * n_alpha + alpha) * 2 + th) * (int64_t)Mp) * NTp;
     if (beta == n_beta) {
@@ -1124,14 +1131,6 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
         if (rc != JTFS_OK) { set_error("operand split kernel failed"); return rc; }
         JTFS_TIMED(JTFS_STAGE_FREQ_FWD, st, rc = launch_freq_fwd_split(P, a, Yh, ysc, Vp, w.vp_bstride, B, st));
         if (rc != JTFS_OK) { if (rc == JTFS_EHIP) set_error("split contraction launch failed"); return rc; }
-        if (s.avg_fr) {
-            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), s2_out_lds(s), st, Vp, w.vp_bstride, (int)s.vchoff[a],
-                               s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2_out_stage(s), s2));
-        } else {
-            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_v_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), 0, st, Vp, w.vp_bstride, (int)s.vchoff[a],
-                               s.nch[a], nlt, s.NTp, s.NT, P->d_Lb, P->d_rowoff, s.Mh, a, s.n_alpha, s2));
-        }
-        LAUNCHCHK("frequency lowpass");
     }
     for (int a = 0; a < s.n_alpha && !split && !s.tscat; ++a) {
         dim3 grid(nlt, s.nch[a], (unsigned)B);
@@ -1149,12 +1148,18 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
         }
         LAUNCHCHK("frequential contraction");
         }
+    }
+    if (!s.tscat) {
+        // every temporal rate in one launch; the FP32 contraction writes two partial
+        // slots per t-chunk (both halves of its row tile), the split one one
+        const int mult = split ? 1 : 2;
+        const dim3 grid((unsigned)s.n_beta, (unsigned)(2 * s.n_alpha), (unsigned)B);
         if (s.avg_fr) {
-            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), s2_out_lds(s), st, Vp, w.vp_bstride, slot0,
-                               2 * s.nch[a], nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, a, s.n_alpha, s2_out_stage(s), s2));
+            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, grid, dim3(256), s2_out_lds(s), st, Vp, w.vp_bstride, P->d_vchoff,
+                               P->d_nch, mult, nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, s.n_alpha, s2_out_stage(s), s2));
         } else {
-            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_v_out, dim3(s.n_beta, 2, (unsigned)B), dim3(256), 0, st, Vp, w.vp_bstride, slot0,
-                               2 * s.nch[a], nlt, s.NTp, s.NT, P->d_Lb, P->d_rowoff, s.Mh, a, s.n_alpha, s2));
+            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_v_out, grid, dim3(256), 0, st, Vp, w.vp_bstride, P->d_vchoff,
+                               P->d_nch, mult, nlt, s.NTp, s.NT, P->d_Lb, P->d_rowoff, s.Mh, s.n_alpha, s2));
         }
         LAUNCHCHK("frequency lowpass");
     }
@@ -1211,9 +1216,10 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
         rc = gy2_row_fft(P, a, gY2, yb, B, st);
         if (rc != JTFS_OK) return rc;
     }
-    for (int a = 0; a < s.n_alpha && !s.tscat; ++a) {
-        JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_s2_bwd, dim3(s.n_beta + 1, 2, (unsigned)B), dim3(256), s2_bwd_lds(s), st, gs2, P->PF, P->d_pfoff, P->d_Lb,
-                           P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, a, s.n_alpha, (int)s.avg_fr,
+    if (!s.tscat) {
+        // every temporal rate in one launch
+        JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_s2_bwd, dim3(s.n_beta + 1, 2 * s.n_alpha, (unsigned)B), dim3(256), s2_bwd_lds(s), st, gs2, P->PF, P->d_pfoff, P->d_Lb,
+                           P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, s.n_alpha, (int)s.avg_fr,
                            s2_bwd_stage(s), gV, (float*)(base + w.gvmax)));
         LAUNCHCHK("frequency lowpass adjoint");
     }

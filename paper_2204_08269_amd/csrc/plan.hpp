@@ -117,6 +117,8 @@ struct jtfs_plan {
     int64_t* d_yoff = nullptr;     // per alpha: offset of its Y2 block
     int* d_Tp = nullptr;           // per alpha: padded length
     int* d_Ta = nullptr;           // per alpha: length NX / 2^k2
+    int64_t* d_vchoff = nullptr;   // per alpha: first partial-V slot
+    int* d_nch = nullptr;          // per alpha: partial-V slots (t-chunks)
     int64_t* d_pfoff = nullptr;    // per beta: offset of its frequency-lowpass matrix
     int* d_Lb = nullptr;           // per beta: L / 2^kfr
     int* d_rowoff = nullptr;       // per beta: first row of the contraction
