@@ -84,10 +84,15 @@ def algorithmic_flops(info, shapes, B, split):
     """Dense-contraction flops of the frequential stage per step (unpadded sizes):
     forward 8 M_h n1 T_alpha + time lowpass 2 (2 M_h) T_alpha N/T per signal and
     rate; the backward recomputes both and adds the W^H product 8 M_h n1 T_alpha
-    (one fused kernel in the split-FP16 mode, two kernels in the FP32 mode)."""
+    (one fused kernel in the split-FP16 mode, two kernels in the FP32 mode).  With
+    the stored phase the backward recomputes neither the contraction nor the
+    modulus: it does the lowpass adjoint and the W^H product only."""
     Mh, n1, NT = info.M_h, info.n1, info.out_t
     fwd = sum(8 * Mh * n1 * Ta + 4 * Mh * Ta * NT for Ta in shapes) * B
+    lp = sum(4 * Mh * Ta * NT for Ta in shapes) * B
     wh = sum(8 * Mh * n1 * Ta for Ta in shapes) * B
+    if split == "phase":
+        return {"freq_fwd": fwd, "freq_adj_pq": lp + wh}
     if split:
         return {"freq_fwd": fwd, "freq_adj_pq": fwd + wh}
     return {"freq_fwd": fwd, "freq_adj_pq": fwd, "freq_adj_wh": wh}
@@ -123,15 +128,17 @@ def algorithmic_bytes(info, N, shapes, B):
 # HBM bytes per launch of a stage's kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes (scaled by the same counters on a copy of known size), kept beside the
 # profiles with the hash of the kernel's source; stale once that source changes.
-TRAFFIC_FILES = {"freq_adj_pq": ("profiles/k_freq_bwd_h_64x65536_hbm_traffic.json",
-                                 "paper_2204_08269_amd/csrc/split.hip")}
+TRAFFIC_FILES = {("freq_adj_pq", "split16"): ("profiles/k_freq_bwd_h_64x65536_hbm_traffic.json",
+                                            "paper_2204_08269_amd/csrc/split.hip"),
+                 ("freq_adj_pq", "split16_phase"): ("profiles/k_freq_bwd_p_64x65536_hbm_traffic.json",
+                                                  "paper_2204_08269_amd/csrc/split.hip")}
 
 
-def measured_traffic(stage):
+def measured_traffic(stage, contraction):
     import hashlib
-    if stage not in TRAFFIC_FILES:
+    if (stage, contraction) not in TRAFFIC_FILES:
         return None
-    rec_path, src = (os.path.join(HERE, v) for v in TRAFFIC_FILES[stage])
+    rec_path, src = (os.path.join(HERE, v) for v in TRAFFIC_FILES[(stage, contraction)])
     if not os.path.exists(rec_path):
         return None
     rec = json.load(open(rec_path))
@@ -181,7 +188,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=16)
-    ap.add_argument("--contraction", choices=["split16", "fp32"], default=None,
+    ap.add_argument("--contraction", choices=["split16", "split16_phase", "fp32"], default=None,
                     help="frequential contraction arithmetic (default: the plan's, split16 where available)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device copy first (calibrates HBM byte counters)")
@@ -230,7 +237,7 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] autotune: {tuning['contraction']}, register rows {tuning['register_rows']}, "
               f"{tuning['step_ms']:.2f} ms/step", file=sys.stderr, flush=True)
-    split = op.contraction == "split16"
+    split = {"split16": True, "split16_phase": "phase"}.get(op.contraction, False)
     ws = op.new_workspace(B)
 
     def step():
@@ -312,7 +319,7 @@ def main():
     dom = max(stage_roofline, key=lambda k: stages[k][0])
     dom_ms, dom_n = stages[dom]
     roofline = dict(stage_roofline[dom])
-    traffic = measured_traffic(dom)
+    traffic = measured_traffic(dom, op.contraction)
     roofline.update({"kernel": dom, "traffic": traffic["bytes_per_launch"] if traffic else None,
                      "traffic_detail": traffic, "launches_per_step": dom_n // args.steps,
                      "avg_launch_ms": round(dom_ms / max(dom_n, 1), 4),

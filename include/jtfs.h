@@ -153,10 +153,23 @@ int jtfs_backward(const jtfs_plan* plan, const float* x, const float* gs1, const
  *                              as v = hi + lo with hi, lo FP16, and the product
  *                              formed as hi*hi + hi*lo + lo*hi on the FP16 matrix
  *                              cores (22-bit operand precision; products exact).
+ *   JTFS_CONTRACTION_SPLIT_F16_PHASE  SPLIT_F16, and the forward also stores the
+ *                              unit phase z / max(|z|, eps) of every contraction
+ *                              output z (both spins, FP32 complex) in the workspace,
+ *                              so that a backward with JTFS_BWD_REUSE_FORWARD applies
+ *                              the modulus adjoint (sec. 5) from it instead of
+ *                              recomputing the contraction.  The workspace grows by
+ *                              16 * B * M_p * sum_alpha T_p(alpha) bytes (M_p: M_h
+ *                              rounded up to 64; T_p: T_alpha rounded up to 128);
+ *                              jtfs_workspace_size accounts for it.  A backward
+ *                              without JTFS_BWD_REUSE_FORWARD recomputes as SPLIT_F16.
  * The default is SPLIT_F16 where the shapes allow it (n1 <= 240), else FP32.
- * Returns JTFS_ENOTSUP if the requested mode is not available for the plan. */
-#define JTFS_CONTRACTION_FP32      0
-#define JTFS_CONTRACTION_SPLIT_F16 1
+ * Returns JTFS_ENOTSUP if the requested mode is not available for the plan
+ * (SPLIT_F16_PHASE: where the split backward is, and not with
+ * JTFS_TIME_SCATTERING, which has no contraction). */
+#define JTFS_CONTRACTION_FP32            0
+#define JTFS_CONTRACTION_SPLIT_F16       1
+#define JTFS_CONTRACTION_SPLIT_F16_PHASE 2
 int jtfs_plan_set_contraction(jtfs_plan* plan, int mode);
 int jtfs_plan_get_contraction(const jtfs_plan* plan, int* mode);
 
@@ -248,8 +261,10 @@ void jtfs_texture_destroy(jtfs_texture* tex);
  * allocates its buffers itself (the largest workspace over the modes plus
  * coefficients and gradient for B signals), synchronises the stream, uses the
  * per-stage timers (JTFS_EINVAL if timing is enabled) and leaves their records
- * cleared.  candidates_ms: fwd+bwd per step of (split, register), (split, LDS),
- * (FP32, register), (FP32, LDS); 0 for candidates not run. */
+ * cleared.  SPLIT_F16_PHASE is a candidate only where its workspace fits in 80 %
+ * of the device memory free at the call.  candidates_ms: fwd+bwd per step of
+ * (split, register), (split, LDS), (FP32, register), (FP32, LDS), (split with
+ * stored phase, register), (split with stored phase, LDS); 0 for candidates not run. */
 #define JTFS_REG_SCALOGRAM    1
 #define JTFS_REG_SECOND_ORDER 2
 #define JTFS_REG_ROW_FFT      4
@@ -258,7 +273,7 @@ typedef struct {
     int32_t contraction;
     int32_t reg_rows;
     double step_ms;
-    double candidates_ms[4];
+    double candidates_ms[6];
 } jtfs_tuning;
 int jtfs_plan_autotune(jtfs_plan* plan, const float* x, int64_t B, int reps, hipStream_t stream, jtfs_tuning* out);
 int jtfs_plan_set_tuning(jtfs_plan* plan, int contraction, int reg_rows);

@@ -22,6 +22,9 @@ JTFS_NO_FREQ_AVERAGE = 1
 JTFS_TIME_SCATTERING = 2
 JTFS_CONTRACTION_FP32 = 0
 JTFS_CONTRACTION_SPLIT_F16 = 1
+JTFS_CONTRACTION_SPLIT_F16_PHASE = 2
+CONTRACTIONS = {"fp32": JTFS_CONTRACTION_FP32, "split16": JTFS_CONTRACTION_SPLIT_F16,
+                "split16_phase": JTFS_CONTRACTION_SPLIT_F16_PHASE}
 STAGES = ["input_fft", "scalogram", "s1", "second_order", "operand_split", "freq_fwd", "freq_lowpass",
           "lowpass_adj", "freq_adj_pq", "freq_adj_wh", "second_adj_fft", "second_adj", "first_adj", "band_accum",
           "output_fft"]
@@ -29,7 +32,7 @@ STAGES = ["input_fft", "scalogram", "s1", "second_order", "operand_split", "freq
 
 class Tuning(ctypes.Structure):
     _fields_ = [("contraction", ctypes.c_int32), ("reg_rows", ctypes.c_int32), ("step_ms", ctypes.c_double),
-                ("candidates_ms", ctypes.c_double * 4)]
+                ("candidates_ms", ctypes.c_double * 6)]
 
 
 class Params(ctypes.Structure):

@@ -1,6 +1,7 @@
 // Autotuning of a plan's launch choices on the caller's GPU and batch size.
 //
-// Candidates: the contraction arithmetic (split FP16 or FP32 matrix cores) and,
+// Candidates: the contraction arithmetic (split FP16, split FP16 with the phase
+// stored by the forward, or FP32 matrix cores) and,
 // for rows of 2^14 points, the register-resident or the in-LDS transform in each
 // of the four stages that have both (scalogram, second order, gY2 row FFTs,
 // first-order adjoint).  Every candidate runs whole fwd+bwd steps; the per-stage
@@ -111,6 +112,19 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
     std::vector<int> modes;
     if (P->split_ok) modes.push_back(JTFS_CONTRACTION_SPLIT_F16);
     modes.push_back(JTFS_CONTRACTION_FP32);
+    jtfs_info info;
+    jtfs_plan_info(P, &info);
+    const size_t coef_bytes = sizeof(float) * B * (info.s1_per_signal + info.s2_per_signal + 2 * s.N);
+    if (P->split_ok && P->split_bwd_ok && !s.tscat) {
+        // the stored phase only where the whole candidate set fits in 80 % of free memory
+        P->contraction = JTFS_CONTRACTION_SPLIT_F16_PHASE;
+        size_t b = 0;
+        jtfs_workspace_size(P, B, &b);
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && (double)(b + coef_bytes) <= 0.8 * (double)free_b)
+            modes.push_back(JTFS_CONTRACTION_SPLIT_F16_PHASE);
+        P->contraction = saved_mode;
+    }
     bool has14 = s.logNX == kRegMinLogRows;
     for (int a = 0; a < s.n_alpha; ++a) has14 = has14 || (s.logNX - s.k2[a] == kRegMinLogRows);
     const int all_rows = JTFS_REG_SCALOGRAM | JTFS_REG_SECOND_ORDER | JTFS_REG_ROW_FFT | JTFS_REG_FIRST_ADJ;
@@ -123,8 +137,6 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
         jtfs_workspace_size(P, B, &b);
         wsb = std::max(wsb, b);
     }
-    jtfs_info info;
-    jtfs_plan_info(P, &info);
     DevBuf ws, s1, s2, gx, xz;
     if (!ws.alloc(wsb) || !s1.alloc(sizeof(float) * B * info.s1_per_signal) ||
         !s2.alloc(sizeof(float) * B * info.s2_per_signal) || !gx.alloc(sizeof(float) * B * s.N)) {
@@ -141,8 +153,8 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
         x = (const float*)xz.p;
     }
     // measure
-    double stage[2][2][JTFS_NUM_STAGES] = {};
-    double total[2][2] = {};
+    double stage[3][2][JTFS_NUM_STAGES] = {};
+    double total[3][2] = {};
     for (size_t mi = 0; mi < modes.size(); ++mi) {
         for (size_t ri = 0; ri < row_opts.size(); ++ri) {
             P->contraction = modes[mi];
@@ -154,7 +166,10 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
                 set_rows(P, saved_rows);
                 return rc;
             }
-            const int slot = (modes[mi] == JTFS_CONTRACTION_FP32 ? 2 : 0) + (row_opts[ri] ? 0 : 1);
+            const int slot = (modes[mi] == JTFS_CONTRACTION_FP32             ? 2
+                              : modes[mi] == JTFS_CONTRACTION_SPLIT_F16_PHASE ? 4
+                                                                              : 0) +
+                             (row_opts[ri] ? 0 : 1);
             out->candidates_ms[slot] = total[mi][ri];
         }
     }

@@ -1035,8 +1035,9 @@ using namespace jtfs;
 
 // Workspace of a plan in its current contraction mode.
 static Workspace plan_layout(const jtfs_plan* P, int64_t B) {
-    const bool split = P->contraction == JTFS_CONTRACTION_SPLIT_F16;
-    return layout(P->s, B, split, !(split && P->split_bwd_ok));
+    const bool split = P->contraction != JTFS_CONTRACTION_FP32;          // SPLIT_F16 or SPLIT_F16_PHASE
+    const bool phase = P->contraction == JTFS_CONTRACTION_SPLIT_F16_PHASE && !P->s.tscat;
+    return layout(P->s, B, split, !(split && P->split_bwd_ok), phase);
 }
 
 static int check_common(const jtfs_plan* P, int64_t B, void* ws, size_t ws_bytes) {
@@ -1122,14 +1123,16 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
                            s.n_alpha, s2));
         LAUNCHCHK("time-scattering lowpass");
     }
-    const bool split = P->contraction == JTFS_CONTRACTION_SPLIT_F16 && !s.tscat;
+    const bool split = P->contraction != JTFS_CONTRACTION_FP32 && !s.tscat;
+    float2* phase = P->contraction == JTFS_CONTRACTION_SPLIT_F16_PHASE && !s.tscat ? (float2*)(base + w.phase) : nullptr;
     for (int a = 0; a < s.n_alpha && split; ++a) {
         unsigned short* Yh = (unsigned short*)(base + w.Yh);
         float* ysc = (float*)(base + w.yscale);
         JTFS_TIMED(JTFS_STAGE_OPERAND_SPLIT, st,
                    rc = launch_ysplit(P, a, Y2, (const float*)(base + w.rowmax), Yh, ysc, B, st));
         if (rc != JTFS_OK) { set_error("operand split kernel failed"); return rc; }
-        JTFS_TIMED(JTFS_STAGE_FREQ_FWD, st, rc = launch_freq_fwd_split(P, a, Yh, ysc, Vp, w.vp_bstride, B, st));
+        JTFS_TIMED(JTFS_STAGE_FREQ_FWD, st,
+                   rc = launch_freq_fwd_split(P, a, Yh, ysc, Vp, w.vp_bstride, phase, w.ph_bstride, B, st));
         if (rc != JTFS_OK) { if (rc == JTFS_EHIP) set_error("split contraction launch failed"); return rc; }
     }
     for (int a = 0; a < s.n_alpha && !split && !s.tscat; ++a) {
@@ -1223,7 +1226,10 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
                            s2_bwd_stage(s), gV, (float*)(base + w.gvmax)));
         LAUNCHCHK("frequency lowpass adjoint");
     }
-    const bool split = P->contraction == JTFS_CONTRACTION_SPLIT_F16 && P->split_bwd_ok && !s.tscat;
+    const bool split = P->contraction != JTFS_CONTRACTION_FP32 && P->split_bwd_ok && !s.tscat;
+    // the phase the forward stored, when this backward follows it on the same workspace
+    const bool from_phase = split && P->contraction == JTFS_CONTRACTION_SPLIT_F16_PHASE &&
+                            (flags & JTFS_BWD_REUSE_FORWARD);
     unsigned short* Yh = (unsigned short*)(base + w.Yh);
     float* ysc = (float*)(base + w.yscale);
     if (split && !(flags & JTFS_BWD_REUSE_FORWARD)) {
@@ -1234,8 +1240,14 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
         }
     }
     for (int a = 0; a < s.n_alpha && split; ++a) {
-        JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,
-                   rc = launch_freq_bwd_split(P, a, Yh, ysc, gV, (const float*)(base + w.gvmax), gY2, B, st));
+        if (from_phase) {
+            JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,
+                       rc = launch_freq_bwd_phase(P, a, (const float2*)(base + w.phase), w.ph_bstride, gV,
+                                                  (const float*)(base + w.gvmax), gY2, B, st));
+        } else {
+            JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,
+                       rc = launch_freq_bwd_split(P, a, Yh, ysc, gV, (const float*)(base + w.gvmax), gY2, B, st));
+        }
         if (rc != JTFS_OK) { if (rc == JTFS_EHIP) set_error("split backward contraction launch failed"); return rc; }
         rc = gy2_row_fft(P, a, gY2, yb, B, st);
         if (rc != JTFS_OK) return rc;

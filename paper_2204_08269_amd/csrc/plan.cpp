@@ -171,7 +171,7 @@ int check_supported(const Shapes& s) {
     return JTFS_OK;
 }
 
-Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq) {
+Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq, bool with_phase) {
     Workspace w;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) / 256 * 256; return r; };
@@ -198,6 +198,8 @@ Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq) {
     w.gX = take(sizeof(float) * B * s.n1 * s.NX);
     w.g1 = take(sizeof(float2) * B * s.n1 * s.NX);
     w.gxh = take(sizeof(float2) * B * w.xh_pitch);
+    w.ph_bstride = (int64_t)2 * s.sumTp * s.Mp;
+    w.phase = take(with_phase ? sizeof(float2) * B * w.ph_bstride : 0);
     w.total = o;
     return w;
 }

@@ -73,12 +73,15 @@ struct Workspace {
     size_t xh = 0, tmp = 0, tmp64 = 0, z64 = 0, Xh = 0, Y2 = 0, Vp = 0;   // forward
     size_t Yh = 0, rowmax = 0, yscale = 0, gvmax = 0;          // split-FP16 operands
     size_t gV = 0, PQ = 0, gY2 = 0, gX = 0, g1 = 0, gxh = 0;   // backward
+    size_t phase = 0;              // stored unit phase of the contraction output (SPLIT_F16_PHASE)
+    int64_t ph_bstride = 0;        // float2 of stored phase per signal: 2 spins x sum Tp x Mp
     int64_t vp_bstride = 0;        // floats of partial V per signal
     size_t total = 0;
     int64_t xh_pitch = 0, Xh_pitch = 0;
 };
-// with_split: the split-FP16 operand copy of Y2; with_pq: the FP32 backward's P/Q'.
-Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq);
+// with_split: the split-FP16 operand copy of Y2; with_pq: the FP32 backward's P/Q';
+// with_phase: the stored unit phase [B][alpha][spin][Tp][Mp] of the contraction output.
+Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq, bool with_phase);
 
 }  // namespace jtfs
 
@@ -124,7 +127,7 @@ struct jtfs_plan {
     int* d_rowoff = nullptr;       // per beta: first row of the contraction
     double c1 = 0, c2 = 0, cfr = 0;  // Littlewood-Paley normalisations
     // split-FP16 contraction operands (hi + lo halves of power-of-two scaled FP32 values)
-    int contraction = 0;           // JTFS_CONTRACTION_FP32 or JTFS_CONTRACTION_SPLIT_F16
+    int contraction = 0;           // JTFS_CONTRACTION_FP32, _SPLIT_F16 or _SPLIT_F16_PHASE
     bool split_ok = false;         // shapes allow the split kernels (W tile fits in LDS)
     bool split_bwd_ok = false;     // ... and the split backward (register budget)
     unsigned short* Wsp = nullptr; // [Mp][Kp/8][4][8]: re_hi, re_lo, im_hi, im_lo of W * sw

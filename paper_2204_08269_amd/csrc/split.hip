@@ -236,7 +236,8 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
                                                     const unsigned short* __restrict__ Wsp,
                                                     const unsigned short* __restrict__ Phsp, float unscale_wphi,
                                                     const float* __restrict__ yscale, int alpha, int n_alpha,
-                                                    float* __restrict__ Vp, int64_t vp_bstride, int slot0) {
+                                                    float* __restrict__ Vp, int64_t vp_bstride, int slot0,
+                                                    float2* __restrict__ phase, int64_t ph_bstride, float sw) {
     constexpr int NTp = 32 * NTB;
     constexpr int Kp = 16 * NK;            // K = NK k-steps of 16 (compile time: the K loop is unrolled)
     extern __shared__ __align__(16) unsigned char lds[];
@@ -264,6 +265,12 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
         }
     }
     const unsigned short* Yb = Yh + b * yh_bstride;
+    // floor of |z|^2 in the scaled units of z (kEpsMod2 (sw sy)^2, kept a normal number)
+    float eps2s = 0.f;
+    if (phase) {
+        const double wy = (double)sw * (double)yscale[b * n_alpha + alpha];
+        eps2s = (float)fmax(fmin((double)kEpsMod2 * wy * wy, 1e30), 1.1754943508222875e-38);
+    }
     floatx16 vu[NTB], vd[NTB];
 #pragma unroll
     for (int n = 0; n < NTB; ++n) { vu[n] = z16(); vd[n] = z16(); }
@@ -339,17 +346,28 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
             }
         };
         if constexpr (early) next_tile();
-        // modulus of both spins, per-column scale, split, second product with Phi
+        // modulus of both spins, per-column scale, split, second product with Phi;
+        // with phase storage also z / max(|z|, eps) for the backward (row l of the
+        // lane, rows t = crow(r, h) of the tile), in the scaled units of z with the
+        // floor scaled alike
 #pragma unroll
         for (int spin = 0; spin < 2; ++spin) {
             float uval[16];
             float m = 0.f;
+            float2* pcol = phase ? phase + b * ph_bstride + ((int64_t)spin * Tp + t0 + wt * 32) * (nlt * kTileL) +
+                                       lt * kTileL + wl * 32 + i32
+                                 : nullptr;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const float zr = spin ? rr[r] + ii[r] : rr[r] - ii[r];
                 const float zi = spin ? ir[r] - ri[r] : ir[r] + ri[r];
-                uval[r] = __builtin_amdgcn_sqrtf(zr * zr + zi * zi);   // hardware square root (1 ulp)
+                const float z2 = zr * zr + zi * zi;
+                uval[r] = __builtin_amdgcn_sqrtf(z2);   // hardware square root (1 ulp)
                 m = fmaxf(m, uval[r]);
+                if (pcol) {
+                    const float q = __builtin_amdgcn_rsqf(fmaxf(z2, eps2s));
+                    pcol[(int64_t)crow(r, h) * (nlt * kTileL)] = make_float2(zr * q, zi * q);
+                }
             }
             m = fmaxf(m, __shfl_xor(m, 32));
             const int se = pow2_exp(m);
@@ -744,6 +762,202 @@ __global__ void __launch_bounds__(256) k_freq_bwd_h(const unsigned short* __rest
         }
 }
 
+// ------------------------------------------ backward from the stored phase
+
+// Stored unit phase of rows l0 + crow(r, h) (r = 4 g + j) of this lane's column t,
+// both spins: 32 bytes (four rows) per (spin, g).
+__device__ __forceinline__ void load_phase(uint4 (&pv)[2][4][2], gptr<uint4> pcol, int64_t spin_stride) {
+#pragma unroll
+    for (int spin = 0; spin < 2; ++spin)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            gptr<u32x4> p = (gptr<u32x4>)(pcol + (spin * spin_stride + 8 * g) / 2);   // float2 offsets, even
+            pv[spin][g][0] = __builtin_bit_cast(uint4, p[0]);
+            pv[spin][g][1] = __builtin_bit_cast(uint4, p[1]);
+        }
+}
+
+__device__ __forceinline__ float2 phase_at(const uint4 (&pv)[2][4][2], int spin, int r) {
+    const uint4 q = pv[spin][r >> 2][(r >> 1) & 1];
+    return (r & 1) ? make_float2(__uint_as_float(q.z), __uint_as_float(q.w))
+                   : make_float2(__uint_as_float(q.x), __uint_as_float(q.y));
+}
+
+// One 32-row chunk c of the backward when the forward stored the unit phase u of
+// Z (both spins): gZ = gU u, then P, Q' and the W^T product as in k_freq_bwd_h.
+// On entry the chunk's gV rows and phase are in registers (loaded during the
+// previous chunk) and its W^T chunk is in LDS; the next chunk's W^T staging and
+// its gV and phase loads are issued after this chunk's modulus adjoint, ahead of
+// the W^T product, and waited for only at the chunk's end.
+template <int NTB, int NI>
+__device__ __forceinline__ void bwd_chunk_phase(int c, int nC, int Mp, int wave, int lane, int h, int i32,
+                                                const uint4 (&phv)[NTB * 2][2], const float* gvb,
+                                                const float2* pbase, int64_t spin_stride, float ips, float spq,
+                                                const uint4* Tcur, uint4* Tnext, const uint4* Tsrc,
+                                                floatx16 (&gyr)[NI], floatx16 (&gyi)[NI],
+                                                float4 (&v)[2][NTB * 2][2], uint4 (&pv)[2][4][2]) {
+    // ---- gU = gV Phi^T for both spins (gV split per row, Phi pre-split), times spq
+    floatx16 gu[2];
+#pragma unroll
+    for (int spin = 0; spin < 2; ++spin) {
+        float mx = 0.f;
+#pragma unroll
+        for (int kb = 0; kb < NTB * 2; ++kb) {
+            const float4 a0 = v[spin][kb][0], a1 = v[spin][kb][1];
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(a0.x), fabsf(a0.y)), fmaxf(fabsf(a0.z), fabsf(a0.w))));
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(a1.x), fabsf(a1.y)), fmaxf(fabsf(a1.z), fabsf(a1.w))));
+        }
+        mx = fmaxf(mx, __shfl_xor(mx, 32));
+        const int se = pow2_exp(mx);
+        const float sg = ldexpf(1.f, se);
+        floatx16 acc = z16();
+#pragma unroll
+        for (int kb = 0; kb < NTB * 2; ++kb) {
+            half8 ah, al;
+            const float vv[8] = {v[spin][kb][0].x, v[spin][kb][0].y, v[spin][kb][0].z, v[spin][kb][0].w,
+                                 v[spin][kb][1].x, v[spin][kb][1].y, v[spin][kb][1].z, v[spin][kb][1].w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                _Float16 hi, lo;
+                split_h(vv[j] * sg, hi, lo);
+                ah[j] = hi;
+                al[j] = lo;
+            }
+            const half8 bh = as_h8(phv[kb][0]), bl = as_h8(phv[kb][1]);
+            acc = mfma16(ah, bh, acc);
+            acc = mfma16(ah, bl, acc);
+            acc = mfma16(al, bh, acc);
+        }
+        const float isg = ldexpf(ips, -se);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] *= __shfl(isg, crow(r, h));
+        gu[spin] = acc;
+    }
+    // ---- modulus adjoint from the stored phase; P and Q' (FP32, carrying spq)
+    half8 ph[2][4], pl[2][4];       // [s'][Pr, Pi, Qr, Qi]
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const float2 u = phase_at(pv, 0, r), d = phase_at(pv, 1, r);
+        const float su = gu[0][r], sd = gu[1][r];
+        const float vals[4] = {su * u.x + sd * d.x, su * u.y + sd * d.y, su * u.y - sd * d.y, sd * d.x - su * u.x};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            _Float16 hi, lo;
+            split_h(vals[q], hi, lo);
+            ph[r >> 3][q][r & 7] = hi;
+            pl[r >> 3][q][r & 7] = lo;
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- the next chunk: W^T staging, then its gV rows and phase (every wave has
+    // finished reading Tnext: it held the chunk before this one)
+    const int cn = c + 1 < nC ? c + 1 : c;
+    stage_t<NI>(Tnext, Tsrc, cn, wave, lane);
+    load_gv<NTB>(v, launder_s((const float4*)gvb), Mp, 32 * cn, i32, h);
+    load_phase(pv, launder_v((const uint4*)(pbase + 32 * cn)), spin_stride);
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- gY += Wr^T P + Wi^T Q' (A operand from the staged W^T chunk)
+#pragma unroll
+    for (int q0 = 0; q0 < NI; q0 += 2) {
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+            half8 wr[2][2], wi[2][2];             // [block][hi, lo]
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                const int q = q0 + d < NI ? q0 + d : q0;
+                const uint4* lt = Tcur + (q * 16 + (sp * 2 + h) * 4) * 32 + i32;
+                wr[d][0] = as_h8(lt[0]); wr[d][1] = as_h8(lt[32]);
+                wi[d][0] = as_h8(lt[64]); wi[d][1] = as_h8(lt[96]);
+            }
+#pragma unroll
+            for (int term = 0; term < 6; ++term) {
+                const int wsel = term < 3 ? 0 : 1, whl = (term % 3) == 2 ? 1 : 0, phl = (term % 3) == 1 ? 1 : 0;
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    if (q0 + d >= NI) continue;
+                    const half8 a = wsel ? wi[d][whl] : wr[d][whl];
+                    const half8 br = phl ? pl[sp][wsel * 2] : ph[sp][wsel * 2];
+                    const half8 bi = phl ? pl[sp][wsel * 2 + 1] : ph[sp][wsel * 2 + 1];
+                    gyr[q0 + d] = mfma16(a, br, gyr[q0 + d]);
+                    gyi[q0 + d] = mfma16(a, bi, gyi[q0 + d]);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// Backward contraction from the stored phase: one signal, 128 columns t (four
+// waves of 32), all rows l in 32-row chunks; gY accumulated in registers.
+template <int NTB, int NI>
+__global__ void __launch_bounds__(256) k_freq_bwd_p(const float2* __restrict__ phase, int64_t ph_bstride, int Tp,
+                                                    int nTt, int nU, const unsigned short* __restrict__ WTsp,
+                                                    int Mp, int Kp, const unsigned short* __restrict__ PhTsp,
+                                                    float sphi, const float* __restrict__ gV, int64_t gv_bstride,
+                                                    const float* __restrict__ gvmax, int n_beta, int alpha,
+                                                    int n_alpha, float sw, float2* __restrict__ gY,
+                                                    int64_t gy_bstride) {
+    constexpr int NTp = 32 * NTB;
+    __shared__ uint4 Ls_T0[NI * 512];
+    __shared__ uint4 Ls_T1[NI * 512];
+    const int u = blockIdx.x;
+    if (u >= nU) return;                            // whole block
+    const int64_t b = u / nTt;
+    const int t0 = (u % nTt) * kTileTh;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, i32 = lane & 31;
+    const int tw0 = t0 + wave * 32;                 // this wave's columns
+    const int nC = Mp / 32;
+
+    float G = 0.f;
+    for (int q = 0; q < 2 * n_beta; ++q) G = fmaxf(G, gvmax[(b * n_alpha + alpha) * 2 * n_beta + q]);
+    const float spq = pow2_scale(2.f * G * 16384.f / sphi);
+    const float ips = spq / sphi;
+
+    floatx16 gyr[NI], gyi[NI];
+#pragma unroll
+    for (int q = 0; q < NI; ++q) { gyr[q] = z16(); gyi[q] = z16(); }
+
+    const float* gvb = gV + b * gv_bstride;
+    const uint4* phrow = (const uint4*)(PhTsp + ((int64_t)(tw0 + i32) * (NTp / 8) + h) * 16);
+    const uint4* Tsrc = (const uint4*)WTsp;
+    // this lane's column of the stored phase, rows 4h.. of each chunk: [spin][Tp][Mp]
+    const float2* pbase = phase + b * ph_bstride + (int64_t)(tw0 + i32) * Mp + 4 * h;
+    const int64_t spin_stride = (int64_t)Tp * Mp;
+
+    uint4 phv[NTB * 2][2];
+#pragma unroll
+    for (int kb = 0; kb < NTB * 2; ++kb) {
+        phv[kb][0] = phrow[4 * kb];
+        phv[kb][1] = phrow[4 * kb + 1];
+    }
+    float4 v[2][NTB * 2][2];
+    uint4 pv[2][4][2];
+    load_gv<NTB>(v, (gptr<float4>)gvb, Mp, 0, i32, h);
+    load_phase(pv, (gptr<uint4>)pbase, spin_stride);
+    stage_t<NI>(Ls_T0, Tsrc, 0, wave, lane);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    // nC is even (Mp is a multiple of 64): the W^T buffers alternate at compile time
+    for (int c = 0; c < nC; c += 2) {
+        bwd_chunk_phase<NTB, NI>(c, nC, Mp, wave, lane, h, i32, phv, gvb, pbase, spin_stride, ips, spq, Ls_T0,
+                                 Ls_T1, Tsrc, gyr, gyi, v, pv);
+        bwd_chunk_phase<NTB, NI>(c + 1, nC, Mp, wave, lane, h, i32, phv, gvb, pbase, spin_stride, ips, spq, Ls_T1,
+                                 Ls_T0, Tsrc, gyr, gyi, v, pv);
+    }
+    const float inv = 1.f / (sw * spq);
+    float2* o = gY + b * gy_bstride;
+#pragma unroll
+    for (int q = 0; q < NI; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = q * 32 + crow(r, h);
+            if (i < Kp) o[(int64_t)i * Tp + tw0 + i32] = make_float2(gyr[q][r] * inv, gyi[q][r] * inv);
+        }
+}
+
 }  // namespace jtfs
 
 using namespace jtfs;
@@ -864,7 +1078,7 @@ int launch_ysplit(const jtfs_plan* P, int a, const float2* Y2, const float* rowm
 }
 
 int launch_freq_fwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, const float* yscale, float* Vp,
-                          int64_t vp_bstride, int64_t B, hipStream_t st) {
+                          int64_t vp_bstride, float2* phase, int64_t ph_bstride, int64_t B, hipStream_t st) {
     const Shapes& s = P->s;
     const int nlt = s.Mp / kTileL;
     const int nU = (int)(B * s.nch[a]);
@@ -877,10 +1091,12 @@ int launch_freq_fwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, c
     const int slot0 = (int)s.vchoff[a];
     const int nk = s.Kp / 16;
     if (nk < 1 || nk > kMaxFwdNK) { set_error("K beyond the split contraction's LDS tile"); return JTFS_ENOTSUP; }
+    // this rate's block of the stored phase: [spin][Tp][Mp] after the rates before it
+    float2* pha = phase ? phase + (int64_t)2 * s.Mp * (s.yoff[a] / s.Kp) : nullptr;
     switch (s.NTp / 32) {
-        case 1: launch_fwd_nk<1>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0); break;
-        case 2: launch_fwd_nk<2>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0); break;
-        case 4: launch_fwd_nk<4>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0); break;
+        case 1: launch_fwd_nk<1>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw); break;
+        case 2: launch_fwd_nk<2>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw); break;
+        case 4: launch_fwd_nk<4>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw); break;
         default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
     }
     return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
@@ -942,6 +1158,52 @@ int launch_freq_bwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, c
     return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
 }
 
+template <int NTB>
+static void launch_bwdp_ni(int NI, dim3 grid, hipStream_t st, const float2* pha, int64_t phb, int Tp, int nTt,
+                           int nU, const jtfs_plan* P, const unsigned short* PhT, float sphi, const float* gVa,
+                           int64_t gvb, const float* gvmax, int a, float2* gYa, int64_t gyb) {
+    const Shapes& s = P->s;
+#define JTFS_BWDP_CASE(ni)                                                                                    \
+    case ni:                                                                                                  \
+        hipLaunchKernelGGL((k_freq_bwd_p<NTB, ni>), grid, dim3(256), 0, st, pha, phb, Tp, nTt, nU, P->WTsp, \
+                           s.Mp, s.Kp, PhT, sphi, gVa, gvb, gvmax, s.n_beta, a, s.n_alpha, P->sw, gYa, gyb);  \
+        break;
+    if constexpr (NTB == 1) {
+        switch (NI) {
+            JTFS_BWDP_CASE(1) JTFS_BWDP_CASE(2) JTFS_BWDP_CASE(3) JTFS_BWDP_CASE(4)
+            JTFS_BWDP_CASE(5) JTFS_BWDP_CASE(6)
+            default: break;
+        }
+    } else {
+        switch (NI) {
+            JTFS_BWDP_CASE(1) JTFS_BWDP_CASE(2) JTFS_BWDP_CASE(3) JTFS_BWDP_CASE(4) JTFS_BWDP_CASE(5)
+            default: break;
+        }
+    }
+#undef JTFS_BWDP_CASE
+}
+
+int launch_freq_bwd_phase(const jtfs_plan* P, int a, const float2* phase, int64_t ph_bstride, const float* gV,
+                          const float* gvmax, float2* gY2, int64_t B, hipStream_t st) {
+    const Shapes& s = P->s;
+    const int NI = P->KpT / 32;
+    if (!P->split_bwd_ok) { set_error("split backward not available for these shapes"); return JTFS_ENOTSUP; }
+    const int nTt = s.Tp[a] / kTileTh;
+    const int nU = (int)(B * nTt);
+    const int64_t yb = (int64_t)s.Kp * s.sumTp;
+    const float2* pha = phase + (int64_t)2 * s.Mp * (s.yoff[a] / s.Kp);
+    const unsigned short* PhT = P->PhTsp + s.phioff[a] * 2;
+    const float* gVa = gV + (int64_t)a * 2 * s.Mp * s.NTp;
+    const int64_t gvb = (int64_t)s.n_alpha * 2 * s.Mp * s.NTp;
+    float2* gYa = gY2 + s.yoff[a];
+    switch (s.NTp / 32) {
+        case 1: launch_bwdp_ni<1>(NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], gVa, gvb, gvmax, a, gYa, yb); break;
+        case 2: launch_bwdp_ni<2>(NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], gVa, gvb, gvmax, a, gYa, yb); break;
+        default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
+    }
+    return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
+}
+
 }  // namespace jtfs
 
 extern "C" int jtfs_plan_set_contraction(jtfs_plan* P, int mode) {
@@ -949,6 +1211,14 @@ extern "C" int jtfs_plan_set_contraction(jtfs_plan* P, int mode) {
     if (mode == JTFS_CONTRACTION_FP32) { P->contraction = mode; return JTFS_OK; }
     if (mode == JTFS_CONTRACTION_SPLIT_F16) {
         if (!P->split_ok) { set_error("split-FP16 contraction not available for these shapes"); return JTFS_ENOTSUP; }
+        P->contraction = mode;
+        return JTFS_OK;
+    }
+    if (mode == JTFS_CONTRACTION_SPLIT_F16_PHASE) {
+        if (!P->split_ok || !P->split_bwd_ok || P->s.tscat) {
+            set_error("split-FP16 contraction with stored phase not available for these shapes");
+            return JTFS_ENOTSUP;
+        }
         P->contraction = mode;
         return JTFS_OK;
     }

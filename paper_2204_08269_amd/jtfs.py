@@ -17,6 +17,10 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _mode_name(mode):
+    return {v: k for k, v in _lib.CONTRACTIONS.items()}[mode]
+
+
 class JTFS:
     """Joint time-frequency scattering of real signals x [B, N] (float32, on the GPU).
 
@@ -27,7 +31,9 @@ class JTFS:
     With time_scattering=True, the time-scattering variant of sec. 4 instead (no
     frequential stage): S2 [B, n_alpha, n1, N/T].
     contraction: "split16" (FP16 matrix cores with split operands, the default
-    where available) or "fp32" (FP32 matrix cores).  Calling the object is
+    where available), "split16_phase" (split16, and the forward stores the unit
+    phase of the contraction so that a vjp that reuses the forward's workspace
+    need not recompute it; a larger workspace) or "fp32" (FP32 matrix cores).  Calling the object is
     differentiable through torch.autograd; forward() and vjp() call the library
     directly."""
 
@@ -46,11 +52,10 @@ class JTFS:
         _lib.check(self.lib.jtfs_plan_info(self.plan, ctypes.byref(info)))
         self.info = info
         if contraction is not None:
-            mode = {"fp32": _lib.JTFS_CONTRACTION_FP32, "split16": _lib.JTFS_CONTRACTION_SPLIT_F16}[contraction]
-            _lib.check(self.lib.jtfs_plan_set_contraction(self.plan, mode))
+            _lib.check(self.lib.jtfs_plan_set_contraction(self.plan, _lib.CONTRACTIONS[contraction]))
         m = ctypes.c_int(0)
         _lib.check(self.lib.jtfs_plan_get_contraction(self.plan, ctypes.byref(m)))
-        self.contraction = "split16" if m.value == _lib.JTFS_CONTRACTION_SPLIT_F16 else "fp32"
+        self.contraction = _mode_name(m.value)
         self.N = int(N)
         self.s1_shape = (info.n1, info.out_t)
         if self.time_scattering:
@@ -125,16 +130,18 @@ class JTFS:
         t = _lib.Tuning()
         xp = _ptr(self._check_x(x)) if x is not None else None
         _lib.check(self.lib.jtfs_plan_autotune(self.plan, xp, int(B), int(reps), _stream(), ctypes.byref(t)))
-        self.contraction = "split16" if t.contraction == _lib.JTFS_CONTRACTION_SPLIT_F16 else "fp32"
+        self.contraction = _mode_name(t.contraction)
         self._ws = {}                          # the workspace size may have changed with the mode
         return {"contraction": self.contraction,
                 "register_rows": [k for k, v in self.REG_BITS.items() if t.reg_rows & v],
                 "step_ms": t.step_ms,
                 "candidates_ms": {"split16_register": t.candidates_ms[0], "split16_lds": t.candidates_ms[1],
-                                  "fp32_register": t.candidates_ms[2], "fp32_lds": t.candidates_ms[3]}}
+                                  "fp32_register": t.candidates_ms[2], "fp32_lds": t.candidates_ms[3],
+                                  "split16_phase_register": t.candidates_ms[4],
+                                  "split16_phase_lds": t.candidates_ms[5]}}
 
     def set_tuning(self, contraction, register_rows):
-        mode = {"fp32": _lib.JTFS_CONTRACTION_FP32, "split16": _lib.JTFS_CONTRACTION_SPLIT_F16}[contraction]
+        mode = _lib.CONTRACTIONS[contraction]
         mask = sum(self.REG_BITS[k] for k in register_rows)
         _lib.check(self.lib.jtfs_plan_set_tuning(self.plan, mode, mask))
         self.contraction = contraction

@@ -502,6 +502,73 @@ def test_time_scattering_forward_and_vjp(p):
         assert err <= TOL_VJP, f"signal {b}: gradient relative L2 {err:.3e}"
 
 
+# Stored phase: the forward also writes the unit phase of every contraction
+# output, and a vjp that reuses its workspace takes the modulus adjoint from it
+# instead of recomputing the contraction.  Shapes with 32- and 64-frame tiles,
+# ragged row counts, and both eq. (3) and eq. (4).
+PHASE_SHAPES = [P1, RAGGED[0], RAGGED[2], RAGGED[3],
+                dict(N=4096, J=7, Q=(8, 1), J_fr=3, Q_fr=1, T=64, F=2)]     # N/T = 64
+
+
+@pytest.mark.parametrize("average_fr", [True, False])
+@pytest.mark.parametrize("p", PHASE_SHAPES, ids=lambda p: f"N{p['N']}_T{p['T']}_Q{p['Q'][0]}")
+def test_stored_phase_vjp_matches_oracle(p, average_fr):
+    P = oracle_plan(p)
+    B = 3
+    rng = np.random.default_rng(606 + p["N"] + p["T"])
+    x = (rng.standard_normal((B, p["N"])) * 0.5).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    gs1, gs2 = synth.cotangents((B,) + P.s1_shape(), (B,) + P.s2_shape(average_fr), seed=17)
+    gt1, gt2 = torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda()
+    res = {}
+    for mode in ("split16", "split16_phase"):
+        op = gpu_op(p, mode, average_fr=average_fr)
+        assert op.contraction == mode
+        ws = op.new_workspace(B)
+        s1, s2 = op.forward(xt, ws)
+        g = op.vjp(xt, gt1, gt2, ws=ws, reuse_forward=True)
+        g_alone = op.vjp(xt, gt1, gt2)          # no forward to reuse: recomputes the contraction
+        torch.cuda.synchronize()
+        res[mode] = [t.cpu().numpy() for t in (s1, s2, g, g_alone)]
+    a, b_ = res["split16"], res["split16_phase"]
+    # the phase store leaves the coefficients' bits alone, and without a forward
+    # to reuse the two modes run the same recompute
+    assert np.array_equal(a[0], b_[0]) and np.array_equal(a[1], b_[1])
+    assert np.array_equal(a[3], b_[3])
+    for b in range(B):
+        xb = x[b].astype(np.float64)
+        ref = O.jtfs_vjp(xb, gs1[b].astype(np.float64), gs2[b].astype(np.float64), P, average_fr=average_fr)
+        err = rel_l2(b_[2][b], ref)
+        assert err <= TOL_VJP, f"signal {b}: stored-phase gradient relative L2 {err:.3e}"
+        assert rel_l2(a[2][b], ref) <= TOL_VJP
+
+
+def test_stored_phase_zero_input_and_autograd():
+    """Zero input: the stored phase is zero (|z| below eps), the gradient finite
+    and zero.  Autograd through the object uses the stored phase and equals the
+    explicit forward + vjp on one workspace."""
+    op = gpu_op(P1, "split16_phase")
+    x = torch.zeros((2, P1["N"]), device="cuda")
+    ws = op.new_workspace(2)
+    s1, s2 = op.forward(x, ws)
+    g = op.vjp(x, torch.ones_like(s1), torch.ones_like(s2), ws=ws, reuse_forward=True)
+    torch.cuda.synchronize()
+    assert float(s1.abs().max()) == 0.0 and float(s2.abs().max()) == 0.0
+    assert torch.isfinite(g).all() and float(g.abs().max()) == 0.0
+    P = oracle_plan(P1)
+    xs = torch.from_numpy(synth.batch(1, B=2)).cuda()
+    gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape(), seed=19)
+    gs1, gs2 = torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda()
+    xr = xs.clone().requires_grad_(True)
+    s1, s2 = op(xr)
+    ((s1 * gs1).sum() + (s2 * gs2).sum()).backward()
+    ws = op.new_workspace(2)
+    op.forward(xs, ws)
+    g_ref = op.vjp(xs, gs1, gs2, ws=ws, reuse_forward=True)
+    torch.cuda.synchronize()
+    assert torch.equal(xr.grad, g_ref)
+
+
 # rows of 2^14 points (kX = 0): the autotuner's register-resident / in-LDS choice matters
 MID = dict(N=2 ** 14, J=5, Q=(1, 1), J_fr=2, Q_fr=1, T=2 ** 9, F=2)
 
@@ -517,7 +584,7 @@ def test_autotune_then_every_row_choice_matches_oracle():
     xt = torch.from_numpy(x).cuda()
     op = gpu_op(MID)
     choice = op.autotune(2, xt, reps=2)
-    assert choice["contraction"] in ("split16", "fp32") and choice["step_ms"] > 0
+    assert choice["contraction"] in ("split16", "split16_phase", "fp32") and choice["step_ms"] > 0
     gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape(), seed=31)
     refs = [(O.jtfs(x[b].astype(np.float64), P),
              O.jtfs_vjp(x[b].astype(np.float64), gs1[b].astype(np.float64), gs2[b].astype(np.float64), P))
