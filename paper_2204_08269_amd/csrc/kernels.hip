@@ -1124,7 +1124,7 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
         LAUNCHCHK("time-scattering lowpass");
     }
     const bool split = P->contraction != JTFS_CONTRACTION_FP32 && !s.tscat;
-    float2* phase = P->contraction == JTFS_CONTRACTION_SPLIT_F16_PHASE && !s.tscat ? (float2*)(base + w.phase) : nullptr;
+    unsigned* phase = P->contraction == JTFS_CONTRACTION_SPLIT_F16_PHASE && !s.tscat ? (unsigned*)(base + w.phase) : nullptr;
     for (int a = 0; a < s.n_alpha && split; ++a) {
         unsigned short* Yh = (unsigned short*)(base + w.Yh);
         float* ysc = (float*)(base + w.yscale);
@@ -1242,7 +1242,7 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     for (int a = 0; a < s.n_alpha && split; ++a) {
         if (from_phase) {
             JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,
-                       rc = launch_freq_bwd_phase(P, a, (const float2*)(base + w.phase), w.ph_bstride, gV,
+                       rc = launch_freq_bwd_phase(P, a, (const unsigned*)(base + w.phase), w.ph_bstride, gV,
                                                   (const float*)(base + w.gvmax), gY2, B, st));
         } else {
             JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,

@@ -199,7 +199,7 @@ Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq, bool
     w.g1 = take(sizeof(float2) * B * s.n1 * s.NX);
     w.gxh = take(sizeof(float2) * B * w.xh_pitch);
     w.ph_bstride = (int64_t)2 * s.sumTp * s.Mp;
-    w.phase = take(with_phase ? sizeof(float2) * B * w.ph_bstride : 0);
+    w.phase = take(with_phase ? sizeof(uint32_t) * B * w.ph_bstride : 0);
     w.total = o;
     return w;
 }

@@ -74,13 +74,14 @@ struct Workspace {
     size_t Yh = 0, rowmax = 0, yscale = 0, gvmax = 0;          // split-FP16 operands
     size_t gV = 0, PQ = 0, gY2 = 0, gX = 0, g1 = 0, gxh = 0;   // backward
     size_t phase = 0;              // stored unit phase of the contraction output (SPLIT_F16_PHASE)
-    int64_t ph_bstride = 0;        // float2 of stored phase per signal: 2 spins x sum Tp x Mp
+    int64_t ph_bstride = 0;        // stored-phase elements (two snorm16) per signal: 2 spins x sum Tp x Mp
     int64_t vp_bstride = 0;        // floats of partial V per signal
     size_t total = 0;
     int64_t xh_pitch = 0, Xh_pitch = 0;
 };
 // with_split: the split-FP16 operand copy of Y2; with_pq: the FP32 backward's P/Q';
-// with_phase: the stored unit phase [B][alpha][spin][Tp][Mp] of the contraction output.
+// with_phase: the stored unit phase of the contraction output, per signal and rate
+// [spin][Mp / 32][Tp][32] elements of two snorm16.
 Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq, bool with_phase);
 
 }  // namespace jtfs

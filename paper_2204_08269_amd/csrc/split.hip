@@ -220,6 +220,13 @@ __device__ __forceinline__ void load_y(uint4 (&y)[4], gptr<uint4> ycol, int kq) 
     for (int j = 0; j < 4; ++j) y[j] = __builtin_bit_cast(uint4, p[j]);
 }
 
+// The stored unit phase: two values in [-1, 1] as snorm16, round(x 32767), the
+// first in the low half (absolute error at most 0.5 / 32767 per component).
+__device__ __forceinline__ unsigned pack_snorm16(float a, float b) {
+    return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pknorm_i16(a, b));
+}
+constexpr float kSnormInv = 1.f / 32767.f;
+
 // ------------------------------------------------------- forward contraction
 
 // One workgroup: 64 rows l (W resident in LDS) x one t-chunk, in tiles of 128 t.
@@ -237,7 +244,7 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
                                                     const unsigned short* __restrict__ Phsp, float unscale_wphi,
                                                     const float* __restrict__ yscale, int alpha, int n_alpha,
                                                     float* __restrict__ Vp, int64_t vp_bstride, int slot0,
-                                                    float2* __restrict__ phase, int64_t ph_bstride, float sw) {
+                                                    unsigned* __restrict__ phase, int64_t ph_bstride, float sw) {
     constexpr int NTp = 32 * NTB;
     constexpr int Kp = 16 * NK;            // K = NK k-steps of 16 (compile time: the K loop is unrolled)
     extern __shared__ __align__(16) unsigned char lds[];
@@ -347,16 +354,16 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
         };
         if constexpr (early) next_tile();
         // modulus of both spins, per-column scale, split, second product with Phi;
-        // with phase storage also z / max(|z|, eps) for the backward (row l of the
-        // lane, rows t = crow(r, h) of the tile), in the scaled units of z with the
-        // floor scaled alike
+        // with phase storage also u = z / max(|z|, eps) for the backward, as two
+        // snorm16 (real in the low half), in 32-row blocks of l: element
+        // ((spin, l / 32), t, l % 32); the floor is in the scaled units of z
 #pragma unroll
         for (int spin = 0; spin < 2; ++spin) {
             float uval[16];
             float m = 0.f;
-            float2* pcol = phase ? phase + b * ph_bstride + ((int64_t)spin * Tp + t0 + wt * 32) * (nlt * kTileL) +
-                                       lt * kTileL + wl * 32 + i32
-                                 : nullptr;
+            unsigned* pcol = phase ? phase + b * ph_bstride +
+                                         ((int64_t)(spin * nlt + lt) * 2 + wl) * Tp * 32 + (int64_t)(t0 + wt * 32) * 32 + i32
+                                   : nullptr;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const float zr = spin ? rr[r] + ii[r] : rr[r] - ii[r];
@@ -366,7 +373,7 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
                 m = fmaxf(m, uval[r]);
                 if (pcol) {
                     const float q = __builtin_amdgcn_rsqf(fmaxf(z2, eps2s));
-                    pcol[(int64_t)crow(r, h) * (nlt * kTileL)] = make_float2(zr * q, zi * q);
+                    pcol[crow(r, h) * 32] = pack_snorm16(zr * q, zi * q);
                 }
             }
             m = fmaxf(m, __shfl_xor(m, 32));
@@ -764,23 +771,24 @@ __global__ void __launch_bounds__(256) k_freq_bwd_h(const unsigned short* __rest
 
 // ------------------------------------------ backward from the stored phase
 
-// Stored unit phase of rows l0 + crow(r, h) (r = 4 g + j) of this lane's column t,
-// both spins: 32 bytes (four rows) per (spin, g).
-__device__ __forceinline__ void load_phase(uint4 (&pv)[2][4][2], gptr<uint4> pcol, int64_t spin_stride) {
+// Stored unit phase of rows crow(r, h) (r = 4 g + j) of one 32-row block, this
+// lane's column t, both spins: one 16-byte load (four rows) per (spin, g).
+// pcol points at element 4 h of the lane's column in the block of spin 0.
+__device__ __forceinline__ void load_phase(uint4 (&pv)[2][4], gptr<uint4> pcol, int64_t spin_stride) {
 #pragma unroll
     for (int spin = 0; spin < 2; ++spin)
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            gptr<u32x4> p = (gptr<u32x4>)(pcol + (spin * spin_stride + 8 * g) / 2);   // float2 offsets, even
-            pv[spin][g][0] = __builtin_bit_cast(uint4, p[0]);
-            pv[spin][g][1] = __builtin_bit_cast(uint4, p[1]);
+            gptr<u32x4> p = (gptr<u32x4>)(pcol + (spin * spin_stride + 8 * g) / 4);   // element offsets, % 4 = 0
+            pv[spin][g] = __builtin_bit_cast(uint4, p[0]);
         }
 }
 
-__device__ __forceinline__ float2 phase_at(const uint4 (&pv)[2][4][2], int spin, int r) {
-    const uint4 q = pv[spin][r >> 2][(r >> 1) & 1];
-    return (r & 1) ? make_float2(__uint_as_float(q.z), __uint_as_float(q.w))
-                   : make_float2(__uint_as_float(q.x), __uint_as_float(q.y));
+// the two snorm16 of row crow(r, h) as integers in [-32767, 32767] (real, imaginary)
+__device__ __forceinline__ float2 phase_at(const uint4 (&pv)[2][4], int spin, int r) {
+    const uint4 q = pv[spin][r >> 2];
+    const unsigned w = (r & 3) == 0 ? q.x : (r & 3) == 1 ? q.y : (r & 3) == 2 ? q.z : q.w;
+    return make_float2((float)(int)(short)(w & 0xffffu), (float)((int)w >> 16));
 }
 
 // One 32-row chunk c of the backward when the forward stored the unit phase u of
@@ -792,10 +800,11 @@ __device__ __forceinline__ float2 phase_at(const uint4 (&pv)[2][4][2], int spin,
 template <int NTB, int NI>
 __device__ __forceinline__ void bwd_chunk_phase(int c, int nC, int Mp, int wave, int lane, int h, int i32,
                                                 const uint4 (&phv)[NTB * 2][2], const float* gvb,
-                                                const float2* pbase, int64_t spin_stride, float ips, float spq,
+                                                const unsigned* pbase, int64_t spin_stride, int64_t c_stride,
+                                                float ips, float spq,
                                                 const uint4* Tcur, uint4* Tnext, const uint4* Tsrc,
                                                 floatx16 (&gyr)[NI], floatx16 (&gyi)[NI],
-                                                float4 (&v)[2][NTB * 2][2], uint4 (&pv)[2][4][2]) {
+                                                float4 (&v)[2][NTB * 2][2], uint4 (&pv)[2][4]) {
     // ---- gU = gV Phi^T for both spins (gV split per row, Phi pre-split), times spq
     floatx16 gu[2];
 #pragma unroll
@@ -838,7 +847,7 @@ __device__ __forceinline__ void bwd_chunk_phase(int c, int nC, int Mp, int wave,
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const float2 u = phase_at(pv, 0, r), d = phase_at(pv, 1, r);
-        const float su = gu[0][r], sd = gu[1][r];
+        const float su = gu[0][r] * kSnormInv, sd = gu[1][r] * kSnormInv;
         const float vals[4] = {su * u.x + sd * d.x, su * u.y + sd * d.y, su * u.y - sd * d.y, sd * d.x - su * u.x};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -854,7 +863,7 @@ __device__ __forceinline__ void bwd_chunk_phase(int c, int nC, int Mp, int wave,
     const int cn = c + 1 < nC ? c + 1 : c;
     stage_t<NI>(Tnext, Tsrc, cn, wave, lane);
     load_gv<NTB>(v, launder_s((const float4*)gvb), Mp, 32 * cn, i32, h);
-    load_phase(pv, launder_v((const uint4*)(pbase + 32 * cn)), spin_stride);
+    load_phase(pv, launder_v((const uint4*)(pbase + cn * c_stride)), spin_stride);
     __builtin_amdgcn_sched_barrier(0);
     // ---- gY += Wr^T P + Wi^T Q' (A operand from the staged W^T chunk)
 #pragma unroll
@@ -892,7 +901,7 @@ __device__ __forceinline__ void bwd_chunk_phase(int c, int nC, int Mp, int wave,
 // Backward contraction from the stored phase: one signal, 128 columns t (four
 // waves of 32), all rows l in 32-row chunks; gY accumulated in registers.
 template <int NTB, int NI>
-__global__ void __launch_bounds__(256) k_freq_bwd_p(const float2* __restrict__ phase, int64_t ph_bstride, int Tp,
+__global__ void __launch_bounds__(256) k_freq_bwd_p(const unsigned* __restrict__ phase, int64_t ph_bstride, int Tp,
                                                     int nTt, int nU, const unsigned short* __restrict__ WTsp,
                                                     int Mp, int Kp, const unsigned short* __restrict__ PhTsp,
                                                     float sphi, const float* __restrict__ gV, int64_t gv_bstride,
@@ -923,9 +932,10 @@ __global__ void __launch_bounds__(256) k_freq_bwd_p(const float2* __restrict__ p
     const float* gvb = gV + b * gv_bstride;
     const uint4* phrow = (const uint4*)(PhTsp + ((int64_t)(tw0 + i32) * (NTp / 8) + h) * 16);
     const uint4* Tsrc = (const uint4*)WTsp;
-    // this lane's column of the stored phase, rows 4h.. of each chunk: [spin][Tp][Mp]
-    const float2* pbase = phase + b * ph_bstride + (int64_t)(tw0 + i32) * Mp + 4 * h;
-    const int64_t spin_stride = (int64_t)Tp * Mp;
+    // this lane's column of the stored phase, rows 4h.. of each 32-row block
+    // (blocks [spin][Mp / 32], each Tp x 32 elements)
+    const unsigned* pbase = phase + b * ph_bstride + (int64_t)(tw0 + i32) * 32 + 4 * h;
+    const int64_t spin_stride = (int64_t)Tp * Mp, c_stride = (int64_t)Tp * 32;
 
     uint4 phv[NTB * 2][2];
 #pragma unroll
@@ -934,7 +944,7 @@ __global__ void __launch_bounds__(256) k_freq_bwd_p(const float2* __restrict__ p
         phv[kb][1] = phrow[4 * kb + 1];
     }
     float4 v[2][NTB * 2][2];
-    uint4 pv[2][4][2];
+    uint4 pv[2][4];
     load_gv<NTB>(v, (gptr<float4>)gvb, Mp, 0, i32, h);
     load_phase(pv, (gptr<uint4>)pbase, spin_stride);
     stage_t<NI>(Ls_T0, Tsrc, 0, wave, lane);
@@ -942,9 +952,9 @@ __global__ void __launch_bounds__(256) k_freq_bwd_p(const float2* __restrict__ p
     __syncthreads();
     // nC is even (Mp is a multiple of 64): the W^T buffers alternate at compile time
     for (int c = 0; c < nC; c += 2) {
-        bwd_chunk_phase<NTB, NI>(c, nC, Mp, wave, lane, h, i32, phv, gvb, pbase, spin_stride, ips, spq, Ls_T0,
+        bwd_chunk_phase<NTB, NI>(c, nC, Mp, wave, lane, h, i32, phv, gvb, pbase, spin_stride, c_stride, ips, spq, Ls_T0,
                                  Ls_T1, Tsrc, gyr, gyi, v, pv);
-        bwd_chunk_phase<NTB, NI>(c + 1, nC, Mp, wave, lane, h, i32, phv, gvb, pbase, spin_stride, ips, spq, Ls_T1,
+        bwd_chunk_phase<NTB, NI>(c + 1, nC, Mp, wave, lane, h, i32, phv, gvb, pbase, spin_stride, c_stride, ips, spq, Ls_T1,
                                  Ls_T0, Tsrc, gyr, gyi, v, pv);
     }
     const float inv = 1.f / (sw * spq);
@@ -1078,7 +1088,7 @@ int launch_ysplit(const jtfs_plan* P, int a, const float2* Y2, const float* rowm
 }
 
 int launch_freq_fwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, const float* yscale, float* Vp,
-                          int64_t vp_bstride, float2* phase, int64_t ph_bstride, int64_t B, hipStream_t st) {
+                          int64_t vp_bstride, unsigned* phase, int64_t ph_bstride, int64_t B, hipStream_t st) {
     const Shapes& s = P->s;
     const int nlt = s.Mp / kTileL;
     const int nU = (int)(B * s.nch[a]);
@@ -1091,8 +1101,8 @@ int launch_freq_fwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, c
     const int slot0 = (int)s.vchoff[a];
     const int nk = s.Kp / 16;
     if (nk < 1 || nk > kMaxFwdNK) { set_error("K beyond the split contraction's LDS tile"); return JTFS_ENOTSUP; }
-    // this rate's block of the stored phase: [spin][Tp][Mp] after the rates before it
-    float2* pha = phase ? phase + (int64_t)2 * s.Mp * (s.yoff[a] / s.Kp) : nullptr;
+    // this rate's block of the stored phase (2 Mp Tp elements) after the rates before it
+    unsigned* pha = phase ? phase + (int64_t)2 * s.Mp * (s.yoff[a] / s.Kp) : nullptr;
     switch (s.NTp / 32) {
         case 1: launch_fwd_nk<1>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw); break;
         case 2: launch_fwd_nk<2>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw); break;
@@ -1159,7 +1169,7 @@ int launch_freq_bwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, c
 }
 
 template <int NTB>
-static void launch_bwdp_ni(int NI, dim3 grid, hipStream_t st, const float2* pha, int64_t phb, int Tp, int nTt,
+static void launch_bwdp_ni(int NI, dim3 grid, hipStream_t st, const unsigned* pha, int64_t phb, int Tp, int nTt,
                            int nU, const jtfs_plan* P, const unsigned short* PhT, float sphi, const float* gVa,
                            int64_t gvb, const float* gvmax, int a, float2* gYa, int64_t gyb) {
     const Shapes& s = P->s;
@@ -1183,7 +1193,7 @@ static void launch_bwdp_ni(int NI, dim3 grid, hipStream_t st, const float2* pha,
 #undef JTFS_BWDP_CASE
 }
 
-int launch_freq_bwd_phase(const jtfs_plan* P, int a, const float2* phase, int64_t ph_bstride, const float* gV,
+int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int64_t ph_bstride, const float* gV,
                           const float* gvmax, float2* gY2, int64_t B, hipStream_t st) {
     const Shapes& s = P->s;
     const int NI = P->KpT / 32;
@@ -1191,7 +1201,7 @@ int launch_freq_bwd_phase(const jtfs_plan* P, int a, const float2* phase, int64_
     const int nTt = s.Tp[a] / kTileTh;
     const int nU = (int)(B * nTt);
     const int64_t yb = (int64_t)s.Kp * s.sumTp;
-    const float2* pha = phase + (int64_t)2 * s.Mp * (s.yoff[a] / s.Kp);
+    const unsigned* pha = phase + (int64_t)2 * s.Mp * (s.yoff[a] / s.Kp);
     const unsigned short* PhT = P->PhTsp + s.phioff[a] * 2;
     const float* gVa = gV + (int64_t)a * 2 * s.Mp * s.NTp;
     const int64_t gvb = (int64_t)s.n_alpha * 2 * s.Mp * s.NTp;

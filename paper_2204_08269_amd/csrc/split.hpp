@@ -14,10 +14,11 @@ int launch_ysplit(const jtfs_plan* P, int a, const float2* Y2, const float* rowm
                   int64_t B, hipStream_t st);
 int launch_freq_bwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, const float* yscale, const float* gV,
                           const float* gvmax, float2* gY2, int64_t B, hipStream_t st);
-// phase: NULL, or the stored-phase buffer of the workspace (ph_bstride float2 per signal)
+// phase: NULL, or the stored-phase buffer of the workspace (ph_bstride packed snorm16
+// pairs per signal)
 int launch_freq_fwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, const float* yscale, float* Vp,
-                          int64_t vp_bstride, float2* phase, int64_t ph_bstride, int64_t B, hipStream_t st);
+                          int64_t vp_bstride, unsigned* phase, int64_t ph_bstride, int64_t B, hipStream_t st);
 // backward contraction from the phase the forward stored (no recomputation of Z)
-int launch_freq_bwd_phase(const jtfs_plan* P, int a, const float2* phase, int64_t ph_bstride, const float* gV,
+int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int64_t ph_bstride, const float* gV,
                           const float* gvmax, float2* gY2, int64_t B, hipStream_t st);
 }  // namespace jtfs
