@@ -155,11 +155,15 @@ int jtfs_backward(const jtfs_plan* plan, const float* x, const float* gs1, const
  *                              cores (22-bit operand precision; products exact).
  *   JTFS_CONTRACTION_SPLIT_F16_PHASE  SPLIT_F16, and the forward also stores the
  *                              unit phase z / max(|z|, eps) of every contraction
- *                              output z (both spins, FP32 complex) in the workspace,
+ *                              output z (both spins; real and imaginary part each
+ *                              as a snorm16, round(32767 x), so an absolute error
+ *                              of at most 0.5 / 32767 = 1.5e-5) in the workspace,
  *                              so that a backward with JTFS_BWD_REUSE_FORWARD applies
  *                              the modulus adjoint (sec. 5) from it instead of
- *                              recomputing the contraction.  The workspace grows by
- *                              16 * B * M_p * sum_alpha T_p(alpha) bytes (M_p: M_h
+ *                              recomputing the contraction.  The gradient then
+ *                              carries a relative error of order 1e-5 (the
+ *                              recomputing modes: order 1e-6).  The workspace grows
+ *                              by 8 * B * M_p * sum_alpha T_p(alpha) bytes (M_p: M_h
  *                              rounded up to 64; T_p: T_alpha rounded up to 128);
  *                              jtfs_workspace_size accounts for it.  A backward
  *                              without JTFS_BWD_REUSE_FORWARD recomputes as SPLIT_F16.
@@ -262,7 +266,10 @@ void jtfs_texture_destroy(jtfs_texture* tex);
  * coefficients and gradient for B signals), synchronises the stream, uses the
  * per-stage timers (JTFS_EINVAL if timing is enabled) and leaves their records
  * cleared.  SPLIT_F16_PHASE is a candidate only where its workspace fits in 80 %
- * of the device memory free at the call.  candidates_ms: fwd+bwd per step of
+ * of the device memory free at the call (the timed steps reuse the forward, so
+ * where it is chosen, a backward that does not reuse its forward runs as
+ * SPLIT_F16; a caller that wants the recomputing backward's gradient precision
+ * sets the mode with jtfs_plan_set_tuning instead).  candidates_ms: fwd+bwd per step of
  * (split, register), (split, LDS), (FP32, register), (FP32, LDS), (split with
  * stored phase, register), (split with stored phase, LDS); 0 for candidates not run. */
 #define JTFS_REG_SCALOGRAM    1

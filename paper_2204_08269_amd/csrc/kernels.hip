@@ -1239,10 +1239,15 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
             if (rc != JTFS_OK) { set_error("operand split kernel failed"); return rc; }
         }
     }
+    if (from_phase) {
+        JTFS_TIMED(JTFS_STAGE_OPERAND_SPLIT, st, rc = launch_gv_split(P, gV, (uint4*)(base + w.gvs), B, st));
+        if (rc != JTFS_OK) { if (rc == JTFS_EHIP) set_error("gV split launch failed"); return rc; }
+    }
     for (int a = 0; a < s.n_alpha && split; ++a) {
         if (from_phase) {
             JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,
-                       rc = launch_freq_bwd_phase(P, a, (const unsigned*)(base + w.phase), w.ph_bstride, gV,
+                       rc = launch_freq_bwd_phase(P, a, (const unsigned*)(base + w.phase), w.ph_bstride,
+                                                  (const uint4*)(base + w.gvs), w.gvs_bstride,
                                                   (const float*)(base + w.gvmax), gY2, B, st));
         } else {
             JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,

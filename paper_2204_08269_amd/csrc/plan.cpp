@@ -200,6 +200,10 @@ Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq, bool
     w.gxh = take(sizeof(float2) * B * w.xh_pitch);
     w.ph_bstride = (int64_t)2 * s.sumTp * s.Mp;
     w.phase = take(with_phase ? sizeof(uint32_t) * B * w.ph_bstride : 0);
+    // gV split for the backward from the stored phase: per rate and 32-row chunk, the
+    // FP16 planes of both spins and the rows' scales
+    w.gvs_bstride = (int64_t)s.n_alpha * (s.Mp / 32) * (512 * (s.NTp / 32) + 16);
+    w.gvs = take(with_phase ? 16 * B * w.gvs_bstride : 0);
     w.total = o;
     return w;
 }

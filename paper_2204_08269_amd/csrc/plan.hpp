@@ -75,6 +75,8 @@ struct Workspace {
     size_t gV = 0, PQ = 0, gY2 = 0, gX = 0, g1 = 0, gxh = 0;   // backward
     size_t phase = 0;              // stored unit phase of the contraction output (SPLIT_F16_PHASE)
     int64_t ph_bstride = 0;        // stored-phase elements (two snorm16) per signal: 2 spins x sum Tp x Mp
+    size_t gvs = 0;                // gV split into FP16 planes for the stored-phase backward
+    int64_t gvs_bstride = 0;       // 16-byte units of gvs per signal
     int64_t vp_bstride = 0;        // floats of partial V per signal
     size_t total = 0;
     int64_t xh_pitch = 0, Xh_pitch = 0;

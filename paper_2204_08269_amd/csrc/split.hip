@@ -771,14 +771,75 @@ __global__ void __launch_bounds__(256) k_freq_bwd_h(const unsigned short* __rest
 
 // ------------------------------------------ backward from the stored phase
 
-// Stored unit phase of rows crow(r, h) (r = 4 g + j) of one 32-row block, this
-// lane's column t, both spins: one 16-byte load (four rows) per (spin, g).
-// pcol points at element 4 h of the lane's column in the block of spin 0.
-__device__ __forceinline__ void load_phase(uint4 (&pv)[2][4], gptr<uint4> pcol, int64_t spin_stride) {
+// 16-byte units per 32-row chunk of the split gV: both spins' FP16 planes, then the
+// rows' scales
+template <int NTB>
+constexpr int gvs_chunk() { return 512 * NTB + 16; }
+
+// gV split once for the stored-phase backward (the recomputing backward splits it in
+// registers, the same way).  Per (signal, rate) and 32-row chunk: planes
+// [spin][kb][hl][h][i] of 8 halves, the values tau = 16 kb + 8 h + j of row 32 c + i
+// times 2^se (se = pow2_exp of the row's largest |gV|), hi or lo; then 2^-se of the
+// chunk's rows as [spin][32] floats.  One thread per (signal, rate, spin, row).
+template <int NTB>
+__global__ void k_gvsplit(const float* __restrict__ gV, int Mp, int64_t nrows, uint4* __restrict__ Gs) {
+    constexpr int NTp = 32 * NTB;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nrows) return;
+    const int l = (int)(e % Mp);
+    const int spin = (int)((e / Mp) & 1);
+    const int64_t ba = e / (2 * Mp);                 // signal x rate
+    const float4* row = (const float4*)(gV + e * NTp);
+    float4 v[NTp / 4];
+    float mx = 0.f;
+#pragma unroll
+    for (int q = 0; q < NTp / 4; ++q) {
+        v[q] = row[q];
+        mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[q].x), fabsf(v[q].y)), fmaxf(fabsf(v[q].z), fabsf(v[q].w))));
+    }
+    const int se = pow2_exp(mx);
+    const float sg = ldexpf(1.f, se);
+    uint4* blk = Gs + (ba * (Mp / 32) + l / 32) * gvs_chunk<NTB>();
+    const int i = l & 31;
+#pragma unroll
+    for (int kb = 0; kb < 2 * NTB; ++kb)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float4 x0 = v[4 * kb + 2 * h], x1 = v[4 * kb + 2 * h + 1];
+            const float vv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+            half8 hi8, lo8;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                _Float16 hi, lo;
+                split_h(vv[j] * sg, hi, lo);
+                hi8[j] = hi;
+                lo8[j] = lo;
+            }
+            blk[(((spin * 2 * NTB + kb) * 2 + 0) * 2 + h) * 32 + i] = __builtin_bit_cast(uint4, hi8);
+            blk[(((spin * 2 * NTB + kb) * 2 + 1) * 2 + h) * 32 + i] = __builtin_bit_cast(uint4, lo8);
+        }
+    ((float*)(blk + 512 * NTB))[spin * 32 + i] = ldexpf(1.f, -se);
+}
+
+// Chunk c of the split gV into LDS (all 256 threads; lane order = source order).
+template <int NTB>
+__device__ __forceinline__ void stage_g(uint4* Ls, const uint4* Gb, int c, int tid) {
+    const uint4* src = Gb + (int64_t)c * gvs_chunk<NTB>();
+    uint4* dst = Ls + 64 * (tid >> 6);
+#pragma unroll
+    for (int k = 0; k < 2 * NTB; ++k) dma16(src + 256 * k, (uint32_t)tid * 16u, dst + 256 * k);
+    if (tid < 16) dma16(src + 512 * NTB, (uint32_t)tid * 16u, Ls + 512 * NTB);
+}
+
+// Stored unit phase of rows crow(r, h), r = 8 s .. 8 s + 7 (g = 2 s, 2 s + 1), of one
+// 32-row block, this lane's column t, both spins: one 16-byte load (four rows) per
+// (spin, g).  pcol points at element 4 h of the lane's column in the block of spin 0.
+__device__ __forceinline__ void load_phase_half(uint4 (&pv)[2][4], int s, gptr<uint4> pcol, int64_t spin_stride) {
 #pragma unroll
     for (int spin = 0; spin < 2; ++spin)
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
+        for (int gg = 0; gg < 2; ++gg) {
+            const int g = 2 * s + gg;
             gptr<u32x4> p = (gptr<u32x4>)(pcol + (spin * spin_stride + 8 * g) / 4);   // element offsets, % 4 = 0
             pv[spin][g] = __builtin_bit_cast(uint4, p[0]);
         }
@@ -791,109 +852,148 @@ __device__ __forceinline__ float2 phase_at(const uint4 (&pv)[2][4], int spin, in
     return make_float2((float)(int)(short)(w & 0xffffu), (float)((int)w >> 16));
 }
 
-// One 32-row chunk c of the backward when the forward stored the unit phase u of
-// Z (both spins): gZ = gU u, then P, Q' and the W^T product as in k_freq_bwd_h.
-// On entry the chunk's gV rows and phase are in registers (loaded during the
-// previous chunk) and its W^T chunk is in LDS; the next chunk's W^T staging and
-// its gV and phase loads are issued after this chunk's modulus adjoint, ahead of
-// the W^T product, and waited for only at the chunk's end.
-template <int NTB, int NI>
-__device__ __forceinline__ void bwd_chunk_phase(int c, int nC, int Mp, int wave, int lane, int h, int i32,
-                                                const uint4 (&phv)[NTB * 2][2], const float* gvb,
-                                                const unsigned* pbase, int64_t spin_stride, int64_t c_stride,
-                                                float ips, float spq,
-                                                const uint4* Tcur, uint4* Tnext, const uint4* Tsrc,
-                                                floatx16 (&gyr)[NI], floatx16 (&gyi)[NI],
-                                                float4 (&v)[2][NTB * 2][2], uint4 (&pv)[2][4]) {
-    // ---- gU = gV Phi^T for both spins (gV split per row, Phi pre-split), times spq
-    floatx16 gu[2];
+// gU = gV Phi^T of one chunk for both spins (A operand from the split gV in LDS, Phi
+// pre-split in registers); each row then scaled by its 2^-se times c0 (the scale of
+// P and Q' over the snorm16 unit of the phase).
+template <int NTB>
+__device__ __forceinline__ void gu_chunk(const uint4* Lg, const uint4 (&phv)[NTB * 2][2], int h, int i32, float c0,
+                                         floatx16 (&gu)[2]) {
+    const float4* rs = (const float4*)(Lg + 512 * NTB);
 #pragma unroll
     for (int spin = 0; spin < 2; ++spin) {
-        float mx = 0.f;
-#pragma unroll
-        for (int kb = 0; kb < NTB * 2; ++kb) {
-            const float4 a0 = v[spin][kb][0], a1 = v[spin][kb][1];
-            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(a0.x), fabsf(a0.y)), fmaxf(fabsf(a0.z), fabsf(a0.w))));
-            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(a1.x), fabsf(a1.y)), fmaxf(fabsf(a1.z), fabsf(a1.w))));
-        }
-        mx = fmaxf(mx, __shfl_xor(mx, 32));
-        const int se = pow2_exp(mx);
-        const float sg = ldexpf(1.f, se);
         floatx16 acc = z16();
 #pragma unroll
         for (int kb = 0; kb < NTB * 2; ++kb) {
-            half8 ah, al;
-            const float vv[8] = {v[spin][kb][0].x, v[spin][kb][0].y, v[spin][kb][0].z, v[spin][kb][0].w,
-                                 v[spin][kb][1].x, v[spin][kb][1].y, v[spin][kb][1].z, v[spin][kb][1].w};
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                _Float16 hi, lo;
-                split_h(vv[j] * sg, hi, lo);
-                ah[j] = hi;
-                al[j] = lo;
-            }
+            const half8 ah = as_h8(Lg[(((spin * 2 * NTB + kb) * 2 + 0) * 2 + h) * 32 + i32]);
+            const half8 al = as_h8(Lg[(((spin * 2 * NTB + kb) * 2 + 1) * 2 + h) * 32 + i32]);
             const half8 bh = as_h8(phv[kb][0]), bl = as_h8(phv[kb][1]);
             acc = mfma16(ah, bh, acc);
             acc = mfma16(ah, bl, acc);
             acc = mfma16(al, bh, acc);
         }
-        const float isg = ldexpf(ips, -se);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] *= __shfl(isg, crow(r, h));
+        for (int g = 0; g < 4; ++g) {
+            const float4 q = rs[spin * 8 + 2 * g + h];        // rows 8 g + 4 h .. + 3
+            acc[4 * g + 0] *= q.x * c0;
+            acc[4 * g + 1] *= q.y * c0;
+            acc[4 * g + 2] *= q.z * c0;
+            acc[4 * g + 3] *= q.w * c0;
+        }
         gu[spin] = acc;
     }
-    // ---- modulus adjoint from the stored phase; P and Q' (FP32, carrying spq)
-    half8 ph[2][4], pl[2][4];       // [s'][Pr, Pi, Qr, Qi]
+}
+
+// Modulus adjoint of rows r = 8 s .. 8 s + 7 from the scaled gU and the stored
+// phase: P and Q', split into FP16 hi / lo (ph[s], pl[s]).
+__device__ __forceinline__ void modadj_half(int s, const floatx16 (&gu)[2], const uint4 (&pv)[2][4],
+                                            half8 (&ph)[2][4], half8 (&pl)[2][4]) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int rr = 0; rr < 8; ++rr) {
+        const int r = 8 * s + rr;
         const float2 u = phase_at(pv, 0, r), d = phase_at(pv, 1, r);
-        const float su = gu[0][r] * kSnormInv, sd = gu[1][r] * kSnormInv;
+        const float su = gu[0][r], sd = gu[1][r];
         const float vals[4] = {su * u.x + sd * d.x, su * u.y + sd * d.y, su * u.y - sd * d.y, sd * d.x - su * u.x};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             _Float16 hi, lo;
             split_h(vals[q], hi, lo);
-            ph[r >> 3][q][r & 7] = hi;
-            pl[r >> 3][q][r & 7] = lo;
+            ph[s][q][rr] = hi;
+            pl[s][q][rr] = lo;
         }
     }
-    __builtin_amdgcn_sched_barrier(0);
-    // ---- the next chunk: W^T staging, then its gV rows and phase (every wave has
-    // finished reading Tnext: it held the chunk before this one)
-    const int cn = c + 1 < nC ? c + 1 : c;
-    stage_t<NI>(Tnext, Tsrc, cn, wave, lane);
-    load_gv<NTB>(v, launder_s((const float4*)gvb), Mp, 32 * cn, i32, h);
-    load_phase(pv, launder_v((const uint4*)(pbase + cn * c_stride)), spin_stride);
-    __builtin_amdgcn_sched_barrier(0);
-    // ---- gY += Wr^T P + Wi^T Q' (A operand from the staged W^T chunk)
+}
+
+// gY += Wr^T P + Wi^T Q' over the rows of half sp of the chunk (A operand from the
+// staged W^T chunk), two i-blocks at a time so that four accumulations alternate.
+template <int NI>
+__device__ __forceinline__ void wh_half(int sp, const uint4* Tcur, int h, int i32, const half8 (&ph)[2][4],
+                                        const half8 (&pl)[2][4], floatx16 (&gyr)[NI], floatx16 (&gyi)[NI]) {
 #pragma unroll
     for (int q0 = 0; q0 < NI; q0 += 2) {
+        half8 wr[2][2], wi[2][2];             // [block][hi, lo]
 #pragma unroll
-        for (int sp = 0; sp < 2; ++sp) {
-            half8 wr[2][2], wi[2][2];             // [block][hi, lo]
+        for (int d = 0; d < 2; ++d) {
+            const int q = q0 + d < NI ? q0 + d : q0;
+            const uint4* lt = Tcur + (q * 16 + (sp * 2 + h) * 4) * 32 + i32;
+            wr[d][0] = as_h8(lt[0]); wr[d][1] = as_h8(lt[32]);
+            wi[d][0] = as_h8(lt[64]); wi[d][1] = as_h8(lt[96]);
+        }
+#pragma unroll
+        for (int term = 0; term < 6; ++term) {
+            const int wsel = term < 3 ? 0 : 1, whl = (term % 3) == 2 ? 1 : 0, phl = (term % 3) == 1 ? 1 : 0;
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
-                const int q = q0 + d < NI ? q0 + d : q0;
-                const uint4* lt = Tcur + (q * 16 + (sp * 2 + h) * 4) * 32 + i32;
-                wr[d][0] = as_h8(lt[0]); wr[d][1] = as_h8(lt[32]);
-                wi[d][0] = as_h8(lt[64]); wi[d][1] = as_h8(lt[96]);
+                if (q0 + d >= NI) continue;
+                const half8 a = wsel ? wi[d][whl] : wr[d][whl];
+                const half8 br = phl ? pl[sp][wsel * 2] : ph[sp][wsel * 2];
+                const half8 bi = phl ? pl[sp][wsel * 2 + 1] : ph[sp][wsel * 2 + 1];
+                gyr[q0 + d] = mfma16(a, br, gyr[q0 + d]);
+                gyi[q0 + d] = mfma16(a, bi, gyi[q0 + d]);
             }
-#pragma unroll
-            for (int term = 0; term < 6; ++term) {
-                const int wsel = term < 3 ? 0 : 1, whl = (term % 3) == 2 ? 1 : 0, phl = (term % 3) == 1 ? 1 : 0;
-#pragma unroll
-                for (int d = 0; d < 2; ++d) {
-                    if (q0 + d >= NI) continue;
-                    const half8 a = wsel ? wi[d][whl] : wr[d][whl];
-                    const half8 br = phl ? pl[sp][wsel * 2] : ph[sp][wsel * 2];
-                    const half8 bi = phl ? pl[sp][wsel * 2 + 1] : ph[sp][wsel * 2 + 1];
-                    gyr[q0 + d] = mfma16(a, br, gyr[q0 + d]);
-                    gyi[q0 + d] = mfma16(a, bi, gyi[q0 + d]);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
         }
     }
+}
+
+// Scheduling hint for a half: NM groups of one MFMA followed by NV VALU
+// instructions, so that the vector work of the next rows issues while the matrix
+// cores work (one wave per SIMD: nothing else would fill those cycles).
+template <int NM, int NV>
+__device__ __forceinline__ void interleave_mfma_valu() {
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);
+    }
+}
+
+// Values a half produces for the next half are pinned before its barrier (an empty
+// asm that reads and writes them), so that the compiler cannot sink their
+// arithmetic past the barrier into the next half, where it would not overlap with
+// matrix work.
+__device__ __forceinline__ void pin_pq(half8 (&ph)[2][4], half8 (&pl)[2][4], int s) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(ph[s][q]), "+v"(pl[s][q]));
+}
+__device__ __forceinline__ void pin_gu(floatx16 (&gu)[2]) {
+    asm volatile("" : "+v"(gu[0]), "+v"(gu[1]));
+}
+
+// One 32-row chunk c in two halves.  On entry: P/Q' of rows 0-15 in ph/pl[0], gU of
+// the chunk (scaled) in gu, the phase of rows 16-31 in pv[.][2..3], W^T of the chunk
+// in Tcur.  First half: the W^T product over rows 0-15 while the modulus adjoint of
+// rows 16-31 runs; the next chunk's W^T, split gV and phase of rows 0-15 are
+// requested at its start.  Second half: the product over rows 16-31 while gU of the
+// next chunk and the modulus adjoint of its rows 0-15 run; the phase of its rows
+// 16-31 is requested at its start.  Each half ends with a full wait and a barrier,
+// so every request has a half chunk of matrix work to land.
+template <int NTB, int NI>
+__device__ __forceinline__ void bwd_phase_chunk(int c, int nC, int wave, int lane, int tid, int h, int i32,
+                                                const uint4 (&phv)[NTB * 2][2], const uint4* Tsrc, const uint4* Gb,
+                                                uint4* Ls_G, const unsigned* pbase, int64_t spin_stride,
+                                                int64_t c_stride, float c0, const uint4* Tcur, uint4* Tnext,
+                                                floatx16 (&gyr)[NI], floatx16 (&gyi)[NI], floatx16 (&gu)[2],
+                                                uint4 (&pv)[2][4], half8 (&ph)[2][4], half8 (&pl)[2][4]) {
+    const int cn = c + 1 < nC ? c + 1 : c;       // the last chunk reloads itself
+    stage_t<NI>(Tnext, Tsrc, cn, wave, lane);
+    stage_g<NTB>(Ls_G, Gb, cn, tid);
+    load_phase_half(pv, 0, launder_v((const uint4*)(pbase + cn * c_stride)), spin_stride);
+    __builtin_amdgcn_sched_barrier(0);
+    wh_half<NI>(0, Tcur, h, i32, ph, pl, gyr, gyi);
+    modadj_half(1, gu, pv, ph, pl);
+    pin_pq(ph, pl, 1);
+    interleave_mfma_valu<NI * 12, 3>();
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    load_phase_half(pv, 1, launder_v((const uint4*)(pbase + cn * c_stride)), spin_stride);
+    __builtin_amdgcn_sched_barrier(0);
+    wh_half<NI>(1, Tcur, h, i32, ph, pl, gyr, gyi);
+    gu_chunk<NTB>(Ls_G, phv, h, i32, c0, gu);
+    modadj_half(0, gu, pv, ph, pl);
+    pin_pq(ph, pl, 0);
+    pin_gu(gu);
+    interleave_mfma_valu<NI * 12 + 6 * NTB, 3>();
+    __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 }
@@ -904,13 +1004,14 @@ template <int NTB, int NI>
 __global__ void __launch_bounds__(256) k_freq_bwd_p(const unsigned* __restrict__ phase, int64_t ph_bstride, int Tp,
                                                     int nTt, int nU, const unsigned short* __restrict__ WTsp,
                                                     int Mp, int Kp, const unsigned short* __restrict__ PhTsp,
-                                                    float sphi, const float* __restrict__ gV, int64_t gv_bstride,
+                                                    float sphi, const uint4* __restrict__ Gs, int64_t gs_bstride,
                                                     const float* __restrict__ gvmax, int n_beta, int alpha,
                                                     int n_alpha, float sw, float2* __restrict__ gY,
                                                     int64_t gy_bstride) {
     constexpr int NTp = 32 * NTB;
     __shared__ uint4 Ls_T0[NI * 512];
     __shared__ uint4 Ls_T1[NI * 512];
+    __shared__ uint4 Ls_G[gvs_chunk<NTB>()];
     const int u = blockIdx.x;
     if (u >= nU) return;                            // whole block
     const int64_t b = u / nTt;
@@ -923,15 +1024,15 @@ __global__ void __launch_bounds__(256) k_freq_bwd_p(const unsigned* __restrict__
     float G = 0.f;
     for (int q = 0; q < 2 * n_beta; ++q) G = fmaxf(G, gvmax[(b * n_alpha + alpha) * 2 * n_beta + q]);
     const float spq = pow2_scale(2.f * G * 16384.f / sphi);
-    const float ips = spq / sphi;
+    const float c0 = spq / sphi * kSnormInv;
 
     floatx16 gyr[NI], gyi[NI];
 #pragma unroll
     for (int q = 0; q < NI; ++q) { gyr[q] = z16(); gyi[q] = z16(); }
 
-    const float* gvb = gV + b * gv_bstride;
     const uint4* phrow = (const uint4*)(PhTsp + ((int64_t)(tw0 + i32) * (NTp / 8) + h) * 16);
     const uint4* Tsrc = (const uint4*)WTsp;
+    const uint4* Gb = Gs + b * gs_bstride;
     // this lane's column of the stored phase, rows 4h.. of each 32-row block
     // (blocks [spin][Mp / 32], each Tp x 32 elements)
     const unsigned* pbase = phase + b * ph_bstride + (int64_t)(tw0 + i32) * 32 + 4 * h;
@@ -943,19 +1044,26 @@ __global__ void __launch_bounds__(256) k_freq_bwd_p(const unsigned* __restrict__
         phv[kb][0] = phrow[4 * kb];
         phv[kb][1] = phrow[4 * kb + 1];
     }
-    float4 v[2][NTB * 2][2];
     uint4 pv[2][4];
-    load_gv<NTB>(v, (gptr<float4>)gvb, Mp, 0, i32, h);
-    load_phase(pv, (gptr<uint4>)pbase, spin_stride);
+    floatx16 gu[2];
+    half8 ph[2][4], pl[2][4];
+    // chunk 0: operands, gU and the P/Q' of its rows 0-15
     stage_t<NI>(Ls_T0, Tsrc, 0, wave, lane);
+    stage_g<NTB>(Ls_G, Gb, 0, tid);
+    load_phase_half(pv, 0, (gptr<uint4>)pbase, spin_stride);
+    load_phase_half(pv, 1, (gptr<uint4>)pbase, spin_stride);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    gu_chunk<NTB>(Ls_G, phv, h, i32, c0, gu);
+    modadj_half(0, gu, pv, ph, pl);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     // nC is even (Mp is a multiple of 64): the W^T buffers alternate at compile time
     for (int c = 0; c < nC; c += 2) {
-        bwd_chunk_phase<NTB, NI>(c, nC, Mp, wave, lane, h, i32, phv, gvb, pbase, spin_stride, c_stride, ips, spq, Ls_T0,
-                                 Ls_T1, Tsrc, gyr, gyi, v, pv);
-        bwd_chunk_phase<NTB, NI>(c + 1, nC, Mp, wave, lane, h, i32, phv, gvb, pbase, spin_stride, c_stride, ips, spq, Ls_T1,
-                                 Ls_T0, Tsrc, gyr, gyi, v, pv);
+        bwd_phase_chunk<NTB, NI>(c, nC, wave, lane, tid, h, i32, phv, Tsrc, Gb, Ls_G, pbase, spin_stride, c_stride,
+                                 c0, Ls_T0, Ls_T1, gyr, gyi, gu, pv, ph, pl);
+        bwd_phase_chunk<NTB, NI>(c + 1, nC, wave, lane, tid, h, i32, phv, Tsrc, Gb, Ls_G, pbase, spin_stride,
+                                 c_stride, c0, Ls_T1, Ls_T0, gyr, gyi, gu, pv, ph, pl);
     }
     const float inv = 1.f / (sw * spq);
     float2* o = gY + b * gy_bstride;
@@ -1170,13 +1278,13 @@ int launch_freq_bwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, c
 
 template <int NTB>
 static void launch_bwdp_ni(int NI, dim3 grid, hipStream_t st, const unsigned* pha, int64_t phb, int Tp, int nTt,
-                           int nU, const jtfs_plan* P, const unsigned short* PhT, float sphi, const float* gVa,
-                           int64_t gvb, const float* gvmax, int a, float2* gYa, int64_t gyb) {
+                           int nU, const jtfs_plan* P, const unsigned short* PhT, float sphi, const uint4* Gsa,
+                           int64_t gsb, const float* gvmax, int a, float2* gYa, int64_t gyb) {
     const Shapes& s = P->s;
 #define JTFS_BWDP_CASE(ni)                                                                                    \
     case ni:                                                                                                  \
         hipLaunchKernelGGL((k_freq_bwd_p<NTB, ni>), grid, dim3(256), 0, st, pha, phb, Tp, nTt, nU, P->WTsp, \
-                           s.Mp, s.Kp, PhT, sphi, gVa, gvb, gvmax, s.n_beta, a, s.n_alpha, P->sw, gYa, gyb);  \
+                           s.Mp, s.Kp, PhT, sphi, Gsa, gsb, gvmax, s.n_beta, a, s.n_alpha, P->sw, gYa, gyb);  \
         break;
     if constexpr (NTB == 1) {
         switch (NI) {
@@ -1193,8 +1301,20 @@ static void launch_bwdp_ni(int NI, dim3 grid, hipStream_t st, const unsigned* ph
 #undef JTFS_BWDP_CASE
 }
 
-int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int64_t ph_bstride, const float* gV,
-                          const float* gvmax, float2* gY2, int64_t B, hipStream_t st) {
+int launch_gv_split(const jtfs_plan* P, const float* gV, uint4* Gs, int64_t B, hipStream_t st) {
+    const Shapes& s = P->s;
+    const int64_t nrows = B * s.n_alpha * 2 * (int64_t)s.Mp;
+    const unsigned grid = (unsigned)((nrows + 255) / 256);
+    switch (s.NTp / 32) {
+        case 1: hipLaunchKernelGGL(k_gvsplit<1>, dim3(grid), dim3(256), 0, st, gV, s.Mp, nrows, Gs); break;
+        case 2: hipLaunchKernelGGL(k_gvsplit<2>, dim3(grid), dim3(256), 0, st, gV, s.Mp, nrows, Gs); break;
+        default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
+    }
+    return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
+}
+
+int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int64_t ph_bstride, const uint4* Gs,
+                          int64_t gs_bstride, const float* gvmax, float2* gY2, int64_t B, hipStream_t st) {
     const Shapes& s = P->s;
     const int NI = P->KpT / 32;
     if (!P->split_bwd_ok) { set_error("split backward not available for these shapes"); return JTFS_ENOTSUP; }
@@ -1203,12 +1323,12 @@ int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int6
     const int64_t yb = (int64_t)s.Kp * s.sumTp;
     const unsigned* pha = phase + (int64_t)2 * s.Mp * (s.yoff[a] / s.Kp);
     const unsigned short* PhT = P->PhTsp + s.phioff[a] * 2;
-    const float* gVa = gV + (int64_t)a * 2 * s.Mp * s.NTp;
-    const int64_t gvb = (int64_t)s.n_alpha * 2 * s.Mp * s.NTp;
+    // this rate's chunks of the split gV
+    const uint4* Gsa = Gs + (int64_t)a * (s.Mp / 32) * (512 * (s.NTp / 32) + 16);
     float2* gYa = gY2 + s.yoff[a];
     switch (s.NTp / 32) {
-        case 1: launch_bwdp_ni<1>(NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], gVa, gvb, gvmax, a, gYa, yb); break;
-        case 2: launch_bwdp_ni<2>(NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], gVa, gvb, gvmax, a, gYa, yb); break;
+        case 1: launch_bwdp_ni<1>(NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], Gsa, gs_bstride, gvmax, a, gYa, yb); break;
+        case 2: launch_bwdp_ni<2>(NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], Gsa, gs_bstride, gvmax, a, gYa, yb); break;
         default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
     }
     return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;

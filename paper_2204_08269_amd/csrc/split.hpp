@@ -19,6 +19,9 @@ int launch_freq_bwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, c
 int launch_freq_fwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, const float* yscale, float* Vp,
                           int64_t vp_bstride, unsigned* phase, int64_t ph_bstride, int64_t B, hipStream_t st);
 // backward contraction from the phase the forward stored (no recomputation of Z)
-int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int64_t ph_bstride, const float* gV,
-                          const float* gvmax, float2* gY2, int64_t B, hipStream_t st);
+int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int64_t ph_bstride, const uint4* Gs,
+                          int64_t gs_bstride, const float* gvmax, float2* gY2, int64_t B, hipStream_t st);
+// gV of every rate split into the FP16 planes and row scales the stored-phase
+// backward reads (Gs: gs_bstride 16-byte units per signal)
+int launch_gv_split(const jtfs_plan* P, const float* gV, uint4* Gs, int64_t B, hipStream_t st);
 }  // namespace jtfs
