@@ -83,7 +83,7 @@ struct Workspace {
 };
 // with_split: the split-FP16 operand copy of Y2; with_pq: the FP32 backward's P/Q';
 // with_phase: the stored unit phase of the contraction output, per signal and rate
-// [spin][Mp / 32][Tp][32] elements of two snorm16.
+// [spin][Mp / 32][4][Tp][8] elements of two snorm16.
 Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq, bool with_phase);
 
 }  // namespace jtfs
@@ -137,7 +137,7 @@ struct jtfs_plan {
     float sw = 1.f;
     unsigned short* Phsp = nullptr;  // per alpha [Tp/32][2][2][NTp][2][8]: Phi * sphi[alpha]
     int KpT = 0;                   // Kp rounded up to 32 (rows of WTsp)
-    unsigned short* WTsp = nullptr;  // [KpT][Mp/32][2][2][4][8]: W^T * sw in C-register row order
+    unsigned short* WTsp = nullptr;  // [Mp/32][KpT/32][16][32][8]: W^T * sw, chunks in LDS order
     unsigned short* PhTsp = nullptr; // per alpha [Tp][NTp/8][2][8]: Phi * sphi[alpha], tau contiguous
     std::vector<float> sphi;
     void* owned = nullptr;         // list of device allocations released by destroy

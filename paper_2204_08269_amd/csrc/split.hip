@@ -99,10 +99,11 @@ __global__ void k_phsplit(const float* __restrict__ Phi, int Tp, int NTp, float 
     o[8] = lo;
 }
 
-// WTsp[c][i][s][h][p][j]: W[l][i] * sw split (p = re hi, re lo, im hi, im lo) for
-// l = 32 c + crow(8 s + j, h): the rows of a 32-row chunk in the order in which the
-// contraction's C registers hold them; chunk-major, so that the KpT x 32 block of
-// one chunk is contiguous.  Rows i >= Kp are zero.
+// WTsp[c][q][seg][i32][j], seg = (s * 2 + h) * 4 + p: W[l][i] * sw split (p = re hi,
+// re lo, im hi, im lo) for i = 32 q + i32 and l = 32 c + crow(8 s + j, h): the rows of
+// a 32-row chunk in the order in which the contraction's C registers hold them.  A
+// chunk (KpT x 32) is contiguous and laid out exactly as the backward holds it in
+// LDS, so that its staging copies contiguous 1 KB runs.  Rows i >= Kp are zero.
 __global__ void k_wtsplit(const float2* __restrict__ Wl, int Mp, int Kp, int KpT, float sw,
                           unsigned short* __restrict__ WTsp) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,8 +119,9 @@ __global__ void k_wtsplit(const float2* __restrict__ Wl, int Mp, int Kp, int KpT
     _Float16 a, b, cc, d;
     split_h(w.x * sw, a, b);
     split_h(w.y * sw, cc, d);
-    _Float16* o = (_Float16*)WTsp + ((((int64_t)c * KpT + i) * 2 + s) * 2 + h) * 32 + j;
-    o[0] = a; o[8] = b; o[16] = cc; o[24] = d;
+    _Float16* o = (_Float16*)WTsp +
+                  ((int64_t)c * KpT * 16 + (i >> 5) * 512 + ((s * 2 + h) * 4) * 32 + (i & 31)) * 8 + j;
+    o[0] = a; o[256] = b; o[512] = cc; o[768] = d;        // p = 0..3: 32 uint4 apart
 }
 
 // PhTsp[t][g][p][j] = split(Phi[t][8 g + j] * sphi): tau-contiguous rows of Phi.
@@ -137,10 +139,11 @@ __global__ void k_phtsplit(const float* __restrict__ Phi, int Tp, int NTp, float
 
 // ------------------------------------------------------------ Y2 conversion
 
-// Yh[t][kb][p][j] = split(Y2[k][t] * sy) (k = 8 kb + j), transposed so that each
-// lane of the contraction reads 8 consecutive lambda_1 of one t.  sy = 2^(13-e)
-// from the block maximum (row maxima written by the second-order kernel).
-// grid (Tp/64, B), 256 threads.
+// Yh[t / 32][kb][p][t % 32][j] = split(Y2[k][t] * sy) (k = 8 kb + j; p = re hi, re
+// lo, im hi, im lo): each lane of the contraction reads 8 consecutive lambda_1 of
+// one t as 16 bytes, and the 32 lanes of a column block read 512 contiguous bytes.
+// sy = 2^(13-e) from the block maximum (row maxima written by the second-order
+// kernel).  grid (Tp/64, B), 256 threads.
 __global__ void __launch_bounds__(256) k_ysplit(const float2* __restrict__ Y, int64_t y_bstride, int Tp, int Kp,
                                                 const float* __restrict__ rowmax, int alpha, int n_alpha,
                                                 unsigned short* __restrict__ Yh, float* __restrict__ yscale) {
@@ -169,12 +172,12 @@ __global__ void __launch_bounds__(256) k_ysplit(const float2* __restrict__ Y, in
             tile[r][c] = Yb[(int64_t)(k0 + r) * Tp + t0 + c];
         }
         __syncthreads();
-        // one work item per (t, k-group, plane): consecutive lanes store consecutive
-        // 16-byte planes, so that a column's k-groups go out as one contiguous run
+        // one work item per (t, k-group, plane), t fastest: consecutive lanes store
+        // consecutive 16-byte planes of one (k-group, plane)
         const int nkb = nk / 8;
         for (int e = threadIdx.x; e < 64 * nkb * 4; e += 256) {
-            const int pl = e & 3, g = e >> 2;
-            const int t = g / nkb, kb = g % nkb;
+            const int t = e & 63, g = e >> 6;
+            const int pl = g & 3, kb = g >> 2;
             half8 out;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -183,8 +186,9 @@ __global__ void __launch_bounds__(256) k_ysplit(const float2* __restrict__ Y, in
                 split_h((pl < 2 ? v.x : v.y) * sy, hi, lo);
                 out[j] = (pl & 1) ? lo : hi;
             }
-            half8* o = (half8*)(Ho + ((int64_t)(t0 + t) * (Kp / 8) + k0 / 8 + kb) * 32);
-            o[pl] = out;
+            const int tt = t0 + t;
+            half8* o = (half8*)Ho + ((((int64_t)(tt >> 5) * (Kp / 8) + k0 / 8 + kb) * 4 + pl) * 32 + (tt & 31));
+            *o = out;
         }
     }
 }
@@ -210,14 +214,16 @@ __device__ __forceinline__ gptr<T> launder_s(const T* p) {
     return g;
 }
 
-// Y fragments of k-step kq (k-groups 2 kq + h) of this lane's column
+// Y fragments of k-step kq (k-groups 2 kq + h) of this lane's column: ycol points
+// at plane 0 of k-group h of the lane's column; k-groups are 128 uint4 apart and
+// planes 32
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void load_y(uint4 (&y)[4], gptr<uint4> ycol, int kq) {
-    gptr<u32x4> p = (gptr<u32x4>)(ycol + 8 * kq);
+    gptr<u32x4> p = (gptr<u32x4>)(ycol + 256 * kq);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) y[j] = __builtin_bit_cast(uint4, p[j]);
+    for (int j = 0; j < 4; ++j) y[j] = __builtin_bit_cast(uint4, p[32 * j]);
 }
 
 // The stored unit phase: two values in [-1, 1] as snorm16, round(x 32767), the
@@ -292,7 +298,7 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
     // so that waiting for them never waits for Y.
     const int tbeg = ch * chunk, tend = (ch + 1) * chunk;
     auto ycol_at = [&](int t0) {
-        return launder_v((const uint4*)(Yb + ((int64_t)(t0 + wt * 32 + i32) * nkb + h) * 32));
+        return launder_v((const uint4*)Yb + (((int64_t)((t0 >> 5) + wt) * nkb + h) * 128 + i32));
     };
     constexpr int NR0 = NTB == 1 ? 4 : 2;                     // ring depth within the register budget
     constexpr int NR = NK < NR0 ? NK : NR0;
@@ -318,8 +324,11 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
             load_phi(0, 1, phf[1]);
         }
         // K loop, unrolled: k-step kq lives in ring slot kq % NR; W fragments are
-        // read one k-step ahead, and a scheduling barrier closes every k-step so
-        // that the LDS reads are not all hoisted to the top
+        // read one k-step ahead, at the top of the k-step (a scheduling barrier
+        // keeps them there: left to itself the compiler issues them after the
+        // k-step's products, and the next k-step then waits for LDS), and a
+        // scheduling barrier closes every k-step so that the LDS reads are not
+        // all hoisted to the top
         floatx16 rr = z16(), ir = z16(), ri = z16(), ii = z16();
         uint4 wc[4];
 #pragma unroll
@@ -331,6 +340,7 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
 #pragma unroll
                 for (int j = 0; j < 4; ++j) wn[j] = *(const uint4*)(wbase + (kq + 1) * 128 + 16 * j);
             }
+            __builtin_amdgcn_sched_barrier(0);
             const half8 w0 = as_h8(wc[0]), w1 = as_h8(wc[1]), w2 = as_h8(wc[2]), w3 = as_h8(wc[3]);
             uint4(&q)[4] = yr[kq % NR];
             const half8 y0 = as_h8(q[0]), y1 = as_h8(q[1]), y2 = as_h8(q[2]), y3 = as_h8(q[3]);
@@ -355,25 +365,33 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
         if constexpr (early) next_tile();
         // modulus of both spins, per-column scale, split, second product with Phi;
         // with phase storage also u = z / max(|z|, eps) for the backward, as two
-        // snorm16 (real in the low half), in 32-row blocks of l: element
-        // ((spin, l / 32), t, l % 32); the floor is in the scaled units of z
+        // snorm16 (real in the low half), in groups of 8 rows l: element
+        // ((spin, l / 32, (l % 32) / 8), t, l % 8); the floor is in the scaled
+        // units of z
 #pragma unroll
         for (int spin = 0; spin < 2; ++spin) {
             float uval[16];
             float m = 0.f;
             unsigned* pcol = phase ? phase + b * ph_bstride +
-                                         ((int64_t)(spin * nlt + lt) * 2 + wl) * Tp * 32 + (int64_t)(t0 + wt * 32) * 32 + i32
+                                         (((int64_t)(spin * nlt + lt) * 2 + wl) * 4 + (i32 >> 3)) * Tp * 8 +
+                                         (int64_t)(t0 + wt * 32) * 8 + (i32 & 7)
                                    : nullptr;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const float zr = spin ? rr[r] + ii[r] : rr[r] - ii[r];
                 const float zi = spin ? ir[r] - ri[r] : ir[r] + ri[r];
-                const float z2 = zr * zr + zi * zi;
-                uval[r] = __builtin_amdgcn_sqrtf(z2);   // hardware square root (1 ulp)
+                uval[r] = __builtin_amdgcn_sqrtf(zr * zr + zi * zi);   // hardware square root (1 ulp)
                 m = fmaxf(m, uval[r]);
-                if (pcol) {
-                    const float q = __builtin_amdgcn_rsqf(fmaxf(z2, eps2s));
-                    pcol[crow(r, h) * 32] = pack_snorm16(zr * q, zi * q);
+            }
+            // one branch per spin (not per element), so that the 16 stores share
+            // one address with immediate offsets
+            if (pcol) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float zr = spin ? rr[r] + ii[r] : rr[r] - ii[r];
+                    const float zi = spin ? ir[r] - ri[r] : ir[r] + ri[r];
+                    const float q = __builtin_amdgcn_rsqf(fmaxf(zr * zr + zi * zi, eps2s));
+                    pcol[crow(r, h) * 8] = pack_snorm16(zr * q, zi * q);
                 }
             }
             m = fmaxf(m, __shfl_xor(m, 32));
@@ -493,16 +511,16 @@ __device__ __forceinline__ void stage_w(uint4* Ls, const uint4* Wsrc, int c, int
     for (int j = 0; j < nK; ++j) dma16(base + 8 * j, off, dst + 256 * j);
 }
 
-// W^T chunk c (KpT = 32 NI rows): LDS slot e = seg * 32 + i32, seg = q * 16 + (sp * 2 + h) * 4 + p.
-// Group g = wave + 4 k: seg = 8 k + 2 wave + h, i.e. q = k >> 1 and the segment
-// inside q is 8 (k & 1) + 2 wave + h.
+// W^T chunk c (KpT = 32 NI rows) into LDS, slot e = seg * 32 + i32 with
+// seg = q * 16 + (sp * 2 + h) * 4 + p: the table holds the chunk in this order, so
+// that the wave's 64 lanes copy 1 KB runs.
 template <int NI>
 __device__ __forceinline__ void stage_t(uint4* Ls, const uint4* Tsrc, int c, int wave, int lane) {
     const uint4* base = Tsrc + (int64_t)c * (NI * 512);
-    const uint32_t off = (uint32_t)((lane & 31) * 16 + 2 * wave + (lane >> 5)) * 16u;
+    const uint32_t off = (uint32_t)(wave * 64 + lane) * 16u;
     uint4* dst = Ls + wave * 64;
 #pragma unroll
-    for (int k = 0; k < 2 * NI; ++k) dma16(base + (k >> 1) * 512 + 8 * (k & 1), off, dst + 256 * k);
+    for (int k = 0; k < 2 * NI; ++k) dma16(base + 256 * k, off, dst + 256 * k);
 }
 
 // gV rows l0 + i32 of both spins, this lane's tau half (8 h.. of each 16)
@@ -728,7 +746,7 @@ __global__ void __launch_bounds__(256) k_freq_bwd_h(const unsigned short* __rest
     for (int q = 0; q < NI; ++q) { gyr[q] = z16(); gyi[q] = z16(); }
 
     const unsigned short* Yb = Yh + b * yh_bstride;
-    const uint4* ycol = (const uint4*)(Yb + ((int64_t)(tw0 + i32) * nkb + h) * 32);   // B operand: column t
+    const uint4* ycol = (const uint4*)Yb + (((int64_t)(tw0 >> 5) * nkb + h) * 128 + i32);   // B operand: column t
     const float* gvb = gV + b * gv_bstride;
     const uint4* phrow = (const uint4*)(PhTsp + ((int64_t)(tw0 + i32) * (NTp / 8) + h) * 16);
     const uint4* Wsrc = (const uint4*)Wsp;
@@ -833,14 +851,17 @@ __device__ __forceinline__ void stage_g(uint4* Ls, const uint4* Gb, int c, int t
 
 // Stored unit phase of rows crow(r, h), r = 8 s .. 8 s + 7 (g = 2 s, 2 s + 1), of one
 // 32-row block, this lane's column t, both spins: one 16-byte load (four rows) per
-// (spin, g).  pcol points at element 4 h of the lane's column in the block of spin 0.
-__device__ __forceinline__ void load_phase_half(uint4 (&pv)[2][4], int s, gptr<uint4> pcol, int64_t spin_stride) {
+// (spin, g); a wave's load is one contiguous 1 KB run.  pcol points at element 4 h
+// of the lane's column in row group 0 of the block of spin 0; row groups are
+// g_stride elements apart.
+__device__ __forceinline__ void load_phase_half(uint4 (&pv)[2][4], int s, gptr<uint4> pcol, int64_t spin_stride,
+                                                int64_t g_stride) {
 #pragma unroll
     for (int spin = 0; spin < 2; ++spin)
 #pragma unroll
         for (int gg = 0; gg < 2; ++gg) {
             const int g = 2 * s + gg;
-            gptr<u32x4> p = (gptr<u32x4>)(pcol + (spin * spin_stride + 8 * g) / 4);   // element offsets, % 4 = 0
+            gptr<u32x4> p = (gptr<u32x4>)(pcol + (spin * spin_stride + g * g_stride) / 4);   // element offsets, % 4 = 0
             pv[spin][g] = __builtin_bit_cast(uint4, p[0]);
         }
 }
@@ -976,7 +997,7 @@ __device__ __forceinline__ void bwd_phase_chunk(int c, int nC, int wave, int lan
     const int cn = c + 1 < nC ? c + 1 : c;       // the last chunk reloads itself
     stage_t<NI>(Tnext, Tsrc, cn, wave, lane);
     stage_g<NTB>(Ls_G, Gb, cn, tid);
-    load_phase_half(pv, 0, launder_v((const uint4*)(pbase + cn * c_stride)), spin_stride);
+    load_phase_half(pv, 0, launder_v((const uint4*)(pbase + cn * c_stride)), spin_stride, c_stride / 4);
     __builtin_amdgcn_sched_barrier(0);
     wh_half<NI>(0, Tcur, h, i32, ph, pl, gyr, gyi);
     modadj_half(1, gu, pv, ph, pl);
@@ -985,7 +1006,7 @@ __device__ __forceinline__ void bwd_phase_chunk(int c, int nC, int wave, int lan
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    load_phase_half(pv, 1, launder_v((const uint4*)(pbase + cn * c_stride)), spin_stride);
+    load_phase_half(pv, 1, launder_v((const uint4*)(pbase + cn * c_stride)), spin_stride, c_stride / 4);
     __builtin_amdgcn_sched_barrier(0);
     wh_half<NI>(1, Tcur, h, i32, ph, pl, gyr, gyi);
     gu_chunk<NTB>(Ls_G, phv, h, i32, c0, gu);
@@ -1033,9 +1054,9 @@ __global__ void __launch_bounds__(256) k_freq_bwd_p(const unsigned* __restrict__
     const uint4* phrow = (const uint4*)(PhTsp + ((int64_t)(tw0 + i32) * (NTp / 8) + h) * 16);
     const uint4* Tsrc = (const uint4*)WTsp;
     const uint4* Gb = Gs + b * gs_bstride;
-    // this lane's column of the stored phase, rows 4h.. of each 32-row block
-    // (blocks [spin][Mp / 32], each Tp x 32 elements)
-    const unsigned* pbase = phase + b * ph_bstride + (int64_t)(tw0 + i32) * 32 + 4 * h;
+    // this lane's column of the stored phase, rows 4h.. of each 8-row group
+    // (blocks [spin][Mp / 32], each four row groups of Tp x 8 elements)
+    const unsigned* pbase = phase + b * ph_bstride + (int64_t)(tw0 + i32) * 8 + 4 * h;
     const int64_t spin_stride = (int64_t)Tp * Mp, c_stride = (int64_t)Tp * 32;
 
     uint4 phv[NTB * 2][2];
@@ -1050,8 +1071,8 @@ __global__ void __launch_bounds__(256) k_freq_bwd_p(const unsigned* __restrict__
     // chunk 0: operands, gU and the P/Q' of its rows 0-15
     stage_t<NI>(Ls_T0, Tsrc, 0, wave, lane);
     stage_g<NTB>(Ls_G, Gb, 0, tid);
-    load_phase_half(pv, 0, (gptr<uint4>)pbase, spin_stride);
-    load_phase_half(pv, 1, (gptr<uint4>)pbase, spin_stride);
+    load_phase_half(pv, 0, (gptr<uint4>)pbase, spin_stride, c_stride / 4);
+    load_phase_half(pv, 1, (gptr<uint4>)pbase, spin_stride, c_stride / 4);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     gu_chunk<NTB>(Ls_G, phv, h, i32, c0, gu);
