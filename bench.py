@@ -130,6 +130,8 @@ def algorithmic_bytes(info, N, shapes, B):
 # profiles with the hash of the kernel's source; stale once that source changes.
 TRAFFIC_FILES = {("freq_adj_pq", "split16"): ("profiles/k_freq_bwd_h_64x65536_hbm_traffic.json",
                                             "paper_2204_08269_amd/csrc/split.hip"),
+                 ("freq_fwd", "split16_phase"): ("profiles/k_freq_fwd_h_phase_64x65536_hbm_traffic.json",
+                                               "paper_2204_08269_amd/csrc/split.hip"),
                  ("freq_adj_pq", "split16_phase"): ("profiles/k_freq_bwd_p_64x65536_hbm_traffic.json",
                                                   "paper_2204_08269_amd/csrc/split.hip")}
 
