@@ -904,12 +904,13 @@ __device__ __forceinline__ void gu_chunk(const uint4* Lg, const uint4 (&phv)[NTB
     }
 }
 
-// Modulus adjoint of rows r = 8 s .. 8 s + 7 from the scaled gU and the stored
-// phase: P and Q', split into FP16 hi / lo (ph[s], pl[s]).
-__device__ __forceinline__ void modadj_half(int s, const floatx16 (&gu)[2], const uint4 (&pv)[2][4],
+// Modulus adjoint of rows r = 8 s + r0 .. 8 s + r1 - 1 from the scaled gU and the
+// stored phase: P and Q', split into FP16 hi / lo (lanes r - 8 s of ph[s], pl[s]).
+__device__ __forceinline__ void modadj_rows(int s, int r0, int r1, const floatx16 (&gu)[2], const uint4 (&pv)[2][4],
                                             half8 (&ph)[2][4], half8 (&pl)[2][4]) {
 #pragma unroll
     for (int rr = 0; rr < 8; ++rr) {
+        if (rr < r0 || rr >= r1) continue;
         const int r = 8 * s + rr;
         const float2 u = phase_at(pv, 0, r), d = phase_at(pv, 1, r);
         const float su = gu[0][r], sd = gu[1][r];
@@ -923,34 +924,43 @@ __device__ __forceinline__ void modadj_half(int s, const floatx16 (&gu)[2], cons
         }
     }
 }
+__device__ __forceinline__ void modadj_half(int s, const floatx16 (&gu)[2], const uint4 (&pv)[2][4],
+                                            half8 (&ph)[2][4], half8 (&pl)[2][4]) {
+    modadj_rows(s, 0, 8, gu, pv, ph, pl);
+}
 
-// gY += Wr^T P + Wi^T Q' over the rows of half sp of the chunk (A operand from the
-// staged W^T chunk), two i-blocks at a time so that four accumulations alternate.
+// W^T fragments (hi, lo of Wr and Wi) of i-blocks q0 and q0 + 1 (clamped to q0 past
+// NI) for the rows of half sp of the staged chunk.
+struct WtFrag {
+    half8 wr[2][2], wi[2][2];             // [block][hi, lo]
+};
 template <int NI>
-__device__ __forceinline__ void wh_half(int sp, const uint4* Tcur, int h, int i32, const half8 (&ph)[2][4],
-                                        const half8 (&pl)[2][4], floatx16 (&gyr)[NI], floatx16 (&gyi)[NI]) {
+__device__ __forceinline__ void load_wt(WtFrag& f, const uint4* Tcur, int sp, int q0, int h, int i32) {
 #pragma unroll
-    for (int q0 = 0; q0 < NI; q0 += 2) {
-        half8 wr[2][2], wi[2][2];             // [block][hi, lo]
+    for (int d = 0; d < 2; ++d) {
+        const int q = q0 + d < NI ? q0 + d : q0;
+        const uint4* lt = Tcur + (q * 16 + (sp * 2 + h) * 4) * 32 + i32;
+        f.wr[d][0] = as_h8(lt[0]); f.wr[d][1] = as_h8(lt[32]);
+        f.wi[d][0] = as_h8(lt[64]); f.wi[d][1] = as_h8(lt[96]);
+    }
+}
+
+// gY[q0], gY[q0 + 1] += Wr^T P + Wi^T Q' over the rows of half sp: the two i-blocks
+// alternate, so that four accumulations are in flight.
+template <int NI>
+__device__ __forceinline__ void mma_group(const WtFrag& f, int sp, int q0, const half8 (&ph)[2][4],
+                                          const half8 (&pl)[2][4], floatx16 (&gyr)[NI], floatx16 (&gyi)[NI]) {
+#pragma unroll
+    for (int term = 0; term < 6; ++term) {
+        const int wsel = term < 3 ? 0 : 1, whl = (term % 3) == 2 ? 1 : 0, phl = (term % 3) == 1 ? 1 : 0;
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
-            const int q = q0 + d < NI ? q0 + d : q0;
-            const uint4* lt = Tcur + (q * 16 + (sp * 2 + h) * 4) * 32 + i32;
-            wr[d][0] = as_h8(lt[0]); wr[d][1] = as_h8(lt[32]);
-            wi[d][0] = as_h8(lt[64]); wi[d][1] = as_h8(lt[96]);
-        }
-#pragma unroll
-        for (int term = 0; term < 6; ++term) {
-            const int wsel = term < 3 ? 0 : 1, whl = (term % 3) == 2 ? 1 : 0, phl = (term % 3) == 1 ? 1 : 0;
-#pragma unroll
-            for (int d = 0; d < 2; ++d) {
-                if (q0 + d >= NI) continue;
-                const half8 a = wsel ? wi[d][whl] : wr[d][whl];
-                const half8 br = phl ? pl[sp][wsel * 2] : ph[sp][wsel * 2];
-                const half8 bi = phl ? pl[sp][wsel * 2 + 1] : ph[sp][wsel * 2 + 1];
-                gyr[q0 + d] = mfma16(a, br, gyr[q0 + d]);
-                gyi[q0 + d] = mfma16(a, bi, gyi[q0 + d]);
-            }
+            if (q0 + d >= NI) continue;
+            const half8 a = wsel ? f.wi[d][whl] : f.wr[d][whl];
+            const half8 br = phl ? pl[sp][wsel * 2] : ph[sp][wsel * 2];
+            const half8 bi = phl ? pl[sp][wsel * 2 + 1] : ph[sp][wsel * 2 + 1];
+            gyr[q0 + d] = mfma16(a, br, gyr[q0 + d]);
+            gyi[q0 + d] = mfma16(a, bi, gyi[q0 + d]);
         }
     }
 }
@@ -986,7 +996,10 @@ __device__ __forceinline__ void pin_gu(floatx16 (&gu)[2]) {
 // requested at its start.  Second half: the product over rows 16-31 while gU of the
 // next chunk and the modulus adjoint of its rows 0-15 run; the phase of its rows
 // 16-31 is requested at its start.  Each half ends with a full wait and a barrier,
-// so every request has a half chunk of matrix work to land.
+// so every request has a half chunk of matrix work to land.  Within a half, each
+// pair of i-blocks is one scheduling region: the W^T fragments of the next pair are
+// read from LDS at its top (they land while its products run) and a share of the
+// rows' modulus adjoint is interleaved with its products.
 template <int NTB, int NI>
 __device__ __forceinline__ void bwd_phase_chunk(int c, int nC, int wave, int lane, int tid, int h, int i32,
                                                 const uint4 (&phv)[NTB * 2][2], const uint4* Tsrc, const uint4* Gb,
@@ -994,27 +1007,48 @@ __device__ __forceinline__ void bwd_phase_chunk(int c, int nC, int wave, int lan
                                                 int64_t c_stride, float c0, const uint4* Tcur, uint4* Tnext,
                                                 floatx16 (&gyr)[NI], floatx16 (&gyi)[NI], floatx16 (&gu)[2],
                                                 uint4 (&pv)[2][4], half8 (&ph)[2][4], half8 (&pl)[2][4]) {
+    constexpr int NG = (NI + 1) / 2;             // pairs of i-blocks
     const int cn = c + 1 < nC ? c + 1 : c;       // the last chunk reloads itself
+    WtFrag f[2];
+    // ---- first half
     stage_t<NI>(Tnext, Tsrc, cn, wave, lane);
     stage_g<NTB>(Ls_G, Gb, cn, tid);
     load_phase_half(pv, 0, launder_v((const uint4*)(pbase + cn * c_stride)), spin_stride, c_stride / 4);
+    load_wt<NI>(f[0], Tcur, 0, 0, h, i32);
     __builtin_amdgcn_sched_barrier(0);
-    wh_half<NI>(0, Tcur, h, i32, ph, pl, gyr, gyi);
-    modadj_half(1, gu, pv, ph, pl);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        if (g + 1 < NG) load_wt<NI>(f[(g + 1) & 1], Tcur, 0, 2 * (g + 1), h, i32);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_group<NI>(f[g & 1], 0, 2 * g, ph, pl, gyr, gyi);
+        modadj_rows(1, g * 8 / NG, (g + 1) * 8 / NG, gu, pv, ph, pl);
+        interleave_mfma_valu<24, 4>();
+        __builtin_amdgcn_sched_barrier(0);
+    }
     pin_pq(ph, pl, 1);
-    interleave_mfma_valu<NI * 12, 3>();
-    __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    // ---- second half
     load_phase_half(pv, 1, launder_v((const uint4*)(pbase + cn * c_stride)), spin_stride, c_stride / 4);
+    load_wt<NI>(f[0], Tcur, 1, 0, h, i32);
     __builtin_amdgcn_sched_barrier(0);
-    wh_half<NI>(1, Tcur, h, i32, ph, pl, gyr, gyi);
-    gu_chunk<NTB>(Ls_G, phv, h, i32, c0, gu);
-    modadj_half(0, gu, pv, ph, pl);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        if (g + 1 < NG) load_wt<NI>(f[(g + 1) & 1], Tcur, 1, 2 * (g + 1), h, i32);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_group<NI>(f[g & 1], 1, 2 * g, ph, pl, gyr, gyi);
+        if (g == 0) {
+            gu_chunk<NTB>(Ls_G, phv, h, i32, c0, gu);
+            if (NG == 1) modadj_rows(0, 0, 8, gu, pv, ph, pl);
+            interleave_mfma_valu<24 + 6 * NTB, 2>();
+        } else {
+            modadj_rows(0, (g - 1) * 8 / (NG - 1), g * 8 / (NG - 1), gu, pv, ph, pl);
+            interleave_mfma_valu<24, 5>();
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
     pin_pq(ph, pl, 0);
     pin_gu(gu);
-    interleave_mfma_valu<NI * 12 + 6 * NTB, 3>();
-    __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 }
