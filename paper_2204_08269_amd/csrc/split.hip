@@ -372,10 +372,6 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
         for (int spin = 0; spin < 2; ++spin) {
             float uval[16];
             float m = 0.f;
-            unsigned* pcol = phase ? phase + b * ph_bstride +
-                                         (((int64_t)(spin * nlt + lt) * 2 + wl) * 4 + (i32 >> 3)) * Tp * 8 +
-                                         (int64_t)(t0 + wt * 32) * 8 + (i32 & 7)
-                                   : nullptr;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const float zr = spin ? rr[r] + ii[r] : rr[r] - ii[r];
@@ -383,16 +379,24 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
                 uval[r] = __builtin_amdgcn_sqrtf(zr * zr + zi * zi);   // hardware square root (1 ulp)
                 m = fmaxf(m, uval[r]);
             }
-            // one branch per spin (not per element), so that the 16 stores share
-            // one address with immediate offsets
-            if (pcol) {
+            // the wave's 32 x 32 tile of packed phases goes through its own LDS
+            // area (rows t, 36-element pitch), so that each lane then stores 16
+            // bytes (four rows l of one t) and a wave's store is a 1 KB run
+            if (phase) {
+                unsigned* tb = (unsigned*)(lds + 64 * WS) + wave * (32 * 36);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const float zr = spin ? rr[r] + ii[r] : rr[r] - ii[r];
                     const float zi = spin ? ir[r] - ri[r] : ir[r] + ri[r];
                     const float q = __builtin_amdgcn_rsqf(fmaxf(zr * zr + zi * zi, eps2s));
-                    pcol[crow(r, h) * 8] = pack_snorm16(zr * q, zi * q);
+                    tb[crow(r, h) * 36 + i32] = pack_snorm16(zr * q, zi * q);
                 }
+                const int tt = lane >> 1, hh = lane & 1;
+                unsigned* pb = phase + b * ph_bstride + ((int64_t)(spin * nlt + lt) * 2 + wl) * 4 * Tp * 8 +
+                               (int64_t)(t0 + wt * 32 + tt) * 8 + 4 * hh;
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    *(uint4*)(pb + (int64_t)g * Tp * 8) = *(const uint4*)(tb + tt * 36 + 8 * g + 4 * hh);
             }
             m = fmaxf(m, __shfl_xor(m, 32));
             const int se = pow2_exp(m);
@@ -1137,14 +1141,15 @@ using namespace jtfs;
 
 namespace jtfs {
 
-size_t split_fwd_lds(const Shapes& s);
+size_t split_fwd_lds(const Shapes& s, bool with_phase);
 
-bool split_supported(const Shapes& s) { return split_fwd_lds(s) <= (size_t)kMaxDynLds && s.NTp <= 64; }
+bool split_supported(const Shapes& s) { return split_fwd_lds(s, false) <= (size_t)kMaxDynLds && s.NTp <= 64; }
 
-// LDS of k_freq_fwd_h: resident W rows during the main loop, then the cross-wave
-// reduction buffer (8 waves x 2 spins x 64 lanes x 16 floats).
-size_t split_fwd_lds(const Shapes& s) {
-    const size_t main_loop = (size_t)64 * (s.Kp * 8 + 16);
+// LDS of k_freq_fwd_h: resident W rows during the main loop (with the stored phase
+// also a 32 x 36-element transpose area per wave), then the cross-wave reduction
+// buffer (8 waves x 2 spins x 64 lanes x 16 floats).
+size_t split_fwd_lds(const Shapes& s, bool with_phase) {
+    const size_t main_loop = (size_t)64 * (s.Kp * 8 + 16) + (with_phase ? (size_t)8 * 32 * 36 * 4 : 0);
     const size_t reduction = (size_t)8 * 2 * 64 * 16 * sizeof(float);
     return std::max(main_loop, reduction);
 }
@@ -1258,7 +1263,8 @@ int launch_freq_fwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, c
     const unsigned grid = (unsigned)(((nU + 7) / 8) * 8 * nlt);
     const int64_t yhb = (int64_t)s.Kp * s.sumTp * 4;
     const float unscale = 1.f / (P->sw * P->sphi[a]);
-    const size_t lds = split_fwd_lds(s);
+    const size_t lds = split_fwd_lds(s, phase != nullptr);
+    if (lds > (size_t)kMaxDynLds) { set_error("K beyond the split contraction's LDS tile"); return JTFS_ENOTSUP; }
     const unsigned short* Ya = Yh + s.yoff[a] * 4;
     const unsigned short* Ph = P->Phsp + s.phioff[a] * 2;
     const int slot0 = (int)s.vchoff[a];

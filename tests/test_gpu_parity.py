@@ -505,9 +505,11 @@ def test_time_scattering_forward_and_vjp(p):
 # Stored phase: the forward also writes the unit phase of every contraction
 # output, and a vjp that reuses its workspace takes the modulus adjoint from it
 # instead of recomputing the contraction.  Shapes with 32- and 64-frame tiles,
-# ragged row counts, and both eq. (3) and eq. (4).
-PHASE_SHAPES = [P1, RAGGED[0], RAGGED[2], RAGGED[3],
-                dict(N=4096, J=7, Q=(8, 1), J_fr=3, Q_fr=1, T=64, F=2)]     # N/T = 64
+# ragged row counts, 1 to 6 blocks of 32 lambda rows, and both eq. (3) and eq. (4).
+PHASE_SHAPES = [P1, RAGGED[0], RAGGED[1], RAGGED[2], RAGGED[3],
+                dict(N=4096, J=7, Q=(8, 1), J_fr=3, Q_fr=1, T=64, F=2),      # N/T = 64
+                dict(N=4096, J=8, Q=(28, 1), J_fr=3, Q_fr=1, T=64, F=2),     # N/T = 64, n1 = 158: 5 i-blocks
+                dict(N=4096, J=8, Q=(32, 1), J_fr=3, Q_fr=1, T=256, F=2)]    # n1 = 175: 6 i-blocks
 
 
 @pytest.mark.parametrize("average_fr", [True, False])
