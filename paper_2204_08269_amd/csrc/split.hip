@@ -908,29 +908,55 @@ __device__ __forceinline__ void gu_chunk(const uint4* Lg, const uint4 (&phv)[NTB
     }
 }
 
-// Modulus adjoint of rows r = 8 s + r0 .. 8 s + r1 - 1 from the scaled gU and the
-// stored phase: P and Q', split into FP16 hi / lo (lanes r - 8 s of ph[s], pl[s]).
-__device__ __forceinline__ void modadj_rows(int s, int r0, int r1, const floatx16 (&gu)[2], const uint4 (&pv)[2][4],
-                                            half8 (&ph)[2][4], half8 (&pl)[2][4]) {
+// hi / lo FP16 split (as split_h) of two values, each packed as a pair: hp = (hi0,
+// hi1) by one packed conversion, lp = (lo0, lo1) by two mixed-precision FMAs that
+// form v - hi exactly in FP32 and round it once, writing the low and high halves.
+__device__ __forceinline__ void split2(float v0, float v1, unsigned& hp, unsigned& lp) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+    hp = __builtin_bit_cast(unsigned, __builtin_convertvector((f2v){v0, v1}, h2v));
+    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%3 op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixhi_f16 %0, %2, 1.0, -%3 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+        : "=&v"(lp)
+        : "v"(v0), "v"(v1), "v"(hp));
+}
+
+// Modulus adjoint of row pairs 8 s + 2 p0 .. 8 s + 2 p1 - 1 from the scaled gU and
+// the stored phase: P and Q', split into FP16 hi / lo (lanes r - 8 s of ph[s],
+// pl[s]).
+__device__ __forceinline__ void modadj_pairs(int s, int p0, int p1, const floatx16 (&gu)[2], const uint4 (&pv)[2][4],
+                                             half8 (&ph)[2][4], half8 (&pl)[2][4]) {
 #pragma unroll
-    for (int rr = 0; rr < 8; ++rr) {
-        if (rr < r0 || rr >= r1) continue;
-        const int r = 8 * s + rr;
-        const float2 u = phase_at(pv, 0, r), d = phase_at(pv, 1, r);
-        const float su = gu[0][r], sd = gu[1][r];
-        const float vals[4] = {su * u.x + sd * d.x, su * u.y + sd * d.y, su * u.y - sd * d.y, sd * d.x - su * u.x};
+    for (int pr = 0; pr < 4; ++pr) {
+        if (pr < p0 || pr >= p1) continue;
+        float vals[2][4];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int r = 8 * s + 2 * pr + e;
+            const float2 u = phase_at(pv, 0, r), d = phase_at(pv, 1, r);
+            const float su = gu[0][r], sd = gu[1][r];
+            vals[e][0] = su * u.x + sd * d.x;
+            vals[e][1] = su * u.y + sd * d.y;
+            vals[e][2] = su * u.y - sd * d.y;
+            vals[e][3] = sd * d.x - su * u.x;
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            _Float16 hi, lo;
-            split_h(vals[q], hi, lo);
-            ph[s][q][rr] = hi;
-            pl[s][q][rr] = lo;
+            unsigned hp, lp;
+            split2(vals[0][q], vals[1][q], hp, lp);
+            uint4 hv = __builtin_bit_cast(uint4, ph[s][q]), lv = __builtin_bit_cast(uint4, pl[s][q]);
+            if (pr == 0) { hv.x = hp; lv.x = lp; }
+            else if (pr == 1) { hv.y = hp; lv.y = lp; }
+            else if (pr == 2) { hv.z = hp; lv.z = lp; }
+            else { hv.w = hp; lv.w = lp; }
+            ph[s][q] = __builtin_bit_cast(half8, hv);
+            pl[s][q] = __builtin_bit_cast(half8, lv);
         }
     }
 }
 __device__ __forceinline__ void modadj_half(int s, const floatx16 (&gu)[2], const uint4 (&pv)[2][4],
                                             half8 (&ph)[2][4], half8 (&pl)[2][4]) {
-    modadj_rows(s, 0, 8, gu, pv, ph, pl);
+    modadj_pairs(s, 0, 4, gu, pv, ph, pl);
 }
 
 // W^T fragments (hi, lo of Wr and Wi) of i-blocks q0 and q0 + 1 (clamped to q0 past
@@ -1025,7 +1051,7 @@ __device__ __forceinline__ void bwd_phase_chunk(int c, int nC, int wave, int lan
         if (g + 1 < NG) load_wt<NI>(f[(g + 1) & 1], Tcur, 0, 2 * (g + 1), h, i32);
         __builtin_amdgcn_sched_barrier(0);
         mma_group<NI>(f[g & 1], 0, 2 * g, ph, pl, gyr, gyi);
-        modadj_rows(1, g * 8 / NG, (g + 1) * 8 / NG, gu, pv, ph, pl);
+        modadj_pairs(1, g * 4 / NG, (g + 1) * 4 / NG, gu, pv, ph, pl);
         interleave_mfma_valu<24, 4>();
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -1043,10 +1069,10 @@ __device__ __forceinline__ void bwd_phase_chunk(int c, int nC, int wave, int lan
         mma_group<NI>(f[g & 1], 1, 2 * g, ph, pl, gyr, gyi);
         if (g == 0) {
             gu_chunk<NTB>(Ls_G, phv, h, i32, c0, gu);
-            if (NG == 1) modadj_rows(0, 0, 8, gu, pv, ph, pl);
+            if (NG == 1) modadj_pairs(0, 0, 4, gu, pv, ph, pl);
             interleave_mfma_valu<24 + 6 * NTB, 2>();
         } else {
-            modadj_rows(0, (g - 1) * 8 / (NG - 1), g * 8 / (NG - 1), gu, pv, ph, pl);
+            modadj_pairs(0, (g - 1) * 4 / (NG - 1), g * 4 / (NG - 1), gu, pv, ph, pl);
             interleave_mfma_valu<24, 5>();
         }
         __builtin_amdgcn_sched_barrier(0);
