@@ -128,7 +128,9 @@ def algorithmic_bytes(info, N, shapes, B):
 # HBM bytes per launch of a stage's kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes (scaled by the same counters on a copy of known size), kept beside the
 # profiles with the hash of the kernel's source; stale once that source changes.
-TRAFFIC_FILES = {("freq_adj_pq", "split16"): ("profiles/k_freq_bwd_h_64x65536_hbm_traffic.json",
+TRAFFIC_FILES = {("freq_fwd", "split16"): ("profiles/k_freq_fwd_h_64x65536_hbm_traffic.json",
+                                         "paper_2204_08269_amd/csrc/split.hip"),
+                 ("freq_adj_pq", "split16"): ("profiles/k_freq_bwd_h_64x65536_hbm_traffic.json",
                                             "paper_2204_08269_amd/csrc/split.hip"),
                  ("freq_fwd", "split16_phase"): ("profiles/k_freq_fwd_h_phase_64x65536_hbm_traffic.json",
                                                "paper_2204_08269_amd/csrc/split.hip"),
