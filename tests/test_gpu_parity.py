@@ -587,6 +587,9 @@ def test_autotune_then_every_row_choice_matches_oracle():
     op = gpu_op(MID)
     choice = op.autotune(2, xt, reps=2)
     assert choice["contraction"] in ("split16", "split16_phase", "fp32") and choice["step_ms"] > 0
+    # every available mode was timed (the stored phase fits in memory at this size)
+    c = choice["candidates_ms"]
+    assert c["split16_register"] > 0 and c["fp32_register"] > 0 and c["split16_phase_register"] > 0
     gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape(), seed=31)
     refs = [(O.jtfs(x[b].astype(np.float64), P),
              O.jtfs_vjp(x[b].astype(np.float64), gs1[b].astype(np.float64), gs2[b].astype(np.float64), P))
