@@ -395,8 +395,12 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
                 unsigned* pb = phase + b * ph_bstride + ((int64_t)(spin * nlt + lt) * 2 + wl) * 4 * Tp * 8 +
                                (int64_t)(t0 + wt * 32 + tt) * 8 + 4 * hh;
 #pragma unroll
-                for (int g = 0; g < 4; ++g)
-                    *(uint4*)(pb + (int64_t)g * Tp * 8) = *(const uint4*)(tb + tt * 36 + 8 * g + 4 * hh);
+                for (int g = 0; g < 4; ++g) {
+                    // read back only by the backward, long after: a streaming store, so that
+                    // it does not evict the Y operand the row tiles share in L2
+                    const u32x4 v = __builtin_bit_cast(u32x4, *(const uint4*)(tb + tt * 36 + 8 * g + 4 * hh));
+                    __builtin_nontemporal_store(v, (u32x4*)(pb + (int64_t)g * Tp * 8));
+                }
             }
             m = fmaxf(m, __shfl_xor(m, 32));
             const int se = pow2_exp(m);
@@ -866,7 +870,7 @@ __device__ __forceinline__ void load_phase_half(uint4 (&pv)[2][4], int s, gptr<u
         for (int gg = 0; gg < 2; ++gg) {
             const int g = 2 * s + gg;
             gptr<u32x4> p = (gptr<u32x4>)(pcol + (spin * spin_stride + g * g_stride) / 4);   // element offsets, % 4 = 0
-            pv[spin][g] = __builtin_bit_cast(uint4, p[0]);
+            pv[spin][g] = __builtin_bit_cast(uint4, __builtin_nontemporal_load(p));   // read once
         }
 }
 
