@@ -61,15 +61,25 @@ __global__ void __launch_bounds__(1024) k_fft_cols_t(const CI* in, C* out, int l
     const int64_t b = blockIdx.y;
     in += b * ib;
     out += b * ob;
-    if (ics == 1) {
-        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-            const int c = e & (Cn - 1), k = e >> logC;
-            s[c * st + lpad(k)] = to_cplx<CI, C>(in[(int64_t)(c0 + c) + (int64_t)k * ies]);
+    // all of a thread's loads (at most 16: tot <= 16 blockDim, as the transform
+    // requires) are issued before any LDS store, so that their latencies overlap
+    // instead of following one another
+    constexpr int kMaxPerThread = 16;
+    C v[kMaxPerThread];
+#pragma unroll
+    for (int q = 0; q < kMaxPerThread; ++q) {
+        const int e = threadIdx.x + q * blockDim.x;
+        if (e < tot) {
+            const int c = ics == 1 ? (e & (Cn - 1)) : (e >> loglen), k = ics == 1 ? (e >> logC) : (e & (len - 1));
+            v[q] = to_cplx<CI, C>(in[(int64_t)(c0 + c) * ics + (int64_t)k * ies]);
         }
-    } else {
-        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-            const int c = e >> loglen, k = e & (len - 1);
-            s[c * st + lpad(k)] = to_cplx<CI, C>(in[(int64_t)(c0 + c) * ics + (int64_t)k * ies]);
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxPerThread; ++q) {
+        const int e = threadIdx.x + q * blockDim.x;
+        if (e < tot) {
+            const int c = ics == 1 ? (e & (Cn - 1)) : (e >> loglen), k = ics == 1 ? (e >> logC) : (e & (len - 1));
+            s[c * st + lpad(k)] = v[q];
         }
     }
     __syncthreads();
