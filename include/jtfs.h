@@ -187,7 +187,10 @@ int jtfs_plan_table(const jtfs_plan* plan, int which, void* host_dst, size_t byt
 /* Ragged batches (many signals of uneven lengths).  Each signal of length L_i
  * (16 <= L_i <= 2^24) is zero-padded to the next power of two N_i; the signals of
  * one padded length form a bucket with its own plan (the parameters p with N = N_i)
- * and workspace, owned by the bucket object.
+ * and workspace, owned by the bucket object.  Runs with a gradient use the
+ * JTFS_CONTRACTION_SPLIT_F16_PHASE contraction where every bucket's plan allows it
+ * and the larger workspaces fit in 80 % of the device memory free at creation
+ * (else, and for forward-only runs, each plan's own contraction).
  *
  * Packed layouts (float32, device):
  *   x_packed  the signals back to back, signal i at x_offset[i], L_i samples;

@@ -53,6 +53,8 @@ struct Bucket {
     jtfs_info info{};
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    int mode_plain = JTFS_CONTRACTION_FP32;   // the plan's own contraction (forward-only runs)
+    bool phase = false;                       // runs with a gradient store the phase
     float *xb = nullptr, *s1 = nullptr, *s2 = nullptr, *g1 = nullptr, *g2 = nullptr, *gxb = nullptr;
     int64_t *d_xoff = nullptr, *d_len = nullptr, *d_soff = nullptr;
 };
@@ -110,11 +112,35 @@ extern "C" int jtfs_bucket_create(jtfs_bucket** out, const int64_t* lengths, int
     bk->soff.resize(count + 1);
     bk->soff[0] = 0;
     for (int i = 0; i < count; ++i) bk->soff[i + 1] = bk->soff[i] + s_per[i];
-    // per-bucket device buffers
+    // Runs with a gradient use the split-FP16 contraction with the phase stored by
+    // the forward (the backward reuses the forward's workspace) where every
+    // bucket's plan allows it and the larger workspaces fit in 80 % of the free
+    // device memory; forward-only runs keep each plan's own contraction.
+    {
+        bool all = true;
+        size_t need = 0;
+        for (auto& b : bk->buckets) jtfs_plan_get_contraction(b.plan, &b.mode_plain);
+        for (auto& b : bk->buckets) {
+            const int64_t B = (int64_t)b.members.size();
+            all = all && b.plan->split_ok && b.plan->split_bwd_ok && !b.plan->s.tscat;
+            if (!all) break;
+            b.plan->contraction = JTFS_CONTRACTION_SPLIT_F16_PHASE;
+            size_t w = 0;
+            jtfs_workspace_size(b.plan, B, &w);
+            b.plan->contraction = b.mode_plain;
+            need += w + sizeof(float) * B * (2 * b.N + 2 * (b.info.s1_per_signal + b.info.s2_per_signal));
+        }
+        size_t free_b = 0, total_b = 0;
+        const bool fits = all && hipMemGetInfo(&free_b, &total_b) == hipSuccess && (double)need <= 0.8 * (double)free_b;
+        for (auto& b : bk->buckets) b.phase = fits;
+    }
+    // per-bucket device buffers (the workspace sized for the contraction with a gradient)
     for (auto& b : bk->buckets) {
         const int64_t B = (int64_t)b.members.size();
         size_t wsb = 0;
+        if (b.phase) b.plan->contraction = JTFS_CONTRACTION_SPLIT_F16_PHASE;
         jtfs_workspace_size(b.plan, B, &wsb);
+        b.plan->contraction = b.mode_plain;
         auto get = [&](size_t bytes) -> void* {
             void* q = nullptr;
             if (hipMalloc(&q, std::max<size_t>(bytes, 16)) != hipSuccess) return nullptr;
@@ -164,6 +190,8 @@ static int enqueue(jtfs_bucket* bk, const float* xp, float* sp, const float* gp,
         const int64_t s1n = b.info.s1_per_signal, s2n = b.info.s2_per_signal, row = s1n + s2n;
         hipLaunchKernelGGL(k_pack, dim3((unsigned)((b.N + 255) / 256), B), dim3(256), 0, st, xp, b.d_xoff, b.d_len,
                            b.N, b.xb);
+        // the contraction is fixed when the work is recorded
+        b.plan->contraction = (gp && gxp && b.phase) ? JTFS_CONTRACTION_SPLIT_F16_PHASE : b.mode_plain;
         int rc = jtfs_forward(b.plan, b.xb, B, b.s1, b.s2, b.ws, b.ws_bytes, st);
         if (rc != JTFS_OK) return rc;
         hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)((s1n + 255) / 256), B), dim3(256), 0, st, b.s1, sp, b.d_soff,
