@@ -400,17 +400,19 @@ def test_mulog_matches_oracle(average_fr):
         check_paths(d1.cpu().numpy()[b], g_d2[b], f1[b], f2[b])
 
 
-def test_texture_loop_matches_oracle():
+@pytest.mark.parametrize("mode", ["split16", "split16_phase"])
+def test_texture_loop_matches_oracle(mode):
     """Texture resynthesis (sec. 5), every step on the GPU, against the oracle's
     loop from the same start: the start's error, the best error after each of 8
     bold-driver iterations, the final iterate and rate, for 2 signals; and 3 + 5
-    iterations in two calls (two graph captures) equal 8 in one."""
+    iterations in two calls (two graph captures) equal 8 in one.  With the stored
+    phase each iteration's backward takes the modulus adjoint from its forward."""
     from paper_2204_08269_amd.jtfs import Texture
     P = oracle_plan(P1)
     x = synth.batch(1, B=2)
     rng = np.random.default_rng(55)
     y0 = (rng.standard_normal((2, P1["N"])) * x.std(axis=1, keepdims=True)).astype(np.float32)
-    op = gpu_op(P1)
+    op = gpu_op(P1, mode)
     xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y0).cuda()
     tex = Texture(op, 2, mu0=-0.05)
     tex.set_target(xt)
