@@ -1264,7 +1264,6 @@ int split_attributes() {
     // the backward kernels use static LDS only; the forward takes it dynamically
     int rc = fwd_attributes<1>();
     if (rc == JTFS_OK) rc = fwd_attributes<2>();
-    if (rc == JTFS_OK) rc = fwd_attributes<4>();
     return rc;
 }
 
@@ -1305,7 +1304,6 @@ int launch_freq_fwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, c
     switch (s.NTp / 32) {
         case 1: launch_fwd_nk<1>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw); break;
         case 2: launch_fwd_nk<2>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw); break;
-        case 4: launch_fwd_nk<4>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw); break;
         default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
     }
     return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
