@@ -202,7 +202,7 @@ def main():
                     help="time the fwd+bwd step only (no forward-only or ragged-batch legs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: this library has no multi-GPU path "
               "(signals shard across GPUs with no communication; see the design notes)", file=sys.stderr)
         sys.exit(2)
 

@@ -54,7 +54,7 @@ extern "C" {
 #define JTFS_ENOMEM     -2   /* device allocation of plan tables failed            */
 #define JTFS_EHIP       -3   /* a HIP runtime call or kernel launch failed         */
 #define JTFS_EWORKSPACE -4   /* workspace smaller than jtfs_workspace_size()       */
-#define JTFS_ENOTSUP    -6   /* valid parameters outside what this build supports  */
+#define JTFS_ENOTSUP    -6   /* valid parameters outside what this library supports */
 
 /* Flags of jtfs_backward. */
 #define JTFS_BWD_REUSE_FORWARD 1u  /* ws holds the intermediates of the immediately

@@ -233,7 +233,7 @@ extern "C" int jtfs_plan_create_ex(jtfs_plan** out, const jtfs_params* p) {
     if (st != JTFS_OK) return st;
     st = check_supported(s);
     if (st != JTFS_OK) return st;
-    if (s.NTp > 128) { set_error("N/T above 128 frames is not supported by this build"); return JTFS_ENOTSUP; }
+    if (s.NTp > 128) { set_error("N/T above 128 frames is not supported by this library"); return JTFS_ENOTSUP; }
     if ((s.NX / 2 + 1 + s.NT) * sizeof(float2) > 160 * 1024 || (size_t)33 * s.L * sizeof(float) > 160 * 1024) {
         set_error("LDS needs of these shapes exceed 160 KB"); return JTFS_ENOTSUP; }
     int dev = 0;

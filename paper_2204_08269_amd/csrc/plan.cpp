@@ -165,7 +165,7 @@ int solve_shapes(const jtfs_params& p, Shapes* s) {
 
 int check_supported(const Shapes& s) {
     if (s.logNX > kMaxLogNX) {
-        set_error("scalogram length N/2^kX above 2^15 is not supported by this build");
+        set_error("scalogram length N/2^kX above 2^15 is not supported by this library");
         return JTFS_ENOTSUP;
     }
     return JTFS_OK;

@@ -64,7 +64,7 @@ struct Shapes {
 
 // Validate and solve; returns JTFS_OK or JTFS_EINVAL with the error set.
 int solve_shapes(const jtfs_params& p, Shapes* s);
-// JTFS_OK if the device path of this build handles the shapes, else JTFS_ENOTSUP.
+// JTFS_OK if the device path of this library handles the shapes, else JTFS_ENOTSUP.
 int check_supported(const Shapes& s);
 const char* last_error();
 
