@@ -46,14 +46,18 @@ __device__ __forceinline__ C twiddle(const C* __restrict__ tw, int k, bool inv) 
     return w;
 }
 
-// LDS slot of element j of one transform: one unused element after every eight,
-// so that the strided stores of the first passes (8 and 64 elements apart across
-// the lanes) fall into distinct banks; contiguous runs gain at most a 2-way
-// conflict where they cross a pad.  Every kernel that fills or reads an LDS
-// transform buffer indexes it through lpad.
-__device__ __forceinline__ int lpad(int j) { return j + (j >> 3); }
-// slots one transform of n points occupies
-constexpr int lpad_len(int n) { return n + (n >> 3); }
+// LDS slot of element j of one transform: the low five bits of j are XORed with
+// bits 3..7.  A half-wave's 8-byte accesses cover the 64 four-byte banks once, so
+// a pass's loads (32 consecutive elements, permuted inside their aligned block
+// of 32) and its stores (8 apart in the first pass, runs of 8 spaced 64 apart in
+// the second, longer runs after) meet no bank twice for transforms of 256 points
+// or more.  For j < n (n a power of two) the slot stays below n; element n of a
+// half spectrum lands at n + n/8 below 256 points and at n from there on.  Every
+// kernel that fills or reads an LDS transform buffer indexes it through lpad.
+__device__ __forceinline__ int lpad(int j) { return j ^ ((j >> 3) & 31); }
+// slots one transform of n points occupies, with element n of a half spectrum;
+// even from 16 points on, so that a column stride of lpad_len + 1 is odd
+constexpr int lpad_len(int n) { return n + (n < 256 ? n / 8 : 0) + 2; }
 
 // Workgroup barrier that orders LDS only: it waits for this wave's LDS accesses
 // (not for its global loads and stores, which may stay in flight across it).
