@@ -416,3 +416,147 @@ def test_scattering1d_vjp_matches_finite_differences(P1, x1):
         h = 1e-6
         fd = (f(x1 + h * v) - f(x1 - h * v)) / (2 * h)
         assert abs(fd - g @ v) <= 1e-7 * abs(fd)
+
+
+# ------------------------------------- subsampling schedule and stopping rules
+#
+# Decimating a complex band by 2^k keeps one period of width 2^-k of its
+# spectrum: the band may be decimated without folding onto itself when the
+# spectrum outside the interval of that width centred on its peak is negligible.
+# The reading of the critical rate (sec. 1: each band's rate depends on its
+# centre frequency) takes "negligible" as a Gaussian's value beyond five standard
+# deviations, e^-12.5, and the rate as the lowest one that meets it (up to the
+# caps that keep the output on the N/T and L/F grids).  These tests measure that
+# property on the filter spectra themselves, so a change of the envelope
+# constant, of a lowpass width or of a stopping rule fails one of them.
+
+GAUSS_5SIGMA = math.exp(-12.5)
+
+
+def _outside_band_ratio(hat, M, xi, halfwidth):
+    """max |hat| over grid bins farther than halfwidth (cycles per grid sample)
+    from xi, relative to the spectrum's peak (bin m has frequency m~/M)."""
+    f = O.signed_bins(M) / M
+    out = np.abs(f - xi) > halfwidth
+    return float(np.max(np.abs(hat[out]), initial=0.0) / np.max(np.abs(hat)))
+
+
+def _family_schedule(P, which):
+    """(grid size, list of (xi, sigma, spectrum, k, cap)) of one wavelet family."""
+    logT, logF = int(math.log2(P.T)), int(math.log2(P.F))
+    if which == "first":
+        return P.N, [(P.xi1[i], P.sigma1[i], P.psi1_hat[i], P.kX, logT) for i in range(P.n1)]
+    if which == "second":
+        return P.NX, [(P.xi2[a], P.sigma2[a], P.psi2_hat[a], P.k2[a], logT - P.kX) for a in range(P.n_alpha)]
+    return P.L, [(P.xi_fr[b], P.sigma_fr[b], P.psi_fr_hat[b], P.k_fr[b], logF) for b in range(P.n_beta)]
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("which", ["first", "second", "frequential"])
+def test_decimation_keeps_each_band_within_its_alias_period(cfg, which):
+    """Sufficient: every filter's spectrum outside the period kept by its
+    decimation (width 2^-k, centred on xi) is at most e^-12.5 of its peak."""
+    P = plan(cfg)
+    M, fam = _family_schedule(P, which)
+    for xi, sg, hat, k, cap in fam:
+        r = _outside_band_ratio(hat, M, xi, 2.0 ** -(k + 1))
+        assert r <= GAUSS_5SIGMA * (1 + 1e-9), (which, xi, k, r)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("which", ["first", "second", "frequential"])
+def test_decimation_is_the_lowest_rate_that_keeps_the_band(cfg, which):
+    """Minimal: one more halving of the rate (where the cap allows it) leaves
+    part of the spectrum above e^-12.5 of the peak outside the kept period.  The
+    first order uses one common rate set by its widest filter (the top one)."""
+    P = plan(cfg)
+    M, fam = _family_schedule(P, which)
+    if which == "first":
+        fam = fam[:1]
+        assert np.argmax(P.sigma1) == 0
+    for xi, sg, hat, k, cap in fam:
+        if k == cap:
+            continue
+        h = 2.0 ** -(k + 2)
+        # the continuous spectrum just outside the halved period, same normalisation
+        c = np.max(np.abs(hat)) / float(O.morlet_hat(xi, sg, np.array([xi]))[0])
+        edge = float(O.morlet_hat(xi, sg, np.array([xi + h]))[0]) * c
+        grid = _outside_band_ratio(hat, M, xi, h)
+        assert max(edge / np.max(np.abs(hat)), grid) > GAUSS_5SIGMA, (which, xi, k)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5])
+def test_lowpass_at_output_nyquist(cfg):
+    """phi_T at the output Nyquist 1/(2T) and phi_F at 1/(2F) are e^-12.5 of their
+    DC gain of 1: the same five-deviation rule as the wavelets' rates, so the
+    N/T and L/F output grids hold the lowpassed coefficients."""
+    P = plan(cfg)
+    phT = O.gauss_lowpass_hat(P.N, P.N, P.T)
+    assert phT[0] == 1.0
+    assert abs(phT[P.N // (2 * P.T)] - GAUSS_5SIGMA) <= 1e-15
+    phF = O.gauss_lowpass_hat(P.L, P.L, P.F)
+    assert phF[0] == 1.0
+    assert abs(phF[P.L // (2 * P.F)] - GAUSS_5SIGMA) <= 1e-15
+    # the same lowpass on every decimated grid the cascade uses: bin N/(2T) is the
+    # output Nyquist at any rate 2^-k with k <= log2 T
+    for k in sorted({P.kX} | {P.kX + k2 for k2 in P.k2}):
+        M = P.N >> k
+        ph = O.gauss_lowpass_hat(M, P.N, P.T)
+        assert P.N // (2 * P.T) <= M // 2
+        assert abs(ph[P.N // (2 * P.T)] - GAUSS_5SIGMA) <= 1e-15
+
+
+def _cq_count(xi, Q):
+    r = xi[1:] / xi[:-1]
+    n = 1
+    while n < len(xi) and abs(r[n - 1] - 2.0 ** (-1.0 / Q)) <= 1e-12:
+        n += 1
+    return n
+
+
+@pytest.mark.parametrize("Jp,Q", [(6, 8), (12, 16), (13, 12), (11, 16), (14, 24), (4, 1), (10, 1), (3, 1),
+                                  (4, 2), (5, 2), (12, 2)])
+def test_filterbank_top_and_stopping_rules(Jp, Q):
+    """The family's ends follow from the geometry alone:
+    * top: the next filter up the geometric ladder, xi_0 2^(1/Q), would be the
+      mirror of xi_0 about Nyquist, 1 - xi_0 (Q >= 2); for one filter per
+      octave that mirror would leave xi_0 = 1/3 and the top sits at 0.35;
+    * constant-Q part: the last filter's bandwidth sigma = xi/Q_f is still at
+      least sigma_min = 0.1/2^J (its time support at most about 2^J), and the
+      next one down would be narrower (longer than 2^J);
+    * linear part: filters of bandwidth sigma_min, neighbours crossing at -3 dB;
+      the lowest centre lies at least one spacing above DC and one more filter
+      would not."""
+    xi, sg = O.filterbank_centres(Jp, Q)
+    if Q >= 2:
+        assert abs(xi[0] * 2.0 ** (1.0 / Q) - (1.0 - xi[0])) <= 1e-15
+    else:
+        assert 1.0 / (1.0 + 2.0) < 0.35 and xi[0] == 0.35
+    smin = 0.1 / 2.0 ** Jp
+    n = _cq_count(xi, Q)
+    Qf = O.quality_factor(Q)
+    assert sg[n - 1] >= smin and np.all(sg[:n] >= smin)
+    assert xi[n - 1] * 2.0 ** (-1.0 / Q) / Qf < smin
+    lin = xi[n:]
+    assert np.all(sg[n:] == smin)
+    # spacing: Gaussians of width smin whose centres are `spacing` apart cross at -3 dB
+    spacing = (xi[n - 1] - lin[0]) if len(lin) else None
+    if spacing is not None:
+        assert abs(math.exp(-(spacing / 2) ** 2 / (2 * smin ** 2)) - 1 / math.sqrt(2)) <= 1e-12
+        assert np.allclose(-np.diff(xi[n - 1:]), spacing, rtol=0, atol=1e-15)
+        assert lin[-1] >= spacing and lin[-1] - spacing < spacing
+    else:
+        # no linear filter fits: the last constant-Q centre is already within two spacings of DC
+        d = 2 * math.sqrt(math.log(2)) * smin
+        assert xi[n - 1] - d < d
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5])
+def test_first_order_family_covers_up_to_nyquist(cfg):
+    """The first order reaches the top of the band: the LP sum is at least its
+    in-band floor on [xi_0, 1/2] (where config 2's chirps end, at 0.45)."""
+    P = plan(cfg)
+    lp = np.sum(P.psi1_hat ** 2, axis=0)[: P.N // 2 + 1]
+    f = np.arange(P.N // 2 + 1) / P.N
+    band = (f >= P.xi1[-1]) & (f <= 0.45)
+    assert lp[band].min() >= 0.86
