@@ -216,7 +216,9 @@ void jtfs_bucket_destroy(jtfs_bucket* bk);
  * is S1 as a whole or one (alpha, beta, theta) slice of S2 (either layout).
  * jtfs_path_means writes mu = the mean of each path over the B signals and over
  * (lambda, t): mu1 [1] for S1 and mu2 [n_alpha * n_beta * 2] (theta fastest),
- * device FP32, accumulated in FP64.  jtfs_mulog writes log(1 + S / (eps mu)) for
+ * device FP32, accumulated in FP64.  For a time-scattering plan a second-order
+ * path is one (alpha, lambda1) row of S2 [n_alpha][n1][N/T], mu2 [n_alpha * n1]
+ * (lambda1 fastest) its mean over the signals and frames.  jtfs_mulog writes log(1 + S / (eps mu)) for
  * every coefficient (o1, o2 may alias s1, s2); jtfs_mulog_backward writes
  * gS = g / (eps mu + S), the adjoint with mu held fixed (mu estimated beforehand
  * over a training set).  eps > 0 (the paper uses 0.1).  All pointers are device

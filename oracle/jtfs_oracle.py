@@ -516,30 +516,38 @@ def jtfs_direct(x, P: Plan, average_fr=True):
 MULOG_EPS = 0.1   # the constant epsilon of the paper, the same for every path
 
 
-def path_means(S1s, S2s):
+def path_means(S1s, S2s, path_axes=2):
     """mu per path over a set of signals.  S1s [n, n1, N/T] is one path (the
     first order); S2s [n, n_alpha, n_beta, 2, L/F, N/T] has one path per
     (alpha, beta, theta).  mu is the mean over the signals and over (lambda, t):
-    the integral over the time-frequency plane divided by its area."""
+    the integral over the time-frequency plane divided by its area.  The last
+    ``path_axes`` axes of S2s span one path: 2 for JTFS, 1 for time scattering,
+    whose S2s [n, n_alpha, n1, N/T] has one path per (alpha, lambda1) pair,
+    averaged over its frames."""
     S1s = np.asarray(S1s, np.float64)
     S2s = np.asarray(S2s, np.float64)
     mu1 = np.float64(S1s.mean())
-    mu2 = S2s.mean(axis=(0, 4, 5))
+    mu2 = S2s.mean(axis=(0,) + tuple(range(S2s.ndim - path_axes, S2s.ndim)))
     return mu1, mu2
 
 
-def mulog(S1, S2, mu1, mu2, eps=MULOG_EPS):
+def _per_coeff(mu2, path_axes):
+    mu2 = np.asarray(mu2, np.float64)
+    return mu2.reshape(mu2.shape + (1,) * path_axes)
+
+
+def mulog(S1, S2, mu1, mu2, eps=MULOG_EPS, path_axes=2):
     """log(1 + S / (eps mu(path))) for one or several signals."""
     S1 = np.asarray(S1, np.float64)
     S2 = np.asarray(S2, np.float64)
-    return np.log1p(S1 / (eps * mu1)), np.log1p(S2 / (eps * mu2[..., None, None]))
+    return np.log1p(S1 / (eps * mu1)), np.log1p(S2 / (eps * _per_coeff(mu2, path_axes)))
 
 
-def mulog_vjp(S1, S2, mu1, mu2, g1, g2, eps=MULOG_EPS):
+def mulog_vjp(S1, S2, mu1, mu2, g1, g2, eps=MULOG_EPS, path_axes=2):
     """Adjoint of mulog in S with mu held fixed: g / (eps mu + S)."""
     S1 = np.asarray(S1, np.float64)
     S2 = np.asarray(S2, np.float64)
-    return np.asarray(g1) / (eps * mu1 + S1), np.asarray(g2) / (eps * mu2[..., None, None] + S2)
+    return np.asarray(g1) / (eps * mu1 + S1), np.asarray(g2) / (eps * _per_coeff(mu2, path_axes) + S2)
 
 
 # ---------------------------------------------------------------------------

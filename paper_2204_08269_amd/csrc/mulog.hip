@@ -5,7 +5,9 @@
 // (alpha, beta, theta) slice of S2.  In both S2 layouts (eq. (3) and the packed
 // eq. (4) layout) a slice is one contiguous block per signal, so every kernel
 // runs one workgroup per (path, signal) over that block; block index n_paths
-// stands for S1.
+// stands for S1.  In time scattering (S2 [n_alpha][n1][N/T]) a second-order
+// path is one (alpha, lambda1) pair, its N/T frames a contiguous row: the same
+// geometry as eq. (3) with one row per path.
 #include <hip/hip_runtime.h>
 
 #include "plan.hpp"
@@ -90,6 +92,19 @@ __global__ void __launch_bounds__(256) k_mulog_bwd(PathGeom g, const float* __re
 static PathGeom geom(const jtfs_plan* P) {
     const Shapes& s = P->s;
     PathGeom g;
+    if (s.tscat) {
+        g.n_paths = s.n_alpha * s.n1;
+        g.n_beta = 0;
+        g.NL = 1;
+        g.NT = s.NT;
+        g.Mh = 0;
+        g.avg = 1;
+        g.s1_per = (int64_t)s.n1 * s.NT;
+        g.s2_per = (int64_t)g.n_paths * s.NT;
+        g.rowoff = nullptr;
+        g.Lb = nullptr;
+        return g;
+    }
     g.n_paths = s.n_alpha * s.n_beta * 2;
     g.n_beta = s.n_beta;
     g.NL = s.NL;

@@ -155,11 +155,13 @@ class JTFS:
         return s1.contiguous(), s2.contiguous(), B
 
     def path_means(self, s1, s2):
-        """mu per path over the batch: (mu1 [1], mu2 [n_alpha * n_beta * 2])."""
+        """mu per path over the batch: (mu1 [1], mu2 [n_alpha * n_beta * 2]); with
+        time scattering one path per (alpha, lambda1): mu2 [n_alpha * n1]."""
         s1, s2, B = self._check_s(s1, s2)
         i = self.info
+        n2 = i.n_alpha * i.n1 if self.time_scattering else i.n_alpha * i.n_beta * 2
         mu1 = torch.empty(1, dtype=torch.float32, device=s1.device)
-        mu2 = torch.empty(i.n_alpha * i.n_beta * 2, dtype=torch.float32, device=s1.device)
+        mu2 = torch.empty(n2, dtype=torch.float32, device=s1.device)
         _lib.check(self.lib.jtfs_path_means(self.plan, _ptr(s1), _ptr(s2), B, _ptr(mu1), _ptr(mu2), _stream()))
         return mu1, mu2
 

@@ -400,6 +400,34 @@ def test_mulog_matches_oracle(average_fr):
         check_paths(d1.cpu().numpy()[b], g_d2[b], f1[b], f2[b])
 
 
+def test_mulog_time_scattering_matches_oracle():
+    """mu-log of a time-scattering transform: one path per (alpha, lambda1) row
+    of S2 [n_alpha][n1][N/T], means over a batch of 3, the renormalised
+    coefficients and the adjoint."""
+    P = oracle_plan(P1)
+    x = synth.batch(1, B=3)
+    op = gpu_op(P1, time_scattering=True)
+    s1, s2 = op.forward(torch.from_numpy(x).cuda())
+    mu1, mu2 = op.path_means(s1, s2)
+    assert tuple(mu2.shape) == (P.n_alpha * P.n1,)
+    o1, o2 = op.mulog(s1, s2, mu1, mu2)
+    gs1, gs2 = synth.cotangents(tuple(s1.shape), tuple(s2.shape), seed=19)
+    d1, d2 = op.mulog_vjp(s1, s2, mu1, mu2, torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda())
+    refs = [O.scattering1d(x[b].astype(np.float64), P) for b in range(3)]
+    R1 = np.stack([r[0] for r in refs])
+    R2 = np.stack([r[1] for r in refs])
+    m1, m2 = O.path_means(R1, R2, path_axes=1)
+    assert abs(float(mu1.cpu()) - m1) <= 1e-5 * m1
+    assert np.max(np.abs(mu2.cpu().numpy().reshape(m2.shape) - m2) / m2) <= 1e-5
+    e1, e2 = O.mulog(R1, R2, m1, m2, path_axes=1)
+    f1, f2 = O.mulog_vjp(R1, R2, m1, m2, gs1, gs2, path_axes=1)
+    for b in range(3):
+        for got, ref in ((o1.cpu().numpy()[b], e1[b]), (d1.cpu().numpy()[b], f1[b])):
+            assert path_errors(got, ref, 1)[0].max() <= TOL
+        for got, ref in ((o2.cpu().numpy()[b], e2[b]), (d2.cpu().numpy()[b], f2[b])):
+            assert path_errors(got, ref, 2)[0].max() <= TOL
+
+
 @pytest.mark.parametrize("mode", ["split16", "split16_phase"])
 def test_texture_loop_matches_oracle(mode):
     """Texture resynthesis (sec. 5), every step on the GPU, against the oracle's

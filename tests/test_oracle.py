@@ -338,6 +338,26 @@ def test_mulog_means_and_closed_values():
     assert np.allclose(v2, g2 * (p2 - m2) / (2 * h), rtol=1e-7, atol=1e-9)
 
 
+def test_mulog_time_scattering_paths():
+    """Time scattering: one path per (alpha, lambda1) row, its mean over the
+    signals and frames (a brute-force loop); S = eps mu (e - 1) maps to 1."""
+    rng = np.random.default_rng(81)
+    S1 = rng.random((3, 5, 4))
+    S2 = rng.random((3, 2, 5, 4))
+    mu1, mu2 = O.path_means(S1, S2, path_axes=1)
+    assert mu2.shape == (2, 5)
+    for a in range(2):
+        for lam in range(5):
+            vals = [S2[n, a, lam, k] for n in range(3) for k in range(4)]
+            assert abs(mu2[a, lam] - sum(vals) / len(vals)) <= 1e-15
+    T2 = O.MULOG_EPS * mu2[None, :, :, None] * (math.e - 1.0) * np.ones_like(S2)
+    _, o2 = O.mulog(S1, T2, mu1, mu2, path_axes=1)
+    assert np.allclose(o2, 1.0, atol=1e-15)
+    g2 = rng.standard_normal(S2.shape)
+    _, v2 = O.mulog_vjp(S1, S2, mu1, mu2, S1, g2, path_axes=1)
+    assert np.allclose(v2, g2 / (O.MULOG_EPS * mu2[None, :, :, None] + S2), rtol=1e-15)
+
+
 # ------------------------------------------------------- texture resynthesis
 
 def test_texture_error_gradient_matches_finite_differences(P1, x1):
