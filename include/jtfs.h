@@ -136,8 +136,13 @@ void jtfs_plan_destroy(jtfs_plan* plan);
  * batch of B signals (the same workspace serves both; the backward reuses the
  * forward's intermediates when called with JTFS_BWD_REUSE_FORWARD). */
 int jtfs_workspace_size(const jtfs_plan* plan, int64_t B, size_t* bytes);
+/* The leading part of that workspace which a forward alone uses (the forward's
+ * intermediates; the backward's buffers follow it). */
+int jtfs_forward_workspace_size(const jtfs_plan* plan, int64_t B, size_t* bytes);
 
-/* S1 and S2 of B signals (layouts above).  ws: device workspace of ws_bytes. */
+/* S1 and S2 of B signals (layouts above).  ws: device workspace of ws_bytes, at
+ * least jtfs_forward_workspace_size (its leading part; a backward that reuses
+ * this forward's workspace needs the whole jtfs_workspace_size). */
 int jtfs_forward(const jtfs_plan* plan, const float* x, int64_t B, float* s1, float* s2,
                  void* ws, size_t ws_bytes, hipStream_t stream);
 
@@ -166,11 +171,16 @@ int jtfs_backward(const jtfs_plan* plan, const float* x, const float* gs1, const
  *                              by 8 * B * M_p * sum_alpha T_p(alpha) bytes (M_p: M_h
  *                              rounded up to 64; T_p: T_alpha rounded up to 128);
  *                              jtfs_workspace_size accounts for it.  A backward
- *                              without JTFS_BWD_REUSE_FORWARD recomputes as SPLIT_F16.
- * The default is SPLIT_F16 where the shapes allow it (n1 <= 240), else FP32.
+ *                              without JTFS_BWD_REUSE_FORWARD recomputes as SPLIT_F16
+ *                              where that backward holds the shapes, else it takes
+ *                              the phase again with the forward contraction.
+ * The default is SPLIT_F16 where the shapes allow it (n1 <= 304 and N/T <= 64),
+ * else FP32.  The SPLIT_F16 backward holds n1 <= 192 (160 at N/T = 64); beyond
+ * that a SPLIT_F16 plan differentiates with the FP32 kernels.  SPLIT_F16_PHASE
+ * holds every shape of the split forward.
  * Returns JTFS_ENOTSUP if the requested mode is not available for the plan
- * (SPLIT_F16_PHASE: where the split backward is, and not with
- * JTFS_TIME_SCATTERING, which has no contraction). */
+ * (and SPLIT_F16_PHASE not with JTFS_TIME_SCATTERING, which has no
+ * contraction). */
 #define JTFS_CONTRACTION_FP32            0
 #define JTFS_CONTRACTION_SPLIT_F16       1
 #define JTFS_CONTRACTION_SPLIT_F16_PHASE 2

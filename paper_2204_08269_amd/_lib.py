@@ -49,7 +49,7 @@ class Info(ctypes.Structure):
 
 
 EXPORTS = ["jtfs_query", "jtfs_query_filters", "jtfs_plan_create", "jtfs_plan_create_ex", "jtfs_plan_info",
-           "jtfs_plan_destroy", "jtfs_workspace_size", "jtfs_forward", "jtfs_backward", "jtfs_plan_table",
+           "jtfs_plan_destroy", "jtfs_workspace_size", "jtfs_forward_workspace_size", "jtfs_forward", "jtfs_backward", "jtfs_plan_table",
            "jtfs_plan_set_contraction", "jtfs_plan_get_contraction", "jtfs_bucket_create", "jtfs_bucket_offsets",
            "jtfs_bucket_run", "jtfs_bucket_destroy", "jtfs_path_means", "jtfs_mulog", "jtfs_mulog_backward",
            "jtfs_texture_create", "jtfs_texture_set_target", "jtfs_texture_set_start", "jtfs_texture_iterate",
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH):
     L.jtfs_plan_destroy.argtypes = [vp]
     L.jtfs_plan_destroy.restype = None
     L.jtfs_workspace_size.argtypes = [vp, i64, P(sz)]
+    L.jtfs_forward_workspace_size.argtypes = [vp, i64, P(sz)]
     L.jtfs_forward.argtypes = [vp, vp, i64, vp, vp, vp, sz, vp]
     L.jtfs_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, sz, u32, vp]
     L.jtfs_plan_table.argtypes = [vp, ctypes.c_int, vp, sz]

@@ -115,7 +115,7 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
     jtfs_info info;
     jtfs_plan_info(P, &info);
     const size_t coef_bytes = sizeof(float) * B * (info.s1_per_signal + info.s2_per_signal + 2 * s.N);
-    if (P->split_ok && P->split_bwd_ok && !s.tscat) {
+    if (P->split_ok && P->split_bwdp_ok && !s.tscat) {
         // the stored phase only where the whole candidate set fits in 80 % of free memory
         P->contraction = JTFS_CONTRACTION_SPLIT_F16_PHASE;
         size_t b = 0;

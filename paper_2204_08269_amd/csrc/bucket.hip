@@ -122,7 +122,7 @@ extern "C" int jtfs_bucket_create(jtfs_bucket** out, const int64_t* lengths, int
         for (auto& b : bk->buckets) jtfs_plan_get_contraction(b.plan, &b.mode_plain);
         for (auto& b : bk->buckets) {
             const int64_t B = (int64_t)b.members.size();
-            all = all && b.plan->split_ok && b.plan->split_bwd_ok && !b.plan->s.tscat;
+            all = all && b.plan->split_ok && b.plan->split_bwdp_ok && !b.plan->s.tscat;
             if (!all) break;
             b.plan->contraction = JTFS_CONTRACTION_SPLIT_F16_PHASE;
             size_t w = 0;

@@ -1043,19 +1043,27 @@ using namespace jtfs;
         }                                                                                \
     } while (0)
 
+// Whether the backward of the plan's contraction mode runs on the split kernels
+// (else the FP32 pair, which keeps P and Q' in the workspace).
+static bool split_backward(const jtfs_plan* P) {
+    if (P->contraction == JTFS_CONTRACTION_FP32 || P->s.tscat) return false;
+    return P->contraction == JTFS_CONTRACTION_SPLIT_F16_PHASE ? P->split_bwdp_ok : P->split_bwd_ok;
+}
+
 // Workspace of a plan in its current contraction mode.
 static Workspace plan_layout(const jtfs_plan* P, int64_t B) {
     const bool split = P->contraction != JTFS_CONTRACTION_FP32;          // SPLIT_F16 or SPLIT_F16_PHASE
     const bool phase = P->contraction == JTFS_CONTRACTION_SPLIT_F16_PHASE && !P->s.tscat;
-    return layout(P->s, B, split, !(split && P->split_bwd_ok), phase);
+    return layout(P->s, B, split, !(split && split_backward(P)), phase);
 }
 
-static int check_common(const jtfs_plan* P, int64_t B, void* ws, size_t ws_bytes) {
+// forward_only: a forward needs the leading part of the layout only
+static int check_common(const jtfs_plan* P, int64_t B, void* ws, size_t ws_bytes, bool forward_only) {
     if (!P) { set_error("null plan"); return JTFS_EINVAL; }
     if (B < 1) { set_error("B must be >= 1"); return JTFS_EINVAL; }
     if (!ws) { set_error("null workspace"); return JTFS_EINVAL; }
     const Workspace w = plan_layout(P, B);
-    if (ws_bytes < w.total) { set_error("workspace too small"); return JTFS_EWORKSPACE; }
+    if (ws_bytes < (forward_only ? w.fwd_total : w.total)) { set_error("workspace too small"); return JTFS_EWORKSPACE; }
     return JTFS_OK;
 }
 
@@ -1063,6 +1071,13 @@ extern "C" int jtfs_workspace_size(const jtfs_plan* P, int64_t B, size_t* bytes)
     if (!P || !bytes) { set_error("null pointer"); return JTFS_EINVAL; }
     if (B < 1) { set_error("B must be >= 1"); return JTFS_EINVAL; }
     *bytes = plan_layout(P, B).total;
+    return JTFS_OK;
+}
+
+extern "C" int jtfs_forward_workspace_size(const jtfs_plan* P, int64_t B, size_t* bytes) {
+    if (!P || !bytes) { set_error("null pointer"); return JTFS_EINVAL; }
+    if (B < 1) { set_error("B must be >= 1"); return JTFS_EINVAL; }
+    *bytes = plan_layout(P, B).fwd_total;
     return JTFS_OK;
 }
 
@@ -1116,7 +1131,7 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
 
 extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float* s1, float* s2, void* ws,
                             size_t ws_bytes, hipStream_t st) {
-    int rc = check_common(P, B, ws, ws_bytes);
+    int rc = check_common(P, B, ws, ws_bytes, true);
     if (rc != JTFS_OK) return rc;
     if (!x || !s1 || !s2) { set_error("null pointer"); return JTFS_EINVAL; }
     const Shapes& s = P->s;
@@ -1199,7 +1214,7 @@ static int gy2_row_fft(const jtfs_plan* P, int a, float2* gY2, int64_t yb, int64
 
 extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs1, const float* gs2, float* gx,
                              int64_t B, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t st) {
-    int rc = check_common(P, B, ws, ws_bytes);
+    int rc = check_common(P, B, ws, ws_bytes, false);
     if (rc != JTFS_OK) return rc;
     if (!x || !gx) { set_error("null pointer"); return JTFS_EINVAL; }
     const Shapes& s = P->s;
@@ -1236,17 +1251,27 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
                            s2_bwd_stage(s), gV, (float*)(base + w.gvmax)));
         LAUNCHCHK("frequency lowpass adjoint");
     }
-    const bool split = P->contraction != JTFS_CONTRACTION_FP32 && P->split_bwd_ok && !s.tscat;
-    // the phase the forward stored, when this backward follows it on the same workspace
-    const bool from_phase = split && P->contraction == JTFS_CONTRACTION_SPLIT_F16_PHASE &&
-                            (flags & JTFS_BWD_REUSE_FORWARD);
+    const bool split = split_backward(P);
+    const bool phase_mode = split && P->contraction == JTFS_CONTRACTION_SPLIT_F16_PHASE;
+    // the phase the forward stored, when this backward follows it on the same
+    // workspace; without that forward, the phase is taken again by the forward
+    // contraction where the recomputing kernel cannot hold the shapes
+    const bool reuse = flags & JTFS_BWD_REUSE_FORWARD;
+    const bool regen_phase = phase_mode && !reuse && !P->split_bwd_ok;
+    const bool from_phase = phase_mode && (reuse || regen_phase);
     unsigned short* Yh = (unsigned short*)(base + w.Yh);
     float* ysc = (float*)(base + w.yscale);
-    if (split && !(flags & JTFS_BWD_REUSE_FORWARD)) {
+    if (split && !reuse) {
         for (int a = 0; a < s.n_alpha; ++a) {
             JTFS_TIMED(JTFS_STAGE_OPERAND_SPLIT, st,
                        rc = launch_ysplit(P, a, Y2, (const float*)(base + w.rowmax), Yh, ysc, B, st));
             if (rc != JTFS_OK) { set_error("operand split kernel failed"); return rc; }
+            if (regen_phase) {
+                JTFS_TIMED(JTFS_STAGE_FREQ_FWD, st,
+                           rc = launch_freq_fwd_split(P, a, Yh, ysc, (float*)(base + w.Vp), w.vp_bstride,
+                                                      (unsigned*)(base + w.phase), w.ph_bstride, B, st));
+                if (rc != JTFS_OK) { if (rc == JTFS_EHIP) set_error("split contraction launch failed"); return rc; }
+            }
         }
     }
     if (from_phase) {

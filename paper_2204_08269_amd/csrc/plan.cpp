@@ -186,10 +186,13 @@ Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq, bool
     w.Yh = take(with_split ? sizeof(float2) * B * s.Kp * s.sumTp : 0);   // 4 halves per complex value
     w.rowmax = take(sizeof(float) * B * s.n_alpha * s.Kp);
     w.yscale = take(sizeof(float) * B * s.n_alpha);
-    w.gvmax = take(sizeof(float) * B * s.n_alpha * 2 * s.n_beta);
     // partial V: per signal, per (alpha, t-chunk, t-half) slot, per l-tile, spin, tau, l
     w.vp_bstride = s.sumch * 2 * (s.Mp / kTileL) * 2 * (int64_t)s.NTp * kTileL;
     w.Vp = take(sizeof(float) * B * w.vp_bstride);
+    w.ph_bstride = (int64_t)2 * s.sumTp * s.Mp;
+    w.phase = take(with_phase ? sizeof(uint32_t) * B * w.ph_bstride : 0);
+    w.fwd_total = o;                 // the forward touches nothing beyond this point
+    w.gvmax = take(sizeof(float) * B * s.n_alpha * 2 * s.n_beta);
     w.gV = take(sizeof(float) * B * s.n_alpha * 2 * s.Mp * s.NTp);
     int64_t maxTp = 0;
     for (int a = 0; a < s.n_alpha; ++a) maxTp = std::max<int64_t>(maxTp, s.Tp[a]);
@@ -198,8 +201,6 @@ Workspace layout(const Shapes& s, int64_t B, bool with_split, bool with_pq, bool
     w.gX = take(sizeof(float) * B * s.n1 * s.NX);
     w.g1 = take(sizeof(float2) * B * s.n1 * s.NX);
     w.gxh = take(sizeof(float2) * B * w.xh_pitch);
-    w.ph_bstride = (int64_t)2 * s.sumTp * s.Mp;
-    w.phase = take(with_phase ? sizeof(uint32_t) * B * w.ph_bstride : 0);
     // gV split for the backward from the stored phase: per rate and 32-row chunk, the
     // FP16 planes of both spins and the rows' scales
     w.gvs_bstride = (int64_t)s.n_alpha * (s.Mp / 32) * (512 * (s.NTp / 32) + 16);

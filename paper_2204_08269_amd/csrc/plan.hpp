@@ -79,6 +79,7 @@ struct Workspace {
     int64_t gvs_bstride = 0;       // 16-byte units of gvs per signal
     int64_t vp_bstride = 0;        // floats of partial V per signal
     size_t total = 0;
+    size_t fwd_total = 0;          // leading part of the layout that the forward uses
     int64_t xh_pitch = 0, Xh_pitch = 0;
 };
 // with_split: the split-FP16 operand copy of Y2; with_pq: the FP32 backward's P/Q';
@@ -132,7 +133,8 @@ struct jtfs_plan {
     // split-FP16 contraction operands (hi + lo halves of power-of-two scaled FP32 values)
     int contraction = 0;           // JTFS_CONTRACTION_FP32, _SPLIT_F16 or _SPLIT_F16_PHASE
     bool split_ok = false;         // shapes allow the split kernels (W tile fits in LDS)
-    bool split_bwd_ok = false;     // ... and the split backward (register budget)
+    bool split_bwd_ok = false;     // ... and the recomputing split backward (register budget)
+    bool split_bwdp_ok = false;    // ... and the stored-phase split backward
     unsigned short* Wsp = nullptr; // [Mp][Kp/8][4][8]: re_hi, re_lo, im_hi, im_lo of W * sw
     float sw = 1.f;
     unsigned short* Phsp = nullptr;  // per alpha [Tp/32][2][2][NTp][2][8]: Phi * sphi[alpha]

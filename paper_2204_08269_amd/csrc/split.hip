@@ -235,6 +235,11 @@ constexpr float kSnormInv = 1.f / 32767.f;
 
 // ------------------------------------------------------- forward contraction
 
+// rows t per pass of a wave's phase transpose in LDS: the whole 32-row tile where
+// it fits beside the resident W rows (64 x (16 NK x 8 + 16) bytes), else 8 rows
+template <int NK>
+constexpr int kPhaseTrp = 64 * (16 * NK * 8 + 16) + 8 * 32 * 36 * 4 <= kMaxDynLds ? 32 : 8;
+
 // One workgroup: 64 rows l (W resident in LDS) x one t-chunk, in tiles of 128 t.
 // Eight waves: wave (wl, wt) owns rows 32 wl.. and t 32 wt.. of each 128-t tile and
 // streams its Y fragments from global memory (no barrier inside the K loop).
@@ -381,25 +386,34 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
             }
             // the wave's 32 x 32 tile of packed phases goes through its own LDS
             // area (rows t, 36-element pitch), so that each lane then stores 16
-            // bytes (four rows l of one t) and a wave's store is a 1 KB run
+            // bytes (four rows l of one t) and a wave's store covers runs of TRP
+            // consecutive t; TRP rows t per pass (32, or 8 where the resident W
+            // tile leaves no room for the whole tile)
             if (phase) {
-                unsigned* tb = (unsigned*)(lds + 64 * WS) + wave * (32 * 36);
+                unsigned* tb = (unsigned*)(lds + 64 * WS) + wave * (kPhaseTrp<NK> * 36);
+                constexpr int TRP = kPhaseTrp<NK>, LTRP = TRP == 32 ? 5 : 3;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const float zr = spin ? rr[r] + ii[r] : rr[r] - ii[r];
-                    const float zi = spin ? ir[r] - ri[r] : ir[r] + ri[r];
-                    const float q = __builtin_amdgcn_rsqf(fmaxf(zr * zr + zi * zi, eps2s));
-                    tb[crow(r, h) * 36 + i32] = pack_snorm16(zr * q, zi * q);
-                }
-                const int tt = lane >> 1, hh = lane & 1;
-                unsigned* pb = phase + b * ph_bstride + ((int64_t)(spin * nlt + lt) * 2 + wl) * 4 * Tp * 8 +
-                               (int64_t)(t0 + wt * 32 + tt) * 8 + 4 * hh;
+                for (int pass = 0; pass < 32 / TRP; ++pass) {
 #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    // read back only by the backward, long after: a streaming store, so that
-                    // it does not evict the Y operand the row tiles share in L2
-                    const u32x4 v = __builtin_bit_cast(u32x4, *(const uint4*)(tb + tt * 36 + 8 * g + 4 * hh));
-                    __builtin_nontemporal_store(v, (u32x4*)(pb + (int64_t)g * Tp * 8));
+                    for (int r = 0; r < 16; ++r) {
+                        if (TRP == 8 && (r >> 2) != pass) continue;   // crow(r, h) / 8 = r / 4
+                        const float zr = spin ? rr[r] + ii[r] : rr[r] - ii[r];
+                        const float zi = spin ? ir[r] - ri[r] : ir[r] + ri[r];
+                        const float q = __builtin_amdgcn_rsqf(fmaxf(zr * zr + zi * zi, eps2s));
+                        tb[(crow(r, h) & (TRP - 1)) * 36 + i32] = pack_snorm16(zr * q, zi * q);
+                    }
+                    unsigned* pb = phase + b * ph_bstride + ((int64_t)(spin * nlt + lt) * 2 + wl) * 4 * Tp * 8 +
+                                   (int64_t)(t0 + wt * 32 + pass * TRP) * 8;
+#pragma unroll
+                    for (int k = 0; k < TRP / 8; ++k) {
+                        // element e of the pass: half hh of row group g at row tt
+                        const int e = lane + 64 * k;
+                        const int hh = e & 1, tt = (e >> 1) & (TRP - 1), g = e >> (1 + LTRP);
+                        // read back only by the backward, long after: a streaming store, so
+                        // that it does not evict the Y operand the row tiles share in L2
+                        const u32x4 v = __builtin_bit_cast(u32x4, *(const uint4*)(tb + tt * 36 + 8 * g + 4 * hh));
+                        __builtin_nontemporal_store(v, (u32x4*)(pb + (int64_t)g * Tp * 8 + tt * 8 + 4 * hh));
+                    }
                 }
             }
             m = fmaxf(m, __shfl_xor(m, 32));
@@ -519,12 +533,13 @@ __device__ __forceinline__ void stage_w(uint4* Ls, const uint4* Wsrc, int c, int
     for (int j = 0; j < nK; ++j) dma16(base + 8 * j, off, dst + 256 * j);
 }
 
-// W^T chunk c (KpT = 32 NI rows) into LDS, slot e = seg * 32 + i32 with
+// W^T chunk c (NI blocks of 32 rows i) into LDS, slot e = seg * 32 + i32 with
 // seg = q * 16 + (sp * 2 + h) * 4 + p: the table holds the chunk in this order, so
-// that the wave's 64 lanes copy 1 KB runs.
+// that the wave's 64 lanes copy 1 KB runs.  Chunks are cstride slots apart in the
+// table (512 per i-block of the whole K); Tsrc points at the first staged block.
 template <int NI>
-__device__ __forceinline__ void stage_t(uint4* Ls, const uint4* Tsrc, int c, int wave, int lane) {
-    const uint4* base = Tsrc + (int64_t)c * (NI * 512);
+__device__ __forceinline__ void stage_t(uint4* Ls, const uint4* Tsrc, int c, int64_t cstride, int wave, int lane) {
+    const uint4* base = Tsrc + (int64_t)c * cstride;
     const uint32_t off = (uint32_t)(wave * 64 + lane) * 16u;
     uint4* dst = Ls + wave * 64;
 #pragma unroll
@@ -611,7 +626,7 @@ __device__ __forceinline__ void bwd_chunk(int c, int nC, int Mp, int wave, int l
     __builtin_amdgcn_s_barrier();
     const int cn = c + 1 < nC ? c + 1 : c;
     stage_w(Ls_W, Wsrc, cn, NK, 2 * NK, wave, lane);
-    stage_t<NI>(Tnext, Tsrc, cn, wave, lane);
+    stage_t<NI>(Tnext, Tsrc, cn, (int64_t)NI * 512, wave, lane);
     // ---- gU = gV Phi^T for both spins (gV split per row, Phi pre-split), times spq
     floatx16 gu[2];
 #pragma unroll
@@ -772,7 +787,7 @@ __global__ void __launch_bounds__(256) k_freq_bwd_h(const unsigned short* __rest
 #pragma unroll
     for (int s = 0; s < (NK < 4 ? NK : 4); ++s) load_y(yr[s], (gptr<uint4>)ycol, s);
     stage_w(Ls_W, Wsrc, 0, NK, nkb, wave, lane);
-    stage_t<NI>(Ls_T0, Tsrc, 0, wave, lane);
+    stage_t<NI>(Ls_T0, Tsrc, 0, (int64_t)NI * 512, wave, lane);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     // nC is even (Mp is a multiple of 64): the W^T buffers alternate at compile
@@ -1038,14 +1053,15 @@ template <int NTB, int NI>
 __device__ __forceinline__ void bwd_phase_chunk(int c, int nC, int wave, int lane, int tid, int h, int i32,
                                                 const uint4 (&phv)[NTB * 2][2], const uint4* Tsrc, const uint4* Gb,
                                                 uint4* Ls_G, const unsigned* pbase, int64_t spin_stride,
-                                                int64_t c_stride, float c0, const uint4* Tcur, uint4* Tnext,
+                                                int64_t c_stride, float c0, int64_t cstride, const uint4* Tcur,
+                                                uint4* Tnext,
                                                 floatx16 (&gyr)[NI], floatx16 (&gyi)[NI], floatx16 (&gu)[2],
                                                 uint4 (&pv)[2][4], half8 (&ph)[2][4], half8 (&pl)[2][4]) {
     constexpr int NG = (NI + 1) / 2;             // pairs of i-blocks
     const int cn = c + 1 < nC ? c + 1 : c;       // the last chunk reloads itself
     WtFrag f[2];
     // ---- first half
-    stage_t<NI>(Tnext, Tsrc, cn, wave, lane);
+    stage_t<NI>(Tnext, Tsrc, cn, cstride, wave, lane);
     stage_g<NTB>(Ls_G, Gb, cn, tid);
     load_phase_half(pv, 0, launder_v((const uint4*)(pbase + cn * c_stride)), spin_stride, c_stride / 4);
     load_wt<NI>(f[0], Tcur, 0, 0, h, i32);
@@ -1088,10 +1104,14 @@ __device__ __forceinline__ void bwd_phase_chunk(int c, int nC, int wave, int lan
 }
 
 // Backward contraction from the stored phase: one signal, 128 columns t (four
-// waves of 32), all rows l in 32-row chunks; gY accumulated in registers.
+// waves of 32), all rows l in 32-row chunks; gY accumulated in registers for the
+// NI i-blocks q_base .. q_base + NI - 1 of the nit blocks of W^T (the register
+// budget holds at most 8 at 32 frames; larger K runs as several launches over
+// disjoint i-ranges, each repeating the modulus adjoint).
 template <int NTB, int NI>
 __global__ void __launch_bounds__(256) k_freq_bwd_p(const unsigned* __restrict__ phase, int64_t ph_bstride, int Tp,
                                                     int nTt, int nU, const unsigned short* __restrict__ WTsp,
+                                                    int q_base, int nit,
                                                     int Mp, int Kp, const unsigned short* __restrict__ PhTsp,
                                                     float sphi, const uint4* __restrict__ Gs, int64_t gs_bstride,
                                                     const float* __restrict__ gvmax, int n_beta, int alpha,
@@ -1120,7 +1140,8 @@ __global__ void __launch_bounds__(256) k_freq_bwd_p(const unsigned* __restrict__
     for (int q = 0; q < NI; ++q) { gyr[q] = z16(); gyi[q] = z16(); }
 
     const uint4* phrow = (const uint4*)(PhTsp + ((int64_t)(tw0 + i32) * (NTp / 8) + h) * 16);
-    const uint4* Tsrc = (const uint4*)WTsp;
+    const uint4* Tsrc = (const uint4*)WTsp + (int64_t)q_base * 512;
+    const int64_t cstride = (int64_t)nit * 512;
     const uint4* Gb = Gs + b * gs_bstride;
     // this lane's column of the stored phase, rows 4h.. of each 8-row group
     // (blocks [spin][Mp / 32], each four row groups of Tp x 8 elements)
@@ -1137,7 +1158,7 @@ __global__ void __launch_bounds__(256) k_freq_bwd_p(const unsigned* __restrict__
     floatx16 gu[2];
     half8 ph[2][4], pl[2][4];
     // chunk 0: operands, gU and the P/Q' of its rows 0-15
-    stage_t<NI>(Ls_T0, Tsrc, 0, wave, lane);
+    stage_t<NI>(Ls_T0, Tsrc, 0, cstride, wave, lane);
     stage_g<NTB>(Ls_G, Gb, 0, tid);
     load_phase_half(pv, 0, (gptr<uint4>)pbase, spin_stride, c_stride / 4);
     load_phase_half(pv, 1, (gptr<uint4>)pbase, spin_stride, c_stride / 4);
@@ -1150,9 +1171,9 @@ __global__ void __launch_bounds__(256) k_freq_bwd_p(const unsigned* __restrict__
     // nC is even (Mp is a multiple of 64): the W^T buffers alternate at compile time
     for (int c = 0; c < nC; c += 2) {
         bwd_phase_chunk<NTB, NI>(c, nC, wave, lane, tid, h, i32, phv, Tsrc, Gb, Ls_G, pbase, spin_stride, c_stride,
-                                 c0, Ls_T0, Ls_T1, gyr, gyi, gu, pv, ph, pl);
+                                 c0, cstride, Ls_T0, Ls_T1, gyr, gyi, gu, pv, ph, pl);
         bwd_phase_chunk<NTB, NI>(c + 1, nC, wave, lane, tid, h, i32, phv, Tsrc, Gb, Ls_G, pbase, spin_stride,
-                                 c_stride, c0, Ls_T1, Ls_T0, gyr, gyi, gu, pv, ph, pl);
+                                 c_stride, c0, cstride, Ls_T1, Ls_T0, gyr, gyi, gu, pv, ph, pl);
     }
     const float inv = 1.f / (sw * spq);
     float2* o = gY + b * gy_bstride;
@@ -1160,7 +1181,7 @@ __global__ void __launch_bounds__(256) k_freq_bwd_p(const unsigned* __restrict__
     for (int q = 0; q < NI; ++q)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int i = q * 32 + crow(r, h);
+            const int i = (q_base + q) * 32 + crow(r, h);
             if (i < Kp) o[(int64_t)i * Tp + tw0 + i32] = make_float2(gyr[q][r] * inv, gyi[q][r] * inv);
         }
 }
@@ -1172,14 +1193,17 @@ using namespace jtfs;
 namespace jtfs {
 
 size_t split_fwd_lds(const Shapes& s, bool with_phase);
+int bwdp_max_ni(int NTp);
 
 bool split_supported(const Shapes& s) { return split_fwd_lds(s, false) <= (size_t)kMaxDynLds && s.NTp <= 64; }
 
 // LDS of k_freq_fwd_h: resident W rows during the main loop (with the stored phase
-// also a 32 x 36-element transpose area per wave), then the cross-wave reduction
-// buffer (8 waves x 2 spins x 64 lanes x 16 floats).
+// also a transpose area of 32 or 8 rows of 36 elements per wave), then the
+// cross-wave reduction buffer (8 waves x 2 spins x 64 lanes x 16 floats).
 size_t split_fwd_lds(const Shapes& s, bool with_phase) {
-    const size_t main_loop = (size_t)64 * (s.Kp * 8 + 16) + (with_phase ? (size_t)8 * 32 * 36 * 4 : 0);
+    const size_t wres = (size_t)64 * (s.Kp * 8 + 16);
+    const size_t trans = wres + (size_t)8 * 32 * 36 * 4 <= (size_t)kMaxDynLds ? 32 : 8;   // kPhaseTrp
+    const size_t main_loop = wres + (with_phase ? (size_t)8 * trans * 36 * 4 : 0);
     const size_t reduction = (size_t)8 * 2 * 64 * 16 * sizeof(float);
     return std::max(main_loop, reduction);
 }
@@ -1236,8 +1260,12 @@ int build_split_tables(jtfs_plan* P, std::vector<void*>& owned) {
         set_error("split-operand construction failed"); return JTFS_EHIP; }
     {
         const int NI = P->KpT / 32;
-        // static LDS of the backward: W chunk + two W^T chunks, 24 NI KB (<= 160 KB)
+        // recomputing backward: static LDS of a W chunk and two W^T chunks, 24 NI KB
+        // (<= 160 KB), and one wave per SIMD without scratch
         P->split_bwd_ok = (s.NTp == 32 && NI <= 6) || (s.NTp == 64 && NI <= 5);
+        // stored-phase backward: two W^T chunks (16 NI KB) per launch, at most two
+        // launches over halves of the i-blocks
+        P->split_bwdp_ok = NI <= 2 * bwdp_max_ni(s.NTp);
     }
     P->contraction = JTFS_CONTRACTION_SPLIT_F16;
     return JTFS_OK;
@@ -1365,20 +1393,25 @@ int launch_freq_bwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, c
     return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
 }
 
+// i-blocks one phase-backward workgroup holds in registers without scratch
+// (one wave per SIMD): 8 at 32 frames, 5 at 64
+int bwdp_max_ni(int NTp) { return NTp == 32 ? 8 : NTp == 64 ? 5 : 0; }
+
 template <int NTB>
-static void launch_bwdp_ni(int NI, dim3 grid, hipStream_t st, const unsigned* pha, int64_t phb, int Tp, int nTt,
-                           int nU, const jtfs_plan* P, const unsigned short* PhT, float sphi, const uint4* Gsa,
-                           int64_t gsb, const float* gvmax, int a, float2* gYa, int64_t gyb) {
+static void launch_bwdp_ni(int NI, int q_base, int nit, dim3 grid, hipStream_t st, const unsigned* pha, int64_t phb,
+                           int Tp, int nTt, int nU, const jtfs_plan* P, const unsigned short* PhT, float sphi,
+                           const uint4* Gsa, int64_t gsb, const float* gvmax, int a, float2* gYa, int64_t gyb) {
     const Shapes& s = P->s;
 #define JTFS_BWDP_CASE(ni)                                                                                    \
     case ni:                                                                                                  \
         hipLaunchKernelGGL((k_freq_bwd_p<NTB, ni>), grid, dim3(256), 0, st, pha, phb, Tp, nTt, nU, P->WTsp, \
-                           s.Mp, s.Kp, PhT, sphi, Gsa, gsb, gvmax, s.n_beta, a, s.n_alpha, P->sw, gYa, gyb);  \
+                           q_base, nit, s.Mp, s.Kp, PhT, sphi, Gsa, gsb, gvmax, s.n_beta, a, s.n_alpha, P->sw, \
+                           gYa, gyb);                                                                         \
         break;
     if constexpr (NTB == 1) {
         switch (NI) {
             JTFS_BWDP_CASE(1) JTFS_BWDP_CASE(2) JTFS_BWDP_CASE(3) JTFS_BWDP_CASE(4)
-            JTFS_BWDP_CASE(5) JTFS_BWDP_CASE(6)
+            JTFS_BWDP_CASE(5) JTFS_BWDP_CASE(6) JTFS_BWDP_CASE(7) JTFS_BWDP_CASE(8)
             default: break;
         }
     } else {
@@ -1406,7 +1439,12 @@ int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int6
                           int64_t gs_bstride, const float* gvmax, float2* gY2, int64_t B, hipStream_t st) {
     const Shapes& s = P->s;
     const int NI = P->KpT / 32;
-    if (!P->split_bwd_ok) { set_error("split backward not available for these shapes"); return JTFS_ENOTSUP; }
+    if (!P->split_bwdp_ok) { set_error("stored-phase backward not available for these shapes"); return JTFS_ENOTSUP; }
+    // one launch per range of i-blocks: a single one up to the register budget, else
+    // two balanced halves
+    const int nmax = bwdp_max_ni(s.NTp);
+    const int ng = NI <= nmax ? 1 : 2;
+    const int nia = (NI + ng - 1) / ng;
     const int nTt = s.Tp[a] / kTileTh;
     const int nU = (int)(B * nTt);
     const int64_t yb = (int64_t)s.Kp * s.sumTp;
@@ -1415,10 +1453,14 @@ int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int6
     // this rate's chunks of the split gV
     const uint4* Gsa = Gs + (int64_t)a * (s.Mp / 32) * (512 * (s.NTp / 32) + 16);
     float2* gYa = gY2 + s.yoff[a];
-    switch (s.NTp / 32) {
-        case 1: launch_bwdp_ni<1>(NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], Gsa, gs_bstride, gvmax, a, gYa, yb); break;
-        case 2: launch_bwdp_ni<2>(NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], Gsa, gs_bstride, gvmax, a, gYa, yb); break;
-        default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
+    for (int g = 0, q0 = 0; g < ng; ++g) {
+        const int ni = g == 0 ? nia : NI - nia;
+        switch (s.NTp / 32) {
+            case 1: launch_bwdp_ni<1>(ni, q0, NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], Gsa, gs_bstride, gvmax, a, gYa, yb); break;
+            case 2: launch_bwdp_ni<2>(ni, q0, NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], Gsa, gs_bstride, gvmax, a, gYa, yb); break;
+            default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
+        }
+        q0 += ni;
     }
     return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
 }
@@ -1434,7 +1476,7 @@ extern "C" int jtfs_plan_set_contraction(jtfs_plan* P, int mode) {
         return JTFS_OK;
     }
     if (mode == JTFS_CONTRACTION_SPLIT_F16_PHASE) {
-        if (!P->split_ok || !P->split_bwd_ok || P->s.tscat) {
+        if (!P->split_ok || !P->split_bwdp_ok || P->s.tscat) {
             set_error("split-FP16 contraction with stored phase not available for these shapes");
             return JTFS_ENOTSUP;
         }

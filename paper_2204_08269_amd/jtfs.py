@@ -86,6 +86,11 @@ class JTFS:
         _lib.check(self.lib.jtfs_workspace_size(self.plan, int(B), ctypes.byref(n)))
         return n.value
 
+    def forward_workspace_bytes(self, B: int) -> int:
+        n = ctypes.c_size_t(0)
+        _lib.check(self.lib.jtfs_forward_workspace_size(self.plan, int(B), ctypes.byref(n)))
+        return n.value
+
     def new_workspace(self, B: int) -> torch.Tensor:
         return torch.empty(self.workspace_bytes(B), dtype=torch.uint8, device=self.device)
 

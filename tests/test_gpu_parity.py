@@ -275,8 +275,9 @@ def test_cfg3_full_batch_sampled_forward_and_gradient():
     cotangent on S1 and on those two rates.  At the click trains themselves the
     gradient is ill-conditioned in any FP32 arithmetic: between clicks the
     high-frequency first-order outputs sit at the rounding floor, and the phase
-    factor y/|y| of the modulus adjoint there is rounding noise (a 1e-7 relative
-    perturbation of y moves the FP64 gradient by about 6 %)."""
+    factor y/|y| of the modulus adjoint there is rounding noise (an input change
+    of 1e-7 of its RMS moves the FP64 gradient by several percent at the target,
+    by about 1e-7 at the start: test_click_train_gradient_is_ill_conditioned)."""
     p = synth.PARAMS[3]
     y, x0 = synth.cfg3_batch()
     P = oracle_plan(p)
@@ -332,6 +333,73 @@ def test_cfg5_full_batch_sampled_and_properties(mode):
     expect = 0.5 * A * np.abs(P.psi1_hat[:, m])
     assert np.max(np.abs(t1[0] - expect[:, None])) <= 1e-5 * expect.max()
     assert np.max(np.abs(t2)) <= 1e-5 * expect.max()
+
+
+CFG5_REF = None
+
+
+def cfg5_reference():
+    """FP64 oracle outputs of the 32 x 2^18 workload (signals 0 and 31; S2 at
+    three temporal rates; the VJP of signal 0), written by
+    tests/golden/make_cfg5_reference.py, which calls only the oracle."""
+    global CFG5_REF
+    if CFG5_REF is None:
+        import hashlib
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg5_reference.npz")
+        ref = dict(np.load(path, allow_pickle=False))
+        x = synth.batch(5)
+        assert str(ref["x_sha256"]) == hashlib.sha256(np.ascontiguousarray(x).tobytes()).hexdigest(), \
+            "the seeded 2^18 inputs differ from those the stored reference was computed on"
+        ref["x"] = x
+        CFG5_REF = ref
+    return CFG5_REF
+
+
+@pytest.mark.parametrize("mode", ["fp32", "split16", "split16_phase"])
+def test_cfg5_s2_and_gradient_match_oracle(mode):
+    """32 x 2^18 FM mixtures (n1 = 285: K = 288, 18 k-steps of the split forward,
+    9 i-blocks of the backward), in the launch configuration of the benchmark
+    (the whole batch): every S1 path and every (beta, theta) path of S2 at the
+    temporal rates k2 = 0 (rows of 2^15 points), a middle one and the shortest,
+    for the first and last signal, against the FP64 oracle; the gradient of
+    signal 0 for a cotangent on S1 and those rates against the oracle's VJP,
+    after a forward on the same workspace (the stored-phase mode reads the
+    phase it kept) and without one (that mode then takes the phase again)."""
+    p = synth.PARAMS[5]
+    ref = cfg5_reference()
+    x = ref["x"]
+    alphas = [int(a) for a in ref["alphas"]]
+    op = gpu_op(p, mode)
+    assert op.contraction == mode
+    B = x.shape[0]
+    xt = torch.from_numpy(x).cuda()
+    ws = op.new_workspace(B)
+    s1, s2 = op.forward(xt, ws)
+    torch.cuda.synchronize()
+    g1, g2 = s1.cpu().numpy(), s2.cpu().numpy()
+    for b in (int(v) for v in ref["signals"]):
+        e1, _ = path_errors(g1[b], ref[f"s1_{b}"], 1)
+        e2, _ = path_errors(g2[b][alphas], ref[f"s2_{b}"], 3)
+        assert e1.max() <= TOL, f"signal {b}: S1 worst path error {e1.max():.3e}"
+        assert e2.max() <= TOL, f"signal {b}: S2 worst path error {e2.max():.3e} at {np.unravel_index(e2.argmax(), e2.shape)}"
+    Po = oracle_plan(p)
+    gs1 = np.zeros((B,) + Po.s1_shape(), np.float32)
+    gs2 = np.zeros((B,) + Po.s2_shape(), np.float32)
+    c1, c2 = synth.cotangents((1,) + Po.s1_shape(), (1,) + Po.s2_shape(), seed=9)
+    keep = np.zeros(Po.n_alpha, bool)
+    keep[alphas] = True
+    c2[:, ~keep] = 0.0
+    gs1[0], gs2[0] = c1[0], c2[0]
+    gs1t, gs2t = torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda()
+    for reuse in (True, False):
+        gx = op.vjp(xt, gs1t, gs2t, ws=ws, reuse_forward=reuse)
+        torch.cuda.synchronize()
+        err = rel_l2(gx[0].cpu().numpy(), ref["gx_0"])
+        assert err <= TOL_VJP, f"reuse_forward={reuse}: gradient relative L2 {err:.3e}"
+        assert float(gx[1:].abs().max()) == 0.0, "a signal with zero cotangent got a gradient"
+    del ws
+    torch.cuda.empty_cache()
 
 
 # Eq. (4): no frequential averaging.  The packed (beta, theta) slices are spread
