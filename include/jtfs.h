@@ -146,6 +146,24 @@ int jtfs_forward_workspace_size(const jtfs_plan* plan, int64_t B, size_t* bytes)
 int jtfs_forward(const jtfs_plan* plan, const float* x, int64_t B, float* s1, float* s2,
                  void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): jtfs_forward with its
+ * workspace taken from a fixed array of JTFS_NOALLOC_SCRATCH_BYTES bytes that the
+ * library keeps on every GPU it runs on until the process ends (256 MiB; e.g. up
+ * to 128 signals of 2^11 samples or 1 signal of 2^16 samples with the
+ * 64 x 2^16 chirp parameters).  x, s1, s2: caller-owned device buffers, layouts
+ * of jtfs_forward.  The current device must be the plan's.  Calls no allocating
+ * routine and records no stage events.  Every call on one GPU uses the same
+ * array and leaves its last contents there (the transform writes every scratch
+ * value it reads, so nothing needs clearing); calls that overlap on one GPU
+ * (concurrent streams or threads) race on it and must be serialised by the
+ * caller.  Errors: JTFS_EWORKSPACE if the plan's forward workspace for B
+ * signals (jtfs_forward_workspace_size) exceeds the array, else those of
+ * jtfs_forward. */
+#define JTFS_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int jtfs_forward_noalloc(const jtfs_plan* plan, const float* x, int64_t B, float* s1, float* s2,
+                         hipStream_t stream);
+
 /* gx = d<gS1,S1(x)> + <gS2,S2(x)> / dx for B signals.  gx is overwritten.
  * Either of gs1 / gs2 may be NULL (a zero cotangent). */
 int jtfs_backward(const jtfs_plan* plan, const float* x, const float* gs1, const float* gs2,

@@ -18,6 +18,7 @@ JTFS_EHIP = -3
 JTFS_EWORKSPACE = -4
 JTFS_ENOTSUP = -6
 JTFS_BWD_REUSE_FORWARD = 1
+JTFS_NOALLOC_SCRATCH_BYTES = 256 << 20
 JTFS_NO_FREQ_AVERAGE = 1
 JTFS_TIME_SCATTERING = 2
 JTFS_CONTRACTION_FP32 = 0
@@ -54,7 +55,7 @@ EXPORTS = ["jtfs_query", "jtfs_query_filters", "jtfs_plan_create", "jtfs_plan_cr
            "jtfs_bucket_run", "jtfs_bucket_destroy", "jtfs_path_means", "jtfs_mulog", "jtfs_mulog_backward",
            "jtfs_texture_create", "jtfs_texture_set_target", "jtfs_texture_set_start", "jtfs_texture_iterate",
            "jtfs_texture_read", "jtfs_texture_destroy", "jtfs_plan_autotune", "jtfs_plan_set_tuning",
-           "jtfs_plan_get_tuning",
+           "jtfs_plan_get_tuning", "jtfs_forward_noalloc",
            "jtfs_timing_enable", "jtfs_timing_read", "jtfs_last_error"]
 
 _lib = None
@@ -88,6 +89,7 @@ def load(path: str = LIB_PATH):
     L.jtfs_workspace_size.argtypes = [vp, i64, P(sz)]
     L.jtfs_forward_workspace_size.argtypes = [vp, i64, P(sz)]
     L.jtfs_forward.argtypes = [vp, vp, i64, vp, vp, vp, sz, vp]
+    L.jtfs_forward_noalloc.argtypes = [vp, vp, i64, vp, vp, vp]
     L.jtfs_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, sz, u32, vp]
     L.jtfs_plan_table.argtypes = [vp, ctypes.c_int, vp, sz]
     L.jtfs_plan_set_contraction.argtypes = [vp, ctypes.c_int]

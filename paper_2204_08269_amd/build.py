@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjtfs.so")
 ARCH = "gfx950"
 
-SOURCES = ["plan.cpp", "timing.cpp", "filters.hip", "kernels.hip", "split.hip", "bucket.hip", "kernels_reg.hip", "mulog.hip", "texture.hip", "autotune.cpp"]
+SOURCES = ["plan.cpp", "timing.cpp", "filters.hip", "kernels.hip", "split.hip", "bucket.hip", "kernels_reg.hip", "mulog.hip", "texture.hip", "autotune.cpp", "noalloc.hip"]
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of every device code object

@@ -20,9 +20,15 @@ hipEvent_t take() {
 }
 }  // namespace
 
+static thread_local int t_quiet = 0;
+
 bool timing_on() { std::lock_guard<std::mutex> l(g_mu); return g_on; }
 
+TimingSuppressed::TimingSuppressed() { ++t_quiet; }
+TimingSuppressed::~TimingSuppressed() { --t_quiet; }
+
 TimedLaunch::TimedLaunch(int stage, hipStream_t st) : stage_(stage), st_(st) {
+    if (t_quiet) return;
     std::lock_guard<std::mutex> l(g_mu);
     if (!g_on) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;

@@ -6,6 +6,12 @@
 
 namespace jtfs {
 bool timing_on();
+// While an object of this type lives, launches of the calling thread record no
+// stage events (for paths that must not create any).
+struct TimingSuppressed {
+    TimingSuppressed();
+    ~TimingSuppressed();
+};
 class TimedLaunch {
   public:
     TimedLaunch(int stage, hipStream_t st);
