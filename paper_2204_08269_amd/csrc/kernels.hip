@@ -1280,10 +1280,10 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     }
     for (int a = 0; a < s.n_alpha && split; ++a) {
         if (from_phase) {
-            JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,
-                       rc = launch_freq_bwd_phase(P, a, (const unsigned*)(base + w.phase), w.ph_bstride,
-                                                  (const uint4*)(base + w.gvs), w.gvs_bstride,
-                                                  (const float*)(base + w.gvmax), gY2, B, st));
+            // (one or two launches, each timed on its own)
+            rc = launch_freq_bwd_phase(P, a, (const unsigned*)(base + w.phase), w.ph_bstride,
+                                       (const uint4*)(base + w.gvs), w.gvs_bstride, (const float*)(base + w.gvmax),
+                                       gY2, B, st);
         } else {
             JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,
                        rc = launch_freq_bwd_split(P, a, Yh, ysc, gV, (const float*)(base + w.gvmax), gY2, B, st));

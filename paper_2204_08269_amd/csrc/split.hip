@@ -1456,8 +1456,8 @@ int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int6
     for (int g = 0, q0 = 0; g < ng; ++g) {
         const int ni = g == 0 ? nia : NI - nia;
         switch (s.NTp / 32) {
-            case 1: launch_bwdp_ni<1>(ni, q0, NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], Gsa, gs_bstride, gvmax, a, gYa, yb); break;
-            case 2: launch_bwdp_ni<2>(ni, q0, NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], Gsa, gs_bstride, gvmax, a, gYa, yb); break;
+            case 1: JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st, launch_bwdp_ni<1>(ni, q0, NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], Gsa, gs_bstride, gvmax, a, gYa, yb)); break;
+            case 2: JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st, launch_bwdp_ni<2>(ni, q0, NI, dim3(nU), st, pha, ph_bstride, s.Tp[a], nTt, nU, P, PhT, P->sphi[a], Gsa, gs_bstride, gvmax, a, gYa, yb)); break;
             default: set_error("unsupported N/T"); return JTFS_ENOTSUP;
         }
         q0 += ni;
