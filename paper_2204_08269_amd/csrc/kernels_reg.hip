@@ -12,7 +12,8 @@
 
 namespace jtfs {
 
-constexpr int kRegE = 32;
+constexpr int kRegE = 16;                            // values per thread
+constexpr int kRegT = (1 << kRegMinLog) / kRegE;     // threads per row transform of 2^14 points
 
 // fold of src * ps over the band [lo, hi] onto M = 2^logM bins, at bin p
 __device__ __forceinline__ float2 fold_at(const float2* __restrict__ src, const float* __restrict__ ps, int lo, int hi,
@@ -32,16 +33,17 @@ __device__ __forceinline__ float2 fold_at(const float2* __restrict__ src, const 
 // of reg_fft), folded from src * ps over [lo, hi].  When the band fits the row
 // every bin receives at most one band sample, and the loads go out four
 // elements at a time with no loop between them.
+template <int LOGM>
 __device__ __forceinline__ void fold_inputs(float2 (&v)[kRegE], const float2* __restrict__ src,
-                                            const float* __restrict__ ps, int lo, int hi, int logM) {
-    const int M = 1 << logM;
+                                            const float* __restrict__ ps, int lo, int hi) {
+    constexpr int M = 1 << LOGM;
     if (hi - lo < M) {
 #pragma unroll
         for (int e0 = 0; e0 < kRegE; e0 += 4) {
             float g[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int p = reg_input_pos(e0 + q, logM);
+                const int p = reg_input_pos<LOGM, kRegE>(e0 + q);
                 const int m = lo + ((p - lo) & (M - 1));
                 const bool ok = m <= hi;
                 v[e0 + q] = ok ? src[m] : make_float2(0.f, 0.f);
@@ -53,7 +55,7 @@ __device__ __forceinline__ void fold_inputs(float2 (&v)[kRegE], const float2* __
         return;
     }
 #pragma unroll
-    for (int e = 0; e < kRegE; ++e) v[e] = fold_at(src, ps, lo, hi, logM, reg_input_pos(e, logM));
+    for (int e = 0; e < kRegE; ++e) v[e] = fold_at(src, ps, lo, hi, LOGM, reg_input_pos<LOGM, kRegE>(e));
 }
 
 // Rows of 2^15 points run as two 2^14-point register transforms:
@@ -77,38 +79,69 @@ __device__ __forceinline__ void load_dif(float2 (&v)[kRegE], float* A, float* B,
 #pragma unroll
             for (int e = 0; e < kRegE; ++e) v[e] = make_float2(0.f, 0.f);
         } else {
-            fold_inputs(v, src, ps, lo, hi, logn);
+            fold_inputs<kRegMinLog>(v, src, ps, lo, hi);
         }
         return;
     }
     const int logS = logn - 1;
     const int m = 1 << logS;
+    const int n = 1 << logn;
     __syncthreads();                                   // A, B free (2^logn floats)
-    for (int p = threadIdx.x; p < m; p += blockDim.x) {
-        float2 u = make_float2(0.f, 0.f);
-        if (!zero) {
-            const float2 a = fold_at(src, ps, lo, hi, logn, p);
-            if (TWO) {
-                const float2 c = fold_at(src, ps, lo, hi, logn, p + m);
-                u = half == 0 ? cadd(a, c) : cmul(csub(a, c), twiddle(tw, p << (tw_log - logn), true));
-            } else {
-                u = a;
+    if (zero) {
+        for (int p = threadIdx.x; p < m; p += blockDim.x) { A[p] = 0.f; B[p] = 0.f; }
+    } else if (hi - lo < 2 * n) {
+        // every bin of the row receives at most two band samples: a thread requests
+        // all samples (and twiddles) of KU positions before forming any of them,
+        // instead of waiting for each position's loads in turn
+        constexpr int KU = 4;
+        for (int p0 = threadIdx.x; p0 < m; p0 += KU * (int)blockDim.x) {
+            float2 sa[KU][2], sc[KU][2], w[KU];
+            float ga[KU][2], gc[KU][2];
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const int p = p0 + u * (int)blockDim.x;
+                const int ma = lo + ((p - lo) & (n - 1)), mc = lo + ((p + m - lo) & (n - 1));
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const bool oka = p < m && ma + k * n <= hi, okc = p < m && mc + k * n <= hi;
+                    sa[u][k] = oka ? src[ma + k * n] : make_float2(0.f, 0.f);
+                    ga[u][k] = oka ? ps[ma + k * n - lo] : 0.f;
+                    sc[u][k] = okc ? src[mc + k * n] : make_float2(0.f, 0.f);
+                    gc[u][k] = okc ? ps[mc + k * n - lo] : 0.f;
+                }
+                w[u] = half == 1 && p < m ? twiddle(tw, p << (tw_log - logn), true) : make_float2(1.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const int p = p0 + u * (int)blockDim.x;
+                if (p >= m) continue;
+                const float2 a = cadd(cscale(sa[u][0], ga[u][0]), cscale(sa[u][1], ga[u][1]));
+                const float2 c = cadd(cscale(sc[u][0], gc[u][0]), cscale(sc[u][1], gc[u][1]));
+                const float2 q = half == 0 ? cadd(a, c) : cmul(csub(a, c), w[u]);
+                A[p] = q.x;
+                B[p] = q.y;
             }
         }
-        A[p] = u.x;
-        B[p] = u.y;
+    } else {
+        for (int p = threadIdx.x; p < m; p += blockDim.x) {
+            const float2 a = fold_at(src, ps, lo, hi, logn, p);
+            const float2 c = fold_at(src, ps, lo, hi, logn, p + m);
+            const float2 q = half == 0 ? cadd(a, c) : cmul(csub(a, c), twiddle(tw, p << (tw_log - logn), true));
+            A[p] = q.x;
+            B[p] = q.y;
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < kRegE; ++e) {
-        const int q = reg_input_pos(e, logS);
+        const int q = reg_input_pos<kRegMinLog, kRegE>(e);
         v[e] = make_float2(A[q], B[q]);
     }
 }
 
 // scalogram row -> X_hat (same computation as the in-LDS scalogram kernel)
 template <bool TWO>
-__global__ void __launch_bounds__(512) k_scalogram_r(const float2* __restrict__ xh, int64_t xh_pitch,
+__global__ void __launch_bounds__(kRegT) k_scalogram_r(const float2* __restrict__ xh, int64_t xh_pitch,
                                                      const float* __restrict__ psi1, const int* __restrict__ band1,
                                                      const int64_t* __restrict__ off1, float2* __restrict__ Xh,
                                                      int64_t Xh_pitch, int logNX, float invN,
@@ -127,44 +160,45 @@ __global__ void __launch_bounds__(512) k_scalogram_r(const float2* __restrict__ 
     float even[TWO ? kRegE : 1];
     if constexpr (TWO) {
         load_dif<true>(v, A, Bf, src, ps, lo, hi, logNX, 0, tw, tw_log, false);
-        reg_fft<kRegE>(v, A, logS, tw, tw_log, true);
+        reg_fft<kRegE, kRegMinLog>(v, A, tw, tw_log, true);
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) even[e] = __builtin_amdgcn_sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN;   // X[2 pos]
         load_dif<true>(v, A, Bf, src, ps, lo, hi, logNX, 1, tw, tw_log, false);
-        reg_fft<kRegE>(v, A, logS, tw, tw_log, true);
+        reg_fft<kRegE, kRegMinLog>(v, A, tw, tw_log, true);
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
-            const int pos = reg_output_pos(e, logS);
+            const int pos = reg_output_pos<kRegMinLog, kRegE>(e);
             xbuf[pos] = even[e];                                              // X[2 pos]
             xbuf[H + pos] = __builtin_amdgcn_sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN; // X[2 pos + 1]
         }
     } else {
         // the whole row fits one register transform; the exchange buffer is NX floats
         __syncthreads();
-        fold_inputs(v, src, ps, lo, hi, logNX);
-        reg_fft<kRegE>(v, xbuf, logNX, tw, tw_log, true);
+        fold_inputs<kRegMinLog>(v, src, ps, lo, hi);
+        reg_fft<kRegE, kRegMinLog>(v, xbuf, tw, tw_log, true);
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
-            const int pos = reg_output_pos(e, logNX);
+            const int pos = reg_output_pos<kRegMinLog, kRegE>(e);
             xbuf[(pos & 1) * H + (pos >> 1)] = __builtin_amdgcn_sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN;
         }
     }
     __syncthreads();
     // real FFT of X through the complex FFT of z[k] = X[2k] + i X[2k+1] (H points)
     constexpr int EZ = TWO ? kRegE : kRegE / 2;
+    constexpr int LH = TWO ? kRegMinLog : kRegMinLog - 1;      // log2 H
     float2 z[EZ];
 #pragma unroll
     for (int e = 0; e < EZ; ++e) {
-        const int k = reg_input_pos(e, logH);
+        const int k = reg_input_pos<LH, EZ>(e);
         z[e] = make_float2(xbuf[k], xbuf[H + k]);
     }
-    reg_fft<EZ>(z, xbuf, logH, tw, tw_log, false);
+    reg_fft<EZ, LH>(z, xbuf, tw, tw_log, false);
     __syncthreads();
     float2* Z = (float2*)xbuf;               // H complex values = NX floats
 #pragma unroll
-    for (int e = 0; e < EZ; ++e) Z[reg_output_pos(e, logH)] = z[e];
+    for (int e = 0; e < EZ; ++e) Z[reg_output_pos<LH, EZ>(e)] = z[e];
     __syncthreads();
     float2* out = Xh + (b * n1 + lam) * Xh_pitch;
     const int tws = tw_log - logNX;
@@ -189,7 +223,7 @@ __global__ void __launch_bounds__(512) k_scalogram_r(const float2* __restrict__ 
 
 // one second-order row (T_alpha = 2^logTa >= 2^14): fold, inverse FFT, store, row max
 template <bool TWO>
-__global__ void __launch_bounds__(512) k_second_order_r(const float2* __restrict__ Xh, int64_t Xh_pitch, int n1,
+__global__ void __launch_bounds__(kRegT) k_second_order_r(const float2* __restrict__ Xh, int64_t Xh_pitch, int n1,
                                                         const float* __restrict__ ps, int lo, int hi, int logTa,
                                                         int Tp, int Kp, float2* __restrict__ Y, int64_t y_bstride,
                                                         float invNX, const float2* __restrict__ tw, int tw_log,
@@ -212,15 +246,23 @@ __global__ void __launch_bounds__(512) k_second_order_r(const float2* __restrict
     const float2* row = Xh + (b * n1 + (lam < n1 ? lam : 0)) * Xh_pitch;
     float m = 0.f;
     float2 v[kRegE];
+    // with two halves, the even outputs y[2 pos] stay in registers until the odd
+    // ones y[2 pos + 1] are known, and each pair goes out as one 16-byte store
+    float2 ev[TWO ? kRegE : 1];
 #pragma unroll
     for (int half = 0; half < (TWO ? 2 : 1); ++half) {
         load_dif<TWO>(v, A, Bf, row, ps, lo, hi, logTa, half, tw, tw_log, lam >= n1);
-        reg_fft<kRegE>(v, A, logS, tw, tw_log, true);
+        reg_fft<kRegE, kRegMinLog>(v, A, tw, tw_log, true);
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
             const float2 y = cscale(v[e], invNX);
-            const int pos = reg_output_pos(e, logS);
-            out[TWO ? 2 * pos + half : pos] = y;
+            const int pos = reg_output_pos<kRegMinLog, kRegE>(e);
+            if constexpr (TWO) {
+                if (half == 0) ev[e] = y;
+                else *(float4*)(out + 2 * pos) = make_float4(ev[e].x, ev[e].y, y.x, y.y);
+            } else {
+                out[pos] = y;
+            }
             m = fmaxf(m, fmaxf(fabsf(y.x), fabsf(y.y)));
         }
     }
@@ -234,7 +276,7 @@ __global__ void __launch_bounds__(512) k_second_order_r(const float2* __restrict
 
 // in-place forward FFT of rows of 2^logn points (row r of batch b at base + b*bs + r*rs)
 template <bool TWO>
-__global__ void __launch_bounds__(512) k_rowfft_r(float2* __restrict__ base, int64_t bs, int64_t rs, int logn,
+__global__ void __launch_bounds__(kRegT) k_rowfft_r(float2* __restrict__ base, int64_t bs, int64_t rs, int logn,
                                                   const float2* __restrict__ tw, int tw_log) {
     extern __shared__ float xbuf[];
     float2* row = base + (int64_t)blockIdx.y * bs + (int64_t)blockIdx.x * rs;
@@ -242,33 +284,37 @@ __global__ void __launch_bounds__(512) k_rowfft_r(float2* __restrict__ base, int
     float2 v[kRegE];
     if constexpr (!TWO) {
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e) v[e] = row[reg_input_pos(e, logn)];
-        reg_fft<kRegE>(v, xbuf, logn, tw, tw_log, false);
+        for (int e = 0; e < kRegE; ++e) v[e] = row[reg_input_pos<kRegMinLog, kRegE>(e)];
+        reg_fft<kRegE, kRegMinLog>(v, xbuf, tw, tw_log, false);
         __syncthreads();      // every thread has read its inputs before any output is stored
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e) row[reg_output_pos(e, logn)] = v[e];
+        for (int e = 0; e < kRegE; ++e) row[reg_output_pos<kRegMinLog, kRegE>(e)] = v[e];
     } else {
         const int m = 1 << logS;
         // E = DFT of the even samples, parked in the first half of the row once every
         // thread holds its odd samples; then O = DFT of the odd samples; combine
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e) v[e] = row[2 * reg_input_pos(e, logS)];
-        reg_fft<kRegE>(v, xbuf, logS, tw, tw_log, false);
+        for (int e = 0; e < kRegE; ++e) v[e] = row[2 * reg_input_pos<kRegMinLog, kRegE>(e)];
+        reg_fft<kRegE, kRegMinLog>(v, xbuf, tw, tw_log, false);
         float2 o[kRegE];
+        const float2* rowo = after(row, v[0]);
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e) o[e] = row[2 * reg_input_pos(e, logS) + 1];
+        for (int e = 0; e < kRegE; ++e) o[e] = rowo[2 * reg_input_pos<kRegMinLog, kRegE>(e) + 1];
         __syncthreads();
         __threadfence_block();
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e) row[reg_output_pos(e, logS)] = v[e];
-        reg_fft<kRegE>(o, xbuf, logS, tw, tw_log, false);
+        for (int e = 0; e < kRegE; ++e) row[reg_output_pos<kRegMinLog, kRegE>(e)] = v[e];
+        reg_fft<kRegE, kRegMinLog>(o, xbuf, tw, tw_log, false);
+        // the parked even half and the combining twiddles are read only now
+        float2* rowc = after(row, o[0]);
+        const float2* twc = after(tw, o[0]);
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
-            const int k = reg_output_pos(e, logS);
-            const float2 ev = row[k];                  // written by this thread above
-            const float2 wo = cmul(o[e], twiddle(tw, k << (tw_log - logn), false));
-            row[k] = cadd(ev, wo);
-            row[k + m] = csub(ev, wo);
+            const int k = reg_output_pos<kRegMinLog, kRegE>(e);
+            const float2 ev = rowc[k];                 // written by this thread above
+            const float2 wo = cmul(o[e], twiddle(twc, k << (tw_log - logn), false));
+            rowc[k] = cadd(ev, wo);
+            rowc[k + m] = csub(ev, wo);
         }
     }
 }
@@ -276,7 +322,7 @@ __global__ void __launch_bounds__(512) k_rowfft_r(float2* __restrict__ base, int
 // adjoint of the modulus and first-order filter for one row: recompute y, weight
 // gX by its phase, forward FFT -> g1[b][lambda][0..NX)
 template <bool TWO>
-__global__ void __launch_bounds__(512) k_scal_bwd_b_r(const float2* __restrict__ xh, int64_t xh_pitch,
+__global__ void __launch_bounds__(kRegT) k_scal_bwd_b_r(const float2* __restrict__ xh, int64_t xh_pitch,
                                                       const float* __restrict__ psi1, const int* __restrict__ band1,
                                                       const int64_t* __restrict__ off1, const float* __restrict__ gX,
                                                       float2* __restrict__ g1, int logNX, float invN,
@@ -293,48 +339,48 @@ __global__ void __launch_bounds__(512) k_scal_bwd_b_r(const float2* __restrict__
     const int lo = band1[2 * lam], hi = band1[2 * lam + 1];
     const float* gx = gX + (b * n1 + lam) * (int64_t)NX;
     float2* o = g1 + (b * n1 + lam) * (int64_t)NX;
-    const int lr = reg_pass_lr(logS, reg_num_passes(logS) - 1);
-    const int lNs = logS - lr;
     float2 v[kRegE];
 #pragma unroll
     for (int half = 0; half < (TWO ? 2 : 1); ++half) {
         if (TWO) {
             load_dif<true>(v, A, Bf, src, ps, lo, hi, logNX, half, tw, tw_log, false);
         } else {
-            fold_inputs(v, src, ps, lo, hi, logNX);
+            fold_inputs<kRegMinLog>(v, src, ps, lo, hi);
         }
-        reg_fft<kRegE>(v, A, logS, tw, tw_log, true);
+        reg_fft<kRegE, kRegMinLog>(v, A, tw, tw_log, true);
+        const float* gxh = after(gx, v[0]);
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
             const float2 y = cscale(v[e], invN);
-            const int pos = reg_output_pos(e, logS);
-            const float sc = gx[TWO ? 2 * pos + half : pos] *
+            const int pos = reg_output_pos<kRegMinLog, kRegE>(e);
+            const float sc = gxh[TWO ? 2 * pos + half : pos] *
                              __builtin_amdgcn_rcpf(fmaxf(__builtin_amdgcn_sqrtf(y.x * y.x + y.y * y.y), kEpsMod));
             v[e] = cscale(y, sc);
         }
         // from the last pass's output layout to the first pass's input layout
-        if (lr == 3) reg_exchange<3, 3, kRegE>(v, A, logS, lNs);
-        else if (lr == 2) reg_exchange<2, 3, kRegE>(v, A, logS, lNs);
-        else reg_exchange<1, 3, kRegE>(v, A, logS, lNs);
-        reg_fft<kRegE>(v, A, logS, tw, tw_log, false);
+        reg_output_to_input<kRegMinLog, kRegE>(v, A);
+        reg_fft<kRegE, kRegMinLog>(v, A, tw, tw_log, false);
         if (TWO && half == 0) {
             // spectrum of the even samples, parked in the output row
 #pragma unroll
-            for (int e = 0; e < kRegE; ++e) o[reg_output_pos(e, logS)] = v[e];
+            for (int e = 0; e < kRegE; ++e) o[reg_output_pos<kRegMinLog, kRegE>(e)] = v[e];
         }
     }
     if constexpr (!TWO) {
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e) o[reg_output_pos(e, logNX)] = v[e];
+        for (int e = 0; e < kRegE; ++e) o[reg_output_pos<kRegMinLog, kRegE>(e)] = v[e];
     } else {
         const int m = 1 << logS;
+        // the parked even half and the combining twiddles are read only now
+        float2* oc = after(o, v[0]);
+        const float2* twc = after(tw, v[0]);
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
-            const int k = reg_output_pos(e, logS);
-            const float2 ev = o[k];                    // written by this thread above
-            const float2 wo = cmul(v[e], twiddle(tw, k << (tw_log - logNX), false));
-            o[k] = cadd(ev, wo);
-            o[k + m] = csub(ev, wo);
+            const int k = reg_output_pos<kRegMinLog, kRegE>(e);
+            const float2 ev = oc[k];                   // written by this thread above
+            const float2 wo = cmul(v[e], twiddle(twc, k << (tw_log - logNX), false));
+            oc[k] = cadd(ev, wo);
+            oc[k + m] = csub(ev, wo);
         }
     }
 }

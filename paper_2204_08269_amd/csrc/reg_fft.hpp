@@ -1,11 +1,16 @@
 // Block-wide power-of-two FFT with the data resident in registers.
 //
-// Each of the T = blockDim.x threads holds E = n / T complex values.  Passes are
-// Stockham radix-8 (then one radix-4 or radix-2 pass); between passes the values
-// move to the thread that needs them through LDS, the real parts first and the
-// imaginary parts second, so the exchange buffer holds only n floats plus one pad
-// float per eight (a little over half of an in-LDS complex transform).  Unnormalised in both directions; twiddles from the
-// FP64-generated table tw[k] = exp(-2 pi i k / 2^tw_log).
+// Each of the T = 2^LOGN / E threads holds E complex values.  Passes are Stockham
+// radix-8 (then one radix-4 or radix-2 pass); between passes the values move to
+// the thread that needs them through LDS, the real parts first and the imaginary
+// parts second, so the exchange buffer holds only n floats plus one pad float per
+// eight (a little over half of an in-LDS complex transform).  Unnormalised in
+// both directions; twiddles from the FP64-generated table
+// tw[k] = exp(-2 pi i k / 2^tw_log).
+//
+// The length and the thread count are compile-time constants: every position a
+// thread reads or writes is then its thread index plus a constant, so the LDS
+// exchanges take immediate offsets instead of one address register per element.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,39 +19,49 @@
 
 namespace jtfs {
 
-// radix (log2) of pass `i` for a transform of 2^logn points
-__device__ __forceinline__ int reg_pass_lr(int logn, int i) {
-    const int full = logn / 3;
-    return i < full ? 3 : logn - 3 * full;
-}
-__device__ __forceinline__ int reg_num_passes(int logn) { return logn / 3 + (logn % 3 ? 1 : 0); }
+// radix (log2) of pass i of a transform of 2^logn points, and the pass count
+constexpr int reg_pass_lr(int logn, int i) { return i < logn / 3 ? 3 : logn - 3 * (logn / 3); }
+constexpr int reg_num_passes(int logn) { return logn / 3 + (logn % 3 ? 1 : 0); }
+// log2 of the sub-transform length after the passes before pass i
+constexpr int reg_lns_before(int logn, int i) { return i == 0 ? 0 : reg_lns_before(logn, i - 1) + reg_pass_lr(logn, i - 1); }
 
 // position read by element e of the thread in a pass of radix 2^LR
-template <int LR>
-__device__ __forceinline__ int reg_in_pos(int e, int logn) {
-    constexpr int R = 1 << LR;
+template <int LR, int LOGN, int E>
+__device__ __forceinline__ int reg_in_pos(int e) {
+    constexpr int R = 1 << LR, T = (1 << LOGN) / E;
     const int q = e >> LR, r = e & (R - 1);
-    return (int)threadIdx.x + q * (int)blockDim.x + (r << (logn - LR));
+    return (int)threadIdx.x + q * T + (r << (LOGN - LR));
 }
-// position written by element e in a pass of radix 2^LR with sub-transform length 2^lNs
-template <int LR>
-__device__ __forceinline__ int reg_out_pos(int e, int lNs) {
-    constexpr int R = 1 << LR;
+// position written by element e in a pass of radix 2^LR with sub-transform length 2^LNS
+template <int LR, int LNS, int LOGN, int E>
+__device__ __forceinline__ int reg_out_pos(int e) {
+    constexpr int R = 1 << LR, T = (1 << LOGN) / E;
     const int q = e >> LR, r = e & (R - 1);
-    const int j = (int)threadIdx.x + q * (int)blockDim.x;
-    return ((j >> lNs) << (lNs + LR)) + (j & ((1 << lNs) - 1)) + (r << lNs);
+    const int j = (int)threadIdx.x + q * T;
+    return ((j >> LNS) << (LNS + LR)) + (j & ((1 << LNS) - 1)) + (r << LNS);
+}
+
+// A pointer the compiler cannot see through, taken once v0 is known: loads from
+// it are not issued before the code that produced v0.  Twiddle addresses depend
+// only on the thread index; without this the loads of every pass are hoisted to
+// the start of the transform (an LDS-only barrier does not hold back global
+// loads) and their values occupy registers through all the passes before.
+template <typename T>
+__device__ __forceinline__ T* after(T* p, float2& v0) {
+    asm volatile("" : "+s"(p), "+v"(v0.x));
+    return p;
 }
 
 // Butterflies of one pass on the thread's E values (E / R butterflies).
-template <int LR, int E>
-__device__ __forceinline__ void reg_butterflies(float2 (&v)[E], int lNs, const float2* __restrict__ tw, int tw_log,
-                                                bool inv) {
-    constexpr int R = 1 << LR;
-    const int tws = tw_log - lNs - LR;
+template <int LR, int LNS, int LOGN, int E>
+__device__ __forceinline__ void reg_butterflies(float2 (&v)[E], const float2* __restrict__ tw0, int tw_log, bool inv) {
+    constexpr int R = 1 << LR, T = (1 << LOGN) / E;
+    const int tws = tw_log - LNS - LR;
+    const float2* tw = after(tw0, v[0]);
 #pragma unroll
     for (int q = 0; q < E / R; ++q) {
-        const int j = (int)threadIdx.x + q * (int)blockDim.x;
-        const int k = j & ((1 << lNs) - 1);
+        const int j = (int)threadIdx.x + q * T;
+        const int k = j & ((1 << LNS) - 1);
         float2* a = v + q * R;
         float2 w[R];
         butterfly_twiddles<R>(w, tw, k << tws, inv);
@@ -92,64 +107,68 @@ __device__ __forceinline__ int xpad(int i) { return i + (i >> 3); }
 // floats of exchange buffer that reg_fft needs for 2^logn points
 constexpr int reg_xbuf_floats(int logn) { return (1 << logn) + (1 << (logn - 3)); }
 
-// Move the outputs of a radix-2^LR pass (sub-length 2^lNs) to the inputs of the
-// next pass (radix 2^LR2) through `x` (reg_xbuf_floats(logn) floats): real
+// Move the outputs of a radix-2^LR pass (sub-length 2^LNS) to the inputs of the
+// next pass (radix 2^LR2) through `x` (reg_xbuf_floats(LOGN) floats): real
 // parts, then imaginary.
-template <int LR, int LR2, int E>
-__device__ __forceinline__ void reg_exchange(float2 (&v)[E], float* x, int logn, int lNs) {
+template <int LR, int LR2, int LNS, int LOGN, int E>
+__device__ __forceinline__ void reg_exchange(float2 (&v)[E], float* x) {
     lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) x[xpad(reg_out_pos<LR>(e, lNs))] = v[e].x;
+    for (int e = 0; e < E; ++e) x[xpad(reg_out_pos<LR, LNS, LOGN, E>(e))] = v[e].x;
     lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e].x = x[xpad(reg_in_pos<LR2>(e, logn))];
+    for (int e = 0; e < E; ++e) v[e].x = x[xpad(reg_in_pos<LR2, LOGN, E>(e))];
     lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) x[xpad(reg_out_pos<LR>(e, lNs))] = v[e].y;
+    for (int e = 0; e < E; ++e) x[xpad(reg_out_pos<LR, LNS, LOGN, E>(e))] = v[e].y;
     lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e].y = x[xpad(reg_in_pos<LR2>(e, logn))];
+    for (int e = 0; e < E; ++e) v[e].y = x[xpad(reg_in_pos<LR2, LOGN, E>(e))];
 }
 
-// Full transform (x: reg_xbuf_floats(logn) floats of LDS).  On entry element e of the thread holds the input at
-// reg_in_pos<first radix>(e) (use reg_input_pos below); on exit it holds the
-// output at reg_output_pos(e, logn).  Needs 2^logn = E * blockDim.x and logn >= 6.
-template <int E>
-__device__ __forceinline__ void reg_fft(float2 (&v)[E], float* x, int logn, const float2* __restrict__ tw,
-                                        int tw_log, bool inv) {
-    const int np = reg_num_passes(logn);
-    int lNs = 0;
-    for (int i = 0; i < np; ++i) {
-        const int lr = reg_pass_lr(logn, i);
-        const bool last = i + 1 == np;
-        const int lr2 = last ? 0 : reg_pass_lr(logn, i + 1);
-        if (lr == 3) {
-            reg_butterflies<3, E>(v, lNs, tw, tw_log, inv);
-            if (!last) {
-                if (lr2 == 3) reg_exchange<3, 3, E>(v, x, logn, lNs);
-                else if (lr2 == 2) reg_exchange<3, 2, E>(v, x, logn, lNs);
-                else reg_exchange<3, 1, E>(v, x, logn, lNs);
-            }
-        } else if (lr == 2) {
-            reg_butterflies<2, E>(v, lNs, tw, tw_log, inv);
-        } else {
-            reg_butterflies<1, E>(v, lNs, tw, tw_log, inv);
+template <int E, int LOGN, int I>
+__device__ __forceinline__ void reg_fft_from(float2 (&v)[E], float* x, const float2* __restrict__ tw, int tw_log,
+                                             bool inv) {
+    constexpr int NP = reg_num_passes(LOGN);
+    if constexpr (I < NP) {
+        constexpr int LR = reg_pass_lr(LOGN, I), LNS = reg_lns_before(LOGN, I);
+        reg_butterflies<LR, LNS, LOGN, E>(v, tw, tw_log, inv);
+        if constexpr (I + 1 < NP) {
+            reg_exchange<LR, reg_pass_lr(LOGN, I + 1), LNS, LOGN, E>(v, x);
+            reg_fft_from<E, LOGN, I + 1>(v, x, tw, tw_log, inv);
         }
-        lNs += lr;
     }
 }
 
-// input position of element e (the first pass is radix 8 for logn >= 3)
-__device__ __forceinline__ int reg_input_pos(int e, int logn) { return reg_in_pos<3>(e, logn); }
+// Full transform of 2^LOGN points by (2^LOGN / E)-thread blocks (x:
+// reg_xbuf_floats(LOGN) floats of LDS).  On entry element e of the thread holds
+// the input at reg_input_pos<LOGN, E>(e); on exit it holds the output at
+// reg_output_pos<LOGN, E>(e).  Needs LOGN >= 6.
+template <int E, int LOGN>
+__device__ __forceinline__ void reg_fft(float2 (&v)[E], float* x, const float2* __restrict__ tw, int tw_log,
+                                        bool inv) {
+    static_assert(LOGN >= 6 && (1 << LOGN) % E == 0, "transform shape");
+    reg_fft_from<E, LOGN, 0>(v, x, tw, tw_log, inv);
+}
+
+// input position of element e (the first pass is radix 8)
+template <int LOGN, int E>
+__device__ __forceinline__ int reg_input_pos(int e) { return reg_in_pos<3, LOGN, E>(e); }
 
 // output position of element e after reg_fft
-__device__ __forceinline__ int reg_output_pos(int e, int logn) {
-    const int np = reg_num_passes(logn);
-    const int lr = reg_pass_lr(logn, np - 1);
-    const int lNs = logn - lr;
-    if (lr == 3) return reg_out_pos<3>(e, lNs);
-    if (lr == 2) return reg_out_pos<2>(e, lNs);
-    return reg_out_pos<1>(e, lNs);
+template <int LOGN, int E>
+__device__ __forceinline__ int reg_output_pos(int e) {
+    constexpr int NP = reg_num_passes(LOGN);
+    constexpr int LR = reg_pass_lr(LOGN, NP - 1);
+    return reg_out_pos<LR, LOGN - LR, LOGN, E>(e);
+}
+
+// Exchange from the last pass's output layout to the first pass's input layout
+template <int LOGN, int E>
+__device__ __forceinline__ void reg_output_to_input(float2 (&v)[E], float* x) {
+    constexpr int NP = reg_num_passes(LOGN);
+    constexpr int LR = reg_pass_lr(LOGN, NP - 1);
+    reg_exchange<LR, 3, LOGN - LR, LOGN, E>(v, x);
 }
 
 }  // namespace jtfs
