@@ -290,11 +290,18 @@ void jtfs_texture_destroy(jtfs_texture* tex);
 /* Launch choices and their autotuning.  reg_rows is a bit mask over the four
  * stages that have both a register-resident and an in-LDS transform for rows of
  * 2^14 points (longer rows always use the register-resident one, shorter rows the
- * in-LDS one).  jtfs_plan_autotune runs, for B signals x (device, [B][N]; NULL:
+ * in-LDS one), plus JTFS_TUNE_FWD_TILE16 (the tile of the split forward
+ * contraction).  jtfs_plan_autotune runs, for B signals x (device, [B][N]; NULL:
  * zeros), one untimed and `reps` timed fwd+bwd steps per candidate: each
- * available contraction mode, with all four stages register-resident and with
- * all four in LDS.  It keeps the contraction whose own stages took least time
- * and, per stage, the faster transform, then times the result (step_ms).  It
+ * available contraction mode, once with all four stages register-resident and
+ * 32 x 32 forward tiles and once with all four in LDS and 16 x 16 forward tiles
+ * (where these choices exist).  It keeps the contraction whose own stages took
+ * least time (its forward with the faster tile), per stage the faster transform,
+ * and the faster forward tile, then times the result (step_ms).  With the
+ * environment variable JTFS_TUNE_CACHE naming a file, a result is appended to it
+ * under a key of the device's architecture and name, the plan parameters and B,
+ * and a later call with the same key applies the stored choice without timing
+ * (from_cache = 1; candidates and fwd_ms then 0).  It
  * allocates its buffers itself (the largest workspace over the modes plus
  * coefficients and gradient for B signals), synchronises the stream, uses the
  * per-stage timers (JTFS_EINVAL if timing is enabled) and leaves their records
@@ -303,17 +310,24 @@ void jtfs_texture_destroy(jtfs_texture* tex);
  * where it is chosen, a backward that does not reuse its forward runs as
  * SPLIT_F16; a caller that wants the recomputing backward's gradient precision
  * sets the mode with jtfs_plan_set_tuning instead).  candidates_ms: fwd+bwd per step of
- * (split, register), (split, LDS), (FP32, register), (FP32, LDS), (split with
- * stored phase, register), (split with stored phase, LDS); 0 for candidates not run. */
+ * (split, first run), (split, second run), (FP32, first), (FP32, second), (split with
+ * stored phase, first), (split with stored phase, second); 0 for candidates not run.
+ * fwd_ms: the chosen mode's forward contraction per step with 32 x 32 and 16 x 16
+ * tiles (0 where not run). */
 #define JTFS_REG_SCALOGRAM    1
 #define JTFS_REG_SECOND_ORDER 2
 #define JTFS_REG_ROW_FFT      4
 #define JTFS_REG_FIRST_ADJ    8
+/* In the same mask: the split forward contraction in 16 x 16 MFMA tiles (each
+ * wave 64 rows l x 16 columns t; available where N/T <= 32), else 32 x 32 tiles. */
+#define JTFS_TUNE_FWD_TILE16  16
 typedef struct {
     int32_t contraction;
-    int32_t reg_rows;
+    int32_t reg_rows;                 /* including JTFS_TUNE_FWD_TILE16 */
     double step_ms;
     double candidates_ms[6];
+    double fwd_ms[2];
+    int32_t from_cache;
 } jtfs_tuning;
 int jtfs_plan_autotune(jtfs_plan* plan, const float* x, int64_t B, int reps, hipStream_t stream, jtfs_tuning* out);
 int jtfs_plan_set_tuning(jtfs_plan* plan, int contraction, int reg_rows);

@@ -1,20 +1,26 @@
 // Autotuning of a plan's launch choices on the caller's GPU and batch size.
 //
 // Candidates: the contraction arithmetic (split FP16, split FP16 with the phase
-// stored by the forward, or FP32 matrix cores) and,
-// for rows of 2^14 points, the register-resident or the in-LDS transform in each
-// of the four stages that have both (scalogram, second order, gY2 row FFTs,
-// first-order adjoint).  Every candidate runs whole fwd+bwd steps; the per-stage
-// HIP-event timers attribute the time, so the four row choices are settled from
-// two runs per contraction mode (all register-resident, all in LDS) rather than
-// from sixteen.
+// stored by the forward, or FP32 matrix cores); the tile of the split forward
+// contraction (32 x 32 or 16 x 16 MFMA tiles); and, for rows of 2^14 points, the
+// register-resident or the in-LDS transform in each of the four stages that have
+// both (scalogram, second order, gY2 row FFTs, first-order adjoint).  Every
+// candidate runs whole fwd+bwd steps; the per-stage HIP-event timers attribute
+// the time, so the five binary choices are settled from two runs per contraction
+// mode (all register-resident with 32 x 32 tiles, all in LDS with 16 x 16 tiles)
+// rather than from thirty-two.  Results can be kept in a text file keyed by the
+// device and the plan's shape (JTFS_TUNE_CACHE).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "plan.hpp"
+#include "split.hpp"
 
 namespace jtfs {
 bool timing_on();
@@ -34,11 +40,62 @@ void set_rows(jtfs_plan* P, int mask) {
     P->tune.reg_second = (mask & JTFS_REG_SECOND_ORDER) != 0;
     P->tune.reg_rowfft = (mask & JTFS_REG_ROW_FFT) != 0;
     P->tune.reg_first_adj = (mask & JTFS_REG_FIRST_ADJ) != 0;
+    P->tune.fwd16 = (mask & JTFS_TUNE_FWD_TILE16) != 0;
 }
 
 int get_rows(const jtfs_plan* P) {
     return (P->tune.reg_scalogram ? JTFS_REG_SCALOGRAM : 0) | (P->tune.reg_second ? JTFS_REG_SECOND_ORDER : 0) |
-           (P->tune.reg_rowfft ? JTFS_REG_ROW_FFT : 0) | (P->tune.reg_first_adj ? JTFS_REG_FIRST_ADJ : 0);
+           (P->tune.reg_rowfft ? JTFS_REG_ROW_FFT : 0) | (P->tune.reg_first_adj ? JTFS_REG_FIRST_ADJ : 0) |
+           (P->tune.fwd16 ? JTFS_TUNE_FWD_TILE16 : 0);
+}
+
+// Cache key: the device's architecture and name, the plan parameters and B.
+std::string cache_key(const jtfs_plan* P, int64_t B) {
+    hipDeviceProp_t prop;
+    std::string dev = "unknown";
+    if (hipGetDeviceProperties(&prop, P->device) == hipSuccess) dev = std::string(prop.gcnArchName) + "/" + prop.name;
+    for (char& c : dev)
+        if (c == ' ' || c == '\t') c = '_';
+    const jtfs_params& p = P->s.p;
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "N=%lld,J=%d,Q=%d/%d,Jfr=%d,Qfr=%d,T=%lld,F=%lld,flags=%u,B=%lld", (long long)p.N,
+                  p.J, p.Q1, p.Q2, p.J_fr, p.Q_fr, (long long)p.T, (long long)p.F, p.flags, (long long)B);
+    return dev + "|" + buf;
+}
+
+const char* cache_path() {
+    const char* f = std::getenv("JTFS_TUNE_CACHE");
+    return f && *f ? f : nullptr;
+}
+
+// the last entry for key in the cache file: contraction, choice mask, step ms
+bool cache_lookup(const std::string& key, int* mode, int* mask, double* ms) {
+    const char* path = cache_path();
+    if (!path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[400];
+        int m = 0, r = 0;
+        double t = 0.0;
+        if (std::sscanf(line, "%399s %d %d %lf", k, &m, &r, &t) == 4 && key == k) {
+            *mode = m; *mask = r; *ms = t;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const std::string& key, int mode, int mask, double ms) {
+    const char* path = cache_path();
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %.4f\n", key.c_str(), mode, mask, ms);
+    std::fclose(f);
 }
 
 // reps timed fwd+bwd steps after one untimed one: total ms per step and ms per stage per step
@@ -85,7 +142,8 @@ int run_steps(jtfs_plan* P, const float* x, int64_t B, float* s1, float* s2, flo
 
 extern "C" int jtfs_plan_set_tuning(jtfs_plan* P, int contraction, int reg_rows) {
     if (!P) { set_error("null plan"); return JTFS_EINVAL; }
-    if (reg_rows & ~(JTFS_REG_SCALOGRAM | JTFS_REG_SECOND_ORDER | JTFS_REG_ROW_FFT | JTFS_REG_FIRST_ADJ)) {
+    if (reg_rows & ~(JTFS_REG_SCALOGRAM | JTFS_REG_SECOND_ORDER | JTFS_REG_ROW_FFT | JTFS_REG_FIRST_ADJ |
+                     JTFS_TUNE_FWD_TILE16)) {
         set_error("unknown row-kernel bits"); return JTFS_EINVAL; }
     const int rc = jtfs_plan_set_contraction(P, contraction);
     if (rc != JTFS_OK) return rc;
@@ -108,6 +166,20 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
     std::memset(out, 0, sizeof(*out));
     const Shapes& s = P->s;
     const int saved_mode = P->contraction, saved_rows = get_rows(P);
+    const std::string key = cache_key(P, B);
+    {
+        int cm = 0, cr = 0;
+        double cms = 0.0;
+        if (cache_lookup(key, &cm, &cr, &cms) && jtfs_plan_set_tuning(P, cm, cr) == JTFS_OK) {
+            out->contraction = cm;
+            out->reg_rows = cr;
+            out->step_ms = cms;
+            out->from_cache = 1;
+            return JTFS_OK;
+        }
+        P->contraction = saved_mode;
+        set_rows(P, saved_rows);
+    }
     // candidates
     std::vector<int> modes;
     if (P->split_ok) modes.push_back(JTFS_CONTRACTION_SPLIT_F16);
@@ -128,7 +200,10 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
     bool has14 = s.logNX == kRegMinLogRows;
     for (int a = 0; a < s.n_alpha; ++a) has14 = has14 || (s.logNX - s.k2[a] == kRegMinLogRows);
     const int all_rows = JTFS_REG_SCALOGRAM | JTFS_REG_SECOND_ORDER | JTFS_REG_ROW_FFT | JTFS_REG_FIRST_ADJ;
-    std::vector<int> row_opts = has14 ? std::vector<int>{all_rows, 0} : std::vector<int>{all_rows};
+    // second run: rows in LDS and the 16 x 16 forward tile, where either choice exists
+    const bool tile16 = P->split_ok && !s.tscat && fwdq_supported(P, false);
+    std::vector<int> row_opts{all_rows};
+    if (has14 || tile16) row_opts.push_back((has14 ? 0 : all_rows) | (tile16 ? JTFS_TUNE_FWD_TILE16 : 0));
     // buffers: the largest workspace over the modes; the coefficients double as cotangents
     size_t wsb = 0;
     for (int m : modes) {
@@ -169,23 +244,32 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
             const int slot = (modes[mi] == JTFS_CONTRACTION_FP32             ? 2
                               : modes[mi] == JTFS_CONTRACTION_SPLIT_F16_PHASE ? 4
                                                                               : 0) +
-                             (row_opts[ri] ? 0 : 1);
+                             (int)ri;
             out->candidates_ms[slot] = total[mi][ri];
         }
     }
-    // contraction: the stages it owns, with register-resident rows
-    const int cstages[] = {JTFS_STAGE_OPERAND_SPLIT, JTFS_STAGE_FREQ_FWD, JTFS_STAGE_FREQ_LOWPASS,
-                           JTFS_STAGE_LOWPASS_ADJ, JTFS_STAGE_FREQ_ADJ_PQ, JTFS_STAGE_FREQ_ADJ_WH};
+    // contraction: the stages it owns (the forward with the faster of its tiles)
+    const int cstages[] = {JTFS_STAGE_OPERAND_SPLIT, JTFS_STAGE_FREQ_LOWPASS, JTFS_STAGE_LOWPASS_ADJ,
+                           JTFS_STAGE_FREQ_ADJ_PQ, JTFS_STAGE_FREQ_ADJ_WH};
+    auto fwd_ms = [&](size_t mi, size_t ri) { return stage[mi][ri][JTFS_STAGE_FREQ_FWD]; };
+    auto tile_ok = [&](size_t mi) {
+        return tile16 && modes[mi] != JTFS_CONTRACTION_FP32 &&
+               fwdq_supported(P, modes[mi] == JTFS_CONTRACTION_SPLIT_F16_PHASE);
+    };
     size_t best_m = 0;
     double best_c = 1e300;
     for (size_t mi = 0; mi < modes.size(); ++mi) {
-        double c = 0.0;
+        double c = fwd_ms(mi, 0);
+        if (tile_ok(mi) && row_opts.size() == 2) c = std::min(c, fwd_ms(mi, 1));
         for (int k : cstages) c += stage[mi][0][k];
         if (c < best_c) { best_c = c; best_m = mi; }
     }
+    const bool use16 = tile_ok(best_m) && row_opts.size() == 2 && fwd_ms(best_m, 1) < fwd_ms(best_m, 0);
+    out->fwd_ms[0] = fwd_ms(best_m, 0);
+    out->fwd_ms[1] = tile_ok(best_m) && row_opts.size() == 2 ? fwd_ms(best_m, 1) : 0.0;
     // rows of 2^14 points: per stage, the faster of the two runs of the chosen mode
     int rows = all_rows;
-    if (row_opts.size() == 2) {
+    if (has14) {
         const int kstage[4] = {JTFS_STAGE_SCALOGRAM, JTFS_STAGE_SECOND_ORDER, JTFS_STAGE_SECOND_ADJ_FFT,
                                JTFS_STAGE_FIRST_ADJ};
         const int kbit[4] = {JTFS_REG_SCALOGRAM, JTFS_REG_SECOND_ORDER, JTFS_REG_ROW_FFT, JTFS_REG_FIRST_ADJ};
@@ -193,6 +277,7 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
         for (int q = 0; q < 4; ++q)
             if (stage[best_m][0][kstage[q]] <= stage[best_m][1][kstage[q]]) rows |= kbit[q];
     }
+    if (use16) rows |= JTFS_TUNE_FWD_TILE16;
     P->contraction = modes[best_m];
     set_rows(P, rows);
     double stage_final[JTFS_NUM_STAGES];
@@ -205,5 +290,6 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
     }
     out->contraction = P->contraction;
     out->reg_rows = rows;
+    cache_store(key, out->contraction, rows, out->step_ms);
     return JTFS_OK;
 }

@@ -25,19 +25,31 @@ constexpr int reg_num_passes(int logn) { return logn / 3 + (logn % 3 ? 1 : 0); }
 // log2 of the sub-transform length after the passes before pass i
 constexpr int reg_lns_before(int logn, int i) { return i == 0 ? 0 : reg_lns_before(logn, i - 1) + reg_pass_lr(logn, i - 1); }
 
-// position read by element e of the thread in a pass of radix 2^LR
-template <int LR, int LOGN, int E>
-__device__ __forceinline__ int reg_in_pos(int e) {
-    constexpr int R = 1 << LR, T = (1 << LOGN) / E;
-    const int q = e >> LR, r = e & (R - 1);
-    return (int)threadIdx.x + q * T + (r << (LOGN - LR));
+// The thread index as a value the compiler cannot relate to any other copy of it.
+// Positions are the thread index plus constants, the same in every pass; with
+// one shared index the compiler keeps those sums for all passes at once (and
+// spills them) instead of forming each where it is used.  Each pass takes its
+// own copy.
+__device__ __forceinline__ int opaque_tid() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
 }
-// position written by element e in a pass of radix 2^LR with sub-transform length 2^LNS
-template <int LR, int LNS, int LOGN, int E>
-__device__ __forceinline__ int reg_out_pos(int e) {
+
+// position read by element e of thread tid in a pass of radix 2^LR
+template <int LR, int LOGN, int E>
+__device__ __forceinline__ int reg_in_pos(int e, int tid) {
     constexpr int R = 1 << LR, T = (1 << LOGN) / E;
     const int q = e >> LR, r = e & (R - 1);
-    const int j = (int)threadIdx.x + q * T;
+    return tid + q * T + (r << (LOGN - LR));
+}
+// position written by element e of thread tid in a pass of radix 2^LR with
+// sub-transform length 2^LNS
+template <int LR, int LNS, int LOGN, int E>
+__device__ __forceinline__ int reg_out_pos(int e, int tid) {
+    constexpr int R = 1 << LR, T = (1 << LOGN) / E;
+    const int q = e >> LR, r = e & (R - 1);
+    const int j = tid + q * T;
     return ((j >> LNS) << (LNS + LR)) + (j & ((1 << LNS) - 1)) + (r << LNS);
 }
 
@@ -58,9 +70,10 @@ __device__ __forceinline__ void reg_butterflies(float2 (&v)[E], const float2* __
     constexpr int R = 1 << LR, T = (1 << LOGN) / E;
     const int tws = tw_log - LNS - LR;
     const float2* tw = after(tw0, v[0]);
+    const int tid = opaque_tid();
 #pragma unroll
     for (int q = 0; q < E / R; ++q) {
-        const int j = (int)threadIdx.x + q * T;
+        const int j = tid + q * T;
         const int k = j & ((1 << LNS) - 1);
         float2* a = v + q * R;
         float2 w[R];
@@ -112,18 +125,19 @@ constexpr int reg_xbuf_floats(int logn) { return (1 << logn) + (1 << (logn - 3))
 // parts, then imaginary.
 template <int LR, int LR2, int LNS, int LOGN, int E>
 __device__ __forceinline__ void reg_exchange(float2 (&v)[E], float* x) {
+    const int tid = opaque_tid();
     lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) x[xpad(reg_out_pos<LR, LNS, LOGN, E>(e))] = v[e].x;
+    for (int e = 0; e < E; ++e) x[xpad(reg_out_pos<LR, LNS, LOGN, E>(e, tid))] = v[e].x;
     lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e].x = x[xpad(reg_in_pos<LR2, LOGN, E>(e))];
+    for (int e = 0; e < E; ++e) v[e].x = x[xpad(reg_in_pos<LR2, LOGN, E>(e, tid))];
     lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) x[xpad(reg_out_pos<LR, LNS, LOGN, E>(e))] = v[e].y;
+    for (int e = 0; e < E; ++e) x[xpad(reg_out_pos<LR, LNS, LOGN, E>(e, tid))] = v[e].y;
     lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e].y = x[xpad(reg_in_pos<LR2, LOGN, E>(e))];
+    for (int e = 0; e < E; ++e) v[e].y = x[xpad(reg_in_pos<LR2, LOGN, E>(e, tid))];
 }
 
 template <int E, int LOGN, int I>
@@ -153,14 +167,14 @@ __device__ __forceinline__ void reg_fft(float2 (&v)[E], float* x, const float2* 
 
 // input position of element e (the first pass is radix 8)
 template <int LOGN, int E>
-__device__ __forceinline__ int reg_input_pos(int e) { return reg_in_pos<3, LOGN, E>(e); }
+__device__ __forceinline__ int reg_input_pos(int e) { return reg_in_pos<3, LOGN, E>(e, (int)threadIdx.x); }
 
 // output position of element e after reg_fft
 template <int LOGN, int E>
 __device__ __forceinline__ int reg_output_pos(int e) {
     constexpr int NP = reg_num_passes(LOGN);
     constexpr int LR = reg_pass_lr(LOGN, NP - 1);
-    return reg_out_pos<LR, LOGN - LR, LOGN, E>(e);
+    return reg_out_pos<LR, LOGN - LR, LOGN, E>(e, (int)threadIdx.x);
 }
 
 // Exchange from the last pass's output layout to the first pass's input layout

@@ -349,10 +349,10 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
             const half8 w0 = as_h8(wc[0]), w1 = as_h8(wc[1]), w2 = as_h8(wc[2]), w3 = as_h8(wc[3]);
             uint4(&q)[4] = yr[kq % NR];
             const half8 y0 = as_h8(q[0]), y1 = as_h8(q[1]), y2 = as_h8(q[2]), y3 = as_h8(q[3]);
-            rr = mfma16(y0, w0, rr); rr = mfma16(y0, w1, rr); rr = mfma16(y1, w0, rr);
-            ir = mfma16(y2, w0, ir); ir = mfma16(y2, w1, ir); ir = mfma16(y3, w0, ir);
-            ri = mfma16(y0, w2, ri); ri = mfma16(y0, w3, ri); ri = mfma16(y1, w2, ri);
-            ii = mfma16(y2, w2, ii); ii = mfma16(y2, w3, ii); ii = mfma16(y3, w2, ii);
+            // the four accumulators in turn (each keeps its own summation order)
+            rr = mfma16(y0, w0, rr); ir = mfma16(y2, w0, ir); ri = mfma16(y0, w2, ri); ii = mfma16(y2, w2, ii);
+            rr = mfma16(y0, w1, rr); ir = mfma16(y2, w1, ir); ri = mfma16(y0, w3, ri); ii = mfma16(y2, w3, ii);
+            rr = mfma16(y1, w0, rr); ir = mfma16(y3, w0, ir); ri = mfma16(y1, w2, ri); ii = mfma16(y3, w2, ii);
             if (kq + NR < NK) load_y(q, yc, kq + NR);
             if (kq + 1 < NK) {
 #pragma unroll
@@ -487,6 +487,271 @@ __global__ void __launch_bounds__(512) k_freq_fwd_h(const unsigned short* __rest
     }
 }
 
+
+// ---------------------------------------- forward contraction, 16 x 16 tiles
+
+// D (16 x 16, FP32) += A (16 x 32) B (32 x 16) in FP16: lane j + 16 g holds
+// A[j][8g .. 8g+7], B[8g .. 8g+7][j] and D[4g .. 4g+3][j].
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ floatx4 mfma16q(half8 a, half8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+// the same with K = 16: lane j + 16 g holds A[j][4g .. 4g+3] and B[4g .. 4g+3][j]
+__device__ __forceinline__ floatx4 mfma16k(half4 a, half4 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx4 z4() { return floatx4{0.f, 0.f, 0.f, 0.f}; }
+
+// Phq[t / 16][tau / 16][lane][p][r]: split(Phi[t][tau] * sphi) (p = hi, lo) for
+// tau = 16 (tau / 16) + lane % 16, t = 16 (t / 16) + 4 (lane / 16) + r: the A operand
+// of the 16 x 16 x 16 lowpass product, one 16-byte load per lane.
+__global__ void k_phqsplit(const float* __restrict__ Phi, int Tp, int NTp, float sphi,
+                           unsigned short* __restrict__ Phq) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)Tp * NTp) return;
+    const int r = (int)(e & 3);
+    int64_t q = e >> 2;
+    const int lane = (int)(q & 63); q >>= 6;
+    const int n = (int)(q % (NTp / 16));
+    const int t16 = (int)(q / (NTp / 16));
+    const int tau = 16 * n + (lane & 15), t = 16 * t16 + 4 * (lane >> 4) + r;
+    _Float16 hi, lo;
+    split_h(Phi[(int64_t)t * NTp + tau] * sphi, hi, lo);
+    _Float16* o = (_Float16*)Phq + (((int64_t)t16 * (NTp / 16) + n) * 64 + lane) * 8 + r;
+    o[0] = hi;
+    o[4] = lo;
+}
+
+// LDS of k_freq_fwd_q: the resident W rows and a 16 x 20-word phase transpose
+// area per wave, then the cross-wave reduction of V (8 waves x NTQ x 4 row blocks
+// x 2 spins x 64 lanes x 4 floats).
+constexpr size_t fwdq_lds(int Kp, int NTQ, bool with_phase) {
+    const size_t main_loop = (size_t)64 * (Kp * 8 + 16) + (with_phase ? (size_t)8 * 16 * 20 * 4 : 0);
+    const size_t reduction = (size_t)8 * NTQ * 4 * 2 * 64 * 4 * sizeof(float);
+    return main_loop > reduction ? main_loop : reduction;
+}
+
+// One workgroup: 64 rows l (W resident in LDS) x one t-chunk, in tiles of 128 t.
+// Eight waves; wave w owns t 16 w .. 16 w + 15 of each tile and all 64 rows, in
+// four 16-row blocks: every Y fragment is loaded from global memory by exactly one
+// wave, and each wave reads all W fragments of the tile from LDS.
+//   Z_up^T[t][l] = sum_k Y[k][t] W[l][k],   Z_down^T[t][l] = sum_k Y[k][t] conj W[l][k]
+//   V^T[tau][l] += sum_t Phi[t][tau] |Z^T[t][l]|     (per spin)
+// The C registers of the first product (rows t) are the B operand of the second
+// (K = t) as they stand.  The modulus enters the second product split with a
+// per-column power-of-two scale, removed from that tile's contribution before
+// accumulation.  NTQ blocks of 16 frames (N/T <= 32).  Workgroups are mapped as in
+// k_freq_fwd_h.
+template <int NK, int NTQ>
+__global__ void __launch_bounds__(512) k_freq_fwd_q(const unsigned short* __restrict__ Yh, int64_t yh_bstride, int Tp,
+                                                    int chunk, int nch, int nU, int nlt,
+                                                    const unsigned short* __restrict__ Wsp,
+                                                    const unsigned short* __restrict__ Phq, float unscale_wphi,
+                                                    const float* __restrict__ yscale, int alpha, int n_alpha,
+                                                    float* __restrict__ Vp, int64_t vp_bstride, int slot0,
+                                                    unsigned* __restrict__ phase, int64_t ph_bstride, float sw) {
+    constexpr int NTp = 32;                  // tau slots of the partial-V layout
+    constexpr int Kp = 16 * NK;
+    constexpr int NS = (NK + 1) / 2;         // k-steps of 32
+    constexpr bool TAIL = (NK & 1) != 0;     // the last k-step holds 16 k (k-groups 0, 1)
+    constexpr int WS = Kp * 8 + 16;          // bytes per resident W row
+    constexpr int NR = NS < 2 ? NS : 2;      // Y ring depth (k-steps)
+    extern __shared__ __align__(16) unsigned char lds[];
+
+    const int g = blockIdx.x;
+    const int u = ((g >> 3) / nlt) * 8 + (g & 7);
+    const int lt = (g >> 3) % nlt;
+    if (u >= nU) return;
+    const int64_t b = u / nch;
+    const int ch = u % nch;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j16 = lane & 15, g4 = lane >> 4;
+    constexpr int nkb = Kp / 8;
+
+    // resident W rows l0 .. l0+63
+    {
+        const uint4* src = (const uint4*)(Wsp + (int64_t)lt * 64 * Kp * 4);
+        constexpr int per_row = Kp / 2;      // uint4 per row
+        for (int e = tid; e < 64 * per_row; e += 512) {
+            const int r = e / per_row, c = e - r * per_row;
+            *(uint4*)(lds + r * WS + c * 16) = src[e];
+        }
+    }
+    const unsigned short* Yb = Yh + b * yh_bstride;
+    float eps2s = 0.f;
+    if (phase) {
+        const double wy = (double)sw * (double)yscale[b * n_alpha + alpha];
+        eps2s = (float)fmax(fmin((double)kEpsMod2 * wy * wy, 1e30), 1.1754943508222875e-38);
+    }
+    floatx4 vacc[NTQ][4][2];
+#pragma unroll
+    for (int n = 0; n < NTQ; ++n)
+#pragma unroll
+        for (int lb = 0; lb < 4; ++lb) { vacc[n][lb][0] = z4(); vacc[n][lb][1] = z4(); }
+    __syncthreads();                         // resident W complete
+
+    // this lane's W fragments: row 16 lb + j16, k-group 4 ks + g4, plane p
+    const unsigned char* wrow = lds + j16 * WS + g4 * 64;
+    auto load_w = [&](uint4 (&w)[4], int ks, int lb) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) w[p] = *(const uint4*)(wrow + lb * 16 * WS + ks * 256 + p * 16);
+    };
+    // this lane's Y fragments: column t, k-group 4 ks + g4, plane p (uint4 units)
+    const int tbeg = ch * chunk, tend = (ch + 1) * chunk;
+    auto ycol_at = [&](int t0) {
+        const int t = t0 + wave * 16 + j16;
+        return launder_v((const uint4*)Yb + (((int64_t)(t >> 5) * nkb + g4) * 128 + (t & 31)));
+    };
+    auto load_yq = [&](uint4 (&y)[4], gptr<uint4> yc, int ks) {
+        gptr<u32x4> p = (gptr<u32x4>)(yc + 512 * ks);
+        const bool ok = !(TAIL && ks == NS - 1 && g4 >= 2);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) y[j] = ok ? __builtin_bit_cast(uint4, p[32 * j]) : make_uint4(0, 0, 0, 0);
+    };
+    uint4 yr[NR][4];
+    gptr<uint4> yc = ycol_at(tbeg);
+#pragma unroll
+    for (int s = 0; s < NR; ++s) load_yq(yr[s], yc, s);
+    unsigned* tb = (unsigned*)(lds + 64 * WS) + wave * (16 * 20);   // phase transpose area
+    for (int t0 = tbeg; t0 < tend; t0 += kTileTh) {
+        const int t16 = (t0 >> 4) + wave;
+        // Phi fragments of this tile (A operand of the lowpass product)
+        uint4 phf[NTQ];
+#pragma unroll
+        for (int n = 0; n < NTQ; ++n)
+            phf[n] = __builtin_bit_cast(uint4, ((gptr<u32x4>)launder_v((const uint4*)Phq))[((int64_t)t16 * (NTp / 16) + n) * 64 + lane]);
+        floatx4 rr[4], ir[4], ri[4], ii[4];
+#pragma unroll
+        for (int lb = 0; lb < 4; ++lb) { rr[lb] = z4(); ir[lb] = z4(); ri[lb] = z4(); ii[lb] = z4(); }
+        uint4 wc[4], wn[4];
+        load_w(wc, 0, 0);
+#pragma unroll
+        for (int ks = 0; ks < NS; ++ks) {
+            uint4(&q)[4] = yr[ks % NR];
+            const bool tail_step = TAIL && ks == NS - 1;
+            const half8 y0 = as_h8(q[0]), y1 = as_h8(q[1]), y2 = as_h8(q[2]), y3 = as_h8(q[3]);
+#pragma unroll
+            for (int lb = 0; lb < 4; ++lb) {
+                // the next fragments (next row block, or the next k-step's first) are
+                // requested before this block's products
+                if (lb + 1 < 4) load_w(wn, ks, lb + 1);
+                else if (ks + 1 < NS) load_w(wn, ks + 1, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                uint4 wv[4];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) wv[p] = tail_step && g4 >= 2 ? make_uint4(0, 0, 0, 0) : wc[p];
+                const half8 w0 = as_h8(wv[0]), w1 = as_h8(wv[1]), w2 = as_h8(wv[2]), w3 = as_h8(wv[3]);
+                // the four accumulators in turn, so that no product waits for the one
+                // before it (each keeps its own summation order)
+                rr[lb] = mfma16q(y0, w0, rr[lb]); ir[lb] = mfma16q(y2, w0, ir[lb]);
+                ri[lb] = mfma16q(y0, w2, ri[lb]); ii[lb] = mfma16q(y2, w2, ii[lb]);
+                rr[lb] = mfma16q(y0, w1, rr[lb]); ir[lb] = mfma16q(y2, w1, ir[lb]);
+                ri[lb] = mfma16q(y0, w3, ri[lb]); ii[lb] = mfma16q(y2, w3, ii[lb]);
+                rr[lb] = mfma16q(y1, w0, rr[lb]); ir[lb] = mfma16q(y3, w0, ir[lb]);
+                ri[lb] = mfma16q(y1, w2, ri[lb]); ii[lb] = mfma16q(y3, w2, ii[lb]);
+#pragma unroll
+                for (int p = 0; p < 4; ++p) wc[p] = wn[p];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (ks + NR < NS) load_yq(q, yc, ks + NR);
+        }
+        // the next tile's first Y k-steps go out before this tile's epilogue
+        if (t0 + kTileTh < tend) {
+            yc = ycol_at(t0 + kTileTh);
+#pragma unroll
+            for (int s = 0; s < NR; ++s) load_yq(yr[s], yc, s);
+        }
+        // modulus of both spins, per-column scale, split, lowpass product; with
+        // phase storage also u = z / max(|z|, eps) as two snorm16 (real in the low
+        // half) in the layout of k_freq_fwd_h: element ((spin, l / 32, (l % 32) / 8), t, l % 8)
+#pragma unroll
+        for (int spin = 0; spin < 2; ++spin) {
+#pragma unroll
+            for (int lb = 0; lb < 4; ++lb) {
+                float uv[4];
+                float m = 0.f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float zr = spin ? rr[lb][r] + ii[lb][r] : rr[lb][r] - ii[lb][r];
+                    const float zi = spin ? ir[lb][r] - ri[lb][r] : ir[lb][r] + ri[lb][r];
+                    uv[r] = __builtin_amdgcn_sqrtf(zr * zr + zi * zi);   // hardware square root (1 ulp)
+                    m = fmaxf(m, uv[r]);
+                }
+                if (phase) {
+                    // rows t 4 g4 + r, column j16 of the wave's 16 x 16 block -> 16-byte
+                    // runs of four rows l of one t
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float zr = spin ? rr[lb][r] + ii[lb][r] : rr[lb][r] - ii[lb][r];
+                        const float zi = spin ? ir[lb][r] - ri[lb][r] : ir[lb][r] + ri[lb][r];
+                        const float qn = __builtin_amdgcn_rsqf(fmaxf(zr * zr + zi * zi, eps2s));
+                        tb[(4 * g4 + r) * 20 + j16] = pack_snorm16(zr * qn, zi * qn);
+                    }
+                    const int tt = lane >> 2, jq = lane & 3;
+                    const int ll = lb * 16 + 4 * jq;                 // first row of the quad in the 64-row tile
+                    const int wl = ll >> 5, g8 = (ll & 31) >> 3;
+                    unsigned* pb = phase + b * ph_bstride +
+                                   ((((int64_t)(spin * nlt + lt) * 2 + wl) * 4 + g8) * Tp + t0 + wave * 16 + tt) * 8 +
+                                   (ll & 7);
+                    const u32x4 v = __builtin_bit_cast(u32x4, *(const uint4*)(tb + tt * 20 + 4 * jq));
+                    // read back only by the backward, long after: a streaming store, so
+                    // that it does not evict the Y operand the row tiles share in L2
+                    __builtin_nontemporal_store(v, (u32x4*)pb);
+                }
+                m = fmaxf(m, __shfl_xor(m, 16));
+                m = fmaxf(m, __shfl_xor(m, 32));
+                const int se = pow2_exp(m);
+                const float su = ldexpf(1.f, se), inv_su = ldexpf(1.f, -se);
+                half4 uh, ul;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    _Float16 hi, lo;
+                    split_h(uv[r] * su, hi, lo);
+                    uh[r] = hi;
+                    ul[r] = lo;
+                }
+#pragma unroll
+                for (int n = 0; n < NTQ; ++n) {
+                    const uint4 f = phf[n];
+                    const half4 phi = __builtin_bit_cast(half4, make_uint2(f.x, f.y));
+                    const half4 plo = __builtin_bit_cast(half4, make_uint2(f.z, f.w));
+                    floatx4 tmp = z4();
+                    tmp = mfma16k(phi, uh, tmp);
+                    tmp = mfma16k(phi, ul, tmp);
+                    tmp = mfma16k(plo, uh, tmp);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) vacc[n][lb][spin][r] += tmp[r] * inv_su;
+                }
+            }
+        }
+    }
+    // sum the eight waves' partial V through LDS, unscale, store
+    const float unscale = unscale_wphi / yscale[b * n_alpha + alpha];
+    float* red = (float*)lds;                // [wave][n][lb][spin][64 lanes][4]
+    __syncthreads();
+#pragma unroll
+    for (int n = 0; n < NTQ; ++n)
+#pragma unroll
+        for (int lb = 0; lb < 4; ++lb)
+#pragma unroll
+            for (int spin = 0; spin < 2; ++spin)
+                *(float4*)(red + ((((wave * NTQ + n) * 4 + lb) * 2 + spin) * 64 + lane) * 4) =
+                    make_float4(vacc[n][lb][spin][0], vacc[n][lb][spin][1], vacc[n][lb][spin][2],
+                                vacc[n][lb][spin][3]);
+    __syncthreads();
+    float* o = Vp + b * vp_bstride + ((int64_t)(slot0 + ch) * nlt + lt) * 2 * NTp * kTileL;
+    for (int e = tid; e < NTQ * 4 * 2 * 64 * 4; e += 512) {
+        // e = (((n * 4 + lb) * 2 + spin) * 64 + ln) * 4 + r: element tau = 16 n + 4 (ln / 16) + r,
+        // l = 16 lb + ln % 16
+        const int r = e & 3, ln = (e >> 2) & 63, spin = (e >> 8) & 1, lb = (e >> 9) & 3, n = e >> 11;
+        float acc = 0.f;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) acc += red[(((w * NTQ * 4 * 2) * 64) * 4) + e];
+        const int tau = 16 * n + 4 * (ln >> 4) + r, l = 16 * lb + (ln & 15);
+        o[((int64_t)spin * NTp + tau) * kTileL + l] = acc * unscale;
+    }
+}
 
 // ------------------------------------------------------ backward contraction
 
@@ -1256,6 +1521,16 @@ int build_split_tables(jtfs_plan* P, std::vector<void*>& owned) {
         hipLaunchKernelGGL(k_phtsplit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, P->Phi + s.phioff[a],
                            s.Tp[a], s.NTp, P->sphi[a], P->PhTsp + s.phioff[a] * 2);
     }
+    if (s.NTp == 32) {
+        // the lowpass operand of the 16 x 16-tile forward
+        P->Phq = (unsigned short*)alloc(sizeof(float) * s.sumTp * s.NTp);
+        if (!P->Phq) { set_error("device allocation failed"); return JTFS_ENOMEM; }
+        for (int a = 0; a < s.n_alpha; ++a) {
+            const int64_t n = (int64_t)s.Tp[a] * s.NTp;
+            hipLaunchKernelGGL(k_phqsplit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, P->Phi + s.phioff[a],
+                               s.Tp[a], s.NTp, P->sphi[a], P->Phq + s.phioff[a] * 2);
+        }
+    }
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         set_error("split-operand construction failed"); return JTFS_EHIP; }
     {
@@ -1264,8 +1539,9 @@ int build_split_tables(jtfs_plan* P, std::vector<void*>& owned) {
         // (<= 160 KB), and one wave per SIMD without scratch
         P->split_bwd_ok = (s.NTp == 32 && NI <= 6) || (s.NTp == 64 && NI <= 5);
         // stored-phase backward: two W^T chunks (16 NI KB) per launch, at most two
-        // launches over halves of the i-blocks
-        P->split_bwdp_ok = NI <= 2 * bwdp_max_ni(s.NTp);
+        // launches over halves of the i-blocks; the forward must hold its phase
+        // transpose area beside the resident W tile
+        P->split_bwdp_ok = NI <= 2 * bwdp_max_ni(s.NTp) && split_fwd_lds(s, true) <= (size_t)kMaxDynLds;
     }
     P->contraction = JTFS_CONTRACTION_SPLIT_F16;
     return JTFS_OK;
@@ -1288,11 +1564,43 @@ static int fwd_attributes() {
     }
 }
 
+template <int NTQ, int NK = 1>
+static int fwdq_attributes() {
+    if constexpr (NK > kMaxFwdNK) {
+        return JTFS_OK;
+    } else {
+        if (hipFuncSetAttribute((const void*)k_freq_fwd_q<NK, NTQ>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kMaxDynLds) != hipSuccess) {
+            set_error("hipFuncSetAttribute failed for the split contraction");
+            return JTFS_EHIP;
+        }
+        return fwdq_attributes<NTQ, NK + 1>();
+    }
+}
+
 int split_attributes() {
     // the backward kernels use static LDS only; the forward takes it dynamically
     int rc = fwd_attributes<1>();
     if (rc == JTFS_OK) rc = fwd_attributes<2>();
+    if (rc == JTFS_OK) rc = fwdq_attributes<1>();
+    if (rc == JTFS_OK) rc = fwdq_attributes<2>();
     return rc;
+}
+
+template <int NTQ, int NK = 1, typename... Args>
+static void launch_fwdq_nk(int nk, dim3 grid, size_t lds, hipStream_t st, Args... args) {
+    if constexpr (NK <= kMaxFwdNK) {
+        if (nk == NK) hipLaunchKernelGGL((k_freq_fwd_q<NK, NTQ>), grid, dim3(512), lds, st, args...);
+        else launch_fwdq_nk<NTQ, NK + 1>(nk, grid, lds, st, args...);
+    }
+}
+
+// whether the 16 x 16-tile forward handles the plan's shapes (N/T <= 32, LDS)
+bool fwdq_supported(const jtfs_plan* P, bool with_phase) {
+    const Shapes& s = P->s;
+    const int ntq = (s.NT + 15) / 16;
+    return P->Phq && s.NTp == 32 && ntq <= 2 && s.Kp / 16 <= kMaxFwdNK &&
+           fwdq_lds(s.Kp, ntq, with_phase) <= (size_t)kMaxDynLds;
 }
 
 template <int NTB, int NK = 1, typename... Args>
@@ -1329,6 +1637,16 @@ int launch_freq_fwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, c
     if (nk < 1 || nk > kMaxFwdNK) { set_error("K beyond the split contraction's LDS tile"); return JTFS_ENOTSUP; }
     // this rate's block of the stored phase (2 Mp Tp elements) after the rates before it
     unsigned* pha = phase ? phase + (int64_t)2 * s.Mp * (s.yoff[a] / s.Kp) : nullptr;
+    if (P->tune.fwd16 && fwdq_supported(P, phase != nullptr)) {
+        const int ntq = (s.NT + 15) / 16;
+        const size_t ldsq = fwdq_lds(s.Kp, ntq, phase != nullptr);
+        const unsigned short* Pq = P->Phq + s.phioff[a] * 2;
+        if (ntq == 1)
+            launch_fwdq_nk<1>(nk, dim3(grid), ldsq, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Pq, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw);
+        else
+            launch_fwdq_nk<2>(nk, dim3(grid), ldsq, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Pq, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw);
+        return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
+    }
     switch (s.NTp / 32) {
         case 1: launch_fwd_nk<1>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw); break;
         case 2: launch_fwd_nk<2>(nk, dim3(grid), lds, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Ph, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw); break;

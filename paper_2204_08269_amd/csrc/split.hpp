@@ -24,4 +24,6 @@ int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int6
 // gV of every rate split into the FP16 planes and row scales the stored-phase
 // backward reads (Gs: gs_bstride 16-byte units per signal)
 int launch_gv_split(const jtfs_plan* P, const float* gV, uint4* Gs, int64_t B, hipStream_t st);
+// whether the 16 x 16-tile forward contraction handles the plan's shapes
+bool fwdq_supported(const jtfs_plan* P, bool with_phase);
 }  // namespace jtfs

@@ -356,8 +356,9 @@ def cfg5_reference():
     return CFG5_REF
 
 
-@pytest.mark.parametrize("mode", ["fp32", "split16", "split16_phase"])
-def test_cfg5_s2_and_gradient_match_oracle(mode):
+@pytest.mark.parametrize("mode,tile", [("fp32", 32), ("split16", 32), ("split16_phase", 32), ("split16", 16),
+                                       ("split16_phase", 16)])
+def test_cfg5_s2_and_gradient_match_oracle(mode, tile):
     """32 x 2^18 FM mixtures (n1 = 285: K = 288, 18 k-steps of the split forward,
     9 i-blocks of the backward), in the launch configuration of the benchmark
     (the whole batch): every S1 path and every (beta, theta) path of S2 at the
@@ -365,13 +366,15 @@ def test_cfg5_s2_and_gradient_match_oracle(mode):
     for the first and last signal, against the FP64 oracle; the gradient of
     signal 0 for a cotangent on S1 and those rates against the oracle's VJP,
     after a forward on the same workspace (the stored-phase mode reads the
-    phase it kept) and without one (that mode then takes the phase again)."""
+    phase it kept) and without one (that mode then takes the phase again);
+    both tiles of the split forward."""
     p = synth.PARAMS[5]
     ref = cfg5_reference()
     x = ref["x"]
     alphas = [int(a) for a in ref["alphas"]]
     op = gpu_op(p, mode)
     assert op.contraction == mode
+    op.set_tuning(mode, ["scalogram", "second_order", "row_fft", "first_adj"], fwd_tile=tile)
     B = x.shape[0]
     xt = torch.from_numpy(x).cuda()
     ws = op.new_workspace(B)
@@ -675,8 +678,10 @@ MID = dict(N=2 ** 14, J=5, Q=(1, 1), J_fr=2, Q_fr=1, T=2 ** 9, F=2)
 
 def test_autotune_then_every_row_choice_matches_oracle():
     """The autotuner returns a valid choice; and every combination of
-    register-resident and in-LDS transforms for 2^14-point rows, in both
-    contraction modes, gives the oracle's coefficients and gradient."""
+    register-resident and in-LDS transforms for 2^14-point rows and of the
+    forward contraction's tiles, in every contraction mode, gives the oracle's
+    coefficients and gradient (the stored-phase mode's gradient after a forward
+    on the same workspace)."""
     P = oracle_plan(MID)
     assert P.NX == 2 ** 14
     rng = np.random.default_rng(1414)
@@ -685,20 +690,45 @@ def test_autotune_then_every_row_choice_matches_oracle():
     op = gpu_op(MID)
     choice = op.autotune(2, xt, reps=2)
     assert choice["contraction"] in ("split16", "split16_phase", "fp32") and choice["step_ms"] > 0
-    # every available mode was timed (the stored phase fits in memory at this size)
+    assert not choice["from_cache"] and choice["fwd_tile"] in (16, 32)
+    # every available mode was timed (the stored phase fits in memory at this size), both forward tiles
     c = choice["candidates_ms"]
     assert c["split16_register"] > 0 and c["fp32_register"] > 0 and c["split16_phase_register"] > 0
+    assert c["split16_lds"] > 0 and choice["fwd_ms"]["tile16"] > 0
+    assert op.tuning() == (choice["contraction"], choice["register_rows"], choice["fwd_tile"])
     gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape(), seed=31)
     refs = [(O.jtfs(x[b].astype(np.float64), P),
              O.jtfs_vjp(x[b].astype(np.float64), gs1[b].astype(np.float64), gs2[b].astype(np.float64), P))
             for b in range(2)]
-    for mode in MODES:
-        for rows in ([], ["scalogram", "second_order", "row_fft", "first_adj"], ["scalogram", "row_fft"],
-                     ["second_order", "first_adj"]):
-            op.set_tuning(mode, rows)
-            g1, g2 = run_forward(op, x)
-            g = op.vjp(xt, torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda()).cpu().numpy()
+    for mode in MODES + ["split16_phase"]:
+        for rows, tile in (([], 16), (["scalogram", "second_order", "row_fft", "first_adj"], 32),
+                           (["scalogram", "row_fft"], 16), (["second_order", "first_adj"], 32)):
+            op.set_tuning(mode, rows, fwd_tile=tile)
+            ws = op.new_workspace(2)
+            s1, s2 = op.forward(xt, ws)
+            g = op.vjp(xt, torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda(), ws=ws,
+                       reuse_forward=True).cpu().numpy()
+            g1, g2 = s1.cpu().numpy(), s2.cpu().numpy()
             for b in range(2):
                 (r1, r2), rg = refs[b]
                 check_paths(g1[b], g2[b], r1, r2)
-                assert rel_l2(g[b], rg) <= TOL_VJP, (mode, rows)
+                assert rel_l2(g[b], rg) <= TOL_VJP, (mode, rows, tile)
+
+
+def test_autotune_cache_reuses_the_choice(tmp_path, monkeypatch):
+    """With JTFS_TUNE_CACHE set, a second autotune of the same shape and batch on
+    the same device applies the stored choice without timing it."""
+    monkeypatch.setenv("JTFS_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    xt = torch.from_numpy(synth.batch(1, B=2)).cuda()
+    first = gpu_op(P1).autotune(2, xt, reps=1)
+    assert not first["from_cache"]
+    assert (tmp_path / "tune.txt").read_text().count("B=2") == 1
+    op = gpu_op(P1)
+    second = op.autotune(2, xt, reps=1)
+    assert second["from_cache"]
+    for k in ("contraction", "register_rows", "fwd_tile"):
+        assert second[k] == first[k], k
+    assert op.tuning() == (first["contraction"], first["register_rows"], first["fwd_tile"])
+    # another batch size is another key
+    third = op.autotune(3, torch.from_numpy(synth.batch(1, B=3)).cuda(), reps=1)
+    assert not third["from_cache"]
