@@ -1,6 +1,9 @@
 // Ragged batches: signals bucketed by padded power-of-two length, one plan and
 // workspace per bucket, pack / forward / backward / unpack recorded once as a HIP
-// graph and replayed.
+// graph and replayed.  Each bucket's work is recorded on a stream of its own,
+// forked from and joined back to the caller's stream, so that the graph holds
+// one independent branch per bucket and the buckets' launches can overlap (the
+// short launches of one bucket's low temporal rates fill the GPU with another's).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -53,6 +56,8 @@ struct Bucket {
     jtfs_info info{};
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;             // the bucket's branch while the graph is recorded
+    hipEvent_t done = nullptr;
     int mode_plain = JTFS_CONTRACTION_FP32;   // the plan's own contraction (forward-only runs)
     bool phase = false;                       // runs with a gradient store the phase
     float *xb = nullptr, *s1 = nullptr, *s2 = nullptr, *g1 = nullptr, *g2 = nullptr, *gxb = nullptr;
@@ -66,6 +71,7 @@ struct jtfs_bucket {
     std::vector<void*> owned;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t fork = nullptr;
     const void* key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -73,7 +79,12 @@ static void release(jtfs_bucket* bk) {
     if (!bk) return;
     if (bk->exec) (void)hipGraphExecDestroy(bk->exec);
     if (bk->graph) (void)hipGraphDestroy(bk->graph);
-    for (auto& b : bk->buckets) if (b.plan) jtfs_plan_destroy(b.plan);
+    if (bk->fork) (void)hipEventDestroy(bk->fork);
+    for (auto& b : bk->buckets) {
+        if (b.plan) jtfs_plan_destroy(b.plan);
+        if (b.stream) (void)hipStreamDestroy(b.stream);
+        if (b.done) (void)hipEventDestroy(b.done);
+    }
     for (void* q : bk->owned) (void)hipFree(q);
     delete bk;
 }
@@ -172,6 +183,14 @@ extern "C" int jtfs_bucket_create(jtfs_bucket** out, const int64_t* lengths, int
             hipMemcpy(b.d_soff, so.data(), sizeof(int64_t) * B, hipMemcpyHostToDevice) != hipSuccess) {
             release(bk); set_error("upload failed"); return JTFS_EHIP;
         }
+        // the branch's stream (default priority) and its join event
+        if (hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) {
+            release(bk); set_error("stream or event creation failed"); return JTFS_EHIP;
+        }
+    }
+    if (hipEventCreateWithFlags(&bk->fork, hipEventDisableTiming) != hipSuccess) {
+        release(bk); set_error("event creation failed"); return JTFS_EHIP;
     }
     *out = bk;
     return JTFS_OK;
@@ -184,8 +203,13 @@ extern "C" int jtfs_bucket_offsets(const jtfs_bucket* bk, int64_t* x_offset, int
     return JTFS_OK;
 }
 
-static int enqueue(jtfs_bucket* bk, const float* xp, float* sp, const float* gp, float* gxp, hipStream_t st) {
+// Records every bucket's work on its own stream, forked from st and joined back
+// (called while st is being captured: the branches become parallel in the graph).
+static int enqueue(jtfs_bucket* bk, const float* xp, float* sp, const float* gp, float* gxp, hipStream_t st0) {
+    if (hipEventRecord(bk->fork, st0) != hipSuccess) { set_error("fork event failed"); return JTFS_EHIP; }
     for (auto& b : bk->buckets) {
+        const hipStream_t st = b.stream;
+        if (hipStreamWaitEvent(st, bk->fork, 0) != hipSuccess) { set_error("fork wait failed"); return JTFS_EHIP; }
         const unsigned B = (unsigned)b.members.size();
         const int64_t s1n = b.info.s1_per_signal, s2n = b.info.s2_per_signal, row = s1n + s2n;
         hipLaunchKernelGGL(k_pack, dim3((unsigned)((b.N + 255) / 256), B), dim3(256), 0, st, xp, b.d_xoff, b.d_len,
@@ -210,6 +234,8 @@ static int enqueue(jtfs_bucket* bk, const float* xp, float* sp, const float* gp,
         }
         (void)row;
         if (hipGetLastError() != hipSuccess) { set_error("bucket kernel launch failed"); return JTFS_EHIP; }
+        if (hipEventRecord(b.done, st) != hipSuccess || hipStreamWaitEvent(st0, b.done, 0) != hipSuccess) {
+            set_error("join failed"); return JTFS_EHIP; }
     }
     return JTFS_OK;
 }
