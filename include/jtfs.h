@@ -231,8 +231,10 @@ int jtfs_plan_table(const jtfs_plan* plan, int which, void* host_dst, size_t byt
  *
  * jtfs_bucket_run computes S (and gx when g_packed and gx_packed are non-NULL).
  * The first call for a given (pointer set, stream) records all buckets' work as
- * one HIP graph (pack, forward, backward, unpack); later calls with the same
- * pointers replay it with a single graph launch.  Not thread-safe per object. */
+ * one HIP graph (pack, forward, backward, unpack), each bucket on a branch of its
+ * own (forked from and joined back to the stream, so that the buckets may run
+ * concurrently); later calls with the same pointers replay it with a single
+ * graph launch.  Not thread-safe per object. */
 typedef struct jtfs_bucket jtfs_bucket;
 int jtfs_bucket_create(jtfs_bucket** out, const int64_t* lengths, int count, const jtfs_params* p);
 int jtfs_bucket_offsets(const jtfs_bucket* bk, int64_t* x_offset, int64_t* s_offset);
@@ -294,10 +296,11 @@ void jtfs_texture_destroy(jtfs_texture* tex);
  * contraction).  jtfs_plan_autotune runs, for B signals x (device, [B][N]; NULL:
  * zeros), one untimed and `reps` timed fwd+bwd steps per candidate: each
  * available contraction mode, once with all four stages register-resident and
- * 32 x 32 forward tiles and once with all four in LDS and 16 x 16 forward tiles
- * (where these choices exist).  It keeps the contraction whose own stages took
- * least time (its forward with the faster tile), per stage the faster transform,
- * and the faster forward tile, then times the result (step_ms).  With the
+ * 32 x 32 contraction tiles and once with all four in LDS and 16 x 16 tiles in
+ * the forward and the stored-phase backward (where these choices exist).  It
+ * keeps the contraction whose own stages took least time (each contraction
+ * kernel with its faster tile), per stage the faster transform, and the faster
+ * tiles, then times the result (step_ms).  With the
  * environment variable JTFS_TUNE_CACHE naming a file, a result is appended to it
  * under a key of the device's architecture and name, the plan parameters and B,
  * and a later call with the same key applies the stored choice without timing
@@ -312,8 +315,8 @@ void jtfs_texture_destroy(jtfs_texture* tex);
  * sets the mode with jtfs_plan_set_tuning instead).  candidates_ms: fwd+bwd per step of
  * (split, first run), (split, second run), (FP32, first), (FP32, second), (split with
  * stored phase, first), (split with stored phase, second); 0 for candidates not run.
- * fwd_ms: the chosen mode's forward contraction per step with 32 x 32 and 16 x 16
- * tiles (0 where not run). */
+ * fwd_ms, bwd_ms: the chosen mode's forward contraction and backward contraction
+ * per step with 32 x 32 and 16 x 16 tiles (0 where not run). */
 #define JTFS_REG_SCALOGRAM    1
 #define JTFS_REG_SECOND_ORDER 2
 #define JTFS_REG_ROW_FFT      4
@@ -321,12 +324,16 @@ void jtfs_texture_destroy(jtfs_texture* tex);
 /* In the same mask: the split forward contraction in 16 x 16 MFMA tiles (each
  * wave 64 rows l x 16 columns t; available where N/T <= 32), else 32 x 32 tiles. */
 #define JTFS_TUNE_FWD_TILE16  16
+/* ... and the stored-phase backward in 16 x 16 tiles (each wave 16 columns t and
+ * all rows i, one pass for any K; N/T <= 32), else 32 x 32 tiles. */
+#define JTFS_TUNE_BWD_TILE16  32
 typedef struct {
     int32_t contraction;
     int32_t reg_rows;                 /* including JTFS_TUNE_FWD_TILE16 */
     double step_ms;
     double candidates_ms[6];
     double fwd_ms[2];
+    double bwd_ms[2];
     int32_t from_cache;
 } jtfs_tuning;
 int jtfs_plan_autotune(jtfs_plan* plan, const float* x, int64_t B, int reps, hipStream_t stream, jtfs_tuning* out);

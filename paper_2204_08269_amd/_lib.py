@@ -34,7 +34,7 @@ STAGES = ["input_fft", "scalogram", "s1", "second_order", "operand_split", "freq
 class Tuning(ctypes.Structure):
     _fields_ = [("contraction", ctypes.c_int32), ("reg_rows", ctypes.c_int32), ("step_ms", ctypes.c_double),
                 ("candidates_ms", ctypes.c_double * 6), ("fwd_ms", ctypes.c_double * 2),
-                ("from_cache", ctypes.c_int32)]
+                ("bwd_ms", ctypes.c_double * 2), ("from_cache", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):

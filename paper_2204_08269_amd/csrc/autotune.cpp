@@ -41,12 +41,13 @@ void set_rows(jtfs_plan* P, int mask) {
     P->tune.reg_rowfft = (mask & JTFS_REG_ROW_FFT) != 0;
     P->tune.reg_first_adj = (mask & JTFS_REG_FIRST_ADJ) != 0;
     P->tune.fwd16 = (mask & JTFS_TUNE_FWD_TILE16) != 0;
+    P->tune.bwd16 = (mask & JTFS_TUNE_BWD_TILE16) != 0;
 }
 
 int get_rows(const jtfs_plan* P) {
     return (P->tune.reg_scalogram ? JTFS_REG_SCALOGRAM : 0) | (P->tune.reg_second ? JTFS_REG_SECOND_ORDER : 0) |
            (P->tune.reg_rowfft ? JTFS_REG_ROW_FFT : 0) | (P->tune.reg_first_adj ? JTFS_REG_FIRST_ADJ : 0) |
-           (P->tune.fwd16 ? JTFS_TUNE_FWD_TILE16 : 0);
+           (P->tune.fwd16 ? JTFS_TUNE_FWD_TILE16 : 0) | (P->tune.bwd16 ? JTFS_TUNE_BWD_TILE16 : 0);
 }
 
 // Cache key: the device's architecture and name, the plan parameters and B.
@@ -143,7 +144,7 @@ int run_steps(jtfs_plan* P, const float* x, int64_t B, float* s1, float* s2, flo
 extern "C" int jtfs_plan_set_tuning(jtfs_plan* P, int contraction, int reg_rows) {
     if (!P) { set_error("null plan"); return JTFS_EINVAL; }
     if (reg_rows & ~(JTFS_REG_SCALOGRAM | JTFS_REG_SECOND_ORDER | JTFS_REG_ROW_FFT | JTFS_REG_FIRST_ADJ |
-                     JTFS_TUNE_FWD_TILE16)) {
+                     JTFS_TUNE_FWD_TILE16 | JTFS_TUNE_BWD_TILE16)) {
         set_error("unknown row-kernel bits"); return JTFS_EINVAL; }
     const int rc = jtfs_plan_set_contraction(P, contraction);
     if (rc != JTFS_OK) return rc;
@@ -200,10 +201,13 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
     bool has14 = s.logNX == kRegMinLogRows;
     for (int a = 0; a < s.n_alpha; ++a) has14 = has14 || (s.logNX - s.k2[a] == kRegMinLogRows);
     const int all_rows = JTFS_REG_SCALOGRAM | JTFS_REG_SECOND_ORDER | JTFS_REG_ROW_FFT | JTFS_REG_FIRST_ADJ;
-    // second run: rows in LDS and the 16 x 16 forward tile, where either choice exists
+    // second run: rows in LDS and the 16 x 16 contraction tiles, where any of these choices exists
     const bool tile16 = P->split_ok && !s.tscat && fwdq_supported(P, false);
+    const bool btile16 = P->split_ok && P->split_bwdp_ok && !s.tscat && bwdq_supported(P);
     std::vector<int> row_opts{all_rows};
-    if (has14 || tile16) row_opts.push_back((has14 ? 0 : all_rows) | (tile16 ? JTFS_TUNE_FWD_TILE16 : 0));
+    if (has14 || tile16 || btile16)
+        row_opts.push_back((has14 ? 0 : all_rows) | (tile16 ? JTFS_TUNE_FWD_TILE16 : 0) |
+                           (btile16 ? JTFS_TUNE_BWD_TILE16 : 0));
     // buffers: the largest workspace over the modes; the coefficients double as cotangents
     size_t wsb = 0;
     for (int m : modes) {
@@ -248,25 +252,32 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
             out->candidates_ms[slot] = total[mi][ri];
         }
     }
-    // contraction: the stages it owns (the forward with the faster of its tiles)
+    // contraction: the stages it owns (each contraction kernel with the faster of its tiles)
     const int cstages[] = {JTFS_STAGE_OPERAND_SPLIT, JTFS_STAGE_FREQ_LOWPASS, JTFS_STAGE_LOWPASS_ADJ,
-                           JTFS_STAGE_FREQ_ADJ_PQ, JTFS_STAGE_FREQ_ADJ_WH};
+                           JTFS_STAGE_FREQ_ADJ_WH};
     auto fwd_ms = [&](size_t mi, size_t ri) { return stage[mi][ri][JTFS_STAGE_FREQ_FWD]; };
+    auto bwd_ms = [&](size_t mi, size_t ri) { return stage[mi][ri][JTFS_STAGE_FREQ_ADJ_PQ]; };
     auto tile_ok = [&](size_t mi) {
-        return tile16 && modes[mi] != JTFS_CONTRACTION_FP32 &&
+        return tile16 && row_opts.size() == 2 && modes[mi] != JTFS_CONTRACTION_FP32 &&
                fwdq_supported(P, modes[mi] == JTFS_CONTRACTION_SPLIT_F16_PHASE);
+    };
+    auto btile_ok = [&](size_t mi) {
+        return btile16 && row_opts.size() == 2 && modes[mi] == JTFS_CONTRACTION_SPLIT_F16_PHASE;
     };
     size_t best_m = 0;
     double best_c = 1e300;
     for (size_t mi = 0; mi < modes.size(); ++mi) {
-        double c = fwd_ms(mi, 0);
-        if (tile_ok(mi) && row_opts.size() == 2) c = std::min(c, fwd_ms(mi, 1));
+        double c = tile_ok(mi) ? std::min(fwd_ms(mi, 0), fwd_ms(mi, 1)) : fwd_ms(mi, 0);
+        c += btile_ok(mi) ? std::min(bwd_ms(mi, 0), bwd_ms(mi, 1)) : bwd_ms(mi, 0);
         for (int k : cstages) c += stage[mi][0][k];
         if (c < best_c) { best_c = c; best_m = mi; }
     }
-    const bool use16 = tile_ok(best_m) && row_opts.size() == 2 && fwd_ms(best_m, 1) < fwd_ms(best_m, 0);
+    const bool use16 = tile_ok(best_m) && fwd_ms(best_m, 1) < fwd_ms(best_m, 0);
+    const bool buse16 = btile_ok(best_m) && bwd_ms(best_m, 1) < bwd_ms(best_m, 0);
     out->fwd_ms[0] = fwd_ms(best_m, 0);
-    out->fwd_ms[1] = tile_ok(best_m) && row_opts.size() == 2 ? fwd_ms(best_m, 1) : 0.0;
+    out->fwd_ms[1] = tile_ok(best_m) ? fwd_ms(best_m, 1) : 0.0;
+    out->bwd_ms[0] = bwd_ms(best_m, 0);
+    out->bwd_ms[1] = btile_ok(best_m) ? bwd_ms(best_m, 1) : 0.0;
     // rows of 2^14 points: per stage, the faster of the two runs of the chosen mode
     int rows = all_rows;
     if (has14) {
@@ -278,6 +289,7 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
             if (stage[best_m][0][kstage[q]] <= stage[best_m][1][kstage[q]]) rows |= kbit[q];
     }
     if (use16) rows |= JTFS_TUNE_FWD_TILE16;
+    if (buse16) rows |= JTFS_TUNE_BWD_TILE16;
     P->contraction = modes[best_m];
     set_rows(P, rows);
     double stage_final[JTFS_NUM_STAGES];

@@ -97,6 +97,7 @@ struct Tuning {
     bool reg_rowfft = true;      // FFT of the gY2 rows of 2^14 points
     bool reg_first_adj = true;   // first-order adjoint rows of 2^14 points
     bool fwd16 = false;          // forward contraction in 16 x 16 tiles (else 32 x 32)
+    bool bwd16 = false;          // stored-phase backward in 16 x 16 tiles (else 32 x 32)
 };
 // rows of 2^logn points take the register-resident kernels above 2^14 always, at
 // 2^14 when the tuning says so, and the in-LDS kernels below
@@ -143,6 +144,7 @@ struct jtfs_plan {
     unsigned short* WTsp = nullptr;  // [Mp/32][KpT/32][16][32][8]: W^T * sw, chunks in LDS order
     unsigned short* PhTsp = nullptr; // per alpha [Tp][NTp/8][2][8]: Phi * sphi[alpha], tau contiguous
     unsigned short* Phq = nullptr;   // per alpha [Tp/16][NTp/16][64][2][4]: Phi * sphi[alpha] (N/T <= 32)
+    unsigned short* WTq = nullptr;   // [Mp/32][KpT/16][4][64][8]: W^T * sw in the 16 x 16 backward's k order
     std::vector<float> sphi;
     void* owned = nullptr;         // list of device allocations released by destroy
 };

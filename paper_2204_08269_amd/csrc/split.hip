@@ -1451,6 +1451,242 @@ __global__ void __launch_bounds__(256) k_freq_bwd_p(const unsigned* __restrict__
         }
 }
 
+
+// ------------------------------ backward from the stored phase, 16 x 16 tiles
+
+// Row of the 32-row chunk that k-slot j (0..7) of lane group g holds in the
+// W^H product of k_freq_bwd_q: 4 g + j, then 16 + 4 g + j - 4 -- the rows whose
+// gU a lane holds after the 16 x 16 lowpass-adjoint products of the chunk's two
+// 16-row halves, and whose stored phase it loads.
+__device__ __forceinline__ int qrow(int g, int j) { return j < 4 ? 4 * g + j : 12 + 4 * g + j; }
+
+// WTq[c][it][p][lane][j] = split(W[l][i] * sw), p = re hi, re lo, im hi, im lo, for
+// i = 16 it + lane % 16 and l = 32 c + qrow(lane / 16, j): the A operand of the
+// 16 x 16 x 32 W^H product, a chunk (KpT x 32) contiguous.  Rows i >= Kp are zero.
+__global__ void k_wtqsplit(const float2* __restrict__ Wl, int Mp, int Kp, int KpT, float sw,
+                           unsigned short* __restrict__ WTq) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)KpT * Mp) return;
+    const int j = (int)(e & 7);
+    const int lane = (int)((e >> 3) & 63);
+    const int64_t r = e >> 9;
+    const int nq = KpT / 16;
+    const int it = (int)(r % nq);
+    const int c = (int)(r / nq);
+    const int i = 16 * it + (lane & 15);
+    const int l = 32 * c + qrow(lane >> 4, j);
+    const float2 w = i < Kp ? Wl[(int64_t)l * Kp + i] : make_float2(0.f, 0.f);
+    _Float16 a, bb, cc, d;
+    split_h(w.x * sw, a, bb);
+    split_h(w.y * sw, cc, d);
+    _Float16* o = (_Float16*)WTq + ((((int64_t)c * nq + it) * 4) * 64 + lane) * 8 + j;
+    o[0] = a; o[512] = bb; o[1024] = cc; o[1536] = d;      // planes 64 lanes x 8 halves apart
+}
+
+// Backward contraction from the stored phase in 16 x 16 tiles: one signal, 16 NW
+// columns t (NW waves of 16), all rows l in 32-row chunks, all NI pairs of
+// 16-row i-tiles accumulated in registers (16 NI of them per lane), so that any
+// K the split forward handles runs in one pass over the phase; with NW = 8 two
+// waves share each SIMD, one's vector work beside the other's matrix work.
+// Per chunk:
+//   gU[l][t] = sum_tau gV[l][tau] Phi[t][tau]       (16 x 16 x 32, both spins, both row halves)
+//   P, Q' from gU and the stored unit phase         (the lane's eight rows of its column)
+//   gY[i][t] += sum_l Wr[l][i] P[l][t] + Wi[l][i] Q'[l][t]
+// The W^T chunk and the split gV are staged in LDS by direct global-to-LDS loads
+// (double-buffered where LDS allows, else gV single-buffered behind a second
+// barrier); the next chunk's phase rows are requested at the chunk's start.
+// LEAN: four waves, single buffers (at most 80 KB of LDS, the gV row scales read
+// from global memory) and two workgroups per CU, whose barriers are independent,
+// so that one workgroup's vector work can run beside the other's products.
+template <int NI, int NW, bool LEAN = false>
+__global__ void __launch_bounds__(64 * NW, LEAN ? 2 : 1) k_freq_bwd_q(const unsigned* __restrict__ phase, int64_t ph_bstride,
+                                                        int Tp, int nTt, int nU,
+                                                        const unsigned short* __restrict__ WTq, int Mp, int Kp,
+                                                        const unsigned short* __restrict__ PhTsp, float sphi,
+                                                        const uint4* __restrict__ Gs, int64_t gs_bstride,
+                                                        const float* __restrict__ gvmax, int n_beta, int alpha,
+                                                        int n_alpha, float sw, float2* __restrict__ gY,
+                                                        int64_t gy_bstride) {
+    constexpr int NTp = 32, NQ = 2 * NI;
+    constexpr int TCH = NI * 512;                     // uint4 per W^T chunk
+    constexpr int GCH = gvs_chunk<1>();               // uint4 per split-gV chunk
+    constexpr bool GDB = !LEAN && (2 * TCH + 2 * GCH) * 16 <= 160 * 1024;   // double-buffered gV
+    constexpr int NT = 64 * NW;
+    constexpr int GST = LEAN ? 512 : GCH;            // staged part of a gV chunk (planes, scales)
+    __shared__ uint4 Ls_T[LEAN ? 1 : 2][TCH];
+    __shared__ uint4 Ls_G[GDB ? 2 : 1][GST];
+    const int u = blockIdx.x;
+    if (u >= nU) return;                              // whole block
+    const int64_t b = u / nTt;
+    const int t0 = (u % nTt) * (16 * NW);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j16 = lane & 15, g4 = lane >> 4;
+    const int t = t0 + wave * 16 + j16;               // this lane's column
+    const int nC = Mp / 32;
+
+    float G = 0.f;
+    for (int q = 0; q < 2 * n_beta; ++q) G = fmaxf(G, gvmax[(b * n_alpha + alpha) * 2 * n_beta + q]);
+    const float spq = pow2_scale(2.f * G * 16384.f / sphi);
+    const float c0 = spq / sphi * kSnormInv;
+
+    floatx4 gyr[NQ], gyi[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) { gyr[q] = z4(); gyi[q] = z4(); }
+
+    // Phi of the lane's column, tau 8 g4 .. 8 g4 + 7: hi and lo planes
+    const uint4* phrow = (const uint4*)(PhTsp + ((int64_t)t * (NTp / 8) + g4) * 16);
+    const half8 fh = as_h8(phrow[0]), fl = as_h8(phrow[1]);
+    const uint4* Gb = Gs + b * gs_bstride;
+    // the lane's phase rows: 4 (g4 % 2) .. of row group g4 / 2 (rows 4 g4 ..) and of
+    // group 2 + g4 / 2 (rows 16 + 4 g4 ..)
+    const unsigned* pbase = phase + b * ph_bstride + (int64_t)t * 8 + 4 * (g4 & 1);
+    const int64_t spin_stride = (int64_t)Tp * Mp, c_stride = (int64_t)Tp * 32, g_stride = (int64_t)Tp * 8;
+    auto load_phase = [&](uint4 (&pv)[2][2], int c) {
+        gptr<uint4> base = launder_v((const uint4*)(pbase + c * c_stride));
+#pragma unroll
+        for (int spin = 0; spin < 2; ++spin)
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf) {
+                gptr<u32x4> p = (gptr<u32x4>)(base + (spin * spin_stride + ((g4 >> 1) + 2 * hf) * g_stride) / 4);
+                pv[spin][hf] = __builtin_bit_cast(uint4, __builtin_nontemporal_load(p));   // read once
+            }
+    };
+    auto stage_T = [&](int c, int slot) {
+        const uint4* src = (const uint4*)WTq + (int64_t)c * TCH;
+        const uint32_t off = (uint32_t)tid * 16u;
+#pragma unroll
+        for (int k = 0; k < TCH / NT; ++k) dma16(src + k * NT, off, &Ls_T[slot][k * NT + wave * 64]);
+    };
+    auto stage_G = [&](int c, int slot) {
+        const uint4* src = Gb + (int64_t)c * GCH;
+        const uint32_t off = (uint32_t)tid * 16u;
+#pragma unroll
+        for (int k = 0; k < 512 / NT; ++k) dma16(src + k * NT, off, &Ls_G[slot][k * NT + wave * 64]);
+        if (!LEAN && tid < 16) dma16(src + 512, off, &Ls_G[slot][512]);
+    };
+    uint4 pv[2][2], pn[2][2];
+    if (!LEAN) {
+        stage_T(0, 0);
+        stage_G(0, 0);
+        load_phase(pv, 0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+    for (int c = 0; c < nC; ++c) {
+        const int slot = LEAN ? 0 : c & 1, gs = GDB ? slot : 0;
+        const bool more = c + 1 < nC;
+        if (LEAN) {
+            // this chunk's operands, waited for at once (the other workgroup on the
+            // CU computes meanwhile)
+            stage_T(c, 0);
+            stage_G(c, 0);
+            load_phase(pv, c);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+        if (GDB && more) {
+            stage_T(c + 1, slot ^ 1);
+            stage_G(c + 1, slot ^ 1);
+            load_phase(pn, c + 1);
+        }
+        // gU of the chunk's rows 16 hf + 4 g4 + r at column t, scaled per row
+        floatx4 gu[2][2];
+        {
+            const uint4* Lg = Ls_G[gs];
+            const float* rs = (const float*)(Lg + 512);
+#pragma unroll
+            for (int spin = 0; spin < 2; ++spin)
+#pragma unroll
+                for (int hf = 0; hf < 2; ++hf) {
+                    const int base = (((spin * 2 + (g4 >> 1)) * 2) * 2 + (g4 & 1)) * 32 + 16 * hf + j16;
+                    const half8 ah = as_h8(Lg[base]), al = as_h8(Lg[base + 64]);
+                    floatx4 acc = z4();
+                    acc = mfma16q(ah, fh, acc);
+                    acc = mfma16q(ah, fl, acc);
+                    acc = mfma16q(al, fh, acc);
+                    const float4 q = LEAN ? *(const float4*)((const float*)(Gb + (int64_t)c * GCH + 512) + spin * 32 +
+                                                             16 * hf + 4 * g4)
+                                          : *(const float4*)(rs + spin * 32 + 16 * hf + 4 * g4);
+                    acc[0] *= q.x * c0; acc[1] *= q.y * c0; acc[2] *= q.z * c0; acc[3] *= q.w * c0;
+                    gu[spin][hf] = acc;
+                }
+        }
+        if (!GDB && !LEAN) {
+            __syncthreads();                       // every wave has read the staged gV
+            if (more) {
+                stage_T(c + 1, slot ^ 1);
+                stage_G(c + 1, 0);
+                load_phase(pn, c + 1);
+            }
+        }
+        // modulus adjoint: P = gZ_up + gZ_down, Q' = i (gZ_down - gZ_up), gZ = gU u, for
+        // k-slot s = 4 hf + r (row qrow(g4, s)); planes q = P re, P im, Q' re, Q' im
+        half8 bh[4], bl[4];
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+            for (int pr = 0; pr < 2; ++pr) {
+                float vals[2][4];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int r = 2 * pr + e;
+                    const unsigned wu = r == 0 ? pv[0][hf].x : r == 1 ? pv[0][hf].y : r == 2 ? pv[0][hf].z : pv[0][hf].w;
+                    const unsigned wd = r == 0 ? pv[1][hf].x : r == 1 ? pv[1][hf].y : r == 2 ? pv[1][hf].z : pv[1][hf].w;
+                    const float ux = (float)(int)(short)(wu & 0xffffu), uy = (float)((int)wu >> 16);
+                    const float dx = (float)(int)(short)(wd & 0xffffu), dy = (float)((int)wd >> 16);
+                    const float su = gu[0][hf][r], sd = gu[1][hf][r];
+                    vals[e][0] = su * ux + sd * dx;
+                    vals[e][1] = su * uy + sd * dy;
+                    vals[e][2] = su * uy - sd * dy;
+                    vals[e][3] = sd * dx - su * ux;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    unsigned hp, lp;
+                    split2(vals[0][q], vals[1][q], hp, lp);
+                    const int w = 2 * hf + pr;                 // 32-bit word of the plane: slots 2 w, 2 w + 1
+                    uint4 hv = __builtin_bit_cast(uint4, bh[q]), lv = __builtin_bit_cast(uint4, bl[q]);
+                    if (w == 0) { hv.x = hp; lv.x = lp; }
+                    else if (w == 1) { hv.y = hp; lv.y = lp; }
+                    else if (w == 2) { hv.z = hp; lv.z = lp; }
+                    else { hv.w = hp; lv.w = lp; }
+                    bh[q] = __builtin_bit_cast(half8, hv);
+                    bl[q] = __builtin_bit_cast(half8, lv);
+                }
+            }
+        // gY += W^T P (real and imaginary parts of P, Q')
+        {
+            const uint4* Lt = Ls_T[slot] + lane;
+#pragma unroll
+            for (int it = 0; it < NQ; ++it) {
+                const half8 wrh = as_h8(Lt[(it * 4 + 0) * 64]), wrl = as_h8(Lt[(it * 4 + 1) * 64]);
+                const half8 wih = as_h8(Lt[(it * 4 + 2) * 64]), wil = as_h8(Lt[(it * 4 + 3) * 64]);
+                gyr[it] = mfma16q(wrh, bh[0], gyr[it]); gyi[it] = mfma16q(wrh, bh[1], gyi[it]);
+                gyr[it] = mfma16q(wrh, bl[0], gyr[it]); gyi[it] = mfma16q(wrh, bl[1], gyi[it]);
+                gyr[it] = mfma16q(wrl, bh[0], gyr[it]); gyi[it] = mfma16q(wrl, bh[1], gyi[it]);
+                gyr[it] = mfma16q(wih, bh[2], gyr[it]); gyi[it] = mfma16q(wih, bh[3], gyi[it]);
+                gyr[it] = mfma16q(wih, bl[2], gyr[it]); gyi[it] = mfma16q(wih, bl[3], gyi[it]);
+                gyr[it] = mfma16q(wil, bh[2], gyr[it]); gyi[it] = mfma16q(wil, bh[3], gyi[it]);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (!LEAN && more) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) { pv[s][0] = pn[s][0]; pv[s][1] = pn[s][1]; }
+        }
+    }
+    const float inv = 1.f / (sw * spq);
+    float2* o = gY + b * gy_bstride;
+#pragma unroll
+    for (int it = 0; it < NQ; ++it)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * it + 4 * g4 + r;
+            if (i < Kp) o[(int64_t)i * Tp + t] = make_float2(gyr[it][r] * inv, gyi[it][r] * inv);
+        }
+}
+
 }  // namespace jtfs
 
 using namespace jtfs;
@@ -1520,6 +1756,14 @@ int build_split_tables(jtfs_plan* P, std::vector<void*>& owned) {
         const int64_t n = (int64_t)s.Tp[a] * s.NTp;
         hipLaunchKernelGGL(k_phtsplit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, P->Phi + s.phioff[a],
                            s.Tp[a], s.NTp, P->sphi[a], P->PhTsp + s.phioff[a] * 2);
+    }
+    if (s.NTp == 32) {
+        // the W^T operand of the 16 x 16-tile stored-phase backward
+        P->WTq = (unsigned short*)alloc(sizeof(float2) * (size_t)P->KpT * s.Mp);
+        if (!P->WTq) { set_error("device allocation failed"); return JTFS_ENOMEM; }
+        const int64_t n = (int64_t)P->KpT * s.Mp;
+        hipLaunchKernelGGL(k_wtqsplit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, P->Wl, s.Mp, s.Kp, P->KpT,
+                           P->sw, P->WTq);
     }
     if (s.NTp == 32) {
         // the lowpass operand of the 16 x 16-tile forward
@@ -1753,10 +1997,59 @@ int launch_gv_split(const jtfs_plan* P, const float* gV, uint4* Gs, int64_t B, h
     return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
 }
 
+// waves per workgroup of the 16 x 16-tile stored-phase backward: eight (two per
+// SIMD) where the accumulators of NI i-tile pairs leave room, else four
+int bwdq_waves(int NI) { return NI <= 8 ? 8 : 4; }
+
+bool bwdq_supported(const jtfs_plan* P) {
+    const int NI = P->KpT / 32;
+    return P->WTq && P->s.NTp == 32 && NI >= 1 && NI <= 9;          // LDS: two W^T chunks of NI x 8 KB
+}
+
+template <int NI = 1>
+static void launch_bwdq_ni(int ni, int nw, unsigned nU, hipStream_t st, const unsigned* pha, int64_t phb, int Tp,
+                           int nTt, const jtfs_plan* P, const unsigned short* PhT, float sphi, const uint4* Gsa,
+                           int64_t gsb, const float* gvmax, int a, float2* gYa, int64_t gyb) {
+    if constexpr (NI <= 9) {
+        if (ni != NI) {
+            launch_bwdq_ni<NI + 1>(ni, nw, nU, st, pha, phb, Tp, nTt, P, PhT, sphi, Gsa, gsb, gvmax, a, gYa, gyb);
+            return;
+        }
+        const Shapes& s = P->s;
+        if (nw == 2 * 4 + 1) {             // four waves, two workgroups per CU
+            if constexpr (NI <= 9)
+                hipLaunchKernelGGL((k_freq_bwd_q<NI, 4, true>), dim3(nU), dim3(256), 0, st, pha, phb, Tp, nTt,
+                                   (int)nU, P->WTq, s.Mp, s.Kp, PhT, sphi, Gsa, gsb, gvmax, s.n_beta, a, s.n_alpha,
+                                   P->sw, gYa, gyb);
+        } else if (nw == 8) {
+            if constexpr (NI <= 8)
+                hipLaunchKernelGGL((k_freq_bwd_q<NI, 8>), dim3(nU), dim3(512), 0, st, pha, phb, Tp, nTt, (int)nU,
+                                   P->WTq, s.Mp, s.Kp, PhT, sphi, Gsa, gsb, gvmax, s.n_beta, a, s.n_alpha, P->sw, gYa,
+                                   gyb);
+        } else {
+            hipLaunchKernelGGL((k_freq_bwd_q<NI, 4>), dim3(nU), dim3(256), 0, st, pha, phb, Tp, nTt, (int)nU, P->WTq,
+                               s.Mp, s.Kp, PhT, sphi, Gsa, gsb, gvmax, s.n_beta, a, s.n_alpha, P->sw, gYa, gyb);
+        }
+    }
+}
+
 int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int64_t ph_bstride, const uint4* Gs,
                           int64_t gs_bstride, const float* gvmax, float2* gY2, int64_t B, hipStream_t st) {
     const Shapes& s = P->s;
     const int NI = P->KpT / 32;
+    if (P->tune.bwd16 && bwdq_supported(P)) {
+        const int nw = bwdq_waves(NI);
+        const int nTt = s.Tp[a] / (16 * nw);
+        const unsigned nU = (unsigned)(B * nTt);
+        const int64_t yb = (int64_t)s.Kp * s.sumTp;
+        const unsigned* pha = phase + (int64_t)2 * s.Mp * (s.yoff[a] / s.Kp);
+        const unsigned short* PhT = P->PhTsp + s.phioff[a] * 2;
+        const uint4* Gsa = Gs + (int64_t)a * (s.Mp / 32) * (512 * (s.NTp / 32) + 16);
+        JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,
+                   launch_bwdq_ni(NI, nw, nU, st, pha, ph_bstride, s.Tp[a], nTt, P, PhT, P->sphi[a], Gsa, gs_bstride,
+                                  gvmax, a, gY2 + s.yoff[a], yb));
+        return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
+    }
     if (!P->split_bwdp_ok) { set_error("stored-phase backward not available for these shapes"); return JTFS_ENOTSUP; }
     // one launch per range of i-blocks: a single one up to the register budget, else
     // two balanced halves

@@ -26,4 +26,6 @@ int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int6
 int launch_gv_split(const jtfs_plan* P, const float* gV, uint4* Gs, int64_t B, hipStream_t st);
 // whether the 16 x 16-tile forward contraction handles the plan's shapes
 bool fwdq_supported(const jtfs_plan* P, bool with_phase);
+// whether the 16 x 16-tile stored-phase backward handles the plan's shapes
+bool bwdq_supported(const jtfs_plan* P);
 }  // namespace jtfs

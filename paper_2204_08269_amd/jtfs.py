@@ -129,6 +129,7 @@ class JTFS:
     # launch choices --------------------------------------------------------
     REG_BITS = {"scalogram": 1, "second_order": 2, "row_fft": 4, "first_adj": 8}
     FWD_TILE16 = 16
+    BWD_TILE16 = 32
 
     def autotune(self, B, x=None, reps=3):
         """Times the candidate launch choices for B signals (x: [B, N] on the
@@ -141,26 +142,29 @@ class JTFS:
         return {"contraction": self.contraction,
                 "register_rows": [k for k, v in self.REG_BITS.items() if t.reg_rows & v],
                 "fwd_tile": 16 if t.reg_rows & self.FWD_TILE16 else 32,
+                "bwd_tile": 16 if t.reg_rows & self.BWD_TILE16 else 32,
                 "step_ms": t.step_ms, "from_cache": bool(t.from_cache),
                 "fwd_ms": {"tile32": t.fwd_ms[0], "tile16": t.fwd_ms[1]},
+                "bwd_ms": {"tile32": t.bwd_ms[0], "tile16": t.bwd_ms[1]},
                 "candidates_ms": {"split16_register": t.candidates_ms[0], "split16_lds": t.candidates_ms[1],
                                   "fp32_register": t.candidates_ms[2], "fp32_lds": t.candidates_ms[3],
                                   "split16_phase_register": t.candidates_ms[4],
                                   "split16_phase_lds": t.candidates_ms[5]}}
 
-    def set_tuning(self, contraction, register_rows, fwd_tile=32):
+    def set_tuning(self, contraction, register_rows, fwd_tile=32, bwd_tile=32):
         mode = _lib.CONTRACTIONS[contraction]
-        mask = sum(self.REG_BITS[k] for k in register_rows) | (self.FWD_TILE16 if fwd_tile == 16 else 0)
+        mask = (sum(self.REG_BITS[k] for k in register_rows) | (self.FWD_TILE16 if fwd_tile == 16 else 0) |
+                (self.BWD_TILE16 if bwd_tile == 16 else 0))
         _lib.check(self.lib.jtfs_plan_set_tuning(self.plan, mode, mask))
         self.contraction = contraction
         self._ws = {}
 
     def tuning(self):
-        """(contraction, register rows, forward tile) now set on the plan."""
+        """(contraction, register rows, forward tile, backward tile) now set on the plan."""
         m, r = ctypes.c_int(0), ctypes.c_int(0)
         _lib.check(self.lib.jtfs_plan_get_tuning(self.plan, ctypes.byref(m), ctypes.byref(r)))
         return (_mode_name(m.value), [k for k, v in self.REG_BITS.items() if r.value & v],
-                16 if r.value & self.FWD_TILE16 else 32)
+                16 if r.value & self.FWD_TILE16 else 32, 16 if r.value & self.BWD_TILE16 else 32)
 
     # mu-log renormalisation (sec. 4) -------------------------------------
     def _check_s(self, s1, s2):

@@ -22,6 +22,7 @@ def gpu_op(p, contraction=None, average_fr=True, time_scattering=False):
 
 
 MODES = ["fp32", "split16"]
+ALL_ROWS = ["scalogram", "second_order", "row_fft", "first_adj"]      # register-resident rows of 2^14 points
 
 
 def run_forward(op, x):
@@ -356,9 +357,10 @@ def cfg5_reference():
     return CFG5_REF
 
 
-@pytest.mark.parametrize("mode,tile", [("fp32", 32), ("split16", 32), ("split16_phase", 32), ("split16", 16),
-                                       ("split16_phase", 16)])
-def test_cfg5_s2_and_gradient_match_oracle(mode, tile):
+@pytest.mark.parametrize("mode,tile,btile", [("fp32", 32, 32), ("split16", 32, 32), ("split16_phase", 32, 32),
+                                             ("split16", 16, 32), ("split16_phase", 16, 16),
+                                             ("split16_phase", 32, 16)])
+def test_cfg5_s2_and_gradient_match_oracle(mode, tile, btile):
     """32 x 2^18 FM mixtures (n1 = 285: K = 288, 18 k-steps of the split forward,
     9 i-blocks of the backward), in the launch configuration of the benchmark
     (the whole batch): every S1 path and every (beta, theta) path of S2 at the
@@ -367,14 +369,15 @@ def test_cfg5_s2_and_gradient_match_oracle(mode, tile):
     signal 0 for a cotangent on S1 and those rates against the oracle's VJP,
     after a forward on the same workspace (the stored-phase mode reads the
     phase it kept) and without one (that mode then takes the phase again);
-    both tiles of the split forward."""
+    both tiles of the split forward and of the stored-phase backward (whose
+    16 x 16 kernel holds the nine 32-row i-blocks in one pass)."""
     p = synth.PARAMS[5]
     ref = cfg5_reference()
     x = ref["x"]
     alphas = [int(a) for a in ref["alphas"]]
     op = gpu_op(p, mode)
     assert op.contraction == mode
-    op.set_tuning(mode, ["scalogram", "second_order", "row_fft", "first_adj"], fwd_tile=tile)
+    op.set_tuning(mode, ALL_ROWS, fwd_tile=tile, bwd_tile=btile)
     B = x.shape[0]
     xt = torch.from_numpy(x).cuda()
     ws = op.new_workspace(B)
@@ -613,9 +616,12 @@ PHASE_SHAPES = [P1, RAGGED[0], RAGGED[1], RAGGED[2], RAGGED[3],
                 dict(N=4096, J=8, Q=(32, 1), J_fr=3, Q_fr=1, T=256, F=2)]    # n1 = 175: 6 i-blocks
 
 
+@pytest.mark.parametrize("bwd_tile", [32, 16])
 @pytest.mark.parametrize("average_fr", [True, False])
 @pytest.mark.parametrize("p", PHASE_SHAPES, ids=lambda p: f"N{p['N']}_T{p['T']}_Q{p['Q'][0]}")
-def test_stored_phase_vjp_matches_oracle(p, average_fr):
+def test_stored_phase_vjp_matches_oracle(p, average_fr, bwd_tile):
+    """(32 x 32 or 16 x 16 tiles of the stored-phase backward; the latter only
+    where N/T <= 32, the former elsewhere.)"""
     P = oracle_plan(p)
     B = 3
     rng = np.random.default_rng(606 + p["N"] + p["T"])
@@ -627,6 +633,8 @@ def test_stored_phase_vjp_matches_oracle(p, average_fr):
     for mode in ("split16", "split16_phase"):
         op = gpu_op(p, mode, average_fr=average_fr)
         assert op.contraction == mode
+        if mode == "split16_phase":
+            op.set_tuning(mode, ALL_ROWS, bwd_tile=bwd_tile)
         ws = op.new_workspace(B)
         s1, s2 = op.forward(xt, ws)
         g = op.vjp(xt, gt1, gt2, ws=ws, reuse_forward=True)
@@ -695,15 +703,15 @@ def test_autotune_then_every_row_choice_matches_oracle():
     c = choice["candidates_ms"]
     assert c["split16_register"] > 0 and c["fp32_register"] > 0 and c["split16_phase_register"] > 0
     assert c["split16_lds"] > 0 and choice["fwd_ms"]["tile16"] > 0
-    assert op.tuning() == (choice["contraction"], choice["register_rows"], choice["fwd_tile"])
+    assert op.tuning() == (choice["contraction"], choice["register_rows"], choice["fwd_tile"], choice["bwd_tile"])
     gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape(), seed=31)
     refs = [(O.jtfs(x[b].astype(np.float64), P),
              O.jtfs_vjp(x[b].astype(np.float64), gs1[b].astype(np.float64), gs2[b].astype(np.float64), P))
             for b in range(2)]
     for mode in MODES + ["split16_phase"]:
-        for rows, tile in (([], 16), (["scalogram", "second_order", "row_fft", "first_adj"], 32),
-                           (["scalogram", "row_fft"], 16), (["second_order", "first_adj"], 32)):
-            op.set_tuning(mode, rows, fwd_tile=tile)
+        for rows, tile, btile in (([], 16, 16), (ALL_ROWS, 32, 32), (["scalogram", "row_fft"], 16, 32),
+                                  (["second_order", "first_adj"], 32, 16)):
+            op.set_tuning(mode, rows, fwd_tile=tile, bwd_tile=btile)
             ws = op.new_workspace(2)
             s1, s2 = op.forward(xt, ws)
             g = op.vjp(xt, torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda(), ws=ws,
@@ -712,7 +720,7 @@ def test_autotune_then_every_row_choice_matches_oracle():
             for b in range(2):
                 (r1, r2), rg = refs[b]
                 check_paths(g1[b], g2[b], r1, r2)
-                assert rel_l2(g[b], rg) <= TOL_VJP, (mode, rows, tile)
+                assert rel_l2(g[b], rg) <= TOL_VJP, (mode, rows, tile, btile)
 
 
 def test_autotune_cache_reuses_the_choice(tmp_path, monkeypatch):
@@ -726,9 +734,9 @@ def test_autotune_cache_reuses_the_choice(tmp_path, monkeypatch):
     op = gpu_op(P1)
     second = op.autotune(2, xt, reps=1)
     assert second["from_cache"]
-    for k in ("contraction", "register_rows", "fwd_tile"):
+    for k in ("contraction", "register_rows", "fwd_tile", "bwd_tile"):
         assert second[k] == first[k], k
-    assert op.tuning() == (first["contraction"], first["register_rows"], first["fwd_tile"])
+    assert op.tuning() == (first["contraction"], first["register_rows"], first["fwd_tile"], first["bwd_tile"])
     # another batch size is another key
     third = op.autotune(3, torch.from_numpy(synth.batch(1, B=3)).cuda(), reps=1)
     assert not third["from_cache"]
