@@ -163,15 +163,19 @@ def algorithmic_bytes(info, N, shapes, B):
 # HBM bytes per launch of a stage's kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes (scaled by the same counters on a copy of known size), kept beside the
 # profiles with the hash of the kernel's source; stale once that source changes.
-TRAFFIC_KERNELS = {("freq_fwd", "split16"): "k_freq_fwd_h", ("freq_adj_pq", "split16"): "k_freq_bwd_h",
-                   ("freq_fwd", "split16_phase"): "k_freq_fwd_h_phase",
-                   ("freq_adj_pq", "split16_phase"): "k_freq_bwd_p"}
+# Keyed by (stage, contraction mode, tile of that stage's kernel).
+TRAFFIC_KERNELS = {("freq_fwd", "split16", 32): "k_freq_fwd_h", ("freq_adj_pq", "split16", 32): "k_freq_bwd_h",
+                   ("freq_fwd", "split16_phase", 32): "k_freq_fwd_h_phase",
+                   ("freq_adj_pq", "split16_phase", 32): "k_freq_bwd_p",
+                   ("freq_fwd", "split16", 16): "k_freq_fwd_q",
+                   ("freq_fwd", "split16_phase", 16): "k_freq_fwd_q_phase",
+                   ("freq_adj_pq", "split16_phase", 16): "k_freq_bwd_q"}
 TRAFFIC_SOURCE = "paper_2204_08269_amd/csrc/split.hip"
 
 
-def measured_traffic(stage, contraction, tag):
+def measured_traffic(stage, contraction, tile, tag):
     import hashlib
-    kern = TRAFFIC_KERNELS.get((stage, contraction))
+    kern = TRAFFIC_KERNELS.get((stage, contraction, tile))
     if kern is None:
         return None
     rec_path = os.path.join(HERE, "profiles", f"{kern}_{tag}_hbm_traffic.json")
@@ -279,7 +283,11 @@ def run_workload(torch, dev, cfg, args, extras=True, stage_pass=True):
         tuning = op.autotune(B, x, reps=2)      # launch choices for this GPU and batch (before the workspace)
         torch.cuda.synchronize()
         print(f"[bench] cfg {cfg} autotune: {tuning['contraction']}, register rows {tuning['register_rows']}, "
-              f"{tuning['step_ms']:.2f} ms/step", file=sys.stderr, flush=True)
+              f"tiles {tuning['fwd_tile']}/{tuning['bwd_tile']}, {tuning['step_ms']:.2f} ms/step", file=sys.stderr,
+              flush=True)
+    elif args.fwd_tile or args.bwd_tile:
+        mode, rows, ft, bt = op.tuning()
+        op.set_tuning(mode, rows, fwd_tile=args.fwd_tile or ft, bwd_tile=args.bwd_tile or bt)
     ws = op.new_workspace(B)
 
     def step():
@@ -300,7 +308,7 @@ def run_workload(torch, dev, cfg, args, extras=True, stage_pass=True):
     print(f"[bench] cfg {cfg}: {args.steps} timed steps, {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
     res = {"cfg": cfg, "B": B, "N": p["N"], "op": op, "x": x, "ws": ws, "s1": s1, "s2": s2, "gx": gx,
            "ms_per_step": ms_per_step, "value": samples / (ms_per_step * 1e-3) / 1e6, "tuning": tuning,
-           "contraction": op.contraction, "Po": Po}
+           "contraction": op.contraction, "Po": Po, "tiles": tuple(op.tuning()[2:])}
     if stage_pass:
         _lib.timing_read()                       # clear
         _lib.timing_enable(True)
@@ -374,9 +382,10 @@ def rooflines(res, steps):
     dom = max(out, key=lambda k: stages[k][0])
     dom_ms, dom_n = stages[dom]
     roof = dict(out[dom])
-    traffic = measured_traffic(dom, mode, WORKLOADS[res["cfg"]]["tag"])
+    tile = res["tiles"][0] if dom == "freq_fwd" else res["tiles"][1]
+    traffic = measured_traffic(dom, mode, tile, WORKLOADS[res["cfg"]]["tag"])
     per_step = max(dom_n // steps, 1)
-    roof.update({"kernel": dom, "traffic": traffic["bytes_per_launch"] if traffic else None,
+    roof.update({"kernel": dom, "tile": tile, "traffic": traffic["bytes_per_launch"] if traffic else None,
                  "traffic_detail": traffic, "launches_per_step": per_step,
                  "avg_launch_ms": round(dom_ms / max(dom_n, 1), 4),
                  "per_launch_algorithmic": (flops[dom] if dom in flops else nbytes[dom]) // per_step,
@@ -400,6 +409,10 @@ def main():
                     help="run one 1 GiB device copy first (calibrates HBM byte counters)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the plan's default launch choices (no autotuning before the timed steps)")
+    ap.add_argument("--fwd-tile", type=int, choices=[16, 32], default=None,
+                    help="with --no-autotune: MFMA tile of the split forward contraction")
+    ap.add_argument("--bwd-tile", type=int, choices=[16, 32], default=None,
+                    help="with --no-autotune: MFMA tile of the stored-phase backward")
     ap.add_argument("--no-extras", action="store_true",
                     help="time the fwd+bwd step only (no event pass, forward-only, second-workload or ragged legs)")
     args = ap.parse_args()

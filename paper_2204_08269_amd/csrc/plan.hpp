@@ -145,6 +145,7 @@ struct jtfs_plan {
     unsigned short* PhTsp = nullptr; // per alpha [Tp][NTp/8][2][8]: Phi * sphi[alpha], tau contiguous
     unsigned short* Phq = nullptr;   // per alpha [Tp/16][NTp/16][64][2][4]: Phi * sphi[alpha] (N/T <= 32)
     unsigned short* WTq = nullptr;   // [Mp/32][KpT/16][4][64][8]: W^T * sw in the 16 x 16 backward's k order
+    unsigned short* Wq = nullptr;    // [Mp/64][ceil(Kp/32)][4][4][64][8]: W * sw in the 16 x 16 forward's read order
     std::vector<float> sphi;
     void* owned = nullptr;         // list of device allocations released by destroy
 };

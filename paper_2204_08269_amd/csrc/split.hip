@@ -523,11 +523,35 @@ __global__ void k_phqsplit(const float* __restrict__ Phi, int Tp, int NTp, float
     o[4] = lo;
 }
 
-// LDS of k_freq_fwd_q: the resident W rows and a 16 x 20-word phase transpose
-// area per wave, then the cross-wave reduction of V (8 waves x NTQ x 4 row blocks
-// x 2 spins x 64 lanes x 4 floats).
+// Wq[lt][ks][lb][p][lane][j] = split(W[l][k] * sw), p = re hi, re lo, im hi, im lo,
+// for l = 64 lt + 16 lb + lane % 16 and k = 32 ks + 8 (lane / 16) + j; zero for
+// k >= Kp.  The A operands of the 16 x 16 x 32 forward products of a 64-row tile in
+// the order in which the lanes read them: each fragment is 64 consecutive 16-byte
+// slots, which an LDS read takes without bank conflicts.
+__global__ void k_wqsplit(const float2* __restrict__ Wl, int Mp, int Kp, int NS, float sw,
+                          unsigned short* __restrict__ Wq) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)Mp * NS * 128) return;        // Mp / 64 tiles x NS k-steps x 8192 halves
+    const int j = (int)(e & 7);
+    const int lane = (int)((e >> 3) & 63);
+    const int p = (int)((e >> 9) & 3);
+    const int lb = (int)((e >> 11) & 3);
+    const int64_t r = e >> 13;
+    const int ks = (int)(r % NS);
+    const int lt = (int)(r / NS);
+    const int l = 64 * lt + 16 * lb + (lane & 15);
+    const int k = 32 * ks + 8 * (lane >> 4) + j;
+    const float2 w = k < Kp ? Wl[(int64_t)l * Kp + k] : make_float2(0.f, 0.f);
+    _Float16 hi, lo;
+    split_h((p < 2 ? w.x : w.y) * sw, hi, lo);
+    ((_Float16*)Wq)[e] = (p & 1) ? lo : hi;
+}
+
+// LDS of k_freq_fwd_q: the resident W tile (16 KB per k-step of 32) and a
+// 16 x 20-word phase transpose area per wave, then the cross-wave reduction of V
+// (8 waves x NTQ x 4 row blocks x 2 spins x 64 lanes x 4 floats).
 constexpr size_t fwdq_lds(int Kp, int NTQ, bool with_phase) {
-    const size_t main_loop = (size_t)64 * (Kp * 8 + 16) + (with_phase ? (size_t)8 * 16 * 20 * 4 : 0);
+    const size_t main_loop = (size_t)((Kp / 16 + 1) / 2) * 16384 + (with_phase ? (size_t)8 * 16 * 20 * 4 : 0);
     const size_t reduction = (size_t)8 * NTQ * 4 * 2 * 64 * 4 * sizeof(float);
     return main_loop > reduction ? main_loop : reduction;
 }
@@ -546,7 +570,7 @@ constexpr size_t fwdq_lds(int Kp, int NTQ, bool with_phase) {
 template <int NK, int NTQ>
 __global__ void __launch_bounds__(512) k_freq_fwd_q(const unsigned short* __restrict__ Yh, int64_t yh_bstride, int Tp,
                                                     int chunk, int nch, int nU, int nlt,
-                                                    const unsigned short* __restrict__ Wsp,
+                                                    const unsigned short* __restrict__ Wq,
                                                     const unsigned short* __restrict__ Phq, float unscale_wphi,
                                                     const float* __restrict__ yscale, int alpha, int n_alpha,
                                                     float* __restrict__ Vp, int64_t vp_bstride, int slot0,
@@ -555,7 +579,6 @@ __global__ void __launch_bounds__(512) k_freq_fwd_q(const unsigned short* __rest
     constexpr int Kp = 16 * NK;
     constexpr int NS = (NK + 1) / 2;         // k-steps of 32
     constexpr bool TAIL = (NK & 1) != 0;     // the last k-step holds 16 k (k-groups 0, 1)
-    constexpr int WS = Kp * 8 + 16;          // bytes per resident W row
     constexpr int NR = NS < 2 ? NS : 2;      // Y ring depth (k-steps)
     extern __shared__ __align__(16) unsigned char lds[];
 
@@ -569,14 +592,12 @@ __global__ void __launch_bounds__(512) k_freq_fwd_q(const unsigned short* __rest
     const int j16 = lane & 15, g4 = lane >> 4;
     constexpr int nkb = Kp / 8;
 
-    // resident W rows l0 .. l0+63
+    // resident W tile of rows l0 .. l0+63, in read order (NS x 1024 slots)
     {
-        const uint4* src = (const uint4*)(Wsp + (int64_t)lt * 64 * Kp * 4);
-        constexpr int per_row = Kp / 2;      // uint4 per row
-        for (int e = tid; e < 64 * per_row; e += 512) {
-            const int r = e / per_row, c = e - r * per_row;
-            *(uint4*)(lds + r * WS + c * 16) = src[e];
-        }
+        const uint4* src = (const uint4*)Wq + (int64_t)lt * NS * 1024;
+        uint4* dst = (uint4*)lds;
+#pragma unroll
+        for (int e = 0; e < 2 * NS; ++e) dst[e * 512 + tid] = src[e * 512 + tid];
     }
     const unsigned short* Yb = Yh + b * yh_bstride;
     float eps2s = 0.f;
@@ -592,10 +613,10 @@ __global__ void __launch_bounds__(512) k_freq_fwd_q(const unsigned short* __rest
     __syncthreads();                         // resident W complete
 
     // this lane's W fragments: row 16 lb + j16, k-group 4 ks + g4, plane p
-    const unsigned char* wrow = lds + j16 * WS + g4 * 64;
+    const uint4* wfr = (const uint4*)lds + lane;
     auto load_w = [&](uint4 (&w)[4], int ks, int lb) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) w[p] = *(const uint4*)(wrow + lb * 16 * WS + ks * 256 + p * 16);
+        for (int p = 0; p < 4; ++p) w[p] = wfr[((ks * 4 + lb) * 4 + p) * 64];
     };
     // this lane's Y fragments: column t, k-group 4 ks + g4, plane p (uint4 units)
     const int tbeg = ch * chunk, tend = (ch + 1) * chunk;
@@ -613,7 +634,7 @@ __global__ void __launch_bounds__(512) k_freq_fwd_q(const unsigned short* __rest
     gptr<uint4> yc = ycol_at(tbeg);
 #pragma unroll
     for (int s = 0; s < NR; ++s) load_yq(yr[s], yc, s);
-    unsigned* tb = (unsigned*)(lds + 64 * WS) + wave * (16 * 20);   // phase transpose area
+    unsigned* tb = (unsigned*)(lds + NS * 16384) + wave * (16 * 20);   // phase transpose area
     for (int t0 = tbeg; t0 < tend; t0 += kTileTh) {
         const int t16 = (t0 >> 4) + wave;
         // Phi fragments of this tile (A operand of the lowpass product)
@@ -629,7 +650,6 @@ __global__ void __launch_bounds__(512) k_freq_fwd_q(const unsigned short* __rest
 #pragma unroll
         for (int ks = 0; ks < NS; ++ks) {
             uint4(&q)[4] = yr[ks % NR];
-            const bool tail_step = TAIL && ks == NS - 1;
             const half8 y0 = as_h8(q[0]), y1 = as_h8(q[1]), y2 = as_h8(q[2]), y3 = as_h8(q[3]);
 #pragma unroll
             for (int lb = 0; lb < 4; ++lb) {
@@ -638,10 +658,8 @@ __global__ void __launch_bounds__(512) k_freq_fwd_q(const unsigned short* __rest
                 if (lb + 1 < 4) load_w(wn, ks, lb + 1);
                 else if (ks + 1 < NS) load_w(wn, ks + 1, 0);
                 __builtin_amdgcn_sched_barrier(0);
-                uint4 wv[4];
-#pragma unroll
-                for (int p = 0; p < 4; ++p) wv[p] = tail_step && g4 >= 2 ? make_uint4(0, 0, 0, 0) : wc[p];
-                const half8 w0 = as_h8(wv[0]), w1 = as_h8(wv[1]), w2 = as_h8(wv[2]), w3 = as_h8(wv[3]);
+                // (the tile holds zeros beyond Kp, so a short last k-step needs no mask)
+                const half8 w0 = as_h8(wc[0]), w1 = as_h8(wc[1]), w2 = as_h8(wc[2]), w3 = as_h8(wc[3]);
                 // the four accumulators in turn, so that no product waits for the one
                 // before it (each keeps its own summation order)
                 rr[lb] = mfma16q(y0, w0, rr[lb]); ir[lb] = mfma16q(y2, w0, ir[lb]);
@@ -1483,46 +1501,226 @@ __global__ void k_wtqsplit(const float2* __restrict__ Wl, int Mp, int Kp, int Kp
     o[0] = a; o[512] = bb; o[1024] = cc; o[1536] = d;      // planes 64 lanes x 8 halves apart
 }
 
-// Backward contraction from the stored phase in 16 x 16 tiles: one signal, 16 NW
-// columns t (NW waves of 16), all rows l in 32-row chunks, all NI pairs of
-// 16-row i-tiles accumulated in registers (16 NI of them per lane), so that any
-// K the split forward handles runs in one pass over the phase; with NW = 8 two
-// waves share each SIMD, one's vector work beside the other's matrix work.
+// Power-of-two scales of the lane's gV rows of one 32-row chunk, per spin and
+// 16-row half: rows 16 hf + 4 g4 .. + 3.  Read straight from the split-gV table;
+// the chunk's address goes through launder_v, so that the compiler issues these
+// loads where they stand instead of repeating them next to their uses, where
+// they would wait behind the global-to-LDS copies.
+struct GvScaleQ {
+    float4 q[2][2];       // [spin][hf]
+};
+__device__ __forceinline__ void bwdq_load_scales(GvScaleQ& g, const uint4* Gb, int c, int g4) {
+    gptr<uint4> Lg = launder_v(Gb + (int64_t)c * gvs_chunk<1>() + 512);
+#pragma unroll
+    for (int spin = 0; spin < 2; ++spin)
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf)
+            g.q[spin][hf] = __builtin_bit_cast(float4, ((gptr<u32x4>)Lg)[spin * 8 + 4 * hf + g4]);
+}
+
+// One lowpass-adjoint product: gU of rows 16 hf + 4 g4 + r at the lane's column
+// from the split gV rows of the chunk staged in Lg (unscaled; the row scales are
+// applied by the modulus adjoint).
+__device__ __forceinline__ floatx4 bwdq_gu(const uint4* Lg, int g4, int j16, int spin, int hf, half8 fh, half8 fl) {
+    const int base = (((spin * 2 + (g4 >> 1)) * 2) * 2 + (g4 & 1)) * 32 + 16 * hf + j16;
+    const half8 ah = as_h8(Lg[base]), al = as_h8(Lg[base + 64]);
+    floatx4 acc = z4();
+    acc = mfma16q(ah, fh, acc);
+    acc = mfma16q(ah, fl, acc);
+    acc = mfma16q(al, fh, acc);
+    return acc;
+}
+
+// Modulus adjoint of the rows 16 hf + 4 g4 + 2 pr, + 1 (k-slots 4 hf + 2 pr, + 1):
+// P = gZ_up + gZ_down, Q' = i (gZ_down - gZ_up) with gZ = gU u from the stored unit
+// phase, split into FP16 hi / lo; word 2 hf + pr of the B planes (P re, P im, Q' re,
+// Q' im).
+__device__ __forceinline__ void bwdq_modadj(int hf, int pr, const floatx4 (&gu)[2][2], const GvScaleQ& g, float c0,
+                                            const uint4 (&pv)[2][2], half8 (&bh)[4], half8 (&bl)[4]) {
+    float vals[2][4];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int r = 2 * pr + e;
+        const unsigned wu = r == 0 ? pv[0][hf].x : r == 1 ? pv[0][hf].y : r == 2 ? pv[0][hf].z : pv[0][hf].w;
+        const unsigned wd = r == 0 ? pv[1][hf].x : r == 1 ? pv[1][hf].y : r == 2 ? pv[1][hf].z : pv[1][hf].w;
+        const float qu = r == 0 ? g.q[0][hf].x : r == 1 ? g.q[0][hf].y : r == 2 ? g.q[0][hf].z : g.q[0][hf].w;
+        const float qd = r == 0 ? g.q[1][hf].x : r == 1 ? g.q[1][hf].y : r == 2 ? g.q[1][hf].z : g.q[1][hf].w;
+        const float ux = (float)(int)(short)(wu & 0xffffu), uy = (float)((int)wu >> 16);
+        const float dx = (float)(int)(short)(wd & 0xffffu), dy = (float)((int)wd >> 16);
+        const float su = gu[0][hf][r] * (qu * c0), sd = gu[1][hf][r] * (qd * c0);
+        vals[e][0] = su * ux + sd * dx;
+        vals[e][1] = su * uy + sd * dy;
+        vals[e][2] = su * uy - sd * dy;
+        vals[e][3] = sd * dx - su * ux;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        unsigned hp, lp;
+        split2(vals[0][q], vals[1][q], hp, lp);
+        const int w = 2 * hf + pr;
+        uint4 hv = __builtin_bit_cast(uint4, bh[q]), lv = __builtin_bit_cast(uint4, bl[q]);
+        if (w == 0) { hv.x = hp; lv.x = lp; }
+        else if (w == 1) { hv.y = hp; lv.y = lp; }
+        else if (w == 2) { hv.z = hp; lv.z = lp; }
+        else { hv.w = hp; lv.w = lp; }
+        bh[q] = __builtin_bit_cast(half8, hv);
+        bl[q] = __builtin_bit_cast(half8, lv);
+    }
+}
+
+// the lane's stored phase of a chunk: [spin][hf], four rows of one column each
+__device__ __forceinline__ void bwdq_load_phase(uint4 (&pv)[2][2], const unsigned* pbase, int c, int g4,
+                                                int64_t spin_stride, int64_t c_stride, int64_t g_stride) {
+    gptr<uint4> base = launder_v((const uint4*)(pbase + c * c_stride));
+#pragma unroll
+    for (int spin = 0; spin < 2; ++spin)
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            gptr<u32x4> p = (gptr<u32x4>)(base + (spin * spin_stride + ((g4 >> 1) + 2 * hf) * g_stride) / 4);
+            pv[spin][hf] = __builtin_bit_cast(uint4, __builtin_nontemporal_load(p));   // read once
+        }
+}
+
+// W^T chunk c (NI x 8 KB, contiguous in the table) into LDS by direct
+// global-to-LDS loads: 2 NI per thread of the 256.
+template <int NI>
+__device__ __forceinline__ void bwdq_stage(uint4* Ls, const uint4* WTq, int c, int tid, int wave) {
+    const uint4* src = WTq + (int64_t)c * (NI * 512);
+    const uint32_t off = (uint32_t)tid * 16u;
+#pragma unroll
+    for (int k = 0; k < NI * 2; ++k) dma16(src + k * 256, off, Ls + k * 256 + wave * 64);
+}
+// the split gV rows of chunk c (8 KB, without the scales) the same way
+__device__ __forceinline__ void bwdq_stage_g(uint4* Ls, const uint4* Gb, int c, int tid, int wave) {
+    const uint4* src = Gb + (int64_t)c * gvs_chunk<1>();
+    const uint32_t off = (uint32_t)tid * 16u;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) dma16(src + k * 256, off, Ls + k * 256 + wave * 64);
+}
+
+// The work for the next chunk, as eight events in this order: the lowpass-adjoint
+// chains of row half 0 (spins 0, 1), its two modulus-adjoint shares, the chains of
+// half 1, its shares.  bwdq_epos gives the region (i-tile pair step of the W^T
+// product) of each, in the second half of the chunk and spaced so that each value
+// lives only a few regions.
+constexpr int bwdq_epos(int NQ, int e) {
+    constexpr int off[8] = {0, 1, 2, 4, 5, 6, 7, 9};
+    const int p = NQ - 10 + off[e];
+    return p < 0 ? 0 : p < NQ ? p : NQ - 1;
+}
+// every event lands in a region, in order (within a region, chains run before
+// shares)
+constexpr bool bwdq_schedule_ok(int NQ) {
+    for (int e = 0; e < 8; ++e) {
+        if (bwdq_epos(NQ, e) < 0 || bwdq_epos(NQ, e) >= NQ) return false;
+        if (e > 0 && bwdq_epos(NQ, e) < bwdq_epos(NQ, e - 1)) return false;
+    }
+    return true;
+}
+
+// One 32-row chunk c of the backward below.  On entry: the W^T chunk in Tcur, the
+// B operands (P, Q') of the chunk in bh / bl, the split gV rows of chunk c + 1 in
+// Gnext, their scales and the stored phase of chunk c + 1 in snext / pnext.  At the
+// start, the phase of chunk c + 2 (into pfree), the W^T chunk c + 1 (into Tnext)
+// and the gV rows of chunk c + 2 (into Gfree) are requested.  The W^T products then
+// run as one scheduling region per i-tile pair; the 12 lowpass-adjoint products
+// and the modulus adjoint of chunk c + 1 are spread over those regions
+// (bwdq_epos), giving the B operands of chunk c + 1 in nh / nl; the scales of
+// chunk c + 2 are requested (into sfree) with the last product.  The chunk ends
+// with a full wait and a barrier (the copies have landed; every wave is done with
+// Tcur and Gnext), and nothing requested in a chunk is used before the next one:
+// a wait for a register load while a global-to-LDS copy is in flight is a wait
+// for everything.  The LDS buffers are distinct arrays, so that the compiler sees
+// that reading one does not wait for copies into another.  The last chunks
+// request their own operands again.
+template <int NI>
+__device__ __forceinline__ void bwdq_chunk(int c, int nC, const uint4* Tcur, uint4* Tnext, const uint4* Gnext,
+                                           uint4* Gfree, const uint4* WTq, const uint4* Gb, const unsigned* pbase,
+                                           int64_t spin_stride, int64_t c_stride, int64_t g_stride, half8 fh,
+                                           half8 fl, float c0, int tid, int wave, int lane, int g4, int j16,
+                                           const half8 (&bh)[4], const half8 (&bl)[4], half8 (&nh)[4],
+                                           half8 (&nl)[4], const uint4 (&pnext)[2][2], uint4 (&pfree)[2][2],
+                                           const GvScaleQ& snext, GvScaleQ& sfree, floatx4 (&gyr)[2 * NI],
+                                           floatx4 (&gyi)[2 * NI]) {
+    constexpr int NQ = 2 * NI;
+    static_assert(bwdq_schedule_ok(NQ), "lowpass-adjoint chains and modulus-adjoint shares");
+    const int c1 = c + 1 < nC ? c + 1 : nC - 1, c2 = c + 2 < nC ? c + 2 : nC - 1;
+    bwdq_load_phase(pfree, pbase, c2, g4, spin_stride, c_stride, g_stride);
+    bwdq_stage<NI>(Tnext, WTq, c1, tid, wave);
+    bwdq_stage_g(Gfree, Gb, c2, tid, wave);
+    floatx4 gu[2][2];
+    const uint4* Lt = Tcur + lane;
+    uint4 wc[4], wn[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) wc[p] = Lt[p * 64];
+#pragma unroll
+    for (int it = 0; it < NQ; ++it) {
+        if (it + 1 < NQ) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) wn[p] = Lt[((it + 1) * 4 + p) * 64];
+        }
+        const half8 wrh = as_h8(wc[0]), wrl = as_h8(wc[1]), wih = as_h8(wc[2]), wil = as_h8(wc[3]);
+        gyr[it] = mfma16q(wrh, bh[0], gyr[it]); gyi[it] = mfma16q(wrh, bh[1], gyi[it]);
+        gyr[it] = mfma16q(wrh, bl[0], gyr[it]); gyi[it] = mfma16q(wrh, bl[1], gyi[it]);
+        gyr[it] = mfma16q(wrl, bh[0], gyr[it]); gyi[it] = mfma16q(wrl, bh[1], gyi[it]);
+        gyr[it] = mfma16q(wih, bh[2], gyr[it]); gyi[it] = mfma16q(wih, bh[3], gyi[it]);
+        gyr[it] = mfma16q(wih, bl[2], gyr[it]); gyi[it] = mfma16q(wih, bl[3], gyi[it]);
+        gyr[it] = mfma16q(wil, bh[2], gyr[it]); gyi[it] = mfma16q(wil, bh[3], gyi[it]);
+        // events e = 4 hf + (0, 1: chains of spins 0, 1; 2, 3: shares pr = 0, 1)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if (bwdq_epos(NQ, e) != it) continue;
+            const int hf = e >> 2, k = e & 3;
+            if (k < 2) {
+                gu[k][hf] = bwdq_gu(Gnext, g4, j16, k, hf, fh, fl);
+                if (e == 5) bwdq_load_scales(sfree, Gb, c2, g4);
+            } else {
+                bwdq_modadj(hf, k - 2, gu, snext, c0, pnext, nh, nl);
+                interleave_mfma_valu<12, 4>();
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) wc[p] = wn[p];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(nh[q]), "+v"(nl[q]));
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// Backward contraction from the stored phase in 16 x 16 tiles: one signal, 64
+// columns t (four waves of 16, one per SIMD), all rows l in 32-row chunks, all NI
+// pairs of 16-row i-tiles accumulated in registers (16 NI of them per lane), so
+// that any K the split forward handles runs in one pass over the phase.
 // Per chunk:
 //   gU[l][t] = sum_tau gV[l][tau] Phi[t][tau]       (16 x 16 x 32, both spins, both row halves)
 //   P, Q' from gU and the stored unit phase         (the lane's eight rows of its column)
 //   gY[i][t] += sum_l Wr[l][i] P[l][t] + Wi[l][i] Q'[l][t]
-// The W^T chunk and the split gV are staged in LDS by direct global-to-LDS loads
-// (double-buffered where LDS allows, else gV single-buffered behind a second
-// barrier); the next chunk's phase rows are requested at the chunk's start.
-// LEAN: four waves, single buffers (at most 80 KB of LDS, the gV row scales read
-// from global memory) and two workgroups per CU, whose barriers are independent,
-// so that one workgroup's vector work can run beside the other's products.
-template <int NI, int NW, bool LEAN = false>
-__global__ void __launch_bounds__(64 * NW, LEAN ? 2 : 1) k_freq_bwd_q(const unsigned* __restrict__ phase, int64_t ph_bstride,
-                                                        int Tp, int nTt, int nU,
-                                                        const unsigned short* __restrict__ WTq, int Mp, int Kp,
-                                                        const unsigned short* __restrict__ PhTsp, float sphi,
-                                                        const uint4* __restrict__ Gs, int64_t gs_bstride,
-                                                        const float* __restrict__ gvmax, int n_beta, int alpha,
-                                                        int n_alpha, float sw, float2* __restrict__ gY,
-                                                        int64_t gy_bstride) {
+// pipelined so that the first two steps of chunk c + 1 run during the third of
+// chunk c (bwdq_chunk).  LDS: two W^T chunks (16 NI KB) and two split-gV chunks
+// (16 KB).
+template <int NI>
+__global__ void __launch_bounds__(256) k_freq_bwd_q(const unsigned* __restrict__ phase, int64_t ph_bstride, int Tp,
+                                                    int nTt, int nU, const unsigned short* __restrict__ WTq, int Mp,
+                                                    int Kp, const unsigned short* __restrict__ PhTsp, float sphi,
+                                                    const uint4* __restrict__ Gs, int64_t gs_bstride,
+                                                    const float* __restrict__ gvmax, int n_beta, int alpha,
+                                                    int n_alpha, float sw, float2* __restrict__ gY,
+                                                    int64_t gy_bstride) {
     constexpr int NTp = 32, NQ = 2 * NI;
-    constexpr int TCH = NI * 512;                     // uint4 per W^T chunk
-    constexpr int GCH = gvs_chunk<1>();               // uint4 per split-gV chunk
-    constexpr bool GDB = !LEAN && (2 * TCH + 2 * GCH) * 16 <= 160 * 1024;   // double-buffered gV
-    constexpr int NT = 64 * NW;
-    constexpr int GST = LEAN ? 512 : GCH;            // staged part of a gV chunk (planes, scales)
-    __shared__ uint4 Ls_T[LEAN ? 1 : 2][TCH];
-    __shared__ uint4 Ls_G[GDB ? 2 : 1][GST];
+    __shared__ uint4 Ls_T0[NI * 512];
+    __shared__ uint4 Ls_T1[NI * 512];
+    __shared__ uint4 Ls_G0[512];
+    __shared__ uint4 Ls_G1[512];
     const int u = blockIdx.x;
     if (u >= nU) return;                              // whole block
     const int64_t b = u / nTt;
-    const int t0 = (u % nTt) * (16 * NW);
+    const int t0 = (u % nTt) * 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int j16 = lane & 15, g4 = lane >> 4;
     const int t = t0 + wave * 16 + j16;               // this lane's column
-    const int nC = Mp / 32;
+    const int nC = Mp / 32;                           // even: Mp is a multiple of 64
 
     float G = 0.f;
     for (int q = 0; q < 2 * n_beta; ++q) G = fmaxf(G, gvmax[(b * n_alpha + alpha) * 2 * n_beta + q]);
@@ -1537,144 +1735,39 @@ __global__ void __launch_bounds__(64 * NW, LEAN ? 2 : 1) k_freq_bwd_q(const unsi
     const uint4* phrow = (const uint4*)(PhTsp + ((int64_t)t * (NTp / 8) + g4) * 16);
     const half8 fh = as_h8(phrow[0]), fl = as_h8(phrow[1]);
     const uint4* Gb = Gs + b * gs_bstride;
+    const uint4* Wt = (const uint4*)WTq;
     // the lane's phase rows: 4 (g4 % 2) .. of row group g4 / 2 (rows 4 g4 ..) and of
     // group 2 + g4 / 2 (rows 16 + 4 g4 ..)
     const unsigned* pbase = phase + b * ph_bstride + (int64_t)t * 8 + 4 * (g4 & 1);
     const int64_t spin_stride = (int64_t)Tp * Mp, c_stride = (int64_t)Tp * 32, g_stride = (int64_t)Tp * 8;
-    auto load_phase = [&](uint4 (&pv)[2][2], int c) {
-        gptr<uint4> base = launder_v((const uint4*)(pbase + c * c_stride));
-#pragma unroll
-        for (int spin = 0; spin < 2; ++spin)
-#pragma unroll
-            for (int hf = 0; hf < 2; ++hf) {
-                gptr<u32x4> p = (gptr<u32x4>)(base + (spin * spin_stride + ((g4 >> 1) + 2 * hf) * g_stride) / 4);
-                pv[spin][hf] = __builtin_bit_cast(uint4, __builtin_nontemporal_load(p));   // read once
-            }
-    };
-    auto stage_T = [&](int c, int slot) {
-        const uint4* src = (const uint4*)WTq + (int64_t)c * TCH;
-        const uint32_t off = (uint32_t)tid * 16u;
-#pragma unroll
-        for (int k = 0; k < TCH / NT; ++k) dma16(src + k * NT, off, &Ls_T[slot][k * NT + wave * 64]);
-    };
-    auto stage_G = [&](int c, int slot) {
-        const uint4* src = Gb + (int64_t)c * GCH;
-        const uint32_t off = (uint32_t)tid * 16u;
-#pragma unroll
-        for (int k = 0; k < 512 / NT; ++k) dma16(src + k * NT, off, &Ls_G[slot][k * NT + wave * 64]);
-        if (!LEAN && tid < 16) dma16(src + 512, off, &Ls_G[slot][512]);
-    };
-    uint4 pv[2][2], pn[2][2];
-    if (!LEAN) {
-        stage_T(0, 0);
-        stage_G(0, 0);
-        load_phase(pv, 0);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-    }
-    for (int c = 0; c < nC; ++c) {
-        const int slot = LEAN ? 0 : c & 1, gs = GDB ? slot : 0;
-        const bool more = c + 1 < nC;
-        if (LEAN) {
-            // this chunk's operands, waited for at once (the other workgroup on the
-            // CU computes meanwhile)
-            stage_T(c, 0);
-            stage_G(c, 0);
-            load_phase(pv, c);
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-        }
-        if (GDB && more) {
-            stage_T(c + 1, slot ^ 1);
-            stage_G(c + 1, slot ^ 1);
-            load_phase(pn, c + 1);
-        }
-        // gU of the chunk's rows 16 hf + 4 g4 + r at column t, scaled per row
+
+    // chunk 0's B operands; the gV rows, scales and phase of chunk 1
+    uint4 p0[2][2], p1[2][2];
+    GvScaleQ s0, s1;
+    half8 b0h[4], b0l[4], b1h[4], b1l[4];
+    const int one = 1 < nC ? 1 : 0;
+    bwdq_load_phase(p0, pbase, 0, g4, spin_stride, c_stride, g_stride);
+    bwdq_load_phase(p1, pbase, one, g4, spin_stride, c_stride, g_stride);
+    bwdq_load_scales(s0, Gb, 0, g4);
+    bwdq_load_scales(s1, Gb, one, g4);
+    bwdq_stage<NI>(Ls_T0, Wt, 0, tid, wave);
+    bwdq_stage_g(Ls_G0, Gb, 0, tid, wave);
+    bwdq_stage_g(Ls_G1, Gb, one, tid, wave);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    {
         floatx4 gu[2][2];
-        {
-            const uint4* Lg = Ls_G[gs];
-            const float* rs = (const float*)(Lg + 512);
 #pragma unroll
-            for (int spin = 0; spin < 2; ++spin)
+        for (int k = 0; k < 4; ++k) gu[k & 1][k >> 1] = bwdq_gu(Ls_G0, g4, j16, k & 1, k >> 1, fh, fl);
 #pragma unroll
-                for (int hf = 0; hf < 2; ++hf) {
-                    const int base = (((spin * 2 + (g4 >> 1)) * 2) * 2 + (g4 & 1)) * 32 + 16 * hf + j16;
-                    const half8 ah = as_h8(Lg[base]), al = as_h8(Lg[base + 64]);
-                    floatx4 acc = z4();
-                    acc = mfma16q(ah, fh, acc);
-                    acc = mfma16q(ah, fl, acc);
-                    acc = mfma16q(al, fh, acc);
-                    const float4 q = LEAN ? *(const float4*)((const float*)(Gb + (int64_t)c * GCH + 512) + spin * 32 +
-                                                             16 * hf + 4 * g4)
-                                          : *(const float4*)(rs + spin * 32 + 16 * hf + 4 * g4);
-                    acc[0] *= q.x * c0; acc[1] *= q.y * c0; acc[2] *= q.z * c0; acc[3] *= q.w * c0;
-                    gu[spin][hf] = acc;
-                }
-        }
-        if (!GDB && !LEAN) {
-            __syncthreads();                       // every wave has read the staged gV
-            if (more) {
-                stage_T(c + 1, slot ^ 1);
-                stage_G(c + 1, 0);
-                load_phase(pn, c + 1);
-            }
-        }
-        // modulus adjoint: P = gZ_up + gZ_down, Q' = i (gZ_down - gZ_up), gZ = gU u, for
-        // k-slot s = 4 hf + r (row qrow(g4, s)); planes q = P re, P im, Q' re, Q' im
-        half8 bh[4], bl[4];
-#pragma unroll
-        for (int hf = 0; hf < 2; ++hf)
-#pragma unroll
-            for (int pr = 0; pr < 2; ++pr) {
-                float vals[2][4];
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    const int r = 2 * pr + e;
-                    const unsigned wu = r == 0 ? pv[0][hf].x : r == 1 ? pv[0][hf].y : r == 2 ? pv[0][hf].z : pv[0][hf].w;
-                    const unsigned wd = r == 0 ? pv[1][hf].x : r == 1 ? pv[1][hf].y : r == 2 ? pv[1][hf].z : pv[1][hf].w;
-                    const float ux = (float)(int)(short)(wu & 0xffffu), uy = (float)((int)wu >> 16);
-                    const float dx = (float)(int)(short)(wd & 0xffffu), dy = (float)((int)wd >> 16);
-                    const float su = gu[0][hf][r], sd = gu[1][hf][r];
-                    vals[e][0] = su * ux + sd * dx;
-                    vals[e][1] = su * uy + sd * dy;
-                    vals[e][2] = su * uy - sd * dy;
-                    vals[e][3] = sd * dx - su * ux;
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    unsigned hp, lp;
-                    split2(vals[0][q], vals[1][q], hp, lp);
-                    const int w = 2 * hf + pr;                 // 32-bit word of the plane: slots 2 w, 2 w + 1
-                    uint4 hv = __builtin_bit_cast(uint4, bh[q]), lv = __builtin_bit_cast(uint4, bl[q]);
-                    if (w == 0) { hv.x = hp; lv.x = lp; }
-                    else if (w == 1) { hv.y = hp; lv.y = lp; }
-                    else if (w == 2) { hv.z = hp; lv.z = lp; }
-                    else { hv.w = hp; lv.w = lp; }
-                    bh[q] = __builtin_bit_cast(half8, hv);
-                    bl[q] = __builtin_bit_cast(half8, lv);
-                }
-            }
-        // gY += W^T P (real and imaginary parts of P, Q')
-        {
-            const uint4* Lt = Ls_T[slot] + lane;
-#pragma unroll
-            for (int it = 0; it < NQ; ++it) {
-                const half8 wrh = as_h8(Lt[(it * 4 + 0) * 64]), wrl = as_h8(Lt[(it * 4 + 1) * 64]);
-                const half8 wih = as_h8(Lt[(it * 4 + 2) * 64]), wil = as_h8(Lt[(it * 4 + 3) * 64]);
-                gyr[it] = mfma16q(wrh, bh[0], gyr[it]); gyi[it] = mfma16q(wrh, bh[1], gyi[it]);
-                gyr[it] = mfma16q(wrh, bl[0], gyr[it]); gyi[it] = mfma16q(wrh, bl[1], gyi[it]);
-                gyr[it] = mfma16q(wrl, bh[0], gyr[it]); gyi[it] = mfma16q(wrl, bh[1], gyi[it]);
-                gyr[it] = mfma16q(wih, bh[2], gyr[it]); gyi[it] = mfma16q(wih, bh[3], gyi[it]);
-                gyr[it] = mfma16q(wih, bl[2], gyr[it]); gyi[it] = mfma16q(wih, bl[3], gyi[it]);
-                gyr[it] = mfma16q(wil, bh[2], gyr[it]); gyi[it] = mfma16q(wil, bh[3], gyi[it]);
-            }
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (!LEAN && more) {
-#pragma unroll
-            for (int s = 0; s < 2; ++s) { pv[s][0] = pn[s][0]; pv[s][1] = pn[s][1]; }
-        }
+        for (int uu = 0; uu < 4; ++uu) bwdq_modadj(uu >> 1, uu & 1, gu, s0, c0, p0, b0h, b0l);
+    }
+    __syncthreads();                                  // every wave is done with chunk 0's gV rows
+    for (int c = 0; c < nC; c += 2) {
+        bwdq_chunk<NI>(c, nC, Ls_T0, Ls_T1, Ls_G1, Ls_G0, Wt, Gb, pbase, spin_stride, c_stride, g_stride, fh, fl, c0,
+                       tid, wave, lane, g4, j16, b0h, b0l, b1h, b1l, p1, p0, s1, s0, gyr, gyi);
+        bwdq_chunk<NI>(c + 1, nC, Ls_T1, Ls_T0, Ls_G0, Ls_G1, Wt, Gb, pbase, spin_stride, c_stride, g_stride, fh, fl,
+                       c0, tid, wave, lane, g4, j16, b1h, b1l, b0h, b0l, p0, p1, s0, s1, gyr, gyi);
     }
     const float inv = 1.f / (sw * spq);
     float2* o = gY + b * gy_bstride;
@@ -1766,9 +1859,14 @@ int build_split_tables(jtfs_plan* P, std::vector<void*>& owned) {
                            P->sw, P->WTq);
     }
     if (s.NTp == 32) {
-        // the lowpass operand of the 16 x 16-tile forward
+        // the W and lowpass operands of the 16 x 16-tile forward
+        const int ns = (s.Kp / 16 + 1) / 2;
+        const int64_t nq = (int64_t)s.Mp * ns * 128;     // halves: Mp / 64 tiles x ns k-steps x 16 KB
+        P->Wq = (unsigned short*)alloc(sizeof(unsigned short) * nq);
         P->Phq = (unsigned short*)alloc(sizeof(float) * s.sumTp * s.NTp);
-        if (!P->Phq) { set_error("device allocation failed"); return JTFS_ENOMEM; }
+        if (!P->Wq || !P->Phq) { set_error("device allocation failed"); return JTFS_ENOMEM; }
+        hipLaunchKernelGGL(k_wqsplit, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, 0, P->Wl, s.Mp, s.Kp, ns, P->sw,
+                           P->Wq);
         for (int a = 0; a < s.n_alpha; ++a) {
             const int64_t n = (int64_t)s.Tp[a] * s.NTp;
             hipLaunchKernelGGL(k_phqsplit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, P->Phi + s.phioff[a],
@@ -1843,7 +1941,7 @@ static void launch_fwdq_nk(int nk, dim3 grid, size_t lds, hipStream_t st, Args..
 bool fwdq_supported(const jtfs_plan* P, bool with_phase) {
     const Shapes& s = P->s;
     const int ntq = (s.NT + 15) / 16;
-    return P->Phq && s.NTp == 32 && ntq <= 2 && s.Kp / 16 <= kMaxFwdNK &&
+    return P->Phq && P->Wq && s.NTp == 32 && ntq <= 2 && s.Kp / 16 <= kMaxFwdNK &&
            fwdq_lds(s.Kp, ntq, with_phase) <= (size_t)kMaxDynLds;
 }
 
@@ -1886,9 +1984,9 @@ int launch_freq_fwd_split(const jtfs_plan* P, int a, const unsigned short* Yh, c
         const size_t ldsq = fwdq_lds(s.Kp, ntq, phase != nullptr);
         const unsigned short* Pq = P->Phq + s.phioff[a] * 2;
         if (ntq == 1)
-            launch_fwdq_nk<1>(nk, dim3(grid), ldsq, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Pq, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw);
+            launch_fwdq_nk<1>(nk, dim3(grid), ldsq, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wq, Pq, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw);
         else
-            launch_fwdq_nk<2>(nk, dim3(grid), ldsq, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wsp, Pq, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw);
+            launch_fwdq_nk<2>(nk, dim3(grid), ldsq, st, Ya, yhb, s.Tp[a], s.chunk[a], s.nch[a], nU, nlt, (const unsigned short*)P->Wq, Pq, unscale, yscale, a, s.n_alpha, Vp, vp_bstride, slot0, pha, ph_bstride, P->sw);
         return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
     }
     switch (s.NTp / 32) {
@@ -1997,39 +2095,23 @@ int launch_gv_split(const jtfs_plan* P, const float* gV, uint4* Gs, int64_t B, h
     return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
 }
 
-// waves per workgroup of the 16 x 16-tile stored-phase backward: eight (two per
-// SIMD) where the accumulators of NI i-tile pairs leave room, else four
-int bwdq_waves(int NI) { return NI <= 8 ? 8 : 4; }
-
 bool bwdq_supported(const jtfs_plan* P) {
     const int NI = P->KpT / 32;
     return P->WTq && P->s.NTp == 32 && NI >= 1 && NI <= 9;          // LDS: two W^T chunks of NI x 8 KB
 }
 
 template <int NI = 1>
-static void launch_bwdq_ni(int ni, int nw, unsigned nU, hipStream_t st, const unsigned* pha, int64_t phb, int Tp,
-                           int nTt, const jtfs_plan* P, const unsigned short* PhT, float sphi, const uint4* Gsa,
-                           int64_t gsb, const float* gvmax, int a, float2* gYa, int64_t gyb) {
+static void launch_bwdq_ni(int ni, unsigned nU, hipStream_t st, const unsigned* pha, int64_t phb, int Tp, int nTt,
+                           const jtfs_plan* P, const unsigned short* PhT, float sphi, const uint4* Gsa, int64_t gsb,
+                           const float* gvmax, int a, float2* gYa, int64_t gyb) {
     if constexpr (NI <= 9) {
         if (ni != NI) {
-            launch_bwdq_ni<NI + 1>(ni, nw, nU, st, pha, phb, Tp, nTt, P, PhT, sphi, Gsa, gsb, gvmax, a, gYa, gyb);
+            launch_bwdq_ni<NI + 1>(ni, nU, st, pha, phb, Tp, nTt, P, PhT, sphi, Gsa, gsb, gvmax, a, gYa, gyb);
             return;
         }
         const Shapes& s = P->s;
-        if (nw == 2 * 4 + 1) {             // four waves, two workgroups per CU
-            if constexpr (NI <= 9)
-                hipLaunchKernelGGL((k_freq_bwd_q<NI, 4, true>), dim3(nU), dim3(256), 0, st, pha, phb, Tp, nTt,
-                                   (int)nU, P->WTq, s.Mp, s.Kp, PhT, sphi, Gsa, gsb, gvmax, s.n_beta, a, s.n_alpha,
-                                   P->sw, gYa, gyb);
-        } else if (nw == 8) {
-            if constexpr (NI <= 8)
-                hipLaunchKernelGGL((k_freq_bwd_q<NI, 8>), dim3(nU), dim3(512), 0, st, pha, phb, Tp, nTt, (int)nU,
-                                   P->WTq, s.Mp, s.Kp, PhT, sphi, Gsa, gsb, gvmax, s.n_beta, a, s.n_alpha, P->sw, gYa,
-                                   gyb);
-        } else {
-            hipLaunchKernelGGL((k_freq_bwd_q<NI, 4>), dim3(nU), dim3(256), 0, st, pha, phb, Tp, nTt, (int)nU, P->WTq,
-                               s.Mp, s.Kp, PhT, sphi, Gsa, gsb, gvmax, s.n_beta, a, s.n_alpha, P->sw, gYa, gyb);
-        }
+        hipLaunchKernelGGL((k_freq_bwd_q<NI>), dim3(nU), dim3(256), 0, st, pha, phb, Tp, nTt, (int)nU, P->WTq, s.Mp,
+                           s.Kp, PhT, sphi, Gsa, gsb, gvmax, s.n_beta, a, s.n_alpha, P->sw, gYa, gyb);
     }
 }
 
@@ -2038,16 +2120,15 @@ int launch_freq_bwd_phase(const jtfs_plan* P, int a, const unsigned* phase, int6
     const Shapes& s = P->s;
     const int NI = P->KpT / 32;
     if (P->tune.bwd16 && bwdq_supported(P)) {
-        const int nw = bwdq_waves(NI);
-        const int nTt = s.Tp[a] / (16 * nw);
+        const int nTt = s.Tp[a] / 64;
         const unsigned nU = (unsigned)(B * nTt);
         const int64_t yb = (int64_t)s.Kp * s.sumTp;
         const unsigned* pha = phase + (int64_t)2 * s.Mp * (s.yoff[a] / s.Kp);
         const unsigned short* PhT = P->PhTsp + s.phioff[a] * 2;
         const uint4* Gsa = Gs + (int64_t)a * (s.Mp / 32) * (512 * (s.NTp / 32) + 16);
         JTFS_TIMED(JTFS_STAGE_FREQ_ADJ_PQ, st,
-                   launch_bwdq_ni(NI, nw, nU, st, pha, ph_bstride, s.Tp[a], nTt, P, PhT, P->sphi[a], Gsa, gs_bstride,
-                                  gvmax, a, gY2 + s.yoff[a], yb));
+                   launch_bwdq_ni(NI, nU, st, pha, ph_bstride, s.Tp[a], nTt, P, PhT, P->sphi[a], Gsa, gs_bstride, gvmax,
+                                  a, gY2 + s.yoff[a], yb));
         return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
     }
     if (!P->split_bwdp_ok) { set_error("stored-phase backward not available for these shapes"); return JTFS_ENOTSUP; }
