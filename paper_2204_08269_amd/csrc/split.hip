@@ -1581,14 +1581,15 @@ __device__ __forceinline__ void bwdq_load_phase(uint4 (&pv)[2][2], const unsigne
         }
 }
 
-// W^T chunk c (NI x 8 KB, contiguous in the table) into LDS by direct
-// global-to-LDS loads: 2 NI per thread of the 256.
+// Half h (i-tiles NI h .. NI h + NI - 1, NI x 4 KB) of the W^T chunk c into LDS by
+// direct global-to-LDS loads: NI per thread of the 256.  A chunk's i-tiles are
+// contiguous in the table, each [plane][lane].
 template <int NI>
-__device__ __forceinline__ void bwdq_stage(uint4* Ls, const uint4* WTq, int c, int tid, int wave) {
-    const uint4* src = WTq + (int64_t)c * (NI * 512);
+__device__ __forceinline__ void bwdq_stage_half(uint4* Ls, const uint4* WTq, int c, int h, int tid, int wave) {
+    const uint4* src = WTq + (int64_t)c * (NI * 512) + h * (NI * 256);
     const uint32_t off = (uint32_t)tid * 16u;
 #pragma unroll
-    for (int k = 0; k < NI * 2; ++k) dma16(src + k * 256, off, Ls + k * 256 + wave * 64);
+    for (int k = 0; k < NI; ++k) dma16(src + k * 256, off, Ls + k * 256 + wave * 64);
 }
 // the split gV rows of chunk c (8 KB, without the scales) the same way
 __device__ __forceinline__ void bwdq_stage_g(uint4* Ls, const uint4* Gb, int c, int tid, int wave) {
@@ -1598,66 +1599,26 @@ __device__ __forceinline__ void bwdq_stage_g(uint4* Ls, const uint4* Gb, int c, 
     for (int k = 0; k < 2; ++k) dma16(src + k * 256, off, Ls + k * 256 + wave * 64);
 }
 
-// The work for the next chunk, as eight events in this order: the lowpass-adjoint
-// chains of row half 0 (spins 0, 1), its two modulus-adjoint shares, the chains of
-// half 1, its shares.  bwdq_epos gives the region (i-tile pair step of the W^T
-// product) of each, in the second half of the chunk and spaced so that each value
-// lives only a few regions.
-constexpr int bwdq_epos(int NQ, int e) {
-    constexpr int off[8] = {0, 1, 2, 4, 5, 6, 7, 9};
-    const int p = NQ - 10 + off[e];
-    return p < 0 ? 0 : p < NQ ? p : NQ - 1;
-}
-// every event lands in a region, in order (within a region, chains run before
-// shares)
-constexpr bool bwdq_schedule_ok(int NQ) {
-    for (int e = 0; e < 8; ++e) {
-        if (bwdq_epos(NQ, e) < 0 || bwdq_epos(NQ, e) >= NQ) return false;
-        if (e > 0 && bwdq_epos(NQ, e) < bwdq_epos(NQ, e - 1)) return false;
-    }
-    return true;
-}
-
-// One 32-row chunk c of the backward below.  On entry: the W^T chunk in Tcur, the
-// B operands (P, Q') of the chunk in bh / bl, the split gV rows of chunk c + 1 in
-// Gnext, their scales and the stored phase of chunk c + 1 in snext / pnext.  At the
-// start, the phase of chunk c + 2 (into pfree), the W^T chunk c + 1 (into Tnext)
-// and the gV rows of chunk c + 2 (into Gfree) are requested.  The W^T products then
-// run as one scheduling region per i-tile pair; the 12 lowpass-adjoint products
-// and the modulus adjoint of chunk c + 1 are spread over those regions
-// (bwdq_epos), giving the B operands of chunk c + 1 in nh / nl; the scales of
-// chunk c + 2 are requested (into sfree) with the last product.  The chunk ends
-// with a full wait and a barrier (the copies have landed; every wave is done with
-// Tcur and Gnext), and nothing requested in a chunk is used before the next one:
-// a wait for a register load while a global-to-LDS copy is in flight is a wait
-// for everything.  The LDS buffers are distinct arrays, so that the compiler sees
-// that reading one does not wait for copies into another.  The last chunks
-// request their own operands again.
-template <int NI>
-__device__ __forceinline__ void bwdq_chunk(int c, int nC, const uint4* Tcur, uint4* Tnext, const uint4* Gnext,
-                                           uint4* Gfree, const uint4* WTq, const uint4* Gb, const unsigned* pbase,
-                                           int64_t spin_stride, int64_t c_stride, int64_t g_stride, half8 fh,
-                                           half8 fl, float c0, int tid, int wave, int lane, int g4, int j16,
-                                           const half8 (&bh)[4], const half8 (&bl)[4], half8 (&nh)[4],
-                                           half8 (&nl)[4], const uint4 (&pnext)[2][2], uint4 (&pfree)[2][2],
-                                           const GvScaleQ& snext, GvScaleQ& sfree, floatx4 (&gyr)[2 * NI],
-                                           floatx4 (&gyi)[2 * NI]) {
-    constexpr int NQ = 2 * NI;
-    static_assert(bwdq_schedule_ok(NQ), "lowpass-adjoint chains and modulus-adjoint shares");
-    const int c1 = c + 1 < nC ? c + 1 : nC - 1, c2 = c + 2 < nC ? c + 2 : nC - 1;
-    bwdq_load_phase(pfree, pbase, c2, g4, spin_stride, c_stride, g_stride);
-    bwdq_stage<NI>(Tnext, WTq, c1, tid, wave);
-    bwdq_stage_g(Gfree, Gb, c2, tid, wave);
-    floatx4 gu[2][2];
-    const uint4* Lt = Tcur + lane;
+// The W^T products of i-tiles IT0 .. IT0 + NI - 1 (one half of the chunk, staged in
+// Lh), one scheduling region per i-tile; the work of chunk c + 1 placed in this
+// half (CHAINS: the four lowpass-adjoint chains from the gV rows in Lg; else the
+// four modulus-adjoint shares) is spread over the regions.
+template <int NI, int IT0, bool CHAINS>
+__device__ __forceinline__ void bwdq_half(const uint4* Lh, const uint4* Lg, int lane, int g4, int j16, half8 fh,
+                                          half8 fl, float c0, const half8 (&bh)[4], const half8 (&bl)[4],
+                                          half8 (&nh)[4], half8 (&nl)[4], const uint4 (&pnext)[2][2],
+                                          const GvScaleQ& snext, floatx4 (&gu)[2][2], floatx4 (&gyr)[2 * NI],
+                                          floatx4 (&gyi)[2 * NI]) {
+    const uint4* Lt = Lh + lane;
     uint4 wc[4], wn[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) wc[p] = Lt[p * 64];
 #pragma unroll
-    for (int it = 0; it < NQ; ++it) {
-        if (it + 1 < NQ) {
+    for (int j = 0; j < NI; ++j) {
+        const int it = IT0 + j;
+        if (j + 1 < NI) {
 #pragma unroll
-            for (int p = 0; p < 4; ++p) wn[p] = Lt[((it + 1) * 4 + p) * 64];
+            for (int p = 0; p < 4; ++p) wn[p] = Lt[((j + 1) * 4 + p) * 64];
         }
         const half8 wrh = as_h8(wc[0]), wrl = as_h8(wc[1]), wih = as_h8(wc[2]), wil = as_h8(wc[3]);
         gyr[it] = mfma16q(wrh, bh[0], gyr[it]); gyi[it] = mfma16q(wrh, bh[1], gyi[it]);
@@ -1666,16 +1627,15 @@ __device__ __forceinline__ void bwdq_chunk(int c, int nC, const uint4* Tcur, uin
         gyr[it] = mfma16q(wih, bh[2], gyr[it]); gyi[it] = mfma16q(wih, bh[3], gyi[it]);
         gyr[it] = mfma16q(wih, bl[2], gyr[it]); gyi[it] = mfma16q(wih, bl[3], gyi[it]);
         gyr[it] = mfma16q(wil, bh[2], gyr[it]); gyi[it] = mfma16q(wil, bh[3], gyi[it]);
-        // events e = 4 hf + (0, 1: chains of spins 0, 1; 2, 3: shares pr = 0, 1)
+        // event k (chain (spin k & 1, half k >> 1), or share (half k >> 1, pair k & 1))
+        // in region (k NI) / 4 of the half
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            if (bwdq_epos(NQ, e) != it) continue;
-            const int hf = e >> 2, k = e & 3;
-            if (k < 2) {
-                gu[k][hf] = bwdq_gu(Gnext, g4, j16, k, hf, fh, fl);
-                if (e == 5) bwdq_load_scales(sfree, Gb, c2, g4);
+        for (int k = 0; k < 4; ++k) {
+            if ((k * NI) / 4 != j) continue;
+            if constexpr (CHAINS) {
+                gu[k & 1][k >> 1] = bwdq_gu(Lg, g4, j16, k & 1, k >> 1, fh, fl);
             } else {
-                bwdq_modadj(hf, k - 2, gu, snext, c0, pnext, nh, nl);
+                bwdq_modadj(k >> 1, k & 1, gu, snext, c0, pnext, nh, nl);
                 interleave_mfma_valu<12, 4>();
             }
         }
@@ -1683,10 +1643,6 @@ __device__ __forceinline__ void bwdq_chunk(int c, int nC, const uint4* Tcur, uin
         for (int p = 0; p < 4; ++p) wc[p] = wn[p];
         __builtin_amdgcn_sched_barrier(0);
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(nh[q]), "+v"(nl[q]));
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
 }
 
 // Backward contraction from the stored phase in 16 x 16 tiles: one signal, 64
@@ -1698,8 +1654,21 @@ __device__ __forceinline__ void bwdq_chunk(int c, int nC, const uint4* Tcur, uin
 //   P, Q' from gU and the stored unit phase         (the lane's eight rows of its column)
 //   gY[i][t] += sum_l Wr[l][i] P[l][t] + Wi[l][i] Q'[l][t]
 // pipelined so that the first two steps of chunk c + 1 run during the third of
-// chunk c (bwdq_chunk).  LDS: two W^T chunks (16 NI KB) and two split-gV chunks
-// (16 KB).
+// chunk c.  The W^T chunk is staged in two halves by i-range, X (first NI
+// i-tiles) and Y (the rest), and the split gV rows in G, each a distinct LDS array
+// filled by direct global-to-LDS loads (8 NI + 8 KB in all):
+//   chunk start: Y <- W^T(c) second half; phase of chunk c + 2 requested
+//   first half:  products with X; lowpass-adjoint chains of chunk c + 1 from G
+//   full wait, barrier
+//   middle:      X <- W^T(c + 1) first half, G <- gV rows of chunk c + 2; their
+//                scales requested
+//   second half: products with Y; modulus adjoint of chunk c + 1
+//   full wait, barrier
+// Every copy thus has half a chunk of products to land, the arrays read in a half
+// are never the ones being filled (so the compiler adds no wait for the copies
+// before those reads), and nothing requested into registers is used before the
+// next barrier (a wait for a register load while a copy is in flight is a wait
+// for everything).  The last chunks request their own operands again.
 template <int NI>
 __global__ void __launch_bounds__(256) k_freq_bwd_q(const unsigned* __restrict__ phase, int64_t ph_bstride, int Tp,
                                                     int nTt, int nU, const unsigned short* __restrict__ WTq, int Mp,
@@ -1709,10 +1678,9 @@ __global__ void __launch_bounds__(256) k_freq_bwd_q(const unsigned* __restrict__
                                                     int n_alpha, float sw, float2* __restrict__ gY,
                                                     int64_t gy_bstride) {
     constexpr int NTp = 32, NQ = 2 * NI;
-    __shared__ uint4 Ls_T0[NI * 512];
-    __shared__ uint4 Ls_T1[NI * 512];
-    __shared__ uint4 Ls_G0[512];
-    __shared__ uint4 Ls_G1[512];
+    __shared__ uint4 Ls_X[NI * 256];
+    __shared__ uint4 Ls_Y[NI * 256];
+    __shared__ uint4 Ls_G[512];
     const int u = blockIdx.x;
     if (u >= nU) return;                              // whole block
     const int64_t b = u / nTt;
@@ -1720,7 +1688,7 @@ __global__ void __launch_bounds__(256) k_freq_bwd_q(const unsigned* __restrict__
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int j16 = lane & 15, g4 = lane >> 4;
     const int t = t0 + wave * 16 + j16;               // this lane's column
-    const int nC = Mp / 32;                           // even: Mp is a multiple of 64
+    const int nC = Mp / 32;
 
     float G = 0.f;
     for (int q = 0; q < 2 * n_beta; ++q) G = fmaxf(G, gvmax[(b * n_alpha + alpha) * 2 * n_beta + q]);
@@ -1740,34 +1708,59 @@ __global__ void __launch_bounds__(256) k_freq_bwd_q(const unsigned* __restrict__
     // group 2 + g4 / 2 (rows 16 + 4 g4 ..)
     const unsigned* pbase = phase + b * ph_bstride + (int64_t)t * 8 + 4 * (g4 & 1);
     const int64_t spin_stride = (int64_t)Tp * Mp, c_stride = (int64_t)Tp * 32, g_stride = (int64_t)Tp * 8;
-
-    // chunk 0's B operands; the gV rows, scales and phase of chunk 1
-    uint4 p0[2][2], p1[2][2];
-    GvScaleQ s0, s1;
-    half8 b0h[4], b0l[4], b1h[4], b1l[4];
     const int one = 1 < nC ? 1 : 0;
-    bwdq_load_phase(p0, pbase, 0, g4, spin_stride, c_stride, g_stride);
-    bwdq_load_phase(p1, pbase, one, g4, spin_stride, c_stride, g_stride);
-    bwdq_load_scales(s0, Gb, 0, g4);
-    bwdq_load_scales(s1, Gb, one, g4);
-    bwdq_stage<NI>(Ls_T0, Wt, 0, tid, wave);
-    bwdq_stage_g(Ls_G0, Gb, 0, tid, wave);
-    bwdq_stage_g(Ls_G1, Gb, one, tid, wave);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+
+    // chunk 0's B operands from its gV rows, scales and phase; then the gV rows of
+    // chunk 1 into G, and the first half of W^T(0) into X
+    half8 bh[4], bl[4];
+    uint4 pnext[2][2];
+    GvScaleQ snext;
     {
+        uint4 p0[2][2];
+        GvScaleQ s0;
+        bwdq_load_phase(p0, pbase, 0, g4, spin_stride, c_stride, g_stride);
+        bwdq_load_scales(s0, Gb, 0, g4);
+        bwdq_stage_g(Ls_G, Gb, 0, tid, wave);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
         floatx4 gu[2][2];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) gu[k & 1][k >> 1] = bwdq_gu(Ls_G0, g4, j16, k & 1, k >> 1, fh, fl);
+        for (int k = 0; k < 4; ++k) gu[k & 1][k >> 1] = bwdq_gu(Ls_G, g4, j16, k & 1, k >> 1, fh, fl);
 #pragma unroll
-        for (int uu = 0; uu < 4; ++uu) bwdq_modadj(uu >> 1, uu & 1, gu, s0, c0, p0, b0h, b0l);
+        for (int uu = 0; uu < 4; ++uu) bwdq_modadj(uu >> 1, uu & 1, gu, s0, c0, p0, bh, bl);
     }
     __syncthreads();                                  // every wave is done with chunk 0's gV rows
-    for (int c = 0; c < nC; c += 2) {
-        bwdq_chunk<NI>(c, nC, Ls_T0, Ls_T1, Ls_G1, Ls_G0, Wt, Gb, pbase, spin_stride, c_stride, g_stride, fh, fl, c0,
-                       tid, wave, lane, g4, j16, b0h, b0l, b1h, b1l, p1, p0, s1, s0, gyr, gyi);
-        bwdq_chunk<NI>(c + 1, nC, Ls_T1, Ls_T0, Ls_G0, Ls_G1, Wt, Gb, pbase, spin_stride, c_stride, g_stride, fh, fl,
-                       c0, tid, wave, lane, g4, j16, b1h, b1l, b0h, b0l, p0, p1, s0, s1, gyr, gyi);
+    bwdq_load_phase(pnext, pbase, one, g4, spin_stride, c_stride, g_stride);
+    bwdq_load_scales(snext, Gb, one, g4);
+    bwdq_stage_g(Ls_G, Gb, one, tid, wave);
+    bwdq_stage_half<NI>(Ls_X, Wt, 0, 0, tid, wave);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    for (int c = 0; c < nC; ++c) {
+        const int c1 = c + 1 < nC ? c + 1 : nC - 1, c2 = c + 2 < nC ? c + 2 : nC - 1;
+        uint4 pfree[2][2];
+        GvScaleQ sfree;
+        half8 nh[4], nl[4];
+        floatx4 gu[2][2];
+        bwdq_stage_half<NI>(Ls_Y, Wt, c, 1, tid, wave);
+        bwdq_load_phase(pfree, pbase, c2, g4, spin_stride, c_stride, g_stride);
+        bwdq_half<NI, 0, true>(Ls_X, Ls_G, lane, g4, j16, fh, fl, c0, bh, bl, nh, nl, pnext, snext, gu, gyr, gyi);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        bwdq_stage_half<NI>(Ls_X, Wt, c1, 0, tid, wave);
+        bwdq_stage_g(Ls_G, Gb, c2, tid, wave);
+        bwdq_load_scales(sfree, Gb, c2, g4);
+        bwdq_half<NI, NI, false>(Ls_Y, Ls_G, lane, g4, j16, fh, fl, c0, bh, bl, nh, nl, pnext, snext, gu, gyr, gyi);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) asm volatile("" : "+v"(nh[q]), "+v"(nl[q]));
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { bh[q] = nh[q]; bl[q] = nl[q]; }
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) { pnext[s2][0] = pfree[s2][0]; pnext[s2][1] = pfree[s2][1]; }
+        snext = sfree;
     }
     const float inv = 1.f / (sw * spq);
     float2* o = gY + b * gy_bstride;
