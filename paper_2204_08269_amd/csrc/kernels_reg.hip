@@ -69,7 +69,8 @@ __device__ __forceinline__ void fold_inputs(float2 (&v)[kRegE], const float2* __
 // each) and loaded in the register transform's input layout.  half 0:
 // u[p] + u[p+m]; half 1: (u[p] - u[p+m]) e^{+2 pi i p/n}.  Without the split
 // (TWO false) each thread folds u at its own input positions; no LDS is used.
-template <bool TWO>
+// (KU: positions whose loads a thread issues together in the batched fold.)
+template <bool TWO, int KU = 4>
 __device__ __forceinline__ void load_dif(float2 (&v)[kRegE], float* A, float* B, const float2* __restrict__ src,
                                          const float* __restrict__ ps, int lo, int hi, int logn, int half,
                                          const float2* __restrict__ tw, int tw_log, bool zero) {
@@ -93,7 +94,6 @@ __device__ __forceinline__ void load_dif(float2 (&v)[kRegE], float* A, float* B,
         // every bin of the row receives at most two band samples: a thread requests
         // all samples (and twiddles) of KU positions before forming any of them,
         // instead of waiting for each position's loads in turn
-        constexpr int KU = 4;
         for (int p0 = threadIdx.x; p0 < m; p0 += KU * (int)blockDim.x) {
             float2 sa[KU][2], sc[KU][2], w[KU];
             float ga[KU][2], gc[KU][2];
@@ -291,30 +291,27 @@ __global__ void __launch_bounds__(kRegT) k_rowfft_r(float2* __restrict__ base, i
         for (int e = 0; e < kRegE; ++e) row[reg_output_pos<kRegMinLog, kRegE>(e)] = v[e];
     } else {
         const int m = 1 << logS;
-        // E = DFT of the even samples, parked in the first half of the row once every
-        // thread holds its odd samples; then O = DFT of the odd samples; combine
-#pragma unroll
-        for (int e = 0; e < kRegE; ++e) v[e] = row[2 * reg_input_pos<kRegMinLog, kRegE>(e)];
-        reg_fft<kRegE, kRegMinLog>(v, xbuf, tw, tw_log, false);
+        // E = DFT of the even samples, O = DFT of the odd ones, both held in registers:
+        // each input position's even and odd samples arrive in one 16-byte load, the
+        // row is read once and written once, and the combination pairs the two
+        // transforms' outputs at the same position of the same thread
         float2 o[kRegE];
-        const float2* rowo = after(row, v[0]);
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e) o[e] = rowo[2 * reg_input_pos<kRegMinLog, kRegE>(e) + 1];
-        __syncthreads();
-        __threadfence_block();
-#pragma unroll
-        for (int e = 0; e < kRegE; ++e) row[reg_output_pos<kRegMinLog, kRegE>(e)] = v[e];
+        for (int e = 0; e < kRegE; ++e) {
+            const float4 q = ((const float4*)row)[reg_input_pos<kRegMinLog, kRegE>(e)];
+            v[e] = make_float2(q.x, q.y);
+            o[e] = make_float2(q.z, q.w);
+        }
+        reg_fft<kRegE, kRegMinLog>(v, xbuf, tw, tw_log, false);
         reg_fft<kRegE, kRegMinLog>(o, xbuf, tw, tw_log, false);
-        // the parked even half and the combining twiddles are read only now
-        float2* rowc = after(row, o[0]);
+        __syncthreads();      // every thread has read its inputs before any output is stored
         const float2* twc = after(tw, o[0]);
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
             const int k = reg_output_pos<kRegMinLog, kRegE>(e);
-            const float2 ev = rowc[k];                 // written by this thread above
             const float2 wo = cmul(o[e], twiddle(twc, k << (tw_log - logn), false));
-            rowc[k] = cadd(ev, wo);
-            rowc[k + m] = csub(ev, wo);
+            row[k] = cadd(v[e], wo);
+            row[k + m] = csub(v[e], wo);
         }
     }
 }
@@ -339,48 +336,58 @@ __global__ void __launch_bounds__(kRegT) k_scal_bwd_b_r(const float2* __restrict
     const int lo = band1[2 * lam], hi = band1[2 * lam + 1];
     const float* gx = gX + (b * n1 + lam) * (int64_t)NX;
     float2* o = g1 + (b * n1 + lam) * (int64_t)NX;
-    float2 v[kRegE];
-#pragma unroll
-    for (int half = 0; half < (TWO ? 2 : 1); ++half) {
-        if (TWO) {
-            load_dif<true>(v, A, Bf, src, ps, lo, hi, logNX, half, tw, tw_log, false);
-        } else {
-            fold_inputs<kRegMinLog>(v, src, ps, lo, hi);
-        }
+    if constexpr (!TWO) {
+        float2 v[kRegE];
+        fold_inputs<kRegMinLog>(v, src, ps, lo, hi);
         reg_fft<kRegE, kRegMinLog>(v, A, tw, tw_log, true);
         const float* gxh = after(gx, v[0]);
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
             const float2 y = cscale(v[e], invN);
-            const int pos = reg_output_pos<kRegMinLog, kRegE>(e);
-            const float sc = gxh[TWO ? 2 * pos + half : pos] *
+            const float sc = gxh[reg_output_pos<kRegMinLog, kRegE>(e)] *
                              __builtin_amdgcn_rcpf(fmaxf(__builtin_amdgcn_sqrtf(y.x * y.x + y.y * y.y), kEpsMod));
             v[e] = cscale(y, sc);
         }
         // from the last pass's output layout to the first pass's input layout
         reg_output_to_input<kRegMinLog, kRegE>(v, A);
         reg_fft<kRegE, kRegMinLog>(v, A, tw, tw_log, false);
-        if (TWO && half == 0) {
-            // spectrum of the even samples, parked in the output row
-#pragma unroll
-            for (int e = 0; e < kRegE; ++e) o[reg_output_pos<kRegMinLog, kRegE>(e)] = v[e];
-        }
-    }
-    if constexpr (!TWO) {
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) o[reg_output_pos<kRegMinLog, kRegE>(e)] = v[e];
     } else {
+        // the inverse transform by decimation in frequency gives the even time samples
+        // (half 0) and the odd ones (half 1); both stay in registers, so that gX is
+        // read once (one 8-byte load per position for the two halves) and the
+        // forward transform by decimation in time combines the halves' spectra
+        // without parking one of them in the output row
         const int m = 1 << logS;
-        // the parked even half and the combining twiddles are read only now
-        float2* oc = after(o, v[0]);
-        const float2* twc = after(tw, v[0]);
+        float2 v0[kRegE], v1[kRegE];
+        load_dif<true>(v0, A, Bf, src, ps, lo, hi, logNX, 0, tw, tw_log, false);
+        reg_fft<kRegE, kRegMinLog>(v0, A, tw, tw_log, true);
+        load_dif<true, 1>(v1, A, Bf, src, ps, lo, hi, logNX, 1, tw, tw_log, false);   // beside v0: fewer loads at once
+        reg_fft<kRegE, kRegMinLog>(v1, A, tw, tw_log, true);
+        const float2* gx2 = (const float2*)after(gx, v1[0]);
+        const int tidw = opaque_tid();       // positions formed here, not kept from before
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
-            const int k = reg_output_pos<kRegMinLog, kRegE>(e);
-            const float2 ev = oc[k];                   // written by this thread above
-            const float2 wo = cmul(v[e], twiddle(twc, k << (tw_log - logNX), false));
-            oc[k] = cadd(ev, wo);
-            oc[k + m] = csub(ev, wo);
+            const float2 g = gx2[reg_output_pos<kRegMinLog, kRegE>(e, tidw)];     // samples 2 pos, 2 pos + 1
+            const float2 y0 = cscale(v0[e], invN), y1 = cscale(v1[e], invN);
+            v0[e] = cscale(y0, g.x * __builtin_amdgcn_rcpf(
+                                       fmaxf(__builtin_amdgcn_sqrtf(y0.x * y0.x + y0.y * y0.y), kEpsMod)));
+            v1[e] = cscale(y1, g.y * __builtin_amdgcn_rcpf(
+                                       fmaxf(__builtin_amdgcn_sqrtf(y1.x * y1.x + y1.y * y1.y), kEpsMod)));
+        }
+        reg_output_to_input<kRegMinLog, kRegE>(v0, A);
+        reg_fft<kRegE, kRegMinLog>(v0, A, tw, tw_log, false);
+        reg_output_to_input<kRegMinLog, kRegE>(v1, A);
+        reg_fft<kRegE, kRegMinLog>(v1, A, tw, tw_log, false);
+        const float2* twc = after(tw, v1[0]);
+        const int tido = opaque_tid();
+#pragma unroll
+        for (int e = 0; e < kRegE; ++e) {
+            const int k = reg_output_pos<kRegMinLog, kRegE>(e, tido);
+            const float2 wo = cmul(v1[e], twiddle(twc, k << (tw_log - logNX), false));
+            o[k] = cadd(v0[e], wo);
+            o[k + m] = csub(v0[e], wo);
         }
     }
 }

@@ -169,12 +169,12 @@ __device__ __forceinline__ void reg_fft(float2 (&v)[E], float* x, const float2* 
 template <int LOGN, int E>
 __device__ __forceinline__ int reg_input_pos(int e) { return reg_in_pos<3, LOGN, E>(e, (int)threadIdx.x); }
 
-// output position of element e after reg_fft
+// output position of element e after reg_fft (of thread tid)
 template <int LOGN, int E>
-__device__ __forceinline__ int reg_output_pos(int e) {
+__device__ __forceinline__ int reg_output_pos(int e, int tid = (int)threadIdx.x) {
     constexpr int NP = reg_num_passes(LOGN);
     constexpr int LR = reg_pass_lr(LOGN, NP - 1);
-    return reg_out_pos<LR, LOGN - LR, LOGN, E>(e, (int)threadIdx.x);
+    return reg_out_pos<LR, LOGN - LR, LOGN, E>(e, tid);
 }
 
 // Exchange from the last pass's output layout to the first pass's input layout
