@@ -1584,6 +1584,7 @@ __device__ __forceinline__ void bwdq_load_phase(uint4 (&pv)[2][2], const unsigne
 // Half h (i-tiles NI h .. NI h + NI - 1, NI x 4 KB) of the W^T chunk c into LDS by
 // direct global-to-LDS loads: NI per thread of the 256.  A chunk's i-tiles are
 // contiguous in the table, each [plane][lane].
+// (wave is passed wave-uniform, so that the LDS destinations are scalar.)
 template <int NI>
 __device__ __forceinline__ void bwdq_stage_half(uint4* Ls, const uint4* WTq, int c, int h, int tid, int wave) {
     const uint4* src = WTq + (int64_t)c * (NI * 512) + h * (NI * 256);
@@ -1685,7 +1686,8 @@ __global__ void __launch_bounds__(256) k_freq_bwd_q(const unsigned* __restrict__
     if (u >= nU) return;                              // whole block
     const int64_t b = u / nTt;
     const int t0 = (u % nTt) * 64;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int j16 = lane & 15, g4 = lane >> 4;
     const int t = t0 + wave * 16 + j16;               // this lane's column
     const int nC = Mp / 32;
