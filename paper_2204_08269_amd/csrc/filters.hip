@@ -144,6 +144,14 @@ __global__ void k_fb_pf(float* __restrict__ PF, int NL, int Lb, int step, double
     PF[e] = (float)(acc / Lb);
 }
 
+// PFt_beta[l][m] = PF_beta[m][l]
+__global__ void k_fb_pft(const float* __restrict__ PF, float* __restrict__ PFt, int NL, int Lb) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= NL * Lb) return;
+    const int l = e / NL, m = e % NL;
+    PFt[e] = PF[(int64_t)m * Lb + l];
+}
+
 __global__ void k_fb_phix(float* __restrict__ phiX, int Mphi, double N, double sgT) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m <= Mphi) phiX[m] = (float)gauss_hat((double)m, N, sgT);
@@ -291,6 +299,7 @@ extern "C" int jtfs_plan_create_ex(jtfs_plan** out, const jtfs_params* p) {
         int64_t pf_total = 0;
         for (int b = 0; b < s.n_beta; ++b) pf_total += (int64_t)s.NL * s.Lb[b];
         P->PF = A.get<float>((size_t)pf_total);
+        P->PFt = A.get<float>((size_t)pf_total);
         P->phiX = A.get<float>((size_t)s.Mphi + 1);
         if (A.failed) { set_error("device allocation failed"); return fail(JTFS_ENOMEM); }
         for (int a = 0; a < s.n_alpha; ++a) {
@@ -303,6 +312,8 @@ extern "C" int jtfs_plan_create_ex(jtfs_plan** out, const jtfs_params* p) {
             const int cnt = s.NL * s.Lb[b];
             hipLaunchKernelGGL(k_fb_pf, dim3((cnt + 255) / 256), dim3(256), 0, 0, P->PF + s.pfoff[b], s.NL, s.Lb[b],
                                (int)(s.F >> s.kfr[b]), (double)s.L, sgF);
+            hipLaunchKernelGGL(k_fb_pft, dim3((cnt + 255) / 256), dim3(256), 0, 0, P->PF + s.pfoff[b],
+                               P->PFt + s.pfoff[b], s.NL, s.Lb[b]);
         }
         hipLaunchKernelGGL(k_fb_phix, dim3((s.Mphi + 256) / 256), dim3(256), 0, 0, P->phiX, s.Mphi, (double)s.N, sgT);
         if (hipGetLastError() != hipSuccess) { set_error("lowpass kernels failed"); return fail(JTFS_EHIP); }

@@ -443,74 +443,69 @@ __global__ void __launch_bounds__(256) k_freq_fwd(const float2* __restrict__ Y, 
     }
 }
 
-// S2[b][alpha][beta][theta][m][tau] = sum_l PF_beta[m][l] V[theta][rowoff+l][tau],
-// V = sum over the partial slots.  grid (n_beta, 2, B).
-// Frequency lowpass (eq. (3)): sum the partial V of the block's t-chunks, then
-// S2[m][tau] = sum_l PF[m][l] V[l][tau] per (beta, spin).  With stage_pf the
-// matrix PF (NL x Lb) is held in LDS transposed, and each thread forms four
-// outputs m..m+3 of one tau from one read of V[l][tau] and one 16-byte read of PF.
+// Frequency lowpass (eq. (3)): S2[b][alpha][beta][theta][m][tau] =
+// sum_l PF_beta[m][l] V[theta][rowoff + l][tau], V summed over the partial slots
+// of the contraction's t-chunks.  grid (n_beta, 2 n_alpha, B), every temporal rate
+// in one launch.  The l axis runs in chunks of 64: the chunk's V (64 x TT columns
+// tau, its partial slots summed on the way in) and its rows of PF^T (64 x 32 rows
+// m, from the transposed table PFt) are staged in LDS, and each thread adds its
+// TT / 8 outputs (rows m of one tau) over the chunk, l in order.  Rows m beyond 32
+// and columns beyond TT take further passes.
+template <int TT>
 __global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, int64_t vp_bstride,
                                                 const int64_t* __restrict__ vchoff, const int* __restrict__ nch,
-                                                int slot_mult, int nlt, int NTp, int NT, const float* __restrict__ PFall,
+                                                int slot_mult, int nlt, int NTp, int NT, const float* __restrict__ PFt,
                                                 const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
                                                 const int* __restrict__ rowoffv, int NL, int n_alpha,
-                                                int stage_pf, float* __restrict__ S2) {
-    extern __shared__ float Vs[];   // [Lb][33], then (stage_pf) Pt [Lb][NL] at a 16-byte boundary
-    // grid (n_beta, 2 n_alpha, B): every temporal rate in one launch
+                                                float* __restrict__ S2) {
+    constexpr int LC = 64, MB = 32, NG = 256 / TT, RR = MB / NG;
+    __shared__ float Vs[LC][TT + 1];
+    __shared__ float Ps[LC][MB];
     const int beta = blockIdx.x, th = blockIdx.y & 1, alpha = blockIdx.y >> 1, n_beta = gridDim.x;
     const int slot0 = (int)vchoff[alpha] * slot_mult, nslots = nch[alpha] * slot_mult;
     const int64_t b = blockIdx.z;
     const int Lb = Lbv[beta], ro = rowoffv[beta];
-    const float* PF = PFall + pfoff[beta];
+    const float* PT = PFt + pfoff[beta];             // [Lb][NL]
     const float* Vb = Vp + b * vp_bstride;
     float* o = S2 + ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NL) * (int64_t)NT;
-    float* Pt = Vs + ((Lb * 33 + 3) & ~3);
-    const bool vec = stage_pf && (NL & 3) == 0;
-    if (stage_pf)
-        for (int e = threadIdx.x; e < NL * Lb; e += blockDim.x) {
-            const int l = e / NL, m = e - l * NL;
-            Pt[e] = PF[m * Lb + l];
-        }
-    const int tau = threadIdx.x & 31, grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
-    for (int tb = 0; tb < NT; tb += 32) {
-        for (int e = threadIdx.x; e < Lb * 32; e += blockDim.x) {
-            const int tt = e / Lb, l = e - tt * Lb;
-            const int row = ro + l, lt = row / kTileL, lr = row % kTileL;
-            float acc = 0.f;
-            if (tb + tt < NT) {
-                for (int sl = 0; sl < nslots; ++sl)
-                    acc += Vb[(((int64_t)(slot0 + sl) * nlt + lt) * 2 + th) * NTp * kTileL +
-                              (int64_t)(tb + tt) * kTileL + lr];
-            }
-            Vs[l * 33 + tt] = acc;
-        }
-        __syncthreads();
-        if (tb + tau < NT) {
-            for (int m0 = 4 * grp; m0 < NL; m0 += 4 * ngrp) {
-                float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-                if (vec) {
-                    for (int l = 0; l < Lb; ++l) {
-                        const float v = Vs[l * 33 + tau];
-                        const float4 p = *(const float4*)(Pt + l * NL + m0);
-                        a0 += p.x * v; a1 += p.y * v; a2 += p.z * v; a3 += p.w * v;
+    const int tau = threadIdx.x % TT, grp = threadIdx.x / TT;
+    for (int mb = 0; mb < NL; mb += MB)
+        for (int tb = 0; tb < NT; tb += TT) {
+            float acc[RR];
+#pragma unroll
+            for (int r = 0; r < RR; ++r) acc[r] = 0.f;
+            for (int l0 = 0; l0 < Lb; l0 += LC) {
+                const int lc = Lb - l0 < LC ? Lb - l0 : LC;
+                __syncthreads();                         // the previous chunk is read
+                for (int e = threadIdx.x; e < LC * TT; e += 256) {
+                    const int tt = e / LC, l = e - tt * LC;
+                    float v = 0.f;
+                    if (l < lc && tb + tt < NT) {
+                        const int row = ro + l0 + l, lt = row / kTileL, lr = row % kTileL;
+                        for (int sl = 0; sl < nslots; ++sl)
+                            v += Vb[(((int64_t)(slot0 + sl) * nlt + lt) * 2 + th) * NTp * kTileL +
+                                    (int64_t)(tb + tt) * kTileL + lr];
                     }
-                } else {
-                    for (int l = 0; l < Lb; ++l) {
-                        const float v = Vs[l * 33 + tau];
-                        a0 += PF[m0 * Lb + l] * v;
-                        if (m0 + 1 < NL) a1 += PF[(m0 + 1) * Lb + l] * v;
-                        if (m0 + 2 < NL) a2 += PF[(m0 + 2) * Lb + l] * v;
-                        if (m0 + 3 < NL) a3 += PF[(m0 + 3) * Lb + l] * v;
-                    }
+                    Vs[l][tt] = v;
                 }
-                o[(int64_t)m0 * NT + tb + tau] = a0;
-                if (m0 + 1 < NL) o[(int64_t)(m0 + 1) * NT + tb + tau] = a1;
-                if (m0 + 2 < NL) o[(int64_t)(m0 + 2) * NT + tb + tau] = a2;
-                if (m0 + 3 < NL) o[(int64_t)(m0 + 3) * NT + tb + tau] = a3;
+                for (int e = threadIdx.x; e < LC * MB; e += 256) {
+                    const int l = e / MB, mm = e - l * MB;
+                    Ps[l][mm] = l < lc && mb + mm < NL ? PT[(int64_t)(l0 + l) * NL + mb + mm] : 0.f;
+                }
+                __syncthreads();
+                for (int l = 0; l < lc; ++l) {
+                    const float v = Vs[l][tau];
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) acc[r] += Ps[l][grp * RR + r] * v;
+                }
             }
+            if (tb + tau < NT)
+#pragma unroll
+                for (int r = 0; r < RR; ++r) {
+                    const int m = mb + grp * RR + r;
+                    if (m < NL) o[(int64_t)m * NT + tb + tau] = acc[r];
+                }
         }
-        __syncthreads();
-    }
 }
 
 // Eq. (4) (no frequential lowpass): V summed over its partial slots and stored per
@@ -932,11 +927,6 @@ __global__ void __launch_bounds__(256) k_band_accum(const float2* __restrict__ g
 // LDS of the frequency lowpass and its adjoint: V tile (or row sums and the gS2
 // tile), and the PF matrix when all of it fits kS2LdsCap (then held in LDS)
 constexpr size_t kS2LdsCap = 96 * 1024;
-static size_t s2_out_floats(const Shapes& s, bool stage) {
-    return (size_t)((s.L * 33 + 3) & ~3) + (stage ? (size_t)s.L * s.NL : 0);
-}
-static int s2_out_stage(const Shapes& s) { return sizeof(float) * s2_out_floats(s, true) <= kS2LdsCap ? 1 : 0; }
-static size_t s2_out_lds(const Shapes& s) { return sizeof(float) * s2_out_floats(s, s2_out_stage(s)); }
 static size_t s2_bwd_floats(const Shapes& s, bool stage) {
     return (size_t)s.L + (size_t)s.NL * s.NT + (stage ? (size_t)s.NL * s.L : 0);
 }
@@ -949,7 +939,7 @@ int setup_kernel_attributes() {
     if (g_attr_done) return JTFS_OK;
     const int lds = kMaxDynLds;
     const void* ks[] = {(const void*)k_fft_cols_t<float2, float2>, (const void*)k_fft_cols_t<float2, double2>,
-                        (const void*)k_fft_cols_t<double2, double2>, (const void*)k_scalogram, (const void*)k_s1, (const void*)k_s2_out,
+                        (const void*)k_fft_cols_t<double2, double2>, (const void*)k_scalogram, (const void*)k_s1,
                         (const void*)k_s2_bwd, (const void*)k_second_order, (const void*)k_scal_bwd_a,
                         (const void*)k_scal_bwd_b};
     for (const void* k : ks) {
@@ -1183,8 +1173,9 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
         const int mult = split ? 1 : 2;
         const dim3 grid((unsigned)s.n_beta, (unsigned)(2 * s.n_alpha), (unsigned)B);
         if (s.avg_fr) {
-            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_s2_out, grid, dim3(256), s2_out_lds(s), st, Vp, w.vp_bstride, P->d_vchoff,
-                               P->d_nch, mult, nlt, s.NTp, s.NT, P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, s.n_alpha, s2_out_stage(s), s2));
+            auto k = s.NT <= 16 ? k_s2_out<16> : k_s2_out<32>;
+            JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k, grid, dim3(256), 0, st, Vp, w.vp_bstride, P->d_vchoff,
+                               P->d_nch, mult, nlt, s.NTp, s.NT, P->PFt, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, s.n_alpha, s2));
         } else {
             JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_v_out, grid, dim3(256), 0, st, Vp, w.vp_bstride, P->d_vchoff,
                                P->d_nch, mult, nlt, s.NTp, s.NT, P->d_Lb, P->d_rowoff, s.Mh, s.n_alpha, s2));

@@ -121,6 +121,7 @@ struct jtfs_plan {
     float2* Wl = nullptr;          // same, [Mp][Kp] (row-major)
     float* Phi = nullptr;          // per alpha [Tp][NTp]: phi_alpha[(tau d - t) mod T_alpha]
     float* PF = nullptr;           // per beta [NL][Lb]: phi_F[(m F/2^kfr - l) mod Lb]
+    float* PFt = nullptr;          // per beta [Lb][NL]: PF transposed (the forward lowpass reads rows l)
     float* phiX = nullptr;         // phi_T spectrum on the NX grid, bins 0..Mphi
     int* lam_range = nullptr;      // per 256-bin range of 0..N/2: first and last lambda touching it
     int64_t* d_yoff = nullptr;     // per alpha: offset of its Y2 block

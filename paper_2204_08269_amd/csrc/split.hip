@@ -600,8 +600,8 @@ __global__ void __launch_bounds__(512) k_freq_fwd_q(const unsigned short* __rest
         for (int e = 0; e < 2 * NS; ++e) dst[e * 512 + tid] = src[e * 512 + tid];
     }
     const unsigned short* Yb = Yh + b * yh_bstride;
-    float eps2s = 0.f;
-    if (phase) {
+    float eps2s;                             // the floor of |z|^2 in the scaled units of Z
+    {
         const double wy = (double)sw * (double)yscale[b * n_alpha + alpha];
         eps2s = (float)fmax(fmin((double)kEpsMod2 * wy * wy, 1e30), 1.1754943508222875e-38);
     }
@@ -689,23 +689,26 @@ __global__ void __launch_bounds__(512) k_freq_fwd_q(const unsigned short* __rest
             for (int lb = 0; lb < 4; ++lb) {
                 float uv[4];
                 float m = 0.f;
+                // |z| = |z|^2 rsq(|z|^2), with the reciprocal square root that the phase
+                // uses (below the floor eps^2, |z|^2 / eps < eps: nothing the lowpass sees)
+                float qn[4], zrs[4], zis[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const float zr = spin ? rr[lb][r] + ii[lb][r] : rr[lb][r] - ii[lb][r];
                     const float zi = spin ? ir[lb][r] - ri[lb][r] : ir[lb][r] + ri[lb][r];
-                    uv[r] = __builtin_amdgcn_sqrtf(zr * zr + zi * zi);   // hardware square root (1 ulp)
+                    const float m2 = zr * zr + zi * zi;
+                    qn[r] = __builtin_amdgcn_rsqf(fmaxf(m2, eps2s));
+                    uv[r] = m2 * qn[r];
+                    zrs[r] = zr;
+                    zis[r] = zi;
                     m = fmaxf(m, uv[r]);
                 }
                 if (phase) {
                     // rows t 4 g4 + r, column j16 of the wave's 16 x 16 block -> 16-byte
                     // runs of four rows l of one t
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const float zr = spin ? rr[lb][r] + ii[lb][r] : rr[lb][r] - ii[lb][r];
-                        const float zi = spin ? ir[lb][r] - ri[lb][r] : ir[lb][r] + ri[lb][r];
-                        const float qn = __builtin_amdgcn_rsqf(fmaxf(zr * zr + zi * zi, eps2s));
-                        tb[(4 * g4 + r) * 20 + j16] = pack_snorm16(zr * qn, zi * qn);
-                    }
+                    for (int r = 0; r < 4; ++r)
+                        tb[(4 * g4 + r) * 20 + j16] = pack_snorm16(zrs[r] * qn[r], zis[r] * qn[r]);
                     const int tt = lane >> 2, jq = lane & 3;
                     const int ll = lb * 16 + 4 * jq;                 // first row of the quad in the 64-row tile
                     const int wl = ll >> 5, g8 = (ll & 31) >> 3;
@@ -717,8 +720,16 @@ __global__ void __launch_bounds__(512) k_freq_fwd_q(const unsigned short* __rest
                     // that it does not evict the Y operand the row tiles share in L2
                     __builtin_nontemporal_store(v, (u32x4*)pb);
                 }
-                m = fmaxf(m, __shfl_xor(m, 16));
-                m = fmaxf(m, __shfl_xor(m, 32));
+                {
+                    // maximum over the four lane groups (16 lanes apart) by two lane swaps,
+                    // without a round trip through LDS
+                    const unsigned mb = __float_as_uint(m);
+                    const auto r16 = __builtin_amdgcn_permlane16_swap(mb, mb, false, false);
+                    m = fmaxf(__uint_as_float(r16[0]), __uint_as_float(r16[1]));
+                    const unsigned mc = __float_as_uint(m);
+                    const auto r32 = __builtin_amdgcn_permlane32_swap(mc, mc, false, false);
+                    m = fmaxf(__uint_as_float(r32[0]), __uint_as_float(r32[1]));
+                }
                 const int se = pow2_exp(m);
                 const float su = ldexpf(1.f, se), inv_su = ldexpf(1.f, -se);
                 half4 uh, ul;
