@@ -597,6 +597,25 @@ __global__ void __launch_bounds__(256) k_ts_bwd(const float2* __restrict__ Y, in
     }
 }
 
+// Sum over each aligned group of `width` lanes (32 or 64), returned to every lane of
+// the group: rotations within rows of 16 lanes (DPP), then swaps between rows, all
+// in registers (a butterfly of shuffles takes five round trips through LDS).
+__device__ __forceinline__ float group_sum(float a, int width) {
+    a += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(a), 0x128, 0xF, 0xF, false));   // row_ror:8
+    a += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(a), 0x124, 0xF, 0xF, false));   // row_ror:4
+    a += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(a), 0x122, 0xF, 0xF, false));   // row_ror:2
+    a += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(a), 0x121, 0xF, 0xF, false));   // row_ror:1
+    const unsigned u = __float_as_uint(a);
+    const auto r16 = __builtin_amdgcn_permlane16_swap(u, u, false, false);   // rows 0+1, 2+3
+    a = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
+    if (width > 32) {
+        const unsigned v = __float_as_uint(a);
+        const auto r32 = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        a = __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
+    }
+    return a;
+}
+
 // gV[b][alpha][theta][rowoff+l][tau] = sum_m PF_beta[m][l] gS2[b][alpha][beta][theta][m][tau]
 // (adjoint of the frequency lowpass), or with avg = 0 (eq. (4)) the gS2 row
 // itself; block n_beta zeroes the padding rows.
@@ -652,7 +671,7 @@ __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, c
         }
         if (valid) g[(int64_t)(ro + l) * NTp + tau] = acc;
         float a = fabsf(acc);
-        for (int w = width >> 1; w > 0; w >>= 1) a += __shfl_xor(a, w);
+        a = group_sum(a, width);
         if (valid && (tau & (width - 1)) == 0) atomicAdd(&rowsum[l], a);
     }
     __syncthreads();
