@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(kRegT) k_scalogram_r(const float2* __restrict_
                                                      const int64_t* __restrict__ off1, float2* __restrict__ Xh,
                                                      int64_t Xh_pitch, int logNX, float invN,
                                                      const float2* __restrict__ tw, int tw_log) {
-    extern __shared__ float xbuf[];          // NX floats (TWO: A = first NX/2, B = second NX/2)
+    extern __shared__ __align__(16) float xbuf[];          // NX floats (TWO: A = first NX/2, B = second NX/2)
     const int lam = blockIdx.x, n1 = gridDim.x;
     const int64_t b = blockIdx.y;
     const int NX = 1 << logNX, H = NX >> 1, logH = logNX - 1;
@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(kRegT) k_second_order_r(const float2* __restri
                                                         int Tp, int Kp, float2* __restrict__ Y, int64_t y_bstride,
                                                         float invNX, const float2* __restrict__ tw, int tw_log,
                                                         float* __restrict__ rowmax, int alpha, int n_alpha) {
-    extern __shared__ float xbuf[];
+    extern __shared__ __align__(16) float xbuf[];
     __shared__ unsigned int rmx;
     const int lam = blockIdx.x;
     const int64_t b = blockIdx.y;
@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(kRegT) k_second_order_r(const float2* __restri
 template <bool TWO>
 __global__ void __launch_bounds__(kRegT) k_rowfft_r(float2* __restrict__ base, int64_t bs, int64_t rs, int logn,
                                                   const float2* __restrict__ tw, int tw_log) {
-    extern __shared__ float xbuf[];
+    extern __shared__ __align__(16) float xbuf[];
     float2* row = base + (int64_t)blockIdx.y * bs + (int64_t)blockIdx.x * rs;
     const int logS = TWO ? logn - 1 : logn;
     float2 v[kRegE];
@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(kRegT) k_scal_bwd_b_r(const float2* __restrict
                                                       const int64_t* __restrict__ off1, const float* __restrict__ gX,
                                                       float2* __restrict__ g1, int logNX, float invN,
                                                       const float2* __restrict__ tw, int tw_log) {
-    extern __shared__ float xbuf[];
+    extern __shared__ __align__(16) float xbuf[];
     const int lam = blockIdx.x, n1 = gridDim.x;
     const int64_t b = blockIdx.y;
     const int NX = 1 << logNX;

@@ -2,10 +2,9 @@
 //
 // Each of the T = 2^LOGN / E threads holds E complex values.  Passes are Stockham
 // radix-8 (then one radix-4 or radix-2 pass); between passes the values move to
-// the thread that needs them through LDS, the real parts first and the imaginary
-// parts second, so the exchange buffer holds only n floats plus one pad float per
-// eight (a little over half of an in-LDS complex transform).  Unnormalised in
-// both directions; twiddles from the FP64-generated table
+// the thread that needs them through LDS as 8-byte complex values (one exchange
+// and two barriers per pass), in a buffer of n complex slots plus one pad slot per
+// eight.  Unnormalised in both directions; twiddles from the FP64-generated table
 // tw[k] = exp(-2 pi i k / 2^tw_log).
 //
 // The length and the thread count are compile-time constants: every position a
@@ -110,34 +109,29 @@ __device__ __forceinline__ void reg_butterflies(float2 (&v)[E], const float2* __
     }
 }
 
-// Exchange-buffer slot of position i: one unused float after every eight.  The
+// Exchange-buffer slot of position i: one unused slot after every eight.  The
 // stores of the first passes go to positions R apart across the lanes (R = 8);
-// with the pad those become 9 floats apart, an odd stride, so that consecutive
-// lanes fall into distinct LDS banks.  Contiguous reads gain at most a 2-way
+// with the pad those become 9 slots (72 bytes) apart, so that the 8-byte stores of
+// a half-wave cover the 64 LDS banks once.  Contiguous reads gain at most a 2-way
 // conflict where a run crosses a pad.
 __device__ __forceinline__ int xpad(int i) { return i + (i >> 3); }
 
-// floats of exchange buffer that reg_fft needs for 2^logn points
-constexpr int reg_xbuf_floats(int logn) { return (1 << logn) + (1 << (logn - 3)); }
+// floats of exchange buffer that reg_fft needs for 2^logn points (complex slots)
+constexpr int reg_xbuf_floats(int logn) { return 2 * ((1 << logn) + (1 << (logn - 3))); }
 
 // Move the outputs of a radix-2^LR pass (sub-length 2^LNS) to the inputs of the
-// next pass (radix 2^LR2) through `x` (reg_xbuf_floats(LOGN) floats): real
-// parts, then imaginary.
+// next pass (radix 2^LR2) through `x` (reg_xbuf_floats(LOGN) floats, as complex
+// slots).
 template <int LR, int LR2, int LNS, int LOGN, int E>
 __device__ __forceinline__ void reg_exchange(float2 (&v)[E], float* x) {
+    float2* xc = (float2*)x;
     const int tid = opaque_tid();
     lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) x[xpad(reg_out_pos<LR, LNS, LOGN, E>(e, tid))] = v[e].x;
+    for (int e = 0; e < E; ++e) xc[xpad(reg_out_pos<LR, LNS, LOGN, E>(e, tid))] = v[e];
     lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e].x = x[xpad(reg_in_pos<LR2, LOGN, E>(e, tid))];
-    lds_sync();
-#pragma unroll
-    for (int e = 0; e < E; ++e) x[xpad(reg_out_pos<LR, LNS, LOGN, E>(e, tid))] = v[e].y;
-    lds_sync();
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e].y = x[xpad(reg_in_pos<LR2, LOGN, E>(e, tid))];
+    for (int e = 0; e < E; ++e) v[e] = xc[xpad(reg_in_pos<LR2, LOGN, E>(e, tid))];
 }
 
 template <int E, int LOGN, int I>
