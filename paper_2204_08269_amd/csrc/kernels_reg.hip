@@ -294,21 +294,22 @@ __global__ void __launch_bounds__(kRegT) k_rowfft_r(float2* __restrict__ base, i
         // E = DFT of the even samples, O = DFT of the odd ones, both held in registers:
         // each input position's even and odd samples arrive in one 16-byte load, the
         // row is read once and written once, and the combination pairs the two
-        // transforms' outputs at the same position of the same thread
+        // transforms' outputs at the same position of the same thread (radix-8 passes:
+        // with radix 16 the two halves' transforms need more registers than fit)
         float2 o[kRegE];
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
-            const float4 q = ((const float4*)row)[reg_input_pos<kRegMinLog, kRegE>(e)];
+            const float4 q = ((const float4*)row)[reg_input_pos<kRegMinLog, kRegE, 3>(e)];
             v[e] = make_float2(q.x, q.y);
             o[e] = make_float2(q.z, q.w);
         }
-        reg_fft<kRegE, kRegMinLog>(v, xbuf, tw, tw_log, false);
-        reg_fft<kRegE, kRegMinLog>(o, xbuf, tw, tw_log, false);
+        reg_fft<kRegE, kRegMinLog, 3>(v, xbuf, tw, tw_log, false);
+        reg_fft<kRegE, kRegMinLog, 3>(o, xbuf, tw, tw_log, false);
         __syncthreads();      // every thread has read its inputs before any output is stored
         const float2* twc = after(tw, o[0]);
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
-            const int k = reg_output_pos<kRegMinLog, kRegE>(e);
+            const int k = reg_output_pos<kRegMinLog, kRegE, 3>(e);
             const float2 wo = cmul(o[e], twiddle(twc, k << (tw_log - logn), false));
             row[k] = cadd(v[e], wo);
             row[k + m] = csub(v[e], wo);

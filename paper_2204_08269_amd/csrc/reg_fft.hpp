@@ -1,7 +1,8 @@
 // Block-wide power-of-two FFT with the data resident in registers.
 //
 // Each of the T = 2^LOGN / E threads holds E complex values.  Passes are Stockham
-// radix-8 (then one radix-4 or radix-2 pass); between passes the values move to
+// radix-16 where a thread holds 16 values, else radix-8 (then one shorter pass);
+// between passes the values move to
 // the thread that needs them through LDS as 8-byte complex values (one exchange
 // and two barriers per pass), in a buffer of n complex slots plus one pad slot per
 // eight.  Unnormalised in both directions; twiddles from the FP64-generated table
@@ -18,11 +19,64 @@
 
 namespace jtfs {
 
-// radix (log2) of pass i of a transform of 2^logn points, and the pass count
-constexpr int reg_pass_lr(int logn, int i) { return i < logn / 3 ? 3 : logn - 3 * (logn / 3); }
-constexpr int reg_num_passes(int logn) { return logn / 3 + (logn % 3 ? 1 : 0); }
+// radix (log2) of the full passes with E values per thread by default: 16 (one
+// butterfly per thread and pass) when E >= 16, else 8
+constexpr int reg_lr_max(int E) { return E >= 16 ? 4 : 3; }
+// radix (log2) of pass i of a transform of 2^logn points with full passes of radix
+// 2^lrm, and the pass count
+constexpr int reg_pass_lr(int logn, int i, int lrm) { return i < logn / lrm ? lrm : logn - lrm * (logn / lrm); }
+constexpr int reg_num_passes(int logn, int lrm) { return logn / lrm + (logn % lrm ? 1 : 0); }
 // log2 of the sub-transform length after the passes before pass i
-constexpr int reg_lns_before(int logn, int i) { return i == 0 ? 0 : reg_lns_before(logn, i - 1) + reg_pass_lr(logn, i - 1); }
+constexpr int reg_lns_before(int logn, int i, int lrm) {
+    return i == 0 ? 0 : reg_lns_before(logn, i - 1, lrm) + reg_pass_lr(logn, i - 1, lrm);
+}
+
+// In-register 16-point DFT (sign -1 forward, +1 inverse), output in natural
+// order: four 4-point DFTs over n1 (n = 4 n1 + n2), the twiddles W16^(n2 k1),
+// four 4-point DFTs over n2 (k = k1 + 4 k2).
+__device__ __forceinline__ void dft16(float2* a, bool inv) {
+    constexpr float c1 = 0.92387953251128674f, s1 = 0.38268343236508977f, h = 0.70710678118654752f;
+    float2 b[4][4];                          // [n2][k1]
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        float2 t[4] = {a[n2], a[4 + n2], a[8 + n2], a[12 + n2]};
+        dft4(t, inv);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) b[n2][k1] = t[k1];
+    }
+    // W16^m for m = n2 k1 in {1, 2, 3, 4, 6, 9} (conjugated for the inverse)
+    auto tw16 = [&](float2 v, int m) -> float2 {
+        if (m == 4) return inv ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
+        float c = 0.f, sn = 0.f;
+        if (m == 1) { c = c1; sn = -s1; }
+        else if (m == 2) { c = h; sn = -h; }
+        else if (m == 3) { c = s1; sn = -c1; }
+        else if (m == 6) { c = -h; sn = -h; }
+        else { c = -c1; sn = s1; }          // m == 9
+        if (inv) sn = -sn;
+        return make_float2(v.x * c - v.y * sn, v.x * sn + v.y * c);
+    };
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+        for (int k1 = 1; k1 < 4; ++k1) b[n2][k1] = tw16(b[n2][k1], n2 * k1);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        float2 t[4] = {b[0][k1], b[1][k1], b[2][k1], b[3][k1]};
+        dft4(t, inv);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = t[k2];
+    }
+}
+
+// Twiddles w^r, r = 1..15, of one radix-16 butterfly: w, w^2, w^4, w^8 from the
+// table, the others products of those (at most three roundings deep).
+__device__ __forceinline__ void butterfly_twiddles16(float2 (&w)[16], const float2* __restrict__ tw, int k, bool inv) {
+    butterfly_twiddles<8>(*(float2(*)[8])w, tw, k, inv);
+    w[8] = twiddle(tw, 8 * k, inv);
+#pragma unroll
+    for (int r = 1; r < 8; ++r) w[8 + r] = cmul(w[r], w[8]);
+}
 
 // The thread index as a value the compiler cannot relate to any other copy of it.
 // Positions are the thread index plus constants, the same in every pass; with
@@ -76,10 +130,13 @@ __device__ __forceinline__ void reg_butterflies(float2 (&v)[E], const float2* __
         const int k = j & ((1 << LNS) - 1);
         float2* a = v + q * R;
         float2 w[R];
-        butterfly_twiddles<R>(w, tw, k << tws, inv);
+        if constexpr (R == 16) butterfly_twiddles16(w, tw, k << tws, inv);
+        else butterfly_twiddles<R>(w, tw, k << tws, inv);
 #pragma unroll
         for (int r = 1; r < R; ++r) a[r] = cmul(a[r], w[r]);
-        if constexpr (R == 2) {
+        if constexpr (R == 16) {
+            dft16(a, inv);
+        } else if constexpr (R == 2) {
             const float2 a0 = a[0], a1 = a[1];
             a[0] = cadd(a0, a1);
             a[1] = csub(a0, a1);
@@ -134,16 +191,16 @@ __device__ __forceinline__ void reg_exchange(float2 (&v)[E], float* x) {
     for (int e = 0; e < E; ++e) v[e] = xc[xpad(reg_in_pos<LR2, LOGN, E>(e, tid))];
 }
 
-template <int E, int LOGN, int I>
+template <int E, int LOGN, int LRM, int I>
 __device__ __forceinline__ void reg_fft_from(float2 (&v)[E], float* x, const float2* __restrict__ tw, int tw_log,
                                              bool inv) {
-    constexpr int NP = reg_num_passes(LOGN);
+    constexpr int NP = reg_num_passes(LOGN, LRM);
     if constexpr (I < NP) {
-        constexpr int LR = reg_pass_lr(LOGN, I), LNS = reg_lns_before(LOGN, I);
+        constexpr int LR = reg_pass_lr(LOGN, I, LRM), LNS = reg_lns_before(LOGN, I, LRM);
         reg_butterflies<LR, LNS, LOGN, E>(v, tw, tw_log, inv);
         if constexpr (I + 1 < NP) {
-            reg_exchange<LR, reg_pass_lr(LOGN, I + 1), LNS, LOGN, E>(v, x);
-            reg_fft_from<E, LOGN, I + 1>(v, x, tw, tw_log, inv);
+            reg_exchange<LR, reg_pass_lr(LOGN, I + 1, LRM), LNS, LOGN, E>(v, x);
+            reg_fft_from<E, LOGN, LRM, I + 1>(v, x, tw, tw_log, inv);
         }
     }
 }
@@ -152,31 +209,33 @@ __device__ __forceinline__ void reg_fft_from(float2 (&v)[E], float* x, const flo
 // reg_xbuf_floats(LOGN) floats of LDS).  On entry element e of the thread holds
 // the input at reg_input_pos<LOGN, E>(e); on exit it holds the output at
 // reg_output_pos<LOGN, E>(e).  Needs LOGN >= 6.
-template <int E, int LOGN>
+template <int E, int LOGN, int LRM = reg_lr_max(E)>
 __device__ __forceinline__ void reg_fft(float2 (&v)[E], float* x, const float2* __restrict__ tw, int tw_log,
                                         bool inv) {
-    static_assert(LOGN >= 6 && (1 << LOGN) % E == 0, "transform shape");
-    reg_fft_from<E, LOGN, 0>(v, x, tw, tw_log, inv);
+    static_assert(LOGN >= 6 && (1 << LOGN) % E == 0 && (1 << LRM) <= E, "transform shape");
+    reg_fft_from<E, LOGN, LRM, 0>(v, x, tw, tw_log, inv);
 }
 
-// input position of element e (the first pass is radix 8)
-template <int LOGN, int E>
-__device__ __forceinline__ int reg_input_pos(int e) { return reg_in_pos<3, LOGN, E>(e, (int)threadIdx.x); }
+// input position of element e (that of the first pass)
+template <int LOGN, int E, int LRM = reg_lr_max(E)>
+__device__ __forceinline__ int reg_input_pos(int e) {
+    return reg_in_pos<reg_pass_lr(LOGN, 0, LRM), LOGN, E>(e, (int)threadIdx.x);
+}
 
 // output position of element e after reg_fft (of thread tid)
-template <int LOGN, int E>
+template <int LOGN, int E, int LRM = reg_lr_max(E)>
 __device__ __forceinline__ int reg_output_pos(int e, int tid = (int)threadIdx.x) {
-    constexpr int NP = reg_num_passes(LOGN);
-    constexpr int LR = reg_pass_lr(LOGN, NP - 1);
+    constexpr int NP = reg_num_passes(LOGN, LRM);
+    constexpr int LR = reg_pass_lr(LOGN, NP - 1, LRM);
     return reg_out_pos<LR, LOGN - LR, LOGN, E>(e, tid);
 }
 
 // Exchange from the last pass's output layout to the first pass's input layout
-template <int LOGN, int E>
+template <int LOGN, int E, int LRM = reg_lr_max(E)>
 __device__ __forceinline__ void reg_output_to_input(float2 (&v)[E], float* x) {
-    constexpr int NP = reg_num_passes(LOGN);
-    constexpr int LR = reg_pass_lr(LOGN, NP - 1);
-    reg_exchange<LR, 3, LOGN - LR, LOGN, E>(v, x);
+    constexpr int NP = reg_num_passes(LOGN, LRM);
+    constexpr int LR = reg_pass_lr(LOGN, NP - 1, LRM);
+    reg_exchange<LR, reg_pass_lr(LOGN, 0, LRM), LOGN - LR, LOGN, E>(v, x);
 }
 
 }  // namespace jtfs
