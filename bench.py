@@ -261,6 +261,17 @@ def texture_leg(torch, dev, iters=100, mu0=-0.05):
                              "(one bird-call recording of 2^16 samples, GPU not stated; sec. 5)"}
 
 
+def _time_ms(torch, fn, n):
+    """Mean wall time of fn over n calls (after one untimed call), GPU synchronised."""
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / n
+
+
 def run_workload(torch, dev, cfg, args, extras=True, stage_pass=True):
     """Autotune, warm up and time `args.steps` fwd+bwd steps of workload cfg; then
     (optionally) the same steps again with per-stage HIP events, a batched
@@ -327,6 +338,16 @@ def run_workload(torch, dev, cfg, args, extras=True, stage_pass=True):
             op.forward(x, ws)
         torch.cuda.synchronize()
         res["fwd_ms"] = (time.perf_counter() - t0) * 1e3 / nf
+        # mu-log (sec. 4) fused into the output kernels, against the forward
+        # followed by the separate mu-log pass; mu from this batch's path means
+        mu1, mu2 = op.path_means(s1, s2)
+
+        def separate():
+            a1, a2 = op.forward(x, ws)
+            op.mulog(a1, a2, mu1, mu2)
+
+        res["mulog_ms"] = {"fused": _time_ms(torch, lambda: op.forward_mulog(x, mu1, mu2, ws=ws), nf),
+                           "separate": _time_ms(torch, separate, nf)}
         # plain single-signal forward: no stored phase (a plain forward has no
         # backward to serve), same plan parameters
         plain = "split16" if op.contraction == "split16_phase" else op.contraction
@@ -467,6 +488,7 @@ def main():
         out["plain_fwd_single_msamples_s"] = round(res["N"] / (res["single_ms"] * 1e-3) / 1e6, 3)
         out["plain_fwd_single_ms"] = round(res["single_ms"], 3)
         out["plain_fwd_single_contraction"] = res["single_contraction"]
+        out["mulog_fwd_ms"] = {k: round(v, 3) for k, v in res["mulog_ms"].items()}
         out["stage_ms_per_step"] = {k: round(v[0] / args.steps, 3) for k, v in res["stages"].items()}
         out["roofline"] = roof
         out["stage_roofline"] = stage_roof

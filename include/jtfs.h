@@ -261,6 +261,24 @@ int jtfs_mulog_backward(const jtfs_plan* plan, const float* s1, const float* s2,
                         const float* mu2, float eps, const float* g1, const float* g2, float* gs1, float* gs2,
                         hipStream_t stream);
 
+/* The transform with the mu-log of sec. 4 (eqs. (9)-(10)) fused into its last
+ * stage: o1, o2 (the layouts of s1, s2 in jtfs_forward) receive
+ * log(1 + S / (eps mu)) per path, written by the kernels that produce S, so S
+ * itself never reaches memory.  mu1, mu2 are device FP32 in the layouts of
+ * jtfs_path_means (a statistic taken beforehand, e.g. over a training set);
+ * eps > 0.  Workspace, stream and errors as for jtfs_forward.
+ * jtfs_backward_mulog is the gradient with mu held fixed: go1, go2 are the
+ * cotangents of o1, o2 (either may be null: zero), o1, o2 the outputs that
+ * jtfs_forward_mulog wrote for the same x (needed where the matching cotangent
+ * is given); the cotangent of S is go / (eps mu e^o), applied as the lowpass
+ * adjoints read it.  flags and the rest as for jtfs_backward
+ * (JTFS_BWD_REUSE_FORWARD after jtfs_forward_mulog on the same workspace). */
+int jtfs_forward_mulog(const jtfs_plan* plan, const float* x, int64_t B, const float* mu1, const float* mu2,
+                       float eps, float* o1, float* o2, void* ws, size_t ws_bytes, hipStream_t stream);
+int jtfs_backward_mulog(const jtfs_plan* plan, const float* x, const float* o1, const float* o2, const float* mu1,
+                        const float* mu2, float eps, const float* go1, const float* go2, float* gx, int64_t B,
+                        void* ws, size_t ws_bytes, uint32_t flags, hipStream_t stream);
+
 /* Texture resynthesis (sec. 5): from a start y0, gradient descent on the
  * normalised error E(y) = ||Sx - Sy|| / ||Sx|| (S1 and S2 of the plan's layout
  * together) towards the coefficients of a target x, for B independent signals,

@@ -54,6 +54,7 @@ EXPORTS = ["jtfs_query", "jtfs_query_filters", "jtfs_plan_create", "jtfs_plan_cr
            "jtfs_plan_destroy", "jtfs_workspace_size", "jtfs_forward_workspace_size", "jtfs_forward", "jtfs_backward", "jtfs_plan_table",
            "jtfs_plan_set_contraction", "jtfs_plan_get_contraction", "jtfs_bucket_create", "jtfs_bucket_offsets",
            "jtfs_bucket_run", "jtfs_bucket_destroy", "jtfs_path_means", "jtfs_mulog", "jtfs_mulog_backward",
+           "jtfs_forward_mulog", "jtfs_backward_mulog",
            "jtfs_texture_create", "jtfs_texture_set_target", "jtfs_texture_set_start", "jtfs_texture_iterate",
            "jtfs_texture_read", "jtfs_texture_destroy", "jtfs_plan_autotune", "jtfs_plan_set_tuning",
            "jtfs_plan_get_tuning", "jtfs_forward_noalloc",
@@ -103,6 +104,8 @@ def load(path: str = LIB_PATH):
     L.jtfs_path_means.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     L.jtfs_mulog.argtypes = [vp, vp, vp, i64, vp, vp, ctypes.c_float, vp, vp, vp]
     L.jtfs_mulog_backward.argtypes = [vp, vp, vp, i64, vp, vp, ctypes.c_float, vp, vp, vp, vp, vp]
+    L.jtfs_forward_mulog.argtypes = [vp, vp, i64, vp, vp, ctypes.c_float, vp, vp, vp, sz, vp]
+    L.jtfs_backward_mulog.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_float, vp, vp, vp, i64, vp, sz, u32, vp]
     L.jtfs_plan_autotune.argtypes = [vp, vp, i64, ctypes.c_int, vp, P(Tuning)]
     L.jtfs_plan_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.jtfs_plan_get_tuning.argtypes = [vp, P(ctypes.c_int), P(ctypes.c_int)]

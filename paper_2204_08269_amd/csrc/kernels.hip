@@ -254,11 +254,34 @@ __global__ void __launch_bounds__(1024, 8) k_scalogram(const float2* __restrict_
     }
 }
 
+// mu-log of sec. 4 (eqs. (9)-(10)) fused into the coefficient writers and the
+// cotangent readers.  With mu set, a writer stores O = log(1 + S / (eps mu)) of its
+// path instead of S, and a reader takes the cotangent g of O to the cotangent of
+// S, g / (eps mu + S) = g / (eps mu e^O), from O itself (mu held fixed).
+struct MuLogArg {
+    const float* mu1;   // [1]: the S1 path; null: no mu-log
+    const float* mu2;   // one per second-order path (the layouts of the mu-log entry points)
+    float eps;
+    const float* o1;    // backward: the forward's outputs O1, O2
+    const float* o2;
+};
+
+__device__ __forceinline__ float mulog_inv(const float* mu, int p, float eps) {
+    return mu ? 1.f / (eps * mu[p]) : 0.f;
+}
+__device__ __forceinline__ float mulog_out(float v, const float* mu, float inv) {
+    return mu ? log1pf(v * inv) : v;
+}
+__device__ __forceinline__ float mulog_cot(float g, const float* mu, float em, float o) {
+    return mu ? g / (em * expf(o)) : g;
+}
+
 // S1[tau] = (X (*) phi_T)[tau T/2^kX]: fold X_hat * phi_hat over the N/T-bin grid
 // (bins -Mneg..Mphi of the NX grid), inverse FFT, real part / NX.
 __global__ void __launch_bounds__(256) k_s1(const float2* __restrict__ Xh, int64_t Xh_pitch,
                                             const float* __restrict__ phiX, int Mphi, int logNX, int logNT, float invNX,
-                                            float* __restrict__ S1, const float2* __restrict__ tw, int tw_log) {
+                                            float* __restrict__ S1, const float2* __restrict__ tw, int tw_log,
+                                            const float* __restrict__ mu1, float eps) {
     extern __shared__ float2 s[];
     const int lam = blockIdx.x, n1 = gridDim.x;
     const int64_t b = blockIdx.y;
@@ -278,7 +301,8 @@ __global__ void __launch_bounds__(256) k_s1(const float2* __restrict__ Xh, int64
     __syncthreads();
     lds_fft<64>(s, logNT, 1, NT, tw, tw_log, true);
     float* o = S1 + (b * n1 + lam) * NT;
-    for (int t = threadIdx.x; t < NT; t += blockDim.x) o[t] = s[lpad(t)].x * invNX;
+    const float inv = mulog_inv(mu1, 0, eps);
+    for (int t = threadIdx.x; t < NT; t += blockDim.x) o[t] = mulog_out(s[lpad(t)].x * invNX, mu1, inv);
 }
 
 // Second order: Y2[b][alpha][lambda][t] = (X_lambda (*) psi_alpha)[t 2^k2] for t < Ta,
@@ -457,7 +481,7 @@ __global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, in
                                                 int slot_mult, int nlt, int NTp, int NT, const float* __restrict__ PFt,
                                                 const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
                                                 const int* __restrict__ rowoffv, int NL, int n_alpha,
-                                                float* __restrict__ S2) {
+                                                float* __restrict__ S2, const float* __restrict__ mu2, float eps) {
     constexpr int LC = 64, MB = 32, NG = 256 / TT, RR = MB / NG;
     __shared__ float Vs[LC][TT + 1];
     __shared__ float Ps[LC][MB];
@@ -469,6 +493,7 @@ __global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, in
     const float* Vb = Vp + b * vp_bstride;
     float* o = S2 + ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NL) * (int64_t)NT;
     const int tau = threadIdx.x % TT, grp = threadIdx.x / TT;
+    const float inv = mulog_inv(mu2, (alpha * n_beta + beta) * 2 + th, eps);
     for (int mb = 0; mb < NL; mb += MB)
         for (int tb = 0; tb < NT; tb += TT) {
             float acc[RR];
@@ -503,7 +528,7 @@ __global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, in
 #pragma unroll
                 for (int r = 0; r < RR; ++r) {
                     const int m = mb + grp * RR + r;
-                    if (m < NL) o[(int64_t)m * NT + tb + tau] = acc[r];
+                    if (m < NL) o[(int64_t)m * NT + tb + tau] = mulog_out(acc[r], mu2, inv);
                 }
         }
 }
@@ -515,7 +540,7 @@ __global__ void __launch_bounds__(256) k_v_out(const float* __restrict__ Vp, int
                                                const int64_t* __restrict__ vchoff, const int* __restrict__ nch,
                                                int slot_mult, int nlt, int NTp, int NT, const int* __restrict__ Lbv,
                                                const int* __restrict__ rowoffv, int Mh, int n_alpha,
-                                               float* __restrict__ S2) {
+                                               float* __restrict__ S2, const float* __restrict__ mu2, float eps) {
     // grid (n_beta, 2 n_alpha, B): every temporal rate in one launch
     const int beta = blockIdx.x, th = blockIdx.y & 1, alpha = blockIdx.y >> 1;
     const int slot0 = (int)vchoff[alpha] * slot_mult, nslots = nch[alpha] * slot_mult;
@@ -523,13 +548,14 @@ __global__ void __launch_bounds__(256) k_v_out(const float* __restrict__ Vp, int
     const int Lb = Lbv[beta], ro = rowoffv[beta];
     const float* Vb = Vp + b * vp_bstride;
     float* o = S2 + ((b * n_alpha + alpha) * 2 * (int64_t)Mh + 2 * ro + th * Lb) * NT;
+    const float inv = mulog_inv(mu2, (alpha * (int)gridDim.x + beta) * 2 + th, eps);
     for (int e = threadIdx.x; e < Lb * NT; e += blockDim.x) {
         const int tau = e / Lb, l = e - tau * Lb;
         const int row = ro + l, lt = row / kTileL, lr = row % kTileL;
         float acc = 0.f;
         for (int sl = 0; sl < nslots; ++sl)
             acc += Vb[(((int64_t)(slot0 + sl) * nlt + lt) * 2 + th) * NTp * kTileL + (int64_t)tau * kTileL + lr];
-        o[(int64_t)l * NT + tau] = acc;
+        o[(int64_t)l * NT + tau] = mulog_out(acc, mu2, inv);
     }
 }
 
@@ -538,7 +564,8 @@ __global__ void __launch_bounds__(256) k_v_out(const float* __restrict__ Vp, int
 // Threads are (tau, t-group) pairs; |Y2| of 256 samples at a time goes through LDS.
 __global__ void __launch_bounds__(256) k_ts_out(const float2* __restrict__ Y, int64_t y_bstride, int Tp, int Ta,
                                                 const float* __restrict__ Phi, int NTp, int NT, int alpha,
-                                                int n_alpha, float* __restrict__ S2) {
+                                                int n_alpha, float* __restrict__ S2, const float* __restrict__ mu2,
+                                                float eps) {
     __shared__ float mag[256];
     __shared__ float part[256];
     const int lam = blockIdx.x, n1 = gridDim.x;
@@ -562,7 +589,8 @@ __global__ void __launch_bounds__(256) k_ts_out(const float2* __restrict__ Y, in
     if (g == 0 && tau < NT) {
         float s = 0.f;
         for (int q = 0; q < G; ++q) s += part[q * NTp + tau];
-        S2[((b * n_alpha + alpha) * n1 + lam) * (int64_t)NT + tau] = s;
+        S2[((b * n_alpha + alpha) * n1 + lam) * (int64_t)NT + tau] =
+            mulog_out(s, mu2, mulog_inv(mu2, alpha * n1 + lam, eps));
     }
 }
 
@@ -574,12 +602,16 @@ __global__ void __launch_bounds__(256) k_ts_out(const float2* __restrict__ Y, in
 // for t < Ta, zero for Ta <= t < Tp (rows lambda < n1).
 __global__ void __launch_bounds__(256) k_ts_bwd(const float2* __restrict__ Y, int64_t y_bstride, int Tp, int Ta,
                                                 const float* __restrict__ Phi, int NTp, int NT, int alpha,
-                                                int n_alpha, const float* __restrict__ gS2, float2* __restrict__ gY) {
+                                                int n_alpha, const float* __restrict__ gS2, float2* __restrict__ gY,
+                                                MuLogArg ml) {
     __shared__ float gs[128];
     const int lam = blockIdx.x, n1 = gridDim.x;
     const int64_t b = blockIdx.y;
-    const float* src = gS2 ? gS2 + ((b * n_alpha + alpha) * n1 + lam) * (int64_t)NT : nullptr;
-    for (int i = threadIdx.x; i < NTp; i += blockDim.x) gs[i] = (src && i < NT) ? src[i] : 0.f;
+    const int64_t so = ((b * n_alpha + alpha) * n1 + lam) * (int64_t)NT;
+    const float* src = gS2 ? gS2 + so : nullptr;
+    const float em = ml.mu2 ? ml.eps * ml.mu2[alpha * n1 + lam] : 0.f;
+    for (int i = threadIdx.x; i < NTp; i += blockDim.x)
+        gs[i] = (src && i < NT) ? mulog_cot(src[i], ml.mu2, em, ml.mu2 ? ml.o2[so + i] : 0.f) : 0.f;
     __syncthreads();
     const float2* row = Y + b * y_bstride + (int64_t)lam * Tp;
     float2* out = gY + b * y_bstride + (int64_t)lam * Tp;
@@ -630,7 +662,7 @@ __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, c
                                                 const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
                                                 const int* __restrict__ rowoffv, int n_beta, int NL, int NT, int NTp,
                                                 int Mh, int Mp, int n_alpha, int avg, int stage_pf,
-                                                float* __restrict__ gV, float* __restrict__ gvmax) {
+                                                float* __restrict__ gV, float* __restrict__ gvmax, MuLogArg ml) {
     extern __shared__ float sm[];      // rowsum [Lb] | gS2 tile [NL][NT] | (stage_pf) PF [NL][Lb]
     // grid (n_beta + 1, 2 n_alpha, B): every temporal rate in one launch
     const int beta = blockIdx.x, th = blockIdx.y & 1, alpha = blockIdx.y >> 1;
@@ -645,12 +677,15 @@ __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, c
     float* st = sm + Lb;
     float* pf = st + NL * NT;
     const float* PF = PFall + pfoff[beta];
-    const float* src = !gS2 ? nullptr
-                       : avg ? gS2 + ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NL) * (int64_t)NT
-                             : gS2 + ((b * n_alpha + alpha) * 2 * (int64_t)Mh + 2 * ro + th * Lb) * NT;
+    const int64_t so = avg ? ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NL) * (int64_t)NT
+                           : ((b * n_alpha + alpha) * 2 * (int64_t)Mh + 2 * ro + th * Lb) * NT;
+    const float* src = gS2 ? gS2 + so : nullptr;
+    const float* osrc = ml.mu2 ? ml.o2 + so : nullptr;
+    const float em = ml.mu2 ? ml.eps * ml.mu2[(alpha * n_beta + beta) * 2 + th] : 0.f;
     for (int l = threadIdx.x; l < Lb; l += blockDim.x) rowsum[l] = 0.f;
     if (src && avg) {
-        for (int e = threadIdx.x; e < NL * NT; e += blockDim.x) st[e] = src[e];
+        for (int e = threadIdx.x; e < NL * NT; e += blockDim.x)
+            st[e] = mulog_cot(src[e], ml.mu2, em, osrc ? osrc[e] : 0.f);
         if (stage_pf)
             for (int e = threadIdx.x; e < NL * Lb; e += blockDim.x) pf[e] = PF[e];
     }
@@ -666,7 +701,7 @@ __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, c
                 const float* pc = stage_pf ? pf + l : PF + l;
                 for (int m = 0; m < NL; ++m) acc += pc[m * Lb] * st[m * NT + tau];
             } else {
-                acc = src[(int64_t)l * NT + tau];
+                acc = mulog_cot(src[(int64_t)l * NT + tau], ml.mu2, em, osrc ? osrc[(int64_t)l * NT + tau] : 0.f);
             }
         }
         if (valid) g[(int64_t)(ro + l) * NTp + tau] = acc;
@@ -818,14 +853,18 @@ __global__ void __launch_bounds__(1024, 8) k_scal_bwd_a(const float2* __restrict
                                                     const int* __restrict__ band2, const int64_t* __restrict__ off2,
                                                     int n_alpha, const float* __restrict__ gS1,
                                                     const float* __restrict__ phiX, int Mphi, int logNT, int logNX,
-                                                    float* __restrict__ gX, const float2* __restrict__ tw, int tw_log) {
+                                                    float* __restrict__ gX, const float2* __restrict__ tw, int tw_log,
+                                                    MuLogArg ml) {
     extern __shared__ float2 s[];
     const int lam = blockIdx.x, n1 = gridDim.x;
     const int64_t b = blockIdx.y;
     const int NX = 1 << logNX, H = NX >> 1, NT = 1 << logNT;
     float2* g1 = s + lpad(H) + 1;
-    for (int t = threadIdx.x; t < NT; t += blockDim.x)
-        g1[lpad(t)] = make_float2(gS1 ? gS1[(b * n1 + lam) * NT + t] : 0.f, 0.f);
+    const float em = ml.mu1 ? ml.eps * ml.mu1[0] : 0.f;
+    for (int t = threadIdx.x; t < NT; t += blockDim.x) {
+        const int64_t i = (b * n1 + lam) * NT + t;
+        g1[lpad(t)] = make_float2(gS1 ? mulog_cot(gS1[i], ml.mu1, em, ml.mu1 ? ml.o1[i] : 0.f) : 0.f, 0.f);
+    }
     __syncthreads();
     lds_fft<16>(g1, logNT, 1, NT, tw, tw_log, false);
     // bins m = m0 + tid + q blockDim, q < 5: the temporal rates in the outer loop,
@@ -1094,7 +1133,7 @@ namespace {
 
 // x -> x_hat -> X_hat -> S1, Y2
 int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char* base, const Workspace& w,
-                  hipStream_t st) {
+                  const MuLogArg& ml, hipStream_t st) {
     const Shapes& s = P->s;
     float2* xh = (float2*)(base + w.xh);
     float2* Xh = (float2*)(base + w.Xh);
@@ -1112,7 +1151,7 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
     if (s1) {
         const int logNT = s.logN - s.logT;
         JTFS_TIMED(JTFS_STAGE_S1, st, hipLaunchKernelGGL(k_s1, dim3(s.n1, (unsigned)B), dim3(256), sizeof(float2) * lpad_len(s.NT), st, Xh, w.Xh_pitch,
-                           P->phiX, s.Mphi, s.logNX, logNT, 1.0f / (float)s.NX, s1, P->tw, P->tw_log));
+                           P->phiX, s.Mphi, s.logNX, logNT, 1.0f / (float)s.NX, s1, P->tw, P->tw_log, ml.mu1, ml.eps));
         LAUNCHCHK("first-order lowpass");
     }
     for (int a = 0; a < s.n_alpha; ++a) {
@@ -1136,17 +1175,15 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
     return JTFS_OK;
 }
 
-}  // namespace
-
-extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float* s1, float* s2, void* ws,
-                            size_t ws_bytes, hipStream_t st) {
+int forward_impl(const jtfs_plan* P, const float* x, int64_t B, float* s1, float* s2, void* ws, size_t ws_bytes,
+                 const MuLogArg& ml, hipStream_t st) {
     int rc = check_common(P, B, ws, ws_bytes, true);
     if (rc != JTFS_OK) return rc;
     if (!x || !s1 || !s2) { set_error("null pointer"); return JTFS_EINVAL; }
     const Shapes& s = P->s;
     const Workspace w = plan_layout(P, B);
     char* base = (char*)ws;
-    rc = forward_front(P, x, B, s1, base, w, st);
+    rc = forward_front(P, x, B, s1, base, w, ml, st);
     if (rc != JTFS_OK) return rc;
     float2* Y2 = (float2*)(base + w.Y2);
     float* Vp = (float*)(base + w.Vp);
@@ -1154,7 +1191,7 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
     for (int a = 0; a < s.n_alpha && s.tscat; ++a) {
         JTFS_TIMED(JTFS_STAGE_FREQ_FWD, st, hipLaunchKernelGGL(k_ts_out, dim3(s.n1, (unsigned)B), dim3(256), 0, st, Y2 + s.yoff[a],
                            (int64_t)s.Kp * s.sumTp, s.Tp[a], s.Ta[a], P->Phi + s.phioff[a], s.NTp, s.NT, a,
-                           s.n_alpha, s2));
+                           s.n_alpha, s2, ml.mu2, ml.eps));
         LAUNCHCHK("time-scattering lowpass");
     }
     const bool split = P->contraction != JTFS_CONTRACTION_FP32 && !s.tscat;
@@ -1194,14 +1231,23 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
         if (s.avg_fr) {
             auto k = s.NT <= 16 ? k_s2_out<16> : k_s2_out<32>;
             JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k, grid, dim3(256), 0, st, Vp, w.vp_bstride, P->d_vchoff,
-                               P->d_nch, mult, nlt, s.NTp, s.NT, P->PFt, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, s.n_alpha, s2));
+                               P->d_nch, mult, nlt, s.NTp, s.NT, P->PFt, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, s.n_alpha, s2,
+                               ml.mu2, ml.eps));
         } else {
             JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_v_out, grid, dim3(256), 0, st, Vp, w.vp_bstride, P->d_vchoff,
-                               P->d_nch, mult, nlt, s.NTp, s.NT, P->d_Lb, P->d_rowoff, s.Mh, s.n_alpha, s2));
+                               P->d_nch, mult, nlt, s.NTp, s.NT, P->d_Lb, P->d_rowoff, s.Mh, s.n_alpha, s2,
+                               ml.mu2, ml.eps));
         }
         LAUNCHCHK("frequency lowpass");
     }
     return JTFS_OK;
+}
+
+}  // namespace
+
+extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float* s1, float* s2, void* ws,
+                            size_t ws_bytes, hipStream_t st) {
+    return forward_impl(P, x, B, s1, s2, ws, ws_bytes, MuLogArg{}, st);
 }
 
 // forward FFT of every gY2 row of alpha (length T_alpha, rows lambda < n1), in place
@@ -1222,8 +1268,10 @@ static int gy2_row_fft(const jtfs_plan* P, int a, float2* gY2, int64_t yb, int64
     return JTFS_OK;
 }
 
-extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs1, const float* gs2, float* gx,
-                             int64_t B, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t st) {
+namespace {
+
+int backward_impl(const jtfs_plan* P, const float* x, const float* gs1, const float* gs2, float* gx, int64_t B,
+                  void* ws, size_t ws_bytes, uint32_t flags, const MuLogArg& ml, hipStream_t st) {
     int rc = check_common(P, B, ws, ws_bytes, false);
     if (rc != JTFS_OK) return rc;
     if (!x || !gx) { set_error("null pointer"); return JTFS_EINVAL; }
@@ -1231,7 +1279,7 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     const Workspace w = plan_layout(P, B);
     char* base = (char*)ws;
     if (!(flags & JTFS_BWD_REUSE_FORWARD)) {
-        rc = forward_front(P, x, B, nullptr, base, w, st);
+        rc = forward_front(P, x, B, nullptr, base, w, MuLogArg{}, st);
         if (rc != JTFS_OK) return rc;
     }
     float2* xh = (float2*)(base + w.xh);
@@ -1249,7 +1297,7 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     for (int a = 0; a < s.n_alpha && s.tscat; ++a) {
         JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_ts_bwd, dim3(s.n1, (unsigned)B), dim3(256), 0, st, Y2 + s.yoff[a],
                            yb, s.Tp[a], s.Ta[a], P->Phi + s.phioff[a], s.NTp, s.NT, a, s.n_alpha, gs2,
-                           gY2 + s.yoff[a]));
+                           gY2 + s.yoff[a], ml));
         LAUNCHCHK("time-scattering adjoint");
         rc = gy2_row_fft(P, a, gY2, yb, B, st);
         if (rc != JTFS_OK) return rc;
@@ -1258,7 +1306,7 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
         // every temporal rate in one launch
         JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_s2_bwd, dim3(s.n_beta + 1, 2 * s.n_alpha, (unsigned)B), dim3(256), s2_bwd_lds(s), st, gs2, P->PF, P->d_pfoff, P->d_Lb,
                            P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, s.n_alpha, (int)s.avg_fr,
-                           s2_bwd_stage(s), gV, (float*)(base + w.gvmax)));
+                           s2_bwd_stage(s), gV, (float*)(base + w.gvmax), ml));
         LAUNCHCHK("frequency lowpass adjoint");
     }
     const bool split = split_backward(P);
@@ -1327,7 +1375,7 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     const int logNT = s.logN - s.logT;
     const size_t lds_a = sizeof(float2) * (lpad_len(s.NX / 2) + 1 + lpad_len(s.NT));   // g1 at lpad(H) + 1
     JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_a, dim3(s.n1, (unsigned)B), dim3(1024), lds_a, st, gY2, yb, P->d_yoff, P->d_Tp, P->d_Ta, P->psi2,
-                       P->band2, P->off2, s.n_alpha, gs1, P->phiX, s.Mphi, logNT, s.logNX, gX, P->tw, P->tw_log));
+                       P->band2, P->off2, s.n_alpha, gs1, P->phiX, s.Mphi, logNT, s.logNX, gX, P->tw, P->tw_log, ml));
     LAUNCHCHK("scalogram adjoint");
     if (use_reg_rows(s.logNX, P->tune.reg_first_adj)) {
         JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, launch_scal_bwd_b_r(P, xh, w.xh_pitch, gX, g1, B, st));
@@ -1346,5 +1394,34 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
     JTFS_TIMED(JTFS_STAGE_OUTPUT_FFT, st, fft_rows(tmp, Hn, (float2*)gx, Hn, gxh, s.logN - 1, B, true, 1.0f / (float)s.N, P, st));
     LAUNCHCHK("output inverse FFT");
     return JTFS_OK;
+}
+
+int mulog_check(const jtfs_plan* P, const float* mu1, const float* mu2, float eps) {
+    if (!P || !mu1 || !mu2) { set_error("null pointer"); return JTFS_EINVAL; }
+    if (!(eps > 0.f)) { set_error("eps must be positive"); return JTFS_EINVAL; }
+    return JTFS_OK;
+}
+
+}  // namespace
+
+extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs1, const float* gs2, float* gx,
+                             int64_t B, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t st) {
+    return backward_impl(P, x, gs1, gs2, gx, B, ws, ws_bytes, flags, MuLogArg{}, st);
+}
+
+extern "C" int jtfs_forward_mulog(const jtfs_plan* P, const float* x, int64_t B, const float* mu1, const float* mu2,
+                                  float eps, float* o1, float* o2, void* ws, size_t ws_bytes, hipStream_t st) {
+    const int rc = mulog_check(P, mu1, mu2, eps);
+    if (rc != JTFS_OK) return rc;
+    return forward_impl(P, x, B, o1, o2, ws, ws_bytes, MuLogArg{mu1, mu2, eps, nullptr, nullptr}, st);
+}
+
+extern "C" int jtfs_backward_mulog(const jtfs_plan* P, const float* x, const float* o1, const float* o2,
+                                   const float* mu1, const float* mu2, float eps, const float* go1, const float* go2,
+                                   float* gx, int64_t B, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t st) {
+    const int rc = mulog_check(P, mu1, mu2, eps);
+    if (rc != JTFS_OK) return rc;
+    if ((go1 && !o1) || (go2 && !o2)) { set_error("null pointer"); return JTFS_EINVAL; }
+    return backward_impl(P, x, go1, go2, gx, B, ws, ws_bytes, flags, MuLogArg{mu1, mu2, eps, o1, o2}, st);
 }
 

@@ -202,6 +202,34 @@ class JTFS:
                                                 _ptr(d2), _stream()))
         return d1, d2
 
+    def forward_mulog(self, x, mu1, mu2, eps=0.1, ws=None):
+        """log(1 + S / (eps mu)) per path, computed by the transform's own output
+        kernels (S is not stored): (O1, O2) in the shapes of forward()."""
+        x = self._check_x(x)
+        B = x.shape[0]
+        ws = self._workspace(B) if ws is None else ws
+        o1 = torch.empty((B,) + self.s1_shape, dtype=torch.float32, device=x.device)
+        o2 = torch.empty((B,) + self.s2_shape, dtype=torch.float32, device=x.device)
+        _lib.check(self.lib.jtfs_forward_mulog(self.plan, _ptr(x), B, _ptr(mu1.contiguous()),
+                                               _ptr(mu2.contiguous()), float(eps), _ptr(o1), _ptr(o2), _ptr(ws),
+                                               ws.numel(), _stream()))
+        return o1, o2
+
+    def vjp_mulog(self, x, o1, o2, mu1, mu2, go1, go2, eps=0.1, ws=None, reuse_forward=False):
+        """Gradient of <go, O(x)> with mu fixed, O = forward_mulog(x) (o1, o2 its outputs)."""
+        x = self._check_x(x)
+        B = x.shape[0]
+        ws = self._workspace(B) if ws is None else ws
+        go1 = go1.contiguous().float() if go1 is not None else None
+        go2 = go2.contiguous().float() if go2 is not None else None
+        gx = torch.empty_like(x)
+        flags = _lib.JTFS_BWD_REUSE_FORWARD if reuse_forward else 0
+        _lib.check(self.lib.jtfs_backward_mulog(self.plan, _ptr(x), _ptr(o1.contiguous()), _ptr(o2.contiguous()),
+                                                _ptr(mu1.contiguous()), _ptr(mu2.contiguous()), float(eps),
+                                                _ptr(go1), _ptr(go2), _ptr(gx), B, _ptr(ws), ws.numel(), flags,
+                                                _stream()))
+        return gx
+
     def table(self, which: int):
         """Device filter table copied to the host (0: psi1 dense, 1: psi2 dense, 2: W spin -1)."""
         import numpy as np
@@ -215,8 +243,12 @@ class JTFS:
         _lib.check(self.lib.jtfs_plan_table(self.plan, which, a.ctypes.data_as(ctypes.c_void_p), a.nbytes))
         return a
 
-    def __call__(self, x):
-        return _JTFSFunction.apply(x, self)
+    def __call__(self, x, mu=None, eps=0.1):
+        """(S1, S2), differentiable; with mu = (mu1, mu2) the mu-log outputs
+        log(1 + S / (eps mu)) instead, differentiable with mu held fixed."""
+        if mu is None:
+            return _JTFSFunction.apply(x, self)
+        return _JTFSMuLogFunction.apply(x, self, mu[0], mu[1], float(eps))
 
 
 class _JTFSFunction(torch.autograd.Function):
@@ -237,6 +269,25 @@ class _JTFSFunction(torch.autograd.Function):
         ctx.ws = None
         gx = ctx.op.vjp(x, gs1, gs2, ws=ws, reuse_forward=True)
         return gx, None
+
+
+class _JTFSMuLogFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, op: JTFS, mu1, mu2, eps):
+        x = op._check_x(x)
+        ws = op.new_workspace(x.shape[0])
+        o1, o2 = op.forward_mulog(x, mu1, mu2, eps, ws)
+        ctx.op, ctx.ws, ctx.eps = op, ws, eps
+        ctx.save_for_backward(x, o1, o2, mu1, mu2)
+        return o1, o2
+
+    @staticmethod
+    def backward(ctx, go1, go2):
+        x, o1, o2, mu1, mu2 = ctx.saved_tensors
+        ws = ctx.ws
+        ctx.ws = None
+        gx = ctx.op.vjp_mulog(x, o1, o2, mu1, mu2, go1, go2, ctx.eps, ws=ws, reuse_forward=True)
+        return gx, None, None, None, None
 
 
 class JTFSBucket:

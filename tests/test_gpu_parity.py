@@ -502,6 +502,75 @@ def test_mulog_time_scattering_matches_oracle():
             assert path_errors(got, ref, 2)[0].max() <= TOL
 
 
+@pytest.mark.parametrize("variant,mode", [("eq3", None), ("eq3", "split16_phase"), ("eq4", None),
+                                          ("time_scattering", None)])
+def test_fused_mulog_matches_oracle(variant, mode):
+    """mu-log fused into the transform's output kernels (sec. 4, eqs. (9)-(10)),
+    mu given (here the oracle's path means of the batch): the outputs per path
+    against the oracle's log(1 + S / (eps mu)), bit-identical to the unfused
+    mulog(forward), and the gradient with mu fixed against the oracle's VJP of
+    the mu-log adjoint, through the C ABI (eq. (3), eq. (4), time scattering) and
+    through autograd with the stored phase."""
+    P = oracle_plan(P1)
+    x = synth.batch(1, B=3)
+    tsc = variant == "time_scattering"
+    avg = variant == "eq3"
+    op = gpu_op(P1, contraction=mode, average_fr=avg or tsc, time_scattering=tsc)
+    xt = torch.from_numpy(x).cuda()
+    if tsc:
+        refs = [O.scattering1d(x[b].astype(np.float64), P) for b in range(3)]
+    else:
+        refs = [O.jtfs(x[b].astype(np.float64), P, average_fr=avg) for b in range(3)]
+    R1 = np.stack([r[0] for r in refs])
+    R2 = np.stack([r[1] for r in refs])
+    if variant == "eq3":
+        m1, m2 = O.path_means(R1, R2)
+        m2_rows, axes = m2, 2                   # one mu per (alpha, beta, theta) slice
+    elif tsc:
+        m1, m2 = O.path_means(R1, R2, path_axes=1)
+        m2_rows, axes = m2, 1
+    else:
+        m1 = np.float64(R1.mean())
+        m2 = np.array([[[R2[:, a, P.s2_rows(b, t)].mean() for t in range(2)] for b in range(P.n_beta)]
+                       for a in range(P.n_alpha)])
+        m2_rows = np.zeros((P.n_alpha, R2.shape[2]))      # mu of each packed row's slice
+        for a in range(P.n_alpha):
+            for b in range(P.n_beta):
+                for t in range(2):
+                    m2_rows[a, P.s2_rows(b, t)] = m2[a, b, t]
+        axes = 1
+    mu1 = torch.tensor([m1], dtype=torch.float32, device="cuda")
+    mu2 = torch.from_numpy(np.ascontiguousarray(m2, np.float32).reshape(-1)).cuda()
+    e1, e2 = O.mulog(R1, R2, m1, m2_rows, path_axes=axes)
+    go1, go2 = synth.cotangents((3,) + op.s1_shape, (3,) + op.s2_shape, seed=23)
+    f1, f2 = O.mulog_vjp(R1, R2, m1, m2_rows, go1, go2, path_axes=axes)
+    if mode == "split16_phase":
+        xg = xt.clone().requires_grad_(True)
+        o1, o2 = op(xg, mu=(mu1, mu2))
+        (o1 * torch.from_numpy(go1).cuda()).sum().add((o2 * torch.from_numpy(go2).cuda()).sum()).backward()
+        gx = xg.grad
+    else:
+        o1, o2 = op.forward_mulog(xt, mu1, mu2)
+        gx = op.vjp_mulog(xt, o1, o2, mu1, mu2, torch.from_numpy(go1).cuda(), torch.from_numpy(go2).cuda())
+    s1, s2 = op.forward(xt)
+    u1, u2 = op.mulog(s1, s2, mu1, mu2)
+    assert torch.equal(o1, u1) and torch.equal(o2, u2), "fused and unfused mu-log differ"
+    o1, o2, gx = o1.detach().cpu().numpy(), o2.detach().cpu().numpy(), gx.cpu().numpy()
+    for b in range(3):
+        if variant == "eq3":
+            check_paths(o1[b], o2[b], e1[b], e2[b])
+        else:
+            assert path_errors(o1[b], e1[b], 1)[0].max() <= TOL
+            assert path_errors(o2[b], e2[b], 2)[0].max() <= TOL
+        xb = x[b].astype(np.float64)
+        if tsc:
+            ref = O.scattering1d_vjp(xb, f1[b], f2[b], P)
+        else:
+            ref = O.jtfs_vjp(xb, f1[b], f2[b], P, average_fr=avg)
+        err = rel_l2(gx[b], ref)
+        assert err <= TOL_VJP, f"signal {b}: gradient relative L2 {err:.3e}"
+
+
 @pytest.mark.parametrize("mode", ["split16", "split16_phase"])
 def test_texture_loop_matches_oracle(mode):
     """Texture resynthesis (sec. 5), every step on the GPU, against the oracle's
