@@ -67,8 +67,9 @@ typedef struct jtfs_plan jtfs_plan;
  * filterbanks; Q1 / Q2 wavelets per octave at first / second order; J_fr octaves
  * and Q_fr wavelets per octave of the frequential filterbank; lowpass supports T
  * (time, samples) and F (log-frequency, bins).  N, T, F are powers of two with
- * 16 <= N <= 2^24, T <= N, F <= L.  flags: 0, JTFS_NO_FREQ_AVERAGE or
- * JTFS_TIME_SCATTERING (other bits, or both, give JTFS_EINVAL). */
+ * 16 <= N <= 2^24, T <= N, F <= L.  flags: 0 or an OR of JTFS_NO_FREQ_AVERAGE,
+ * JTFS_TIME_SCATTERING, JTFS_LOWPASS_PAIRS and JTFS_UNPAD_LAMBDA (unknown bits, or
+ * combinations excluded below, give JTFS_EINVAL). */
 typedef struct {
     int64_t N;
     int32_t J, Q1, Q2, J_fr, Q_fr;
@@ -91,17 +92,39 @@ typedef struct {
  * Not combinable with JTFS_NO_FREQ_AVERAGE. */
 #define JTFS_TIME_SCATTERING 2u
 
+/* The lowpass pairs of the joint filterbank (the completion of the cited joint
+ * time-frequency scattering, sec. 2): each axis gains its lowpass as one more
+ * filter, so that
+ *   alpha = n_alpha - 1 is phi_T (its second-order row is X *_t phi_T at N/T
+ *     frames, i.e. the S1 rows, real), and
+ *   beta = n_beta - 1 is phi_F (real and even along lambda, decimation
+ *     log2 F as for the wavelets' critical rate),
+ * and eq. (3) (or eq. (4)) runs over all (alpha, beta, theta): the slices
+ * (psi_alpha, phi_F), (phi_T, psi_beta, theta) and (phi_T, phi_F) are
+ * | X * Psi | * Phi_{T,F} with the lowpass in place of the wavelet.  Both spin
+ * slots of a pair with a lowpass hold equal values (a real filter, or a real
+ * input along lambda).  n_alpha and n_beta of jtfs_info count the lowpasses.
+ * Not combinable with JTFS_TIME_SCATTERING. */
+#define JTFS_LOWPASS_PAIRS 4u
+
+/* Unpadded log-frequency output of eq. (3) (the out_3D input of sec. 4.2):
+ * S2 keeps the rows m < ceil(n1 / F) whose log-frequency m F falls on a
+ * first-order band, out_l = ceil(n1 / F) instead of L / F; the rows dropped are
+ * the ones centred in the zero padding of the lambda axis.  Not combinable with
+ * JTFS_NO_FREQ_AVERAGE or JTFS_TIME_SCATTERING. */
+#define JTFS_UNPAD_LAMBDA 8u
+
 /* Derived sizes. */
 typedef struct {
     int32_t n1;        /* first-order wavelets (lambda rows of the scalogram)      */
-    int32_t n_alpha;   /* second-order temporal wavelets                             */
-    int32_t n_beta;    /* frequential wavelets (each with two spins)                 */
+    int32_t n_alpha;   /* second-order temporal wavelets (+ phi_T with JTFS_LOWPASS_PAIRS) */
+    int32_t n_beta;    /* frequential wavelets, each with two spins (+ phi_F likewise)  */
     int32_t L;         /* zero-padded log-frequency length, next power of two >= n1 */
     int32_t kX;        /* scalogram decimation: X has N / 2^kX samples per row       */
     int32_t M_h;       /* frequential output rows per spin: sum_beta L / 2^kfr(beta) */
     int64_t NX;        /* N / 2^kX                                                   */
     int64_t out_t;     /* N / T frames                                               */
-    int64_t out_l;     /* L / F log-frequency rows of S2                             */
+    int64_t out_l;     /* L / F log-frequency rows of S2 (ceil(n1 / F) unpadded)     */
     int64_t sum_T;     /* sum over alpha of the second-order lengths NX / 2^k2(alpha) */
     int64_t s1_per_signal;   /* n1 * out_t                                          */
     int64_t s2_per_signal;   /* n_alpha * n_beta * 2 * out_l * out_t; with
@@ -260,6 +283,16 @@ int jtfs_mulog(const jtfs_plan* plan, const float* s1, const float* s2, int64_t 
 int jtfs_mulog_backward(const jtfs_plan* plan, const float* s1, const float* s2, int64_t B, const float* mu1,
                         const float* mu2, float eps, const float* g1, const float* g2, float* gs1, float* gs2,
                         hipStream_t stream);
+
+/* Zeroth order: S0[b][tau] = (x * phi_T)(tau T), tau < N/T, the lowpass of the
+ * signal itself that completes S1 and S2 (sec. 2's cited transform; with the
+ * discretisation above: circular, phi_T the Gaussian lowpass of width 0.1/T, DC
+ * gain 1).  x [B][N] and s0 [B][N/T] are device FP32; any plan (flags ignored).
+ * jtfs_zeroth_order_backward ADDS the gradient of sum(gs0 * S0) to gx [B][N]
+ * (so that it composes with jtfs_backward, which overwrites gx).  1 <= B <= 65535;
+ * stream-ordered; no workspace. */
+int jtfs_zeroth_order(const jtfs_plan* plan, const float* x, int64_t B, float* s0, hipStream_t stream);
+int jtfs_zeroth_order_backward(const jtfs_plan* plan, const float* gs0, int64_t B, float* gx, hipStream_t stream);
 
 /* The transform with the mu-log of sec. 4 (eqs. (9)-(10)) fused into its last
  * stage: o1, o2 (the layouts of s1, s2 in jtfs_forward) receive

@@ -22,6 +22,12 @@ It computes, in float64 and in the order the paper states them:
   over a set of signals and log(1 + S / (eps mu))
 * texture resynthesis (sec. 5): gradient descent on the normalised error
   ||Sx - Sy|| / ||Sx|| with the bold-driver learning rate
+* the lowpass pairs that complete the joint filterbank of the cited transform
+  (sec. 2): with ``lowpass_pairs`` the temporal rates gain phi_T and the
+  frequential scales gain phi_F, each kept at its critical rate, and eq. (3)
+  runs over every (alpha, beta, theta); the zeroth order S0 = x * phi_T
+* the unpadded log-frequency output (``unpad``): the rows of S2 whose
+  log-frequency m F falls on a first-order band, m < ceil(n1 / F)
 
 The paper states the operator only as continuous equations.  The discretisation
 used here (each item is a reading of the paper, listed in the design notes):
@@ -208,6 +214,8 @@ class Plan:
     Q_fr: int
     T: int
     F: int
+    lowpass_pairs: bool = False
+    unpad: bool = False
     # derived
     xi1: np.ndarray = field(init=False)
     sigma1: np.ndarray = field(init=False)
@@ -243,6 +251,11 @@ class Plan:
         self.xi2, self.sigma2 = filterbank_centres(self.J - self.kX, self.Q2)
         self.psi2_hat, self.c2 = morlet_family_hat(self.xi2, self.sigma2, self.NX)
         self.k2 = [critical_log2(s, logT - self.kX) for s in self.sigma2]
+        if self.lowpass_pairs:
+            # phi_T as one more temporal rate: its spectrum on the scalogram grid (two-sided,
+            # DC gain 1) at the rate the cap allows, so that its rows fall on the N/T frames
+            self.psi2_hat = np.vstack([self.psi2_hat, gauss_lowpass_hat(self.NX, N, T)[None, :]])
+            self.k2.append(logT - self.kX)
         # frequential filterbank on the zero-padded log-frequency axis
         n1 = len(self.xi1)
         self.L = 1 << int(math.ceil(math.log2(n1)))
@@ -253,6 +266,10 @@ class Plan:
         self.xi_fr, self.sigma_fr = filterbank_centres(self.J_fr, self.Q_fr)
         self.psi_fr_hat, self.c_fr = morlet_family_hat(self.xi_fr, self.sigma_fr, self.L)
         self.k_fr = [critical_log2(s, int(math.log2(F))) for s in self.sigma_fr]
+        if self.lowpass_pairs:
+            # phi_F as one more frequential scale, real and even along lambda, at its critical rate
+            self.psi_fr_hat = np.vstack([self.psi_fr_hat, gauss_lowpass_hat(self.L, self.L, F)[None, :]])
+            self.k_fr.append(critical_log2(SIGMA0 / F, int(math.log2(F))))
 
     # sizes ---------------------------------------------------------------
     @property
@@ -261,11 +278,11 @@ class Plan:
 
     @property
     def n_alpha(self):
-        return len(self.xi2)
+        return len(self.k2)
 
     @property
     def n_beta(self):
-        return len(self.xi_fr)
+        return len(self.k_fr)
 
     def T_alpha(self, a):
         return self.NX >> self.k2[a]
@@ -279,6 +296,8 @@ class Plan:
 
     @property
     def out_l(self):
+        if self.unpad:
+            return -(-self.n1 // self.F)
         return self.L // self.F
 
     def s1_shape(self):
@@ -457,6 +476,16 @@ def jtfs_vjp(x, gS1, gS2, P: Plan, average_fr=True):
         gX += second_order_linear_adj(gY2, P, a)
     gY1d = modulus_adj(gX, Y1d)
     return first_order_linear_adj(gY1d, P)
+
+
+def zeroth_order(x, P: Plan):
+    """S0[tau] = (x (*) phi_T)[tau T], tau < N/T."""
+    return time_lowpass(np.asarray(x, np.float64)[None, :], P, 0)[0]
+
+
+def zeroth_order_adj(g, P: Plan):
+    """Gradient of sum(g * S0) with respect to x."""
+    return time_lowpass_adj(np.asarray(g, np.float64)[None, :], P, 0, P.N)[0]
 
 
 def loss(x, gS1, gS2, P, average_fr=True):

@@ -21,6 +21,8 @@ JTFS_BWD_REUSE_FORWARD = 1
 JTFS_NOALLOC_SCRATCH_BYTES = 256 << 20
 JTFS_NO_FREQ_AVERAGE = 1
 JTFS_TIME_SCATTERING = 2
+JTFS_LOWPASS_PAIRS = 4
+JTFS_UNPAD_LAMBDA = 8
 JTFS_CONTRACTION_FP32 = 0
 JTFS_CONTRACTION_SPLIT_F16 = 1
 JTFS_CONTRACTION_SPLIT_F16_PHASE = 2
@@ -55,6 +57,7 @@ EXPORTS = ["jtfs_query", "jtfs_query_filters", "jtfs_plan_create", "jtfs_plan_cr
            "jtfs_plan_set_contraction", "jtfs_plan_get_contraction", "jtfs_bucket_create", "jtfs_bucket_offsets",
            "jtfs_bucket_run", "jtfs_bucket_destroy", "jtfs_path_means", "jtfs_mulog", "jtfs_mulog_backward",
            "jtfs_forward_mulog", "jtfs_backward_mulog",
+           "jtfs_zeroth_order", "jtfs_zeroth_order_backward",
            "jtfs_texture_create", "jtfs_texture_set_target", "jtfs_texture_set_start", "jtfs_texture_iterate",
            "jtfs_texture_read", "jtfs_texture_destroy", "jtfs_plan_autotune", "jtfs_plan_set_tuning",
            "jtfs_plan_get_tuning", "jtfs_forward_noalloc",
@@ -104,6 +107,8 @@ def load(path: str = LIB_PATH):
     L.jtfs_path_means.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     L.jtfs_mulog.argtypes = [vp, vp, vp, i64, vp, vp, ctypes.c_float, vp, vp, vp]
     L.jtfs_mulog_backward.argtypes = [vp, vp, vp, i64, vp, vp, ctypes.c_float, vp, vp, vp, vp, vp]
+    L.jtfs_zeroth_order.argtypes = [vp, vp, i64, vp, vp]
+    L.jtfs_zeroth_order_backward.argtypes = [vp, vp, i64, vp, vp]
     L.jtfs_forward_mulog.argtypes = [vp, vp, i64, vp, vp, ctypes.c_float, vp, vp, vp, sz, vp]
     L.jtfs_backward_mulog.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_float, vp, vp, vp, i64, vp, sz, u32, vp]
     L.jtfs_plan_autotune.argtypes = [vp, vp, i64, ctypes.c_int, vp, P(Tuning)]
@@ -133,8 +138,10 @@ def check(code: int):
     return code
 
 
-def params(N, J, Q, J_fr, Q_fr, T, F, average_fr=True, time_scattering=False) -> Params:
-    flags = (0 if average_fr else JTFS_NO_FREQ_AVERAGE) | (JTFS_TIME_SCATTERING if time_scattering else 0)
+def params(N, J, Q, J_fr, Q_fr, T, F, average_fr=True, time_scattering=False, lowpass_pairs=False,
+           unpad_lambda=False) -> Params:
+    flags = ((0 if average_fr else JTFS_NO_FREQ_AVERAGE) | (JTFS_TIME_SCATTERING if time_scattering else 0) |
+             (JTFS_LOWPASS_PAIRS if lowpass_pairs else 0) | (JTFS_UNPAD_LAMBDA if unpad_lambda else 0))
     return Params(N=int(N), J=int(J), Q1=int(Q[0]), Q2=int(Q[1]), J_fr=int(J_fr), Q_fr=int(Q_fr),
                   flags=flags, T=int(T), F=int(F))
 

@@ -152,6 +152,38 @@ __global__ void k_fb_pft(const float* __restrict__ PF, float* __restrict__ PFt, 
     PFt[e] = PF[(int64_t)m * Lb + l];
 }
 
+// The lowpass as the last row block of the frequential matrix (lowpass pairs):
+// phi_F[j] = (1/L) sum over the L bins of phi_F_hat(m~/L) e^{2 pi i m j / L}, real
+// and even, so its two spins coincide.
+__global__ void k_fb_phi_fr(double2* __restrict__ out, int L, double sgF) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= L) return;
+    double acc = 0.0;
+    for (int q = 0; q < L; ++q) {
+        const int mt = q <= L / 2 ? q : q - L;
+        double s, c;
+        sincospi(2.0 * (double)((int64_t)q * j % L) / L, &s, &c);
+        acc += gauss_hat((double)mt, L, sgF) * c;
+    }
+    out[j] = make_double2(acc / L, 0.0);
+}
+
+// Zeroth order: phi_T on the N-sample grid around offset 0,
+// h[k] = phi_T[(k - H) mod N] for k < len, phi_T[j] = (1/N) sum over bins |m| <= Mx
+// of phi_hat_T(m/N) e^{2 pi i m j / N} (the Nyquist bin once).
+__global__ void k_fb_phin(float* __restrict__ h, int64_t len, int64_t H, int64_t N, double sgT, int64_t Mx) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= len) return;
+    const int64_t j = ((k - H) % N + N) % N;
+    double acc = gauss_hat(0.0, (double)N, sgT);
+    for (int64_t m = 1; m <= Mx; ++m) {
+        double s, c;
+        sincospi(2.0 * (double)(m * j % N) / (double)N, &s, &c);
+        acc += (2 * m == N ? 1.0 : 2.0) * gauss_hat((double)m, (double)N, sgT) * c;
+    }
+    h[k] = (float)(acc / (double)N);
+}
+
 __global__ void k_fb_phix(float* __restrict__ phiX, int Mphi, double N, double sgT) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m <= Mphi) phiX[m] = (float)gauss_hat((double)m, N, sgT);
@@ -287,7 +319,10 @@ extern "C" int jtfs_plan_create_ex(jtfs_plan** out, const jtfs_params* p) {
         P->Wt = A.get<float2>((size_t)s.Kp * s.Mp);
         P->Wl = A.get<float2>((size_t)s.Mp * s.Kp);
         if (A.failed) { set_error("device allocation failed"); return fail(JTFS_ENOMEM); }
-        hipLaunchKernelGGL(k_fb_psi_fr, dim3((s.L + 127) / 128, s.n_beta), dim3(128), 0, 0, dxi, dsg, s.L, dc, psi);
+        hipLaunchKernelGGL(k_fb_psi_fr, dim3((s.L + 127) / 128, s.n_beta_psi), dim3(128), 0, 0, dxi, dsg, s.L, dc, psi);
+        if (s.complete)
+            hipLaunchKernelGGL(k_fb_phi_fr, dim3((s.L + 127) / 128), dim3(128), 0, 0, psi + (size_t)s.n_beta_psi * s.L,
+                               s.L, kSigma0 / (double)s.F);
         hipLaunchKernelGGL(k_fb_W, dim3((s.Kp + 63) / 64, s.Mp), dim3(64), 0, 0, psi, drb, drl, dkfr, s.Mh, s.Mp, s.n1,
                            s.Kp, s.L, P->Wt, P->Wl);
         if (hipGetLastError() != hipSuccess) { set_error("frequential wavelet kernels failed"); return fail(JTFS_EHIP); }
@@ -316,6 +351,20 @@ extern "C" int jtfs_plan_create_ex(jtfs_plan** out, const jtfs_params* p) {
                                P->PFt + s.pfoff[b], s.NL, s.Lb[b]);
         }
         hipLaunchKernelGGL(k_fb_phix, dim3((s.Mphi + 256) / 256), dim3(256), 0, 0, P->phiX, s.Mphi, (double)s.N, sgT);
+        // zeroth order: phi_T in time, within the offsets where it exceeds kSupportTol of its peak
+        {
+            const double R = std::sqrt(2.0 * std::log(1.0 / kSupportTol));
+            const double sg_t = 1.0 / (2.0 * M_PI * sgT);                 // its width in samples
+            const int64_t H = (int64_t)std::ceil(R * sg_t);
+            if (2 * H + 1 >= s.N) { P->phiN_len = s.N; P->phiN_half = s.N / 2; }
+            else { P->phiN_len = 2 * H + 1; P->phiN_half = H; }
+            const double mm = (double)s.N * sgT * R;
+            const int64_t Mx = std::min<int64_t>(s.N / 2, (int64_t)std::floor(mm) + 1);
+            P->phiN = A.get<float>((size_t)P->phiN_len);
+            if (A.failed) { set_error("device allocation failed"); return fail(JTFS_ENOMEM); }
+            hipLaunchKernelGGL(k_fb_phin, dim3((unsigned)((P->phiN_len + 255) / 256)), dim3(256), 0, 0, P->phiN,
+                               P->phiN_len, P->phiN_half, s.N, sgT, Mx);
+        }
         if (hipGetLastError() != hipSuccess) { set_error("lowpass kernels failed"); return fail(JTFS_EHIP); }
     }
     // first-order bands touching each 256-bin range of 0..N/2 (gradient accumulation)

@@ -277,15 +277,28 @@ __device__ __forceinline__ float mulog_cot(float g, const float* mu, float em, f
 }
 
 // S1[tau] = (X (*) phi_T)[tau T/2^kX]: fold X_hat * phi_hat over the N/T-bin grid
-// (bins -Mneg..Mphi of the NX grid), inverse FFT, real part / NX.
+// (bins -Mneg..Mphi of the NX grid), inverse FFT, real part / NX.  One workgroup per
+// (lambda, signal).  S1 may be null.  With the lowpass pairs, the same rows are also
+// the second-order rows of alpha = phi_T: written to Yphi (real, zero beyond N/T
+// frames and for the padding rows n1 <= lambda < Kp, which take the extra
+// workgroups) with their row maxima for the operand split.
 __global__ void __launch_bounds__(256) k_s1(const float2* __restrict__ Xh, int64_t Xh_pitch,
                                             const float* __restrict__ phiX, int Mphi, int logNX, int logNT, float invNX,
                                             float* __restrict__ S1, const float2* __restrict__ tw, int tw_log,
-                                            const float* __restrict__ mu1, float eps) {
+                                            const float* __restrict__ mu1, float eps, int n1,
+                                            float2* __restrict__ Yphi, int64_t y_bstride, int Tp,
+                                            float* __restrict__ rowmax, int alpha, int n_alpha, int Kp) {
     extern __shared__ float2 s[];
-    const int lam = blockIdx.x, n1 = gridDim.x;
+    __shared__ float red[256];
+    const int lam = blockIdx.x;
     const int64_t b = blockIdx.y;
     const int NX = 1 << logNX, NT = 1 << logNT;
+    if (lam >= n1) {                                 // padding rows of Yphi
+        float2* y = Yphi + b * y_bstride + (int64_t)lam * Tp;
+        for (int t = threadIdx.x; t < Tp; t += blockDim.x) y[t] = make_float2(0.f, 0.f);
+        if (threadIdx.x == 0) rowmax[(b * n_alpha + alpha) * Kp + lam] = 0.f;
+        return;
+    }
     const float2* row = Xh + (b * n1 + lam) * Xh_pitch;
     const int Mneg = (Mphi == NX / 2) ? Mphi - 1 : Mphi;
     for (int p = threadIdx.x; p < NT; p += blockDim.x) {
@@ -300,9 +313,72 @@ __global__ void __launch_bounds__(256) k_s1(const float2* __restrict__ Xh, int64
     }
     __syncthreads();
     lds_fft<64>(s, logNT, 1, NT, tw, tw_log, true);
-    float* o = S1 + (b * n1 + lam) * NT;
-    const float inv = mulog_inv(mu1, 0, eps);
-    for (int t = threadIdx.x; t < NT; t += blockDim.x) o[t] = mulog_out(s[lpad(t)].x * invNX, mu1, inv);
+    if (S1) {
+        float* o = S1 + (b * n1 + lam) * NT;
+        const float inv = mulog_inv(mu1, 0, eps);
+        for (int t = threadIdx.x; t < NT; t += blockDim.x) o[t] = mulog_out(s[lpad(t)].x * invNX, mu1, inv);
+    }
+    if (Yphi) {
+        float2* y = Yphi + b * y_bstride + (int64_t)lam * Tp;
+        float mx = 0.f;
+        for (int t = threadIdx.x; t < Tp; t += blockDim.x) {
+            const float v = t < NT ? s[lpad(t)].x * invNX : 0.f;
+            y[t] = make_float2(v, 0.f);
+            mx = fmaxf(mx, fabsf(v));
+        }
+        red[threadIdx.x] = mx;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) rowmax[(b * n_alpha + alpha) * Kp + lam] = red[0];
+    }
+}
+
+// Zeroth order: S0[b][tau] = (x (*) phi_T)[tau T] as the direct circular sum over the
+// offsets where phi_T is stored, h[k] = phi_T[(k - H) mod N]:
+//   S0[tau] = sum_{k < len} h[k] x[(tau T + H - k) mod N].
+// grid (N/T, B); each thread sums a strided share of k, then the workgroup reduces.
+__global__ void __launch_bounds__(256) k_s0(const float* __restrict__ x, int64_t N, int64_t T,
+                                            const float* __restrict__ h, int64_t len, int64_t H,
+                                            float* __restrict__ s0) {
+    __shared__ float red[256];
+    const int tau = blockIdx.x, NT = gridDim.x;
+    const int64_t b = blockIdx.y;
+    const float* xb = x + b * N;
+    const int64_t base = (int64_t)tau * T + H;       // x index = (base - k) mod N
+    float acc = 0.f;
+    for (int64_t k = threadIdx.x; k < len; k += blockDim.x) {
+        int64_t n = (base - k) % N;
+        if (n < 0) n += N;
+        acc += h[k] * xb[n];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) s0[b * NT + tau] = red[0];
+}
+
+// Its adjoint, added to gx: gx[n] += sum_tau gS0[tau] h[(tau T - n + H) mod N] where
+// that index is below len.  grid (ceil(N / 256), B).
+__global__ void __launch_bounds__(256) k_s0_bwd(const float* __restrict__ gs0, int64_t N, int64_t T, int NT,
+                                                const float* __restrict__ h, int64_t len, int64_t H,
+                                                float* __restrict__ gx) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = blockIdx.y;
+    if (n >= N) return;
+    const float* g = gs0 + b * NT;
+    float acc = 0.f;
+    for (int tau = 0; tau < NT; ++tau) {
+        int64_t k = ((int64_t)tau * T - n + H) % N;
+        if (k < 0) k += N;
+        if (k < len) acc += g[tau] * h[k];
+    }
+    gx[b * N + n] += acc;
 }
 
 // Second order: Y2[b][alpha][lambda][t] = (X_lambda (*) psi_alpha)[t 2^k2] for t < Ta,
@@ -480,8 +556,9 @@ __global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, in
                                                 const int64_t* __restrict__ vchoff, const int* __restrict__ nch,
                                                 int slot_mult, int nlt, int NTp, int NT, const float* __restrict__ PFt,
                                                 const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
-                                                const int* __restrict__ rowoffv, int NL, int n_alpha,
+                                                const int* __restrict__ rowoffv, int NL, int NLo, int n_alpha,
                                                 float* __restrict__ S2, const float* __restrict__ mu2, float eps) {
+    // NLo <= NL output rows (the unpadded lambda axis keeps the first NLo)
     constexpr int LC = 64, MB = 32, NG = 256 / TT, RR = MB / NG;
     __shared__ float Vs[LC][TT + 1];
     __shared__ float Ps[LC][MB];
@@ -491,10 +568,10 @@ __global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, in
     const int Lb = Lbv[beta], ro = rowoffv[beta];
     const float* PT = PFt + pfoff[beta];             // [Lb][NL]
     const float* Vb = Vp + b * vp_bstride;
-    float* o = S2 + ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NL) * (int64_t)NT;
+    float* o = S2 + ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NLo) * (int64_t)NT;
     const int tau = threadIdx.x % TT, grp = threadIdx.x / TT;
     const float inv = mulog_inv(mu2, (alpha * n_beta + beta) * 2 + th, eps);
-    for (int mb = 0; mb < NL; mb += MB)
+    for (int mb = 0; mb < NLo; mb += MB)
         for (int tb = 0; tb < NT; tb += TT) {
             float acc[RR];
 #pragma unroll
@@ -515,7 +592,7 @@ __global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, in
                 }
                 for (int e = threadIdx.x; e < LC * MB; e += 256) {
                     const int l = e / MB, mm = e - l * MB;
-                    Ps[l][mm] = l < lc && mb + mm < NL ? PT[(int64_t)(l0 + l) * NL + mb + mm] : 0.f;
+                    Ps[l][mm] = l < lc && mb + mm < NLo ? PT[(int64_t)(l0 + l) * NL + mb + mm] : 0.f;
                 }
                 __syncthreads();
                 for (int l = 0; l < lc; ++l) {
@@ -528,7 +605,7 @@ __global__ void __launch_bounds__(256) k_s2_out(const float* __restrict__ Vp, in
 #pragma unroll
                 for (int r = 0; r < RR; ++r) {
                     const int m = mb + grp * RR + r;
-                    if (m < NL) o[(int64_t)m * NT + tb + tau] = mulog_out(acc[r], mu2, inv);
+                    if (m < NLo) o[(int64_t)m * NT + tb + tau] = mulog_out(acc[r], mu2, inv);
                 }
         }
 }
@@ -660,7 +737,7 @@ __device__ __forceinline__ float group_sum(float a, int width) {
 // row before one LDS atomic per row segment.
 __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, const float* __restrict__ PFall,
                                                 const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
-                                                const int* __restrict__ rowoffv, int n_beta, int NL, int NT, int NTp,
+                                                const int* __restrict__ rowoffv, int n_beta, int NL, int NLo, int NT, int NTp,
                                                 int Mh, int Mp, int n_alpha, int avg, int stage_pf,
                                                 float* __restrict__ gV, float* __restrict__ gvmax, MuLogArg ml) {
     extern __shared__ float sm[];      // rowsum [Lb] | gS2 tile [NL][NT] | (stage_pf) PF [NL][Lb]
@@ -677,14 +754,14 @@ __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, c
     float* st = sm + Lb;
     float* pf = st + NL * NT;
     const float* PF = PFall + pfoff[beta];
-    const int64_t so = avg ? ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NL) * (int64_t)NT
+    const int64_t so = avg ? ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NLo) * (int64_t)NT
                            : ((b * n_alpha + alpha) * 2 * (int64_t)Mh + 2 * ro + th * Lb) * NT;
     const float* src = gS2 ? gS2 + so : nullptr;
     const float* osrc = ml.mu2 ? ml.o2 + so : nullptr;
     const float em = ml.mu2 ? ml.eps * ml.mu2[(alpha * n_beta + beta) * 2 + th] : 0.f;
     for (int l = threadIdx.x; l < Lb; l += blockDim.x) rowsum[l] = 0.f;
     if (src && avg) {
-        for (int e = threadIdx.x; e < NL * NT; e += blockDim.x)
+        for (int e = threadIdx.x; e < NLo * NT; e += blockDim.x)
             st[e] = mulog_cot(src[e], ml.mu2, em, osrc ? osrc[e] : 0.f);
         if (stage_pf)
             for (int e = threadIdx.x; e < NL * Lb; e += blockDim.x) pf[e] = PF[e];
@@ -699,7 +776,7 @@ __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, c
         if (valid && src && tau < NT) {
             if (avg) {
                 const float* pc = stage_pf ? pf + l : PF + l;
-                for (int m = 0; m < NL; ++m) acc += pc[m * Lb] * st[m * NT + tau];
+                for (int m = 0; m < NLo; ++m) acc += pc[m * Lb] * st[m * NT + tau];
             } else {
                 acc = mulog_cot(src[(int64_t)l * NT + tau], ml.mu2, em, osrc ? osrc[(int64_t)l * NT + tau] : 0.f);
             }
@@ -854,7 +931,7 @@ __global__ void __launch_bounds__(1024, 8) k_scal_bwd_a(const float2* __restrict
                                                     int n_alpha, const float* __restrict__ gS1,
                                                     const float* __restrict__ phiX, int Mphi, int logNT, int logNX,
                                                     float* __restrict__ gX, const float2* __restrict__ tw, int tw_log,
-                                                    MuLogArg ml) {
+                                                    MuLogArg ml, const float2* __restrict__ gYphi, int Tphi) {
     extern __shared__ float2 s[];
     const int lam = blockIdx.x, n1 = gridDim.x;
     const int64_t b = blockIdx.y;
@@ -863,7 +940,9 @@ __global__ void __launch_bounds__(1024, 8) k_scal_bwd_a(const float2* __restrict
     const float em = ml.mu1 ? ml.eps * ml.mu1[0] : 0.f;
     for (int t = threadIdx.x; t < NT; t += blockDim.x) {
         const int64_t i = (b * n1 + lam) * NT + t;
-        g1[lpad(t)] = make_float2(gS1 ? mulog_cot(gS1[i], ml.mu1, em, ml.mu1 ? ml.o1[i] : 0.f) : 0.f, 0.f);
+        float g = gS1 ? mulog_cot(gS1[i], ml.mu1, em, ml.mu1 ? ml.o1[i] : 0.f) : 0.f;
+        if (gYphi) g += gYphi[b * y_bstride + (int64_t)lam * Tphi + t].x;   // Re of phi_T's second-order rows
+        g1[lpad(t)] = make_float2(g, 0.f);
     }
     __syncthreads();
     lds_fft<16>(g1, logNT, 1, NT, tw, tw_log, false);
@@ -1148,13 +1227,18 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
                        P->psi1, P->band1, P->off1, Xh, w.Xh_pitch, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log));
     }
     LAUNCHCHK("scalogram");
-    if (s1) {
+    if (s1 || s.complete) {
+        // with the lowpass pairs the same launch fills the second-order rows of phi_T
         const int logNT = s.logN - s.logT;
-        JTFS_TIMED(JTFS_STAGE_S1, st, hipLaunchKernelGGL(k_s1, dim3(s.n1, (unsigned)B), dim3(256), sizeof(float2) * lpad_len(s.NT), st, Xh, w.Xh_pitch,
-                           P->phiX, s.Mphi, s.logNX, logNT, 1.0f / (float)s.NX, s1, P->tw, P->tw_log, ml.mu1, ml.eps));
+        const int aphi = s.n_alpha_psi;
+        float2* Yphi = s.complete ? Y2 + s.yoff[aphi] : nullptr;
+        JTFS_TIMED(JTFS_STAGE_S1, st, hipLaunchKernelGGL(k_s1, dim3(s.complete ? s.Kp : s.n1, (unsigned)B), dim3(256), sizeof(float2) * lpad_len(s.NT), st, Xh, w.Xh_pitch,
+                           P->phiX, s.Mphi, s.logNX, logNT, 1.0f / (float)s.NX, s1, P->tw, P->tw_log, ml.mu1, ml.eps,
+                           s.n1, Yphi, (int64_t)s.Kp * s.sumTp, s.complete ? s.Tp[aphi] : 0,
+                           (float*)(base + w.rowmax), aphi, s.n_alpha, s.Kp));
         LAUNCHCHK("first-order lowpass");
     }
-    for (int a = 0; a < s.n_alpha; ++a) {
+    for (int a = 0; a < s.n_alpha_psi; ++a) {
         const int logTa = s.logNX - s.k2[a];
         if (use_reg_rows(logTa, P->tune.reg_second)) {
             JTFS_TIMED(JTFS_STAGE_SECOND_ORDER, st,
@@ -1231,7 +1315,7 @@ int forward_impl(const jtfs_plan* P, const float* x, int64_t B, float* s1, float
         if (s.avg_fr) {
             auto k = s.NT <= 16 ? k_s2_out<16> : k_s2_out<32>;
             JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k, grid, dim3(256), 0, st, Vp, w.vp_bstride, P->d_vchoff,
-                               P->d_nch, mult, nlt, s.NTp, s.NT, P->PFt, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, s.n_alpha, s2,
+                               P->d_nch, mult, nlt, s.NTp, s.NT, P->PFt, P->d_pfoff, P->d_Lb, P->d_rowoff, s.NL, s.NLo, s.n_alpha, s2,
                                ml.mu2, ml.eps));
         } else {
             JTFS_TIMED(JTFS_STAGE_FREQ_LOWPASS, st, hipLaunchKernelGGL(k_v_out, grid, dim3(256), 0, st, Vp, w.vp_bstride, P->d_vchoff,
@@ -1253,6 +1337,7 @@ extern "C" int jtfs_forward(const jtfs_plan* P, const float* x, int64_t B, float
 // forward FFT of every gY2 row of alpha (length T_alpha, rows lambda < n1), in place
 static int gy2_row_fft(const jtfs_plan* P, int a, float2* gY2, int64_t yb, int64_t B, hipStream_t st) {
     const Shapes& s = P->s;
+    if (a >= s.n_alpha_psi) return JTFS_OK;      // phi_T's rows go back through the S1 adjoint untransformed
     const int logTa = s.logNX - s.k2[a];
     const int logC = logTa >= 12 ? 0 : 12 - logTa;
     const size_t lds = (size_t)(1 << logC) * (lpad_len(s.Ta[a]) + 1) * sizeof(float2);
@@ -1305,7 +1390,7 @@ int backward_impl(const jtfs_plan* P, const float* x, const float* gs1, const fl
     if (!s.tscat) {
         // every temporal rate in one launch
         JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_s2_bwd, dim3(s.n_beta + 1, 2 * s.n_alpha, (unsigned)B), dim3(256), s2_bwd_lds(s), st, gs2, P->PF, P->d_pfoff, P->d_Lb,
-                           P->d_rowoff, s.n_beta, s.NL, s.NT, s.NTp, s.Mh, s.Mp, s.n_alpha, (int)s.avg_fr,
+                           P->d_rowoff, s.n_beta, s.NL, s.NLo, s.NT, s.NTp, s.Mh, s.Mp, s.n_alpha, (int)s.avg_fr,
                            s2_bwd_stage(s), gV, (float*)(base + w.gvmax), ml));
         LAUNCHCHK("frequency lowpass adjoint");
     }
@@ -1375,7 +1460,8 @@ int backward_impl(const jtfs_plan* P, const float* x, const float* gs1, const fl
     const int logNT = s.logN - s.logT;
     const size_t lds_a = sizeof(float2) * (lpad_len(s.NX / 2) + 1 + lpad_len(s.NT));   // g1 at lpad(H) + 1
     JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_a, dim3(s.n1, (unsigned)B), dim3(1024), lds_a, st, gY2, yb, P->d_yoff, P->d_Tp, P->d_Ta, P->psi2,
-                       P->band2, P->off2, s.n_alpha, gs1, P->phiX, s.Mphi, logNT, s.logNX, gX, P->tw, P->tw_log, ml));
+                       P->band2, P->off2, s.n_alpha_psi, gs1, P->phiX, s.Mphi, logNT, s.logNX, gX, P->tw, P->tw_log, ml,
+                       s.complete ? gY2 + s.yoff[s.n_alpha_psi] : nullptr, s.complete ? s.Tp[s.n_alpha_psi] : 0));
     LAUNCHCHK("scalogram adjoint");
     if (use_reg_rows(s.logNX, P->tune.reg_first_adj)) {
         JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, launch_scal_bwd_b_r(P, xh, w.xh_pitch, gX, g1, B, st));
@@ -1407,6 +1493,26 @@ int mulog_check(const jtfs_plan* P, const float* mu1, const float* mu2, float ep
 extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs1, const float* gs2, float* gx,
                              int64_t B, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t st) {
     return backward_impl(P, x, gs1, gs2, gx, B, ws, ws_bytes, flags, MuLogArg{}, st);
+}
+
+extern "C" int jtfs_zeroth_order(const jtfs_plan* P, const float* x, int64_t B, float* s0, hipStream_t st) {
+    if (!P || !x || !s0) { set_error("null pointer"); return JTFS_EINVAL; }
+    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_EINVAL; }
+    const Shapes& s = P->s;
+    hipLaunchKernelGGL(k_s0, dim3((unsigned)s.NT, (unsigned)B), dim3(256), 0, st, x, s.N, s.T, P->phiN, P->phiN_len,
+                       P->phiN_half, s0);
+    LAUNCHCHK("zeroth order");
+    return JTFS_OK;
+}
+
+extern "C" int jtfs_zeroth_order_backward(const jtfs_plan* P, const float* gs0, int64_t B, float* gx, hipStream_t st) {
+    if (!P || !gs0 || !gx) { set_error("null pointer"); return JTFS_EINVAL; }
+    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_EINVAL; }
+    const Shapes& s = P->s;
+    hipLaunchKernelGGL(k_s0_bwd, dim3((unsigned)((s.N + 255) / 256), (unsigned)B), dim3(256), 0, st, gs0, s.N, s.T, s.NT,
+                       P->phiN, P->phiN_len, P->phiN_half, gx);
+    LAUNCHCHK("zeroth-order adjoint");
+    return JTFS_OK;
 }
 
 extern "C" int jtfs_forward_mulog(const jtfs_plan* P, const float* x, int64_t B, const float* mu1, const float* mu2,

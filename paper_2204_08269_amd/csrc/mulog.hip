@@ -107,12 +107,12 @@ static PathGeom geom(const jtfs_plan* P) {
     }
     g.n_paths = s.n_alpha * s.n_beta * 2;
     g.n_beta = s.n_beta;
-    g.NL = s.NL;
+    g.NL = s.NLo;
     g.NT = s.NT;
     g.Mh = s.Mh;
     g.avg = s.avg_fr ? 1 : 0;
     g.s1_per = (int64_t)s.n1 * s.NT;
-    g.s2_per = s.avg_fr ? (int64_t)g.n_paths * s.NL * s.NT : (int64_t)s.n_alpha * 2 * s.Mh * s.NT;
+    g.s2_per = s.avg_fr ? (int64_t)g.n_paths * s.NLo * s.NT : (int64_t)s.n_alpha * 2 * s.Mh * s.NT;
     g.rowoff = P->d_rowoff;
     g.Lb = P->d_Lb;
     return g;

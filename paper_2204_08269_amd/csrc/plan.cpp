@@ -80,11 +80,19 @@ int solve_shapes(const jtfs_params& p, Shapes* s) {
     if (!pow2(p.N) || !pow2(p.T) || !pow2(p.F)) { set_error("N, T and F must be powers of two"); return JTFS_EINVAL; }
     if (p.N < 16 || p.N > (int64_t(1) << 24)) { set_error("N must lie in [2^4, 2^24]"); return JTFS_EINVAL; }
     if (p.T > p.N) { set_error("T must not exceed N"); return JTFS_EINVAL; }
-    if (p.flags & ~(JTFS_NO_FREQ_AVERAGE | JTFS_TIME_SCATTERING)) { set_error("unknown flag bits"); return JTFS_EINVAL; }
+    if (p.flags & ~(JTFS_NO_FREQ_AVERAGE | JTFS_TIME_SCATTERING | JTFS_LOWPASS_PAIRS | JTFS_UNPAD_LAMBDA)) {
+        set_error("unknown flag bits"); return JTFS_EINVAL; }
     if ((p.flags & JTFS_NO_FREQ_AVERAGE) && (p.flags & JTFS_TIME_SCATTERING)) {
         set_error("JTFS_NO_FREQ_AVERAGE and JTFS_TIME_SCATTERING exclude each other"); return JTFS_EINVAL; }
+    if ((p.flags & JTFS_TIME_SCATTERING) && (p.flags & (JTFS_LOWPASS_PAIRS | JTFS_UNPAD_LAMBDA))) {
+        set_error("JTFS_LOWPASS_PAIRS and JTFS_UNPAD_LAMBDA need the frequential stage (not JTFS_TIME_SCATTERING)");
+        return JTFS_EINVAL; }
+    if ((p.flags & JTFS_NO_FREQ_AVERAGE) && (p.flags & JTFS_UNPAD_LAMBDA)) {
+        set_error("JTFS_UNPAD_LAMBDA applies to the frequency-averaged output (not JTFS_NO_FREQ_AVERAGE)");
+        return JTFS_EINVAL; }
     s->avg_fr = !(p.flags & JTFS_NO_FREQ_AVERAGE);
     s->tscat = (p.flags & JTFS_TIME_SCATTERING) != 0;
+    s->complete = (p.flags & JTFS_LOWPASS_PAIRS) != 0;
     if (p.Q1 < 1 || p.Q2 < 1 || p.Q_fr < 1 || p.Q1 > 64 || p.Q2 > 64 || p.Q_fr > 64) {
         set_error("Q1, Q2 and Q_fr must lie in [1, 64]"); return JTFS_EINVAL; }
     s->N = p.N; s->T = p.T; s->F = p.F;
@@ -105,7 +113,8 @@ int solve_shapes(const jtfs_params& p, Shapes* s) {
     Family& f2 = s->f2;
     f2.M = (int)s->NX;
     if (!family_centres(p.J - s->kX, p.Q2, &f2.xi, &f2.sigma)) { set_error("second-order filterbank is empty"); return JTFS_EINVAL; }
-    s->n_alpha = f2.n();
+    s->n_alpha_psi = f2.n();
+    s->n_alpha = f2.n() + (s->complete ? 1 : 0);     // the last rate: the lowpass phi_T
 
     // frequential, cycles per lambda bin on the zero-padded L grid
     s->logL = ilog2(s->n1);
@@ -115,7 +124,8 @@ int solve_shapes(const jtfs_params& p, Shapes* s) {
     Family& ff = s->ffr;
     ff.M = s->L;
     if (!family_centres(p.J_fr, p.Q_fr, &ff.xi, &ff.sigma)) { set_error("frequential filterbank is empty"); return JTFS_EINVAL; }
-    s->n_beta = ff.n();
+    s->n_beta_psi = ff.n();
+    s->n_beta = ff.n() + (s->complete ? 1 : 0);       // the last scale: the lowpass phi_F
 
     family_supports(&f1);
     family_supports(&f2);
@@ -125,13 +135,16 @@ int solve_shapes(const jtfs_params& p, Shapes* s) {
     s->NT = (int)(p.N / p.T);
     s->NTp = (int)rup(s->NT, 32);
     s->NL = (int)(s->L / p.F);
+    // unpadded: the rows m whose log-frequency m F falls on a first-order band (m F < n1)
+    s->NLo = (p.flags & JTFS_UNPAD_LAMBDA) ? (int)((s->n1 + p.F - 1) / p.F) : s->NL;
     s->Kp = (int)rup(s->n1, kKStep);
     s->k2.resize(s->n_alpha); s->Ta.resize(s->n_alpha); s->Tp.resize(s->n_alpha);
     s->nch.resize(s->n_alpha); s->chunk.resize(s->n_alpha);
     s->yoff.resize(s->n_alpha); s->phioff.resize(s->n_alpha); s->vchoff.resize(s->n_alpha);
     int64_t yo = 0, po = 0, co = 0;
     for (int a = 0; a < s->n_alpha; ++a) {
-        s->k2[a] = critical_log2(f2.sigma[a], s->logT - s->kX);
+        // phi_T keeps the capped rate: its rows land on the N/T frames undecimated
+        s->k2[a] = a < s->n_alpha_psi ? critical_log2(f2.sigma[a], s->logT - s->kX) : s->logT - s->kX;
         s->Ta[a] = (int)(s->NX >> s->k2[a]);
         s->Tp[a] = std::max(s->Ta[a], kTileTh);
         s->chunk[a] = std::min(s->Tp[a], kChunkT);
@@ -147,7 +160,7 @@ int solve_shapes(const jtfs_params& p, Shapes* s) {
     s->kfr.resize(s->n_beta); s->Lb.resize(s->n_beta); s->rowoff.resize(s->n_beta); s->pfoff.resize(s->n_beta);
     int ro = 0; int64_t pf = 0;
     for (int b = 0; b < s->n_beta; ++b) {
-        s->kfr[b] = critical_log2(ff.sigma[b], s->logF);
+        s->kfr[b] = critical_log2(b < s->n_beta_psi ? ff.sigma[b] : kSigma0 / (double)p.F, s->logF);
         s->Lb[b] = s->L >> s->kfr[b];
         s->rowoff[b] = ro; ro += s->Lb[b];
         s->pfoff[b] = pf; pf += (int64_t)s->NL * s->Lb[b];
@@ -222,10 +235,10 @@ int jtfs_query(const jtfs_params* p, jtfs_info* out) {
     if (st != JTFS_OK) return st;
     std::memset(out, 0, sizeof(*out));
     out->n1 = s.n1; out->n_alpha = s.n_alpha; out->n_beta = s.n_beta; out->L = s.L; out->kX = s.kX;
-    out->M_h = s.Mh; out->NX = s.NX; out->out_t = s.NT; out->out_l = s.NL; out->sum_T = s.sumT;
+    out->M_h = s.Mh; out->NX = s.NX; out->out_t = s.NT; out->out_l = s.NLo; out->sum_T = s.sumT;
     out->s1_per_signal = (int64_t)s.n1 * s.NT;
     out->s2_per_signal = s.tscat    ? (int64_t)s.n_alpha * s.n1 * s.NT
-                         : s.avg_fr ? (int64_t)s.n_alpha * s.n_beta * 2 * s.NL * s.NT
+                         : s.avg_fr ? (int64_t)s.n_alpha * s.n_beta * 2 * s.NLo * s.NT
                                     : (int64_t)s.n_alpha * 2 * s.Mh * s.NT;
     return st;
 }

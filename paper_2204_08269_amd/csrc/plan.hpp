@@ -50,7 +50,10 @@ struct Shapes {
     int64_t N = 0, NX = 0, T = 0, F = 0;
     bool avg_fr = true;              // eq. (3); false: eq. (4), no frequency lowpass
     bool tscat = false;              // time scattering: no frequential stage
+    bool complete = false;           // lowpass pairs: alpha = n_alpha_psi is phi_T, beta = n_beta_psi is phi_F
+    int n_alpha_psi = 0, n_beta_psi = 0;   // wavelets among the n_alpha / n_beta rates and scales
     int NT = 0, NTp = 0, NL = 0;     // N/T, padded to 32, L/F
+    int NLo = 0;                     // lambda rows of the S2 output: NL, or ceil(n1 / F) unpadded
     int Kp = 0;                      // n1 padded to kKStep
     int Mh = 0, Mp = 0;              // frequential rows per spin, padded to kTileL
     std::vector<int> k2, Ta, Tp, nch, chunk;   // per alpha: decimation, length, padded length, t-chunks
@@ -123,6 +126,8 @@ struct jtfs_plan {
     float* PF = nullptr;           // per beta [NL][Lb]: phi_F[(m F/2^kfr - l) mod Lb]
     float* PFt = nullptr;          // per beta [Lb][NL]: PF transposed (the forward lowpass reads rows l)
     float* phiX = nullptr;         // phi_T spectrum on the NX grid, bins 0..Mphi
+    float* phiN = nullptr;         // zeroth order: phi_T on the N grid, phiN[k] = phi_T[(k - phiN_half) mod N]
+    int64_t phiN_len = 0, phiN_half = 0;
     int* lam_range = nullptr;      // per 256-bin range of 0..N/2: first and last lambda touching it
     int64_t* d_yoff = nullptr;     // per alpha: offset of its Y2 block
     int* d_Tp = nullptr;           // per alpha: padded length

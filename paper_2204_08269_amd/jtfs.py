@@ -30,6 +30,11 @@ class JTFS:
     of L/2^kfr(beta) rows packed beta-major (s2_rows gives a slice's rows).
     With time_scattering=True, the time-scattering variant of sec. 4 instead (no
     frequential stage): S2 [B, n_alpha, n1, N/T].
+    lowpass_pairs=True adds phi_T as the last temporal rate and phi_F as the last
+    frequential scale (the pairs (psi_alpha, phi_F), (phi_T, psi_beta) and
+    (phi_T, phi_F) of the joint filterbank); unpad_lambda=True keeps the
+    ceil(n1 / F) log-frequency rows of S2 that fall on first-order bands (eq. (3)
+    only).  zeroth_order(x) gives S0 = (x * phi_T)(tau T).
     contraction: "split16" (FP16 matrix cores with split operands, the default
     where available), "split16_phase" (split16, and the forward stores the unit
     phase of the contraction so that a vjp that reuses the forward's workspace
@@ -37,13 +42,16 @@ class JTFS:
     differentiable through torch.autograd; forward() and vjp() call the library
     directly."""
 
-    def __init__(self, N, J, Q, J_fr, Q_fr, T, F, contraction=None, average_fr=True, time_scattering=False):
+    def __init__(self, N, J, Q, J_fr, Q_fr, T, F, contraction=None, average_fr=True, time_scattering=False,
+                 lowpass_pairs=False, unpad_lambda=False):
         if not torch.cuda.is_available():
             raise RuntimeError("JTFS needs a ROCm GPU (no CPU fallback)")
         self.lib = _lib.load()
         self.average_fr = bool(average_fr)
         self.time_scattering = bool(time_scattering)
-        self.params = _lib.params(N, J, Q, J_fr, Q_fr, T, F, average_fr, time_scattering)
+        self.lowpass_pairs = bool(lowpass_pairs)
+        self.params = _lib.params(N, J, Q, J_fr, Q_fr, T, F, average_fr, time_scattering, lowpass_pairs,
+                                  unpad_lambda)
         self.device = torch.device("cuda", torch.cuda.current_device())
         plan = ctypes.c_void_p()
         _lib.check(self.lib.jtfs_plan_create_ex(ctypes.byref(plan), ctypes.byref(self.params)))
@@ -70,6 +78,8 @@ class JTFS:
         """Rows of the (beta, theta) slice in the eq. (4) layout (average_fr=False)."""
         _, _, k = _lib.query_filters(self.params, 2)
         Lb = [self.info.L >> int(v) for v in k]
+        if self.lowpass_pairs:
+            Lb.append(self.info.M_h - sum(Lb))     # phi_F's rows
         o = 2 * sum(Lb[:beta]) + theta * Lb[beta]
         return slice(o, o + Lb[beta])
 
@@ -113,6 +123,22 @@ class JTFS:
         s2 = torch.empty((B,) + self.s2_shape, dtype=torch.float32, device=x.device)
         _lib.check(self.lib.jtfs_forward(self.plan, _ptr(x), B, _ptr(s1), _ptr(s2), _ptr(ws), ws.numel(), _stream()))
         return s1, s2
+
+    def zeroth_order(self, x):
+        """S0 [B, N/T] = (x * phi_T)(tau T)."""
+        x = self._check_x(x)
+        s0 = torch.empty((x.shape[0], self.info.out_t), dtype=torch.float32, device=x.device)
+        _lib.check(self.lib.jtfs_zeroth_order(self.plan, _ptr(x), x.shape[0], _ptr(s0), _stream()))
+        return s0
+
+    def zeroth_order_vjp(self, gs0, gx=None):
+        """Gradient of sum(gs0 * S0) with respect to x, added to gx (zeros if None)."""
+        gs0 = gs0.contiguous().float()
+        B = gs0.shape[0]
+        if gx is None:
+            gx = torch.zeros((B, self.N), dtype=torch.float32, device=gs0.device)
+        _lib.check(self.lib.jtfs_zeroth_order_backward(self.plan, _ptr(gs0), B, _ptr(gx), _stream()))
+        return gx
 
     def vjp(self, x, gs1, gs2, ws=None, reuse_forward=False):
         x = self._check_x(x)

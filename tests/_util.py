@@ -7,7 +7,8 @@ from oracle import jtfs_oracle as O
 
 
 def oracle_plan(p):
-    return O.Plan(p["N"], p["J"], p["Q"][0], p["Q"][1], p["J_fr"], p["Q_fr"], p["T"], p["F"])
+    return O.Plan(p["N"], p["J"], p["Q"][0], p["Q"][1], p["J_fr"], p["Q_fr"], p["T"], p["F"],
+                  lowpass_pairs=p.get("lowpass_pairs", False), unpad=p.get("unpad", False))
 
 
 def path_errors(got, ref, path_axes):

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import jtfs_oracle as O
 from tests._util import oracle_plan
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -93,10 +94,31 @@ def test_unknown_flag_bits_rejected(L):
     p = synth.PARAMS[1]
     prm = L.params(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"])
     info = L.Info()
-    for bad in (4, 3):                      # an unknown bit; both variants at once
+    # an unknown bit; both variants at once; lowpass pairs or unpadding with time
+    # scattering; unpadding without frequential averaging
+    for bad in (16, 3, 2 | 4, 2 | 8, 1 | 8):
         prm.flags = bad
         assert L.load().jtfs_query(ctypes.byref(prm), ctypes.byref(info)) == L.JTFS_EINVAL
     assert ctypes.sizeof(L.Params) == 48
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 5])
+def test_lowpass_pairs_and_unpadded_sizes(L, cfg):
+    """Sizes with the lowpass pairs (one more rate and scale, phi_F's rows at the
+    L/F grid) and with the unpadded lambda axis (ceil(n1 / F) rows), against the
+    oracle's plan with the same options."""
+    p = synth.PARAMS[cfg]
+    P = O.Plan(p["N"], p["J"], p["Q"][0], p["Q"][1], p["J_fr"], p["Q_fr"], p["T"], p["F"],
+               lowpass_pairs=True, unpad=True)
+    i = L.query(L.params(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"], lowpass_pairs=True,
+                         unpad_lambda=True))
+    assert (i.n_alpha, i.n_beta, i.M_h, i.out_l, i.sum_T) == (P.n_alpha, P.n_beta, P.M_h, P.out_l,
+                                                             sum(P.T_alpha(a) for a in range(P.n_alpha)))
+    assert i.out_l == -(-P.n1 // p["F"])
+    assert i.s2_per_signal == int(np.prod(P.s2_shape()))
+    j = L.query(L.params(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"]))
+    assert (i.n_alpha, i.n_beta) == (j.n_alpha + 1, j.n_beta + 1)
+    assert i.M_h == j.M_h + j.L // p["F"]           # phi_F kept at its critical rate: L / F rows
 
 
 def test_null_pointers_rejected(L):

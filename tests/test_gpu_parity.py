@@ -18,7 +18,8 @@ TOL_FD = 1e-3       # gradient against FP64 central finite differences
 def gpu_op(p, contraction=None, average_fr=True, time_scattering=False):
     from paper_2204_08269_amd.jtfs import JTFS
     return JTFS(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"], contraction=contraction,
-                average_fr=average_fr, time_scattering=time_scattering)
+                average_fr=average_fr, time_scattering=time_scattering,
+                lowpass_pairs=p.get("lowpass_pairs", False), unpad_lambda=p.get("unpad", False))
 
 
 MODES = ["fp32", "split16"]
@@ -569,6 +570,88 @@ def test_fused_mulog_matches_oracle(variant, mode):
             ref = O.jtfs_vjp(xb, f1[b], f2[b], P, average_fr=avg)
         err = rel_l2(gx[b], ref)
         assert err <= TOL_VJP, f"signal {b}: gradient relative L2 {err:.3e}"
+
+
+# Lowpass pairs: phi_T as one more temporal rate (its second-order rows are the S1
+# rows) and phi_F as one more frequential scale, through every contraction mode.
+LP_SHAPES = [P1, RAGGED[2], dict(N=4096, J=7, Q=(8, 1), J_fr=3, Q_fr=1, T=64, F=2)]
+
+
+@pytest.mark.parametrize("mode", ["fp32", "split16", "split16_phase"])
+@pytest.mark.parametrize("average_fr", [True, False])
+@pytest.mark.parametrize("p", LP_SHAPES, ids=lambda p: f"N{p['N']}_T{p['T']}_Q{p['Q'][0]}")
+def test_lowpass_pairs_forward_and_vjp(p, average_fr, mode):
+    q = dict(p, lowpass_pairs=True)
+    P = oracle_plan(q)
+    rng = np.random.default_rng(606 + p["N"])
+    x = (rng.standard_normal((2, p["N"])) * 0.5).astype(np.float32)
+    op = gpu_op(q, contraction=mode, average_fr=average_fr)
+    assert (op.info.n_alpha, op.info.n_beta) == (P.n_alpha, P.n_beta)
+    xt = torch.from_numpy(x).cuda()
+    ws = op.new_workspace(2)
+    s1, s2 = op.forward(xt, ws)
+    g1, g2 = s1.cpu().numpy(), s2.cpu().numpy()
+    gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape(average_fr), seed=37)
+    g = op.vjp(xt, torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda(), ws=ws,
+               reuse_forward=(mode == "split16_phase")).cpu().numpy()
+    for b in range(2):
+        xb = x[b].astype(np.float64)
+        r1, r2 = O.jtfs(xb, P, average_fr=average_fr)
+        if average_fr:
+            check_paths(g1[b], g2[b], r1, r2)
+        else:
+            check_paths(g1[b], unpack_eq4(g2[b], P), r1, unpack_eq4(r2, P))
+        ref = O.jtfs_vjp(xb, gs1[b].astype(np.float64), gs2[b].astype(np.float64), P, average_fr=average_fr)
+        err = rel_l2(g[b], ref)
+        assert err <= TOL_VJP, f"signal {b}: gradient relative L2 {err:.3e}"
+
+
+@pytest.mark.parametrize("mode", ["split16", "split16_phase"])
+@pytest.mark.parametrize("p", [P1, RAGGED[2]], ids=lambda p: f"N{p['N']}_Q{p['Q'][0]}")
+def test_unpadded_lambda_forward_and_vjp(p, mode):
+    """S2 with the ceil(n1 / F) rows on first-order bands, with and without the
+    lowpass pairs, and the gradient of a cotangent on those rows."""
+    for lp in (False, True):
+        q = dict(p, unpad=True, lowpass_pairs=lp)
+        P = oracle_plan(q)
+        x = (np.random.default_rng(77).standard_normal((2, p["N"])) * 0.5).astype(np.float32)
+        op = gpu_op(q, contraction=mode)
+        assert op.s2_shape[-2] == -(-P.n1 // p["F"]) < P.L // p["F"]
+        xt = torch.from_numpy(x).cuda()
+        ws = op.new_workspace(2)
+        s1, s2 = op.forward(xt, ws)
+        gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape(), seed=41)
+        g = op.vjp(xt, torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda(), ws=ws,
+                   reuse_forward=True).cpu().numpy()
+        for b in range(2):
+            xb = x[b].astype(np.float64)
+            r1, r2 = O.jtfs(xb, P)
+            check_paths(s1.cpu().numpy()[b], s2.cpu().numpy()[b], r1, r2)
+            ref = O.jtfs_vjp(xb, gs1[b].astype(np.float64), gs2[b].astype(np.float64), P)
+            assert rel_l2(g[b], ref) <= TOL_VJP
+
+
+@pytest.mark.parametrize("p", [P1, RAGGED[0], synth.PARAMS[5]], ids=lambda p: f"N{p['N']}_T{p['T']}")
+def test_zeroth_order_matches_oracle(p):
+    """S0 = (x * phi_T)(tau T) and its adjoint (added to a given gx) against the
+    oracle, up to T = N (one frame) and the 2^18-sample workload."""
+    P = oracle_plan(p)
+    rng = np.random.default_rng(55)
+    x = rng.standard_normal((2, p["N"])).astype(np.float32)
+    op = gpu_op(p)
+    s0 = op.zeroth_order(torch.from_numpy(x).cuda()).cpu().numpy()
+    g = rng.standard_normal((2, P.out_t)).astype(np.float32)
+    gt = torch.from_numpy(g).cuda()
+    gx = op.zeroth_order_vjp(gt).cpu().numpy()
+    # the adjoint adds to what gx holds (one FP32 addition per sample)
+    base = rng.standard_normal((2, p["N"])).astype(np.float32)
+    acc = op.zeroth_order_vjp(gt, torch.from_numpy(base).cuda()).cpu().numpy()
+    assert np.max(np.abs(acc - (base + gx))) <= 1e-6 * np.max(np.abs(base))
+    for b in range(2):
+        ref = O.zeroth_order(x[b].astype(np.float64), P)
+        assert rel_l2(s0[b], ref) <= TOL, rel_l2(s0[b], ref)
+        refg = O.zeroth_order_adj(g[b].astype(np.float64), P)
+        assert rel_l2(gx[b], refg) <= TOL_VJP
 
 
 @pytest.mark.parametrize("mode", ["split16", "split16_phase"])

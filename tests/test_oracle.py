@@ -216,6 +216,127 @@ def test_unaveraged_pure_tone_and_frame_shift(P1, x1):
 
 # ---------------------------------------------------------------- adjoints
 
+# ------------------------------------ lowpass pairs, unpadded lambda, zeroth order
+
+def _plan_opts(p, **kw):
+    return O.Plan(p["N"], p["J"], p["Q"][0], p["Q"][1], p["J_fr"], p["Q_fr"], p["T"], p["F"], **kw)
+
+
+def test_lowpass_pairs_extend_the_wavelet_paths(P1, x1):
+    """The lowpass pairs add one rate (phi_T) and one scale (phi_F): S1 and every
+    wavelet-wavelet slice are those of the plain transform."""
+    Pc = _plan_opts(synth.PARAMS[1], lowpass_pairs=True)
+    S1, S2 = O.jtfs(x1, P1)
+    C1, C2 = O.jtfs(x1, Pc)
+    assert C2.shape == (P1.n_alpha + 1, P1.n_beta + 1, 2, P1.out_l, P1.out_t)
+    assert np.array_equal(C1, S1)
+    assert np.max(np.abs(C2[:-1, :-1] - S2)) <= 1e-14 * np.max(S2)
+    assert Pc.k2[-1] == int(np.log2(Pc.T)) - Pc.kX and Pc.T_alpha(Pc.n_alpha - 1) == Pc.out_t
+    assert Pc.k_fr[-1] == int(np.log2(Pc.F)) and Pc.L_beta(Pc.n_beta - 1) == Pc.L // Pc.F
+
+
+def test_lowpass_pairs_spins_coincide(x1):
+    """A lowpass along lambda (real and even) or along time (a real second-order
+    row) leaves no orientation: both spin slots agree, while the wavelet pairs of
+    a chirp signal differ between spins."""
+    Pc = _plan_opts(synth.PARAMS[1], lowpass_pairs=True)
+    _, C2 = O.jtfs(x1, Pc)
+    ref = np.max(C2)
+    assert np.max(np.abs(C2[:, -1, 0] - C2[:, -1, 1])) <= 1e-12 * ref
+    assert np.max(np.abs(C2[-1, :, 0] - C2[-1, :, 1])) <= 1e-12 * ref
+    assert np.max(np.abs(C2[:-1, :-1, 0] - C2[:-1, :-1, 1])) > 1e-2 * ref
+
+
+@pytest.mark.parametrize("p", [synth.PARAMS[1], dict(N=256, J=5, Q=(8, 2), J_fr=3, Q_fr=2, T=32, F=4)])
+def test_double_lowpass_pair_keeps_the_sum_of_s1(p):
+    """(phi_T, phi_F) is positive and linear in S1: the time lowpass at the frame
+    rate keeps sums (DC gain 1) and phi_F sampled at its critical rate F keeps 1/F
+    of the sum up to aliasing of order exp(-50): F * sum S2[phi_T, phi_F] = sum S1."""
+    Pc = _plan_opts(p, lowpass_pairs=True)
+    x = np.random.default_rng(41).standard_normal(Pc.N)
+    S1, S2 = O.jtfs(x, Pc, alphas=[Pc.n_alpha - 1])
+    for th in range(2):
+        assert abs(Pc.F * S2[-1, -1, th].sum() - S1.sum()) <= 1e-12 * S1.sum()
+
+
+def test_lowpass_pairs_pure_tone(P1):
+    """A pure tone has time-constant scalogram rows: the wavelet rates give zero
+    in every pair, and phi_T's slices are constant along time and not zero."""
+    Pc = _plan_opts(synth.PARAMS[1], lowpass_pairs=True)
+    _, C2 = O.jtfs(synth.tone(Pc.N, 301, 0.7, 0.3), Pc)
+    ref = np.max(np.abs(C2))
+    assert ref > 0
+    assert np.max(np.abs(C2[:-1])) <= 1e-12 * ref
+    assert np.max(np.abs(C2[-1] - C2[-1][..., :1])) <= 1e-12 * ref
+
+
+@pytest.mark.parametrize("p", SMALL)
+@pytest.mark.parametrize("average_fr", [True, False])
+def test_lowpass_pairs_cascade_matches_direct_sums(p, average_fr):
+    P = _plan_opts(p, lowpass_pairs=True)
+    x = np.random.default_rng(p["N"] + 11).standard_normal(p["N"])
+    a1, a2 = O.jtfs(x, P, average_fr=average_fr)
+    b1, b2 = O.jtfs_direct(x, P, average_fr=average_fr)
+    assert np.max(np.abs(a2 - b2)) <= 1e-12 * np.max(np.abs(b2))
+
+
+def test_lowpass_pairs_vjp_matches_finite_differences(x1):
+    Pc = _plan_opts(synth.PARAMS[1], lowpass_pairs=True)
+    gS1, gS2 = synth.cotangents(Pc.s1_shape(), Pc.s2_shape(), seed=31)
+    g = O.jtfs_vjp(x1, gS1, gS2, Pc)
+    rng = np.random.default_rng(9)
+    for _ in range(2):
+        v = rng.standard_normal(Pc.N)
+        h = 1e-6
+        fd = (O.loss(x1 + h * v, gS1, gS2, Pc) - O.loss(x1 - h * v, gS1, gS2, Pc)) / (2 * h)
+        assert abs(fd - g @ v) <= 1e-7 * abs(fd)
+
+
+def test_unpadded_rows_are_the_leading_rows(P1, x1):
+    """Unpadding keeps the rows m < ceil(n1 / F), whose log-frequency m F lies on
+    a first-order band; the rest of the output is unchanged."""
+    Pu = _plan_opts(synth.PARAMS[1], unpad=True)
+    S1, S2 = O.jtfs(x1, P1)
+    U1, U2 = O.jtfs(x1, Pu)
+    nl = -(-P1.n1 // P1.F)
+    assert Pu.out_l == nl < P1.out_l and (nl - 1) * P1.F < P1.n1 <= nl * P1.F
+    assert np.array_equal(U1, S1) and np.max(np.abs(U2 - S2[..., :nl, :])) <= 1e-14 * np.max(S2)
+
+
+def test_unpadded_rows_of_the_convnet_input():
+    """Sec. 4.2 parametrises the transform for a 44 x 32 output (log-frequency x
+    time).  The unpadded row count ceil(n1 / F) depends on n1, which follows the
+    filterbank readings here (183 first-order bands where the paper's filterbank
+    gives about 176): it lands within two rows of the stated 44, against 64 rows
+    padded, and the frame count is the stated 32."""
+    g = GOLDEN["convnet_input_lambda_rows"]
+    P = O.Plan(g["N"], g["J"], g["Q1"], 1, 6, 1, g["T"], g["F"], unpad=True)
+    assert P.out_l == -(-P.n1 // g["F"]) and abs(P.out_l - g["value"]) <= 2
+    assert P.L // g["F"] == 64 and P.out_t == 32
+
+
+def test_zeroth_order_closed_forms(P1):
+    """S0 = x * phi_T at the frames: a constant passes unchanged (DC gain 1); a
+    tone on bin m is scaled by phi_T_hat(m/N), the Gaussian of width 0.1/T."""
+    N, T = P1.N, P1.T
+    assert np.max(np.abs(O.zeroth_order(np.full(N, 2.5), P1) - 2.5)) <= 1e-13
+    m, A, ph = 5, 0.7, 0.3
+    s0 = O.zeroth_order(synth.tone(N, m, A, ph), P1)
+    tau = np.arange(N // T)
+    gain = np.exp(-(m / N) ** 2 / (2 * (0.1 / T) ** 2))
+    assert 0.1 < gain < 0.9
+    assert np.max(np.abs(s0 - A * gain * np.cos(2 * np.pi * m * tau * T / N + ph))) <= 1e-13
+
+
+def test_zeroth_order_adjoint(P1):
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal(P1.N)
+    g = rng.standard_normal(P1.out_t)
+    lhs = float(O.zeroth_order(x, P1) @ g)
+    rhs = float(x @ O.zeroth_order_adj(g, P1))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
 def _rdot(a, b):
     return float(np.real(np.sum(np.conj(a) * b)))
 
