@@ -367,7 +367,11 @@ void jtfs_texture_destroy(jtfs_texture* tex);
  * (split, first run), (split, second run), (FP32, first), (FP32, second), (split with
  * stored phase, first), (split with stored phase, second); 0 for candidates not run.
  * fwd_ms, bwd_ms: the chosen mode's forward contraction and backward contraction
- * per step with 32 x 32 and 16 x 16 tiles (0 where not run). */
+ * per step with 32 x 32 and 16 x 16 tiles (0 where not run).  Then, for the chosen
+ * mode and tiles, one run with every register-resident stage in radix-8 passes
+ * (where rows of 2^14 points or more exist) and one with 8192-point in-LDS
+ * workgroups (where rows of 2^12 points or fewer exist) settle those bits per
+ * stage (a stage must gain 1 % to take the other setting). */
 #define JTFS_REG_SCALOGRAM    1
 #define JTFS_REG_SECOND_ORDER 2
 #define JTFS_REG_ROW_FFT      4
@@ -378,6 +382,17 @@ void jtfs_texture_destroy(jtfs_texture* tex);
 /* ... and the stored-phase backward in 16 x 16 tiles (each wave 16 columns t and
  * all rows i, one pass for any K; N/T <= 32), else 32 x 32 tiles. */
 #define JTFS_TUNE_BWD_TILE16  32
+/* ... the largest radix of the register-resident row transforms' passes, per
+ * stage: radix 8 where the bit is set, else radix 16 (every pass of a 2^14-point
+ * transform held as 16 values per thread). */
+#define JTFS_TUNE_RADIX8_SCALOGRAM    64
+#define JTFS_TUNE_RADIX8_SECOND_ORDER 128
+#define JTFS_TUNE_RADIX8_ROW_FFT      256
+#define JTFS_TUNE_RADIX8_FIRST_ADJ    512
+/* ... and 8192 points per workgroup in the in-LDS second-order and gY2 row
+ * transforms (rows shorter than 2^13: more rows per workgroup, fewer
+ * workgroups of twice the LDS), else 4096. */
+#define JTFS_TUNE_LDS_BATCH8K 1024
 typedef struct {
     int32_t contraction;
     int32_t reg_rows;                 /* including JTFS_TUNE_FWD_TILE16 */

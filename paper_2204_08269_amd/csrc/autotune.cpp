@@ -6,10 +6,13 @@
 // register-resident or the in-LDS transform in each of the four stages that have
 // both (scalogram, second order, gY2 row FFTs, first-order adjoint).  Every
 // candidate runs whole fwd+bwd steps; the per-stage HIP-event timers attribute
-// the time, so the five binary choices are settled from two runs per contraction
+// the time, so these binary choices are settled from two runs per contraction
 // mode (all register-resident with 32 x 32 tiles, all in LDS with 16 x 16 tiles)
-// rather than from thirty-two.  Results can be kept in a text file keyed by the
-// device and the plan's shape (JTFS_TUNE_CACHE).
+// rather than from thirty-two.  For the chosen mode, one more run each settles
+// the largest radix of the register-resident transforms' passes (16 or 8, per
+// stage) and the points per workgroup of the in-LDS row transforms (4096 or
+// 8192, i.e. how many workgroups share a CU's LDS).  Results can be kept in a
+// text file keyed by the device and the plan's shape (JTFS_TUNE_CACHE).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,12 +45,23 @@ void set_rows(jtfs_plan* P, int mask) {
     P->tune.reg_first_adj = (mask & JTFS_REG_FIRST_ADJ) != 0;
     P->tune.fwd16 = (mask & JTFS_TUNE_FWD_TILE16) != 0;
     P->tune.bwd16 = (mask & JTFS_TUNE_BWD_TILE16) != 0;
+    P->tune.r8_scalogram = (mask & JTFS_TUNE_RADIX8_SCALOGRAM) != 0;
+    P->tune.r8_second = (mask & JTFS_TUNE_RADIX8_SECOND_ORDER) != 0;
+    P->tune.r8_rowfft = (mask & JTFS_TUNE_RADIX8_ROW_FFT) != 0;
+    P->tune.r8_first_adj = (mask & JTFS_TUNE_RADIX8_FIRST_ADJ) != 0;
+    P->tune.batch8k = (mask & JTFS_TUNE_LDS_BATCH8K) != 0;
 }
+
+constexpr int kRadix8Bits = JTFS_TUNE_RADIX8_SCALOGRAM | JTFS_TUNE_RADIX8_SECOND_ORDER | JTFS_TUNE_RADIX8_ROW_FFT |
+                            JTFS_TUNE_RADIX8_FIRST_ADJ;
 
 int get_rows(const jtfs_plan* P) {
     return (P->tune.reg_scalogram ? JTFS_REG_SCALOGRAM : 0) | (P->tune.reg_second ? JTFS_REG_SECOND_ORDER : 0) |
            (P->tune.reg_rowfft ? JTFS_REG_ROW_FFT : 0) | (P->tune.reg_first_adj ? JTFS_REG_FIRST_ADJ : 0) |
-           (P->tune.fwd16 ? JTFS_TUNE_FWD_TILE16 : 0) | (P->tune.bwd16 ? JTFS_TUNE_BWD_TILE16 : 0);
+           (P->tune.fwd16 ? JTFS_TUNE_FWD_TILE16 : 0) | (P->tune.bwd16 ? JTFS_TUNE_BWD_TILE16 : 0) |
+           (P->tune.r8_scalogram ? JTFS_TUNE_RADIX8_SCALOGRAM : 0) |
+           (P->tune.r8_second ? JTFS_TUNE_RADIX8_SECOND_ORDER : 0) | (P->tune.r8_rowfft ? JTFS_TUNE_RADIX8_ROW_FFT : 0) |
+           (P->tune.r8_first_adj ? JTFS_TUNE_RADIX8_FIRST_ADJ : 0) | (P->tune.batch8k ? JTFS_TUNE_LDS_BATCH8K : 0);
 }
 
 // Cache key: the device's architecture and name, the plan parameters and B.
@@ -144,7 +158,7 @@ int run_steps(jtfs_plan* P, const float* x, int64_t B, float* s1, float* s2, flo
 extern "C" int jtfs_plan_set_tuning(jtfs_plan* P, int contraction, int reg_rows) {
     if (!P) { set_error("null plan"); return JTFS_EINVAL; }
     if (reg_rows & ~(JTFS_REG_SCALOGRAM | JTFS_REG_SECOND_ORDER | JTFS_REG_ROW_FFT | JTFS_REG_FIRST_ADJ |
-                     JTFS_TUNE_FWD_TILE16 | JTFS_TUNE_BWD_TILE16)) {
+                     JTFS_TUNE_FWD_TILE16 | JTFS_TUNE_BWD_TILE16 | kRadix8Bits | JTFS_TUNE_LDS_BATCH8K)) {
         set_error("unknown row-kernel bits"); return JTFS_EINVAL; }
     const int rc = jtfs_plan_set_contraction(P, contraction);
     if (rc != JTFS_OK) return rc;
@@ -292,14 +306,51 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
     if (buse16) rows |= JTFS_TUNE_BWD_TILE16;
     P->contraction = modes[best_m];
     set_rows(P, rows);
-    double stage_final[JTFS_NUM_STAGES];
-    const int rc = run_steps(P, x, B, (float*)s1.p, (float*)s2.p, (float*)gx.p, ws.p, wsb, reps, st, &out->step_ms,
-                             stage_final);
-    if (rc != JTFS_OK) {
+    auto fail = [&](int rc) {
         P->contraction = saved_mode;
         set_rows(P, saved_rows);
         return rc;
+    };
+    // radix of the register-resident passes and points per in-LDS workgroup: one
+    // run each against the choice so far, settled per stage
+    bool has_long = s.logNX >= kRegMinLogRows, has_short = false;
+    for (int a = 0; a < s.n_alpha_psi; ++a) {
+        has_long = has_long || s.logNX - s.k2[a] >= kRegMinLogRows;
+        has_short = has_short || s.logNX - s.k2[a] <= 12;
     }
+    if (has_long || has_short) {
+        double base_ms = 0.0, base_st[JTFS_NUM_STAGES];
+        int rc = run_steps(P, x, B, (float*)s1.p, (float*)s2.p, (float*)gx.p, ws.p, wsb, reps, st, &base_ms, base_st);
+        if (rc != JTFS_OK) return fail(rc);
+        int next = rows;
+        if (has_long) {
+            double ms = 0.0, st8[JTFS_NUM_STAGES];
+            set_rows(P, rows | kRadix8Bits);
+            rc = run_steps(P, x, B, (float*)s1.p, (float*)s2.p, (float*)gx.p, ws.p, wsb, reps, st, &ms, st8);
+            if (rc != JTFS_OK) return fail(rc);
+            const int kstage[4] = {JTFS_STAGE_SCALOGRAM, JTFS_STAGE_SECOND_ORDER, JTFS_STAGE_SECOND_ADJ_FFT,
+                                   JTFS_STAGE_FIRST_ADJ};
+            const int kbit[4] = {JTFS_TUNE_RADIX8_SCALOGRAM, JTFS_TUNE_RADIX8_SECOND_ORDER, JTFS_TUNE_RADIX8_ROW_FFT,
+                                 JTFS_TUNE_RADIX8_FIRST_ADJ};
+            for (int q = 0; q < 4; ++q)
+                if (st8[kstage[q]] < 0.99 * base_st[kstage[q]]) next |= kbit[q];
+        }
+        if (has_short) {
+            double ms = 0.0, stb[JTFS_NUM_STAGES];
+            set_rows(P, rows | JTFS_TUNE_LDS_BATCH8K);
+            rc = run_steps(P, x, B, (float*)s1.p, (float*)s2.p, (float*)gx.p, ws.p, wsb, reps, st, &ms, stb);
+            if (rc != JTFS_OK) return fail(rc);
+            const double a0 = base_st[JTFS_STAGE_SECOND_ORDER] + base_st[JTFS_STAGE_SECOND_ADJ_FFT];
+            const double a1 = stb[JTFS_STAGE_SECOND_ORDER] + stb[JTFS_STAGE_SECOND_ADJ_FFT];
+            if (a1 < 0.99 * a0) next |= JTFS_TUNE_LDS_BATCH8K;
+        }
+        rows = next;
+        set_rows(P, rows);
+    }
+    double stage_final[JTFS_NUM_STAGES];
+    const int rc = run_steps(P, x, B, (float*)s1.p, (float*)s2.p, (float*)gx.p, ws.p, wsb, reps, st, &out->step_ms,
+                             stage_final);
+    if (rc != JTFS_OK) return fail(rc);
     out->contraction = P->contraction;
     out->reg_rows = rows;
     cache_store(key, out->contraction, rows, out->step_ms);

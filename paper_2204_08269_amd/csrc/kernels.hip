@@ -1246,7 +1246,7 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
             LAUNCHCHK("second order");
             continue;
         }
-        const int rows = std::min(64, std::max(1, 4096 >> logTa));   // <= 64: row-maximum slots
+        const int rows = std::min(64, std::max(1, (1 << lds_batch_log(P->tune)) >> logTa));   // <= 64: row-maximum slots
         const size_t lds = sizeof(float2) * rows * lpad_len(s.Ta[a]);
         const Family& f2 = s.f2;
         // packed second-order spectrum of alpha: the plan's device table at its offset
@@ -1339,7 +1339,8 @@ static int gy2_row_fft(const jtfs_plan* P, int a, float2* gY2, int64_t yb, int64
     const Shapes& s = P->s;
     if (a >= s.n_alpha_psi) return JTFS_OK;      // phi_T's rows go back through the S1 adjoint untransformed
     const int logTa = s.logNX - s.k2[a];
-    const int logC = logTa >= 12 ? 0 : 12 - logTa;
+    const int lb = lds_batch_log(P->tune);
+    const int logC = logTa >= lb ? 0 : lb - logTa;
     const size_t lds = (size_t)(1 << logC) * (lpad_len(s.Ta[a]) + 1) * sizeof(float2);
     if (use_reg_rows(logTa, P->tune.reg_rowfft)) {
         JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st,

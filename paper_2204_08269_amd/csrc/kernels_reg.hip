@@ -33,7 +33,7 @@ __device__ __forceinline__ float2 fold_at(const float2* __restrict__ src, const 
 // of reg_fft), folded from src * ps over [lo, hi].  When the band fits the row
 // every bin receives at most one band sample, and the loads go out four
 // elements at a time with no loop between them.
-template <int LOGM>
+template <int LOGM, int LRM = reg_lr_max(kRegE)>
 __device__ __forceinline__ void fold_inputs(float2 (&v)[kRegE], const float2* __restrict__ src,
                                             const float* __restrict__ ps, int lo, int hi) {
     constexpr int M = 1 << LOGM;
@@ -43,7 +43,7 @@ __device__ __forceinline__ void fold_inputs(float2 (&v)[kRegE], const float2* __
             float g[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int p = reg_input_pos<LOGM, kRegE>(e0 + q);
+                const int p = reg_input_pos<LOGM, kRegE, LRM>(e0 + q);
                 const int m = lo + ((p - lo) & (M - 1));
                 const bool ok = m <= hi;
                 v[e0 + q] = ok ? src[m] : make_float2(0.f, 0.f);
@@ -55,7 +55,7 @@ __device__ __forceinline__ void fold_inputs(float2 (&v)[kRegE], const float2* __
         return;
     }
 #pragma unroll
-    for (int e = 0; e < kRegE; ++e) v[e] = fold_at(src, ps, lo, hi, LOGM, reg_input_pos<LOGM, kRegE>(e));
+    for (int e = 0; e < kRegE; ++e) v[e] = fold_at(src, ps, lo, hi, LOGM, reg_input_pos<LOGM, kRegE, LRM>(e));
 }
 
 // Rows of 2^15 points run as two 2^14-point register transforms:
@@ -70,7 +70,7 @@ __device__ __forceinline__ void fold_inputs(float2 (&v)[kRegE], const float2* __
 // u[p] + u[p+m]; half 1: (u[p] - u[p+m]) e^{+2 pi i p/n}.  Without the split
 // (TWO false) each thread folds u at its own input positions; no LDS is used.
 // (KU: positions whose loads a thread issues together in the batched fold.)
-template <bool TWO, int KU = 4>
+template <bool TWO, int KU = 4, int LRM = reg_lr_max(kRegE)>
 __device__ __forceinline__ void load_dif(float2 (&v)[kRegE], float* A, float* B, const float2* __restrict__ src,
                                          const float* __restrict__ ps, int lo, int hi, int logn, int half,
                                          const float2* __restrict__ tw, int tw_log, bool zero) {
@@ -80,7 +80,7 @@ __device__ __forceinline__ void load_dif(float2 (&v)[kRegE], float* A, float* B,
 #pragma unroll
             for (int e = 0; e < kRegE; ++e) v[e] = make_float2(0.f, 0.f);
         } else {
-            fold_inputs<kRegMinLog>(v, src, ps, lo, hi);
+            fold_inputs<kRegMinLog, LRM>(v, src, ps, lo, hi);
         }
         return;
     }
@@ -134,13 +134,13 @@ __device__ __forceinline__ void load_dif(float2 (&v)[kRegE], float* A, float* B,
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < kRegE; ++e) {
-        const int q = reg_input_pos<kRegMinLog, kRegE>(e);
+        const int q = reg_input_pos<kRegMinLog, kRegE, LRM>(e);
         v[e] = make_float2(A[q], B[q]);
     }
 }
 
 // scalogram row -> X_hat (same computation as the in-LDS scalogram kernel)
-template <bool TWO>
+template <bool TWO, int LRM>
 __global__ void __launch_bounds__(kRegT) k_scalogram_r(const float2* __restrict__ xh, int64_t xh_pitch,
                                                      const float* __restrict__ psi1, const int* __restrict__ band1,
                                                      const int64_t* __restrict__ off1, float2* __restrict__ Xh,
@@ -159,28 +159,28 @@ __global__ void __launch_bounds__(kRegT) k_scalogram_r(const float2* __restrict_
     float2 v[kRegE];
     float even[TWO ? kRegE : 1];
     if constexpr (TWO) {
-        load_dif<true>(v, A, Bf, src, ps, lo, hi, logNX, 0, tw, tw_log, false);
-        reg_fft<kRegE, kRegMinLog>(v, A, tw, tw_log, true);
+        load_dif<true, 4, LRM>(v, A, Bf, src, ps, lo, hi, logNX, 0, tw, tw_log, false);
+        reg_fft<kRegE, kRegMinLog, LRM>(v, A, tw, tw_log, true);
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) even[e] = __builtin_amdgcn_sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN;   // X[2 pos]
-        load_dif<true>(v, A, Bf, src, ps, lo, hi, logNX, 1, tw, tw_log, false);
-        reg_fft<kRegE, kRegMinLog>(v, A, tw, tw_log, true);
+        load_dif<true, 4, LRM>(v, A, Bf, src, ps, lo, hi, logNX, 1, tw, tw_log, false);
+        reg_fft<kRegE, kRegMinLog, LRM>(v, A, tw, tw_log, true);
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
-            const int pos = reg_output_pos<kRegMinLog, kRegE>(e);
+            const int pos = reg_output_pos<kRegMinLog, kRegE, LRM>(e);
             xbuf[pos] = even[e];                                              // X[2 pos]
             xbuf[H + pos] = __builtin_amdgcn_sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN; // X[2 pos + 1]
         }
     } else {
         // the whole row fits one register transform; the exchange buffer is NX floats
         __syncthreads();
-        fold_inputs<kRegMinLog>(v, src, ps, lo, hi);
-        reg_fft<kRegE, kRegMinLog>(v, xbuf, tw, tw_log, true);
+        fold_inputs<kRegMinLog, LRM>(v, src, ps, lo, hi);
+        reg_fft<kRegE, kRegMinLog, LRM>(v, xbuf, tw, tw_log, true);
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
-            const int pos = reg_output_pos<kRegMinLog, kRegE>(e);
+            const int pos = reg_output_pos<kRegMinLog, kRegE, LRM>(e);
             xbuf[(pos & 1) * H + (pos >> 1)] = __builtin_amdgcn_sqrtf(v[e].x * v[e].x + v[e].y * v[e].y) * invN;
         }
     }
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(kRegT) k_scalogram_r(const float2* __restrict_
 }
 
 // one second-order row (T_alpha = 2^logTa >= 2^14): fold, inverse FFT, store, row max
-template <bool TWO>
+template <bool TWO, int LRM>
 __global__ void __launch_bounds__(kRegT) k_second_order_r(const float2* __restrict__ Xh, int64_t Xh_pitch, int n1,
                                                         const float* __restrict__ ps, int lo, int hi, int logTa,
                                                         int Tp, int Kp, float2* __restrict__ Y, int64_t y_bstride,
@@ -251,12 +251,12 @@ __global__ void __launch_bounds__(kRegT) k_second_order_r(const float2* __restri
     float2 ev[TWO ? kRegE : 1];
 #pragma unroll
     for (int half = 0; half < (TWO ? 2 : 1); ++half) {
-        load_dif<TWO>(v, A, Bf, row, ps, lo, hi, logTa, half, tw, tw_log, lam >= n1);
-        reg_fft<kRegE, kRegMinLog>(v, A, tw, tw_log, true);
+        load_dif<TWO, 4, LRM>(v, A, Bf, row, ps, lo, hi, logTa, half, tw, tw_log, lam >= n1);
+        reg_fft<kRegE, kRegMinLog, LRM>(v, A, tw, tw_log, true);
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
             const float2 y = cscale(v[e], invNX);
-            const int pos = reg_output_pos<kRegMinLog, kRegE>(e);
+            const int pos = reg_output_pos<kRegMinLog, kRegE, LRM>(e);
             if constexpr (TWO) {
                 if (half == 0) ev[e] = y;
                 else *(float4*)(out + 2 * pos) = make_float4(ev[e].x, ev[e].y, y.x, y.y);
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(kRegT) k_second_order_r(const float2* __restri
 }
 
 // in-place forward FFT of rows of 2^logn points (row r of batch b at base + b*bs + r*rs)
-template <bool TWO>
+template <bool TWO, int LRM>
 __global__ void __launch_bounds__(kRegT) k_rowfft_r(float2* __restrict__ base, int64_t bs, int64_t rs, int logn,
                                                   const float2* __restrict__ tw, int tw_log) {
     extern __shared__ __align__(16) float xbuf[];
@@ -284,11 +284,11 @@ __global__ void __launch_bounds__(kRegT) k_rowfft_r(float2* __restrict__ base, i
     float2 v[kRegE];
     if constexpr (!TWO) {
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e) v[e] = row[reg_input_pos<kRegMinLog, kRegE>(e)];
-        reg_fft<kRegE, kRegMinLog>(v, xbuf, tw, tw_log, false);
+        for (int e = 0; e < kRegE; ++e) v[e] = row[reg_input_pos<kRegMinLog, kRegE, LRM>(e)];
+        reg_fft<kRegE, kRegMinLog, LRM>(v, xbuf, tw, tw_log, false);
         __syncthreads();      // every thread has read its inputs before any output is stored
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e) row[reg_output_pos<kRegMinLog, kRegE>(e)] = v[e];
+        for (int e = 0; e < kRegE; ++e) row[reg_output_pos<kRegMinLog, kRegE, LRM>(e)] = v[e];
     } else {
         const int m = 1 << logS;
         // E = DFT of the even samples, O = DFT of the odd ones, both held in registers:
@@ -299,17 +299,17 @@ __global__ void __launch_bounds__(kRegT) k_rowfft_r(float2* __restrict__ base, i
         float2 o[kRegE];
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
-            const float4 q = ((const float4*)row)[reg_input_pos<kRegMinLog, kRegE, 3>(e)];
+            const float4 q = ((const float4*)row)[reg_input_pos<kRegMinLog, kRegE, LRM>(e)];
             v[e] = make_float2(q.x, q.y);
             o[e] = make_float2(q.z, q.w);
         }
-        reg_fft<kRegE, kRegMinLog, 3>(v, xbuf, tw, tw_log, false);
-        reg_fft<kRegE, kRegMinLog, 3>(o, xbuf, tw, tw_log, false);
+        reg_fft<kRegE, kRegMinLog, LRM>(v, xbuf, tw, tw_log, false);
+        reg_fft<kRegE, kRegMinLog, LRM>(o, xbuf, tw, tw_log, false);
         __syncthreads();      // every thread has read its inputs before any output is stored
         const float2* twc = after(tw, o[0]);
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
-            const int k = reg_output_pos<kRegMinLog, kRegE, 3>(e);
+            const int k = reg_output_pos<kRegMinLog, kRegE, LRM>(e);
             const float2 wo = cmul(o[e], twiddle(twc, k << (tw_log - logn), false));
             row[k] = cadd(v[e], wo);
             row[k + m] = csub(v[e], wo);
@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(kRegT) k_rowfft_r(float2* __restrict__ base, i
 
 // adjoint of the modulus and first-order filter for one row: recompute y, weight
 // gX by its phase, forward FFT -> g1[b][lambda][0..NX)
-template <bool TWO>
+template <bool TWO, int LRM>
 __global__ void __launch_bounds__(kRegT) k_scal_bwd_b_r(const float2* __restrict__ xh, int64_t xh_pitch,
                                                       const float* __restrict__ psi1, const int* __restrict__ band1,
                                                       const int64_t* __restrict__ off1, const float* __restrict__ gX,
@@ -339,21 +339,21 @@ __global__ void __launch_bounds__(kRegT) k_scal_bwd_b_r(const float2* __restrict
     float2* o = g1 + (b * n1 + lam) * (int64_t)NX;
     if constexpr (!TWO) {
         float2 v[kRegE];
-        fold_inputs<kRegMinLog>(v, src, ps, lo, hi);
-        reg_fft<kRegE, kRegMinLog>(v, A, tw, tw_log, true);
+        fold_inputs<kRegMinLog, LRM>(v, src, ps, lo, hi);
+        reg_fft<kRegE, kRegMinLog, LRM>(v, A, tw, tw_log, true);
         const float* gxh = after(gx, v[0]);
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
             const float2 y = cscale(v[e], invN);
-            const float sc = gxh[reg_output_pos<kRegMinLog, kRegE>(e)] *
+            const float sc = gxh[reg_output_pos<kRegMinLog, kRegE, LRM>(e)] *
                              __builtin_amdgcn_rcpf(fmaxf(__builtin_amdgcn_sqrtf(y.x * y.x + y.y * y.y), kEpsMod));
             v[e] = cscale(y, sc);
         }
         // from the last pass's output layout to the first pass's input layout
-        reg_output_to_input<kRegMinLog, kRegE>(v, A);
-        reg_fft<kRegE, kRegMinLog>(v, A, tw, tw_log, false);
+        reg_output_to_input<kRegMinLog, kRegE, LRM>(v, A);
+        reg_fft<kRegE, kRegMinLog, LRM>(v, A, tw, tw_log, false);
 #pragma unroll
-        for (int e = 0; e < kRegE; ++e) o[reg_output_pos<kRegMinLog, kRegE>(e)] = v[e];
+        for (int e = 0; e < kRegE; ++e) o[reg_output_pos<kRegMinLog, kRegE, LRM>(e)] = v[e];
     } else {
         // the inverse transform by decimation in frequency gives the even time samples
         // (half 0) and the odd ones (half 1); both stay in registers, so that gX is
@@ -362,30 +362,30 @@ __global__ void __launch_bounds__(kRegT) k_scal_bwd_b_r(const float2* __restrict
         // without parking one of them in the output row
         const int m = 1 << logS;
         float2 v0[kRegE], v1[kRegE];
-        load_dif<true>(v0, A, Bf, src, ps, lo, hi, logNX, 0, tw, tw_log, false);
-        reg_fft<kRegE, kRegMinLog>(v0, A, tw, tw_log, true);
-        load_dif<true, 1>(v1, A, Bf, src, ps, lo, hi, logNX, 1, tw, tw_log, false);   // beside v0: fewer loads at once
-        reg_fft<kRegE, kRegMinLog>(v1, A, tw, tw_log, true);
+        load_dif<true, 4, LRM>(v0, A, Bf, src, ps, lo, hi, logNX, 0, tw, tw_log, false);
+        reg_fft<kRegE, kRegMinLog, LRM>(v0, A, tw, tw_log, true);
+        load_dif<true, 1, LRM>(v1, A, Bf, src, ps, lo, hi, logNX, 1, tw, tw_log, false);   // beside v0: fewer loads at once
+        reg_fft<kRegE, kRegMinLog, LRM>(v1, A, tw, tw_log, true);
         const float2* gx2 = (const float2*)after(gx, v1[0]);
         const int tidw = opaque_tid();       // positions formed here, not kept from before
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
-            const float2 g = gx2[reg_output_pos<kRegMinLog, kRegE>(e, tidw)];     // samples 2 pos, 2 pos + 1
+            const float2 g = gx2[reg_output_pos<kRegMinLog, kRegE, LRM>(e, tidw)];     // samples 2 pos, 2 pos + 1
             const float2 y0 = cscale(v0[e], invN), y1 = cscale(v1[e], invN);
             v0[e] = cscale(y0, g.x * __builtin_amdgcn_rcpf(
                                        fmaxf(__builtin_amdgcn_sqrtf(y0.x * y0.x + y0.y * y0.y), kEpsMod)));
             v1[e] = cscale(y1, g.y * __builtin_amdgcn_rcpf(
                                        fmaxf(__builtin_amdgcn_sqrtf(y1.x * y1.x + y1.y * y1.y), kEpsMod)));
         }
-        reg_output_to_input<kRegMinLog, kRegE>(v0, A);
-        reg_fft<kRegE, kRegMinLog>(v0, A, tw, tw_log, false);
-        reg_output_to_input<kRegMinLog, kRegE>(v1, A);
-        reg_fft<kRegE, kRegMinLog>(v1, A, tw, tw_log, false);
+        reg_output_to_input<kRegMinLog, kRegE, LRM>(v0, A);
+        reg_fft<kRegE, kRegMinLog, LRM>(v0, A, tw, tw_log, false);
+        reg_output_to_input<kRegMinLog, kRegE, LRM>(v1, A);
+        reg_fft<kRegE, kRegMinLog, LRM>(v1, A, tw, tw_log, false);
         const float2* twc = after(tw, v1[0]);
         const int tido = opaque_tid();
 #pragma unroll
         for (int e = 0; e < kRegE; ++e) {
-            const int k = reg_output_pos<kRegMinLog, kRegE>(e, tido);
+            const int k = reg_output_pos<kRegMinLog, kRegE, LRM>(e, tido);
             const float2 wo = cmul(v1[e], twiddle(twc, k << (tw_log - logNX), false));
             o[k] = cadd(v0[e], wo);
             o[k + m] = csub(v0[e], wo);
@@ -393,11 +393,14 @@ __global__ void __launch_bounds__(kRegT) k_scal_bwd_b_r(const float2* __restrict
     }
 }
 
+// Each long-row kernel in both row lengths and both largest radices of its
+// transform passes (16, or 8 where the tuning asks for it): LRM = log2 of that radix.
+#define JTFS_REG_VARIANTS(k)                                                          \
+    (const void*)k<false, 4>, (const void*)k<true, 4>, (const void*)k<false, 3>, (const void*)k<true, 3>
+
 int reg_attributes() {
-    const void* ks[] = {(const void*)k_scalogram_r<false>,    (const void*)k_scalogram_r<true>,
-                        (const void*)k_second_order_r<false>, (const void*)k_second_order_r<true>,
-                        (const void*)k_rowfft_r<false>,       (const void*)k_rowfft_r<true>,
-                        (const void*)k_scal_bwd_b_r<false>,   (const void*)k_scal_bwd_b_r<true>};
+    const void* ks[] = {JTFS_REG_VARIANTS(k_scalogram_r), JTFS_REG_VARIANTS(k_second_order_r),
+                        JTFS_REG_VARIANTS(k_rowfft_r), JTFS_REG_VARIANTS(k_scal_bwd_b_r)};
     for (const void* k : ks)
         if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds) != hipSuccess) {
             set_error("hipFuncSetAttribute failed for the long-row kernels");
@@ -408,6 +411,9 @@ int reg_attributes() {
 
 // rows of 2^14 points: one 512-thread register transform; 2^15: two of them
 static inline bool two_of(int logn) { return logn == kRegMinLog + 1; }
+// the variant of long-row kernel k for rows of 2^logn points, radix 8 passes if r8
+#define JTFS_REG_PICK(k, logn, r8) \
+    (two_of(logn) ? ((r8) ? k<true, 3> : k<true, 4>) : ((r8) ? k<false, 3> : k<false, 4>))
 static inline unsigned reg_threads() { return (unsigned)((1 << kRegMinLog) / kRegE); }
 // LDS of a long-row kernel: `floats` of its own use, and at least the padded
 // exchange buffer of one 2^14-point transform
@@ -418,7 +424,7 @@ static inline size_t reg_lds(size_t floats) {
 void launch_scalogram_r(const jtfs_plan* P, const float2* xh, int64_t xh_pitch, float2* Xh, int64_t Xh_pitch,
                         int64_t B, hipStream_t st) {
     const Shapes& s = P->s;
-    auto k = two_of(s.logNX) ? k_scalogram_r<true> : k_scalogram_r<false>;
+    auto k = JTFS_REG_PICK(k_scalogram_r, s.logNX, P->tune.r8_scalogram);
     hipLaunchKernelGGL(k, dim3(s.n1, (unsigned)B), dim3(reg_threads()), reg_lds(s.NX), st, xh, xh_pitch,
                        P->psi1, P->band1, P->off1, Xh, Xh_pitch, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log);
     // LDS: NX floats (the two staged halves at 2^15), at least one padded exchange buffer
@@ -429,7 +435,7 @@ void launch_second_order_r(const jtfs_plan* P, int a, const float2* Xh, int64_t 
     const Shapes& s = P->s;
     const int logTa = s.logNX - s.k2[a];
     const Family& f2 = s.f2;
-    auto k = two_of(logTa) ? k_second_order_r<true> : k_second_order_r<false>;
+    auto k = JTFS_REG_PICK(k_second_order_r, logTa, P->tune.r8_second);
     hipLaunchKernelGGL(k, dim3(s.Kp, (unsigned)B), dim3(reg_threads()), reg_lds((size_t)1 << logTa), st, Xh, Xh_pitch,
                        s.n1, P->psi2 + f2.off[a], f2.lo[a], f2.hi[a], logTa, s.Tp[a], s.Kp, Y2 + s.yoff[a],
                        (int64_t)s.Kp * s.sumTp, 1.0f / (float)s.NX, P->tw, P->tw_log, rowmax, a, s.n_alpha);
@@ -437,7 +443,7 @@ void launch_second_order_r(const jtfs_plan* P, int a, const float2* Xh, int64_t 
 
 void launch_rowfft_r(const jtfs_plan* P, float2* base, int64_t bs, int64_t rs, int rows, int logn, int64_t B,
                      hipStream_t st) {
-    auto k = two_of(logn) ? k_rowfft_r<true> : k_rowfft_r<false>;
+    auto k = JTFS_REG_PICK(k_rowfft_r, logn, P->tune.r8_rowfft);
     hipLaunchKernelGGL(k, dim3((unsigned)rows, (unsigned)B), dim3(reg_threads()), reg_lds(0), st,
                        base, bs, rs, logn, P->tw, P->tw_log);
 }
@@ -445,7 +451,7 @@ void launch_rowfft_r(const jtfs_plan* P, float2* base, int64_t bs, int64_t rs, i
 void launch_scal_bwd_b_r(const jtfs_plan* P, const float2* xh, int64_t xh_pitch, const float* gX, float2* g1,
                          int64_t B, hipStream_t st) {
     const Shapes& s = P->s;
-    auto k = two_of(s.logNX) ? k_scal_bwd_b_r<true> : k_scal_bwd_b_r<false>;
+    auto k = JTFS_REG_PICK(k_scal_bwd_b_r, s.logNX, P->tune.r8_first_adj);
     hipLaunchKernelGGL(k, dim3(s.n1, (unsigned)B), dim3(reg_threads()), reg_lds(s.NX), st, xh,
                        xh_pitch, P->psi1, P->band1, P->off1, gX, g1, s.logNX, 1.0f / (float)s.N, P->tw, P->tw_log);
 }

@@ -101,7 +101,12 @@ struct Tuning {
     bool reg_first_adj = true;   // first-order adjoint rows of 2^14 points
     bool fwd16 = false;          // forward contraction in 16 x 16 tiles (else 32 x 32)
     bool bwd16 = false;          // stored-phase backward in 16 x 16 tiles (else 32 x 32)
+    // register-resident rows: radix-8 passes instead of radix-16 ones, per stage
+    bool r8_scalogram = false, r8_second = false, r8_rowfft = false, r8_first_adj = false;
+    bool batch8k = false;        // in-LDS row transforms: 8192 points per workgroup (else 4096)
 };
+// points per workgroup of the in-LDS second-order and gY2 row transforms
+inline int lds_batch_log(const Tuning& t) { return t.batch8k ? 13 : 12; }
 // rows of 2^logn points take the register-resident kernels above 2^14 always, at
 // 2^14 when the tuning says so, and the in-LDS kernels below
 inline bool use_reg_rows(int logn, bool knob) { return logn > kRegMinLogRows || (logn == kRegMinLogRows && knob); }

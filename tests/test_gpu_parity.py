@@ -251,13 +251,20 @@ def test_ragged_bucket_graph_matches_oracle_and_replays():
 LONG = dict(N=2 ** 15, J=5, Q=(1, 1), J_fr=2, Q_fr=1, T=2 ** 10, F=2)
 
 
+@pytest.mark.parametrize("radix", [16, 8])
 @pytest.mark.parametrize("mode", MODES)
-def test_long_rows_forward_and_vjp(mode):
+def test_long_rows_forward_and_vjp(mode, radix):
+    """(radix: the largest radix of the register-resident transforms' passes, a
+    launch choice of the autotuner, applied to every stage.)"""
     P = oracle_plan(LONG)
     assert P.NX == 2 ** 15 and P.T_alpha(0) == 2 ** 15
     rng = np.random.default_rng(215)
     x = (rng.standard_normal((2, LONG["N"])) * 0.5).astype(np.float32)
     op = gpu_op(LONG, mode)
+    if radix == 8:
+        c, rows, ft, bt = op.tuning()
+        op.set_tuning(c, rows, fwd_tile=ft, bwd_tile=bt, radix8=list(op.RADIX8_BITS))
+        assert op.tuning_radix()[0] == list(op.RADIX8_BITS)
     g1, g2 = run_forward(op, x)
     gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape(), seed=5)
     g = op.vjp(torch.from_numpy(x).cuda(), torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda()).cpu().numpy()
@@ -856,14 +863,18 @@ def test_autotune_then_every_row_choice_matches_oracle():
     assert c["split16_register"] > 0 and c["fp32_register"] > 0 and c["split16_phase_register"] > 0
     assert c["split16_lds"] > 0 and choice["fwd_ms"]["tile16"] > 0
     assert op.tuning() == (choice["contraction"], choice["register_rows"], choice["fwd_tile"], choice["bwd_tile"])
+    assert op.tuning_radix() == (choice["radix8"], choice["lds_batch"])
     gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape(), seed=31)
     refs = [(O.jtfs(x[b].astype(np.float64), P),
              O.jtfs_vjp(x[b].astype(np.float64), gs1[b].astype(np.float64), gs2[b].astype(np.float64), P))
             for b in range(2)]
     for mode in MODES + ["split16_phase"]:
-        for rows, tile, btile in (([], 16, 16), (ALL_ROWS, 32, 32), (["scalogram", "row_fft"], 16, 32),
-                                  (["second_order", "first_adj"], 32, 16)):
-            op.set_tuning(mode, rows, fwd_tile=tile, bwd_tile=btile)
+        # (register-resident stages, forward tile, backward tile, radix-8 stages, in-LDS batch)
+        for rows, tile, btile, r8, lb in (([], 16, 16, [], 8192), (ALL_ROWS, 32, 32, ALL_ROWS, 4096),
+                                          (["scalogram", "row_fft"], 16, 32, ["scalogram", "row_fft"], 8192),
+                                          (["second_order", "first_adj"], 32, 16, ["first_adj"], 4096),
+                                          (ALL_ROWS, 16, 16, ["second_order", "row_fft"], 8192)):
+            op.set_tuning(mode, rows, fwd_tile=tile, bwd_tile=btile, radix8=r8, lds_batch=lb)
             ws = op.new_workspace(2)
             s1, s2 = op.forward(xt, ws)
             g = op.vjp(xt, torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda(), ws=ws,
@@ -872,7 +883,7 @@ def test_autotune_then_every_row_choice_matches_oracle():
             for b in range(2):
                 (r1, r2), rg = refs[b]
                 check_paths(g1[b], g2[b], r1, r2)
-                assert rel_l2(g[b], rg) <= TOL_VJP, (mode, rows, tile, btile)
+                assert rel_l2(g[b], rg) <= TOL_VJP, (mode, rows, tile, btile, r8, lb)
 
 
 def test_autotune_cache_reuses_the_choice(tmp_path, monkeypatch):
