@@ -215,12 +215,35 @@ def ragged_batch(torch, dev, runs=3):
     for n in bk.pads:
         counts[str(n)] = counts.get(str(n), 0) + 1
     print(f"[bench] ragged batch: {ms:.2f} ms per fwd+bwd run", file=sys.stderr, flush=True)
+    pads = list(bk.pads)
     del bk
+    # each bucket alone (its signals as a ragged batch of one pad), for comparison
+    # with the run that holds them all as parallel branches of one graph
+    alone = {}
+    for pad in sorted(set(pads)):
+        idx = [i for i, n in enumerate(pads) if n == pad]
+        b1 = JTFSBucket([lengths[i] for i in idx], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"])
+        x1 = torch.from_numpy(np.concatenate([sigs[i] for i in idx])).to(dev)
+        g1 = torch.from_numpy(np.random.default_rng(5).standard_normal(b1.s_offset[-1]).astype(np.float32)).to(dev)
+        o1 = torch.empty(b1.s_offset[-1], dtype=torch.float32, device=dev)
+        gx1 = torch.empty(b1.x_offset[-1], dtype=torch.float32, device=dev)
+        with torch.cuda.stream(st):
+            b1.run(x1, g1, o1, gx1)
+            st.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(runs):
+                b1.run(x1, g1, o1, gx1)
+            st.synchronize()
+            alone[str(pad)] = round((time.perf_counter() - t0) * 1e3 / runs, 3)
+        del b1, x1, g1, o1, gx1
+    print(f"[bench] ragged batch: buckets alone {alone} ms, sum {sum(alone.values()):.2f}", file=sys.stderr,
+          flush=True)
     return {"workload": "256 harmonic tones + pink noise, lengths log-uniform in [2^13, 2^16], J=11, Q=(16,1), "
                         "J_fr=4, Q_fr=1, T=2^10, F=2^3; buckets of power-of-two pads, one HIP graph per run",
             "ms_per_run": round(ms, 3), "fwd_bwd_msamples_s_real": round(real / (ms * 1e-3) / 1e6, 3),
             "fwd_bwd_msamples_s_padded": round(padded / (ms * 1e-3) / 1e6, 3),
-            "real_samples": real, "padded_samples": padded, "signals_per_pad": counts}
+            "real_samples": real, "padded_samples": padded, "signals_per_pad": counts,
+            "bucket_alone_ms": alone, "sum_of_buckets_alone_ms": round(sum(alone.values()), 3)}
 
 
 def texture_leg(torch, dev, iters=100, mu0=-0.05):
