@@ -289,7 +289,14 @@ class JTFS:
 
     def __call__(self, x, mu=None, eps=0.1):
         """(S1, S2), differentiable; with mu = (mu1, mu2) the mu-log outputs
-        log(1 + S / (eps mu)) instead, differentiable with mu held fixed."""
+        log(1 + S / (eps mu)) instead, differentiable with mu held fixed.  A call
+        that records a graph gets a workspace of its own (kept for its backward);
+        one that does not (no_grad, or x without requires_grad) reuses the plan's."""
+        if not (torch.is_grad_enabled() and x.requires_grad):
+            # no graph to serve: the plan's cached workspace, nothing kept for a backward
+            if mu is None:
+                return self.forward(x)
+            return self.forward_mulog(x, mu[0], mu[1], eps)
         if mu is None:
             return _JTFSFunction.apply(x, self)
         return _JTFSMuLogFunction.apply(x, self, mu[0], mu[1], float(eps))

@@ -197,6 +197,10 @@ def test_autograd_function_matches_vjp():
     g_ref = op.vjp(x.detach(), gs1, gs2)
     torch.cuda.synchronize()
     assert torch.equal(x.grad, g_ref)
+    # without a graph to record, the call returns the same coefficients from the plan's workspace
+    with torch.no_grad():
+        n1, n2 = op(x)
+    assert not n1.requires_grad and torch.equal(n1, s1.detach()) and torch.equal(n2, s2.detach())
 
 
 def test_ragged_bucket_graph_matches_oracle_and_replays():
