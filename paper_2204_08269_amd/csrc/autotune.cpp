@@ -299,8 +299,12 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
                                JTFS_STAGE_FIRST_ADJ};
         const int kbit[4] = {JTFS_REG_SCALOGRAM, JTFS_REG_SECOND_ORDER, JTFS_REG_ROW_FFT, JTFS_REG_FIRST_ADJ};
         rows = 0;
-        for (int q = 0; q < 4; ++q)
-            if (stage[best_m][0][kstage[q]] <= stage[best_m][1][kstage[q]]) rows |= kbit[q];
+        for (int q = 0; q < 4; ++q) {
+            // the first-order adjoint's bit also chooses the kernel of the second-order adjoint
+            const double r0 = stage[best_m][0][kstage[q]] + (q == 3 ? stage[best_m][0][JTFS_STAGE_SECOND_ADJ] : 0.0);
+            const double r1 = stage[best_m][1][kstage[q]] + (q == 3 ? stage[best_m][1][JTFS_STAGE_SECOND_ADJ] : 0.0);
+            if (r0 <= r1) rows |= kbit[q];
+        }
     }
     if (use16) rows |= JTFS_TUNE_FWD_TILE16;
     if (buse16) rows |= JTFS_TUNE_BWD_TILE16;
@@ -332,8 +336,11 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
                                    JTFS_STAGE_FIRST_ADJ};
             const int kbit[4] = {JTFS_TUNE_RADIX8_SCALOGRAM, JTFS_TUNE_RADIX8_SECOND_ORDER, JTFS_TUNE_RADIX8_ROW_FFT,
                                  JTFS_TUNE_RADIX8_FIRST_ADJ};
-            for (int q = 0; q < 4; ++q)
-                if (st8[kstage[q]] < 0.99 * base_st[kstage[q]]) next |= kbit[q];
+            for (int q = 0; q < 4; ++q) {
+                const double r16 = base_st[kstage[q]] + (q == 3 ? base_st[JTFS_STAGE_SECOND_ADJ] : 0.0);
+                const double r8 = st8[kstage[q]] + (q == 3 ? st8[JTFS_STAGE_SECOND_ADJ] : 0.0);
+                if (r8 < 0.99 * r16) next |= kbit[q];
+            }
         }
         if (has_short) {
             double ms = 0.0, stb[JTFS_NUM_STAGES];

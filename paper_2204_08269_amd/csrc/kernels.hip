@@ -254,28 +254,6 @@ __global__ void __launch_bounds__(1024, 8) k_scalogram(const float2* __restrict_
     }
 }
 
-// mu-log of sec. 4 (eqs. (9)-(10)) fused into the coefficient writers and the
-// cotangent readers.  With mu set, a writer stores O = log(1 + S / (eps mu)) of its
-// path instead of S, and a reader takes the cotangent g of O to the cotangent of
-// S, g / (eps mu + S) = g / (eps mu e^O), from O itself (mu held fixed).
-struct MuLogArg {
-    const float* mu1;   // [1]: the S1 path; null: no mu-log
-    const float* mu2;   // one per second-order path (the layouts of the mu-log entry points)
-    float eps;
-    const float* o1;    // backward: the forward's outputs O1, O2
-    const float* o2;
-};
-
-__device__ __forceinline__ float mulog_inv(const float* mu, int p, float eps) {
-    return mu ? 1.f / (eps * mu[p]) : 0.f;
-}
-__device__ __forceinline__ float mulog_out(float v, const float* mu, float inv) {
-    return mu ? log1pf(v * inv) : v;
-}
-__device__ __forceinline__ float mulog_cot(float g, const float* mu, float em, float o) {
-    return mu ? g / (em * expf(o)) : g;
-}
-
 // S1[tau] = (X (*) phi_T)[tau T/2^kX]: fold X_hat * phi_hat over the N/T-bin grid
 // (bins -Mneg..Mphi of the NX grid), inverse FFT, real part / NX.  One workgroup per
 // (lambda, signal).  S1 may be null.  With the lowpass pairs, the same rows are also
@@ -1460,9 +1438,15 @@ int backward_impl(const jtfs_plan* P, const float* x, const float* gs1, const fl
     }
     const int logNT = s.logN - s.logT;
     const size_t lds_a = sizeof(float2) * (lpad_len(s.NX / 2) + 1 + lpad_len(s.NT));   // g1 at lpad(H) + 1
-    JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_a, dim3(s.n1, (unsigned)B), dim3(1024), lds_a, st, gY2, yb, P->d_yoff, P->d_Tp, P->d_Ta, P->psi2,
-                       P->band2, P->off2, s.n_alpha_psi, gs1, P->phiX, s.Mphi, logNT, s.logNX, gX, P->tw, P->tw_log, ml,
-                       s.complete ? gY2 + s.yoff[s.n_alpha_psi] : nullptr, s.complete ? s.Tp[s.n_alpha_psi] : 0));
+    const float2* gYphi = s.complete ? gY2 + s.yoff[s.n_alpha_psi] : nullptr;
+    const int Tphi = s.complete ? s.Tp[s.n_alpha_psi] : 0;
+    if (use_reg_rows(s.logNX, P->tune.reg_first_adj)) {
+        JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, launch_scal_bwd_a_r(P, gY2, yb, gs1, ml, gYphi, Tphi, gX, B, st));
+    } else {
+        JTFS_TIMED(JTFS_STAGE_SECOND_ADJ, st, hipLaunchKernelGGL(k_scal_bwd_a, dim3(s.n1, (unsigned)B), dim3(1024), lds_a, st, gY2, yb, P->d_yoff, P->d_Tp, P->d_Ta, P->psi2,
+                           P->band2, P->off2, s.n_alpha_psi, gs1, P->phiX, s.Mphi, logNT, s.logNX, gX, P->tw, P->tw_log, ml,
+                           gYphi, Tphi));
+    }
     LAUNCHCHK("scalogram adjoint");
     if (use_reg_rows(s.logNX, P->tune.reg_first_adj)) {
         JTFS_TIMED(JTFS_STAGE_FIRST_ADJ, st, launch_scal_bwd_b_r(P, xh, w.xh_pitch, gX, g1, B, st));

@@ -393,6 +393,99 @@ __global__ void __launch_bounds__(kRegT) k_scal_bwd_b_r(const float2* __restrict
     }
 }
 
+// Adjoint of the second order and of S1 for one scalogram row of NX = 2H points,
+// with the inverse real FFT held in registers (the in-LDS kernel computes the same
+// sums): the Hermitian half-spectrum of gX,
+//   S[m] = 1/2 sum_alpha psi_hat_alpha[m] G_alpha[m mod Ta] (real part alone at m = 0, H)
+//        + phi_hat[m] G1[m mod NT],   m = 0..H,
+// G_alpha the FFT of the gY2 rows (taken beforehand), G1 the FFT of the S1
+// cotangent row (plus the real part of phi_T's second-order rows with the lowpass
+// pairs), is formed at the thread's input positions of the H-point transform and
+// parked in LDS, so that each position k takes the packed spectrum
+// Z[k] = S[k] + conj(S[H-k]) + i w^k (S[k] - conj(S[H-k])) (w = e^{2 pi i / NX});
+// the inverse transform of Z gives gX[2n] + i gX[2n+1], scaled 1/NX.
+template <int E, int LOGH, int LRM>
+__global__ void __launch_bounds__(kRegT) k_scal_bwd_a_r(const float2* __restrict__ G, int64_t y_bstride,
+                                                      const int64_t* __restrict__ yoff, const int* __restrict__ Tpv,
+                                                      const int* __restrict__ Tav, const float* __restrict__ psi2,
+                                                      const int* __restrict__ band2, const int64_t* __restrict__ off2,
+                                                      int n_alpha, const float* __restrict__ gS1,
+                                                      const float* __restrict__ phiX, int Mphi, int logNT,
+                                                      float* __restrict__ gX, const float2* __restrict__ tw, int tw_log,
+                                                      MuLogArg ml, const float2* __restrict__ gYphi, int Tphi) {
+    extern __shared__ __align__(16) float xbuf[];
+    constexpr int H = 1 << LOGH;
+    const int lam = blockIdx.x, n1 = gridDim.x;
+    const int64_t b = blockIdx.y;
+    const int NT = 1 << logNT;
+    float2* Sx = (float2*)xbuf;                                  // S[0..H] (H + 1 <= the exchange buffer)
+    float2* g1 = (float2*)(xbuf + reg_xbuf_floats(LOGH));        // G1, lpad_len(NT) slots
+    const float em = ml.mu1 ? ml.eps * ml.mu1[0] : 0.f;
+    for (int t = threadIdx.x; t < NT; t += blockDim.x) {
+        const int64_t i = (b * n1 + lam) * NT + t;
+        float g = gS1 ? mulog_cot(gS1[i], ml.mu1, em, ml.mu1 ? ml.o1[i] : 0.f) : 0.f;
+        if (gYphi) g += gYphi[b * y_bstride + (int64_t)lam * Tphi + t].x;
+        g1[lpad(t)] = make_float2(g, 0.f);
+    }
+    __syncthreads();
+    lds_fft<16>(g1, logNT, 1, NT, tw, tw_log, false);
+    __syncthreads();
+    // the half-spectrum at the thread's positions k (and at H on thread 0): the
+    // temporal rates in the outer loop, so that a rate's loads for all positions
+    // issue together
+    const int extra = threadIdx.x == 0 ? 1 : 0;
+    float2 c[E + 1];
+#pragma unroll
+    for (int e = 0; e <= E; ++e) c[e] = make_float2(0.f, 0.f);
+    for (int a = 0; a < n_alpha; ++a) {
+        const int lo = band2[2 * a], hi = band2[2 * a + 1];
+        const float* pa = psi2 + off2[a] - lo;
+        const float2* ga = G + b * y_bstride + yoff[a] + (int64_t)lam * Tpv[a];
+        const int tmask = Tav[a] - 1;
+#pragma unroll
+        for (int e = 0; e <= E; ++e) {
+            if (e == E && !extra) continue;
+            const int m = e < E ? reg_input_pos<LOGH, E, LRM>(e) : H;
+            if (m >= lo && m <= hi) {
+                const float g = pa[m];
+                const float2 v = ga[m & tmask];
+                c[e].x += g * v.x;
+                c[e].y += g * v.y;
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e <= E; ++e) {
+        if (e == E && !extra) continue;
+        const int m = e < E ? reg_input_pos<LOGH, E, LRM>(e) : H;
+        float2 hm = (m == 0 || m == H) ? make_float2(c[e].x, 0.f) : cscale(c[e], 0.5f);
+        if (m <= Mphi) {
+            const float2 v = g1[lpad(m & (NT - 1))];
+            hm.x += phiX[m] * v.x;
+            hm.y += phiX[m] * v.y;
+        }
+        Sx[m] = hm;
+    }
+    __syncthreads();
+    const int tws = tw_log - (LOGH + 1);
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = reg_input_pos<LOGH, E, LRM>(e);
+        const float2 p = Sx[k], q = Sx[H - k];
+        const float2 Sm = make_float2(p.x + q.x, p.y - q.y);
+        const float2 D = make_float2(p.x - q.x, p.y + q.y);
+        const float2 wD = cmulc(D, tw[k << tws]);
+        v[e] = make_float2(Sm.x - wD.y, Sm.y + wD.x);
+    }
+    __syncthreads();                                             // S is read; the transform reuses the buffer
+    reg_fft<E, LOGH, LRM>(v, xbuf, tw, tw_log, true);
+    float2* o = (float2*)(gX + (b * n1 + lam) * (int64_t)(2 * H));
+    const float sc = 1.f / (float)(2 * H);
+#pragma unroll
+    for (int e = 0; e < E; ++e) o[reg_output_pos<LOGH, E, LRM>(e)] = cscale(v[e], sc);
+}
+
 // Each long-row kernel in both row lengths and both largest radices of its
 // transform passes (16, or 8 where the tuning asks for it): LRM = log2 of that radix.
 #define JTFS_REG_VARIANTS(k)                                                          \
@@ -400,7 +493,10 @@ __global__ void __launch_bounds__(kRegT) k_scal_bwd_b_r(const float2* __restrict
 
 int reg_attributes() {
     const void* ks[] = {JTFS_REG_VARIANTS(k_scalogram_r), JTFS_REG_VARIANTS(k_second_order_r),
-                        JTFS_REG_VARIANTS(k_rowfft_r), JTFS_REG_VARIANTS(k_scal_bwd_b_r)};
+                        JTFS_REG_VARIANTS(k_rowfft_r), JTFS_REG_VARIANTS(k_scal_bwd_b_r),
+                        (const void*)k_scal_bwd_a_r<kRegE, kRegMinLog, 4>,
+                        (const void*)k_scal_bwd_a_r<kRegE, kRegMinLog, 3>,
+                        (const void*)k_scal_bwd_a_r<kRegE / 2, kRegMinLog - 1, 3>};
     for (const void* k : ks)
         if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds) != hipSuccess) {
             set_error("hipFuncSetAttribute failed for the long-row kernels");
@@ -446,6 +542,21 @@ void launch_rowfft_r(const jtfs_plan* P, float2* base, int64_t bs, int64_t rs, i
     auto k = JTFS_REG_PICK(k_rowfft_r, logn, P->tune.r8_rowfft);
     hipLaunchKernelGGL(k, dim3((unsigned)rows, (unsigned)B), dim3(reg_threads()), reg_lds(0), st,
                        base, bs, rs, logn, P->tw, P->tw_log);
+}
+
+void launch_scal_bwd_a_r(const jtfs_plan* P, const float2* G, int64_t y_bstride, const float* gS1, const MuLogArg& ml,
+                         const float2* gYphi, int Tphi, float* gX, int64_t B, hipStream_t st) {
+    const Shapes& s = P->s;
+    const int logNT = s.logN - s.logT;
+    // rows of 2^15 points: a 2^14-point transform of 16 values per thread; 2^14: 2^13 of 8
+    auto k = s.logNX == kRegMinLog + 1
+                 ? (P->tune.r8_first_adj ? k_scal_bwd_a_r<kRegE, kRegMinLog, 3> : k_scal_bwd_a_r<kRegE, kRegMinLog, 4>)
+                 : k_scal_bwd_a_r<kRegE / 2, kRegMinLog - 1, 3>;
+    const int logH = s.logNX - 1;
+    const size_t lds = sizeof(float) * ((size_t)reg_xbuf_floats(logH) + 2 * (size_t)lpad_len(s.NT));
+    hipLaunchKernelGGL(k, dim3(s.n1, (unsigned)B), dim3(reg_threads()), lds, st, G, y_bstride, P->d_yoff, P->d_Tp,
+                       P->d_Ta, P->psi2, P->band2, P->off2, s.n_alpha_psi, gS1, P->phiX, s.Mphi, logNT, gX, P->tw,
+                       P->tw_log, ml, gYphi, Tphi);
 }
 
 void launch_scal_bwd_b_r(const jtfs_plan* P, const float2* xh, int64_t xh_pitch, const float* gX, float2* g1,
