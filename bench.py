@@ -319,9 +319,10 @@ def run_workload(torch, dev, cfg, args, extras=True, stage_pass=True):
         print(f"[bench] cfg {cfg} autotune: {tuning['contraction']}, register rows {tuning['register_rows']}, "
               f"tiles {tuning['fwd_tile']}/{tuning['bwd_tile']}, {tuning['step_ms']:.2f} ms/step", file=sys.stderr,
               flush=True)
-    elif args.fwd_tile or args.bwd_tile:
+    elif args.fwd_tile or args.bwd_tile or args.radix8:
         mode, rows, ft, bt = op.tuning()
-        op.set_tuning(mode, rows, fwd_tile=args.fwd_tile or ft, bwd_tile=args.bwd_tile or bt)
+        r8 = [v for v in args.radix8.split(",") if v] if args.radix8 else []
+        op.set_tuning(mode, rows, fwd_tile=args.fwd_tile or ft, bwd_tile=args.bwd_tile or bt, radix8=r8)
     ws = op.new_workspace(B)
 
     def step():
@@ -457,6 +458,9 @@ def main():
                     help="with --no-autotune: MFMA tile of the split forward contraction")
     ap.add_argument("--bwd-tile", type=int, choices=[16, 32], default=None,
                     help="with --no-autotune: MFMA tile of the stored-phase backward")
+    ap.add_argument("--radix8", default="",
+                    help="with --no-autotune: comma-separated stages whose register-resident transforms use "
+                         "radix-8 passes (scalogram, second_order, row_fft, first_adj)")
     ap.add_argument("--no-extras", action="store_true",
                     help="time the fwd+bwd step only (no event pass, forward-only, second-workload or ragged legs)")
     args = ap.parse_args()
