@@ -54,6 +54,8 @@ extern "C" {
 #define JTFS_ENOMEM     -2   /* device allocation of plan tables failed            */
 #define JTFS_EHIP       -3   /* a HIP runtime call or kernel launch failed         */
 #define JTFS_EWORKSPACE -4   /* workspace smaller than jtfs_workspace_size()       */
+#define JTFS_ESHAPE     -5   /* a batch count outside [1, 65535], or a buffer size
+                                that does not match the plan's shapes              */
 #define JTFS_ENOTSUP    -6   /* valid parameters outside what this library supports */
 
 /* Flags of jtfs_backward. */
@@ -130,6 +132,11 @@ typedef struct {
     int64_t s2_per_signal;   /* n_alpha * n_beta * 2 * out_l * out_t; with
                                 JTFS_NO_FREQ_AVERAGE n_alpha * 2 * M_h * out_t; with
                                 JTFS_TIME_SCATTERING n_alpha * n1 * out_t            */
+    int64_t ws_fwd;    /* workspace bytes of a forward of one signal (B = 1)        */
+    int64_t ws_bwd;    /* ... of a forward and backward (jtfs_workspace_size at B = 1);
+                          jtfs_query: the split contraction without the stored phase,
+                          with the FP32 backward's buffers (an upper bound for the modes
+                          without it); jtfs_plan_info: the plan's contraction mode now */
 } jtfs_info;
 
 /* Host-only queries (no GPU needed). */

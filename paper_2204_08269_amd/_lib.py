@@ -16,6 +16,7 @@ JTFS_EINVAL = -1
 JTFS_ENOMEM = -2
 JTFS_EHIP = -3
 JTFS_EWORKSPACE = -4
+JTFS_ESHAPE = -5
 JTFS_ENOTSUP = -6
 JTFS_BWD_REUSE_FORWARD = 1
 JTFS_NOALLOC_SCRATCH_BYTES = 256 << 20
@@ -49,7 +50,8 @@ class Info(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int32), ("n_alpha", ctypes.c_int32), ("n_beta", ctypes.c_int32),
                 ("L", ctypes.c_int32), ("kX", ctypes.c_int32), ("M_h", ctypes.c_int32),
                 ("NX", ctypes.c_int64), ("out_t", ctypes.c_int64), ("out_l", ctypes.c_int64),
-                ("sum_T", ctypes.c_int64), ("s1_per_signal", ctypes.c_int64), ("s2_per_signal", ctypes.c_int64)]
+                ("sum_T", ctypes.c_int64), ("s1_per_signal", ctypes.c_int64), ("s2_per_signal", ctypes.c_int64),
+                ("ws_fwd", ctypes.c_int64), ("ws_bwd", ctypes.c_int64)]
 
 
 EXPORTS = ["jtfs_query", "jtfs_query_filters", "jtfs_plan_create", "jtfs_plan_create_ex", "jtfs_plan_info",

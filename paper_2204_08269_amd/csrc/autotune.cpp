@@ -176,7 +176,8 @@ extern "C" int jtfs_plan_get_tuning(const jtfs_plan* P, int* contraction, int* r
 extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int reps, hipStream_t st,
                                   jtfs_tuning* out) {
     if (!P || !out) { set_error("null pointer"); return JTFS_EINVAL; }
-    if (B < 1 || B > 65535 || reps < 1 || reps > 100) { set_error("B in [1, 65535] and reps in [1, 100]"); return JTFS_EINVAL; }
+    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_ESHAPE; }
+    if (reps < 1 || reps > 100) { set_error("reps must lie in [1, 100]"); return JTFS_EINVAL; }
     if (timing_on()) { set_error("autotune uses the stage timers: disable jtfs timing first"); return JTFS_EINVAL; }
     std::memset(out, 0, sizeof(*out));
     const Shapes& s = P->s;

@@ -419,7 +419,14 @@ extern "C" void jtfs_plan_destroy(jtfs_plan* P) {
 
 extern "C" int jtfs_plan_info(const jtfs_plan* P, jtfs_info* out) {
     if (!P) { set_error("null plan"); return JTFS_EINVAL; }
-    return jtfs_query(&P->s.p, out);
+    const int rc = jtfs_query(&P->s.p, out);
+    if (rc != JTFS_OK) return rc;
+    size_t f = 0, t = 0;
+    jtfs_forward_workspace_size(P, 1, &f);
+    jtfs_workspace_size(P, 1, &t);
+    out->ws_fwd = (int64_t)f;
+    out->ws_bwd = (int64_t)t;
+    return JTFS_OK;
 }
 
 extern "C" int jtfs_plan_table(const jtfs_plan* P, int which, void* host_dst, size_t bytes) {
@@ -428,7 +435,7 @@ extern "C" int jtfs_plan_table(const jtfs_plan* P, int which, void* host_dst, si
     if (which == 0 || which == 1) {
         const Family& f = which == 0 ? s.f1 : s.f2;
         const int64_t W = f.M / 2 + 1;
-        if (bytes != sizeof(float) * W * f.n()) { set_error("table size mismatch"); return JTFS_EINVAL; }
+        if (bytes != sizeof(float) * W * f.n()) { set_error("table size mismatch"); return JTFS_ESHAPE; }
         std::vector<float> packed(f.total);
         HIPCHK(hipMemcpy(packed.data(), which == 0 ? P->psi1 : P->psi2, sizeof(float) * f.total, hipMemcpyDeviceToHost));
         float* dst = (float*)host_dst;
@@ -438,7 +445,7 @@ extern "C" int jtfs_plan_table(const jtfs_plan* P, int which, void* host_dst, si
         return JTFS_OK;
     }
     if (which == 2) {
-        if (bytes != sizeof(float2) * s.Mh * s.n1) { set_error("table size mismatch"); return JTFS_EINVAL; }
+        if (bytes != sizeof(float2) * s.Mh * s.n1) { set_error("table size mismatch"); return JTFS_ESHAPE; }
         std::vector<float2> Wl((size_t)s.Mp * s.Kp);
         HIPCHK(hipMemcpy(Wl.data(), P->Wl, sizeof(float2) * Wl.size(), hipMemcpyDeviceToHost));
         float2* dst = (float2*)host_dst;

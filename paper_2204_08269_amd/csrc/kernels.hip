@@ -1165,7 +1165,7 @@ static Workspace plan_layout(const jtfs_plan* P, int64_t B) {
 // forward_only: a forward needs the leading part of the layout only
 static int check_common(const jtfs_plan* P, int64_t B, void* ws, size_t ws_bytes, bool forward_only) {
     if (!P) { set_error("null plan"); return JTFS_EINVAL; }
-    if (B < 1) { set_error("B must be >= 1"); return JTFS_EINVAL; }
+    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_ESHAPE; }   // grid y / z
     if (!ws) { set_error("null workspace"); return JTFS_EINVAL; }
     const Workspace w = plan_layout(P, B);
     if (ws_bytes < (forward_only ? w.fwd_total : w.total)) { set_error("workspace too small"); return JTFS_EWORKSPACE; }
@@ -1174,14 +1174,14 @@ static int check_common(const jtfs_plan* P, int64_t B, void* ws, size_t ws_bytes
 
 extern "C" int jtfs_workspace_size(const jtfs_plan* P, int64_t B, size_t* bytes) {
     if (!P || !bytes) { set_error("null pointer"); return JTFS_EINVAL; }
-    if (B < 1) { set_error("B must be >= 1"); return JTFS_EINVAL; }
+    if (B < 1) { set_error("B must be >= 1"); return JTFS_ESHAPE; }
     *bytes = plan_layout(P, B).total;
     return JTFS_OK;
 }
 
 extern "C" int jtfs_forward_workspace_size(const jtfs_plan* P, int64_t B, size_t* bytes) {
     if (!P || !bytes) { set_error("null pointer"); return JTFS_EINVAL; }
-    if (B < 1) { set_error("B must be >= 1"); return JTFS_EINVAL; }
+    if (B < 1) { set_error("B must be >= 1"); return JTFS_ESHAPE; }
     *bytes = plan_layout(P, B).fwd_total;
     return JTFS_OK;
 }
@@ -1482,7 +1482,7 @@ extern "C" int jtfs_backward(const jtfs_plan* P, const float* x, const float* gs
 
 extern "C" int jtfs_zeroth_order(const jtfs_plan* P, const float* x, int64_t B, float* s0, hipStream_t st) {
     if (!P || !x || !s0) { set_error("null pointer"); return JTFS_EINVAL; }
-    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_EINVAL; }
+    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_ESHAPE; }
     const Shapes& s = P->s;
     hipLaunchKernelGGL(k_s0, dim3((unsigned)s.NT, (unsigned)B), dim3(256), 0, st, x, s.N, s.T, P->phiN, P->phiN_len,
                        P->phiN_half, s0);
@@ -1492,7 +1492,7 @@ extern "C" int jtfs_zeroth_order(const jtfs_plan* P, const float* x, int64_t B, 
 
 extern "C" int jtfs_zeroth_order_backward(const jtfs_plan* P, const float* gs0, int64_t B, float* gx, hipStream_t st) {
     if (!P || !gs0 || !gx) { set_error("null pointer"); return JTFS_EINVAL; }
-    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_EINVAL; }
+    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_ESHAPE; }
     const Shapes& s = P->s;
     hipLaunchKernelGGL(k_s0_bwd, dim3((unsigned)((s.N + 255) / 256), (unsigned)B), dim3(256), 0, st, gs0, s.N, s.T, s.NT,
                        P->phiN, P->phiN_len, P->phiN_half, gx);

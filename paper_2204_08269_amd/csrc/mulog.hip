@@ -134,7 +134,7 @@ static int launch_status(const char* what) {
 extern "C" int jtfs_path_means(const jtfs_plan* P, const float* s1, const float* s2, int64_t B, float* mu1,
                                float* mu2, hipStream_t st) {
     if (!P || !s1 || !s2 || !mu1 || !mu2) { set_error("null pointer"); return JTFS_EINVAL; }
-    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_EINVAL; }
+    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_ESHAPE; }
     const PathGeom g = geom(P);
     hipLaunchKernelGGL(k_path_mean, dim3((unsigned)(g.n_paths + 1)), dim3(256), 0, st, g, s1, s2, B, mu1, mu2);
     return launch_status("path means");
@@ -143,7 +143,7 @@ extern "C" int jtfs_path_means(const jtfs_plan* P, const float* s1, const float*
 extern "C" int jtfs_mulog(const jtfs_plan* P, const float* s1, const float* s2, int64_t B, const float* mu1,
                           const float* mu2, float eps, float* o1, float* o2, hipStream_t st) {
     if (!P || !s1 || !s2 || !mu1 || !mu2 || !o1 || !o2) { set_error("null pointer"); return JTFS_EINVAL; }
-    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_EINVAL; }
+    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_ESHAPE; }
     if (!(eps > 0.f)) { set_error("eps must be positive"); return JTFS_EINVAL; }
     const PathGeom g = geom(P);
     hipLaunchKernelGGL(k_mulog, dim3((unsigned)(g.n_paths + 1), (unsigned)B), dim3(256), 0, st, g, s1, s2, mu1, mu2,
@@ -155,7 +155,7 @@ extern "C" int jtfs_mulog_backward(const jtfs_plan* P, const float* s1, const fl
                                    const float* mu1, const float* mu2, float eps, const float* g1, const float* g2,
                                    float* gs1, float* gs2, hipStream_t st) {
     if (!P || !s1 || !s2 || !mu1 || !mu2 || !g1 || !g2 || !gs1 || !gs2) { set_error("null pointer"); return JTFS_EINVAL; }
-    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_EINVAL; }
+    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_ESHAPE; }
     if (!(eps > 0.f)) { set_error("eps must be positive"); return JTFS_EINVAL; }
     const PathGeom g = geom(P);
     hipLaunchKernelGGL(k_mulog_bwd, dim3((unsigned)(g.n_paths + 1), (unsigned)B), dim3(256), 0, st, g, s1, s2, mu1,

@@ -46,7 +46,7 @@ int scratch_ptr(int dev, void** out) {
 extern "C" int jtfs_forward_noalloc(const jtfs_plan* P, const float* x, int64_t B, float* s1, float* s2,
                                     hipStream_t st) {
     if (!P) { jtfs::set_error("null plan"); return JTFS_EINVAL; }
-    if (B < 1) { jtfs::set_error("B must be >= 1"); return JTFS_EINVAL; }
+    if (B < 1) { jtfs::set_error("B must be >= 1"); return JTFS_ESHAPE; }
     size_t need = 0;
     int rc = jtfs_forward_workspace_size(P, B, &need);
     if (rc != JTFS_OK) return rc;

@@ -240,6 +240,9 @@ int jtfs_query(const jtfs_params* p, jtfs_info* out) {
     out->s2_per_signal = s.tscat    ? (int64_t)s.n_alpha * s.n1 * s.NT
                          : s.avg_fr ? (int64_t)s.n_alpha * s.n_beta * 2 * s.NLo * s.NT
                                     : (int64_t)s.n_alpha * 2 * s.Mh * s.NT;
+    const jtfs::Workspace w = jtfs::layout(s, 1, true, true, false);
+    out->ws_fwd = (int64_t)w.fwd_total;
+    out->ws_bwd = (int64_t)w.total;
     return st;
 }
 

@@ -192,7 +192,7 @@ static int tex_evaluate(jtfs_texture* t, int init, float* hist, int cap, hipStre
 extern "C" int jtfs_texture_create(jtfs_texture** out, const jtfs_plan* plan, int64_t B, float mu0) {
     if (!out || !plan) { set_error("null pointer"); return JTFS_EINVAL; }
     *out = nullptr;
-    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_EINVAL; }
+    if (B < 1 || B > 65535) { set_error("B must lie in [1, 65535]"); return JTFS_ESHAPE; }
     if (!(mu0 != 0.f) || !std::isfinite(mu0)) { set_error("mu0 must be finite and non-zero"); return JTFS_EINVAL; }
     auto* t = new (std::nothrow) jtfs_texture();
     if (!t) { set_error("host allocation failed"); return JTFS_ENOMEM; }

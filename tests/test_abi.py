@@ -118,6 +118,7 @@ def test_lowpass_pairs_and_unpadded_sizes(L, cfg):
     assert i.s2_per_signal == int(np.prod(P.s2_shape()))
     j = L.query(L.params(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"]))
     assert (i.n_alpha, i.n_beta) == (j.n_alpha + 1, j.n_beta + 1)
+    assert 0 < j.ws_fwd < j.ws_bwd and i.ws_bwd > j.ws_bwd       # one more rate and scale: more workspace
     assert i.M_h == j.M_h + j.L // p["F"]           # phi_F kept at its critical rate: L / F rows
 
 

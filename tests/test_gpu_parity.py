@@ -203,6 +203,44 @@ def test_autograd_function_matches_vjp():
     assert not n1.requires_grad and torch.equal(n1, s1.detach()) and torch.equal(n2, s2.detach())
 
 
+def test_north_star_plan_create_matches_ex():
+    """jtfs_plan_create(N, J, Q[2], J_fr, Q_fr, T, F) builds the plan that
+    jtfs_plan_create_ex builds with no flags: the same sizes, workspace sizes per
+    signal that jtfs_workspace_size confirms, and bit-identical coefficients."""
+    import ctypes
+    from paper_2204_08269_amd import _lib
+    L = _lib.load()
+    p = P1
+    plan = ctypes.c_void_p()
+    _lib.check(L.jtfs_plan_create(ctypes.byref(plan), p["N"], p["J"], (ctypes.c_int * 2)(*p["Q"]), p["J_fr"],
+                                  p["Q_fr"], p["T"], p["F"]))
+    try:
+        info = _lib.Info()
+        _lib.check(L.jtfs_plan_info(plan, ctypes.byref(info)))
+        op = gpu_op(p)
+        for k in ("n1", "n_alpha", "n_beta", "L", "M_h", "out_t", "out_l", "s1_per_signal", "s2_per_signal",
+                  "ws_fwd", "ws_bwd"):
+            assert getattr(info, k) == getattr(op.info, k), k
+        n = ctypes.c_size_t(0)
+        _lib.check(L.jtfs_workspace_size(plan, 1, ctypes.byref(n)))
+        assert n.value == info.ws_bwd
+        _lib.check(L.jtfs_forward_workspace_size(plan, 1, ctypes.byref(n)))
+        assert n.value == info.ws_fwd
+        xt = torch.from_numpy(synth.batch(1, B=2)).cuda()
+        _lib.check(L.jtfs_workspace_size(plan, 2, ctypes.byref(n)))
+        ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        s1 = torch.empty((2,) + op.s1_shape, dtype=torch.float32, device="cuda")
+        s2 = torch.empty((2,) + op.s2_shape, dtype=torch.float32, device="cuda")
+        _lib.check(L.jtfs_forward(plan, ctypes.c_void_p(xt.data_ptr()), 2, ctypes.c_void_p(s1.data_ptr()),
+                                  ctypes.c_void_p(s2.data_ptr()), ctypes.c_void_p(ws.data_ptr()), n.value,
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        r1, r2 = op.forward(xt)
+        torch.cuda.synchronize()
+        assert torch.equal(s1, r1) and torch.equal(s2, r2)
+    finally:
+        L.jtfs_plan_destroy(plan)
+
+
 def test_ragged_bucket_graph_matches_oracle_and_replays():
     """Uneven lengths, bucketed to powers of two and run as one HIP graph: every
     signal's coefficients equal the oracle's on the zero-padded signal, the
