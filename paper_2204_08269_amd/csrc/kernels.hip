@@ -1224,7 +1224,9 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
             LAUNCHCHK("second order");
             continue;
         }
-        const int rows = std::min(64, std::max(1, (1 << lds_batch_log(P->tune)) >> logTa));   // <= 64: row-maximum slots
+        // <= 64 rows (row-maximum slots), and fewer where the grid would hold under ~1024 workgroups
+        const int fill = (int)std::max<int64_t>(1, ((int64_t)s.Kp * B + 1023) / 1024);
+        const int rows = std::min({64, std::max(1, (1 << lds_batch_log(P->tune)) >> logTa), fill});
         const size_t lds = sizeof(float2) * rows * lpad_len(s.Ta[a]);
         const Family& f2 = s.f2;
         // packed second-order spectrum of alpha: the plan's device table at its offset

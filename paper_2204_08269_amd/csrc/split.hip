@@ -143,7 +143,8 @@ __global__ void k_phtsplit(const float* __restrict__ Phi, int Tp, int NTp, float
 // lo, im hi, im lo): each lane of the contraction reads 8 consecutive lambda_1 of
 // one t as 16 bytes, and the 32 lanes of a column block read 512 contiguous bytes.
 // sy = 2^(13-e) from the block maximum (row maxima written by the second-order
-// kernel).  grid (Tp/64, B), 256 threads.
+// kernel).  grid (Tp/64, B, Z), 256 threads: block z takes the 32-row chunks
+// z, z + Z, ... (Z > 1 where Tp/64 x B alone would leave the GPU idle).
 __global__ void __launch_bounds__(256) k_ysplit(const float2* __restrict__ Y, int64_t y_bstride, int Tp, int Kp,
                                                 const float* __restrict__ rowmax, int alpha, int n_alpha,
                                                 unsigned short* __restrict__ Yh, float* __restrict__ yscale) {
@@ -161,10 +162,10 @@ __global__ void __launch_bounds__(256) k_ysplit(const float2* __restrict__ Y, in
         __syncthreads();
     }
     const float sy = pow2_scale(red[0]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) yscale[b * n_alpha + alpha] = sy;
+    if (blockIdx.x == 0 && blockIdx.z == 0 && threadIdx.x == 0) yscale[b * n_alpha + alpha] = sy;
     const float2* Yb = Y + b * y_bstride;
     _Float16* Ho = (_Float16*)Yh + b * y_bstride * 4;
-    for (int k0 = 0; k0 < Kp; k0 += 32) {
+    for (int k0 = 32 * (int)blockIdx.z; k0 < Kp; k0 += 32 * (int)gridDim.z) {
         const int nk = min(32, Kp - k0);
         __syncthreads();
         for (int e = threadIdx.x; e < nk * 64; e += 256) {
@@ -1963,8 +1964,12 @@ int launch_ysplit(const jtfs_plan* P, int a, const float2* Y2, const float* rowm
                   int64_t B, hipStream_t st) {
     const Shapes& s = P->s;
     const int64_t yb = (int64_t)s.Kp * s.sumTp;
-    hipLaunchKernelGGL(k_ysplit, dim3(s.Tp[a] / 64, (unsigned)B), dim3(256), 0, st, Y2 + s.yoff[a], yb, s.Tp[a], s.Kp,
-                       rowmax, a, s.n_alpha, Yh + s.yoff[a] * 4, yscale);
+    // chunks of 32 rows spread over grid z until there are about 2048 workgroups
+    const int64_t base = (int64_t)(s.Tp[a] / 64) * B;
+    const int nchunk = (s.Kp + 31) / 32;
+    const int z = (int)std::max<int64_t>(1, std::min<int64_t>(nchunk, (2048 + base - 1) / base));
+    hipLaunchKernelGGL(k_ysplit, dim3(s.Tp[a] / 64, (unsigned)B, (unsigned)z), dim3(256), 0, st, Y2 + s.yoff[a], yb,
+                       s.Tp[a], s.Kp, rowmax, a, s.n_alpha, Yh + s.yoff[a] * 4, yscale);
     return hipGetLastError() == hipSuccess ? JTFS_OK : JTFS_EHIP;
 }
 
