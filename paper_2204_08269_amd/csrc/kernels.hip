@@ -772,6 +772,88 @@ __global__ void __launch_bounds__(256) k_s2_bwd(const float* __restrict__ gS2, c
     }
 }
 
+// Adjoint of the frequency lowpass of eq. (3): gV[rowoff + l][tau] =
+// sum_m PF_beta[m][l] gS2[m][tau] over the NLo output rows m, with the row sums
+// over tau of |gV| whose maximum sets the split scale of the backward
+// contraction.  One lane per row l: the gS2 tile (after the mu-log adjoint when
+// set) sits in LDS and every lane reads the same element of it at a time (a
+// broadcast), PF[m][l] comes from global memory with consecutive lanes on
+// consecutive l, and each lane keeps TT outputs of its row in registers, stores
+// them as 16-byte writes and sums their moduli itself.  grid (n_beta + 1,
+// 2 n_alpha, B); block n_beta zeroes the padding rows Mh..Mp.
+template <int TT>
+__global__ void __launch_bounds__(256) k_s2_bwd_avg(const float* __restrict__ gS2, const float* __restrict__ PFall,
+                                                    const int64_t* __restrict__ pfoff, const int* __restrict__ Lbv,
+                                                    const int* __restrict__ rowoffv, int n_beta, int NLo, int NT,
+                                                    int NTp, int Mh, int Mp, int n_alpha, float* __restrict__ gV,
+                                                    float* __restrict__ gvmax, MuLogArg ml) {
+    extern __shared__ __align__(16) float st[];      // gS2 tile [NLo][NT]
+    __shared__ float red[256];
+    const int beta = blockIdx.x, th = blockIdx.y & 1, alpha = blockIdx.y >> 1;
+    const int64_t b = blockIdx.z;
+    float* g = gV + (((b * n_alpha + alpha) * 2 + th) * (int64_t)Mp) * NTp;
+    if (beta == n_beta) {
+        for (int e = threadIdx.x; e < (Mp - Mh) * NTp; e += blockDim.x) g[(int64_t)Mh * NTp + e] = 0.f;
+        return;
+    }
+    const int Lb = Lbv[beta], ro = rowoffv[beta];
+    const float* PF = PFall + pfoff[beta];           // [NL][Lb]
+    const int64_t so = ((((b * n_alpha + alpha) * n_beta + beta) * 2 + th) * NLo) * (int64_t)NT;
+    const float* src = gS2 ? gS2 + so : nullptr;
+    const float* osrc = ml.mu2 ? ml.o2 + so : nullptr;
+    const float em = ml.mu2 ? ml.eps * ml.mu2[(alpha * n_beta + beta) * 2 + th] : 0.f;
+    for (int e = threadIdx.x; e < NLo * NT; e += blockDim.x)
+        st[e] = src ? mulog_cot(src[e], ml.mu2, em, osrc ? osrc[e] : 0.f) : 0.f;
+    __syncthreads();
+    float mx = 0.f;
+    for (int l = threadIdx.x; l < Lb; l += blockDim.x) {
+        float* grow = g + (int64_t)(ro + l) * NTp;
+        float rs = 0.f;
+        for (int t0 = 0; t0 < NTp; t0 += TT) {
+            float acc[TT];
+#pragma unroll
+            for (int j = 0; j < TT; ++j) acc[j] = 0.f;
+            if (t0 < NT) {
+                if (NT - t0 >= TT) {
+                    for (int m = 0; m < NLo; ++m) {
+                        const float p = PF[(int64_t)m * Lb + l];
+                        const float4* s4 = (const float4*)(st + m * NT + t0);
+#pragma unroll
+                        for (int q = 0; q < TT / 4; ++q) {
+                            const float4 v = s4[q];
+                            acc[4 * q] += p * v.x;
+                            acc[4 * q + 1] += p * v.y;
+                            acc[4 * q + 2] += p * v.z;
+                            acc[4 * q + 3] += p * v.w;
+                        }
+                    }
+                } else {
+                    for (int m = 0; m < NLo; ++m) {
+                        const float p = PF[(int64_t)m * Lb + l];
+#pragma unroll
+                        for (int j = 0; j < TT; ++j)
+                            if (t0 + j < NT) acc[j] += p * st[m * NT + t0 + j];
+                    }
+                }
+            }
+            float4* o4 = (float4*)(grow + t0);
+#pragma unroll
+            for (int q = 0; q < TT / 4; ++q) {
+                o4[q] = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+                rs += fabsf(acc[4 * q]) + fabsf(acc[4 * q + 1]) + fabsf(acc[4 * q + 2]) + fabsf(acc[4 * q + 3]);
+            }
+        }
+        mx = fmaxf(mx, rs);
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gvmax[((b * n_alpha + alpha) * 2 + th) * n_beta + beta] = red[0];
+}
+
 // Recompute Z = W Y (both spins) on a 64 l x 64 t tile, gU = gV Phi^T (adjoint of
 // the time lowpass), gZ = gU Z / max(|Z|, eps) (modulus adjoint), and store
 // P = gZ_up + gZ_down and Q' = i (gZ_down - gZ_up), so that the adjoint of the
@@ -1055,8 +1137,8 @@ int setup_kernel_attributes() {
     const int lds = kMaxDynLds;
     const void* ks[] = {(const void*)k_fft_cols_t<float2, float2>, (const void*)k_fft_cols_t<float2, double2>,
                         (const void*)k_fft_cols_t<double2, double2>, (const void*)k_scalogram, (const void*)k_s1,
-                        (const void*)k_s2_bwd, (const void*)k_second_order, (const void*)k_scal_bwd_a,
-                        (const void*)k_scal_bwd_b};
+                        (const void*)k_s2_bwd, (const void*)k_s2_bwd_avg<16>, (const void*)k_s2_bwd_avg<32>,
+                        (const void*)k_second_order, (const void*)k_scal_bwd_a, (const void*)k_scal_bwd_b};
     for (const void* k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) {
@@ -1370,9 +1452,17 @@ int backward_impl(const jtfs_plan* P, const float* x, const float* gs1, const fl
     }
     if (!s.tscat) {
         // every temporal rate in one launch
-        JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_s2_bwd, dim3(s.n_beta + 1, 2 * s.n_alpha, (unsigned)B), dim3(256), s2_bwd_lds(s), st, gs2, P->PF, P->d_pfoff, P->d_Lb,
-                           P->d_rowoff, s.n_beta, s.NL, s.NLo, s.NT, s.NTp, s.Mh, s.Mp, s.n_alpha, (int)s.avg_fr,
-                           s2_bwd_stage(s), gV, (float*)(base + w.gvmax), ml));
+        const dim3 grid(s.n_beta + 1, 2 * s.n_alpha, (unsigned)B);
+        if (s.avg_fr) {
+            auto k = s.NTp % 32 == 0 && s.NT >= 32 ? k_s2_bwd_avg<32> : k_s2_bwd_avg<16>;
+            JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k, grid, dim3(256), sizeof(float) * s.NLo * s.NT, st, gs2,
+                               P->PF, P->d_pfoff, P->d_Lb, P->d_rowoff, s.n_beta, s.NLo, s.NT, s.NTp, s.Mh, s.Mp,
+                               s.n_alpha, gV, (float*)(base + w.gvmax), ml));
+        } else {
+            JTFS_TIMED(JTFS_STAGE_LOWPASS_ADJ, st, hipLaunchKernelGGL(k_s2_bwd, grid, dim3(256), s2_bwd_lds(s), st, gs2, P->PF, P->d_pfoff, P->d_Lb,
+                               P->d_rowoff, s.n_beta, s.NL, s.NLo, s.NT, s.NTp, s.Mh, s.Mp, s.n_alpha, (int)s.avg_fr,
+                               s2_bwd_stage(s), gV, (float*)(base + w.gvmax), ml));
+        }
         LAUNCHCHK("frequency lowpass adjoint");
     }
     const bool split = split_backward(P);
