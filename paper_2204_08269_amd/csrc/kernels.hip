@@ -1404,7 +1404,8 @@ static int gy2_row_fft(const jtfs_plan* P, int a, float2* gY2, int64_t yb, int64
     const int lb = lds_batch_log(P->tune);
     const int logC = logTa >= lb ? 0 : lb - logTa;
     const size_t lds = (size_t)(1 << logC) * (lpad_len(s.Ta[a]) + 1) * sizeof(float2);
-    if (use_reg_rows(logTa, P->tune.reg_rowfft)) {
+    // rows of 2^13 points take the register-resident transform with the same choice as 2^14
+    if (use_reg_rows(logTa, P->tune.reg_rowfft) || (logTa == kRegMinLogRows - 1 && P->tune.reg_rowfft)) {
         JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st,
                    launch_rowfft_r(P, gY2 + s.yoff[a], yb, (int64_t)s.Tp[a], s.n1, logTa, B, st));
     } else {

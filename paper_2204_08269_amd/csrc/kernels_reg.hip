@@ -317,6 +317,23 @@ __global__ void __launch_bounds__(kRegT) k_rowfft_r(float2* __restrict__ base, i
     }
 }
 
+// Rows of 2^13 points: one register transform of 8 values per thread on the same
+// 1024 threads; its exchange buffer (72 KB) and at most 64 VGPRs let two
+// workgroups share a CU.
+__global__ void __launch_bounds__(kRegT, 8) k_rowfft_r13(float2* __restrict__ base, int64_t bs, int64_t rs,
+                                                        const float2* __restrict__ tw, int tw_log) {
+    extern __shared__ __align__(16) float xbuf[];
+    constexpr int E = kRegE / 2, LOGN = kRegMinLog - 1;
+    float2* row = base + (int64_t)blockIdx.y * bs + (int64_t)blockIdx.x * rs;
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = row[reg_input_pos<LOGN, E>(e)];
+    reg_fft<E, LOGN>(v, xbuf, tw, tw_log, false);
+    __syncthreads();      // every thread has read its inputs before any output is stored
+#pragma unroll
+    for (int e = 0; e < E; ++e) row[reg_output_pos<LOGN, E>(e)] = v[e];
+}
+
 // adjoint of the modulus and first-order filter for one row: recompute y, weight
 // gX by its phase, forward FFT -> g1[b][lambda][0..NX)
 template <bool TWO, int LRM>
@@ -496,7 +513,7 @@ int reg_attributes() {
                         JTFS_REG_VARIANTS(k_rowfft_r), JTFS_REG_VARIANTS(k_scal_bwd_b_r),
                         (const void*)k_scal_bwd_a_r<kRegE, kRegMinLog, 4>,
                         (const void*)k_scal_bwd_a_r<kRegE, kRegMinLog, 3>,
-                        (const void*)k_scal_bwd_a_r<kRegE / 2, kRegMinLog - 1, 3>};
+                        (const void*)k_scal_bwd_a_r<kRegE / 2, kRegMinLog - 1, 3>, (const void*)k_rowfft_r13};
     for (const void* k : ks)
         if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds) != hipSuccess) {
             set_error("hipFuncSetAttribute failed for the long-row kernels");
@@ -539,6 +556,11 @@ void launch_second_order_r(const jtfs_plan* P, int a, const float2* Xh, int64_t 
 
 void launch_rowfft_r(const jtfs_plan* P, float2* base, int64_t bs, int64_t rs, int rows, int logn, int64_t B,
                      hipStream_t st) {
+    if (logn == kRegMinLog - 1) {
+        hipLaunchKernelGGL(k_rowfft_r13, dim3((unsigned)rows, (unsigned)B), dim3(reg_threads()),
+                           sizeof(float) * (size_t)reg_xbuf_floats(kRegMinLog - 1), st, base, bs, rs, P->tw, P->tw_log);
+        return;
+    }
     auto k = JTFS_REG_PICK(k_rowfft_r, logn, P->tune.r8_rowfft);
     hipLaunchKernelGGL(k, dim3((unsigned)rows, (unsigned)B), dim3(reg_threads()), reg_lds(0), st,
                        base, bs, rs, logn, P->tw, P->tw_log);
