@@ -1300,7 +1300,8 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
     }
     for (int a = 0; a < s.n_alpha_psi; ++a) {
         const int logTa = s.logNX - s.k2[a];
-        if (use_reg_rows(logTa, P->tune.reg_second)) {
+        // rows of 2^13 points take the register-resident transform with the same choice as 2^14
+        if (use_reg_rows(logTa, P->tune.reg_second) || (logTa == kRegMinLogRows - 1 && P->tune.reg_second)) {
             JTFS_TIMED(JTFS_STAGE_SECOND_ORDER, st,
                        launch_second_order_r(P, a, Xh, w.Xh_pitch, Y2, (float*)(base + w.rowmax), B, st));
             LAUNCHCHK("second order");

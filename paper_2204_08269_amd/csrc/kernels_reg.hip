@@ -33,17 +33,17 @@ __device__ __forceinline__ float2 fold_at(const float2* __restrict__ src, const 
 // of reg_fft), folded from src * ps over [lo, hi].  When the band fits the row
 // every bin receives at most one band sample, and the loads go out four
 // elements at a time with no loop between them.
-template <int LOGM, int LRM = reg_lr_max(kRegE)>
-__device__ __forceinline__ void fold_inputs(float2 (&v)[kRegE], const float2* __restrict__ src,
+template <int LOGM, int LRM = reg_lr_max(kRegE), int EE = kRegE>
+__device__ __forceinline__ void fold_inputs(float2 (&v)[EE], const float2* __restrict__ src,
                                             const float* __restrict__ ps, int lo, int hi) {
     constexpr int M = 1 << LOGM;
     if (hi - lo < M) {
 #pragma unroll
-        for (int e0 = 0; e0 < kRegE; e0 += 4) {
+        for (int e0 = 0; e0 < EE; e0 += 4) {
             float g[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int p = reg_input_pos<LOGM, kRegE, LRM>(e0 + q);
+                const int p = reg_input_pos<LOGM, EE, LRM>(e0 + q);
                 const int m = lo + ((p - lo) & (M - 1));
                 const bool ok = m <= hi;
                 v[e0 + q] = ok ? src[m] : make_float2(0.f, 0.f);
@@ -55,7 +55,7 @@ __device__ __forceinline__ void fold_inputs(float2 (&v)[kRegE], const float2* __
         return;
     }
 #pragma unroll
-    for (int e = 0; e < kRegE; ++e) v[e] = fold_at(src, ps, lo, hi, LOGM, reg_input_pos<LOGM, kRegE, LRM>(e));
+    for (int e = 0; e < EE; ++e) v[e] = fold_at(src, ps, lo, hi, LOGM, reg_input_pos<LOGM, EE, LRM>(e));
 }
 
 // Rows of 2^15 points run as two 2^14-point register transforms:
@@ -317,6 +317,44 @@ __global__ void __launch_bounds__(kRegT) k_rowfft_r(float2* __restrict__ base, i
     }
 }
 
+// Second-order rows of 2^13 points: the fold, inverse transform and row maximum of
+// k_second_order_r with one register transform of 8 values per thread on the same
+// 1024 threads (two workgroups per CU).
+__global__ void __launch_bounds__(kRegT, 8) k_second_order_r13(const float2* __restrict__ Xh, int64_t Xh_pitch, int n1,
+                                                              const float* __restrict__ ps, int lo, int hi, int Tp,
+                                                              int Kp, float2* __restrict__ Y, int64_t y_bstride,
+                                                              float invNX, const float2* __restrict__ tw, int tw_log,
+                                                              float* __restrict__ rowmax, int alpha, int n_alpha) {
+    extern __shared__ __align__(16) float xbuf[];
+    __shared__ unsigned int rmx;
+    constexpr int E = kRegE / 2, LOGN = kRegMinLog - 1;
+    const int lam = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    float2* out = Y + b * y_bstride + (int64_t)lam * Tp;
+    if (lam >= n1) {
+        for (int t = threadIdx.x; t < Tp; t += blockDim.x) out[t] = make_float2(0.f, 0.f);
+        if (threadIdx.x == 0) rowmax[(b * n_alpha + alpha) * Kp + lam] = 0.f;
+        return;
+    }
+    if (threadIdx.x == 0) rmx = 0u;
+    float2 v[E];
+    fold_inputs<LOGN, reg_lr_max(E), E>(v, Xh + (b * n1 + lam) * Xh_pitch, ps, lo, hi);
+    reg_fft<E, LOGN>(v, xbuf, tw, tw_log, true);
+    float m = 0.f;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const float2 y = cscale(v[e], invNX);
+        out[reg_output_pos<LOGN, E>(e)] = y;
+        m = fmaxf(m, fmaxf(fabsf(y.x), fabsf(y.y)));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) atomicMax(&rmx, __float_as_uint(m));
+    __syncthreads();
+    if (threadIdx.x == 0) rowmax[(b * n_alpha + alpha) * Kp + lam] = __uint_as_float(rmx);
+}
+
 // Rows of 2^13 points: one register transform of 8 values per thread on the same
 // 1024 threads; its exchange buffer (72 KB) and at most 64 VGPRs let two
 // workgroups share a CU.
@@ -513,7 +551,8 @@ int reg_attributes() {
                         JTFS_REG_VARIANTS(k_rowfft_r), JTFS_REG_VARIANTS(k_scal_bwd_b_r),
                         (const void*)k_scal_bwd_a_r<kRegE, kRegMinLog, 4>,
                         (const void*)k_scal_bwd_a_r<kRegE, kRegMinLog, 3>,
-                        (const void*)k_scal_bwd_a_r<kRegE / 2, kRegMinLog - 1, 3>, (const void*)k_rowfft_r13};
+                        (const void*)k_scal_bwd_a_r<kRegE / 2, kRegMinLog - 1, 3>, (const void*)k_rowfft_r13,
+                        (const void*)k_second_order_r13};
     for (const void* k : ks)
         if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds) != hipSuccess) {
             set_error("hipFuncSetAttribute failed for the long-row kernels");
@@ -548,6 +587,13 @@ void launch_second_order_r(const jtfs_plan* P, int a, const float2* Xh, int64_t 
     const Shapes& s = P->s;
     const int logTa = s.logNX - s.k2[a];
     const Family& f2 = s.f2;
+    if (logTa == kRegMinLog - 1) {
+        hipLaunchKernelGGL(k_second_order_r13, dim3(s.Kp, (unsigned)B), dim3(reg_threads()),
+                           sizeof(float) * (size_t)reg_xbuf_floats(kRegMinLog - 1), st, Xh, Xh_pitch, s.n1,
+                           P->psi2 + f2.off[a], f2.lo[a], f2.hi[a], s.Tp[a], s.Kp, Y2 + s.yoff[a],
+                           (int64_t)s.Kp * s.sumTp, 1.0f / (float)s.NX, P->tw, P->tw_log, rowmax, a, s.n_alpha);
+        return;
+    }
     auto k = JTFS_REG_PICK(k_second_order_r, logTa, P->tune.r8_second);
     hipLaunchKernelGGL(k, dim3(s.Kp, (unsigned)B), dim3(reg_threads()), reg_lds((size_t)1 << logTa), st, Xh, Xh_pitch,
                        s.n1, P->psi2 + f2.off[a], f2.lo[a], f2.hi[a], logTa, s.Tp[a], s.Kp, Y2 + s.yoff[a],
