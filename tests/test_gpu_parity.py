@@ -553,7 +553,7 @@ def test_mulog_time_scattering_matches_oracle():
 
 
 @pytest.mark.parametrize("variant,mode", [("eq3", None), ("eq3", "split16_phase"), ("eq4", None),
-                                          ("time_scattering", None)])
+                                          ("time_scattering", None), ("eq3_lowpass_pairs", "split16_phase")])
 def test_fused_mulog_matches_oracle(variant, mode):
     """mu-log fused into the transform's output kernels (sec. 4, eqs. (9)-(10)),
     mu given (here the oracle's path means of the batch): the outputs per path
@@ -561,11 +561,13 @@ def test_fused_mulog_matches_oracle(variant, mode):
     mulog(forward), and the gradient with mu fixed against the oracle's VJP of
     the mu-log adjoint, through the C ABI (eq. (3), eq. (4), time scattering) and
     through autograd with the stored phase."""
-    P = oracle_plan(P1)
+    lp = variant == "eq3_lowpass_pairs"
+    p1 = dict(P1, lowpass_pairs=True) if lp else P1
+    P = oracle_plan(p1)
     x = synth.batch(1, B=3)
     tsc = variant == "time_scattering"
-    avg = variant == "eq3"
-    op = gpu_op(P1, contraction=mode, average_fr=avg or tsc, time_scattering=tsc)
+    avg = variant.startswith("eq3")
+    op = gpu_op(p1, contraction=mode, average_fr=avg or tsc, time_scattering=tsc)
     xt = torch.from_numpy(x).cuda()
     if tsc:
         refs = [O.scattering1d(x[b].astype(np.float64), P) for b in range(3)]
@@ -573,7 +575,7 @@ def test_fused_mulog_matches_oracle(variant, mode):
         refs = [O.jtfs(x[b].astype(np.float64), P, average_fr=avg) for b in range(3)]
     R1 = np.stack([r[0] for r in refs])
     R2 = np.stack([r[1] for r in refs])
-    if variant == "eq3":
+    if avg:
         m1, m2 = O.path_means(R1, R2)
         m2_rows, axes = m2, 2                   # one mu per (alpha, beta, theta) slice
     elif tsc:
@@ -607,7 +609,7 @@ def test_fused_mulog_matches_oracle(variant, mode):
     assert torch.equal(o1, u1) and torch.equal(o2, u2), "fused and unfused mu-log differ"
     o1, o2, gx = o1.detach().cpu().numpy(), o2.detach().cpu().numpy(), gx.cpu().numpy()
     for b in range(3):
-        if variant == "eq3":
+        if avg:
             check_paths(o1[b], o2[b], e1[b], e2[b])
         else:
             assert path_errors(o1[b], e1[b], 1)[0].max() <= TOL
