@@ -532,7 +532,7 @@ def jtfs_direct(x, P: Plan, average_fr=True):
                 Z = _circ_direct(Yp.T, h, 1 << P.k_fr[b]).T          # along lambda
                 V = _circ_direct(np.abs(Z).astype(complex), phiU, P.T >> (P.kX + P.k2[a])).real
                 if average_fr:
-                    S2[a, b, s] = _circ_direct(V.T, phiF, P.F >> P.k_fr[b]).T
+                    S2[a, b, s] = _circ_direct(V.T, phiF, P.F >> P.k_fr[b]).T[: P.out_l]
                 else:
                     S2[a, P.s2_rows(b, s)] = V
     return S1, S2

@@ -273,7 +273,7 @@ def test_lowpass_pairs_pure_tone(P1):
 @pytest.mark.parametrize("p", SMALL)
 @pytest.mark.parametrize("average_fr", [True, False])
 def test_lowpass_pairs_cascade_matches_direct_sums(p, average_fr):
-    P = _plan_opts(p, lowpass_pairs=True)
+    P = _plan_opts(p, lowpass_pairs=True, unpad=average_fr)
     x = np.random.default_rng(p["N"] + 11).standard_normal(p["N"])
     a1, a2 = O.jtfs(x, P, average_fr=average_fr)
     b1, b2 = O.jtfs_direct(x, P, average_fr=average_fr)
