@@ -622,8 +622,13 @@ __global__ void __launch_bounds__(512) k_freq_fwd_q(const unsigned short* __rest
     // this lane's Y fragments: column t, k-group 4 ks + g4, plane p (uint4 units)
     const int tbeg = ch * chunk, tend = (ch + 1) * chunk;
     auto ycol_at = [&](int t0) {
-        const int t = t0 + wave * 16 + j16;
-        return launder_v((const uint4*)Yb + (((int64_t)(t >> 5) * nkb + g4) * 128 + (t & 31)));
+        // the column offset formed from the thread index here, not kept live across
+        // the tile loop (at 256 registers the compiler spilled it, and its reload
+        // waited for every memory operation in flight)
+        int tq = (int)threadIdx.x;
+        asm volatile("" : "+v"(tq));
+        const int t = t0 + (tq >> 6) * 16 + (tq & 15);
+        return launder_v((const uint4*)Yb + (((int64_t)(t >> 5) * nkb + ((tq >> 4) & 3)) * 128 + (t & 31)));
     };
     auto load_yq = [&](uint4 (&y)[4], gptr<uint4> yc, int ks) {
         gptr<u32x4> p = (gptr<u32x4>)(yc + 512 * ks);
