@@ -375,9 +375,14 @@ def run_workload(torch, dev, cfg, args, extras=True, stage_pass=True):
         # plain single-signal forward: no stored phase (a plain forward has no
         # backward to serve), same plan parameters
         plain = "split16" if op.contraction == "split16_phase" else op.contraction
-        op1 = op if plain == op.contraction else JTFS(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"],
-                                                      contraction=plain)
+        op1 = JTFS(p["N"], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"], contraction=plain)   # a plan of its own
         x1 = x[:1].contiguous()
+        if not args.no_autotune:
+            # launch choices for one signal (the t-chunk above all), in the plain mode
+            t1 = op1.autotune(1, x1, reps=3)
+            op1.set_tuning(plain, t1["register_rows"], fwd_tile=t1["fwd_tile"], bwd_tile=t1["bwd_tile"],
+                           radix8=t1["radix8"], lds_batch=t1["lds_batch"], t_chunk=t1["t_chunk"])
+            res["single_tuning"] = {k: t1[k] for k in ("register_rows", "fwd_tile", "radix8", "lds_batch", "t_chunk")}
         ws1 = op1.new_workspace(1)
         for _ in range(3):
             op1.forward(x1, ws1)
@@ -515,6 +520,8 @@ def main():
         out["plain_fwd_single_msamples_s"] = round(res["N"] / (res["single_ms"] * 1e-3) / 1e6, 3)
         out["plain_fwd_single_ms"] = round(res["single_ms"], 3)
         out["plain_fwd_single_contraction"] = res["single_contraction"]
+        if "single_tuning" in res:
+            out["plain_fwd_single_tuning"] = res["single_tuning"]
         out["mulog_fwd_ms"] = {k: round(v, 3) for k, v in res["mulog_ms"].items()}
         out["stage_ms_per_step"] = {k: round(v[0] / args.steps, 3) for k, v in res["stages"].items()}
         out["roofline"] = roof

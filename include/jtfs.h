@@ -376,9 +376,10 @@ void jtfs_texture_destroy(jtfs_texture* tex);
  * fwd_ms, bwd_ms: the chosen mode's forward contraction and backward contraction
  * per step with 32 x 32 and 16 x 16 tiles (0 where not run).  Then, for the chosen
  * mode and tiles, one run with every register-resident stage in radix-8 passes
- * (where rows of 2^14 points or more exist) and one with 8192-point in-LDS
- * workgroups (where rows of 2^12 points or fewer exist) settle those bits per
- * stage (a stage must gain 1 % to take the other setting). */
+ * (where rows of 2^14 points or more exist), one with 8192-point in-LDS
+ * workgroups (where rows of 2^12 points or fewer exist) and one with 1024-column
+ * t-chunks in the forward contraction (where a rate has more than 1024 columns)
+ * settle those bits per stage (a stage must gain 1 % to take the other setting). */
 #define JTFS_REG_SCALOGRAM    1
 #define JTFS_REG_SECOND_ORDER 2
 #define JTFS_REG_ROW_FFT      4
@@ -400,6 +401,14 @@ void jtfs_texture_destroy(jtfs_texture* tex);
  * transforms (rows shorter than 2^13: more rows per workgroup, fewer
  * workgroups of twice the LDS), else 4096. */
 #define JTFS_TUNE_LDS_BATCH8K 1024
+/* ... and the t-columns per workgroup of the forward contraction (its t-chunk):
+ * 1024 or 2048 where one of these bits is set (1024 if both), else 4096.  Shorter
+ * chunks give more workgroups to small batches and more partial V slots to sum;
+ * the workspace size follows the choice (query it again after setting it).
+ * Changing it rewrites two small device tables of the plan: not while work of
+ * the plan is in flight. */
+#define JTFS_TUNE_TCHUNK_1K   2048
+#define JTFS_TUNE_TCHUNK_2K   4096
 typedef struct {
     int32_t contraction;
     int32_t reg_rows;                 /* including JTFS_TUNE_FWD_TILE16 */

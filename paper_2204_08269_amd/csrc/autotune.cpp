@@ -10,8 +10,9 @@
 // mode (all register-resident with 32 x 32 tiles, all in LDS with 16 x 16 tiles)
 // rather than from thirty-two.  For the chosen mode, one more run each settles
 // the largest radix of the register-resident transforms' passes (16 or 8, per
-// stage) and the points per workgroup of the in-LDS row transforms (4096 or
-// 8192, i.e. how many workgroups share a CU's LDS).  Results can be kept in a
+// stage), the points per workgroup of the in-LDS row transforms (4096 or
+// 8192, i.e. how many workgroups share a CU's LDS) and the forward contraction's
+// t-chunk (1024 or 4096 columns per workgroup).  Results can be kept in a
 // text file keyed by the device and the plan's shape (JTFS_TUNE_CACHE).
 #include <hip/hip_runtime.h>
 
@@ -50,6 +51,14 @@ void set_rows(jtfs_plan* P, int mask) {
     P->tune.r8_rowfft = (mask & JTFS_TUNE_RADIX8_ROW_FFT) != 0;
     P->tune.r8_first_adj = (mask & JTFS_TUNE_RADIX8_FIRST_ADJ) != 0;
     P->tune.batch8k = (mask & JTFS_TUNE_LDS_BATCH8K) != 0;
+    const int chunk = (mask & JTFS_TUNE_TCHUNK_1K) ? 1024 : (mask & JTFS_TUNE_TCHUNK_2K) ? 2048 : kChunkT;
+    if (chunk != P->tune.chunk) {
+        // the partial-V slot tables of the shapes and their device copies
+        P->tune.chunk = chunk;
+        set_chunks(&P->s, chunk);
+        (void)hipMemcpy(P->d_vchoff, P->s.vchoff.data(), sizeof(int64_t) * P->s.n_alpha, hipMemcpyHostToDevice);
+        (void)hipMemcpy(P->d_nch, P->s.nch.data(), sizeof(int) * P->s.n_alpha, hipMemcpyHostToDevice);
+    }
 }
 
 constexpr int kRadix8Bits = JTFS_TUNE_RADIX8_SCALOGRAM | JTFS_TUNE_RADIX8_SECOND_ORDER | JTFS_TUNE_RADIX8_ROW_FFT |
@@ -61,7 +70,8 @@ int get_rows(const jtfs_plan* P) {
            (P->tune.fwd16 ? JTFS_TUNE_FWD_TILE16 : 0) | (P->tune.bwd16 ? JTFS_TUNE_BWD_TILE16 : 0) |
            (P->tune.r8_scalogram ? JTFS_TUNE_RADIX8_SCALOGRAM : 0) |
            (P->tune.r8_second ? JTFS_TUNE_RADIX8_SECOND_ORDER : 0) | (P->tune.r8_rowfft ? JTFS_TUNE_RADIX8_ROW_FFT : 0) |
-           (P->tune.r8_first_adj ? JTFS_TUNE_RADIX8_FIRST_ADJ : 0) | (P->tune.batch8k ? JTFS_TUNE_LDS_BATCH8K : 0);
+           (P->tune.r8_first_adj ? JTFS_TUNE_RADIX8_FIRST_ADJ : 0) | (P->tune.batch8k ? JTFS_TUNE_LDS_BATCH8K : 0) |
+           (P->tune.chunk == 1024 ? JTFS_TUNE_TCHUNK_1K : P->tune.chunk == 2048 ? JTFS_TUNE_TCHUNK_2K : 0);
 }
 
 // Cache key: the device's architecture and name, the plan parameters and B.
@@ -158,7 +168,8 @@ int run_steps(jtfs_plan* P, const float* x, int64_t B, float* s1, float* s2, flo
 extern "C" int jtfs_plan_set_tuning(jtfs_plan* P, int contraction, int reg_rows) {
     if (!P) { set_error("null plan"); return JTFS_EINVAL; }
     if (reg_rows & ~(JTFS_REG_SCALOGRAM | JTFS_REG_SECOND_ORDER | JTFS_REG_ROW_FFT | JTFS_REG_FIRST_ADJ |
-                     JTFS_TUNE_FWD_TILE16 | JTFS_TUNE_BWD_TILE16 | kRadix8Bits | JTFS_TUNE_LDS_BATCH8K)) {
+                     JTFS_TUNE_FWD_TILE16 | JTFS_TUNE_BWD_TILE16 | kRadix8Bits | JTFS_TUNE_LDS_BATCH8K |
+                     JTFS_TUNE_TCHUNK_1K | JTFS_TUNE_TCHUNK_2K)) {
         set_error("unknown row-kernel bits"); return JTFS_EINVAL; }
     const int rc = jtfs_plan_set_contraction(P, contraction);
     if (rc != JTFS_OK) return rc;
@@ -225,14 +236,17 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
     if (has14 || tile16 || btile16)
         row_opts.push_back((has14 ? 0 : all_rows) | (tile16 ? JTFS_TUNE_FWD_TILE16 : 0) |
                            (btile16 ? JTFS_TUNE_BWD_TILE16 : 0));
-    // buffers: the largest workspace over the modes; the coefficients double as cotangents
+    // buffers: the largest workspace over the modes (at the shortest t-chunk, whose
+    // partial V is largest); the coefficients double as cotangents
     size_t wsb = 0;
+    set_rows(P, saved_rows | JTFS_TUNE_TCHUNK_1K);
     for (int m : modes) {
         P->contraction = m;
         size_t b = 0;
         jtfs_workspace_size(P, B, &b);
         wsb = std::max(wsb, b);
     }
+    set_rows(P, saved_rows);
     DevBuf ws, s1, s2, gx, xz;
     if (!ws.alloc(wsb) || !s1.alloc(sizeof(float) * B * info.s1_per_signal) ||
         !s2.alloc(sizeof(float) * B * info.s2_per_signal) || !gx.alloc(sizeof(float) * B * s.N)) {
@@ -320,12 +334,13 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
     };
     // radix of the register-resident passes and points per in-LDS workgroup: one
     // run each against the choice so far, settled per stage
-    bool has_long = s.logNX >= kRegMinLogRows, has_short = false;
+    bool has_long = s.logNX >= kRegMinLogRows, has_short = false, has_chunks = false;
     for (int a = 0; a < s.n_alpha_psi; ++a) {
         has_long = has_long || s.logNX - s.k2[a] >= kRegMinLogRows;
         has_short = has_short || s.logNX - s.k2[a] <= 12;
     }
-    if (has_long || has_short) {
+    for (int a = 0; a < s.n_alpha; ++a) has_chunks = has_chunks || s.Tp[a] > 1024;
+    if (has_long || has_short || has_chunks) {
         double base_ms = 0.0, base_st[JTFS_NUM_STAGES];
         int rc = run_steps(P, x, B, (float*)s1.p, (float*)s2.p, (float*)gx.p, ws.p, wsb, reps, st, &base_ms, base_st);
         if (rc != JTFS_OK) return fail(rc);
@@ -353,6 +368,17 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
             const double a0 = base_st[JTFS_STAGE_SECOND_ORDER] + base_st[JTFS_STAGE_SECOND_ADJ_FFT];
             const double a1 = stb[JTFS_STAGE_SECOND_ORDER] + stb[JTFS_STAGE_SECOND_ADJ_FFT];
             if (a1 < 0.99 * a0) next |= JTFS_TUNE_LDS_BATCH8K;
+        }
+        if (has_chunks) {
+            // 1024 t-columns per forward workgroup instead of 4096: the forward contraction
+            // and the frequency lowpass that sums its partial slots
+            double ms = 0.0, stc[JTFS_NUM_STAGES];
+            set_rows(P, rows | JTFS_TUNE_TCHUNK_1K);
+            rc = run_steps(P, x, B, (float*)s1.p, (float*)s2.p, (float*)gx.p, ws.p, wsb, reps, st, &ms, stc);
+            if (rc != JTFS_OK) return fail(rc);
+            const double a0 = base_st[JTFS_STAGE_FREQ_FWD] + base_st[JTFS_STAGE_FREQ_LOWPASS];
+            const double a1 = stc[JTFS_STAGE_FREQ_FWD] + stc[JTFS_STAGE_FREQ_LOWPASS];
+            if (a1 < 0.99 * a0) next |= JTFS_TUNE_TCHUNK_1K;
         }
         rows = next;
         set_rows(P, rows);

@@ -139,24 +139,20 @@ int solve_shapes(const jtfs_params& p, Shapes* s) {
     s->NLo = (p.flags & JTFS_UNPAD_LAMBDA) ? (int)((s->n1 + p.F - 1) / p.F) : s->NL;
     s->Kp = (int)rup(s->n1, kKStep);
     s->k2.resize(s->n_alpha); s->Ta.resize(s->n_alpha); s->Tp.resize(s->n_alpha);
-    s->nch.resize(s->n_alpha); s->chunk.resize(s->n_alpha);
-    s->yoff.resize(s->n_alpha); s->phioff.resize(s->n_alpha); s->vchoff.resize(s->n_alpha);
-    int64_t yo = 0, po = 0, co = 0;
+    s->yoff.resize(s->n_alpha); s->phioff.resize(s->n_alpha);
+    int64_t yo = 0, po = 0;
     for (int a = 0; a < s->n_alpha; ++a) {
         // phi_T keeps the capped rate: its rows land on the N/T frames undecimated
         s->k2[a] = a < s->n_alpha_psi ? critical_log2(f2.sigma[a], s->logT - s->kX) : s->logT - s->kX;
         s->Ta[a] = (int)(s->NX >> s->k2[a]);
         s->Tp[a] = std::max(s->Ta[a], kTileTh);
-        s->chunk[a] = std::min(s->Tp[a], kChunkT);
-        s->nch[a] = s->Tp[a] / s->chunk[a];
-        s->yoff[a] = yo; s->phioff[a] = po; s->vchoff[a] = co;
+        s->yoff[a] = yo; s->phioff[a] = po;
         yo += (int64_t)s->Kp * s->Tp[a];
         po += (int64_t)s->Tp[a] * s->NTp;
-        co += s->nch[a];
         s->sumT += s->Ta[a];
     }
     s->sumTp = yo / s->Kp;
-    s->sumch = co;
+    set_chunks(s, kChunkT);
     s->kfr.resize(s->n_beta); s->Lb.resize(s->n_beta); s->rowoff.resize(s->n_beta); s->pfoff.resize(s->n_beta);
     int ro = 0; int64_t pf = 0;
     for (int b = 0; b < s->n_beta; ++b) {
@@ -174,6 +170,18 @@ int solve_shapes(const jtfs_params& p, Shapes* s) {
         s->Mphi = (int)std::min<double>((double)(s->NX / 2), std::floor(mm) + 1.0);
     }
     return JTFS_OK;
+}
+
+void set_chunks(Shapes* s, int chunk) {
+    s->chunk.resize(s->n_alpha); s->nch.resize(s->n_alpha); s->vchoff.resize(s->n_alpha);
+    int64_t co = 0;
+    for (int a = 0; a < s->n_alpha; ++a) {
+        s->chunk[a] = std::min(s->Tp[a], chunk);
+        s->nch[a] = s->Tp[a] / s->chunk[a];
+        s->vchoff[a] = co;
+        co += s->nch[a];
+    }
+    s->sumch = co;
 }
 
 int check_supported(const Shapes& s) {

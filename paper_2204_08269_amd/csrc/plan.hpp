@@ -67,6 +67,9 @@ struct Shapes {
 
 // Validate and solve; returns JTFS_OK or JTFS_EINVAL with the error set.
 int solve_shapes(const jtfs_params& p, Shapes* s);
+// t-chunks of the forward contraction: chunk[a] = min(Tp[a], chunk) columns per
+// workgroup, nch[a] partial-V slots per rate, their offsets and total (sumch).
+void set_chunks(Shapes* s, int chunk);
 // JTFS_OK if the device path of this library handles the shapes, else JTFS_ENOTSUP.
 int check_supported(const Shapes& s);
 const char* last_error();
@@ -104,6 +107,7 @@ struct Tuning {
     // register-resident rows: radix-8 passes instead of radix-16 ones, per stage
     bool r8_scalogram = false, r8_second = false, r8_rowfft = false, r8_first_adj = false;
     bool batch8k = false;        // in-LDS row transforms: 8192 points per workgroup (else 4096)
+    int chunk = kChunkT;         // t-columns per workgroup of the forward contraction (1024, 2048 or 4096)
 };
 // points per workgroup of the in-LDS second-order and gY2 row transforms
 inline int lds_batch_log(const Tuning& t) { return t.batch8k ? 13 : 12; }

@@ -158,6 +158,7 @@ class JTFS:
     BWD_TILE16 = 32
     RADIX8_BITS = {"scalogram": 64, "second_order": 128, "row_fft": 256, "first_adj": 512}
     LDS_BATCH8K = 1024
+    TCHUNK_BITS = {1024: 2048, 2048: 4096, 4096: 0}
 
     def autotune(self, B, x=None, reps=3):
         """Times the candidate launch choices for B signals (x: [B, N] on the
@@ -173,6 +174,7 @@ class JTFS:
                 "bwd_tile": 16 if t.reg_rows & self.BWD_TILE16 else 32,
                 "radix8": [k for k, v in self.RADIX8_BITS.items() if t.reg_rows & v],
                 "lds_batch": 8192 if t.reg_rows & self.LDS_BATCH8K else 4096,
+                "t_chunk": self._chunk_of(t.reg_rows),
                 "step_ms": t.step_ms, "from_cache": bool(t.from_cache),
                 "fwd_ms": {"tile32": t.fwd_ms[0], "tile16": t.fwd_ms[1]},
                 "bwd_ms": {"tile32": t.bwd_ms[0], "tile16": t.bwd_ms[1]},
@@ -181,27 +183,34 @@ class JTFS:
                                   "split16_phase_register": t.candidates_ms[4],
                                   "split16_phase_lds": t.candidates_ms[5]}}
 
-    def set_tuning(self, contraction, register_rows, fwd_tile=32, bwd_tile=32, radix8=(), lds_batch=4096):
+    def _chunk_of(self, mask):
+        return 1024 if mask & self.TCHUNK_BITS[1024] else 2048 if mask & self.TCHUNK_BITS[2048] else 4096
+
+    def set_tuning(self, contraction, register_rows, fwd_tile=32, bwd_tile=32, radix8=(), lds_batch=4096,
+                   t_chunk=4096):
         """Launch choices: contraction mode; stages whose 2^14-point rows are
         register-resident; contraction tiles; stages whose register-resident
         transforms use radix-8 passes (else radix 16); points per workgroup of
-        the in-LDS row transforms (4096 or 8192)."""
+        the in-LDS row transforms (4096 or 8192); t-columns per workgroup of the
+        forward contraction (1024, 2048 or 4096; the workspace size follows)."""
         mode = _lib.CONTRACTIONS[contraction]
         if lds_batch not in (4096, 8192):
             raise ValueError("lds_batch must be 4096 or 8192")
+        if t_chunk not in self.TCHUNK_BITS:
+            raise ValueError("t_chunk must be 1024, 2048 or 4096")
         mask = (sum(self.REG_BITS[k] for k in register_rows) | (self.FWD_TILE16 if fwd_tile == 16 else 0) |
                 (self.BWD_TILE16 if bwd_tile == 16 else 0) | sum(self.RADIX8_BITS[k] for k in radix8) |
-                (self.LDS_BATCH8K if lds_batch == 8192 else 0))
+                (self.LDS_BATCH8K if lds_batch == 8192 else 0) | self.TCHUNK_BITS[t_chunk])
         _lib.check(self.lib.jtfs_plan_set_tuning(self.plan, mode, mask))
         self.contraction = contraction
         self._ws = {}
 
     def tuning_radix(self):
-        """(stages in radix-8 passes, points per in-LDS workgroup) now set on the plan."""
+        """(stages in radix-8 passes, points per in-LDS workgroup, forward t-chunk) now set on the plan."""
         m, r = ctypes.c_int(0), ctypes.c_int(0)
         _lib.check(self.lib.jtfs_plan_get_tuning(self.plan, ctypes.byref(m), ctypes.byref(r)))
         return ([k for k, v in self.RADIX8_BITS.items() if r.value & v],
-                8192 if r.value & self.LDS_BATCH8K else 4096)
+                8192 if r.value & self.LDS_BATCH8K else 4096, self._chunk_of(r.value))
 
     def tuning(self):
         """(contraction, register rows, forward tile, backward tile) now set on the plan."""

@@ -907,18 +907,19 @@ def test_autotune_then_every_row_choice_matches_oracle():
     assert c["split16_register"] > 0 and c["fp32_register"] > 0 and c["split16_phase_register"] > 0
     assert c["split16_lds"] > 0 and choice["fwd_ms"]["tile16"] > 0
     assert op.tuning() == (choice["contraction"], choice["register_rows"], choice["fwd_tile"], choice["bwd_tile"])
-    assert op.tuning_radix() == (choice["radix8"], choice["lds_batch"])
+    assert op.tuning_radix() == (choice["radix8"], choice["lds_batch"], choice["t_chunk"])
     gs1, gs2 = synth.cotangents((2,) + P.s1_shape(), (2,) + P.s2_shape(), seed=31)
     refs = [(O.jtfs(x[b].astype(np.float64), P),
              O.jtfs_vjp(x[b].astype(np.float64), gs1[b].astype(np.float64), gs2[b].astype(np.float64), P))
             for b in range(2)]
     for mode in MODES + ["split16_phase"]:
-        # (register-resident stages, forward tile, backward tile, radix-8 stages, in-LDS batch)
-        for rows, tile, btile, r8, lb in (([], 16, 16, [], 8192), (ALL_ROWS, 32, 32, ALL_ROWS, 4096),
-                                          (["scalogram", "row_fft"], 16, 32, ["scalogram", "row_fft"], 8192),
-                                          (["second_order", "first_adj"], 32, 16, ["first_adj"], 4096),
-                                          (ALL_ROWS, 16, 16, ["second_order", "row_fft"], 8192)):
-            op.set_tuning(mode, rows, fwd_tile=tile, bwd_tile=btile, radix8=r8, lds_batch=lb)
+        # (register-resident stages, forward tile, backward tile, radix-8 stages, in-LDS batch, t-chunk)
+        for rows, tile, btile, r8, lb, tc in (([], 16, 16, [], 8192, 1024), (ALL_ROWS, 32, 32, ALL_ROWS, 4096, 4096),
+                                              (["scalogram", "row_fft"], 16, 32, ["scalogram", "row_fft"], 8192, 2048),
+                                              (["second_order", "first_adj"], 32, 16, ["first_adj"], 4096, 1024),
+                                              (ALL_ROWS, 16, 16, ["second_order", "row_fft"], 8192, 4096)):
+            op.set_tuning(mode, rows, fwd_tile=tile, bwd_tile=btile, radix8=r8, lds_batch=lb, t_chunk=tc)
+            assert op.tuning_radix() == (r8 if r8 != ALL_ROWS else list(op.RADIX8_BITS), lb, tc)
             ws = op.new_workspace(2)
             s1, s2 = op.forward(xt, ws)
             g = op.vjp(xt, torch.from_numpy(gs1).cuda(), torch.from_numpy(gs2).cuda(), ws=ws,
@@ -927,7 +928,7 @@ def test_autotune_then_every_row_choice_matches_oracle():
             for b in range(2):
                 (r1, r2), rg = refs[b]
                 check_paths(g1[b], g2[b], r1, r2)
-                assert rel_l2(g[b], rg) <= TOL_VJP, (mode, rows, tile, btile, r8, lb)
+                assert rel_l2(g[b], rg) <= TOL_VJP, (mode, rows, tile, btile, r8, lb, tc)
 
 
 def test_autotune_cache_reuses_the_choice(tmp_path, monkeypatch):
