@@ -291,6 +291,18 @@ int jtfs_mulog_backward(const jtfs_plan* plan, const float* s1, const float* s2,
                         const float* mu2, float eps, const float* g1, const float* g2, float* gs1, float* gs2,
                         hipStream_t stream);
 
+/* The filterbanks and the critical-rate schedule of a plan, host FP64 (sec. 2, eq. (1);
+ * sec. 1 for the rates), for checks against an independent implementation:
+ *   xi_sigma [2 (n1 + na + nb)]: (centre, width) of each wavelet, the first-order
+ *     family (cycles per sample), then the second-order one (cycles per scalogram
+ *     sample), then the frequential one (cycles per lambda bin);
+ *   schedule [1 + na + nb]: kX, then k2 of each second-order wavelet, then kfr of
+ *     each frequential wavelet (log2 decimations);
+ * na, nb count the wavelets only (n_alpha, n_beta of jtfs_info less the lowpasses
+ * that JTFS_LOWPASS_PAIRS adds).  Host pointers owned by the caller; either may be
+ * NULL.  No GPU work. */
+int jtfs_plan_tables(const jtfs_plan* plan, double* xi_sigma, int32_t* schedule);
+
 /* Zeroth order: S0[b][tau] = (x * phi_T)(tau T), tau < N/T, the lowpass of the
  * signal itself that completes S1 and S2 (sec. 2's cited transform; with the
  * discretisation above: circular, phi_T the Gaussian lowpass of width 0.1/T, DC

@@ -59,7 +59,7 @@ EXPORTS = ["jtfs_query", "jtfs_query_filters", "jtfs_plan_create", "jtfs_plan_cr
            "jtfs_plan_set_contraction", "jtfs_plan_get_contraction", "jtfs_bucket_create", "jtfs_bucket_offsets",
            "jtfs_bucket_run", "jtfs_bucket_destroy", "jtfs_path_means", "jtfs_mulog", "jtfs_mulog_backward",
            "jtfs_forward_mulog", "jtfs_backward_mulog",
-           "jtfs_zeroth_order", "jtfs_zeroth_order_backward",
+           "jtfs_zeroth_order", "jtfs_zeroth_order_backward", "jtfs_plan_tables",
            "jtfs_texture_create", "jtfs_texture_set_target", "jtfs_texture_set_start", "jtfs_texture_iterate",
            "jtfs_texture_read", "jtfs_texture_destroy", "jtfs_plan_autotune", "jtfs_plan_set_tuning",
            "jtfs_plan_get_tuning", "jtfs_forward_noalloc",
@@ -109,6 +109,7 @@ def load(path: str = LIB_PATH):
     L.jtfs_path_means.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     L.jtfs_mulog.argtypes = [vp, vp, vp, i64, vp, vp, ctypes.c_float, vp, vp, vp]
     L.jtfs_mulog_backward.argtypes = [vp, vp, vp, i64, vp, vp, ctypes.c_float, vp, vp, vp, vp, vp]
+    L.jtfs_plan_tables.argtypes = [vp, vp, vp]
     L.jtfs_zeroth_order.argtypes = [vp, vp, i64, vp, vp]
     L.jtfs_zeroth_order_backward.argtypes = [vp, vp, i64, vp, vp]
     L.jtfs_forward_mulog.argtypes = [vp, vp, i64, vp, vp, ctypes.c_float, vp, vp, vp, sz, vp]

@@ -429,6 +429,23 @@ extern "C" int jtfs_plan_info(const jtfs_plan* P, jtfs_info* out) {
     return JTFS_OK;
 }
 
+extern "C" int jtfs_plan_tables(const jtfs_plan* P, double* xi_sigma, int32_t* schedule) {
+    if (!P) { set_error("null plan"); return JTFS_EINVAL; }
+    const Shapes& s = P->s;
+    const Family* fams[3] = {&s.f1, &s.f2, &s.ffr};
+    int64_t o = 0;
+    for (const Family* f : fams)
+        for (int i = 0; i < f->n(); ++i, ++o)
+            if (xi_sigma) { xi_sigma[2 * o] = f->xi[i]; xi_sigma[2 * o + 1] = f->sigma[i]; }
+    if (schedule) {
+        int q = 0;
+        schedule[q++] = s.kX;
+        for (int a = 0; a < s.n_alpha_psi; ++a) schedule[q++] = s.k2[a];
+        for (int b = 0; b < s.n_beta_psi; ++b) schedule[q++] = s.kfr[b];
+    }
+    return JTFS_OK;
+}
+
 extern "C" int jtfs_plan_table(const jtfs_plan* P, int which, void* host_dst, size_t bytes) {
     if (!P || !host_dst) { set_error("null pointer"); return JTFS_EINVAL; }
     const Shapes& s = P->s;

@@ -237,6 +237,17 @@ def test_north_star_plan_create_matches_ex():
         r1, r2 = op.forward(xt)
         torch.cuda.synchronize()
         assert torch.equal(s1, r1) and torch.equal(s2, r2)
+        # its filterbanks and schedule (host FP64) against the oracle's own solve
+        P = oracle_plan(p)
+        n = P.n1 + P.n_alpha + P.n_beta
+        xs = (ctypes.c_double * (2 * n))()
+        sched = (ctypes.c_int32 * (1 + P.n_alpha + P.n_beta))()
+        _lib.check(L.jtfs_plan_tables(plan, xs, sched))
+        xs = np.array(xs).reshape(n, 2)
+        ref = np.concatenate([np.stack([P.xi1, P.sigma1], 1), np.stack([P.xi2, P.sigma2], 1),
+                              np.stack([P.xi_fr, P.sigma_fr], 1)])
+        assert np.max(np.abs(xs - ref) / ref) <= 1e-13
+        assert list(sched) == [P.kX] + list(P.k2) + list(P.k_fr)
     finally:
         L.jtfs_plan_destroy(plan)
 
