@@ -252,6 +252,29 @@ def test_north_star_plan_create_matches_ex():
         L.jtfs_plan_destroy(plan)
 
 
+def test_forward_captured_in_a_graph_replays_like_eager():
+    """The forward allocates nothing and records no memset, so a caller can capture
+    it in a HIP graph (torch.cuda.graph) on fixed buffers: three replays on new
+    inputs, each followed by an eager forward on another workspace and a
+    synchronisation, give the eager coefficients bit for bit."""
+    op = gpu_op(P1, contraction="split16_phase")
+    B = 2
+    ws, ws_eager = op.new_workspace(B), op.new_workspace(B)
+    static_x = torch.from_numpy(synth.batch(1, B=B)).cuda()
+    op.forward(static_x, ws)                     # warm-up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        o1, o2 = op.forward(static_x, ws)
+    for k in range(3):
+        xk = torch.from_numpy(synth.batch(1, B=B, offset=2 * (k + 1))).cuda()
+        static_x.copy_(xk)
+        g.replay()
+        r1, r2 = op.forward(xk, ws_eager)
+        torch.cuda.synchronize()
+        assert torch.equal(o1, r1) and torch.equal(o2, r2), f"replay {k}"
+
+
 def test_ragged_bucket_graph_matches_oracle_and_replays():
     """Uneven lengths, bucketed to powers of two and run as one HIP graph: every
     signal's coefficients equal the oracle's on the zero-padded signal, the
