@@ -203,7 +203,7 @@ def test_autograd_function_matches_vjp():
     assert not n1.requires_grad and torch.equal(n1, s1.detach()) and torch.equal(n2, s2.detach())
 
 
-def test_north_star_plan_create_matches_ex():
+def test_plan_create_signature_matches_ex():
     """jtfs_plan_create(N, J, Q[2], J_fr, Q_fr, T, F) builds the plan that
     jtfs_plan_create_ex builds with no flags: the same sizes, workspace sizes per
     signal that jtfs_workspace_size confirms, and bit-identical coefficients."""
