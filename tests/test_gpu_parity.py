@@ -659,7 +659,8 @@ def test_fused_mulog_matches_oracle(variant, mode):
 
 # Lowpass pairs: phi_T as one more temporal rate (its second-order rows are the S1
 # rows) and phi_F as one more frequential scale, through every contraction mode.
-LP_SHAPES = [P1, RAGGED[2], dict(N=4096, J=7, Q=(8, 1), J_fr=3, Q_fr=1, T=64, F=2)]
+LP_SHAPES = [P1, RAGGED[2], dict(N=4096, J=7, Q=(8, 1), J_fr=3, Q_fr=1, T=64, F=2),
+             RAGGED[0], RAGGED[1]]      # T = N (one frame: phi_T's rate holds one column); F = 1
 
 
 @pytest.mark.parametrize("mode", ["fp32", "split16", "split16_phase"])
