@@ -195,7 +195,7 @@ def ragged_batch(torch, dev, runs=3):
     p = synth.PARAMS[4]
     sigs = synth.cfg4_ragged(synth.BATCH[4])
     lengths = [len(v) for v in sigs]
-    bk = JTFSBucket(lengths, p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"])
+    bk = JTFSBucket(lengths, p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"], autotune=True)
     x = torch.from_numpy(np.concatenate(sigs)).to(dev)
     g = torch.from_numpy(np.random.default_rng(4).standard_normal(bk.s_offset[-1]).astype(np.float32)).to(dev)
     out = torch.empty(bk.s_offset[-1], dtype=torch.float32, device=dev)
@@ -222,7 +222,7 @@ def ragged_batch(torch, dev, runs=3):
     alone = {}
     for pad in sorted(set(pads)):
         idx = [i for i, n in enumerate(pads) if n == pad]
-        b1 = JTFSBucket([lengths[i] for i in idx], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"])
+        b1 = JTFSBucket([lengths[i] for i in idx], p["J"], p["Q"], p["J_fr"], p["Q_fr"], p["T"], p["F"], autotune=True)
         x1 = torch.from_numpy(np.concatenate([sigs[i] for i in idx])).to(dev)
         g1 = torch.from_numpy(np.random.default_rng(5).standard_normal(b1.s_offset[-1]).astype(np.float32)).to(dev)
         o1 = torch.empty(b1.s_offset[-1], dtype=torch.float32, device=dev)
@@ -239,7 +239,8 @@ def ragged_batch(torch, dev, runs=3):
     print(f"[bench] ragged batch: buckets alone {alone} ms, sum {sum(alone.values()):.2f}", file=sys.stderr,
           flush=True)
     return {"workload": "256 harmonic tones + pink noise, lengths log-uniform in [2^13, 2^16], J=11, Q=(16,1), "
-                        "J_fr=4, Q_fr=1, T=2^10, F=2^3; buckets of power-of-two pads, one HIP graph per run",
+                        "J_fr=4, Q_fr=1, T=2^10, F=2^3; buckets of power-of-two pads, each bucket's plan autotuned, "
+                        "one HIP graph per run",
             "ms_per_run": round(ms, 3), "fwd_bwd_msamples_s_real": round(real / (ms * 1e-3) / 1e6, 3),
             "fwd_bwd_msamples_s_padded": round(padded / (ms * 1e-3) / 1e6, 3),
             "real_samples": real, "padded_samples": padded, "signals_per_pad": counts,

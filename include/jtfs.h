@@ -264,7 +264,13 @@ int jtfs_plan_table(const jtfs_plan* plan, int which, void* host_dst, size_t byt
  * one HIP graph (pack, forward, backward, unpack), each bucket on a branch of its
  * own (forked from and joined back to the stream, so that the buckets may run
  * concurrently); later calls with the same pointers replay it with a single
- * graph launch.  Not thread-safe per object. */
+ * graph launch.  Not thread-safe per object.
+ * With JTFS_BUCKET_AUTOTUNE in p->flags (jtfs_bucket_create only; the other bits
+ * go to every bucket's plan), each bucket's plan is autotuned at creation for its
+ * batch (jtfs_plan_autotune on zeros, on the null stream: seconds for large
+ * buckets); the launch choices are kept and the contraction of each run is
+ * chosen as without the flag. */
+#define JTFS_BUCKET_AUTOTUNE 0x100u
 typedef struct jtfs_bucket jtfs_bucket;
 int jtfs_bucket_create(jtfs_bucket** out, const int64_t* lengths, int count, const jtfs_params* p);
 int jtfs_bucket_offsets(const jtfs_bucket* bk, int64_t* x_offset, int64_t* s_offset);

@@ -24,6 +24,7 @@ JTFS_NO_FREQ_AVERAGE = 1
 JTFS_TIME_SCATTERING = 2
 JTFS_LOWPASS_PAIRS = 4
 JTFS_UNPAD_LAMBDA = 8
+JTFS_BUCKET_AUTOTUNE = 0x100
 JTFS_CONTRACTION_FP32 = 0
 JTFS_CONTRACTION_SPLIT_F16 = 1
 JTFS_CONTRACTION_SPLIT_F16_PHASE = 2

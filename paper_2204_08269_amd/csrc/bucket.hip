@@ -95,6 +95,8 @@ extern "C" int jtfs_bucket_create(jtfs_bucket** out, const int64_t* lengths, int
     auto* bk = new (std::nothrow) jtfs_bucket();
     if (!bk) { set_error("host allocation failed"); return JTFS_ENOMEM; }
     bk->p = *p;
+    const bool tune = (p->flags & JTFS_BUCKET_AUTOTUNE) != 0;
+    bk->p.flags &= ~JTFS_BUCKET_AUTOTUNE;           // the plans' own flags
     std::map<int64_t, std::vector<int>> groups;
     for (int i = 0; i < count; ++i) {
         if (lengths[i] < 16 || lengths[i] > (int64_t(1) << 24)) { release(bk); set_error("length out of range"); return JTFS_EINVAL; }
@@ -111,12 +113,24 @@ extern "C" int jtfs_bucket_create(jtfs_bucket** out, const int64_t* lengths, int
         Bucket b;
         b.N = kv.first;
         b.members = kv.second;
-        jtfs_params q = *p;
+        jtfs_params q = bk->p;
         q.N = b.N;
         int st = jtfs_plan_create_ex(&b.plan, &q);
         if (st != JTFS_OK) { release(bk); return st; }
         bk->buckets.push_back(b);
         Bucket& bb = bk->buckets.back();
+        if (tune) {
+            // launch choices for this bucket's batch; the contraction of each run is
+            // chosen below (the stored phase when a gradient is asked for)
+            jtfs_tuning t;
+            st = jtfs_plan_autotune(bb.plan, nullptr, (int64_t)bb.members.size(), 2, nullptr, &t);
+            int mode = 0, mask = 0;
+            if (st == JTFS_OK) st = jtfs_plan_get_tuning(bb.plan, &mode, &mask);
+            if (st == JTFS_OK)
+                st = jtfs_plan_set_tuning(bb.plan, bb.plan->split_ok ? JTFS_CONTRACTION_SPLIT_F16 : JTFS_CONTRACTION_FP32,
+                                          mask);
+            if (st != JTFS_OK) { release(bk); return st; }
+        }
         jtfs_plan_info(bb.plan, &bb.info);
         for (int i : bb.members) s_per[i] = bb.info.s1_per_signal + bb.info.s2_per_signal;
     }

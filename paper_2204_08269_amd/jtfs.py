@@ -359,7 +359,8 @@ class JTFSBucket:
     the input samples when a packed cotangent is given).  Must be called on a
     non-default stream (graph capture)."""
 
-    def __init__(self, lengths, J, Q, J_fr, Q_fr, T, F):
+    def __init__(self, lengths, J, Q, J_fr, Q_fr, T, F, autotune=False):
+        """(autotune: tune each bucket's plan for its batch at creation.)"""
         if not torch.cuda.is_available():
             raise RuntimeError("JTFSBucket needs a ROCm GPU (no CPU fallback)")
         self.lib = _lib.load()
@@ -367,6 +368,8 @@ class JTFSBucket:
         n = len(self.lengths)
         arr = (ctypes.c_int64 * n)(*self.lengths)
         self.params = _lib.params(16, J, Q, J_fr, Q_fr, T, F)
+        if autotune:
+            self.params.flags |= _lib.JTFS_BUCKET_AUTOTUNE
         h = ctypes.c_void_p()
         _lib.check(self.lib.jtfs_bucket_create(ctypes.byref(h), arr, n, ctypes.byref(self.params)))
         self.h = h

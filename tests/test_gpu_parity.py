@@ -275,17 +275,19 @@ def test_forward_captured_in_a_graph_replays_like_eager():
         assert torch.equal(o1, r1) and torch.equal(o2, r2), f"replay {k}"
 
 
-def test_ragged_bucket_graph_matches_oracle_and_replays():
+@pytest.mark.parametrize("autotune", [False, True])
+def test_ragged_bucket_graph_matches_oracle_and_replays(autotune):
     """Uneven lengths, bucketed to powers of two and run as one HIP graph: every
     signal's coefficients equal the oracle's on the zero-padded signal, the
     gradient equals the oracle's VJP on the true samples, and replays of the
-    graph (with eager work between them) are bitwise identical."""
+    graph (with eager work between them) are bitwise identical; also with each
+    bucket's plan autotuned at creation."""
     from paper_2204_08269_amd.jtfs import JTFSBucket
     prm = dict(J=6, Q=(8, 1), J_fr=3, Q_fr=1, T=64, F=4)
     lengths = [3000, 2048, 5000, 1500, 8000, 2500]
     rng = np.random.default_rng(77)
     sigs = [(rng.standard_normal(L) * 0.5).astype(np.float32) for L in lengths]
-    bk = JTFSBucket(lengths, **prm)
+    bk = JTFSBucket(lengths, **prm, autotune=autotune)
     x = torch.from_numpy(np.concatenate(sigs)).cuda()
     g = torch.from_numpy(rng.standard_normal(bk.s_offset[-1]).astype(np.float32)).cuda()
     st = torch.cuda.Stream()
