@@ -317,17 +317,19 @@ __global__ void __launch_bounds__(kRegT) k_rowfft_r(float2* __restrict__ base, i
     }
 }
 
-// Second-order rows of 2^13 points: the fold, inverse transform and row maximum of
-// k_second_order_r with one register transform of 8 values per thread on the same
-// 1024 threads (two workgroups per CU).
-__global__ void __launch_bounds__(kRegT, 8) k_second_order_r13(const float2* __restrict__ Xh, int64_t Xh_pitch, int n1,
+// Second-order rows of 2^LOGN points (2^12 or 2^13): the fold, inverse transform and
+// row maximum of k_second_order_r with one register transform of 8 values per
+// thread on 2^LOGN / 8 threads (72 KB or 36 KB of exchange buffer and at most 64
+// VGPRs: two or four workgroups per CU).
+template <int LOGN>
+__global__ void __launch_bounds__((1 << LOGN) / 8, 8) k_second_order_rs(const float2* __restrict__ Xh, int64_t Xh_pitch, int n1,
                                                               const float* __restrict__ ps, int lo, int hi, int Tp,
                                                               int Kp, float2* __restrict__ Y, int64_t y_bstride,
                                                               float invNX, const float2* __restrict__ tw, int tw_log,
                                                               float* __restrict__ rowmax, int alpha, int n_alpha) {
     extern __shared__ __align__(16) float xbuf[];
     __shared__ unsigned int rmx;
-    constexpr int E = kRegE / 2, LOGN = kRegMinLog - 1;
+    constexpr int E = 8;
     const int lam = blockIdx.x;
     const int64_t b = blockIdx.y;
     float2* out = Y + b * y_bstride + (int64_t)lam * Tp;
@@ -355,13 +357,14 @@ __global__ void __launch_bounds__(kRegT, 8) k_second_order_r13(const float2* __r
     if (threadIdx.x == 0) rowmax[(b * n_alpha + alpha) * Kp + lam] = __uint_as_float(rmx);
 }
 
-// Rows of 2^13 points: one register transform of 8 values per thread on the same
-// 1024 threads; its exchange buffer (72 KB) and at most 64 VGPRs let two
-// workgroups share a CU.
-__global__ void __launch_bounds__(kRegT, 8) k_rowfft_r13(float2* __restrict__ base, int64_t bs, int64_t rs,
-                                                        const float2* __restrict__ tw, int tw_log) {
+// Rows of 2^LOGN points (2^12 or 2^13): one register transform of 8 values per
+// thread on 2^LOGN / 8 threads; its exchange buffer (72 or 36 KB) and at most 64
+// VGPRs let two or four workgroups share a CU.
+template <int LOGN>
+__global__ void __launch_bounds__((1 << LOGN) / 8, 8) k_rowfft_rs(float2* __restrict__ base, int64_t bs, int64_t rs,
+                                                                 const float2* __restrict__ tw, int tw_log) {
     extern __shared__ __align__(16) float xbuf[];
-    constexpr int E = kRegE / 2, LOGN = kRegMinLog - 1;
+    constexpr int E = 8;
     float2* row = base + (int64_t)blockIdx.y * bs + (int64_t)blockIdx.x * rs;
     float2 v[E];
 #pragma unroll
@@ -551,8 +554,9 @@ int reg_attributes() {
                         JTFS_REG_VARIANTS(k_rowfft_r), JTFS_REG_VARIANTS(k_scal_bwd_b_r),
                         (const void*)k_scal_bwd_a_r<kRegE, kRegMinLog, 4>,
                         (const void*)k_scal_bwd_a_r<kRegE, kRegMinLog, 3>,
-                        (const void*)k_scal_bwd_a_r<kRegE / 2, kRegMinLog - 1, 3>, (const void*)k_rowfft_r13,
-                        (const void*)k_second_order_r13};
+                        (const void*)k_scal_bwd_a_r<kRegE / 2, kRegMinLog - 1, 3>, (const void*)k_rowfft_rs<13>,
+                        (const void*)k_rowfft_rs<12>, (const void*)k_second_order_rs<13>,
+                        (const void*)k_second_order_rs<12>};
     for (const void* k : ks)
         if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds) != hipSuccess) {
             set_error("hipFuncSetAttribute failed for the long-row kernels");
@@ -587,9 +591,10 @@ void launch_second_order_r(const jtfs_plan* P, int a, const float2* Xh, int64_t 
     const Shapes& s = P->s;
     const int logTa = s.logNX - s.k2[a];
     const Family& f2 = s.f2;
-    if (logTa == kRegMinLog - 1) {
-        hipLaunchKernelGGL(k_second_order_r13, dim3(s.Kp, (unsigned)B), dim3(reg_threads()),
-                           sizeof(float) * (size_t)reg_xbuf_floats(kRegMinLog - 1), st, Xh, Xh_pitch, s.n1,
+    if (logTa == kRegMinLog - 1 || logTa == kRegMinLog - 2) {
+        auto k = logTa == kRegMinLog - 1 ? k_second_order_rs<kRegMinLog - 1> : k_second_order_rs<kRegMinLog - 2>;
+        hipLaunchKernelGGL(k, dim3(s.Kp, (unsigned)B), dim3((1u << logTa) / 8),
+                           sizeof(float) * (size_t)reg_xbuf_floats(logTa), st, Xh, Xh_pitch, s.n1,
                            P->psi2 + f2.off[a], f2.lo[a], f2.hi[a], s.Tp[a], s.Kp, Y2 + s.yoff[a],
                            (int64_t)s.Kp * s.sumTp, 1.0f / (float)s.NX, P->tw, P->tw_log, rowmax, a, s.n_alpha);
         return;
@@ -602,9 +607,10 @@ void launch_second_order_r(const jtfs_plan* P, int a, const float2* Xh, int64_t 
 
 void launch_rowfft_r(const jtfs_plan* P, float2* base, int64_t bs, int64_t rs, int rows, int logn, int64_t B,
                      hipStream_t st) {
-    if (logn == kRegMinLog - 1) {
-        hipLaunchKernelGGL(k_rowfft_r13, dim3((unsigned)rows, (unsigned)B), dim3(reg_threads()),
-                           sizeof(float) * (size_t)reg_xbuf_floats(kRegMinLog - 1), st, base, bs, rs, P->tw, P->tw_log);
+    if (logn == kRegMinLog - 1 || logn == kRegMinLog - 2) {
+        auto k = logn == kRegMinLog - 1 ? k_rowfft_rs<kRegMinLog - 1> : k_rowfft_rs<kRegMinLog - 2>;
+        hipLaunchKernelGGL(k, dim3((unsigned)rows, (unsigned)B), dim3((1u << logn) / 8),
+                           sizeof(float) * (size_t)reg_xbuf_floats(logn), st, base, bs, rs, P->tw, P->tw_log);
         return;
     }
     auto k = JTFS_REG_PICK(k_rowfft_r, logn, P->tune.r8_rowfft);
