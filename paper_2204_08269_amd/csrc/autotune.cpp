@@ -225,9 +225,9 @@ extern "C" int jtfs_plan_autotune(jtfs_plan* P, const float* x, int64_t B, int r
         P->contraction = saved_mode;
     }
     bool has14 = s.logNX == kRegMinLogRows;
-    // (2^12- and 2^13-point rows of the second order and row FFT stages follow the same choice)
+    // (2^11- to 2^13-point rows of the second order and row FFT stages follow the same choice)
     for (int a = 0; a < s.n_alpha_psi; ++a)
-        has14 = has14 || (s.logNX - s.k2[a] <= kRegMinLogRows && s.logNX - s.k2[a] >= kRegMinLogRows - 2);
+        has14 = has14 || (s.logNX - s.k2[a] <= kRegMinLogRows && s.logNX - s.k2[a] >= kRegMinLogRows - 3);
     const int all_rows = JTFS_REG_SCALOGRAM | JTFS_REG_SECOND_ORDER | JTFS_REG_ROW_FFT | JTFS_REG_FIRST_ADJ;
     // second run: rows in LDS and the 16 x 16 contraction tiles, where any of these choices exists
     const bool tile16 = P->split_ok && !s.tscat && fwdq_supported(P, false);

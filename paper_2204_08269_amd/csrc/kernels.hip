@@ -1300,9 +1300,9 @@ int forward_front(const jtfs_plan* P, const float* x, int64_t B, float* s1, char
     }
     for (int a = 0; a < s.n_alpha_psi; ++a) {
         const int logTa = s.logNX - s.k2[a];
-        // rows of 2^12 and 2^13 points take the register-resident transform with the same choice as 2^14
+        // rows of 2^11 to 2^13 points take the register-resident transform with the same choice as 2^14
         if (use_reg_rows(logTa, P->tune.reg_second) ||
-            ((logTa == kRegMinLogRows - 1 || logTa == kRegMinLogRows - 2) && P->tune.reg_second)) {
+            (logTa >= kRegMinLogRows - 3 && logTa < kRegMinLogRows && P->tune.reg_second)) {
             JTFS_TIMED(JTFS_STAGE_SECOND_ORDER, st,
                        launch_second_order_r(P, a, Xh, w.Xh_pitch, Y2, (float*)(base + w.rowmax), B, st));
             LAUNCHCHK("second order");
@@ -1406,9 +1406,9 @@ static int gy2_row_fft(const jtfs_plan* P, int a, float2* gY2, int64_t yb, int64
     const int lb = lds_batch_log(P->tune);
     const int logC = logTa >= lb ? 0 : lb - logTa;
     const size_t lds = (size_t)(1 << logC) * (lpad_len(s.Ta[a]) + 1) * sizeof(float2);
-    // rows of 2^12 and 2^13 points take the register-resident transform with the same choice as 2^14
+    // rows of 2^11 to 2^13 points take the register-resident transform with the same choice as 2^14
     if (use_reg_rows(logTa, P->tune.reg_rowfft) ||
-        ((logTa == kRegMinLogRows - 1 || logTa == kRegMinLogRows - 2) && P->tune.reg_rowfft)) {
+        (logTa >= kRegMinLogRows - 3 && logTa < kRegMinLogRows && P->tune.reg_rowfft)) {
         JTFS_TIMED(JTFS_STAGE_SECOND_ADJ_FFT, st,
                    launch_rowfft_r(P, gY2 + s.yoff[a], yb, (int64_t)s.Tp[a], s.n1, logTa, B, st));
     } else {

@@ -317,10 +317,10 @@ __global__ void __launch_bounds__(kRegT) k_rowfft_r(float2* __restrict__ base, i
     }
 }
 
-// Second-order rows of 2^LOGN points (2^12 or 2^13): the fold, inverse transform and
+// Second-order rows of 2^LOGN points (2^11 to 2^13): the fold, inverse transform and
 // row maximum of k_second_order_r with one register transform of 8 values per
-// thread on 2^LOGN / 8 threads (72 KB or 36 KB of exchange buffer and at most 64
-// VGPRs: two or four workgroups per CU).
+// thread on 2^LOGN / 8 threads (72, 36 or 18 KB of exchange buffer and at most 64
+// VGPRs: two, four or eight workgroups per CU).
 template <int LOGN>
 __global__ void __launch_bounds__((1 << LOGN) / 8, 8) k_second_order_rs(const float2* __restrict__ Xh, int64_t Xh_pitch, int n1,
                                                               const float* __restrict__ ps, int lo, int hi, int Tp,
@@ -357,9 +357,9 @@ __global__ void __launch_bounds__((1 << LOGN) / 8, 8) k_second_order_rs(const fl
     if (threadIdx.x == 0) rowmax[(b * n_alpha + alpha) * Kp + lam] = __uint_as_float(rmx);
 }
 
-// Rows of 2^LOGN points (2^12 or 2^13): one register transform of 8 values per
-// thread on 2^LOGN / 8 threads; its exchange buffer (72 or 36 KB) and at most 64
-// VGPRs let two or four workgroups share a CU.
+// Rows of 2^LOGN points (2^11 to 2^13): one register transform of 8 values per
+// thread on 2^LOGN / 8 threads; its exchange buffer (72, 36 or 18 KB) and at most
+// 64 VGPRs let two, four or eight workgroups share a CU.
 template <int LOGN>
 __global__ void __launch_bounds__((1 << LOGN) / 8, 8) k_rowfft_rs(float2* __restrict__ base, int64_t bs, int64_t rs,
                                                                  const float2* __restrict__ tw, int tw_log) {
@@ -555,8 +555,9 @@ int reg_attributes() {
                         (const void*)k_scal_bwd_a_r<kRegE, kRegMinLog, 4>,
                         (const void*)k_scal_bwd_a_r<kRegE, kRegMinLog, 3>,
                         (const void*)k_scal_bwd_a_r<kRegE / 2, kRegMinLog - 1, 3>, (const void*)k_rowfft_rs<13>,
-                        (const void*)k_rowfft_rs<12>, (const void*)k_second_order_rs<13>,
-                        (const void*)k_second_order_rs<12>};
+                        (const void*)k_rowfft_rs<12>, (const void*)k_rowfft_rs<11>,
+                        (const void*)k_second_order_rs<13>, (const void*)k_second_order_rs<12>,
+                        (const void*)k_second_order_rs<11>};
     for (const void* k : ks)
         if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds) != hipSuccess) {
             set_error("hipFuncSetAttribute failed for the long-row kernels");
@@ -591,8 +592,10 @@ void launch_second_order_r(const jtfs_plan* P, int a, const float2* Xh, int64_t 
     const Shapes& s = P->s;
     const int logTa = s.logNX - s.k2[a];
     const Family& f2 = s.f2;
-    if (logTa == kRegMinLog - 1 || logTa == kRegMinLog - 2) {
-        auto k = logTa == kRegMinLog - 1 ? k_second_order_rs<kRegMinLog - 1> : k_second_order_rs<kRegMinLog - 2>;
+    if (logTa >= kRegMinLog - 3 && logTa <= kRegMinLog - 1) {
+        auto k = logTa == kRegMinLog - 1   ? k_second_order_rs<kRegMinLog - 1>
+                 : logTa == kRegMinLog - 2 ? k_second_order_rs<kRegMinLog - 2>
+                                           : k_second_order_rs<kRegMinLog - 3>;
         hipLaunchKernelGGL(k, dim3(s.Kp, (unsigned)B), dim3((1u << logTa) / 8),
                            sizeof(float) * (size_t)reg_xbuf_floats(logTa), st, Xh, Xh_pitch, s.n1,
                            P->psi2 + f2.off[a], f2.lo[a], f2.hi[a], s.Tp[a], s.Kp, Y2 + s.yoff[a],
@@ -607,8 +610,10 @@ void launch_second_order_r(const jtfs_plan* P, int a, const float2* Xh, int64_t 
 
 void launch_rowfft_r(const jtfs_plan* P, float2* base, int64_t bs, int64_t rs, int rows, int logn, int64_t B,
                      hipStream_t st) {
-    if (logn == kRegMinLog - 1 || logn == kRegMinLog - 2) {
-        auto k = logn == kRegMinLog - 1 ? k_rowfft_rs<kRegMinLog - 1> : k_rowfft_rs<kRegMinLog - 2>;
+    if (logn >= kRegMinLog - 3 && logn <= kRegMinLog - 1) {
+        auto k = logn == kRegMinLog - 1   ? k_rowfft_rs<kRegMinLog - 1>
+                 : logn == kRegMinLog - 2 ? k_rowfft_rs<kRegMinLog - 2>
+                                          : k_rowfft_rs<kRegMinLog - 3>;
         hipLaunchKernelGGL(k, dim3((unsigned)rows, (unsigned)B), dim3((1u << logn) / 8),
                            sizeof(float) * (size_t)reg_xbuf_floats(logn), st, base, bs, rs, P->tw, P->tw_log);
         return;
