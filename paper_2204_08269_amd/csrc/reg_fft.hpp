@@ -4,8 +4,8 @@
 // radix-16 where a thread holds 16 values, else radix-8 (then one shorter pass);
 // between passes the values move to
 // the thread that needs them through LDS as 8-byte complex values (one exchange
-// and two barriers per pass), in a buffer of n complex slots plus one pad slot per
-// eight.  Unnormalised in both directions; twiddles from the FP64-generated table
+// and two barriers per pass), in a buffer of n complex slots plus at most four pad
+// slots per 32.  Unnormalised in both directions; twiddles from the FP64-generated table
 // tw[k] = exp(-2 pi i k / 2^tw_log).
 //
 // The length and the thread count are compile-time constants: every position a
@@ -166,29 +166,47 @@ __device__ __forceinline__ void reg_butterflies(float2 (&v)[E], const float2* __
     }
 }
 
-// Exchange-buffer slot of position i: one unused slot after every eight.  The
-// stores of the first passes go to positions R apart across the lanes (R = 8);
-// with the pad those become 9 slots (72 bytes) apart, so that the 8-byte stores of
-// a half-wave cover the 64 LDS banks once.  Contiguous reads gain at most a 2-way
-// conflict where a run crosses a pad.
-__device__ __forceinline__ int xpad(int i) { return i + (i >> 3); }
+// Exchange-buffer slot of position i in the exchange after a pass of radix 2^LR
+// over sub-transforms of 2^LNS points: 2^xpad_log(LR, LNS) unused slots after
+// every 32 positions.  A half-wave's 32 eight-byte accesses then cover the 64 LDS
+// banks once, both for the stores (positions R apart in the first exchange; runs
+// of R consecutive positions, R^2 apart, in the second; runs of 2^LNS >= 32 after
+// that) and for the contiguous reads of the next pass: one pad slot per 32 in
+// general, and two (R = 16) or four (R = 8) in the second exchange, which put the
+// stores' runs on distinct banks.  (One slot per eight, the earlier layout, left every exchange with 2-way
+// conflicts on the stores or the reads.)  The pad is additive, so a thread's
+// slots stay its own base plus immediate offsets.
+// (at most four per 32, which the buffer size below allows)
+constexpr int xpad_log(int lr, int lns) { return lns == lr && (lr == 3 || lr == 4) ? 5 - lr : 0; }
+template <int LR, int LNS>
+__device__ __forceinline__ int xpad(int i) { return i + ((i >> 5) << xpad_log(LR, LNS)); }
 
-// floats of exchange buffer that reg_fft needs for 2^logn points (complex slots)
+// floats of exchange buffer that reg_fft needs for 2^logn points (complex slots;
+// at most four pad slots per 32)
 constexpr int reg_xbuf_floats(int logn) { return 2 * ((1 << logn) + (1 << (logn - 3))); }
 
 // Move the outputs of a radix-2^LR pass (sub-length 2^LNS) to the inputs of the
 // next pass (radix 2^LR2) through `x` (reg_xbuf_floats(LOGN) floats, as complex
 // slots).
+// Each position is the bitwise OR of a part that depends on the thread only
+// (element 0's position) and a compile-time part that depends on the element
+// only (thread 0's): tid < T occupies the low bits that q T and r 2^k leave free,
+// and the store map only inserts LR zero bits at bit LNS.  The pad, a multiple of
+// the position's bits above bit 5, then splits over the two parts, so each thread
+// pads one base per direction and every element is an immediate offset from it
+// (the compiler does not split (tid + C) >> 5 by itself).
 template <int LR, int LR2, int LNS, int LOGN, int E>
 __device__ __forceinline__ void reg_exchange(float2 (&v)[E], float* x) {
     float2* xc = (float2*)x;
     const int tid = opaque_tid();
+    float2* wb = xc + xpad<LR, LNS>(reg_out_pos<LR, LNS, LOGN, E>(0, tid));
+    float2* rb = xc + xpad<LR, LNS>(reg_in_pos<LR2, LOGN, E>(0, tid));
     lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) xc[xpad(reg_out_pos<LR, LNS, LOGN, E>(e, tid))] = v[e];
+    for (int e = 0; e < E; ++e) wb[xpad<LR, LNS>(reg_out_pos<LR, LNS, LOGN, E>(e, 0))] = v[e];
     lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = xc[xpad(reg_in_pos<LR2, LOGN, E>(e, tid))];
+    for (int e = 0; e < E; ++e) v[e] = rb[xpad<LR, LNS>(reg_in_pos<LR2, LOGN, E>(e, 0))];
 }
 
 template <int E, int LOGN, int LRM, int I>
