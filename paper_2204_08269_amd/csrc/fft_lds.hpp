@@ -97,6 +97,44 @@ __device__ __forceinline__ void dft4(C* a, bool inv) {
     a[3] = csub(t1, t3);
 }
 
+// In-register DFT of R = 2, 4 or 8 points (sign -1 forward, +1 inverse), output
+// in natural order.  Eight points as two 4-point DFTs: X[2q] = DFT4(a_r + a_{r+4}),
+// X[2q+1] = DFT4((a_r - a_{r+4}) w8^r).  Shared by the in-LDS Stockham passes and
+// the register-resident transforms.
+template <int R, typename C>
+__device__ __forceinline__ void dft_small(C* a, bool inv) {
+    static_assert(R == 2 || R == 4 || R == 8, "radix");
+    using Rl = typename cplx<C>::real;
+    if constexpr (R == 2) {
+        const C a0 = a[0], a1 = a[1];
+        a[0] = cadd(a0, a1);
+        a[1] = csub(a0, a1);
+    } else if constexpr (R == 4) {
+        dft4(a, inv);
+    } else {
+        C b[4], c[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            b[r] = cadd(a[r], a[r + 4]);
+            c[r] = csub(a[r], a[r + 4]);
+        }
+        const Rl h = (Rl)0.70710678118654752440;
+        // c1 *= w8, c2 *= w8^2 = -/+ i, c3 *= w8^3
+        c[1] = inv ? cplx<C>::make(h * (c[1].x - c[1].y), h * (c[1].x + c[1].y))
+                   : cplx<C>::make(h * (c[1].x + c[1].y), h * (c[1].y - c[1].x));
+        c[2] = inv ? cplx<C>::make(-c[2].y, c[2].x) : cplx<C>::make(c[2].y, -c[2].x);
+        c[3] = inv ? cplx<C>::make(-h * (c[3].x + c[3].y), h * (c[3].x - c[3].y))
+                   : cplx<C>::make(h * (c[3].y - c[3].x), -h * (c[3].x + c[3].y));
+        dft4(b, inv);
+        dft4(c, inv);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            a[2 * r] = b[r];
+            a[2 * r + 1] = c[r];
+        }
+    }
+}
+
 // One Stockham pass of radix R = 2^LR over `count` transforms of length 2^logn
 // located at s + t*stride.  Ns = 2^lNs is the length of the sub-transforms
 // already combined.  MAXE bounds the elements each thread holds.
@@ -127,36 +165,7 @@ __device__ __forceinline__ void fft_pass(C* s, int logn, int count, int stride, 
                 if (r) a = cmul(a, w[r]);
                 v[q][r] = a;
             }
-            if constexpr (R == 2) {
-                const C a0 = v[q][0], a1 = v[q][1];
-                v[q][0] = cadd(a0, a1);
-                v[q][1] = csub(a0, a1);
-            } else if constexpr (R == 4) {
-                dft4(v[q], inv);
-            } else {
-                // 8-point DFT as two 4-point DFTs: X[2q] = DFT4(a_r + a_{r+4}),
-                // X[2q+1] = DFT4((a_r - a_{r+4}) w8^r)
-                C b[4], c[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    b[r] = cadd(v[q][r], v[q][r + 4]);
-                    c[r] = csub(v[q][r], v[q][r + 4]);
-                }
-                const Rl h = (Rl)0.70710678118654752440;
-                // c1 *= w8, c2 *= w8^2 = -/+ i, c3 *= w8^3
-                c[1] = inv ? cplx<C>::make(h * (c[1].x - c[1].y), h * (c[1].x + c[1].y))
-                           : cplx<C>::make(h * (c[1].x + c[1].y), h * (c[1].y - c[1].x));
-                c[2] = inv ? cplx<C>::make(-c[2].y, c[2].x) : cplx<C>::make(c[2].y, -c[2].x);
-                c[3] = inv ? cplx<C>::make(-h * (c[3].x + c[3].y), h * (c[3].x - c[3].y))
-                           : cplx<C>::make(h * (c[3].y - c[3].x), -h * (c[3].x + c[3].y));
-                dft4(b, inv);
-                dft4(c, inv);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    v[q][2 * r] = b[r];
-                    v[q][2 * r + 1] = c[r];
-                }
-            }
+            dft_small<R>(v[q], inv);
         }
     }
     __syncthreads();

@@ -136,32 +136,8 @@ __device__ __forceinline__ void reg_butterflies(float2 (&v)[E], const float2* __
         for (int r = 1; r < R; ++r) a[r] = cmul(a[r], w[r]);
         if constexpr (R == 16) {
             dft16(a, inv);
-        } else if constexpr (R == 2) {
-            const float2 a0 = a[0], a1 = a[1];
-            a[0] = cadd(a0, a1);
-            a[1] = csub(a0, a1);
-        } else if constexpr (R == 4) {
-            dft4(a, inv);
         } else {
-            float2 b[4], c[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                b[r] = cadd(a[r], a[r + 4]);
-                c[r] = csub(a[r], a[r + 4]);
-            }
-            const float h = 0.70710678118654752f;
-            c[1] = inv ? make_float2(h * (c[1].x - c[1].y), h * (c[1].x + c[1].y))
-                       : make_float2(h * (c[1].x + c[1].y), h * (c[1].y - c[1].x));
-            c[2] = inv ? make_float2(-c[2].y, c[2].x) : make_float2(c[2].y, -c[2].x);
-            c[3] = inv ? make_float2(-h * (c[3].x + c[3].y), h * (c[3].x - c[3].y))
-                       : make_float2(h * (c[3].y - c[3].x), -h * (c[3].x + c[3].y));
-            dft4(b, inv);
-            dft4(c, inv);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                a[2 * r] = b[r];
-                a[2 * r + 1] = c[r];
-            }
+            dft_small<R>(a, inv);
         }
     }
 }
