@@ -285,6 +285,12 @@ def texture_leg(torch, dev, iters=100, mu0=-0.05):
                              "(one bird-call recording of 2^16 samples, GPU not stated; sec. 5)"}
 
 
+def _graph_ms(res):
+    """Single-signal forward time from graph replays (ms, rounded), or the reason there is none."""
+    v = res.get("single_graph_ms")
+    return round(v, 3) if isinstance(v, float) else v
+
+
 def _time_ms(torch, fn, n):
     """Mean wall time of fn over n calls (after one untimed call), GPU synchronised."""
     fn()
@@ -397,6 +403,30 @@ def run_workload(torch, dev, cfg, args, extras=True, stage_pass=True):
             times.append(time.perf_counter() - t0)
         res["single_ms"] = float(np.median(times)) * 1e3
         res["single_contraction"] = plain
+        # the same forward replayed from a captured HIP graph (no host launch cost
+        # per kernel); reported only if a replay equals the eager forward bit for bit
+        try:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                c1, c2 = op1.forward(x1, ws1)
+            g.replay()
+            torch.cuda.synchronize()
+            e1, e2 = op1.forward(x1, ws1)
+            torch.cuda.synchronize()
+            if torch.equal(c1, e1) and torch.equal(c2, e2):
+                times = []
+                for _ in range(20):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    g.replay()
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                res["single_graph_ms"] = float(np.median(times)) * 1e3
+            else:
+                res["single_graph_ms"] = "replay differs from the eager forward"
+            del g, c1, c2, e1, e2
+        except RuntimeError as e:
+            res["single_graph_ms"] = f"capture failed: {e}"
         del ws1, op1
     return res
 
@@ -521,6 +551,7 @@ def main():
         out["plain_fwd_single_msamples_s"] = round(res["N"] / (res["single_ms"] * 1e-3) / 1e6, 3)
         out["plain_fwd_single_ms"] = round(res["single_ms"], 3)
         out["plain_fwd_single_contraction"] = res["single_contraction"]
+        out["plain_fwd_single_graph_ms"] = _graph_ms(res)
         if "single_tuning" in res:
             out["plain_fwd_single_tuning"] = res["single_tuning"]
         out["mulog_fwd_ms"] = {k: round(v, 3) for k, v in res["mulog_ms"].items()}
@@ -568,7 +599,8 @@ def main():
                        "batched_fwd_msamples_s": round(r2["B"] * r2["N"] / (r2["fwd_ms"] * 1e-3) / 1e6, 3),
                        "plain_fwd_single_msamples_s": round(r2["N"] / (r2["single_ms"] * 1e-3) / 1e6, 3),
                        "plain_fwd_single_ms": round(r2["single_ms"], 3),
-                       "plain_fwd_single_contraction": r2["single_contraction"]}
+                       "plain_fwd_single_contraction": r2["single_contraction"],
+                       "plain_fwd_single_graph_ms": _graph_ms(r2)}
         del r2
         torch.cuda.empty_cache()
     if extras:
